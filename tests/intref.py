@@ -1,0 +1,91 @@
+"""Integer definitions used by the tests (unbounded Python ints).
+
+`textbook` is the plain definition of each operation type; `simulate`
+is an independent, deliberately naive interpreter of a whole design built
+on it (used only to cross-check the C oracle on tiny designs).
+"""
+from rtlgen.design import (ADD, AND, CONCAT, EQ, EXTRACT, LT, MUL, MUX, NOT, OR, ORR, SHL, SHR,
+                           SUB, XOR)
+
+M64 = (1 << 64) - 1
+
+
+def textbook(typ, vals, widths, wd, imm):
+    """Integer definition of each operation type (unbounded ints, then mod 2^wd)."""
+    a = vals[0]
+    if typ == AND:
+        r = a
+        for v in vals[1:]:
+            r &= v
+    elif typ == OR:
+        r = a
+        for v in vals[1:]:
+            r |= v
+    elif typ == XOR:
+        r = a
+        for v in vals[1:]:
+            r ^= v
+    elif typ == NOT:
+        r = (1 << wd) - 1 - (a % (1 << wd))
+    elif typ == ADD:
+        r = a + vals[1]
+    elif typ == SUB:
+        r = a - vals[1]
+    elif typ == MUL:
+        r = a * vals[1]
+    elif typ == MUX:
+        r = vals[1] if a != 0 else vals[2]
+    elif typ == EQ:
+        r = int(a == vals[1])
+    elif typ == LT:
+        r = int(a < vals[1])
+    elif typ == SHL:
+        r = a * (2 ** imm)
+    elif typ in (SHR, EXTRACT):
+        r = a // (2 ** imm)
+    elif typ == CONCAT:
+        r = a * (2 ** widths[1]) + vals[1]
+    elif typ == ORR:
+        r = int(a != 0)
+    else:
+        raise ValueError(typ)
+    return r % (1 << wd)
+
+
+def splitmix64(x):
+    z = (x + 0x9E3779B97F4A7C15) & M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+def stim_value(seed, cycle, k, w):
+    v = 0
+    for limb in range((w + 63) // 64):
+        v |= splitmix64(splitmix64(splitmix64(seed) ^ cycle) ^ ((k << 8) | limb)) << (64 * limb)
+    return v % (1 << w)
+
+
+def simulate(d, seed, n_cycles, start_cycle=0):
+    """All slot values (Python ints) of one instance after n_cycles."""
+    W = [int(x) for x in d.slot_width]
+    V = [0] * d.n_slots
+    for c, s in enumerate(d.const_slot):
+        V[int(s)] = sum(int(x) << (64 * l) for l, x in enumerate(d.const_limbs[c])) % (1 << W[int(s)])
+    ops = []
+    for j in range(d.n_ops):
+        srcs = [int(x) for x in d.op_src[d.op_src_ptr[j]:d.op_src_ptr[j + 1]]]
+        ops.append((int(d.op_type[j]), int(d.op_dst[j]), srcs, int(d.op_imm[j])))
+    for t in range(n_cycles):
+        for k, s in enumerate(d.input_slot):
+            V[int(s)] = stim_value(seed, start_cycle + t, k, W[int(s)])
+        for i in range(d.n_layers):
+            out = []
+            for typ, dst, srcs, imm in ops[int(d.layer_ptr[i]):int(d.layer_ptr[i + 1])]:
+                out.append((dst, textbook(typ, [V[s] for s in srcs], [W[s] for s in srcs], W[dst], imm)))
+            for dst, v in out:
+                V[dst] = v
+        nxt = [V[int(s)] for s in d.reg_next]
+        for j, s in enumerate(d.reg_slot):
+            V[int(s)] = nxt[j] % (1 << W[int(s)])
+    return V

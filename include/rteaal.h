@@ -1,0 +1,264 @@
+/*
+ * rteaal.h -- C interface of the MI355X (gfx950) RTL-simulation library.
+ *
+ * The library evaluates the per-cycle cascade of extended Einsums of the
+ * paper (section "RTL Simulation as a Cascade of Einsums", Cascade 1) for a
+ * levelized dataflow graph: in every clock cycle the primary inputs are
+ * written into the signal vector LI, every layer i (iterative rank I)
+ * gathers its operands through the operation-input mask OIM, applies the
+ * operator of its operation type (ranks N and O: map op_u, reduce op_r,
+ * populate op_s) and writes its layer outputs LO back into LI at the
+ * operation's S coordinate (identity operations elided, section "Identity
+ * Operator Elision"); at the end of the cycle every register latches its
+ * next-state value, all at once.
+ *
+ * Conventions for every call:
+ *   - Every entry point returns an rteaal_status.  On any error the call has
+ *     no side effects, and rteaal_last_error() describes the failure.
+ *   - Pointers marked "host" are ordinary host memory, borrowed for the
+ *     duration of the call unless stated otherwise.  The library copies what
+ *     it keeps.
+ *   - Device memory is obtained through the allocator given to
+ *     rteaal_create (or hipMalloc) and released by rteaal_unload_design,
+ *     rteaal_free_batch or rteaal_destroy.
+ *   - rteaal_step and rteaal_step_many only enqueue work on the context's
+ *     stream; rteaal_sync and rteaal_read_state wait for it.
+ *   - A context is used by one host thread at a time.
+ *   - Values are unsigned; a w-bit value is ceil(w/64) little-endian 64-bit
+ *     limbs with the bits above w equal to zero.
+ */
+#ifndef RTEAAL_H
+#define RTEAAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RTEAAL_OK = 0,
+  RTEAAL_E_INVALID_ARG = 1, /* null pointer, bad handle, size out of range   */
+  RTEAAL_E_BAD_DESIGN = 2,  /* graph violates levelization, arity, widths ...  */
+  RTEAAL_E_FORMAT = 3,      /* a coordinate does not fit its declared cbits    */
+  RTEAAL_E_NO_MEMORY = 4,   /* device allocation failed; nothing was created   */
+  RTEAAL_E_DEVICE = 5,      /* a HIP call failed; destroy the context          */
+  RTEAAL_E_BUSY = 6,        /* handle still in use by a pending step           */
+  RTEAAL_E_UNSUPPORTED = 7  /* valid request this build cannot serve           */
+} rteaal_status;
+
+typedef struct rteaal_ctx rteaal_ctx;
+typedef uint32_t rteaal_design_id;
+typedef uint32_t rteaal_batch_id;
+
+/* Device-memory provider.  alloc returns a device pointer aligned to at
+ * least 256 bytes, or NULL; free releases it.  Both run on the calling
+ * thread, outside any kernel. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, size_t bytes, void* user);
+  void* user;
+} rteaal_allocator;
+
+/* Context on HIP device `device`.  `stream` is a hipStream_t (NULL: the
+ * library creates its own non-blocking stream at default priority).
+ * `alloc` may be NULL (hipMalloc / hipFree). */
+rteaal_status rteaal_create(int device, void* stream, const rteaal_allocator* alloc,
+                            rteaal_ctx** out);
+/* Waits for pending work, then frees every design and batch.  NULL is a no-op. */
+void rteaal_destroy(rteaal_ctx* ctx);
+/* Text of the last failure on ctx (or of the last context-less failure when
+ * ctx is NULL); valid until the next call on the same context. */
+const char* rteaal_last_error(const rteaal_ctx* ctx);
+
+/* ------------------------------------------------------------------------ */
+/* Designs                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Rank-N coordinates.  AND/OR/XOR take 2 or 3 operands (the O fiber's
+ * occupancy, fixed per (type, arity)); NOT/SHL/SHR/EXTRACT/ORR take 1;
+ * ADD/SUB/MUL/EQ/LT/CONCAT take 2; MUX takes 3.
+ * Results (all unsigned, computed on zero-extended operands, then reduced
+ * modulo 2^dst_width):
+ *   AND/OR/XOR  fold over operands       NOT      bitwise complement
+ *   ADD, SUB    o0 + o1, o0 - o1         MUL      o0 * o1 (low bits)
+ *   MUX         o0 != 0 ? o1 : o2        EQ, LT   [o0 == o1], [o0 < o1]
+ *   SHL, SHR    o0 shifted by imm        EXTRACT  o0 >> imm (width from dst)
+ *   CONCAT      o0 * 2^width(o1) + o1    ORR      [o0 != 0]
+ * Operand o=0 is reduced first, as the left operand (section "Evaluating
+ * Multiple Operation Types"); MUX is the select operator op_s of Appendix A. */
+typedef enum {
+  RTEAAL_AND = 0, RTEAAL_OR, RTEAAL_XOR, RTEAAL_NOT, RTEAAL_ADD, RTEAAL_SUB, RTEAAL_MUL,
+  RTEAAL_MUX, RTEAAL_EQ, RTEAAL_LT, RTEAAL_SHL, RTEAAL_SHR, RTEAAL_EXTRACT, RTEAAL_CONCAT,
+  RTEAAL_ORR, RTEAAL_OP_COUNT
+} rteaal_op;
+
+/* Per-rank format (section "Format": uncompressed or compressed, coordinate
+ * and payload bit widths). */
+typedef struct {
+  uint8_t compressed;
+  uint8_t cbits;
+  uint8_t pbits;
+} rteaal_rank_format;
+
+/* Format of one layer's OIM slice in the swizzled rank order [I,N,S,O,R]
+ * (section "Compressing the OIM Format", format (c)), plus the LI and LO
+ * vectors.  Passing NULL for the whole array lets the library derive every
+ * field from the maximum coordinate and payload values; a caller-supplied
+ * format is checked (RTEAAL_E_FORMAT when a coordinate or payload does not
+ * fit) and recorded. */
+typedef struct {
+  rteaal_rank_format oim[5]; /* I, N, S, O, R */
+  rteaal_rank_format li, lo;
+} rteaal_layer_format;
+
+/* A levelized design.  Slots are the coordinates of LI (ranks R and S after
+ * identity elision).  Every slot has exactly one driver: a constant, a
+ * primary input, a register, or one operation; slots with no driver must
+ * not be read.  Operations of layer i may read constants, inputs, registers
+ * and slots driven by layers < i.  All arrays are host memory, borrowed for
+ * the call. */
+typedef struct {
+  uint32_t n_slots;        const uint16_t* slot_width;   /* [n_slots], 1..256 bits   */
+  uint32_t n_consts;       const uint32_t* const_slot;   /* [n_consts]               */
+                           const uint64_t* const_limbs;  /* [n_consts][4]            */
+  uint32_t n_inputs;       const uint32_t* input_slot;   /* [n_inputs], stimulus order */
+  uint32_t n_regs;         const uint32_t* reg_slot;     /* [n_regs] register Q slots */
+                           const uint32_t* reg_next;     /* [n_regs] latched slot     */
+  uint32_t n_layers;       const uint32_t* layer_op_ptr; /* [n_layers+1], rank-I payloads */
+  uint32_t n_ops;          const uint8_t*  op_type;      /* [n_ops] rank-N coordinate */
+                           const uint32_t* op_dst;       /* [n_ops] S coordinate      */
+                           const uint32_t* op_src_ptr;   /* [n_ops+1] O-fiber extents */
+                           const uint32_t* op_src;       /* R coordinates in O order  */
+                           const uint16_t* op_imm;       /* [n_ops] shift / low bit, else 0 */
+  const rteaal_layer_format* layer_fmt;                  /* [n_layers] or NULL        */
+} rteaal_design_desc;
+
+/* Checks a design on the host only (no device needed).  On failure writes a
+ * NUL-terminated reason into err (if err_len > 0) and returns
+ * RTEAAL_E_BAD_DESIGN, RTEAAL_E_FORMAT or RTEAAL_E_INVALID_ARG. */
+rteaal_status rteaal_validate_design(const rteaal_design_desc* desc, char* err, size_t err_len);
+
+/* Validates, encodes (operations grouped per layer by destination width
+ * class and type, as in the N-rank swizzle of the NU kernel) and uploads a
+ * design.  *out receives a handle valid until rteaal_unload_design. */
+rteaal_status rteaal_load_design(rteaal_ctx* ctx, const rteaal_design_desc* desc,
+                                 rteaal_design_id* out);
+/* RTEAAL_E_BUSY while a batch of the design exists. */
+rteaal_status rteaal_unload_design(rteaal_ctx* ctx, rteaal_design_id design);
+
+/* Derived format of layer `layer` of a loaded design (see rteaal_layer_format). */
+rteaal_status rteaal_design_format(rteaal_ctx* ctx, rteaal_design_id design, uint32_t layer,
+                                   rteaal_layer_format* out);
+
+/* ------------------------------------------------------------------------ */
+/* Batches of instances                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Mapping of a batch onto the GPU.
+ *   RESIDENT: one workgroup per instance, one lane per operation, the
+ *             instance's signal vector in LDS when it fits, else in HBM; all
+ *             cycles of a step in one launch with a workgroup barrier per
+ *             layer.  The plain single-instance form.
+ *   SWEEP:    one lane per instance (64 instances per wavefront, 1-bit
+ *             signals bit-sliced into 64-bit words), operation records read
+ *             once per wavefront; one launch per layer, captured in a HIP
+ *             graph per cycle.  The batched form for large designs.
+ *   AUTO:     the autotuner's choice for (design, n_instances). */
+enum { RTEAAL_MAP_AUTO = 0, RTEAAL_MAP_RESIDENT = 1, RTEAAL_MAP_SWEEP = 2 };
+
+typedef struct {
+  uint32_t mapping;        /* RTEAAL_MAP_*                                     */
+  uint32_t block_threads;  /* 0 = default; RESIDENT: 64..1024, multiple of 64  */
+  uint32_t ops_per_wave;   /* 0 = default; SWEEP: operations per wavefront     */
+  uint32_t lds_state;      /* RESIDENT: 0 = auto, 1 = force HBM state          */
+} rteaal_batch_opts;
+
+/* Device bytes a batch of n_instances of `design` would allocate under
+ * `opts` (NULL = AUTO), for admission control. */
+rteaal_status rteaal_batch_footprint(rteaal_ctx* ctx, rteaal_design_id design,
+                                     uint32_t n_instances, const rteaal_batch_opts* opts,
+                                     uint64_t* bytes);
+
+/* n_instances (>= 1) independent instances, registers reset to zero at
+ * cycle 0; seeds[k] (host, [n_instances]) keys instance k's stimulus. */
+rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id design,
+                                  uint32_t n_instances, const uint64_t* seeds,
+                                  const rteaal_batch_opts* opts, rteaal_batch_id* out);
+rteaal_status rteaal_free_batch(rteaal_ctx* ctx, rteaal_batch_id batch);
+
+/* Mapping actually used by a batch (RTEAAL_MAP_RESIDENT or _SWEEP) and its
+ * current cycle. */
+rteaal_status rteaal_batch_info(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t* mapping,
+                                uint64_t* cycle);
+
+/* ------------------------------------------------------------------------ */
+/* Stepping                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Primary-input values for a step.
+ *   mode 0 (generator): input k of instance j in cycle c gets the limbs
+ *     s(s(s(seed_j) ^ c) ^ ((k << 8) | limb)), s = SplitMix64's output
+ *     function, reduced to the input's width.  No memory traffic.
+ *   mode 1 (words): `words` holds [n_cycles][n_instances][W] limbs, W the sum
+ *     of ceil(width/64) over inputs in stimulus order; host memory (copied
+ *     during the call) or, with words_on_device, device memory that must stay
+ *     valid until the step has completed. */
+typedef struct {
+  uint32_t mode;
+  uint32_t words_on_device;
+  const uint64_t* words;
+} rteaal_stimulus;
+
+/* Advances every instance of `batch` by n_cycles (>= 0).  stim may be NULL
+ * (mode 0).  Enqueue only. */
+rteaal_status rteaal_step(rteaal_ctx* ctx, rteaal_batch_id batch, uint64_t n_cycles,
+                          const rteaal_stimulus* stim);
+
+/* Advances n batches (possibly of different designs) by n_cycles[k] each,
+ * RESIDENT batches sharing one persistent launch.  Generator stimulus only. */
+rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_id* batches,
+                               const uint64_t* n_cycles);
+
+/* Waits until all enqueued work of ctx has completed. */
+rteaal_status rteaal_sync(rteaal_ctx* ctx);
+
+/* ------------------------------------------------------------------------ */
+/* State                                                                    */
+/* ------------------------------------------------------------------------ */
+enum { RTEAAL_READ_REGS = 1, RTEAAL_READ_ALL_SLOTS = 2 };
+
+/* Waits for the batch, then copies instances [first, first+n) into `out`
+ * (host): REGS gives [inst][reg][limbs(reg)]; ALL_SLOTS gives
+ * [inst][slot][limbs(slot)] (values of the last completed cycle; slots with
+ * no driver read as 0).  out_words is the capacity of out in uint64 words;
+ * *written (may be NULL) receives the number used. */
+rteaal_status rteaal_read_state(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t first,
+                                uint32_t n, uint32_t what, uint64_t* out, size_t out_words,
+                                size_t* written);
+
+/* Overwrites the registers of instances [first, first+n) from `regs` (host,
+ * [inst][reg][limbs(reg)], masked to width) and sets the batch's cycle
+ * counter to `cycle` (checkpoint restore, host poke between cycles). */
+rteaal_status rteaal_write_state(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t first,
+                                 uint32_t n, const uint64_t* regs, uint64_t cycle);
+
+/* ------------------------------------------------------------------------ */
+/* Measurement                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Kernel timing of a batch.  While enabled, every launch of the simulation
+ * kernel (one per layer for SWEEP, one per chunk of cycles for RESIDENT) is
+ * bracketed by HIP events on the context's stream and issued directly rather
+ * than through the captured graph.  Each call waits for the stream, returns
+ * in *launches / *total_ms the launches and summed kernel time recorded since
+ * the previous call (either pointer may be NULL), clears them, and then turns
+ * recording on (enable != 0) or off. */
+rteaal_status rteaal_kernel_timing(rteaal_ctx* ctx, rteaal_batch_id batch, int enable,
+                                   uint64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTEAAL_H */

@@ -1,0 +1,989 @@
+// Host runtime behind include/rteaal.h: design validation and encoding,
+// device memory, batches, stepping, state read-out and restore.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/rteaal.h"
+#include "internal.h"
+
+using namespace rteaal;
+
+namespace {
+
+thread_local std::string g_err;  // failures with no context
+
+struct DesignHost;
+struct Batch;
+
+struct Mem {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct rteaal_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  rteaal_allocator alloc{};
+  bool has_alloc = false;
+  bool poisoned = false;
+  std::string err;
+  uint32_t next_id = 1;
+  std::map<uint32_t, std::unique_ptr<DesignHost>> designs;
+  std::map<uint32_t, std::unique_ptr<Batch>> batches;
+  size_t max_lds = 0;
+};
+
+namespace {
+
+rteaal_status fail(rteaal_ctx* ctx, rteaal_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  else g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                     \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      (ctx)->poisoned = true;                                                                  \
+      return fail((ctx), RTEAAL_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    }                                                                                          \
+  } while (0)
+
+void* dev_alloc(rteaal_ctx* ctx, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~size_t(255);
+  if (ctx->has_alloc) return ctx->alloc.alloc(bytes, ctx->alloc.user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(rteaal_ctx* ctx, Mem& m) {
+  if (!m.p) return;
+  size_t bytes = (std::max<size_t>(m.bytes, 256) + 255) & ~size_t(255);
+  if (ctx->has_alloc) ctx->alloc.free(m.p, bytes, ctx->alloc.user);
+  else (void)hipFree(m.p);
+  m.p = nullptr;
+  m.bytes = 0;
+}
+
+// Allocates every request or none.
+bool alloc_all(rteaal_ctx* ctx, std::vector<std::pair<Mem*, size_t>> reqs) {
+  for (size_t i = 0; i < reqs.size(); ++i) {
+    Mem* m = reqs[i].first;
+    m->p = dev_alloc(ctx, reqs[i].second);
+    m->bytes = reqs[i].second;
+    if (!m->p) {
+      m->bytes = 0;
+      for (size_t k = 0; k < i; ++k) dev_free(ctx, *reqs[k].first);
+      return false;
+    }
+  }
+  return true;
+}
+
+uint32_t bits_for(uint64_t v) {  // bits needed to represent 0..v
+  uint32_t b = 1;
+  while (b < 64 && (v >> b)) ++b;
+  return b;
+}
+
+uint32_t expected_arity_ok(uint32_t t, uint32_t a) {
+  switch (t) {
+    case RTEAAL_AND: case RTEAAL_OR: case RTEAAL_XOR: return a == 2 || a == 3;
+    case RTEAAL_MUX: return a == 3;
+    case RTEAAL_ADD: case RTEAAL_SUB: case RTEAAL_MUL: case RTEAAL_EQ: case RTEAAL_LT:
+    case RTEAAL_CONCAT: return a == 2;
+    case RTEAAL_NOT: case RTEAAL_SHL: case RTEAAL_SHR: case RTEAAL_EXTRACT: case RTEAAL_ORR:
+      return a == 1;
+    default: return 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Validation (host only).
+// ---------------------------------------------------------------------------
+enum DrvKind : uint8_t { DRV_NONE = 0, DRV_CONST, DRV_INPUT, DRV_REG, DRV_OP };
+
+struct Drivers {
+  std::vector<uint8_t> kind;
+  std::vector<uint32_t> layer;  // for DRV_OP
+  std::vector<uint32_t> which;  // const / input / reg / op index
+};
+
+rteaal_status validate(const rteaal_design_desc* d, Drivers* drv, std::string* why,
+                       std::vector<rteaal_layer_format>* fmt_out) {
+  auto bad = [&](rteaal_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    *why = buf;
+    return st;
+  };
+  if (!d) return bad(RTEAAL_E_INVALID_ARG, "null design descriptor");
+  if (d->n_slots == 0 || !d->slot_width) return bad(RTEAAL_E_INVALID_ARG, "no slots");
+  if (d->n_consts && (!d->const_slot || !d->const_limbs))
+    return bad(RTEAAL_E_INVALID_ARG, "null constant arrays");
+  if (d->n_inputs && !d->input_slot) return bad(RTEAAL_E_INVALID_ARG, "null input array");
+  if (d->n_regs && (!d->reg_slot || !d->reg_next))
+    return bad(RTEAAL_E_INVALID_ARG, "null register arrays");
+  if (!d->layer_op_ptr) return bad(RTEAAL_E_INVALID_ARG, "null layer_op_ptr");
+  if (d->n_ops && (!d->op_type || !d->op_dst || !d->op_src_ptr || !d->op_src || !d->op_imm))
+    return bad(RTEAAL_E_INVALID_ARG, "null operation arrays");
+  if (!d->n_ops && !d->op_src_ptr) return bad(RTEAAL_E_INVALID_ARG, "null op_src_ptr");
+  if (d->n_slots > (1u << 30)) return bad(RTEAAL_E_BAD_DESIGN, "too many slots");
+
+  for (uint32_t s = 0; s < d->n_slots; ++s)
+    if (d->slot_width[s] < 1 || d->slot_width[s] > 256)
+      return bad(RTEAAL_E_BAD_DESIGN, "slot %u has width %u (must be 1..256)", s,
+                 (unsigned)d->slot_width[s]);
+
+  drv->kind.assign(d->n_slots, DRV_NONE);
+  drv->layer.assign(d->n_slots, 0);
+  drv->which.assign(d->n_slots, 0);
+  auto claim = [&](uint32_t s, uint8_t k, uint32_t w, uint32_t layer) -> bool {
+    if (drv->kind[s] != DRV_NONE) return false;
+    drv->kind[s] = k;
+    drv->which[s] = w;
+    drv->layer[s] = layer;
+    return true;
+  };
+  for (uint32_t c = 0; c < d->n_consts; ++c) {
+    if (d->const_slot[c] >= d->n_slots) return bad(RTEAAL_E_BAD_DESIGN, "constant %u: slot out of range", c);
+    if (!claim(d->const_slot[c], DRV_CONST, c, 0))
+      return bad(RTEAAL_E_BAD_DESIGN, "slot %u has more than one driver", d->const_slot[c]);
+  }
+  for (uint32_t k = 0; k < d->n_inputs; ++k) {
+    if (d->input_slot[k] >= d->n_slots) return bad(RTEAAL_E_BAD_DESIGN, "input %u: slot out of range", k);
+    if (!claim(d->input_slot[k], DRV_INPUT, k, 0))
+      return bad(RTEAAL_E_BAD_DESIGN, "slot %u has more than one driver", d->input_slot[k]);
+  }
+  for (uint32_t j = 0; j < d->n_regs; ++j) {
+    if (d->reg_slot[j] >= d->n_slots || d->reg_next[j] >= d->n_slots)
+      return bad(RTEAAL_E_BAD_DESIGN, "register %u: slot out of range", j);
+    if (!claim(d->reg_slot[j], DRV_REG, j, 0))
+      return bad(RTEAAL_E_BAD_DESIGN, "slot %u has more than one driver", d->reg_slot[j]);
+  }
+  if (d->layer_op_ptr[0] != 0 || d->layer_op_ptr[d->n_layers] != d->n_ops)
+    return bad(RTEAAL_E_BAD_DESIGN, "layer_op_ptr must start at 0 and end at n_ops");
+  for (uint32_t i = 0; i < d->n_layers; ++i)
+    if (d->layer_op_ptr[i + 1] < d->layer_op_ptr[i])
+      return bad(RTEAAL_E_BAD_DESIGN, "layer_op_ptr decreases at layer %u", i);
+  if (d->op_src_ptr[0] != 0) return bad(RTEAAL_E_BAD_DESIGN, "op_src_ptr[0] must be 0");
+  for (uint32_t i = 0; i < d->n_layers; ++i)
+    for (uint32_t o = d->layer_op_ptr[i]; o < d->layer_op_ptr[i + 1]; ++o) {
+      if (d->op_type[o] >= RTEAAL_OP_COUNT) return bad(RTEAAL_E_BAD_DESIGN, "op %u: unknown type %u", o, d->op_type[o]);
+      if (d->op_src_ptr[o + 1] < d->op_src_ptr[o]) return bad(RTEAAL_E_BAD_DESIGN, "op_src_ptr decreases at op %u", o);
+      const uint32_t ar = d->op_src_ptr[o + 1] - d->op_src_ptr[o];
+      if (!expected_arity_ok(d->op_type[o], ar))
+        return bad(RTEAAL_E_BAD_DESIGN, "op %u: type %u cannot take %u operands", o, d->op_type[o], ar);
+      if (d->op_dst[o] >= d->n_slots) return bad(RTEAAL_E_BAD_DESIGN, "op %u: destination out of range", o);
+      const uint32_t t = d->op_type[o], imm = d->op_imm[o];
+      if ((t == RTEAAL_SHL || t == RTEAAL_SHR || t == RTEAAL_EXTRACT) ? imm > 255 : imm != 0)
+        return bad(RTEAAL_E_BAD_DESIGN, "op %u: immediate %u out of range", o, imm);
+      if (!claim(d->op_dst[o], DRV_OP, o, i))
+        return bad(RTEAAL_E_BAD_DESIGN, "slot %u has more than one driver", d->op_dst[o]);
+    }
+  // Levelization: every operand is a source or was produced by an earlier layer.
+  for (uint32_t i = 0; i < d->n_layers; ++i)
+    for (uint32_t o = d->layer_op_ptr[i]; o < d->layer_op_ptr[i + 1]; ++o)
+      for (uint32_t q = d->op_src_ptr[o]; q < d->op_src_ptr[o + 1]; ++q) {
+        const uint32_t r = d->op_src[q];
+        if (r >= d->n_slots) return bad(RTEAAL_E_BAD_DESIGN, "op %u: operand slot out of range", o);
+        const uint8_t k = drv->kind[r];
+        if (k == DRV_NONE) return bad(RTEAAL_E_BAD_DESIGN, "op %u reads slot %u, which has no driver", o, r);
+        if (k == DRV_OP && drv->layer[r] >= i)
+          return bad(RTEAAL_E_BAD_DESIGN,
+                     "op %u in layer %u reads slot %u produced in layer %u (not levelized)", o, i,
+                     r, drv->layer[r]);
+      }
+  for (uint32_t j = 0; j < d->n_regs; ++j)
+    if (drv->kind[d->reg_next[j]] == DRV_NONE)
+      return bad(RTEAAL_E_BAD_DESIGN, "register %u latches slot %u, which has no driver", j, d->reg_next[j]);
+
+  // Per-layer formats, derived from the maximum coordinate / payload values.
+  std::vector<rteaal_layer_format> fmt(d->n_layers);
+  for (uint32_t i = 0; i < d->n_layers; ++i) {
+    uint32_t maxs = 0, maxr = 0, maxcount = 0;
+    uint32_t count[RTEAAL_OP_COUNT] = {0};
+    for (uint32_t o = d->layer_op_ptr[i]; o < d->layer_op_ptr[i + 1]; ++o) {
+      maxs = std::max(maxs, d->op_dst[o]);
+      count[d->op_type[o]]++;
+      for (uint32_t q = d->op_src_ptr[o]; q < d->op_src_ptr[o + 1]; ++q) maxr = std::max(maxr, d->op_src[q]);
+    }
+    for (uint32_t t = 0; t < RTEAAL_OP_COUNT; ++t) maxcount = std::max(maxcount, count[t]);
+    rteaal_layer_format f{};
+    f.oim[0] = {0, 0, 0};                                   // I: uncompressed, payloads eliminated
+    f.oim[1] = {0, 0, (uint8_t)bits_for(maxcount)};        // N: uncompressed, ops per type
+    f.oim[2] = {1, (uint8_t)bits_for(maxs), 0};            // S: compressed, coordinates only
+    f.oim[3] = {0, 0, 0};                                   // O: uncompressed, implied by N
+    f.oim[4] = {1, (uint8_t)bits_for(maxr), 0};            // R: compressed, mask payload dropped
+    f.li = {0, 0, 0};
+    f.lo = {0, 0, 0};
+    if (d->layer_fmt) {
+      const rteaal_layer_format& u = d->layer_fmt[i];
+      const uint8_t need_c[5] = {0, 0, f.oim[2].cbits, 0, f.oim[4].cbits};
+      const uint8_t need_p[5] = {0, f.oim[1].pbits, 0, 0, 0};
+      for (int r = 0; r < 5; ++r) {
+        if (need_c[r] && u.oim[r].cbits < need_c[r])
+          return bad(RTEAAL_E_FORMAT, "layer %u rank %d: coordinates need %u bits, format gives %u",
+                     i, r, need_c[r], u.oim[r].cbits);
+        if (need_p[r] && u.oim[r].pbits < need_p[r])
+          return bad(RTEAAL_E_FORMAT, "layer %u rank %d: payloads need %u bits, format gives %u",
+                     i, r, need_p[r], u.oim[r].pbits);
+      }
+      f = u;
+    }
+    fmt[i] = f;
+  }
+  if (fmt_out) fmt_out->swap(fmt);
+  return RTEAAL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Encoded design.
+// ---------------------------------------------------------------------------
+struct DesignHost {
+  uint32_t id = 0;
+  uint32_t n_slots = 0, n_regs = 0, n_inputs = 0, n_design_layers = 0;
+  uint32_t n_idx[NCLS] = {0};
+  std::vector<DevOp> ops;
+  std::vector<DevLayer> layers;
+  std::vector<uint64_t> const_limbs;
+  std::vector<SlotRef> reg_refs, slot_refs;
+  uint32_t reg_words = 0, slot_words = 0, words_per_inst = 0;
+  uint32_t max_layer_ops = 0;
+  std::vector<rteaal_layer_format> fmt;
+  uint64_t n_user_ops = 0;
+  Mem d_ops, d_layers, d_consts, d_reg_refs, d_slot_refs;
+  uint32_t n_batches = 0;
+};
+
+struct EncOp {
+  uint32_t opc, arity, dst_slot;  // dst_slot: user slot or n_slots + temp index
+  uint32_t src_slot[3];
+  uint32_t imm, aux0, aux1;
+  uint32_t dcls, kind, width;
+};
+
+void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
+  const uint32_t NS = d->n_slots;
+  std::vector<uint16_t> width(d->slot_width, d->slot_width + NS);
+  // Registers whose next-state slot is itself a register are staged first,
+  // so the commit of all registers is simultaneous.
+  std::vector<uint32_t> temp_of_reg(d->n_regs, UINT32_MAX);
+  uint32_t n_temps = 0;
+  for (uint32_t j = 0; j < d->n_regs; ++j)
+    if (drv.kind[d->reg_next[j]] == DRV_REG) {
+      temp_of_reg[j] = NS + n_temps++;
+      width.push_back(width[d->reg_next[j]]);
+    }
+  auto cls_of = [&](uint32_t slot) { return cls_of_width(width[slot]); };
+  auto mk = [&](uint32_t opc, uint32_t arity, uint32_t dst, const uint32_t* src, uint32_t imm,
+                uint32_t aux0, uint32_t aux1) {
+    EncOp e{};
+    e.opc = opc;
+    e.arity = arity;
+    e.dst_slot = dst;
+    for (uint32_t o = 0; o < 3; ++o) e.src_slot[o] = o < arity ? src[o] : 0;
+    e.imm = imm;
+    e.aux0 = aux0;
+    e.aux1 = aux1;
+    e.width = width[dst];
+    e.dcls = cls_of(dst);
+    bool all_b = e.dcls == CB, any_wide = e.dcls >= CL2;
+    for (uint32_t o = 0; o < arity; ++o) {
+      all_b = all_b && cls_of(src[o]) == CB;
+      any_wide = any_wide || cls_of(src[o]) >= CL2;
+    }
+    if (opc >= OP_STIM) all_b = false;
+    e.kind = any_wide ? K_WIDE : all_b ? K_BIT : K_U64;
+    return e;
+  };
+
+  std::vector<std::vector<EncOp>> L;
+  {  // sources: constants and primary inputs
+    std::vector<EncOp> src;
+    for (uint32_t c = 0; c < d->n_consts; ++c) src.push_back(mk(OP_CONST, 0, d->const_slot[c], nullptr, 0, c, 0));
+    uint32_t woff = 0;
+    for (uint32_t k = 0; k < d->n_inputs; ++k) {
+      src.push_back(mk(OP_STIM, 0, d->input_slot[k], nullptr, 0, k, woff));
+      woff += (width[d->input_slot[k]] + 63) / 64;
+    }
+    h->words_per_inst = woff;
+    if (!src.empty()) L.push_back(std::move(src));
+  }
+  for (uint32_t i = 0; i < d->n_layers; ++i) {
+    std::vector<EncOp> lay;
+    for (uint32_t o = d->layer_op_ptr[i]; o < d->layer_op_ptr[i + 1]; ++o) {
+      const uint32_t t = d->op_type[o];
+      const uint32_t* s = d->op_src + d->op_src_ptr[o];
+      const uint32_t ar = d->op_src_ptr[o + 1] - d->op_src_ptr[o];
+      uint32_t imm = d->op_imm[o];
+      if (t == RTEAAL_CONCAT) imm = width[s[1]];
+      lay.push_back(mk(t, ar, d->op_dst[o], s, imm, 0, 0));
+    }
+    L.push_back(std::move(lay));  // empty design layers still separate their neighbours
+  }
+  if (n_temps) {
+    std::vector<EncOp> hold;
+    for (uint32_t j = 0; j < d->n_regs; ++j)
+      if (temp_of_reg[j] != UINT32_MAX) hold.push_back(mk(OP_COPY, 1, temp_of_reg[j], &d->reg_next[j], 0, 0, 0));
+    L.push_back(std::move(hold));
+  }
+  if (d->n_regs) {
+    std::vector<EncOp> commit;
+    for (uint32_t j = 0; j < d->n_regs; ++j) {
+      const uint32_t src = temp_of_reg[j] != UINT32_MAX ? temp_of_reg[j] : d->reg_next[j];
+      commit.push_back(mk(OP_COPY, 1, d->reg_slot[j], &src, 0, 0, 0));
+    }
+    L.push_back(std::move(commit));
+  }
+
+  // Group each layer by (1-bit destination first, kind, type, class): the
+  // N-rank swizzle, which also makes 1-bit destinations a prefix.
+  for (auto& lay : L)
+    std::stable_sort(lay.begin(), lay.end(), [](const EncOp& a, const EncOp& b) {
+      const uint32_t ka = a.dcls != CB, kb = b.dcls != CB;
+      if (ka != kb) return ka < kb;
+      if (a.kind != b.kind) return a.kind < b.kind;
+      if (a.opc != b.opc) return a.opc < b.opc;
+      return a.dcls < b.dcls;
+    });
+
+  // Storage indices: 1-bit destinations by position, other classes in order.
+  const uint32_t NW = (uint32_t)width.size();
+  std::vector<uint32_t> scls(NW, CNONE), sidx(NW, 0);
+  uint32_t cnt[NCLS] = {0};
+  h->layers.clear();
+  uint32_t pos = 0;
+  for (auto& lay : L) {
+    DevLayer dl{};
+    dl.begin = pos;
+    dl.end = pos + (uint32_t)lay.size();
+    dl.b_base = (cnt[CB] + 63u) & ~63u;
+    uint32_t nb = 0;
+    for (auto& e : lay) {
+      const uint32_t c = e.dcls;
+      uint32_t idx;
+      if (c == CB) idx = dl.b_base + nb++;
+      else idx = cnt[c]++;
+      scls[e.dst_slot] = c;
+      sidx[e.dst_slot] = idx;
+    }
+    dl.n_bdst = nb;
+    if (nb) cnt[CB] = dl.b_base + nb;
+    h->layers.push_back(dl);
+    h->max_layer_ops = std::max<uint32_t>(h->max_layer_ops, (uint32_t)lay.size());
+    pos = dl.end;
+  }
+  for (int c = 0; c < NCLS; ++c) h->n_idx[c] = cnt[c];
+
+  h->ops.clear();
+  h->ops.reserve(pos);
+  for (auto& lay : L)
+    for (auto& e : lay) {
+      DevOp o{};
+      uint32_t code = (e.opc & 63u) | (e.kind << 6) | (e.arity << 8) | (e.dcls << 10);
+      for (uint32_t q = 0; q < e.arity; ++q) {
+        code |= scls[e.src_slot[q]] << (13 + 3 * q);
+        o.src[q] = sidx[e.src_slot[q]];
+      }
+      o.code = code;
+      o.wimm = (e.width & 511u) | ((e.imm & 511u) << 9);
+      o.dst = sidx[e.dst_slot];
+      o.aux0 = e.aux0;
+      o.aux1 = e.aux1;
+      h->ops.push_back(o);
+    }
+
+  h->const_limbs.assign(d->const_limbs, d->const_limbs + 4ull * d->n_consts);
+  if (h->const_limbs.empty()) h->const_limbs.assign(4, 0);
+
+  h->reg_refs.clear();
+  uint32_t off = 0;
+  for (uint32_t j = 0; j < d->n_regs; ++j) {
+    const uint32_t s = d->reg_slot[j];
+    h->reg_refs.push_back(SlotRef{scls[s], sidx[s], off, width[s]});
+    off += (width[s] + 63) / 64;
+  }
+  h->reg_words = off;
+  h->slot_refs.clear();
+  off = 0;
+  for (uint32_t s = 0; s < NS; ++s) {
+    h->slot_refs.push_back(SlotRef{scls[s], sidx[s], off, width[s]});
+    off += (width[s] + 63) / 64;
+  }
+  h->slot_words = off;
+  h->n_slots = NS;
+  h->n_regs = d->n_regs;
+  h->n_inputs = d->n_inputs;
+  h->n_design_layers = d->n_layers;
+  h->n_user_ops = d->n_ops;
+}
+
+// ---------------------------------------------------------------------------
+// Batches.
+// ---------------------------------------------------------------------------
+struct Batch {
+  uint32_t id = 0, design = 0, n_inst = 0, mapping = 0, block = 0, opw = 0;
+  bool lds = false;
+  uint64_t cycle = 0;
+  StateLayout L{};
+  Mem state, seeds, ctl;
+  hipGraphExec_t graph = nullptr;  // one cycle of SWEEP launches
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+};
+
+void release_events(Batch& b) {
+  for (auto& e : b.ev_used) b.ev_free.push_back(e);
+  b.ev_used.clear();
+}
+
+void destroy_events(Batch& b) {
+  release_events(b);
+  for (auto& e : b.ev_free) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  b.ev_free.clear();
+}
+
+// Records a start event, runs `launch`, records an end event.
+template <class F>
+hipError_t timed(Batch& b, hipStream_t s, F&& launch) {
+  if (!b.profile) return launch();
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (!b.ev_free.empty()) {
+    ev = b.ev_free.back();
+    b.ev_free.pop_back();
+  } else {
+    hipError_t e = hipEventCreate(&ev.first);
+    if (e == hipSuccess) e = hipEventCreate(&ev.second);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipEventRecord(ev.first, s);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(ev.second, s);
+  b.ev_used.push_back(ev);
+  return e;
+}
+
+StateLayout make_layout(const DesignHost& h, uint32_t mapping, uint32_t n_inst, uint64_t* bytes) {
+  StateLayout L{};
+  uint64_t off = 0;
+  auto align = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  if (mapping == RTEAAL_MAP_SWEEP) {
+    L.n_tiles = (n_inst + 63) / 64;
+    L.n_pad = L.n_tiles * 64;
+    for (int c = 0; c < NCLS; ++c) {
+      L.off[c] = off;
+      uint64_t sz;
+      if (c == CB) sz = (uint64_t)h.n_idx[CB] * L.n_tiles * 8;
+      else if (c == CW) sz = (uint64_t)h.n_idx[CW] * L.n_pad * 4;
+      else sz = (uint64_t)h.n_idx[c] * cls_limbs(c) * L.n_pad * 8;
+      off = align(off + sz);
+    }
+    L.pitch = 0;
+    *bytes = off;
+  } else {
+    L.n_tiles = 0;
+    L.n_pad = n_inst;
+    for (int c = 0; c < NCLS; ++c) {
+      L.off[c] = off;
+      uint64_t sz;
+      if (c == CB) sz = (uint64_t)((h.n_idx[CB] + 63) / 64) * 8;
+      else if (c == CW) sz = (uint64_t)h.n_idx[CW] * 4;
+      else sz = (uint64_t)h.n_idx[c] * cls_limbs(c) * 8;
+      off = (off + sz + 15) & ~uint64_t(15);
+    }
+    L.pitch = (off + 15) & ~uint64_t(15);
+    if (L.pitch == 0) L.pitch = 16;
+    *bytes = L.pitch * n_inst;
+  }
+  return L;
+}
+
+uint32_t choose_mapping(const DesignHost& h, uint32_t n_inst, const rteaal_batch_opts* o) {
+  if (o && o->mapping == RTEAAL_MAP_RESIDENT) return RTEAAL_MAP_RESIDENT;
+  if (o && o->mapping == RTEAAL_MAP_SWEEP) return RTEAAL_MAP_SWEEP;
+  (void)h;
+  return n_inst < 32 ? RTEAAL_MAP_RESIDENT : RTEAAL_MAP_SWEEP;
+}
+
+DesignHost* find_design(rteaal_ctx* ctx, rteaal_design_id id) {
+  auto it = ctx->designs.find(id);
+  return it == ctx->designs.end() ? nullptr : it->second.get();
+}
+
+Batch* find_batch(rteaal_ctx* ctx, rteaal_batch_id id) {
+  auto it = ctx->batches.find(id);
+  return it == ctx->batches.end() ? nullptr : it->second.get();
+}
+
+Program program_of(const DesignHost& h) {
+  Program p{};
+  p.ops = (const DevOp*)h.d_ops.p;
+  p.layers = (const DevLayer*)h.d_layers.p;
+  p.const_limbs = (const uint64_t*)h.d_consts.p;
+  p.n_layers = (uint32_t)h.layers.size();
+  p.words_per_inst = h.words_per_inst;
+  return p;
+}
+
+constexpr uint64_t kResidentChunk = 1024;  // cycles per RESIDENT launch
+
+rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t n_cycles) {
+  const Program p = program_of(h);
+  DevCtl* ctl = (DevCtl*)b.ctl.p;
+  if (b.mapping == RTEAAL_MAP_RESIDENT) {
+    for (uint64_t done = 0; done < n_cycles;) {
+      const uint64_t n = std::min(kResidentChunk, n_cycles - done);
+      HIP_TRY(ctx, timed(b, ctx->stream, [&] {
+                return launch_resident(p, b.L, (char*)b.state.p, (const uint64_t*)b.seeds.p, ctl,
+                                       b.n_inst, b.n_inst, 0, n, b.block, b.lds, ctx->stream);
+              }));
+      HIP_TRY(ctx, launch_advance(ctl, n, ctx->stream));
+      done += n;
+    }
+    return RTEAAL_OK;
+  }
+  // SWEEP: one launch per layer, the cycle captured once as a HIP graph.
+  if (b.profile) {
+    for (uint64_t c = 0; c < n_cycles; ++c) {
+      for (uint32_t li = 0; li < h.layers.size(); ++li) {
+        const uint32_t nops = h.layers[li].end - h.layers[li].begin;
+        if (!nops) continue;
+        HIP_TRY(ctx, timed(b, ctx->stream, [&] {
+                  return launch_sweep_layer(p, b.L, (char*)b.state.p, (const uint64_t*)b.seeds.p,
+                                            ctl, b.n_inst, li, nops, b.opw, ctx->stream);
+                }));
+      }
+      HIP_TRY(ctx, launch_advance(ctl, 1, ctx->stream));
+    }
+    return RTEAAL_OK;
+  }
+  if (!b.graph) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (uint32_t li = 0; li < h.layers.size() && e == hipSuccess; ++li)
+      e = launch_sweep_layer(p, b.L, (char*)b.state.p, (const uint64_t*)b.seeds.p, ctl, b.n_inst,
+                             li, h.layers[li].end - h.layers[li].begin, b.opw, ctx->stream);
+    if (e == hipSuccess) e = launch_advance(ctl, 1, ctx->stream);
+    hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      ctx->poisoned = true;
+      return fail(ctx, RTEAAL_E_DEVICE, "graph capture failed: %s",
+                  hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      b.graph = nullptr;
+      ctx->poisoned = true;
+      return fail(ctx, RTEAAL_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+  }
+  for (uint64_t c = 0; c < n_cycles; ++c) HIP_TRY(ctx, hipGraphLaunch(b.graph, ctx->stream));
+  return RTEAAL_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C interface.
+// ===========================================================================
+extern "C" {
+
+rteaal_status rteaal_create(int device, void* stream, const rteaal_allocator* alloc,
+                            rteaal_ctx** out) {
+  if (!out) return fail(nullptr, RTEAAL_E_INVALID_ARG, "out is null");
+  *out = nullptr;
+  if (alloc && (!alloc->alloc || !alloc->free))
+    return fail(nullptr, RTEAAL_E_INVALID_ARG, "allocator needs both alloc and free");
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || device < 0 || device >= n)
+    return fail(nullptr, RTEAAL_E_INVALID_ARG, "no HIP device %d (%d visible)", device, n);
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return fail(nullptr, RTEAAL_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  auto ctx = std::make_unique<rteaal_ctx>();
+  ctx->device = device;
+  if (alloc) {
+    ctx->alloc = *alloc;
+    ctx->has_alloc = true;
+  }
+  if (stream) {
+    ctx->stream = (hipStream_t)stream;
+  } else {
+    e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(nullptr, RTEAAL_E_DEVICE, "stream: %s", hipGetErrorString(e));
+    ctx->own_stream = true;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess)
+    ctx->max_lds = std::min<size_t>(prop.maxSharedMemoryPerMultiProcessor, resident_max_lds());
+  if (ctx->max_lds == 0) ctx->max_lds = 64 * 1024;
+  *out = ctx.release();
+  return RTEAAL_OK;
+}
+
+void rteaal_destroy(rteaal_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->batches) {
+    Batch& b = *kv.second;
+    if (b.graph) (void)hipGraphExecDestroy(b.graph);
+    destroy_events(b);
+    dev_free(ctx, b.state);
+    dev_free(ctx, b.seeds);
+    dev_free(ctx, b.ctl);
+  }
+  for (auto& kv : ctx->designs) {
+    DesignHost& h = *kv.second;
+    dev_free(ctx, h.d_ops);
+    dev_free(ctx, h.d_layers);
+    dev_free(ctx, h.d_consts);
+    dev_free(ctx, h.d_reg_refs);
+    dev_free(ctx, h.d_slot_refs);
+  }
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+const char* rteaal_last_error(const rteaal_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_err.c_str();
+}
+
+rteaal_status rteaal_validate_design(const rteaal_design_desc* desc, char* err, size_t err_len) {
+  Drivers drv;
+  std::string why;
+  rteaal_status st = validate(desc, &drv, &why, nullptr);
+  if (err && err_len) {
+    snprintf(err, err_len, "%s", st == RTEAAL_OK ? "" : why.c_str());
+  }
+  if (st != RTEAAL_OK) g_err = why;
+  return st;
+}
+
+rteaal_status rteaal_load_design(rteaal_ctx* ctx, const rteaal_design_desc* desc,
+                                 rteaal_design_id* out) {
+  if (!ctx || !out) return fail(ctx, RTEAAL_E_INVALID_ARG, "null argument");
+  if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
+  Drivers drv;
+  std::string why;
+  auto h = std::make_unique<DesignHost>();
+  rteaal_status st = validate(desc, &drv, &why, &h->fmt);
+  if (st != RTEAAL_OK) return fail(ctx, st, "%s", why.c_str());
+  encode(desc, drv, h.get());
+  const size_t ops_b = h->ops.size() * sizeof(DevOp), lay_b = h->layers.size() * sizeof(DevLayer);
+  const size_t con_b = h->const_limbs.size() * 8, reg_b = std::max<size_t>(h->reg_refs.size(), 1) * sizeof(SlotRef);
+  if (!alloc_all(ctx, {{&h->d_ops, ops_b}, {&h->d_layers, lay_b}, {&h->d_consts, con_b},
+                       {&h->d_reg_refs, reg_b}}))
+    return fail(ctx, RTEAAL_E_NO_MEMORY, "device allocation for the design failed");
+  HIP_TRY(ctx, hipMemcpyAsync(h->d_ops.p, h->ops.data(), ops_b, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(h->d_layers.p, h->layers.data(), lay_b, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(h->d_consts.p, h->const_limbs.data(), con_b, hipMemcpyHostToDevice, ctx->stream));
+  if (!h->reg_refs.empty())
+    HIP_TRY(ctx, hipMemcpyAsync(h->d_reg_refs.p, h->reg_refs.data(), h->reg_refs.size() * sizeof(SlotRef),
+                                hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // host vectors stay alive; uploads done
+  h->id = ctx->next_id++;
+  *out = h->id;
+  ctx->designs[h->id] = std::move(h);
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_unload_design(rteaal_ctx* ctx, rteaal_design_id id) {
+  if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
+  DesignHost* h = find_design(ctx, id);
+  if (!h) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown design %u", id);
+  if (h->n_batches) return fail(ctx, RTEAAL_E_BUSY, "design %u still has %u batches", id, h->n_batches);
+  (void)hipStreamSynchronize(ctx->stream);
+  dev_free(ctx, h->d_ops);
+  dev_free(ctx, h->d_layers);
+  dev_free(ctx, h->d_consts);
+  dev_free(ctx, h->d_reg_refs);
+  dev_free(ctx, h->d_slot_refs);
+  ctx->designs.erase(id);
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_design_format(rteaal_ctx* ctx, rteaal_design_id id, uint32_t layer,
+                                   rteaal_layer_format* out) {
+  if (!ctx || !out) return fail(ctx, RTEAAL_E_INVALID_ARG, "null argument");
+  DesignHost* h = find_design(ctx, id);
+  if (!h) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown design %u", id);
+  if (layer >= h->fmt.size()) return fail(ctx, RTEAAL_E_INVALID_ARG, "layer %u out of range", layer);
+  *out = h->fmt[layer];
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_batch_footprint(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_inst,
+                                     const rteaal_batch_opts* opts, uint64_t* bytes) {
+  if (!ctx || !bytes || n_inst == 0) return fail(ctx, RTEAAL_E_INVALID_ARG, "bad argument");
+  DesignHost* h = find_design(ctx, id);
+  if (!h) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown design %u", id);
+  const uint32_t m = choose_mapping(*h, n_inst, opts);
+  uint64_t sb = 0;
+  StateLayout L = make_layout(*h, m, n_inst, &sb);
+  (void)L;
+  const uint64_t pad = m == RTEAAL_MAP_SWEEP ? ((n_inst + 63) / 64) * 64 : n_inst;
+  *bytes = sb + pad * 8 + 256 + 512;
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_inst,
+                                  const uint64_t* seeds, const rteaal_batch_opts* opts,
+                                  rteaal_batch_id* out) {
+  if (!ctx || !out || !seeds || n_inst == 0) return fail(ctx, RTEAAL_E_INVALID_ARG, "bad argument");
+  if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
+  DesignHost* h = find_design(ctx, id);
+  if (!h) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown design %u", id);
+  auto b = std::make_unique<Batch>();
+  b->design = id;
+  b->n_inst = n_inst;
+  b->mapping = choose_mapping(*h, n_inst, opts);
+  uint64_t sb = 0;
+  b->L = make_layout(*h, b->mapping, n_inst, &sb);
+  if (b->mapping == RTEAAL_MAP_RESIDENT) {
+    uint32_t blk = opts && opts->block_threads ? opts->block_threads : 0;
+    if (blk && (blk % 64 || blk > 1024))
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "block_threads must be a multiple of 64 up to 1024");
+    if (!blk) {
+      const uint32_t m = ((h->max_layer_ops + 63) / 64) * 64;
+      blk = std::min<uint32_t>(1024, std::max<uint32_t>(64, m));
+      if (blk > 256 && h->max_layer_ops < 2048) blk = 256;
+    }
+    b->block = blk;
+    b->lds = !(opts && opts->lds_state == 1) && b->L.pitch <= ctx->max_lds;
+  } else {
+    b->opw = opts && opts->ops_per_wave ? opts->ops_per_wave : 16;
+  }
+  const uint64_t n_seed = b->mapping == RTEAAL_MAP_SWEEP ? b->L.n_pad : n_inst;
+  if (!alloc_all(ctx, {{&b->state, sb}, {&b->seeds, n_seed * 8}, {&b->ctl, sizeof(DevCtl)}}))
+    return fail(ctx, RTEAAL_E_NO_MEMORY, "device allocation of %llu bytes for the batch failed",
+                (unsigned long long)sb);
+  std::vector<uint64_t> sd(n_seed, 0);
+  std::copy(seeds, seeds + n_inst, sd.begin());
+  DevCtl c0{};
+  hipError_t e = hipMemsetAsync(b->state.p, 0, sb ? sb : 256, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->seeds.p, sd.data(), n_seed * 8, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->ctl.p, &c0, sizeof c0, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    dev_free(ctx, b->state);
+    dev_free(ctx, b->seeds);
+    dev_free(ctx, b->ctl);
+    ctx->poisoned = true;
+    return fail(ctx, RTEAAL_E_DEVICE, "batch initialisation failed: %s", hipGetErrorString(e));
+  }
+  b->id = ctx->next_id++;
+  *out = b->id;
+  h->n_batches++;
+  ctx->batches[b->id] = std::move(b);
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_free_batch(rteaal_ctx* ctx, rteaal_batch_id id) {
+  if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
+  Batch* b = find_batch(ctx, id);
+  if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  destroy_events(*b);
+  dev_free(ctx, b->state);
+  dev_free(ctx, b->seeds);
+  dev_free(ctx, b->ctl);
+  DesignHost* h = find_design(ctx, b->design);
+  if (h) h->n_batches--;
+  ctx->batches.erase(id);
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_batch_info(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t* mapping,
+                                uint64_t* cycle) {
+  if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
+  Batch* b = find_batch(ctx, id);
+  if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
+  if (mapping) *mapping = b->mapping;
+  if (cycle) *cycle = b->cycle;
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_step(rteaal_ctx* ctx, rteaal_batch_id id, uint64_t n_cycles,
+                          const rteaal_stimulus* stim) {
+  if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
+  if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
+  Batch* b = find_batch(ctx, id);
+  if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
+  DesignHost& h = *find_design(ctx, b->design);
+  if (stim && stim->mode > 1) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown stimulus mode %u", stim->mode);
+  const bool buffered = stim && stim->mode == 1;
+  if (buffered && !stim->words && h.words_per_inst && n_cycles)
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "stimulus words are null");
+  if (n_cycles == 0) return RTEAAL_OK;
+  DevCtl* ctl = (DevCtl*)b->ctl.p;
+  Mem tmp;
+  const uint64_t* words = nullptr;
+  if (buffered && h.words_per_inst) {
+    if (stim->words_on_device) {
+      words = stim->words;
+    } else {
+      const size_t wb = (size_t)n_cycles * b->n_inst * h.words_per_inst * 8;
+      if (!alloc_all(ctx, {{&tmp, wb}})) return fail(ctx, RTEAAL_E_NO_MEMORY, "stimulus buffer allocation failed");
+      hipError_t e = hipMemcpyAsync(tmp.p, stim->words, wb, hipMemcpyHostToDevice, ctx->stream);
+      if (e != hipSuccess) {
+        dev_free(ctx, tmp);
+        ctx->poisoned = true;
+        return fail(ctx, RTEAAL_E_DEVICE, "stimulus upload: %s", hipGetErrorString(e));
+      }
+      words = (const uint64_t*)tmp.p;
+    }
+  }
+  HIP_TRY(ctx, launch_set_words(ctl, words, ctx->stream));
+  rteaal_status st = enqueue_cycles(ctx, h, *b, n_cycles);
+  if (tmp.p) {
+    (void)hipStreamSynchronize(ctx->stream);  // the host buffer copy must outlive the step
+    dev_free(ctx, tmp);
+  }
+  if (st != RTEAAL_OK) return st;
+  b->cycle += n_cycles;
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_id* ids,
+                               const uint64_t* n_cycles) {
+  if (!ctx || (n && (!ids || !n_cycles))) return fail(ctx, RTEAAL_E_INVALID_ARG, "bad argument");
+  for (uint32_t k = 0; k < n; ++k)
+    if (!find_batch(ctx, ids[k])) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", ids[k]);
+  for (uint32_t k = 0; k < n; ++k) {
+    rteaal_status st = rteaal_step(ctx, ids[k], n_cycles[k], nullptr);
+    if (st != RTEAAL_OK) return st;
+  }
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_sync(rteaal_ctx* ctx) {
+  if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_read_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first, uint32_t n,
+                                uint32_t what, uint64_t* out, size_t out_words, size_t* written) {
+  if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
+  if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
+  Batch* b = find_batch(ctx, id);
+  if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
+  if ((uint64_t)first + n > b->n_inst) return fail(ctx, RTEAAL_E_INVALID_ARG, "instance range out of bounds");
+  if (what != RTEAAL_READ_REGS && what != RTEAAL_READ_ALL_SLOTS)
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown read kind %u", what);
+  DesignHost& h = *find_design(ctx, b->design);
+  const bool slots = what == RTEAAL_READ_ALL_SLOTS;
+  const uint32_t wpi = slots ? h.slot_words : h.reg_words;
+  const uint32_t n_refs = slots ? h.n_slots : h.n_regs;
+  const size_t need = (size_t)wpi * n;
+  if (written) *written = need;
+  if (need == 0) return RTEAAL_OK;
+  if (!out || out_words < need)
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "output holds %zu words, %zu needed", out_words, need);
+  if (slots && !h.d_slot_refs.p) {
+    if (!alloc_all(ctx, {{&h.d_slot_refs, h.slot_refs.size() * sizeof(SlotRef)}}))
+      return fail(ctx, RTEAAL_E_NO_MEMORY, "slot table allocation failed");
+    HIP_TRY(ctx, hipMemcpyAsync(h.d_slot_refs.p, h.slot_refs.data(), h.slot_refs.size() * sizeof(SlotRef),
+                                hipMemcpyHostToDevice, ctx->stream));
+  }
+  Mem tmp;
+  if (!alloc_all(ctx, {{&tmp, need * 8}})) return fail(ctx, RTEAAL_E_NO_MEMORY, "read-out buffer allocation failed");
+  const SlotRef* refs = (const SlotRef*)(slots ? h.d_slot_refs.p : h.d_reg_refs.p);
+  hipError_t e = launch_pack(b->mapping == RTEAAL_MAP_SWEEP, b->L, (const char*)b->state.p, refs,
+                             n_refs, wpi, first, n, (uint64_t*)tmp.p, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, tmp.p, need * 8, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dev_free(ctx, tmp);
+  if (e != hipSuccess) {
+    ctx->poisoned = true;
+    return fail(ctx, RTEAAL_E_DEVICE, "read_state: %s", hipGetErrorString(e));
+  }
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_write_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first, uint32_t n,
+                                 const uint64_t* regs, uint64_t cycle) {
+  if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
+  if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
+  Batch* b = find_batch(ctx, id);
+  if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
+  if ((uint64_t)first + n > b->n_inst) return fail(ctx, RTEAAL_E_INVALID_ARG, "instance range out of bounds");
+  DesignHost& h = *find_design(ctx, b->design);
+  const size_t need = (size_t)h.reg_words * n;
+  if (need && !regs) return fail(ctx, RTEAAL_E_INVALID_ARG, "regs is null");
+  Mem tmp;
+  if (need && !alloc_all(ctx, {{&tmp, need * 8}})) return fail(ctx, RTEAAL_E_NO_MEMORY, "restore buffer allocation failed");
+  hipError_t e = hipSuccess;
+  if (need) {
+    e = hipMemcpyAsync(tmp.p, regs, need * 8, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+      e = launch_unpack(b->mapping == RTEAAL_MAP_SWEEP, b->L, (char*)b->state.p,
+                        (const SlotRef*)h.d_reg_refs.p, h.n_regs, h.reg_words, first, n,
+                        (const uint64_t*)tmp.p, ctx->stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&((DevCtl*)b->ctl.p)->cycle, &cycle, 8, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  dev_free(ctx, tmp);
+  if (e != hipSuccess) {
+    ctx->poisoned = true;
+    return fail(ctx, RTEAAL_E_DEVICE, "write_state: %s", hipGetErrorString(e));
+  }
+  b->cycle = cycle;
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_kernel_timing(rteaal_ctx* ctx, rteaal_batch_id id, int enable,
+                                   uint64_t* launches, double* total_ms) {
+  if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
+  Batch* b = find_batch(ctx, id);
+  if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  double total = 0.0;
+  for (auto& e : b->ev_used) {
+    float ms = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, e.first, e.second));
+    total += ms;
+  }
+  if (launches) *launches = b->ev_used.size();
+  if (total_ms) *total_ms = total;
+  release_events(*b);
+  b->profile = enable != 0;
+  return RTEAAL_OK;
+}
+
+}  // extern "C"

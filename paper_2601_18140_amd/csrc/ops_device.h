@@ -1,0 +1,235 @@
+// Per-type operators (op_u / op_r / op_s of the paper's Cascade 1) on the
+// device, in three forms:
+//   eval_u64  : every operand and the result fit 64 bits (one lane = one value);
+//   eval_bits : every operand and the result are 1 bit and each 64-bit word
+//               holds that signal for 64 instances (bit-sliced);
+//   eval_wide : up to 256 bits in four 64-bit limbs.
+// All results are reduced modulo 2^width of the destination.
+#pragma once
+#include "internal.h"
+
+namespace rteaal {
+
+__device__ __forceinline__ uint64_t mask64(uint32_t w) {
+  return w >= 64 ? ~0ull : ((1ull << w) - 1ull);
+}
+
+// Operand order follows the O rank: a = o0 (left / high / selector), b = o1, c = o2.
+__device__ __forceinline__ uint64_t eval_u64(uint32_t opc, uint32_t arity, uint64_t a, uint64_t b,
+                                             uint64_t c, uint32_t imm, uint32_t w) {
+  uint64_t r;
+  switch (opc) {
+    case OP_AND: r = a & b & (arity == 3 ? c : ~0ull); break;
+    case OP_OR: r = a | b | (arity == 3 ? c : 0ull); break;
+    case OP_XOR: r = a ^ b ^ (arity == 3 ? c : 0ull); break;
+    case OP_NOT: r = ~a; break;
+    case OP_ADD: r = a + b; break;
+    case OP_SUB: r = a - b; break;
+    case OP_MUL: r = a * b; break;
+    case OP_MUX: r = a ? b : c; break;
+    case OP_EQ: r = a == b; break;
+    case OP_LT: r = a < b; break;
+    case OP_SHL: r = imm >= 64 ? 0ull : a << imm; break;
+    case OP_SHR:
+    case OP_EXTRACT: r = imm >= 64 ? 0ull : a >> imm; break;
+    case OP_CONCAT: r = (imm >= 64 ? 0ull : a << imm) | b; break;
+    case OP_ORR: r = a != 0; break;
+    default: r = a; break;  // COPY
+  }
+  return r & mask64(w);
+}
+
+// 1-bit destination, 1-bit operands, 64 instances per word.  Each identity
+// is the 1-bit case of the integer definition: a+b and a-b are a^b modulo 2,
+// a*b is a&b, [a==b] is ~(a^b), [a<b] is ~a&b, a shift by k>0 leaves bit 0
+// empty, CONCAT keeps the low operand, ORR of one bit is the bit.
+__device__ __forceinline__ uint64_t eval_bits(uint32_t opc, uint32_t arity, uint64_t a, uint64_t b,
+                                              uint64_t c, uint32_t imm) {
+  switch (opc) {
+    case OP_AND: return a & b & (arity == 3 ? c : ~0ull);
+    case OP_OR: return a | b | (arity == 3 ? c : 0ull);
+    case OP_XOR: return a ^ b ^ (arity == 3 ? c : 0ull);
+    case OP_NOT: return ~a;
+    case OP_ADD:
+    case OP_SUB: return a ^ b;
+    case OP_MUL: return a & b;
+    case OP_MUX: return (a & b) | (~a & c);
+    case OP_EQ: return ~(a ^ b);
+    case OP_LT: return ~a & b;
+    case OP_SHL:
+    case OP_SHR:
+    case OP_EXTRACT: return imm == 0 ? a : 0ull;
+    case OP_CONCAT: return b;
+    default: return a;  // ORR, COPY
+  }
+}
+
+struct V4 {
+  uint64_t l[4];
+};
+
+__device__ __forceinline__ V4 v4_from(uint64_t x) { return V4{{x, 0ull, 0ull, 0ull}}; }
+
+__device__ __forceinline__ bool v4_nonzero(const V4& a) {
+  return (a.l[0] | a.l[1] | a.l[2] | a.l[3]) != 0ull;
+}
+
+__device__ __forceinline__ V4 v4_add(const V4& a, const V4& b) {
+  V4 r;
+  uint64_t carry = 0;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    uint64_t t = a.l[i] + b.l[i];
+    uint64_t c1 = t < a.l[i];
+    uint64_t s = t + carry;
+    uint64_t c2 = s < t;
+    r.l[i] = s;
+    carry = c1 | c2;
+  }
+  return r;
+}
+
+__device__ __forceinline__ V4 v4_sub(const V4& a, const V4& b) {
+  V4 r;
+  uint64_t borrow = 0;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    uint64_t t = a.l[i] - b.l[i];
+    uint64_t b1 = a.l[i] < b.l[i];
+    uint64_t s = t - borrow;
+    uint64_t b2 = t < borrow;
+    r.l[i] = s;
+    borrow = b1 | b2;
+  }
+  return r;
+}
+
+__device__ __forceinline__ V4 v4_mul(const V4& a, const V4& b) {
+  V4 r = v4_from(0);
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    uint64_t carry = 0;
+#pragma unroll
+    for (int j = 0; i + j < 4; j++) {
+      uint64_t lo = a.l[i] * b.l[j];
+      uint64_t hi = __umul64hi(a.l[i], b.l[j]);
+      uint64_t t = r.l[i + j] + lo;
+      uint64_t c1 = t < lo;
+      uint64_t t2 = t + carry;
+      uint64_t c2 = t2 < t;
+      r.l[i + j] = t2;
+      carry = hi + c1 + c2;  // a_i*b_j + r + carry < 2^128, so this cannot wrap
+    }
+  }
+  return r;
+}
+
+__device__ __forceinline__ V4 v4_shl(const V4& a, uint32_t k) {
+  V4 r = v4_from(0);
+  if (k >= 256) return r;
+  const uint32_t q = k >> 6, s = k & 63;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const int j = i - (int)q;
+    uint64_t x = 0;
+    if (j >= 0) {
+      x = a.l[j] << s;
+      if (s && j >= 1) x |= a.l[j - 1] >> (64 - s);
+    }
+    r.l[i] = x;
+  }
+  return r;
+}
+
+__device__ __forceinline__ V4 v4_shr(const V4& a, uint32_t k) {
+  V4 r = v4_from(0);
+  if (k >= 256) return r;
+  const uint32_t q = k >> 6, s = k & 63;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const int j = i + (int)q;
+    uint64_t x = 0;
+    if (j < 4) {
+      x = a.l[j] >> s;
+      if (s && j + 1 < 4) x |= a.l[j + 1] << (64 - s);
+    }
+    r.l[i] = x;
+  }
+  return r;
+}
+
+__device__ __forceinline__ bool v4_lt(const V4& a, const V4& b) {
+  if (a.l[3] != b.l[3]) return a.l[3] < b.l[3];
+  if (a.l[2] != b.l[2]) return a.l[2] < b.l[2];
+  if (a.l[1] != b.l[1]) return a.l[1] < b.l[1];
+  return a.l[0] < b.l[0];
+}
+
+__device__ __forceinline__ V4 v4_mask(V4 a, uint32_t w) {
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const uint32_t lo = 64u * i;
+    if (w <= lo) a.l[i] = 0;
+    else if (w < lo + 64) a.l[i] &= (1ull << (w - lo)) - 1ull;
+  }
+  return a;
+}
+
+__device__ __forceinline__ V4 eval_wide(uint32_t opc, uint32_t arity, const V4& a, const V4& b,
+                                        const V4& c, uint32_t imm, uint32_t w) {
+  V4 r;
+  switch (opc) {
+    case OP_AND:
+#pragma unroll
+      for (int i = 0; i < 4; i++) r.l[i] = a.l[i] & b.l[i] & (arity == 3 ? c.l[i] : ~0ull);
+      break;
+    case OP_OR:
+#pragma unroll
+      for (int i = 0; i < 4; i++) r.l[i] = a.l[i] | b.l[i] | (arity == 3 ? c.l[i] : 0ull);
+      break;
+    case OP_XOR:
+#pragma unroll
+      for (int i = 0; i < 4; i++) r.l[i] = a.l[i] ^ b.l[i] ^ (arity == 3 ? c.l[i] : 0ull);
+      break;
+    case OP_NOT:
+#pragma unroll
+      for (int i = 0; i < 4; i++) r.l[i] = ~a.l[i];
+      break;
+    case OP_ADD: r = v4_add(a, b); break;
+    case OP_SUB: r = v4_sub(a, b); break;
+    case OP_MUL: r = v4_mul(a, b); break;
+    case OP_MUX: r = v4_nonzero(a) ? b : c; break;
+    case OP_EQ:
+      r = v4_from((a.l[0] == b.l[0]) & (a.l[1] == b.l[1]) & (a.l[2] == b.l[2]) & (a.l[3] == b.l[3]));
+      break;
+    case OP_LT: r = v4_from(v4_lt(a, b)); break;
+    case OP_SHL: r = v4_shl(a, imm); break;
+    case OP_SHR:
+    case OP_EXTRACT: r = v4_shr(a, imm); break;
+    case OP_CONCAT: {
+      r = v4_shl(a, imm);
+#pragma unroll
+      for (int i = 0; i < 4; i++) r.l[i] |= b.l[i];
+      break;
+    }
+    case OP_ORR: r = v4_from(v4_nonzero(a)); break;
+    default: r = a; break;  // COPY
+  }
+  return v4_mask(r, w);
+}
+
+// Stimulus: SplitMix64's output function (Steele, Lea & Flood, OOPSLA 2014)
+// applied to seed, cycle and (input, limb) in turn.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t stim_word(uint64_t seed, uint64_t cycle, uint32_t input,
+                                              uint32_t limb) {
+  return splitmix64(splitmix64(splitmix64(seed) ^ cycle) ^ (((uint64_t)input << 8) | limb));
+}
+
+}  // namespace rteaal

@@ -1,0 +1,161 @@
+"""The C interface on the host (no GPU): exports, validation and error paths."""
+import copy
+import re
+import os
+
+import numpy as np
+import pytest
+
+import rtlgen
+from rtlgen import circuits as cir
+from paper_2601_18140_amd import rteaal as R
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "rteaal.h")
+
+
+def test_library_exports_every_declared_function():
+    lib = R.library()
+    decl = set(re.findall(r"\b(rteaal_[a-z_]+)\s*\(", open(HEADER).read()))
+    assert decl == set(R.exported_symbols())
+    for name in decl:
+        assert hasattr(lib, name), name
+
+
+def _clone(d):
+    return copy.deepcopy(d)
+
+
+@pytest.fixture(scope="module")
+def good():
+    return rtlgen.generate(rtlgen.GenConfig(300, 6, 20, 8, rtlgen.generator.WIDTHS_LARGE, "v"), 5)
+
+
+def expect(design, status, fragment=""):
+    st, msg = R.rteaal_validate_design(design)
+    assert st == status, (st, msg)
+    assert fragment in msg, msg
+
+
+def test_generated_and_closed_form_designs_validate(good):
+    expect(good, 0)
+    for d in (cir.ripple_carry_adder(5), cir.counter(70), cir.xnor_lfsr(9),
+              cir.shift_chain(3, 4, True), cir.paper_multiply_example()):
+        expect(d, 0)
+    expect(rtlgen.generate(rtlgen.CFG0, 0), 0)
+
+
+def test_width_out_of_range(good):
+    d = _clone(good)
+    d.slot_width[3] = 0
+    expect(d, 2, "width")
+    d.slot_width[3] = 257
+    expect(d, 2, "width")
+
+
+def test_two_drivers(good):
+    d = _clone(good)
+    d.op_dst[5] = d.op_dst[6]
+    expect(d, 2, "more than one driver")
+
+
+def test_not_levelized(good):
+    d = _clone(good)
+    j = int(d.layer_ptr[2])                      # first op of layer 2
+    d.op_src[d.op_src_ptr[j]] = d.op_dst[j + 1]  # reads an output of its own layer
+    expect(d, 2, "not levelized")
+    d = _clone(good)
+    j = int(d.layer_ptr[1])
+    d.op_src[d.op_src_ptr[j]] = d.op_dst[int(d.layer_ptr[4])]  # a later layer
+    expect(d, 2, "not levelized")
+
+
+def test_undriven_operand(good):
+    d = _clone(good)
+    d.slot_width = np.concatenate([d.slot_width, [7]]).astype(np.uint16)
+    j = int(d.layer_ptr[3])
+    d.op_src[d.op_src_ptr[j]] = d.n_slots - 1
+    expect(d, 2, "no driver")
+
+
+def test_wrong_arity(good):
+    d = _clone(good)
+    j = int(np.nonzero(d.op_type == rtlgen.NOT)[0][0])
+    d.op_type[j] = rtlgen.SUB
+    expect(d, 2, "cannot take")
+
+
+def test_immediate_out_of_range(good):
+    d = _clone(good)
+    j = int(np.nonzero(d.op_type == rtlgen.SHL)[0][0])
+    d.op_imm[j] = 300
+    expect(d, 2, "immediate")
+    d = _clone(good)
+    j = int(np.nonzero(d.op_type == rtlgen.ADD)[0][0])
+    d.op_imm[j] = 1
+    expect(d, 2, "immediate")
+
+
+def test_register_out_of_range(good):
+    d = _clone(good)
+    d.reg_next[0] = d.n_slots + 10
+    expect(d, 2, "out of range")
+
+
+def test_layer_pointer_errors(good):
+    d = _clone(good)
+    d.layer_ptr[-1] = d.layer_ptr[-1] - 1
+    expect(d, 2, "layer_op_ptr")
+
+
+def _formats(d):
+    out = []
+    for i in range(d.n_layers):
+        f = R.rteaal_layer_format()
+        a, b = int(d.layer_ptr[i]), int(d.layer_ptr[i + 1])
+        maxs = int(d.op_dst[a:b].max())
+        maxr = int(d.op_src[d.op_src_ptr[a]:d.op_src_ptr[b]].max())
+        cnt = np.bincount(d.op_type[a:b], minlength=15).max()
+        f.oim[1].pbits = int(cnt).bit_length()
+        f.oim[2].compressed, f.oim[2].cbits = 1, max(1, maxs.bit_length())
+        f.oim[4].compressed, f.oim[4].cbits = 1, max(1, maxr.bit_length())
+        out.append(f)
+    return out
+
+
+def test_caller_formats_checked(good):
+    fm = _formats(good)
+    st, msg = R.rteaal_validate_design(good, fm)
+    assert st == 0, msg
+    fm[2].oim[4].cbits -= 1                      # R coordinates no longer fit
+    st, msg = R.rteaal_validate_design(good, fm)
+    assert st == 3 and "rank 4" in msg
+    fm = _formats(good)
+    fm[1].oim[1].pbits -= 1                      # N payloads no longer fit
+    st, msg = R.rteaal_validate_design(good, fm)
+    assert st == 3 and "payloads" in msg
+
+
+def test_null_descriptor():
+    lib = R.library()
+    buf = R.C.create_string_buffer(128)
+    assert lib.rteaal_validate_design(None, buf, 128) == 1
+
+
+def test_no_device_is_a_clean_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    out = R.C.c_void_p()
+    st = R.library().rteaal_create(0, None, None, R.C.byref(out))
+    assert st == 1 and not out.value
+    assert "device" in R.rteaal_last_error(None)
+
+
+def test_limb_packing_roundtrip():
+    rng = np.random.default_rng(0)
+    widths = np.array([1, 64, 65, 200, 256, 7])
+    vals = rng.integers(0, 2**63, size=(3, 6, 4), dtype=np.uint64)
+    nl = (widths + 63) // 64
+    for k in range(6):
+        vals[:, k, nl[k]:] = 0
+    assert np.array_equal(R.unpack_limbs(R.pack_limbs(vals, widths), widths), vals)

@@ -1,0 +1,185 @@
+"""Parity of the HIP path with the CPU oracle (GPU).
+
+Integer arithmetic: every comparison is bit-exact (tolerance 0) on the
+final registers and, where the oracle can afford it, on every slot of the
+signal vector LI after the last cycle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import rtlgen
+from rtlgen import circuits as cir
+from paper_2601_18140_amd import rteaal as R
+from tests.gpu_util import assert_same, gpu_ctx, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+MAPS = [R.RTEAAL_MAP_RESIDENT, R.RTEAAL_MAP_SWEEP]
+MAP_IDS = ["resident", "sweep"]
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gpu_ctx()
+    yield c
+    R.rteaal_destroy(c)
+
+
+# ---- closed-form circuits ---------------------------------------------------
+@pytest.mark.parametrize("mapping", MAPS, ids=MAP_IDS)
+def test_counter_and_lfsr(ctx, mapping):
+    for d, n, exp in [(cir.counter(8), 300, 300 % 256),
+                      (cir.counter(130, 3**70), 77, (77 * 3**70) % (1 << 130))]:
+        note(f"counter w={d.slot_width[0]} mapping={mapping}")
+        regs, _, _ = run_gpu(ctx, d, [0, 1, 2], [n // 2, n - n // 2], mapping=mapping)
+        for i in range(3):
+            assert rtlgen.limbs_to_int(regs[i, 0]) == exp
+    d = cir.xnor_lfsr(10)
+    ref, _, _ = oracle.run(d, [0], 1500)
+    regs, _, _ = run_gpu(ctx, d, [0], 1500, mapping=mapping)
+    assert_same(regs, ref, "lfsr10")
+
+
+@pytest.mark.parametrize("mapping", MAPS, ids=MAP_IDS)
+def test_adder_buffer_stimulus(ctx, mapping):
+    rng = np.random.default_rng(1)
+    for w in (8, 64, 100):
+        d = cir.ripple_carry_adder(w)
+        n_inst, cyc = 5, 3
+        vals = [[[int(x) for x in rng.integers(0, 2**62, 2)] for _ in range(n_inst)] for _ in range(cyc)]
+        nl = (w + 63) // 64
+        words = np.zeros((cyc, n_inst, 2 * nl), np.uint64)
+        for c in range(cyc):
+            for j in range(n_inst):
+                a, b = [v % (1 << w) for v in vals[c][j]]
+                vals[c][j] = (a, b)
+                for l in range(nl):
+                    words[c, j, l] = (a >> (64 * l)) & (2**64 - 1)
+                    words[c, j, nl + l] = (b >> (64 * l)) & (2**64 - 1)
+        note(f"adder w={w} mapping={mapping}")
+        regs, _, _ = run_gpu(ctx, d, np.arange(n_inst), [1, 2], mapping=mapping, words=words)
+        for j in range(n_inst):
+            a, b = vals[cyc - 1][j]
+            assert rtlgen.limbs_to_int(regs[j, 0]) == a + b
+
+
+@pytest.mark.parametrize("mapping", MAPS, ids=MAP_IDS)
+def test_shift_chain_commit(ctx, mapping):
+    for rev in (False, True):
+        d = cir.shift_chain(5, 70, reverse=rev)
+        ref, _, _ = oracle.run(d, [4, 9], 12)
+        regs, _, _ = run_gpu(ctx, d, [4, 9], 12, mapping=mapping)
+        assert_same(regs, ref, f"shift chain reverse={rev}")
+
+
+# ---- generated designs, small (every slot compared) -------------------------
+SMALL = [
+    rtlgen.GenConfig(700, 7, 40, 12, rtlgen.generator.WIDTHS_LARGE, "s-wide"),
+    rtlgen.GenConfig(1500, 12, 64, 16, rtlgen.generator.WIDTHS_STD, "s-std"),
+    rtlgen.GenConfig(400, 20, 30, 8, rtlgen.generator.WIDTHS_MULTIDESIGN, "s-multi"),
+]
+
+
+@pytest.mark.parametrize("cfg", SMALL, ids=[c.name for c in SMALL])
+@pytest.mark.parametrize("mapping", MAPS, ids=MAP_IDS)
+@pytest.mark.parametrize("n_inst", [1, 3, 64, 100, 130])
+def test_small_designs_all_slots(ctx, cfg, mapping, n_inst):
+    d = rtlgen.generate(cfg, 7)
+    seeds = np.arange(n_inst, dtype=np.uint64) * 7919 + 3
+    cyc = 25
+    note(f"small {cfg.name} mapping={mapping} n={n_inst}")
+    regs, slots, used = run_gpu(ctx, d, seeds, [10, 15], mapping=mapping, slots=True)
+    assert used == mapping
+    ref_r, ref_s, _ = oracle.run(d, seeds, cyc, want_slots=True)
+    assert_same(regs, ref_r, "registers")
+    assert_same(slots, ref_s, "slots")
+
+
+@pytest.mark.parametrize("mapping", MAPS, ids=MAP_IDS)
+def test_resident_hbm_state_and_block_sizes(ctx, mapping):
+    d = rtlgen.generate(SMALL[0], 3)
+    ref, _, _ = oracle.run(d, [5, 6, 7], 20)
+    if mapping == R.RTEAAL_MAP_RESIDENT:
+        for blk in (64, 128, 1024):
+            for lds in (0, 1):
+                regs, _, _ = run_gpu(ctx, d, [5, 6, 7], 20, mapping=mapping, block_threads=blk,
+                                     lds_state=lds)
+                assert_same(regs, ref, f"block={blk} lds_state={lds}")
+    else:
+        for opw in (1, 5, 64):
+            regs, _, _ = run_gpu(ctx, d, [5, 6, 7], 20, mapping=mapping, ops_per_wave=opw)
+            assert_same(regs, ref, f"ops_per_wave={opw}")
+
+
+def test_plain_2k_full_run(ctx):
+    """The small workload: 2,000 ops, 16 layers, one instance, 10,000 cycles."""
+    w = rtlgen.WORKLOADS["plain-2k"]
+    d = rtlgen.generate(w["cfg"], w["seed"])
+    note("plain-2k 10000 cycles")
+    regs, slots, used = run_gpu(ctx, d, [0], w["cycles"], slots=True)
+    assert used == R.RTEAAL_MAP_RESIDENT
+    ref_r, ref_s, _ = oracle.run(d, [0], w["cycles"], want_slots=True)
+    assert_same(regs, ref_r, "registers")
+    assert_same(slots, ref_s, "slots")
+
+
+@pytest.mark.parametrize("mapping", MAPS, ids=MAP_IDS)
+def test_checkpoint_restore(ctx, mapping):
+    d = rtlgen.generate(SMALL[0], 11)
+    seeds = [1, 2, 3, 4]
+    full, _, _ = oracle.run(d, seeds, 50)
+    did = R.rteaal_load_design(ctx, d)
+    b1 = R.rteaal_create_batch(ctx, did, seeds, mapping=mapping)
+    R.rteaal_step(ctx, b1, 20)
+    ck = R.rteaal_read_state(ctx, b1)
+    R.rteaal_free_batch(ctx, b1)
+    b2 = R.rteaal_create_batch(ctx, did, seeds, mapping=mapping)
+    R.rteaal_write_state(ctx, b2, 0, ck, 20)
+    R.rteaal_step(ctx, b2, 30)
+    got = R.unpack_limbs(R.rteaal_read_state(ctx, b2), d.slot_width[d.reg_slot])
+    R.rteaal_free_batch(ctx, b2)
+    R.rteaal_unload_design(ctx, did)
+    assert_same(got, full, "restored run")
+
+
+def test_instance_alone_equals_in_batch(ctx):
+    d = rtlgen.generate(SMALL[1], 2)
+    seeds = np.arange(200, dtype=np.uint64) * 31
+    batch, _, _ = run_gpu(ctx, d, seeds, 15, mapping=R.RTEAAL_MAP_SWEEP)
+    for k in (0, 63, 64, 199):
+        alone, _, _ = run_gpu(ctx, d, seeds[k:k + 1], 15, mapping=R.RTEAAL_MAP_RESIDENT)
+        assert_same(batch[k:k + 1], alone, f"instance {k}")
+
+
+# ---- full-size workloads, sampled instances ---------------------------------
+def test_single_200k_batched_and_plain(ctx):
+    w = rtlgen.WORKLOADS["single-200k"]
+    d = rtlgen.generate(w["cfg"], w["seed"])
+    seeds = rtlgen.instance_seeds(w["instances"])
+    rng = np.random.default_rng(7)
+    sample = sorted(set([0, 1, 2, 511, 512, 1022, 1023]) | set(rng.choice(1024, 9, replace=False).tolist()))
+    cyc = 6
+    note("single-200k batched 1024 x 6 cycles")
+    did = R.rteaal_load_design(ctx, d)
+    bid = R.rteaal_create_batch(ctx, did, seeds, mapping=R.RTEAAL_MAP_SWEEP)
+    R.rteaal_step(ctx, bid, cyc)
+    got = R.unpack_limbs(R.rteaal_read_state(ctx, bid), d.slot_width[d.reg_slot])
+    R.rteaal_free_batch(ctx, bid)
+    ref, _, _ = oracle.run(d, seeds[sample], cyc)
+    assert_same(got[sample], ref, "batched sample")
+    note("single-200k plain 1 x 12 cycles")
+    pb = R.rteaal_create_batch(ctx, did, seeds[:1], mapping=R.RTEAAL_MAP_RESIDENT)
+    R.rteaal_step(ctx, pb, 12)
+    got1 = R.unpack_limbs(R.rteaal_read_state(ctx, pb), d.slot_width[d.reg_slot])
+    R.rteaal_free_batch(ctx, pb)
+    R.rteaal_unload_design(ctx, did)
+    ref1, _, _ = oracle.run(d, seeds[:1], 12)
+    assert_same(got1, ref1, "plain")

@@ -101,11 +101,27 @@ def main():
     ap.add_argument("--mapping", default="auto", choices=["auto", "resident", "sweep"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--ops-per-wave", type=int, default=0)
+    ap.add_argument("--unroll", type=int, default=0)
     ap.add_argument("--plain-cycles", type=int, default=None)
     ap.add_argument("--profile-cycles", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default shapes instead of autotuned ones")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB three times (counter scale)")
     args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each": n, "copies": 3}), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: every workload here is a single-GPU "
@@ -137,8 +153,15 @@ def main():
     ok = parity_sample(R, ctx, did, d, seeds, mapping)
     print(f"[bench] parity sample vs oracle: {ok}", file=sys.stderr, flush=True)
 
+    manual = args.mapping != "auto" or args.block or args.ops_per_wave or args.unroll
+    tuned = None
+    if not manual and not args.no_autotune:
+        t0 = time.perf_counter()
+        tuned, trate = R.rteaal_autotune(ctx, did, n_inst)
+        print(f"[bench] autotune batched ({time.perf_counter() - t0:.1f}s): {tuned} "
+              f"-> {trate:.4g} instance-cycles/s", file=sys.stderr, flush=True)
     bid = R.rteaal_create_batch(ctx, did, seeds, mapping=mapping, block_threads=args.block,
-                                ops_per_wave=args.ops_per_wave)
+                                ops_per_wave=args.ops_per_wave, unroll=args.unroll)
     used_map, _ = R.rteaal_batch_info(ctx, bid)
     for _ in range(args.warmup):
         R.rteaal_step(ctx, bid, cps)
@@ -185,7 +208,11 @@ def main():
     plain = None
     if not args.no_plain:
         pc = args.plain_cycles or min(cps, 2000)
-        pb = R.rteaal_create_batch(ctx, did, seeds[:1], mapping=R.RTEAAL_MAP_RESIDENT)
+        plain_opts = {"mapping": R.RTEAAL_MAP_RESIDENT}
+        if not args.no_autotune:
+            plain_opts, prate = R.rteaal_autotune(ctx, did, 1)
+            print(f"[bench] autotune plain: {plain_opts} -> {prate:.4g}", file=sys.stderr, flush=True)
+        pb = R.rteaal_create_batch(ctx, did, seeds[:1], **plain_opts)
         R.rteaal_step(ctx, pb, min(pc, 200))
         R.rteaal_sync(ctx)
         ev0.record(stream)
@@ -195,7 +222,7 @@ def main():
         pms = ev0.elapsed_time(ev1)
         R.rteaal_free_batch(ctx, pb)
         plain = {"value": pc / (pms / 1e3), "unit": "instance-cycles/s", "instances": 1,
-                 "cycles": pc, "mapping": "resident"}
+                 "cycles": pc, "opts": plain_opts}
         print(f"[bench] plain: {pc} cycles in {pms:.1f} ms -> {plain['value']:.4g}",
               file=sys.stderr, flush=True)
 
@@ -219,6 +246,7 @@ def main():
                    "registers": d.n_regs, "inputs": d.n_inputs, "instances": n_inst,
                    "cycles_per_step": cps,
                    "mapping": "sweep" if used_map == R.RTEAAL_MAP_SWEEP else "resident",
+                   "opts": tuned,
                    "design_fingerprint": d.fingerprint()},
         "plain": plain,
         "batched_over_plain": round(value / plain["value"], 2) if plain else None,

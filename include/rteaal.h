@@ -169,10 +169,13 @@ rteaal_status rteaal_design_format(rteaal_ctx* ctx, rteaal_design_id design, uin
 enum { RTEAAL_MAP_AUTO = 0, RTEAAL_MAP_RESIDENT = 1, RTEAAL_MAP_SWEEP = 2 };
 
 typedef struct {
-  uint32_t mapping;        /* RTEAAL_MAP_*                                     */
-  uint32_t block_threads;  /* 0 = default; RESIDENT: 64..1024, multiple of 64  */
-  uint32_t ops_per_wave;   /* 0 = default; SWEEP: operations per wavefront     */
-  uint32_t lds_state;      /* RESIDENT: 0 = auto, 1 = force HBM state          */
+  uint32_t mapping;        /* RTEAAL_MAP_*                                      */
+  uint32_t block_threads;  /* 0 = default; RESIDENT: 64..1024, multiple of 64   */
+  uint32_t ops_per_wave;   /* 0 = default; SWEEP: operations per wavefront      */
+  uint32_t lds_state;      /* RESIDENT: 0 = LDS when it fits, 1 = keep in HBM   */
+  uint32_t lds_ops;        /* RESIDENT: 0 = records in LDS when they fit, 1 = no */
+  uint32_t unroll;         /* 0 = default; operations in flight per lane or
+                              wavefront: SWEEP 1, 2, 4, 8; RESIDENT 1, 2, 4      */
 } rteaal_batch_opts;
 
 /* Device bytes a batch of n_instances of `design` would allocate under
@@ -243,6 +246,18 @@ rteaal_status rteaal_read_state(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t
  * counter to `cycle` (checkpoint restore, host poke between cycles). */
 rteaal_status rteaal_write_state(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t first,
                                  uint32_t n, const uint64_t* regs, uint64_t cycle);
+
+/* Autotuner: picks the mapping and launch shape for n_instances of `design`
+ * on this device.  Each candidate (RESIDENT block sizes and unroll depths,
+ * SWEEP operations-per-wavefront and unroll depths) runs `trial_cycles`
+ * cycles (0 = a size-dependent default) on a temporary batch and is timed
+ * with HIP events on the context's stream; candidates whose state does not
+ * fit in device memory are skipped.  The fastest options are written to
+ * *best (may be NULL) with their rate in instance-cycles/s in *rate (may be
+ * NULL), and remembered: later rteaal_create_batch calls with mapping AUTO
+ * for the same design and instance count use them.  Waits for the stream. */
+rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id design, uint32_t n_instances,
+                              uint32_t trial_cycles, rteaal_batch_opts* best, double* rate);
 
 /* ------------------------------------------------------------------------ */
 /* Measurement                                                              */

@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/rteaal.h"
@@ -42,6 +43,13 @@ struct rteaal_ctx {
   std::map<uint32_t, std::unique_ptr<DesignHost>> designs;
   std::map<uint32_t, std::unique_ptr<Batch>> batches;
   size_t max_lds = 0;
+  // rteaal_step_many: auxiliary streams (default priority) for SWEEP batches,
+  // fork/join events, and a grow-only device scratch for job tables.
+  hipStream_t aux[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[4] = {nullptr, nullptr, nullptr, nullptr};
+  Mem multi;
+  // Autotuned batch options, keyed by (design, instance count).
+  std::map<std::pair<uint32_t, uint32_t>, rteaal_batch_opts> tuned;
 };
 
 namespace {
@@ -269,6 +277,7 @@ struct DesignHost {
   uint32_t id = 0;
   uint32_t n_slots = 0, n_regs = 0, n_inputs = 0, n_design_layers = 0;
   uint32_t n_idx[NCLS] = {0};
+  uint64_t wide_bytes = 0;  // bytes of one instance's wide region (all classes but CB)
   std::vector<DevOp> ops;
   std::vector<DevLayer> layers;
   std::vector<uint64_t> const_limbs;
@@ -401,6 +410,19 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
   }
   for (int c = 0; c < NCLS; ++c) h->n_idx[c] = cnt[c];
 
+  // Wide region of one instance: CW elements (4 bytes), then CD, CL2, CL3,
+  // CL4 (8 bytes per limb), each class starting on a 16-byte boundary.  A
+  // non-1-bit slot is addressed by its byte offset Y in this region.
+  uint64_t base[NCLS] = {0};
+  uint64_t wb = 0;
+  for (uint32_t c = CW; c < NCLS; ++c) {
+    base[c] = wb;
+    wb = (wb + (uint64_t)cnt[c] * cls_bytes(c) + 15) & ~uint64_t(15);
+  }
+  h->wide_bytes = wb;
+  for (uint32_t k = 0; k < NW; ++k)
+    if (scls[k] != CB && scls[k] != CNONE) sidx[k] = (uint32_t)(base[scls[k]] + (uint64_t)sidx[k] * cls_bytes(scls[k]));
+
   h->ops.clear();
   h->ops.reserve(pos);
   for (auto& lay : L)
@@ -448,8 +470,8 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
 // Batches.
 // ---------------------------------------------------------------------------
 struct Batch {
-  uint32_t id = 0, design = 0, n_inst = 0, mapping = 0, block = 0, opw = 0;
-  bool lds = false;
+  uint32_t id = 0, design = 0, n_inst = 0, mapping = 0, block = 0, opw = 0, unroll = 0;
+  bool lds = false, lds_ops = false;
   uint64_t cycle = 0;
   StateLayout L{};
   Mem state, seeds, ctl;
@@ -494,34 +516,25 @@ hipError_t timed(Batch& b, hipStream_t s, F&& launch) {
 
 StateLayout make_layout(const DesignHost& h, uint32_t mapping, uint32_t n_inst, uint64_t* bytes) {
   StateLayout L{};
-  uint64_t off = 0;
-  auto align = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  const uint64_t bwords = (h.n_idx[CB] + 63) / 64;
   if (mapping == RTEAAL_MAP_SWEEP) {
+    auto align = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
     L.n_tiles = (n_inst + 63) / 64;
     L.n_pad = L.n_tiles * 64;
-    for (int c = 0; c < NCLS; ++c) {
-      L.off[c] = off;
-      uint64_t sz;
-      if (c == CB) sz = (uint64_t)h.n_idx[CB] * L.n_tiles * 8;
-      else if (c == CW) sz = (uint64_t)h.n_idx[CW] * L.n_pad * 4;
-      else sz = (uint64_t)h.n_idx[c] * cls_limbs(c) * L.n_pad * 8;
-      off = align(off + sz);
-    }
+    L.b_off = 0;
+    L.nb_off = align((uint64_t)h.n_idx[CB] * L.n_tiles * 8);
+    L.tile_bytes = h.wide_bytes * 64;
+    L.zero_off = L.nb_off + L.tile_bytes * L.n_tiles;
     L.pitch = 0;
-    *bytes = off;
+    *bytes = L.zero_off + 256;
   } else {
     L.n_tiles = 0;
     L.n_pad = n_inst;
-    for (int c = 0; c < NCLS; ++c) {
-      L.off[c] = off;
-      uint64_t sz;
-      if (c == CB) sz = (uint64_t)((h.n_idx[CB] + 63) / 64) * 8;
-      else if (c == CW) sz = (uint64_t)h.n_idx[CW] * 4;
-      else sz = (uint64_t)h.n_idx[c] * cls_limbs(c) * 8;
-      off = (off + sz + 15) & ~uint64_t(15);
-    }
-    L.pitch = (off + 15) & ~uint64_t(15);
-    if (L.pitch == 0) L.pitch = 16;
+    L.b_off = 0;
+    L.nb_off = (bwords * 8 + 15) & ~uint64_t(15);
+    L.zero_off = L.nb_off + h.wide_bytes;
+    L.tile_bytes = 0;
+    L.pitch = L.zero_off + 16;
     *bytes = L.pitch * n_inst;
   }
   return L;
@@ -532,6 +545,14 @@ uint32_t choose_mapping(const DesignHost& h, uint32_t n_inst, const rteaal_batch
   if (o && o->mapping == RTEAAL_MAP_SWEEP) return RTEAAL_MAP_SWEEP;
   (void)h;
   return n_inst < 32 ? RTEAAL_MAP_RESIDENT : RTEAAL_MAP_SWEEP;
+}
+
+// AUTO options with a tuned entry for (design, n_inst) resolve to that entry.
+const rteaal_batch_opts* resolve_opts(rteaal_ctx* ctx, uint32_t design, uint32_t n_inst,
+                                      const rteaal_batch_opts* o) {
+  if (o && o->mapping != RTEAAL_MAP_AUTO) return o;
+  auto it = ctx->tuned.find({design, n_inst});
+  return it == ctx->tuned.end() ? o : &it->second;
 }
 
 DesignHost* find_design(rteaal_ctx* ctx, rteaal_design_id id) {
@@ -556,6 +577,23 @@ Program program_of(const DesignHost& h) {
 
 constexpr uint64_t kResidentChunk = 1024;  // cycles per RESIDENT launch
 
+ResJob res_job(const DesignHost& h, const Batch& b, uint64_t n_cycles) {
+  ResJob J{};
+  J.ops = (const DevOp*)h.d_ops.p;
+  J.layers = (const DevLayer*)h.d_layers.p;
+  J.const_limbs = (const uint64_t*)h.d_consts.p;
+  J.n_layers = (uint32_t)h.layers.size();
+  J.words_per_inst = h.words_per_inst;
+  J.n_ops_total = (uint32_t)h.ops.size();
+  J.n_inst_total = b.n_inst;
+  J.L = b.L;
+  J.state = (char*)b.state.p;
+  J.seeds = (const uint64_t*)b.seeds.p;
+  J.ctl = (const DevCtl*)b.ctl.p;
+  J.n_cycles = n_cycles;
+  return J;
+}
+
 rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t n_cycles) {
   const Program p = program_of(h);
   DevCtl* ctl = (DevCtl*)b.ctl.p;
@@ -563,8 +601,9 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
     for (uint64_t done = 0; done < n_cycles;) {
       const uint64_t n = std::min(kResidentChunk, n_cycles - done);
       HIP_TRY(ctx, timed(b, ctx->stream, [&] {
-                return launch_resident(p, b.L, (char*)b.state.p, (const uint64_t*)b.seeds.p, ctl,
-                                       b.n_inst, b.n_inst, 0, n, b.block, b.lds, ctx->stream);
+                const ResJob J = res_job(h, b, n);
+                return launch_resident(J, b.n_inst, 0, b.block, b.lds, b.lds_ops, b.unroll,
+                                       ctx->stream);
               }));
       HIP_TRY(ctx, launch_advance(ctl, n, ctx->stream));
       done += n;
@@ -579,7 +618,7 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
         if (!nops) continue;
         HIP_TRY(ctx, timed(b, ctx->stream, [&] {
                   return launch_sweep_layer(p, b.L, (char*)b.state.p, (const uint64_t*)b.seeds.p,
-                                            ctl, b.n_inst, li, nops, b.opw, ctx->stream);
+                                            ctl, b.n_inst, li, nops, b.opw, b.unroll, ctx->stream);
                 }));
       }
       HIP_TRY(ctx, launch_advance(ctl, 1, ctx->stream));
@@ -592,7 +631,8 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
     hipError_t e = hipSuccess;
     for (uint32_t li = 0; li < h.layers.size() && e == hipSuccess; ++li)
       e = launch_sweep_layer(p, b.L, (char*)b.state.p, (const uint64_t*)b.seeds.p, ctl, b.n_inst,
-                             li, h.layers[li].end - h.layers[li].begin, b.opw, ctx->stream);
+                             li, h.layers[li].end - h.layers[li].begin, b.opw, b.unroll,
+                             ctx->stream);
     if (e == hipSuccess) e = launch_advance(ctl, 1, ctx->stream);
     hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -673,6 +713,12 @@ void rteaal_destroy(rteaal_ctx* ctx) {
     dev_free(ctx, h.d_reg_refs);
     dev_free(ctx, h.d_slot_refs);
   }
+  dev_free(ctx, ctx->multi);
+  for (int k = 0; k < 4; ++k) {
+    if (ctx->aux[k]) (void)hipStreamDestroy(ctx->aux[k]);
+    if (ctx->join[k]) (void)hipEventDestroy(ctx->join[k]);
+  }
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -702,6 +748,9 @@ rteaal_status rteaal_load_design(rteaal_ctx* ctx, const rteaal_design_desc* desc
   rteaal_status st = validate(desc, &drv, &why, &h->fmt);
   if (st != RTEAAL_OK) return fail(ctx, st, "%s", why.c_str());
   encode(desc, drv, h.get());
+  if (h->wide_bytes >= (1ull << 32))
+    return fail(ctx, RTEAAL_E_UNSUPPORTED, "one instance's multi-bit state (%llu bytes) exceeds 4 GiB",
+                (unsigned long long)h->wide_bytes);
   const size_t ops_b = h->ops.size() * sizeof(DevOp), lay_b = h->layers.size() * sizeof(DevLayer);
   const size_t con_b = h->const_limbs.size() * 8, reg_b = std::max<size_t>(h->reg_refs.size(), 1) * sizeof(SlotRef);
   if (!alloc_all(ctx, {{&h->d_ops, ops_b}, {&h->d_layers, lay_b}, {&h->d_consts, con_b},
@@ -750,6 +799,7 @@ rteaal_status rteaal_batch_footprint(rteaal_ctx* ctx, rteaal_design_id id, uint3
   if (!ctx || !bytes || n_inst == 0) return fail(ctx, RTEAAL_E_INVALID_ARG, "bad argument");
   DesignHost* h = find_design(ctx, id);
   if (!h) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown design %u", id);
+  opts = resolve_opts(ctx, id, n_inst, opts);
   const uint32_t m = choose_mapping(*h, n_inst, opts);
   uint64_t sb = 0;
   StateLayout L = make_layout(*h, m, n_inst, &sb);
@@ -766,6 +816,7 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
   if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
   DesignHost* h = find_design(ctx, id);
   if (!h) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown design %u", id);
+  opts = resolve_opts(ctx, id, n_inst, opts);
   auto b = std::make_unique<Batch>();
   b->design = id;
   b->n_inst = n_inst;
@@ -782,9 +833,21 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
       if (blk > 256 && h->max_layer_ops < 2048) blk = 256;
     }
     b->block = blk;
-    b->lds = !(opts && opts->lds_state == 1) && b->L.pitch <= ctx->max_lds;
+    const uint32_t n_ops = (uint32_t)h->ops.size(), n_lay = (uint32_t)h->layers.size();
+    b->lds = !(opts && opts->lds_state == 1) &&
+             resident_lds_bytes(b->L, n_ops, n_lay, true, false) <= ctx->max_lds;
+    b->lds_ops = !(opts && opts->lds_ops == 1) &&
+                 resident_lds_bytes(b->L, n_ops, n_lay, b->lds, true) <= ctx->max_lds;
+    const uint32_t u = opts && opts->unroll ? opts->unroll : (b->lds ? 1u : 4u);
+    if (u != 1 && u != 2 && u != 4)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "RESIDENT unroll must be 1, 2 or 4");
+    b->unroll = u;
   } else {
     b->opw = opts && opts->ops_per_wave ? opts->ops_per_wave : 16;
+    const uint32_t u = opts && opts->unroll ? opts->unroll : 4u;
+    if (u != 1 && u != 2 && u != 4 && u != 8)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP unroll must be 1, 2, 4 or 8");
+    b->unroll = u;
   }
   const uint64_t n_seed = b->mapping == RTEAAL_MAP_SWEEP ? b->L.n_pad : n_inst;
   if (!alloc_all(ctx, {{&b->state, sb}, {&b->seeds, n_seed * 8}, {&b->ctl, sizeof(DevCtl)}}))
@@ -881,11 +944,100 @@ rteaal_status rteaal_step(rteaal_ctx* ctx, rteaal_batch_id id, uint64_t n_cycles
 rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_id* ids,
                                const uint64_t* n_cycles) {
   if (!ctx || (n && (!ids || !n_cycles))) return fail(ctx, RTEAAL_E_INVALID_ARG, "bad argument");
-  for (uint32_t k = 0; k < n; ++k)
-    if (!find_batch(ctx, ids[k])) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", ids[k]);
+  if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
+  std::vector<Batch*> bs(n);
   for (uint32_t k = 0; k < n; ++k) {
-    rteaal_status st = rteaal_step(ctx, ids[k], n_cycles[k], nullptr);
+    bs[k] = find_batch(ctx, ids[k]);
+    if (!bs[k]) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", ids[k]);
+    for (uint32_t q = 0; q < k; ++q)
+      if (ids[q] == ids[k]) return fail(ctx, RTEAAL_E_INVALID_ARG, "batch %u listed twice", ids[k]);
+  }
+  for (uint32_t k = 0; k < n; ++k) HIP_TRY(ctx, launch_set_words((DevCtl*)bs[k]->ctl.p, nullptr, ctx->stream));
+
+  // SWEEP batches: each on an auxiliary stream, forked from and joined back
+  // into the context stream, so their layer kernels overlap.
+  uint32_t n_aux = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    Batch& b = *bs[k];
+    if (b.mapping != RTEAAL_MAP_SWEEP || n_cycles[k] == 0) continue;
+    const uint32_t a = n_aux % 4;
+    if (!ctx->aux[a]) {
+      HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->aux[a], hipStreamNonBlocking));
+      HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->join[a], hipEventDisableTiming));
+    }
+    if (!ctx->fork) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    if (n_aux < 4) {
+      HIP_TRY(ctx, hipEventRecord(ctx->fork, ctx->stream));
+      HIP_TRY(ctx, hipStreamWaitEvent(ctx->aux[a], ctx->fork, 0));
+    }
+    hipStream_t keep = ctx->stream;
+    ctx->stream = ctx->aux[a];
+    rteaal_status st = enqueue_cycles(ctx, *find_design(ctx, b.design), b, n_cycles[k]);
+    ctx->stream = keep;
     if (st != RTEAAL_OK) return st;
+    b.cycle += n_cycles[k];
+    ++n_aux;
+  }
+
+  // RESIDENT batches: one persistent launch per kernel configuration, every
+  // workgroup running one instance of one batch for that batch's cycles.
+  struct Key {
+    bool lds, ops;
+    uint32_t unroll, block;
+    bool operator<(const Key& o) const {
+      return std::tie(lds, ops, unroll, block) < std::tie(o.lds, o.ops, o.unroll, o.block);
+    }
+  };
+  std::map<Key, std::vector<uint32_t>> groups;
+  for (uint32_t k = 0; k < n; ++k)
+    if (bs[k]->mapping == RTEAAL_MAP_RESIDENT && n_cycles[k])
+      groups[Key{bs[k]->lds, bs[k]->lds_ops, bs[k]->unroll, bs[k]->block}].push_back(k);
+  for (auto& g : groups) {
+    std::vector<uint64_t> left(g.second.size());
+    for (size_t q = 0; q < g.second.size(); ++q) left[q] = n_cycles[g.second[q]];
+    for (;;) {
+      std::vector<ResJob> jobs;
+      std::vector<uint2> map;
+      std::vector<std::pair<DevCtl*, uint64_t>> adv;
+      size_t lds = 0;
+      for (size_t q = 0; q < g.second.size(); ++q) {
+        if (!left[q]) continue;
+        Batch& b = *bs[g.second[q]];
+        DesignHost& h = *find_design(ctx, b.design);
+        const uint64_t c = std::min(kResidentChunk, left[q]);
+        left[q] -= c;
+        const uint32_t j = (uint32_t)jobs.size();
+        jobs.push_back(res_job(h, b, c));
+        for (uint32_t i = 0; i < b.n_inst; ++i) map.push_back(make_uint2(j, i));
+        adv.push_back({(DevCtl*)b.ctl.p, c});
+        lds = std::max(lds, resident_lds_bytes(b.L, (uint32_t)h.ops.size(), (uint32_t)h.layers.size(),
+                                               b.lds, b.lds_ops));
+      }
+      if (jobs.empty()) break;
+      const size_t need = jobs.size() * sizeof(ResJob) + map.size() * sizeof(uint2);
+      if (ctx->multi.bytes < need) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        dev_free(ctx, ctx->multi);
+        if (!alloc_all(ctx, {{&ctx->multi, std::max<size_t>(need, 1u << 16) * 2}}))
+          return fail(ctx, RTEAAL_E_NO_MEMORY, "job table allocation failed");
+      }
+      std::vector<char> blob(need);
+      memcpy(blob.data(), jobs.data(), jobs.size() * sizeof(ResJob));
+      memcpy(blob.data() + jobs.size() * sizeof(ResJob), map.data(), map.size() * sizeof(uint2));
+      HIP_TRY(ctx, hipMemcpyAsync(ctx->multi.p, blob.data(), need, hipMemcpyHostToDevice, ctx->stream));
+      // The copy above was staged from pageable memory; the next reuse of the
+      // table is ordered after this launch on the same stream.
+      const ResJob* dj = (const ResJob*)ctx->multi.p;
+      const uint2* dm = (const uint2*)((char*)ctx->multi.p + jobs.size() * sizeof(ResJob));
+      HIP_TRY(ctx, launch_resident_multi(dj, dm, (uint32_t)map.size(), g.first.block, g.first.lds,
+                                         g.first.ops, g.first.unroll, lds, ctx->stream));
+      for (auto& a : adv) HIP_TRY(ctx, launch_advance(a.first, a.second, ctx->stream));
+    }
+    for (uint32_t k : g.second) bs[k]->cycle += n_cycles[k];
+  }
+  for (uint32_t a = 0; a < std::min<uint32_t>(n_aux, 4); ++a) {
+    HIP_TRY(ctx, hipEventRecord(ctx->join[a], ctx->aux[a]));
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, ctx->join[a], 0));
   }
   return RTEAAL_OK;
 }
@@ -964,6 +1116,70 @@ rteaal_status rteaal_write_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t f
     return fail(ctx, RTEAAL_E_DEVICE, "write_state: %s", hipGetErrorString(e));
   }
   b->cycle = cycle;
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_inst,
+                              uint32_t trial_cycles, rteaal_batch_opts* best, double* rate) {
+  if (!ctx || n_inst == 0) return fail(ctx, RTEAAL_E_INVALID_ARG, "bad argument");
+  if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
+  DesignHost* h = find_design(ctx, id);
+  if (!h) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown design %u", id);
+  // Trial length: about 2e9 op-evaluations per candidate, 1..64 cycles.
+  uint64_t cyc = trial_cycles;
+  if (!cyc) {
+    const double per_cycle = (double)h->ops.size() * n_inst;
+    cyc = (uint64_t)std::max(1.0, std::min(64.0, 2e9 / std::max(per_cycle, 1.0)));
+  }
+  std::vector<rteaal_batch_opts> cand;
+  const uint32_t m64 = ((h->max_layer_ops + 63) / 64) * 64;
+  for (uint32_t blk : {128u, 256u, 512u, 1024u}) {
+    if (blk > 2 * std::max<uint32_t>(m64, 128u)) continue;
+    for (uint32_t u : {1u, 2u, 4u}) cand.push_back(rteaal_batch_opts{RTEAAL_MAP_RESIDENT, blk, 0, 0, 0, u});
+  }
+  for (uint32_t opw : {2u, 4u, 8u, 16u, 32u})
+    for (uint32_t u : {1u, 2u, 4u}) cand.push_back(rteaal_batch_opts{RTEAAL_MAP_SWEEP, 0, opw, 0, 0, u});
+  std::vector<uint64_t> seeds(n_inst);
+  for (uint32_t i = 0; i < n_inst; ++i) seeds[i] = i;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  double best_rate = -1.0;
+  rteaal_batch_opts best_o{};
+  rteaal_status st = RTEAAL_OK;
+  std::string keep_err;
+  for (const auto& o : cand) {
+    rteaal_batch_id b = 0;
+    st = rteaal_create_batch(ctx, id, n_inst, seeds.data(), &o, &b);
+    if (st == RTEAAL_E_NO_MEMORY) { st = RTEAAL_OK; continue; }
+    if (st != RTEAAL_OK) break;
+    st = rteaal_step(ctx, b, 1, nullptr);  // warm-up (and graph capture)
+    hipError_t e = hipSuccess;
+    if (st == RTEAAL_OK) e = hipEventRecord(e0, ctx->stream);
+    if (st == RTEAAL_OK && e == hipSuccess) st = rteaal_step(ctx, b, cyc, nullptr);
+    if (st == RTEAAL_OK && e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+    if (st == RTEAAL_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (st == RTEAAL_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    rteaal_free_batch(ctx, b);
+    if (e != hipSuccess) {
+      ctx->poisoned = true;
+      st = fail(ctx, RTEAAL_E_DEVICE, "autotune timing: %s", hipGetErrorString(e));
+    }
+    if (st != RTEAAL_OK) break;
+    const double r = (double)n_inst * (double)cyc / (std::max(ms, 1e-3f) * 1e-3);
+    if (r > best_rate) {
+      best_rate = r;
+      best_o = o;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != RTEAAL_OK) return st;
+  if (best_rate < 0) return fail(ctx, RTEAAL_E_NO_MEMORY, "no candidate fits in device memory");
+  ctx->tuned[{id, n_inst}] = best_o;
+  if (best) *best = best_o;
+  if (rate) *rate = best_rate;
   return RTEAAL_OK;
 }
 

@@ -15,6 +15,8 @@ __host__ __device__ inline uint32_t cls_limbs(uint32_t c) { return c <= CD ? 1u 
 __host__ __device__ inline uint32_t cls_of_width(uint32_t w) {
   return w == 1 ? CB : w <= 32 ? CW : w <= 64 ? CD : w <= 128 ? CL2 : w <= 192 ? CL3 : CL4;
 }
+// Bytes one value of class c takes in an instance's wide region (c != CB).
+__host__ __device__ inline uint32_t cls_bytes(uint32_t c) { return c == CW ? 4u : 8u * cls_limbs(c); }
 
 // Operation codes: the public rank-N coordinates 0..14 plus three
 // bookkeeping operations the encoder adds around the design's layers:
@@ -32,7 +34,7 @@ enum Kind : uint32_t { K_BIT = 0, K_U64 = 1, K_WIDE = 2 };
 // One operation, 32 bytes.
 //   code: opc[0:5] kind[6:7] arity[8:9] dst class[10:12] src classes [13:15][16:18][19:21]
 //   wimm: dst width[0:8] (1..256), imm[9:17] (shift, low bit, width of o1 for CONCAT)
-//   dst, src[3]: indices within their class
+//   dst, src[3]: bit index of a 1-bit slot, else its byte offset Y (see StateLayout)
 //   aux0: STIM input number / CONST literal index;  aux1: STIM limb offset in a words row
 struct DevOp {
   uint32_t code, wimm, dst, src[3], aux0, aux1;
@@ -64,15 +66,24 @@ struct DevCtl {
 };
 
 // Byte layout of one batch's signal state.
+//
+// Every 1-bit slot has a bit index i; every other slot has a byte offset Y
+// inside one instance's "wide region" (CW elements take 4 bytes, CD 8, CLk
+// 8k with the limbs contiguous).  Operation records carry i or Y, so one
+// record format serves both mappings:
+//   RESIDENT, instance j at j*pitch:
+//     1-bit slot i: bit i of the 64-bit words at b_off;
+//     other slot:   its bytes at nb_off + Y (limb l at + 8l).
+//   SWEEP, tile t = j / 64, lane = j % 64:
+//     1-bit slot i: bit `lane` of the word at b_off + (i*n_tiles + t)*8
+//       (the words of one slot are adjacent across tiles);
+//     other slot:   tile t's block starts at nb_off + t*tile_bytes; the 4- or
+//       8-byte element at resident offset Y (limb l: Y + 8l) becomes a row of
+//       64 lanes at (Y + 8l)*64, lane at +4*lane (CW) or +8*lane (others).
+//   zero_off: zero bytes (16 per instance block for RESIDENT, 256 for SWEEP)
+//   read in place of an absent operand or high half.
 struct StateLayout {
-  // RESIDENT: class c of instance j at base + j*pitch + off[c];
-  //           CB bit i at word i/64, CW/CD element i, CLk element i*k + limb.
-  // SWEEP:    class c at base + off[c];
-  //           CB slot i, tile t at word i*n_tiles + t;
-  //           CW/CD slot i, instance j at element i*n_pad + j;
-  //           CLk slot i limb l instance j at element (i*k + l)*n_pad + j.
-  uint64_t off[NCLS];
-  uint64_t pitch;
+  uint64_t b_off, nb_off, zero_off, pitch, tile_bytes;
   uint32_t n_tiles, n_pad;
 };
 
@@ -84,20 +95,38 @@ struct Program {
   uint32_t words_per_inst;      // stimulus limbs per instance and cycle
 };
 
-// Reference to a stored value for state read-out and restore.
+// Reference to a stored value for state read-out and restore: class, bit
+// index (1-bit) or wide-region byte offset Y (others), offset in the packed
+// output row, declared width.
 struct SlotRef {
-  uint32_t cls, idx, out_off, width;
+  uint32_t cls, pos, out_off, width;
+};
+
+// Everything a RESIDENT workgroup needs to run its instance of one batch.
+struct ResJob {
+  const DevOp* ops;
+  const DevLayer* layers;
+  const uint64_t* const_limbs;
+  uint32_t n_layers, words_per_inst, n_ops_total, n_inst_total;
+  StateLayout L;
+  char* state;
+  const uint64_t* seeds;
+  const DevCtl* ctl;
+  uint64_t n_cycles;
 };
 
 // ---- kernel launchers (kernels.hip) ---------------------------------------
-hipError_t launch_resident(const Program& p, const StateLayout& L, char* state,
-                           const uint64_t* seeds, DevCtl* ctl, uint32_t n_inst,
-                           uint32_t n_inst_total, uint32_t inst_base, uint64_t n_cycles,
-                           uint32_t block, bool lds, hipStream_t s);
+hipError_t launch_resident(const ResJob& J, uint32_t n_inst, uint32_t inst_base, uint32_t block,
+                           bool lds_state, bool lds_ops, uint32_t unroll, hipStream_t s);
+hipError_t launch_resident_multi(const ResJob* jobs, const uint2* map, uint32_t n_blocks,
+                                 uint32_t block, bool lds_state, bool lds_ops, uint32_t unroll,
+                                 size_t lds, hipStream_t s);
+size_t resident_lds_bytes(const StateLayout& L, uint32_t n_ops_total, uint32_t n_layers,
+                          bool lds_state, bool lds_ops);
 hipError_t launch_sweep_layer(const Program& p, const StateLayout& L, char* state,
                               const uint64_t* seeds, DevCtl* ctl, uint32_t n_inst,
                               uint32_t layer, uint32_t layer_ops, uint32_t ops_per_wave,
-                              hipStream_t s);
+                              uint32_t unroll, hipStream_t s);
 hipError_t launch_advance(DevCtl* ctl, uint64_t n, hipStream_t s);
 hipError_t launch_set_words(DevCtl* ctl, const uint64_t* words, hipStream_t s);
 hipError_t launch_pack(bool sweep, const StateLayout& L, const char* state, const SlotRef* refs,

@@ -5,18 +5,19 @@
 //  * k_resident — one workgroup per instance, one lane per operation.  All
 //    cycles of a step run inside one launch; layers are separated by a
 //    workgroup barrier (the iterative rank I of Cascade 1).  The instance's
-//    signal vector LI lives in LDS when it fits, else in HBM/L2.
+//    signal vector LI, and optionally the whole program, live in LDS when
+//    they fit, else LI stays in HBM/L2.
 //
 //  * k_sweep — one lane per instance (64 instances per wavefront), one
-//    launch per layer.  An operation record is read once per wavefront
-//    (wave-uniform, shared by 64 instances) and each operand gather is one
-//    coalesced row of 64 instance values; 1-bit signals are bit-sliced so
-//    that a whole row is one 64-bit word.
+//    launch per layer.  An operation record is read once per wavefront with
+//    scalar loads (shared by 64 instances), each operand gather is one
+//    coalesced row of 64 instance values, and 1-bit signals are bit-sliced so
+//    that one 64-bit word holds the signal for the wavefront's 64 instances.
 //
-// Within a layer, every operation reads only slots written by earlier
-// layers (levelization), so operations of one layer may run in any order
-// and the store of each layer output LO goes straight to its LI slot
-// (identity elision).
+// Within a layer every operation reads only slots written by earlier layers
+// (levelization), so the operations of a layer may run in any order, several
+// of them may be in flight at once, and each layer output LO is stored
+// straight into its LI slot (identity elision).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -24,254 +25,363 @@
 
 namespace rteaal {
 
-// ---------------------------------------------------------------------------
-// RESIDENT: per-instance state at `s` (LDS or global).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t res_ld64(const char* s, const StateLayout& L, uint32_t cls,
-                                             uint32_t idx) {
-  if (cls == CB) {
-    const uint64_t w = *(const uint64_t*)(s + L.off[CB] + (uint64_t)(idx >> 6) * 8u);
-    return (w >> (idx & 63u)) & 1ull;
-  }
-  if (cls == CW) return *(const uint32_t*)(s + L.off[CW] + (uint64_t)idx * 4u);
-  return *(const uint64_t*)(s + L.off[CD] + (uint64_t)idx * 8u);
-}
-
-__device__ __forceinline__ V4 res_ldv(const char* s, const StateLayout& L, uint32_t cls,
-                                      uint32_t idx) {
-  if (cls <= CD) return v4_from(res_ld64(s, L, cls, idx));
-  const uint32_t k = cls_limbs(cls);
-  const uint64_t* q = (const uint64_t*)(s + L.off[cls]) + (uint64_t)idx * k;
-  V4 r = v4_from(q[0]);
-  r.l[1] = q[1];
-  if (k > 2) r.l[2] = q[2];
-  if (k > 3) r.l[3] = q[3];
-  return r;
-}
-
-__device__ __forceinline__ void res_st64(char* s, const StateLayout& L, uint32_t cls, uint32_t idx,
-                                         uint64_t v) {
-  if (cls == CW) *(uint32_t*)(s + L.off[CW] + (uint64_t)idx * 4u) = (uint32_t)v;
-  else *(uint64_t*)(s + L.off[CD] + (uint64_t)idx * 8u) = v;
-}
-
-__device__ __forceinline__ void res_stv(char* s, const StateLayout& L, uint32_t cls, uint32_t idx,
-                                        const V4& v) {
-  if (cls <= CD) {
-    res_st64(s, L, cls, idx, v.l[0]);
-    return;
-  }
-  const uint32_t k = cls_limbs(cls);
-  uint64_t* q = (uint64_t*)(s + L.off[cls]) + (uint64_t)idx * k;
-  q[0] = v.l[0];
-  q[1] = v.l[1];
-  if (k > 2) q[2] = v.l[2];
-  if (k > 3) q[3] = v.l[3];
-}
-
 // Value of a STIM or CONST operation for one instance.
-__device__ __forceinline__ V4 source_value(const Program& p, const DevOp& op, uint64_t seed,
-                                           uint64_t cycle, const uint64_t* words,
+__device__ __forceinline__ V4 source_value(const uint64_t* const_limbs, const DevOp& op,
+                                           uint64_t seed, uint64_t cycle, const uint64_t* words,
                                            uint64_t words_row, uint32_t w) {
   V4 v = v4_from(0);
   const uint32_t nl = (w + 63u) >> 6;
   if (op_opc(op.code) == OP_CONST) {
-    for (uint32_t l = 0; l < nl; ++l) v.l[l] = p.const_limbs[(uint64_t)op.aux0 * 4u + l];
+#pragma unroll
+    for (uint32_t l = 0; l < 4; ++l)
+      if (l < nl) v.l[l] = const_limbs[(uint64_t)op.aux0 * 4u + l];
   } else if (words) {
-    for (uint32_t l = 0; l < nl; ++l) v.l[l] = words[words_row + op.aux1 + l];
+#pragma unroll
+    for (uint32_t l = 0; l < 4; ++l)
+      if (l < nl) v.l[l] = words[words_row + op.aux1 + l];
   } else {
-    for (uint32_t l = 0; l < nl; ++l) v.l[l] = stim_word(seed, cycle, op.aux0, l);
+#pragma unroll
+    for (uint32_t l = 0; l < 4; ++l)
+      if (l < nl) v.l[l] = stim_word(seed, cycle, op.aux0, l);
   }
   return v4_mask(v, w);
 }
 
-template <bool LDS>
-__global__ void __launch_bounds__(1024)
-k_resident(Program p, StateLayout L, char* __restrict__ state, const uint64_t* __restrict__ seeds,
-           const DevCtl* __restrict__ ctl, uint32_t n_inst_total, uint32_t inst_base,
-           uint64_t n_cycles) {
-  extern __shared__ uint4 lds_state[];
-  const uint32_t inst = inst_base + blockIdx.x;
-  char* g = state + (uint64_t)inst * L.pitch;
-  char* s = LDS ? (char*)lds_state : g;
-  if (LDS) {
-    for (uint64_t i = threadIdx.x; i < L.pitch / 16u; i += blockDim.x)
-      lds_state[i] = ((const uint4*)g)[i];
-    __syncthreads();
-  }
-  const uint64_t seed = seeds[inst];
-  const uint64_t c0 = ctl->cycle, wc0 = ctl->step_cycle0;
-  const uint64_t* words = ctl->words;
-  const uint32_t lane = threadIdx.x & 63u;
+// ---------------------------------------------------------------------------
+// RESIDENT: per-instance state block at `s` (LDS or global).
+// ---------------------------------------------------------------------------
 
-  for (uint64_t t = 0; t < n_cycles; ++t) {
+// Operand fetch without branches: two 32-bit loads at addresses chosen by
+// selects (the second reads the zero page for 1-bit and 32-bit classes, and
+// both do for an absent operand), so every load of a group of operations is
+// issued before the first wait.  A 1-bit value comes from the dword that
+// holds its bit.
+__device__ __forceinline__ uint64_t res_fetch(const char* s, const StateLayout& L, uint32_t cls,
+                                              uint32_t pos, bool on) {
+  const char* z = s + L.zero_off;
+  const char* lo = cls == CB ? s + L.b_off + (uint64_t)(pos >> 5) * 4u : s + L.nb_off + pos;
+  const char* hi = cls == CD ? lo + 4 : z;
+  if (!on) lo = hi = z;
+  const uint32_t l = *(const uint32_t*)lo, h = *(const uint32_t*)hi;
+  return cls == CB ? (uint64_t)((l >> (pos & 31u)) & 1u) : ((uint64_t)h << 32) | l;
+}
+
+__device__ __forceinline__ V4 res_ldv(const char* s, const StateLayout& L, uint32_t cls,
+                                      uint32_t pos) {
+  if (cls == CB) {
+    const uint32_t w = *(const uint32_t*)(s + L.b_off + (uint64_t)(pos >> 5) * 4u);
+    return v4_from((w >> (pos & 31u)) & 1u);
+  }
+  const char* q = s + L.nb_off + pos;
+  if (cls == CW) return v4_from(*(const uint32_t*)q);
+  const uint32_t k = cls_limbs(cls);
+  V4 r = v4_from(*(const uint64_t*)q);
+  if (k > 1) r.l[1] = *(const uint64_t*)(q + 8);
+  if (k > 2) r.l[2] = *(const uint64_t*)(q + 16);
+  if (k > 3) r.l[3] = *(const uint64_t*)(q + 24);
+  return r;
+}
+
+__device__ __forceinline__ void res_st64(char* s, const StateLayout& L, uint32_t cls,
+                                         uint32_t pos, uint64_t v) {
+  char* q = s + L.nb_off + pos;
+  if (cls == CW) *(uint32_t*)q = (uint32_t)v;
+  else *(uint64_t*)q = v;
+}
+
+__device__ __forceinline__ void res_stv(char* s, const StateLayout& L, uint32_t cls, uint32_t pos,
+                                        const V4& v) {
+  char* q = s + L.nb_off + pos;
+  if (cls == CW) {
+    *(uint32_t*)q = (uint32_t)v.l[0];
+    return;
+  }
+  const uint32_t k = cls_limbs(cls);
+  *(uint64_t*)q = v.l[0];
+  if (k > 1) *(uint64_t*)(q + 8) = v.l[1];
+  if (k > 2) *(uint64_t*)(q + 16) = v.l[2];
+  if (k > 3) *(uint64_t*)(q + 24) = v.l[3];
+}
+
+// One RESIDENT instance for n_cycles.
+// LDS_STATE: the instance's signal vector is copied into LDS for the launch.
+// LDS_OPS:   the whole program (operation and layer records) is copied into
+//            LDS as well, so no global load remains in the cycle loop.
+// U:         positions per thread handled together (records, then operands,
+//            then evaluation), so U gathers are in flight per lane.
+template <bool LDS_STATE, bool LDS_OPS, int U>
+__device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uint4* lds_dyn) {
+  const StateLayout& L = J.L;
+  char* g = J.state + (uint64_t)inst * L.pitch;
+  char* s = LDS_STATE ? (char*)lds_dyn : g;
+  const uint64_t state_lds = LDS_STATE ? L.pitch : 0;
+  const DevOp* ops = J.ops;
+  const DevLayer* layers = J.layers;
+  const uint32_t n_layers = J.n_layers;
+  if (LDS_OPS) {
+    uint4* o4 = (uint4*)((char*)lds_dyn + state_lds);
+    const uint4* go = (const uint4*)J.ops;
+    for (uint32_t i = threadIdx.x; i < J.n_ops_total * 2u; i += blockDim.x) o4[i] = go[i];
+    uint4* l4 = o4 + J.n_ops_total * 2u;
+    const uint4* gl = (const uint4*)J.layers;
+    for (uint32_t i = threadIdx.x; i < n_layers; i += blockDim.x) l4[i] = gl[i];
+    ops = (const DevOp*)o4;
+    layers = (const DevLayer*)l4;
+  }
+  if (LDS_STATE)
+    for (uint64_t i = threadIdx.x; i < L.pitch / 16u; i += blockDim.x)
+      lds_dyn[i] = ((const uint4*)g)[i];
+  if (LDS_STATE || LDS_OPS) __syncthreads();
+
+  const uint64_t seed = J.seeds[inst];
+  const uint64_t c0 = J.ctl->cycle, wc0 = J.ctl->step_cycle0;
+  const uint64_t* words = J.ctl->words;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t bd = blockDim.x;
+
+  for (uint64_t t = 0; t < J.n_cycles; ++t) {
     const uint64_t cycle = c0 + t;
     const uint64_t words_row =
-        ((cycle - wc0) * (uint64_t)n_inst_total + inst) * (uint64_t)p.words_per_inst;
-    for (uint32_t li = 0; li < p.n_layers; ++li) {
-      const DevLayer ly = p.layers[li];
+        ((cycle - wc0) * (uint64_t)J.n_inst_total + inst) * (uint64_t)J.words_per_inst;
+    for (uint32_t li = 0; li < n_layers; ++li) {
+      const DevLayer ly = layers[li];
       const uint32_t n = ly.end - ly.begin;
       const uint32_t n64 = (n + 63u) & ~63u;
-      for (uint32_t q = threadIdx.x; q < n64; q += blockDim.x) {
-        uint64_t bit = 0;
-        bool bdst = false;
-        if (q < n) {
-          const DevOp op = p.ops[ly.begin + q];
-          const uint32_t code = op.code, opc = op_opc(code), ar = op_arity(code);
-          const uint32_t dc = op_dcls(code), w = op_width(op.wimm), imm = op_imm(op.wimm);
-          if (opc >= OP_STIM) {
-            const V4 v = source_value(p, op, seed, cycle, words, words_row, w);
-            if (dc == CB) {
-              bdst = true;
-              bit = v.l[0] & 1ull;
-            } else {
-              res_stv(s, L, dc, op.dst, v);
+      for (uint32_t q0 = threadIdx.x; q0 < n64; q0 += U * bd) {
+        DevOp op[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) op[u] = ops[ly.begin + min(q0 + u * bd, n - 1u)];
+        uint64_t va[U], vb[U], vc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t q = q0 + u * bd, code = op[u].code, ar = op_arity(code);
+          const bool fast = q < n && op_kind(code) != K_WIDE && op_opc(code) < OP_STIM;
+          va[u] = res_fetch(s, L, op_scls(code, 0), op[u].src[0], fast);
+          vb[u] = res_fetch(s, L, op_scls(code, 1), op[u].src[1], fast && ar > 1);
+          vc[u] = res_fetch(s, L, op_scls(code, 2), op[u].src[2], fast && ar > 2);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t q = q0 + u * bd;
+          if (q < n64) {  // the same for every lane of a wavefront
+            uint64_t bit = 0;
+            bool bdst = false;
+            if (q < n) {
+              const DevOp& o = op[u];
+              const uint32_t code = o.code, opc = op_opc(code), ar = op_arity(code);
+              const uint32_t dc = op_dcls(code), w = op_width(o.wimm), imm = op_imm(o.wimm);
+              if (opc >= OP_STIM) {
+                const V4 x = source_value(J.const_limbs, o, seed, cycle, words, words_row, w);
+                if (dc == CB) {
+                  bdst = true;
+                  bit = x.l[0] & 1ull;
+                } else {
+                  res_stv(s, L, dc, o.dst, x);
+                }
+              } else if (op_kind(code) != K_WIDE) {
+                const uint64_t r = eval_u64(opc, ar, va[u], vb[u], vc[u], imm, w);
+                if (dc == CB) {
+                  bdst = true;
+                  bit = r & 1ull;
+                } else {
+                  res_st64(s, L, dc, o.dst, r);
+                }
+              } else {
+                const V4 a = res_ldv(s, L, op_scls(code, 0), o.src[0]);
+                const V4 b = ar > 1 ? res_ldv(s, L, op_scls(code, 1), o.src[1]) : v4_from(0);
+                const V4 c = ar > 2 ? res_ldv(s, L, op_scls(code, 2), o.src[2]) : v4_from(0);
+                const V4 r = eval_wide(opc, ar, a, b, c, imm, w);
+                if (dc == CB) {
+                  bdst = true;
+                  bit = r.l[0] & 1ull;
+                } else {
+                  res_stv(s, L, dc, o.dst, r);
+                }
+              }
             }
-          } else if (op_kind(code) != K_WIDE) {
-            const uint64_t a = res_ld64(s, L, op_scls(code, 0), op.src[0]);
-            const uint64_t b = ar > 1 ? res_ld64(s, L, op_scls(code, 1), op.src[1]) : 0ull;
-            const uint64_t c = ar > 2 ? res_ld64(s, L, op_scls(code, 2), op.src[2]) : 0ull;
-            const uint64_t r = eval_u64(opc, ar, a, b, c, imm, w);
-            if (dc == CB) {
-              bdst = true;
-              bit = r & 1ull;
-            } else {
-              res_st64(s, L, dc, op.dst, r);
-            }
-          } else {
-            const V4 a = res_ldv(s, L, op_scls(code, 0), op.src[0]);
-            const V4 b = ar > 1 ? res_ldv(s, L, op_scls(code, 1), op.src[1]) : v4_from(0);
-            const V4 c = ar > 2 ? res_ldv(s, L, op_scls(code, 2), op.src[2]) : v4_from(0);
-            const V4 r = eval_wide(opc, ar, a, b, c, imm, w);
-            if (dc == CB) {
-              bdst = true;
-              bit = r.l[0] & 1ull;
-            } else {
-              res_stv(s, L, dc, op.dst, r);
-            }
+            // 1-bit outputs: the wavefront's 64 consecutive operations own one word.
+            const uint64_t m = __ballot(bit != 0ull);
+            const uint64_t any = __ballot(bdst);
+            if (any != 0ull && lane == 0)
+              *(uint64_t*)(s + L.b_off + (uint64_t)((ly.b_base + q) >> 6) * 8u) = m;
           }
         }
-        // 1-bit outputs: the wavefront's 64 consecutive operations own one word.
-        const uint64_t m = __ballot(bit != 0ull);
-        const uint64_t any = __ballot(bdst);
-        if (any != 0ull && lane == 0)
-          *(uint64_t*)(s + L.off[CB] + (uint64_t)((ly.b_base + q) >> 6) * 8u) = m;
       }
       __syncthreads();
     }
   }
-  if (LDS) {
+  if (LDS_STATE) {
     for (uint64_t i = threadIdx.x; i < L.pitch / 16u; i += blockDim.x)
-      ((uint4*)g)[i] = lds_state[i];
+      ((uint4*)g)[i] = lds_dyn[i];
   }
 }
 
+// One batch: workgroup b runs instance inst_base + b.
+template <bool LDS_STATE, bool LDS_OPS, int U>
+__global__ void __launch_bounds__(1024) k_resident(ResJob J, uint32_t inst_base) {
+  extern __shared__ uint4 lds_dyn[];
+  resident_run<LDS_STATE, LDS_OPS, U>(J, inst_base + blockIdx.x, lds_dyn);
+}
+
+// Many batches (of possibly different designs and cycle counts) in one
+// persistent launch: workgroup b runs instance map[b].y of job map[b].x.
+template <bool LDS_STATE, bool LDS_OPS, int U>
+__global__ void __launch_bounds__(1024)
+k_resident_multi(const ResJob* __restrict__ jobs, const uint2* __restrict__ map) {
+  extern __shared__ uint4 lds_dyn[];
+  const uint2 m = map[blockIdx.x];
+  const ResJob J = jobs[m.x];
+  resident_run<LDS_STATE, LDS_OPS, U>(J, m.y, lds_dyn);
+}
+
 // ---------------------------------------------------------------------------
-// SWEEP: slot-major state, lane = instance.
+// SWEEP: lane = instance.  The per-wavefront bases are plain scalars computed
+// once, so an operand address is a select between two bases plus one add.
 // ---------------------------------------------------------------------------
 struct SweepView {
-  char* base;
-  StateLayout L;
-  uint32_t tile, lane, j;
+  char* bB;          // 1-bit words of this tile: bit index i at bB + i*bstride
+  char* bT;          // this tile's block: resident offset Y at bT + Y*64
+  char* zero;        // zero page
+  uint64_t bstride;  // 8 * n_tiles
+  uint32_t lane;
 
-  __device__ __forceinline__ uint64_t ld_word(uint32_t idx) const {  // CB row of this tile
-    return ((const uint64_t*)(base + L.off[CB]))[(uint64_t)idx * L.n_tiles + tile];
+  __device__ __forceinline__ SweepView(char* st, const StateLayout& L, uint32_t tile, uint32_t ln)
+      : bB(st + L.b_off + 8ull * tile), bT(st + L.nb_off + L.tile_bytes * tile),
+        zero(st + L.zero_off), bstride(8ull * L.n_tiles), lane(ln) {}
+
+  __device__ __forceinline__ uint64_t ld_word(uint32_t i) const {
+    return *(const uint64_t*)(bB + i * bstride);
   }
-  __device__ __forceinline__ uint64_t ld64(uint32_t cls, uint32_t idx) const {
-    if (cls == CB) return (ld_word(idx) >> lane) & 1ull;
-    if (cls == CW) return ((const uint32_t*)(base + L.off[CW]))[(uint64_t)idx * L.n_pad + j];
-    return ((const uint64_t*)(base + L.off[CD]))[(uint64_t)idx * L.n_pad + j];
+  __device__ __forceinline__ void st_word(uint32_t i, uint64_t w) const {
+    *(uint64_t*)(bB + i * bstride) = w;
   }
-  __device__ __forceinline__ V4 ldv(uint32_t cls, uint32_t idx) const {
-    if (cls <= CD) return v4_from(ld64(cls, idx));
+  __device__ __forceinline__ char* elem(uint32_t cls, uint32_t pos) const {
+    return bT + (uint64_t)pos * 64u + lane * (cls == CW ? 4u : 8u);
+  }
+  // Element as stored (the whole bit-sliced word for CB, else this lane's
+  // value), as two 32-bit loads at selected addresses; the high half of a
+  // 32-bit class and an absent operand read the zero page.
+  __device__ __forceinline__ uint64_t fetch(uint32_t cls, uint32_t pos, bool on) const {
+    const bool b = cls == CB;
+    const char* row = b ? bB + pos * bstride : bT + (uint64_t)pos * 64u;
+    const uint32_t lo_lane = b ? 0u : lane * (cls == CW ? 4u : 8u);
+    const char* lo = on ? row + lo_lane : zero;
+    const char* hi = (on && cls != CW) ? row + lo_lane + 4 : zero;
+    const uint32_t l = *(const uint32_t*)lo, h = *(const uint32_t*)hi;
+    return ((uint64_t)h << 32) | l;
+  }
+  __device__ __forceinline__ uint64_t lane_val(uint32_t cls, uint64_t raw) const {
+    return cls == CB ? (raw >> lane) & 1ull : raw;
+  }
+  __device__ __forceinline__ V4 ldv(uint32_t cls, uint32_t pos) const {
+    if (cls == CB) return v4_from((ld_word(pos) >> lane) & 1ull);
+    const char* q = elem(cls, pos);
+    if (cls == CW) return v4_from(*(const uint32_t*)q);
     const uint32_t k = cls_limbs(cls);
-    const uint64_t* q = (const uint64_t*)(base + L.off[cls]) + (uint64_t)idx * k * L.n_pad + j;
-    V4 r = v4_from(q[0]);
-    r.l[1] = q[L.n_pad];
-    if (k > 2) r.l[2] = q[2ull * L.n_pad];
-    if (k > 3) r.l[3] = q[3ull * L.n_pad];
+    V4 r = v4_from(*(const uint64_t*)q);
+    if (k > 1) r.l[1] = *(const uint64_t*)(q + 512);
+    if (k > 2) r.l[2] = *(const uint64_t*)(q + 1024);
+    if (k > 3) r.l[3] = *(const uint64_t*)(q + 1536);
     return r;
   }
-  __device__ __forceinline__ void st_word(uint32_t idx, uint64_t w) const {
-    ((uint64_t*)(base + L.off[CB]))[(uint64_t)idx * L.n_tiles + tile] = w;
+  __device__ __forceinline__ void st64(uint32_t cls, uint32_t pos, uint64_t v) const {
+    char* q = elem(cls, pos);
+    if (cls == CW) *(uint32_t*)q = (uint32_t)v;
+    else *(uint64_t*)q = v;
   }
-  __device__ __forceinline__ void st64(uint32_t cls, uint32_t idx, uint64_t v) const {
-    if (cls == CW) ((uint32_t*)(base + L.off[CW]))[(uint64_t)idx * L.n_pad + j] = (uint32_t)v;
-    else ((uint64_t*)(base + L.off[CD]))[(uint64_t)idx * L.n_pad + j] = v;
-  }
-  __device__ __forceinline__ void stv(uint32_t cls, uint32_t idx, const V4& v) const {
-    if (cls <= CD) {
-      st64(cls, idx, v.l[0]);
+  __device__ __forceinline__ void stv(uint32_t cls, uint32_t pos, const V4& v) const {
+    char* q = elem(cls, pos);
+    if (cls == CW) {
+      *(uint32_t*)q = (uint32_t)v.l[0];
       return;
     }
     const uint32_t k = cls_limbs(cls);
-    uint64_t* q = (uint64_t*)(base + L.off[cls]) + (uint64_t)idx * k * L.n_pad + j;
-    q[0] = v.l[0];
-    q[L.n_pad] = v.l[1];
-    if (k > 2) q[2ull * L.n_pad] = v.l[2];
-    if (k > 3) q[3ull * L.n_pad] = v.l[3];
+    *(uint64_t*)q = v.l[0];
+    if (k > 1) *(uint64_t*)(q + 512) = v.l[1];
+    if (k > 2) *(uint64_t*)(q + 1024) = v.l[2];
+    if (k > 3) *(uint64_t*)(q + 1536) = v.l[3];
   }
 };
 
+// Operations of one wavefront are processed U at a time: first the U records
+// (scalar loads), then every operand row of the fast operations, then the
+// evaluations and stores, so U gathers are in flight per wavefront.
+template <int U>
 __global__ void __launch_bounds__(256)
-k_sweep(Program p, StateLayout L, char* __restrict__ state, const uint64_t* __restrict__ seeds,
+k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
+        const uint64_t* __restrict__ const_limbs, uint32_t words_per_inst, StateLayout L,
+        char* __restrict__ state, const uint64_t* __restrict__ seeds,
         const DevCtl* __restrict__ ctl, uint32_t n_inst, uint32_t layer, uint32_t opw) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   const uint32_t tile = wave % L.n_tiles, chunk = wave / L.n_tiles;
-  const DevLayer ly = p.layers[layer];
+  const DevLayer ly = layers[layer];
   const uint32_t o0 = ly.begin + chunk * opw;
   if (o0 >= ly.end) return;
   const uint32_t o1 = min(o0 + opw, ly.end);
-  SweepView v{state, L, tile, lane, tile * 64u + lane};
-  const bool live = v.j < n_inst;
-  const uint64_t seed = seeds[v.j];
-  const uint64_t cycle = ctl->cycle;
-  const uint64_t* words = ctl->words;
-  const uint64_t words_row =
-      ((cycle - ctl->step_cycle0) * (uint64_t)n_inst + v.j) * (uint64_t)p.words_per_inst;
+  const SweepView v(state, L, tile, lane);
+  const uint32_t inst = tile * 64u + lane;
+  const bool live = inst < n_inst;
 
-  for (uint32_t o = o0; o < o1; ++o) {
-    const DevOp op = p.ops[o];
-    const uint32_t code = op.code, opc = op_opc(code), ar = op_arity(code), kind = op_kind(code);
-    const uint32_t dc = op_dcls(code), w = op_width(op.wimm), imm = op_imm(op.wimm);
-    if (opc >= OP_STIM) {
-      V4 x = v4_from(0);
-      if (live) x = source_value(p, op, seed, cycle, words, words_row, w);
-      if (dc == CB) {
-        const uint64_t m = __ballot((x.l[0] & 1ull) != 0ull);
-        if (lane == 0) v.st_word(op.dst, m);
-      } else {
-        v.stv(dc, op.dst, x);
-      }
-    } else if (kind == K_BIT) {
-      const uint64_t a = v.ld_word(op.src[0]);
-      const uint64_t b = ar > 1 ? v.ld_word(op.src[1]) : 0ull;
-      const uint64_t c = ar > 2 ? v.ld_word(op.src[2]) : 0ull;
-      const uint64_t r = eval_bits(opc, ar, a, b, c, imm);
-      if (lane == 0) v.st_word(op.dst, r);
-    } else if (kind == K_U64) {
-      const uint64_t a = v.ld64(op_scls(code, 0), op.src[0]);
-      const uint64_t b = ar > 1 ? v.ld64(op_scls(code, 1), op.src[1]) : 0ull;
-      const uint64_t c = ar > 2 ? v.ld64(op_scls(code, 2), op.src[2]) : 0ull;
-      const uint64_t r = eval_u64(opc, ar, a, b, c, imm, w);
-      if (dc == CB) {
-        const uint64_t m = __ballot((r & 1ull) != 0ull);
-        if (lane == 0) v.st_word(op.dst, m);
-      } else {
-        v.st64(dc, op.dst, r);
-      }
-    } else {
-      const V4 a = v.ldv(op_scls(code, 0), op.src[0]);
-      const V4 b = ar > 1 ? v.ldv(op_scls(code, 1), op.src[1]) : v4_from(0);
-      const V4 c = ar > 2 ? v.ldv(op_scls(code, 2), op.src[2]) : v4_from(0);
-      const V4 r = eval_wide(opc, ar, a, b, c, imm, w);
-      if (dc == CB) {
-        const uint64_t m = __ballot((r.l[0] & 1ull) != 0ull);
-        if (lane == 0) v.st_word(op.dst, m);
-      } else {
-        v.stv(dc, op.dst, r);
+  for (uint32_t o = o0; o < o1; o += U) {
+    DevOp op[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) op[u] = ops[min(o + (uint32_t)u, o1 - 1u)];
+    uint64_t ra[U], rb[U], rc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t code = op[u].code, ar = op_arity(code);
+      const bool fast = o + u < o1 && op_kind(code) != K_WIDE && op_opc(code) < OP_STIM;
+      ra[u] = v.fetch(op_scls(code, 0), op[u].src[0], fast);
+      rb[u] = v.fetch(op_scls(code, 1), op[u].src[1], fast && ar > 1);
+      rc[u] = v.fetch(op_scls(code, 2), op[u].src[2], fast && ar > 2);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (o + u < o1) {
+        const DevOp& q = op[u];
+        const uint32_t code = q.code, opc = op_opc(code), ar = op_arity(code), kind = op_kind(code);
+        const uint32_t dc = op_dcls(code), w = op_width(q.wimm), imm = op_imm(q.wimm);
+        const uint32_t c0 = op_scls(code, 0), c1 = op_scls(code, 1), c2 = op_scls(code, 2);
+        if (opc >= OP_STIM) {
+          const uint64_t cycle = ctl->cycle;
+          const uint64_t words_row =
+              ((cycle - ctl->step_cycle0) * (uint64_t)n_inst + inst) * (uint64_t)words_per_inst;
+          V4 x = v4_from(0);
+          if (live) x = source_value(const_limbs, q, seeds[inst], cycle, ctl->words, words_row, w);
+          if (dc == CB) {
+            const uint64_t m = __ballot((x.l[0] & 1ull) != 0ull);
+            if (lane == 0) v.st_word(q.dst, m);
+          } else {
+            v.stv(dc, q.dst, x);
+          }
+        } else if (kind == K_BIT) {
+          const uint64_t r = eval_bits(opc, ar, ra[u], rb[u], rc[u], imm);
+          if (lane == 0) v.st_word(q.dst, r);
+        } else if (kind == K_U64) {
+          const uint64_t a = v.lane_val(c0, ra[u]);
+          const uint64_t b = v.lane_val(c1, rb[u]);
+          const uint64_t c = v.lane_val(c2, rc[u]);
+          const uint64_t r = eval_u64(opc, ar, a, b, c, imm, w);
+          if (dc == CB) {
+            const uint64_t m = __ballot((r & 1ull) != 0ull);
+            if (lane == 0) v.st_word(q.dst, m);
+          } else {
+            v.st64(dc, q.dst, r);
+          }
+        } else {
+          const V4 a = v.ldv(c0, q.src[0]);
+          const V4 b = ar > 1 ? v.ldv(c1, q.src[1]) : v4_from(0);
+          const V4 c = ar > 2 ? v.ldv(c2, q.src[2]) : v4_from(0);
+          const V4 r = eval_wide(opc, ar, a, b, c, imm, w);
+          if (dc == CB) {
+            const uint64_t m = __ballot((r.l[0] & 1ull) != 0ull);
+            if (lane == 0) v.st_word(q.dst, m);
+          } else {
+            v.stv(dc, q.dst, r);
+          }
+        }
       }
     }
   }
@@ -291,32 +401,26 @@ __global__ void k_set_words(DevCtl* ctl, const uint64_t* words) {
   }
 }
 
-__device__ __forceinline__ uint64_t* elem_ptr(bool sweep, const StateLayout& L, char* state,
-                                              uint32_t cls, uint32_t idx, uint32_t limb,
-                                              uint32_t inst, uint32_t* bitpos) {
+// Address of limb `limb` of a stored value of instance `inst` (for CB: the
+// word holding its bit, with the bit position in *bitpos).
+__device__ __forceinline__ char* elem_addr(bool sweep, const StateLayout& L, char* state,
+                                           uint32_t cls, uint32_t pos, uint32_t limb,
+                                           uint32_t inst, uint32_t* bitpos) {
   if (sweep) {
+    const uint64_t t = inst >> 6, ln = inst & 63u;
     if (cls == CB) {
-      *bitpos = inst & 63u;
-      return (uint64_t*)(state + L.off[CB]) + (uint64_t)idx * L.n_tiles + (inst >> 6);
+      *bitpos = (uint32_t)ln;
+      return state + L.b_off + ((uint64_t)pos * L.n_tiles + t) * 8u;
     }
-    if (cls == CW) return nullptr;  // 32-bit element, handled by the caller
-    const uint32_t k = cls_limbs(cls);
-    return (uint64_t*)(state + L.off[cls]) + ((uint64_t)idx * k + limb) * L.n_pad + inst;
+    return state + L.nb_off + t * L.tile_bytes + ((uint64_t)pos + 8u * limb) * 64u +
+           ln * (cls == CW ? 4u : 8u);
   }
   char* s = state + (uint64_t)inst * L.pitch;
   if (cls == CB) {
-    *bitpos = idx & 63u;
-    return (uint64_t*)(s + L.off[CB]) + (idx >> 6);
+    *bitpos = pos & 63u;
+    return s + L.b_off + (uint64_t)(pos >> 6) * 8u;
   }
-  if (cls == CW) return nullptr;
-  const uint32_t k = cls_limbs(cls);
-  return (uint64_t*)(s + L.off[cls]) + (uint64_t)idx * k + limb;
-}
-
-__device__ __forceinline__ uint32_t* elem32_ptr(bool sweep, const StateLayout& L, char* state,
-                                                uint32_t idx, uint32_t inst) {
-  if (sweep) return (uint32_t*)(state + L.off[CW]) + (uint64_t)idx * L.n_pad + inst;
-  return (uint32_t*)(state + (uint64_t)inst * L.pitch + L.off[CW]) + idx;
+  return s + L.nb_off + pos + 8u * limb;
 }
 
 __global__ void k_pack(bool sweep, StateLayout L, const char* state, const SlotRef* refs,
@@ -330,14 +434,12 @@ __global__ void k_pack(bool sweep, StateLayout L, const char* state, const SlotR
   uint64_t* o = out + (uint64_t)k * wpi + ref.out_off;
   for (uint32_t l = 0; l < nl; ++l) {
     uint64_t x = 0;
-    if (ref.cls == CNONE) {
-      x = 0;
-    } else if (ref.cls == CW) {
-      x = *elem32_ptr(sweep, L, (char*)state, ref.idx, inst);
-    } else {
+    if (ref.cls != CNONE) {
       uint32_t bp = 0;
-      const uint64_t* e = elem_ptr(sweep, L, (char*)state, ref.cls, ref.idx, l, inst, &bp);
-      x = ref.cls == CB ? ((*e >> bp) & 1ull) : *e;
+      const char* e = elem_addr(sweep, L, (char*)state, ref.cls, ref.pos, l, inst, &bp);
+      if (ref.cls == CB) x = (*(const uint64_t*)e >> bp) & 1ull;
+      else if (ref.cls == CW) x = *(const uint32_t*)e;
+      else x = *(const uint64_t*)e;
     }
     o[l] = x;
   }
@@ -355,21 +457,23 @@ __global__ void k_unpack(bool sweep, StateLayout L, char* state, const SlotRef* 
   const uint64_t* src = in + (uint64_t)k * wpi + ref.out_off;
   V4 v = v4_from(0);
   const uint32_t nl = (ref.width + 63u) >> 6;
-  for (uint32_t l = 0; l < nl; ++l) v.l[l] = src[l];
+#pragma unroll
+  for (uint32_t l = 0; l < 4; ++l)
+    if (l < nl) v.l[l] = src[l];
   v = v4_mask(v, ref.width);
-  if (ref.cls == CW) {
-    *elem32_ptr(sweep, L, state, ref.idx, inst) = (uint32_t)v.l[0];
-  } else if (ref.cls == CB) {
-    uint32_t bp = 0;
+  uint32_t bp = 0;
+  if (ref.cls == CB) {
     unsigned long long* e =
-        (unsigned long long*)elem_ptr(sweep, L, state, CB, ref.idx, 0, inst, &bp);
+        (unsigned long long*)elem_addr(sweep, L, state, CB, ref.pos, 0, inst, &bp);
     if (v.l[0] & 1ull) atomicOr(e, 1ull << bp);
     else atomicAnd(e, ~(1ull << bp));
+  } else if (ref.cls == CW) {
+    *(uint32_t*)elem_addr(sweep, L, state, CW, ref.pos, 0, inst, &bp) = (uint32_t)v.l[0];
   } else {
-    for (uint32_t l = 0; l < cls_limbs(ref.cls); ++l) {
-      uint32_t bp = 0;
-      *elem_ptr(sweep, L, state, ref.cls, ref.idx, l, inst, &bp) = v.l[l];
-    }
+    const uint32_t k2 = cls_limbs(ref.cls);
+#pragma unroll
+    for (uint32_t l = 0; l < 4; ++l)
+      if (l < k2) *(uint64_t*)elem_addr(sweep, L, state, ref.cls, ref.pos, l, inst, &bp) = v.l[l];
   }
 }
 
@@ -378,39 +482,112 @@ __global__ void k_unpack(bool sweep, StateLayout L, char* state, const SlotRef* 
 // ---------------------------------------------------------------------------
 size_t resident_max_lds() { return 160u * 1024u; }
 
-hipError_t launch_resident(const Program& p, const StateLayout& L, char* state,
-                           const uint64_t* seeds, DevCtl* ctl, uint32_t n_inst,
-                           uint32_t n_inst_total, uint32_t inst_base, uint64_t n_cycles,
-                           uint32_t block, bool lds, hipStream_t s) {
-  if (n_inst == 0 || n_cycles == 0) return hipSuccess;
-  if (lds) {
-    static bool attr_set = false;
-    if (!attr_set) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_resident<true>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)resident_max_lds());
-      if (e != hipSuccess) return e;
-      attr_set = true;
-    }
-    hipLaunchKernelGGL(k_resident<true>, dim3(n_inst), dim3(block), (size_t)L.pitch, s, p, L,
-                       state, seeds, (const DevCtl*)ctl, n_inst_total, inst_base, n_cycles);
-  } else {
-    hipLaunchKernelGGL(k_resident<false>, dim3(n_inst), dim3(block), 0, s, p, L, state, seeds,
-                       (const DevCtl*)ctl, n_inst_total, inst_base, n_cycles);
-  }
+namespace {
+template <class K>
+hipError_t allow_lds(K kernel, size_t lds) {
+  if (lds <= 64u * 1024u) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)resident_max_lds());
+}
+
+template <bool S, bool O, int U>
+hipError_t launch_res_t(const ResJob& J, uint32_t n_inst, uint32_t inst_base, uint32_t block,
+                        size_t lds, hipStream_t s) {
+  hipError_t e = allow_lds(k_resident<S, O, U>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_resident<S, O, U>), dim3(n_inst), dim3(block), lds, s, J, inst_base);
   return hipGetLastError();
+}
+
+template <bool S, bool O, int U>
+hipError_t launch_resm_t(const ResJob* jobs, const uint2* map, uint32_t n_blocks, uint32_t block,
+                         size_t lds, hipStream_t s) {
+  hipError_t e = allow_lds(k_resident_multi<S, O, U>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_resident_multi<S, O, U>), dim3(n_blocks), dim3(block), lds, s, jobs, map);
+  return hipGetLastError();
+}
+
+// Dispatch on the run-time configuration to the kernel instantiation.
+template <template <bool, bool, int> class F, class... A>
+hipError_t dispatch_res(bool S, bool O, uint32_t U, A&&... a) {
+  if (S && O) {
+    if (U == 1) return F<true, true, 1>::go(a...);
+    if (U == 2) return F<true, true, 2>::go(a...);
+    return F<true, true, 4>::go(a...);
+  }
+  if (S) {
+    if (U == 1) return F<true, false, 1>::go(a...);
+    if (U == 2) return F<true, false, 2>::go(a...);
+    return F<true, false, 4>::go(a...);
+  }
+  if (O) {
+    if (U == 1) return F<false, true, 1>::go(a...);
+    if (U == 2) return F<false, true, 2>::go(a...);
+    return F<false, true, 4>::go(a...);
+  }
+  if (U == 1) return F<false, false, 1>::go(a...);
+  if (U == 2) return F<false, false, 2>::go(a...);
+  return F<false, false, 4>::go(a...);
+}
+
+template <bool S, bool O, int U>
+struct ResOne {
+  static hipError_t go(const ResJob& J, uint32_t n_inst, uint32_t inst_base, uint32_t block,
+                       size_t lds, hipStream_t s) {
+    return launch_res_t<S, O, U>(J, n_inst, inst_base, block, lds, s);
+  }
+};
+
+template <bool S, bool O, int U>
+struct ResMany {
+  static hipError_t go(const ResJob* jobs, const uint2* map, uint32_t n_blocks, uint32_t block,
+                       size_t lds, hipStream_t s) {
+    return launch_resm_t<S, O, U>(jobs, map, n_blocks, block, lds, s);
+  }
+};
+}  // namespace
+
+size_t resident_lds_bytes(const StateLayout& L, uint32_t n_ops_total, uint32_t n_layers,
+                          bool lds_state, bool lds_ops) {
+  size_t b = lds_state ? L.pitch : 0;
+  if (lds_ops) b += (size_t)n_ops_total * sizeof(DevOp) + (size_t)n_layers * sizeof(DevLayer);
+  return b;
+}
+
+hipError_t launch_resident(const ResJob& J, uint32_t n_inst, uint32_t inst_base, uint32_t block,
+                           bool lds_state, bool lds_ops, uint32_t unroll, hipStream_t s) {
+  if (n_inst == 0 || J.n_cycles == 0) return hipSuccess;
+  const size_t lds = resident_lds_bytes(J.L, J.n_ops_total, J.n_layers, lds_state, lds_ops);
+  return dispatch_res<ResOne>(lds_state, lds_ops, unroll, J, n_inst, inst_base, block, lds, s);
+}
+
+hipError_t launch_resident_multi(const ResJob* jobs, const uint2* map, uint32_t n_blocks,
+                                 uint32_t block, bool lds_state, bool lds_ops, uint32_t unroll,
+                                 size_t lds, hipStream_t s) {
+  if (n_blocks == 0) return hipSuccess;
+  return dispatch_res<ResMany>(lds_state, lds_ops, unroll, jobs, map, n_blocks, block, lds, s);
 }
 
 hipError_t launch_sweep_layer(const Program& p, const StateLayout& L, char* state,
                               const uint64_t* seeds, DevCtl* ctl, uint32_t n_inst,
                               uint32_t layer, uint32_t layer_ops, uint32_t ops_per_wave,
-                              hipStream_t s) {
+                              uint32_t unroll, hipStream_t s) {
   if (layer_ops == 0) return hipSuccess;
   const uint64_t chunks = (layer_ops + ops_per_wave - 1) / ops_per_wave;
   const uint64_t waves = chunks * L.n_tiles;
-  const uint32_t blocks = (uint32_t)((waves + 3) / 4);
-  hipLaunchKernelGGL(k_sweep, dim3(blocks), dim3(256), 0, s, p, L, state, seeds,
-                     (const DevCtl*)ctl, n_inst, layer, ops_per_wave);
+  const dim3 grid((uint32_t)((waves + 3) / 4)), blk(256);
+  const DevCtl* c = ctl;
+#define RTEAAL_SWEEP(UU)                                                                       \
+  hipLaunchKernelGGL(k_sweep<UU>, grid, blk, 0, s, p.ops, p.layers, p.const_limbs,            \
+                     p.words_per_inst, L, state, seeds, c, n_inst, layer, ops_per_wave)
+  switch (unroll) {
+    case 1: RTEAAL_SWEEP(1); break;
+    case 2: RTEAAL_SWEEP(2); break;
+    case 8: RTEAAL_SWEEP(8); break;
+    default: RTEAAL_SWEEP(4); break;
+  }
+#undef RTEAAL_SWEEP
   return hipGetLastError();
 }
 

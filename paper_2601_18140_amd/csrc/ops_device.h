@@ -124,19 +124,21 @@ __device__ __forceinline__ V4 v4_mul(const V4& a, const V4& b) {
   return r;
 }
 
+// Limb k of a (0 outside 0..3), as a select chain so that no local array is
+// indexed with a run-time value.
+__device__ __forceinline__ uint64_t v4_limb(const V4& a, int k) {
+  return k == 0 ? a.l[0] : k == 1 ? a.l[1] : k == 2 ? a.l[2] : k == 3 ? a.l[3] : 0ull;
+}
+
 __device__ __forceinline__ V4 v4_shl(const V4& a, uint32_t k) {
   V4 r = v4_from(0);
   if (k >= 256) return r;
-  const uint32_t q = k >> 6, s = k & 63;
+  const int q = (int)(k >> 6);
+  const uint32_t s = k & 63u;
 #pragma unroll
   for (int i = 0; i < 4; i++) {
-    const int j = i - (int)q;
-    uint64_t x = 0;
-    if (j >= 0) {
-      x = a.l[j] << s;
-      if (s && j >= 1) x |= a.l[j - 1] >> (64 - s);
-    }
-    r.l[i] = x;
+    const uint64_t hi = v4_limb(a, i - q), lo = v4_limb(a, i - q - 1);
+    r.l[i] = s ? (hi << s) | (lo >> (64u - s)) : hi;
   }
   return r;
 }
@@ -144,16 +146,12 @@ __device__ __forceinline__ V4 v4_shl(const V4& a, uint32_t k) {
 __device__ __forceinline__ V4 v4_shr(const V4& a, uint32_t k) {
   V4 r = v4_from(0);
   if (k >= 256) return r;
-  const uint32_t q = k >> 6, s = k & 63;
+  const int q = (int)(k >> 6);
+  const uint32_t s = k & 63u;
 #pragma unroll
   for (int i = 0; i < 4; i++) {
-    const int j = i + (int)q;
-    uint64_t x = 0;
-    if (j < 4) {
-      x = a.l[j] >> s;
-      if (s && j + 1 < 4) x |= a.l[j + 1] << (64 - s);
-    }
-    r.l[i] = x;
+    const uint64_t lo = v4_limb(a, i + q), hi = v4_limb(a, i + q + 1);
+    r.l[i] = s ? (lo >> s) | (hi << (64u - s)) : lo;
   }
   return r;
 }

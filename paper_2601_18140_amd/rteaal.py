@@ -23,7 +23,7 @@ __all__ = [
     "rteaal_validate_design", "rteaal_load_design", "rteaal_unload_design", "rteaal_design_format",
     "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch", "rteaal_batch_info",
     "rteaal_step", "rteaal_step_many", "rteaal_sync", "rteaal_read_state", "rteaal_write_state",
-    "rteaal_kernel_timing", "unpack_limbs", "pack_limbs", "rteaal_layer_format", "rteaal_rank_format",
+    "rteaal_kernel_timing", "rteaal_autotune", "opts_dict", "unpack_limbs", "pack_limbs", "rteaal_layer_format", "rteaal_rank_format",
 ]
 
 RTEAAL_OK = 0
@@ -63,7 +63,8 @@ class rteaal_design_desc(C.Structure):
 
 class rteaal_batch_opts(C.Structure):
     _fields_ = [("mapping", C.c_uint32), ("block_threads", C.c_uint32),
-                ("ops_per_wave", C.c_uint32), ("lds_state", C.c_uint32)]
+                ("ops_per_wave", C.c_uint32), ("lds_state", C.c_uint32),
+                ("lds_ops", C.c_uint32), ("unroll", C.c_uint32)]
 
 
 class rteaal_stimulus(C.Structure):
@@ -112,6 +113,7 @@ def library():
         "rteaal_read_state": ([vp, u32, u32, u32, u32, vp, C.c_size_t, C.POINTER(C.c_size_t)], st),
         "rteaal_write_state": ([vp, u32, u32, u32, vp, u64], st),
         "rteaal_kernel_timing": ([vp, u32, C.c_int, C.POINTER(u64), C.POINTER(C.c_double)], st),
+        "rteaal_autotune": ([vp, u32, u32, u32, C.POINTER(rteaal_batch_opts), C.POINTER(C.c_double)], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -126,7 +128,7 @@ def exported_symbols():
             "rteaal_load_design", "rteaal_unload_design", "rteaal_design_format",
             "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch",
             "rteaal_batch_info", "rteaal_step", "rteaal_step_many", "rteaal_sync",
-            "rteaal_read_state", "rteaal_write_state", "rteaal_kernel_timing"]
+            "rteaal_read_state", "rteaal_write_state", "rteaal_kernel_timing", "rteaal_autotune"]
 
 
 def _check(ctx, status):
@@ -283,23 +285,23 @@ def rteaal_design_format(ctx, design_id, layer):
     return f
 
 
-def _opts(mapping, block_threads, ops_per_wave, lds_state):
-    return rteaal_batch_opts(int(mapping), int(block_threads), int(ops_per_wave), int(lds_state))
+def _opts(mapping, block_threads=0, ops_per_wave=0, lds_state=0, lds_ops=0, unroll=0):
+    return rteaal_batch_opts(int(mapping), int(block_threads), int(ops_per_wave), int(lds_state),
+                             int(lds_ops), int(unroll))
 
 
-def rteaal_batch_footprint(ctx, design_id, n_instances, mapping=RTEAAL_MAP_AUTO,
-                           block_threads=0, ops_per_wave=0, lds_state=0):
-    o = _opts(mapping, block_threads, ops_per_wave, lds_state)
+def rteaal_batch_footprint(ctx, design_id, n_instances, mapping=RTEAAL_MAP_AUTO, **opts):
+    o = _opts(mapping, **opts)
     out = C.c_uint64()
     _check(ctx.handle, library().rteaal_batch_footprint(ctx.handle, int(design_id), int(n_instances),
                                                         C.byref(o), C.byref(out)))
     return out.value
 
 
-def rteaal_create_batch(ctx, design_id, seeds, mapping=RTEAAL_MAP_AUTO, block_threads=0,
-                        ops_per_wave=0, lds_state=0):
+def rteaal_create_batch(ctx, design_id, seeds, mapping=RTEAAL_MAP_AUTO, **opts):
+    """opts: block_threads, ops_per_wave, lds_state, lds_ops, unroll (see rteaal_batch_opts)."""
     seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
-    o = _opts(mapping, block_threads, ops_per_wave, lds_state)
+    o = _opts(mapping, **opts)
     out = C.c_uint32()
     _check(ctx.handle, library().rteaal_create_batch(ctx.handle, int(design_id), int(seeds.shape[0]),
                                                      seeds.ctypes.data, C.byref(o), C.byref(out)))
@@ -364,6 +366,19 @@ def rteaal_write_state(ctx, batch_id, first, regs, cycle):
     _check(ctx.handle, library().rteaal_write_state(ctx.handle, int(batch_id), int(first), int(n),
                                                     regs.ctypes.data if regs.size else None,
                                                     int(cycle)))
+
+
+def opts_dict(o):
+    return {"mapping": o.mapping, "block_threads": o.block_threads, "ops_per_wave": o.ops_per_wave,
+            "lds_state": o.lds_state, "lds_ops": o.lds_ops, "unroll": o.unroll}
+
+
+def rteaal_autotune(ctx, design_id, n_instances, trial_cycles=0):
+    """(best options as a dict, instance-cycles/s); later AUTO batches use them."""
+    o, r = rteaal_batch_opts(), C.c_double()
+    _check(ctx.handle, library().rteaal_autotune(ctx.handle, int(design_id), int(n_instances),
+                                                 int(trial_cycles), C.byref(o), C.byref(r)))
+    return opts_dict(o), r.value
 
 
 def rteaal_kernel_timing(ctx, batch_id, enable):

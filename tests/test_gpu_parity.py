@@ -183,3 +183,39 @@ def test_single_200k_batched_and_plain(ctx):
     R.rteaal_unload_design(ctx, did)
     ref1, _, _ = oracle.run(d, seeds[:1], 12)
     assert_same(got1, ref1, "plain")
+
+
+# ---- several designs in one step -------------------------------------------
+def test_step_many_mixed_designs(ctx):
+    """Batches of different designs, sizes, mappings and cycle counts advanced
+    together by one rteaal_step_many equal the oracle and the batch alone."""
+    cfgs = [rtlgen.GenConfig(300, 5, 20, 6, rtlgen.generator.WIDTHS_STD, "m0"),
+            rtlgen.GenConfig(2500, 11, 50, 16, rtlgen.generator.WIDTHS_MULTIDESIGN, "m1"),
+            rtlgen.GenConfig(900, 20, 30, 8, rtlgen.generator.WIDTHS_LARGE, "m2"),
+            rtlgen.GenConfig(120, 3, 8, 4, rtlgen.generator.WIDTHS_STD, "m3")]
+    plan = [(0, 3, R.RTEAAL_MAP_RESIDENT, 17), (1, 70, R.RTEAAL_MAP_SWEEP, 9),
+            (2, 5, R.RTEAAL_MAP_RESIDENT, 23), (3, 130, R.RTEAAL_MAP_SWEEP, 4),
+            (1, 2, R.RTEAAL_MAP_RESIDENT, 12), (2, 66, R.RTEAAL_MAP_SWEEP, 15)]
+    designs = [rtlgen.generate(c, 40 + i) for i, c in enumerate(cfgs)]
+    dids = [R.rteaal_load_design(ctx, d) for d in designs]
+    bids, seeds_of = [], []
+    for k, (di, n, m, cyc) in enumerate(plan):
+        seeds = rtlgen.instance_seeds(n, design_index=k)
+        seeds_of.append(seeds)
+        bids.append(R.rteaal_create_batch(ctx, dids[di], seeds, mapping=m))
+    note("step_many: two rounds over six batches")
+    R.rteaal_step_many(ctx, bids, [p[3] for p in plan])
+    R.rteaal_step_many(ctx, bids[::2], [p[3] for p in plan[::2]])
+    for k, (di, n, m, cyc) in enumerate(plan):
+        total = cyc * (2 if k % 2 == 0 else 1)
+        d = designs[di]
+        got = R.unpack_limbs(R.rteaal_read_state(ctx, bids[k]), d.slot_width[d.reg_slot])
+        ref, _, _ = oracle.run(d, seeds_of[k], total)
+        assert_same(got, ref, f"batch {k}")
+        alone, _, _ = run_gpu(ctx, d, seeds_of[k], total, mapping=m)
+        assert_same(got, alone, f"batch {k} alone")
+        assert R.rteaal_batch_info(ctx, bids[k])[1] == total
+    for b in bids:
+        R.rteaal_free_batch(ctx, b)
+    for d in dids:
+        R.rteaal_unload_design(ctx, d)

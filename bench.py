@@ -90,18 +90,138 @@ def parity_sample(R, ctx, did, d, seeds, mapping, cycles=3):
     return bool(np.array_equal(got, ref))
 
 
+def bench_multi(args, R, torch):
+    """64 designs of uneven size, each with its own instance count, advanced
+    together by rteaal_step_many (one persistent launch for the RESIDENT
+    batches, overlapping streams for the SWEEP batches)."""
+    t0 = time.perf_counter()
+    plan = rtlgen.multidesign_batch(seed=2, n_designs=args.designs)
+    designs = [rtlgen.generate(cfg, seed) for cfg, seed, _ in plan]
+    print(f"[bench] {len(designs)} designs ({sum(d.n_ops for d in designs)} ops, "
+          f"{sum(n for _, _, n in plan)} instances) generated in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    ctx = R.rteaal_create(0)
+    dids = [R.rteaal_load_design(ctx, d) for d in designs]
+    bids, tuned = [], []
+    t0 = time.perf_counter()
+    for k, (did, (cfg, seed, n)) in enumerate(zip(dids, plan)):
+        if not args.no_autotune:
+            o, _ = R.rteaal_autotune(ctx, did, n, trial_cycles=2)
+            tuned.append(o)
+        bids.append(R.rteaal_create_batch(ctx, did, rtlgen.instance_seeds(n, design_index=k)))
+    print(f"[bench] batches created (autotune {time.perf_counter() - t0:.1f}s)", file=sys.stderr,
+          flush=True)
+    ok = True
+    import oracle
+    for k in (0, len(bids) - 1):                      # parity sample: a few cycles, first instance
+        d = designs[k]
+        b = R.rteaal_create_batch(ctx, dids[k], rtlgen.instance_seeds(plan[k][2], design_index=k))
+        R.rteaal_step_many(ctx, [b], [3])
+        got = R.unpack_limbs(R.rteaal_read_state(ctx, b, 0, 1), d.slot_width[d.reg_slot])
+        R.rteaal_free_batch(ctx, b)
+        ref, _, _ = oracle.run(d, rtlgen.instance_seeds(plan[k][2], design_index=k)[:1], 3)
+        ok = ok and bool(np.array_equal(got, ref))
+    cps = args.cycles_per_step or 200
+    steps = args.steps if args.steps is not None else 5
+    n_inst = [n for _, _, n in plan]
+    for _ in range(args.warmup):
+        R.rteaal_step_many(ctx, bids, [cps] * len(bids))
+    R.rteaal_sync(ctx)
+    stream = ctx.stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        R.rteaal_step_many(ctx, bids, [cps] * len(bids))
+    ev1.record(stream)
+    ev1.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    value = sum(n_inst) * cps * steps / (ms / 1e3)
+    maps = [R.rteaal_batch_info(ctx, b)[0] for b in bids]
+    for b in bids:
+        R.rteaal_free_batch(ctx, b)
+    R.rteaal_destroy(ctx)
+    return {
+        "metric": METRIC, "value": round(value, 2), "unit": "instance-cycles/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms / steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "multi-64", "designs": len(designs),
+                   "ops": sum(d.n_ops for d in designs), "instances": sum(n_inst),
+                   "cycles_per_step": cps, "resident_batches": maps.count(R.RTEAAL_MAP_RESIDENT),
+                   "sweep_batches": maps.count(R.RTEAAL_MAP_SWEEP)},
+        "parity_sample_ok": ok, "roofline": None, "cpu_baseline": None,
+    }
+
+
+def bench_serving(args, R, torch):
+    """Poisson stream of jobs over a pool of designs with continuous batching."""
+    from paper_2601_18140_amd import serving
+    t0 = time.perf_counter()
+    pool_cfg = rtlgen.serving_pool(seed=4, n_designs=args.designs,
+                                   ops_hi=args.serving_ops_hi)
+    pool = [rtlgen.generate(cfg, seed) for cfg, seed in pool_cfg]
+    print(f"[bench] pool of {len(pool)} designs generated in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    n_jobs = args.serving_jobs
+    spec = rtlgen.serving_jobs(seed=4, n_jobs=n_jobs, pool_size=len(pool),
+                               inst_hi=args.serving_inst_hi, cyc_hi=args.serving_cycles_hi)
+    jobs = [serving.Job(job_id=k, design=d, n_inst=n, n_cycles=c) for k, (d, n, c) in enumerate(spec)]
+    arrivals = serving.poisson_arrivals(args.serving_rate, n_jobs, seed=4)
+    ctx = R.rteaal_create(0)
+    srv = serving.Server(ctx, pool, budget_bytes=int(args.serving_budget_gb * (1 << 30)))
+    stats = srv.run(jobs, arrivals, duration=args.serving_seconds)
+    srv.close()
+    # Each finished job, re-run alone: identical registers.
+    import numpy as _np
+    same = True
+    check = [j for j in srv.finished][: args.serving_verify]
+    for j in check:
+        d = pool[j.design]
+        did = R.rteaal_load_design(ctx, d)
+        b = R.rteaal_create_batch(ctx, did, j.seeds)
+        R.rteaal_step(ctx, b, j.n_cycles)
+        alone = R.rteaal_read_state(ctx, b)
+        R.rteaal_free_batch(ctx, b)
+        R.rteaal_unload_design(ctx, did)
+        same = same and bool(_np.array_equal(alone, j.regs))
+    R.rteaal_destroy(ctx)
+    return {
+        "metric": METRIC, "value": round(stats["instance_cycles_per_s"], 2),
+        "unit": "instance-cycles/s", "n_gpus": 1, "steps": stats["jobs"], "warmup": 0,
+        "ms_per_step": round(1e3 * stats["wall_s"] / max(stats["jobs"], 1), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "serving", "designs": len(pool), "jobs_offered": n_jobs,
+                   "arrival_rate_per_s": args.serving_rate, "admission_seconds": args.serving_seconds,
+                   "budget_gb": args.serving_budget_gb},
+        "serving": stats, "alone_equals_mix": same, "verified_jobs": len(check),
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="single-200k", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="single-200k",
+                    choices=sorted(WORKLOADS) + ["multi-64", "serving"])
+    ap.add_argument("--designs", type=int, default=None)
+    ap.add_argument("--serving-jobs", type=int, default=200)
+    ap.add_argument("--serving-rate", type=float, default=4.0, help="job arrivals per second")
+    ap.add_argument("--serving-seconds", type=float, default=40.0, help="admission window")
+    ap.add_argument("--serving-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serving-ops-hi", type=int, default=1_000_000)
+    ap.add_argument("--serving-inst-hi", type=int, default=512)
+    ap.add_argument("--serving-cycles-hi", type=int, default=50_000)
+    ap.add_argument("--serving-verify", type=int, default=8)
     ap.add_argument("--cycles-per-step", type=int, default=None)
     ap.add_argument("--instances", type=int, default=None)
     ap.add_argument("--mapping", default="auto", choices=["auto", "resident", "sweep"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--ops-per-wave", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)
+    ap.add_argument("--tiles-per-wave", type=int, default=0)
     ap.add_argument("--plain-cycles", type=int, default=None)
     ap.add_argument("--profile-cycles", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -132,6 +252,15 @@ def main():
     import torch
     from paper_2601_18140_amd import rteaal as R
 
+    if args.workload == "multi-64":
+        args.designs = args.designs or 64
+        print(json.dumps(bench_multi(args, R, torch)), flush=True)
+        return
+    if args.workload == "serving":
+        args.designs = args.designs or 32
+        print(json.dumps(bench_serving(args, R, torch)), flush=True)
+        return
+
     wl = WORKLOADS[args.workload]
     n_inst = args.instances or wl["instances"]
     cps = args.cycles_per_step or wl["cycles_per_step"]
@@ -153,7 +282,8 @@ def main():
     ok = parity_sample(R, ctx, did, d, seeds, mapping)
     print(f"[bench] parity sample vs oracle: {ok}", file=sys.stderr, flush=True)
 
-    manual = args.mapping != "auto" or args.block or args.ops_per_wave or args.unroll
+    manual = (args.mapping != "auto" or args.block or args.ops_per_wave or args.unroll
+              or args.tiles_per_wave)
     tuned = None
     if not manual and not args.no_autotune:
         t0 = time.perf_counter()
@@ -161,7 +291,8 @@ def main():
         print(f"[bench] autotune batched ({time.perf_counter() - t0:.1f}s): {tuned} "
               f"-> {trate:.4g} instance-cycles/s", file=sys.stderr, flush=True)
     bid = R.rteaal_create_batch(ctx, did, seeds, mapping=mapping, block_threads=args.block,
-                                ops_per_wave=args.ops_per_wave, unroll=args.unroll)
+                                ops_per_wave=args.ops_per_wave, unroll=args.unroll,
+                                tiles_per_wave=args.tiles_per_wave)
     used_map, _ = R.rteaal_batch_info(ctx, bid)
     for _ in range(args.warmup):
         R.rteaal_step(ctx, bid, cps)

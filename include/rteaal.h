@@ -175,7 +175,10 @@ typedef struct {
   uint32_t lds_state;      /* RESIDENT: 0 = LDS when it fits, 1 = keep in HBM   */
   uint32_t lds_ops;        /* RESIDENT: 0 = records in LDS when they fit, 1 = no */
   uint32_t unroll;         /* 0 = default; operations in flight per lane or
-                              wavefront: SWEEP 1, 2, 4, 8; RESIDENT 1, 2, 4      */
+                              wavefront: 1, 2 or 4                              */
+  uint32_t tiles_per_wave; /* 0 = default; SWEEP: 64-instance tiles one
+                              wavefront evaluates per decoded operation: 1, 2
+                              or 4, with unroll x tiles_per_wave <= 4          */
 } rteaal_batch_opts;
 
 /* Device bytes a batch of n_instances of `design` would allocate under

@@ -322,13 +322,14 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
     e.aux1 = aux1;
     e.width = width[dst];
     e.dcls = cls_of(dst);
-    bool all_b = e.dcls == CB, any_wide = e.dcls >= CL2;
+    bool all_b = e.dcls == CB, any_wide = e.dcls >= CL2, all_32 = e.dcls <= CW;
     for (uint32_t o = 0; o < arity; ++o) {
       all_b = all_b && cls_of(src[o]) == CB;
       any_wide = any_wide || cls_of(src[o]) >= CL2;
+      all_32 = all_32 && cls_of(src[o]) <= CW;
     }
-    if (opc >= OP_STIM) all_b = false;
-    e.kind = any_wide ? K_WIDE : all_b ? K_BIT : K_U64;
+    if (opc >= OP_STIM) all_b = all_32 = false;
+    e.kind = any_wide ? K_WIDE : all_b ? K_BIT : all_32 ? K_U32 : K_U64;
     return e;
   };
 
@@ -470,7 +471,7 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
 // Batches.
 // ---------------------------------------------------------------------------
 struct Batch {
-  uint32_t id = 0, design = 0, n_inst = 0, mapping = 0, block = 0, opw = 0, unroll = 0;
+  uint32_t id = 0, design = 0, n_inst = 0, mapping = 0, block = 0, opw = 0, unroll = 0, tg = 1;
   bool lds = false, lds_ops = false;
   uint64_t cycle = 0;
   StateLayout L{};
@@ -516,13 +517,18 @@ hipError_t timed(Batch& b, hipStream_t s, F&& launch) {
 
 StateLayout make_layout(const DesignHost& h, uint32_t mapping, uint32_t n_inst, uint64_t* bytes) {
   StateLayout L{};
-  const uint64_t bwords = (h.n_idx[CB] + 63) / 64;
+  // At least one 1-bit row / word: absent operands read 1-bit position 0.
+  const uint64_t n_b = std::max<uint64_t>(h.n_idx[CB], 64);
+  const uint64_t bwords = (n_b + 63) / 64;
   if (mapping == RTEAAL_MAP_SWEEP) {
     auto align = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
     L.n_tiles = (n_inst + 63) / 64;
     L.n_pad = L.n_tiles * 64;
+    uint32_t p2 = 1, lg = 0;
+    while (p2 < L.n_tiles) { p2 <<= 1; ++lg; }
+    L.b_shift = 3 + lg;
     L.b_off = 0;
-    L.nb_off = align((uint64_t)h.n_idx[CB] * L.n_tiles * 8);
+    L.nb_off = align(n_b * p2 * 8);
     L.tile_bytes = h.wide_bytes * 64;
     L.zero_off = L.nb_off + L.tile_bytes * L.n_tiles;
     L.pitch = 0;
@@ -618,7 +624,8 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
         if (!nops) continue;
         HIP_TRY(ctx, timed(b, ctx->stream, [&] {
                   return launch_sweep_layer(p, b.L, (char*)b.state.p, (const uint64_t*)b.seeds.p,
-                                            ctl, b.n_inst, li, nops, b.opw, b.unroll, ctx->stream);
+                                            ctl, b.n_inst, li, nops, b.opw, b.unroll, b.tg,
+                                            ctx->stream);
                 }));
       }
       HIP_TRY(ctx, launch_advance(ctl, 1, ctx->stream));
@@ -631,7 +638,7 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
     hipError_t e = hipSuccess;
     for (uint32_t li = 0; li < h.layers.size() && e == hipSuccess; ++li)
       e = launch_sweep_layer(p, b.L, (char*)b.state.p, (const uint64_t*)b.seeds.p, ctl, b.n_inst,
-                             li, h.layers[li].end - h.layers[li].begin, b.opw, b.unroll,
+                             li, h.layers[li].end - h.layers[li].begin, b.opw, b.unroll, b.tg,
                              ctx->stream);
     if (e == hipSuccess) e = launch_advance(ctl, 1, ctx->stream);
     hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
@@ -844,10 +851,16 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
     b->unroll = u;
   } else {
     b->opw = opts && opts->ops_per_wave ? opts->ops_per_wave : 16;
-    const uint32_t u = opts && opts->unroll ? opts->unroll : 4u;
-    if (u != 1 && u != 2 && u != 4 && u != 8)
-      return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP unroll must be 1, 2, 4 or 8");
+    const uint32_t u = opts && opts->unroll ? opts->unroll : 2u;
+    if (u != 1 && u != 2 && u != 4)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP unroll must be 1, 2 or 4");
     b->unroll = u;
+    const uint32_t tg = opts && opts->tiles_per_wave ? opts->tiles_per_wave : 1u;
+    if (tg != 1 && tg != 2 && tg != 4)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP tiles_per_wave must be 1, 2 or 4");
+    if (tg * u > 4)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP unroll x tiles_per_wave must be at most 4");
+    b->tg = tg;
   }
   const uint64_t n_seed = b->mapping == RTEAAL_MAP_SWEEP ? b->L.n_pad : n_inst;
   if (!alloc_all(ctx, {{&b->state, sb}, {&b->seeds, n_seed * 8}, {&b->ctl, sizeof(DevCtl)}}))
@@ -1135,10 +1148,16 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
   const uint32_t m64 = ((h->max_layer_ops + 63) / 64) * 64;
   for (uint32_t blk : {128u, 256u, 512u, 1024u}) {
     if (blk > 2 * std::max<uint32_t>(m64, 128u)) continue;
-    for (uint32_t u : {1u, 2u, 4u}) cand.push_back(rteaal_batch_opts{RTEAAL_MAP_RESIDENT, blk, 0, 0, 0, u});
+    for (uint32_t u : {1u, 2u, 4u})
+      cand.push_back(rteaal_batch_opts{RTEAAL_MAP_RESIDENT, blk, 0, 0, 0, u, 0});
   }
-  for (uint32_t opw : {2u, 4u, 8u, 16u, 32u})
-    for (uint32_t u : {1u, 2u, 4u}) cand.push_back(rteaal_batch_opts{RTEAAL_MAP_SWEEP, 0, opw, 0, 0, u});
+  const uint32_t n_tiles = (n_inst + 63) / 64;
+  for (uint32_t tg : {1u, 2u, 4u}) {
+    if (tg > 1 && tg > n_tiles) continue;
+    for (uint32_t opw : {2u, 4u, 8u, 16u, 32u})
+      for (uint32_t u : {1u, 2u, 4u})
+        if (u * tg <= 4) cand.push_back(rteaal_batch_opts{RTEAAL_MAP_SWEEP, 0, opw, 0, 0, u, tg});
+  }
   std::vector<uint64_t> seeds(n_inst);
   for (uint32_t i = 0; i < n_inst; ++i) seeds[i] = i;
   hipEvent_t e0 = nullptr, e1 = nullptr;

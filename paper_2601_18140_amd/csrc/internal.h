@@ -28,8 +28,9 @@ enum Opc : uint32_t {
 };
 
 // Evaluation kind: every class is CB (1-bit logic on whole words of
-// bit-sliced instances), every class fits 64 bits, or some class is wider.
-enum Kind : uint32_t { K_BIT = 0, K_U64 = 1, K_WIDE = 2 };
+// bit-sliced instances), every class fits 32 bits, every class fits 64 bits,
+// or some class is wider.
+enum Kind : uint32_t { K_BIT = 0, K_U64 = 1, K_WIDE = 2, K_U32 = 3 };
 
 // One operation, 32 bytes.
 //   code: opc[0:5] kind[6:7] arity[8:9] dst class[10:12] src classes [13:15][16:18][19:21]
@@ -75,8 +76,9 @@ struct DevCtl {
 //     1-bit slot i: bit i of the 64-bit words at b_off;
 //     other slot:   its bytes at nb_off + Y (limb l at + 8l).
 //   SWEEP, tile t = j / 64, lane = j % 64:
-//     1-bit slot i: bit `lane` of the word at b_off + (i*n_tiles + t)*8
-//       (the words of one slot are adjacent across tiles);
+//     1-bit slot i: bit `lane` of the word at b_off + ((i << b_shift) + t*8),
+//       b_shift = 3 + log2(tile count rounded up to a power of two) (the words
+//       of one slot are adjacent across tiles);
 //     other slot:   tile t's block starts at nb_off + t*tile_bytes; the 4- or
 //       8-byte element at resident offset Y (limb l: Y + 8l) becomes a row of
 //       64 lanes at (Y + 8l)*64, lane at +4*lane (CW) or +8*lane (others).
@@ -84,7 +86,7 @@ struct DevCtl {
 //   read in place of an absent operand or high half.
 struct StateLayout {
   uint64_t b_off, nb_off, zero_off, pitch, tile_bytes;
-  uint32_t n_tiles, n_pad;
+  uint32_t n_tiles, n_pad, b_shift, pad;
 };
 
 struct Program {
@@ -126,7 +128,7 @@ size_t resident_lds_bytes(const StateLayout& L, uint32_t n_ops_total, uint32_t n
 hipError_t launch_sweep_layer(const Program& p, const StateLayout& L, char* state,
                               const uint64_t* seeds, DevCtl* ctl, uint32_t n_inst,
                               uint32_t layer, uint32_t layer_ops, uint32_t ops_per_wave,
-                              uint32_t unroll, hipStream_t s);
+                              uint32_t unroll, uint32_t tiles_per_wave, hipStream_t s);
 hipError_t launch_advance(DevCtl* ctl, uint64_t n, hipStream_t s);
 hipError_t launch_set_words(DevCtl* ctl, const uint64_t* words, hipStream_t s);
 hipError_t launch_pack(bool sweep, const StateLayout& L, const char* state, const SlotRef* refs,

@@ -51,19 +51,18 @@ __device__ __forceinline__ V4 source_value(const uint64_t* const_limbs, const De
 // RESIDENT: per-instance state block at `s` (LDS or global).
 // ---------------------------------------------------------------------------
 
-// Operand fetch without branches: two 32-bit loads at addresses chosen by
-// selects (the second reads the zero page for 1-bit and 32-bit classes, and
-// both do for an absent operand), so every load of a group of operations is
-// issued before the first wait.  A 1-bit value comes from the dword that
-// holds its bit.
+// Operand fetch without branches: one aligned 8-byte load per operand.  A
+// 1-bit value comes from the word holding its bit, a 32-bit value from the
+// aligned word holding it (then shifted down), so the address depends only on
+// the class and the position.  Absent operands (arity < 3) carry position 0
+// of class CB and read a valid word that is never used.
 __device__ __forceinline__ uint64_t res_fetch(const char* s, const StateLayout& L, uint32_t cls,
-                                              uint32_t pos, bool on) {
-  const char* z = s + L.zero_off;
-  const char* lo = cls == CB ? s + L.b_off + (uint64_t)(pos >> 5) * 4u : s + L.nb_off + pos;
-  const char* hi = cls == CD ? lo + 4 : z;
-  if (!on) lo = hi = z;
-  const uint32_t l = *(const uint32_t*)lo, h = *(const uint32_t*)hi;
-  return cls == CB ? (uint64_t)((l >> (pos & 31u)) & 1u) : ((uint64_t)h << 32) | l;
+                                              uint32_t pos) {
+  const char* a = cls == CB ? s + L.b_off + (uint64_t)(pos >> 6) * 8u
+                            : s + L.nb_off + (pos & ~7u);
+  const uint64_t v = *(const uint64_t*)a;
+  return cls == CB ? (v >> (pos & 63u)) & 1ull
+       : cls == CW ? (v >> ((pos & 4u) * 8u)) & 0xffffffffull : v;
 }
 
 __device__ __forceinline__ V4 res_ldv(const char* s, const StateLayout& L, uint32_t cls,
@@ -155,10 +154,11 @@ __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uin
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const uint32_t q = q0 + u * bd, code = op[u].code, ar = op_arity(code);
-          const bool fast = q < n && op_kind(code) != K_WIDE && op_opc(code) < OP_STIM;
-          va[u] = res_fetch(s, L, op_scls(code, 0), op[u].src[0], fast);
-          vb[u] = res_fetch(s, L, op_scls(code, 1), op[u].src[1], fast && ar > 1);
-          vc[u] = res_fetch(s, L, op_scls(code, 2), op[u].src[2], fast && ar > 2);
+          (void)q;
+          (void)ar;
+          va[u] = res_fetch(s, L, op_scls(code, 0), op[u].src[0]);
+          vb[u] = res_fetch(s, L, op_scls(code, 1), op[u].src[1]);
+          vc[u] = res_fetch(s, L, op_scls(code, 2), op[u].src[2]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -177,6 +177,15 @@ __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uin
                   bit = x.l[0] & 1ull;
                 } else {
                   res_stv(s, L, dc, o.dst, x);
+                }
+              } else if (op_kind(code) == K_U32 || op_kind(code) == K_BIT) {
+                const uint32_t r = eval_u32(opc, ar, (uint32_t)va[u], (uint32_t)vb[u],
+                                            (uint32_t)vc[u], imm, w);
+                if (dc == CB) {
+                  bdst = true;
+                  bit = r & 1u;
+                } else {
+                  res_st64(s, L, dc, o.dst, r);
                 }
               } else if (op_kind(code) != K_WIDE) {
                 const uint64_t r = eval_u64(opc, ar, va[u], vb[u], vc[u], imm, w);
@@ -239,39 +248,47 @@ k_resident_multi(const ResJob* __restrict__ jobs, const uint2* __restrict__ map)
 // once, so an operand address is a select between two bases plus one add.
 // ---------------------------------------------------------------------------
 struct SweepView {
-  char* bB;          // 1-bit words of this tile: bit index i at bB + i*bstride
+  char* bB;          // 1-bit words of this tile: bit index i at bB + (i << bshift)
   char* bT;          // this tile's block: resident offset Y at bT + Y*64
-  char* zero;        // zero page
-  uint64_t bstride;  // 8 * n_tiles
+  uint32_t bshift;   // 3 + log2(tile count rounded up to a power of two)
   uint32_t lane;
 
   __device__ __forceinline__ SweepView(char* st, const StateLayout& L, uint32_t tile, uint32_t ln)
       : bB(st + L.b_off + 8ull * tile), bT(st + L.nb_off + L.tile_bytes * tile),
-        zero(st + L.zero_off), bstride(8ull * L.n_tiles), lane(ln) {}
+        bshift(L.b_shift), lane(ln) {}
 
   __device__ __forceinline__ uint64_t ld_word(uint32_t i) const {
-    return *(const uint64_t*)(bB + i * bstride);
+    return *(const uint64_t*)(bB + ((uint64_t)i << bshift));
   }
   __device__ __forceinline__ void st_word(uint32_t i, uint64_t w) const {
-    *(uint64_t*)(bB + i * bstride) = w;
+    *(uint64_t*)(bB + ((uint64_t)i << bshift)) = w;
   }
   __device__ __forceinline__ char* elem(uint32_t cls, uint32_t pos) const {
     return bT + (uint64_t)pos * 64u + lane * (cls == CW ? 4u : 8u);
   }
-  // Element as stored (the whole bit-sliced word for CB, else this lane's
-  // value), as two 32-bit loads at selected addresses; the high half of a
-  // 32-bit class and an absent operand read the zero page.
-  __device__ __forceinline__ uint64_t fetch(uint32_t cls, uint32_t pos, bool on) const {
+  // Element as stored, as one 8-byte load: the bit-sliced word for CB (one
+  // address for the whole wavefront), this lane's value for CD, and for CW
+  // the aligned 8-byte word holding this lane's value (lanes 2k and 2k+1
+  // share it, so a row is read exactly once).  Absent operands carry
+  // position 0 of class CB and read a valid word that is never used.
+  __device__ __forceinline__ uint64_t fetch(uint32_t cls, uint32_t pos) const {
     const bool b = cls == CB;
-    const char* row = b ? bB + pos * bstride : bT + (uint64_t)pos * 64u;
-    const uint32_t lo_lane = b ? 0u : lane * (cls == CW ? 4u : 8u);
-    const char* lo = on ? row + lo_lane : zero;
-    const char* hi = (on && cls != CW) ? row + lo_lane + 4 : zero;
-    const uint32_t l = *(const uint32_t*)lo, h = *(const uint32_t*)hi;
-    return ((uint64_t)h << 32) | l;
+    const char* row = (b ? bB : bT) + ((uint64_t)pos << (b ? bshift : 6u));
+    const uint32_t off = b ? 0u : cls == CW ? (lane & ~1u) * 4u : lane * 8u;
+    return *(const uint64_t*)(row + off);
   }
+  // As lane_val for classes of at most 32 bits.
+  __device__ __forceinline__ uint32_t lane_val32(uint32_t cls, uint64_t raw) const {
+    const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
+    return cls == CB ? (uint32_t)((raw >> lane) & 1ull) : (lane & 1u) ? hi : lo;
+  }
+  __device__ __forceinline__ void st32(uint32_t pos, uint32_t v) const {
+    *(uint32_t*)(bT + (uint64_t)pos * 64u + lane * 4u) = v;
+  }
+  // The operand's value in this lane from what fetch() returned.
   __device__ __forceinline__ uint64_t lane_val(uint32_t cls, uint64_t raw) const {
-    return cls == CB ? (raw >> lane) & 1ull : raw;
+    return cls == CB ? (raw >> lane) & 1ull
+         : cls == CW ? (raw >> ((lane & 1u) * 32u)) & 0xffffffffull : raw;
   }
   __device__ __forceinline__ V4 ldv(uint32_t cls, uint32_t pos) const {
     if (cls == CB) return v4_from((ld_word(pos) >> lane) & 1ull);
@@ -303,10 +320,12 @@ struct SweepView {
   }
 };
 
-// Operations of one wavefront are processed U at a time: first the U records
-// (scalar loads), then every operand row of the fast operations, then the
-// evaluations and stores, so U gathers are in flight per wavefront.
-template <int U>
+// A wavefront handles a chunk of operations for TG tiles (64 instances
+// each).  Operations are processed U at a time: first the U records (scalar
+// loads, decoded once for all TG tiles), then every operand row for every
+// tile, then the evaluations and stores, so 3*U*TG gathers are in flight
+// per wavefront and the type dispatch is paid once per operation.
+template <int U, int TG>
 __global__ void __launch_bounds__(256)
 k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
         const uint64_t* __restrict__ const_limbs, uint32_t words_per_inst, StateLayout L,
@@ -315,27 +334,33 @@ k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  const uint32_t tile = wave % L.n_tiles, chunk = wave / L.n_tiles;
+  const uint32_t n_groups = (L.n_tiles + TG - 1) / TG;
+  const uint32_t grp = wave % n_groups, chunk = wave / n_groups;
   const DevLayer ly = layers[layer];
   const uint32_t o0 = ly.begin + chunk * opw;
   if (o0 >= ly.end) return;
   const uint32_t o1 = min(o0 + opw, ly.end);
-  const SweepView v(state, L, tile, lane);
-  const uint32_t inst = tile * 64u + lane;
-  const bool live = inst < n_inst;
+  // Tiles of this wavefront; a short last group repeats its last tile, which
+  // recomputes and rewrites identical values.
+  uint32_t tile[TG];
+#pragma unroll
+  for (int g = 0; g < TG; ++g) tile[g] = min(grp * TG + g, L.n_tiles - 1u);
 
   for (uint32_t o = o0; o < o1; o += U) {
     DevOp op[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) op[u] = ops[min(o + (uint32_t)u, o1 - 1u)];
-    uint64_t ra[U], rb[U], rc[U];
+    uint64_t ra[U][TG], rb[U][TG], rc[U][TG];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t code = op[u].code, ar = op_arity(code);
-      const bool fast = o + u < o1 && op_kind(code) != K_WIDE && op_opc(code) < OP_STIM;
-      ra[u] = v.fetch(op_scls(code, 0), op[u].src[0], fast);
-      rb[u] = v.fetch(op_scls(code, 1), op[u].src[1], fast && ar > 1);
-      rc[u] = v.fetch(op_scls(code, 2), op[u].src[2], fast && ar > 2);
+      const uint32_t code = op[u].code;
+#pragma unroll
+      for (int g = 0; g < TG; ++g) {
+        const SweepView v(state, L, tile[g], lane);
+        ra[u][g] = v.fetch(op_scls(code, 0), op[u].src[0]);
+        rb[u][g] = v.fetch(op_scls(code, 1), op[u].src[1]);
+        rc[u][g] = v.fetch(op_scls(code, 2), op[u].src[2]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -344,42 +369,74 @@ k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
         const uint32_t code = q.code, opc = op_opc(code), ar = op_arity(code), kind = op_kind(code);
         const uint32_t dc = op_dcls(code), w = op_width(q.wimm), imm = op_imm(q.wimm);
         const uint32_t c0 = op_scls(code, 0), c1 = op_scls(code, 1), c2 = op_scls(code, 2);
-        if (opc >= OP_STIM) {
-          const uint64_t cycle = ctl->cycle;
-          const uint64_t words_row =
-              ((cycle - ctl->step_cycle0) * (uint64_t)n_inst + inst) * (uint64_t)words_per_inst;
-          V4 x = v4_from(0);
-          if (live) x = source_value(const_limbs, q, seeds[inst], cycle, ctl->words, words_row, w);
-          if (dc == CB) {
-            const uint64_t m = __ballot((x.l[0] & 1ull) != 0ull);
-            if (lane == 0) v.st_word(q.dst, m);
-          } else {
-            v.stv(dc, q.dst, x);
+        if (kind == K_U32) {
+          uint32_t a[TG], b[TG], c[TG], r[TG];
+#pragma unroll
+          for (int g = 0; g < TG; ++g) {
+            const SweepView v(state, L, tile[g], lane);
+            a[g] = v.lane_val32(c0, ra[u][g]);
+            b[g] = v.lane_val32(c1, rb[u][g]);
+            c[g] = v.lane_val32(c2, rc[u][g]);
+          }
+          eval_u32_n<TG>(opc, ar, a, b, c, imm, w, r);
+#pragma unroll
+          for (int g = 0; g < TG; ++g) {
+            const SweepView v(state, L, tile[g], lane);
+            if (dc == CB) {
+              const uint64_t m = __ballot((r[g] & 1u) != 0u);
+              if (lane == 0) v.st_word(q.dst, m);
+            } else {
+              v.st32(q.dst, r[g]);
+            }
           }
         } else if (kind == K_BIT) {
-          const uint64_t r = eval_bits(opc, ar, ra[u], rb[u], rc[u], imm);
-          if (lane == 0) v.st_word(q.dst, r);
-        } else if (kind == K_U64) {
-          const uint64_t a = v.lane_val(c0, ra[u]);
-          const uint64_t b = v.lane_val(c1, rb[u]);
-          const uint64_t c = v.lane_val(c2, rc[u]);
-          const uint64_t r = eval_u64(opc, ar, a, b, c, imm, w);
-          if (dc == CB) {
-            const uint64_t m = __ballot((r & 1ull) != 0ull);
-            if (lane == 0) v.st_word(q.dst, m);
-          } else {
-            v.st64(dc, q.dst, r);
+#pragma unroll
+          for (int g = 0; g < TG; ++g) {
+            const SweepView v(state, L, tile[g], lane);
+            const uint64_t r = eval_bits(opc, ar, ra[u][g], rb[u][g], rc[u][g], imm);
+            if (lane == 0) v.st_word(q.dst, r);
           }
         } else {
-          const V4 a = v.ldv(c0, q.src[0]);
-          const V4 b = ar > 1 ? v.ldv(c1, q.src[1]) : v4_from(0);
-          const V4 c = ar > 2 ? v.ldv(c2, q.src[2]) : v4_from(0);
-          const V4 r = eval_wide(opc, ar, a, b, c, imm, w);
-          if (dc == CB) {
-            const uint64_t m = __ballot((r.l[0] & 1ull) != 0ull);
-            if (lane == 0) v.st_word(q.dst, m);
-          } else {
-            v.stv(dc, q.dst, r);
+#pragma unroll
+          for (int g = 0; g < TG; ++g) {
+            const SweepView v(state, L, tile[g], lane);
+            const uint32_t inst = tile[g] * 64u + lane;
+            if (opc >= OP_STIM) {
+              const uint64_t cycle = ctl->cycle;
+              const uint64_t words_row = ((cycle - ctl->step_cycle0) * (uint64_t)n_inst + inst) *
+                                         (uint64_t)words_per_inst;
+              V4 x = v4_from(0);
+              if (inst < n_inst)
+                x = source_value(const_limbs, q, seeds[inst], cycle, ctl->words, words_row, w);
+              if (dc == CB) {
+                const uint64_t m = __ballot((x.l[0] & 1ull) != 0ull);
+                if (lane == 0) v.st_word(q.dst, m);
+              } else {
+                v.stv(dc, q.dst, x);
+              }
+            } else if (kind == K_U64) {
+              const uint64_t a = v.lane_val(c0, ra[u][g]);
+              const uint64_t b = v.lane_val(c1, rb[u][g]);
+              const uint64_t c = v.lane_val(c2, rc[u][g]);
+              const uint64_t r = eval_u64(opc, ar, a, b, c, imm, w);
+              if (dc == CB) {
+                const uint64_t m = __ballot((r & 1ull) != 0ull);
+                if (lane == 0) v.st_word(q.dst, m);
+              } else {
+                v.st64(dc, q.dst, r);
+              }
+            } else {
+              const V4 a = v.ldv(c0, q.src[0]);
+              const V4 b = ar > 1 ? v.ldv(c1, q.src[1]) : v4_from(0);
+              const V4 c = ar > 2 ? v.ldv(c2, q.src[2]) : v4_from(0);
+              const V4 r = eval_wide(opc, ar, a, b, c, imm, w);
+              if (dc == CB) {
+                const uint64_t m = __ballot((r.l[0] & 1ull) != 0ull);
+                if (lane == 0) v.st_word(q.dst, m);
+              } else {
+                v.stv(dc, q.dst, r);
+              }
+            }
           }
         }
       }
@@ -410,7 +467,7 @@ __device__ __forceinline__ char* elem_addr(bool sweep, const StateLayout& L, cha
     const uint64_t t = inst >> 6, ln = inst & 63u;
     if (cls == CB) {
       *bitpos = (uint32_t)ln;
-      return state + L.b_off + ((uint64_t)pos * L.n_tiles + t) * 8u;
+      return state + L.b_off + ((uint64_t)pos << L.b_shift) + t * 8u;
     }
     return state + L.nb_off + t * L.tile_bytes + ((uint64_t)pos + 8u * limb) * 64u +
            ln * (cls == CW ? 4u : 8u);
@@ -572,20 +629,25 @@ hipError_t launch_resident_multi(const ResJob* jobs, const uint2* map, uint32_t 
 hipError_t launch_sweep_layer(const Program& p, const StateLayout& L, char* state,
                               const uint64_t* seeds, DevCtl* ctl, uint32_t n_inst,
                               uint32_t layer, uint32_t layer_ops, uint32_t ops_per_wave,
-                              uint32_t unroll, hipStream_t s) {
+                              uint32_t unroll, uint32_t tiles_per_wave, hipStream_t s) {
   if (layer_ops == 0) return hipSuccess;
+  const uint32_t tg = tiles_per_wave == 4 ? 4u : tiles_per_wave == 2 ? 2u : 1u;
   const uint64_t chunks = (layer_ops + ops_per_wave - 1) / ops_per_wave;
-  const uint64_t waves = chunks * L.n_tiles;
+  const uint64_t waves = chunks * ((L.n_tiles + tg - 1) / tg);
   const dim3 grid((uint32_t)((waves + 3) / 4)), blk(256);
   const DevCtl* c = ctl;
-#define RTEAAL_SWEEP(UU)                                                                       \
-  hipLaunchKernelGGL(k_sweep<UU>, grid, blk, 0, s, p.ops, p.layers, p.const_limbs,            \
+#define RTEAAL_SWEEP(UU, GG)                                                                   \
+  hipLaunchKernelGGL((k_sweep<UU, GG>), grid, blk, 0, s, p.ops, p.layers, p.const_limbs,      \
                      p.words_per_inst, L, state, seeds, c, n_inst, layer, ops_per_wave)
-  switch (unroll) {
-    case 1: RTEAAL_SWEEP(1); break;
-    case 2: RTEAAL_SWEEP(2); break;
-    case 8: RTEAAL_SWEEP(8); break;
-    default: RTEAAL_SWEEP(4); break;
+  // unroll x tiles_per_wave is at most 4: larger products run out of
+  // registers and spill to scratch.
+  switch (tg * 8 + unroll) {
+    case 8 + 1: RTEAAL_SWEEP(1, 1); break;
+    case 8 + 4: RTEAAL_SWEEP(4, 1); break;
+    case 16 + 1: RTEAAL_SWEEP(1, 2); break;
+    case 16 + 2: RTEAAL_SWEEP(2, 2); break;
+    case 32 + 1: RTEAAL_SWEEP(1, 4); break;
+    default: RTEAAL_SWEEP(2, 1); break;
   }
 #undef RTEAAL_SWEEP
   return hipGetLastError();

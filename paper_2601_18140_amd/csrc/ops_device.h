@@ -39,6 +39,107 @@ __device__ __forceinline__ uint64_t eval_u64(uint32_t opc, uint32_t arity, uint6
   return r & mask64(w);
 }
 
+// Every operand and the result fit 32 bits (so 32-bit arithmetic modulo 2^32,
+// then the mask, equals the unbounded result modulo 2^w).
+__device__ __forceinline__ uint32_t eval_u32(uint32_t opc, uint32_t arity, uint32_t a, uint32_t b,
+                                             uint32_t c, uint32_t imm, uint32_t w) {
+  uint32_t r;
+  switch (opc) {
+    case OP_AND: r = a & b & (arity == 3 ? c : ~0u); break;
+    case OP_OR: r = a | b | (arity == 3 ? c : 0u); break;
+    case OP_XOR: r = a ^ b ^ (arity == 3 ? c : 0u); break;
+    case OP_NOT: r = ~a; break;
+    case OP_ADD: r = a + b; break;
+    case OP_SUB: r = a - b; break;
+    case OP_MUL: r = a * b; break;
+    case OP_MUX: r = a ? b : c; break;
+    case OP_EQ: r = a == b; break;
+    case OP_LT: r = a < b; break;
+    case OP_SHL: r = imm >= 32 ? 0u : a << imm; break;
+    case OP_SHR:
+    case OP_EXTRACT: r = imm >= 32 ? 0u : a >> imm; break;
+    case OP_CONCAT: r = (imm >= 32 ? 0u : a << imm) | b; break;
+    case OP_ORR: r = a != 0; break;
+    default: r = a; break;  // COPY
+  }
+  return r & (w >= 32 ? ~0u : ((1u << w) - 1u));
+}
+
+// The same operator applied to N independent value sets (one per tile of a
+// wavefront), with the type dispatch done once.
+template <int N>
+__device__ __forceinline__ void eval_u32_n(uint32_t opc, uint32_t arity, const uint32_t* a,
+                                           const uint32_t* b, const uint32_t* c, uint32_t imm,
+                                           uint32_t w, uint32_t* r) {
+  const bool a3 = arity == 3;
+  switch (opc) {
+    case OP_AND:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = a[g] & b[g] & (a3 ? c[g] : ~0u);
+      break;
+    case OP_OR:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = a[g] | b[g] | (a3 ? c[g] : 0u);
+      break;
+    case OP_XOR:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = a[g] ^ b[g] ^ (a3 ? c[g] : 0u);
+      break;
+    case OP_NOT:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = ~a[g];
+      break;
+    case OP_ADD:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = a[g] + b[g];
+      break;
+    case OP_SUB:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = a[g] - b[g];
+      break;
+    case OP_MUL:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = a[g] * b[g];
+      break;
+    case OP_MUX:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = a[g] ? b[g] : c[g];
+      break;
+    case OP_EQ:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = a[g] == b[g];
+      break;
+    case OP_LT:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = a[g] < b[g];
+      break;
+    case OP_SHL:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = imm >= 32 ? 0u : a[g] << imm;
+      break;
+    case OP_SHR:
+    case OP_EXTRACT:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = imm >= 32 ? 0u : a[g] >> imm;
+      break;
+    case OP_CONCAT:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = (imm >= 32 ? 0u : a[g] << imm) | b[g];
+      break;
+    case OP_ORR:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = a[g] != 0;
+      break;
+    default:
+#pragma unroll
+      for (int g = 0; g < N; ++g) r[g] = a[g];
+      break;
+  }
+  const uint32_t m = w >= 32 ? ~0u : ((1u << w) - 1u);
+#pragma unroll
+  for (int g = 0; g < N; ++g) r[g] &= m;
+}
+
 // 1-bit destination, 1-bit operands, 64 instances per word.  Each identity
 // is the 1-bit case of the integer definition: a+b and a-b are a^b modulo 2,
 // a*b is a&b, [a==b] is ~(a^b), [a<b] is ~a&b, a shift by k>0 leaves bit 0

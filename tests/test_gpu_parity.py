@@ -119,6 +119,36 @@ def test_resident_hbm_state_and_block_sizes(ctx, mapping):
             assert_same(regs, ref, f"ops_per_wave={opw}")
 
 
+SWEEP_SHAPES = [(1, 1), (2, 1), (4, 1), (1, 2), (2, 2), (1, 4)]   # (unroll, tiles_per_wave)
+
+
+@pytest.mark.parametrize("cfg", SMALL[:2], ids=[c.name for c in SMALL[:2]])
+def test_sweep_tile_groups(ctx, cfg):
+    """Every (unroll, tiles per wavefront) variant, with tile counts that
+    leave a short last group (2, 3 and 5 tiles), on every slot."""
+    d = rtlgen.generate(cfg, 19)
+    for n_inst in (100, 130, 300):
+        seeds = np.arange(n_inst, dtype=np.uint64) * 104729 + 11
+        ref_r, ref_s, _ = oracle.run(d, seeds, 9, want_slots=True)
+        for u, tg in SWEEP_SHAPES:
+            note(f"tile groups {cfg.name} n={n_inst} unroll={u} tiles_per_wave={tg}")
+            regs, slots, _ = run_gpu(ctx, d, seeds, [4, 5], mapping=R.RTEAAL_MAP_SWEEP,
+                                     slots=True, unroll=u, tiles_per_wave=tg, ops_per_wave=7)
+            assert_same(regs, ref_r, f"registers u={u} tg={tg}")
+            assert_same(slots, ref_s, f"slots u={u} tg={tg}")
+
+
+def test_sweep_rejects_oversized_shape(ctx):
+    d = rtlgen.generate(SMALL[2], 1)
+    did = R.rteaal_load_design(ctx, d)
+    try:
+        with pytest.raises(R.RteaalError):
+            R.rteaal_create_batch(ctx, did, np.arange(70, dtype=np.uint64),
+                                  mapping=R.RTEAAL_MAP_SWEEP, unroll=4, tiles_per_wave=2)
+    finally:
+        R.rteaal_unload_design(ctx, did)
+
+
 def test_plain_2k_full_run(ctx):
     """The small workload: 2,000 ops, 16 layers, one instance, 10,000 cycles."""
     w = rtlgen.WORKLOADS["plain-2k"]

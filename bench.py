@@ -47,23 +47,49 @@ def wb(w):
 
 
 def algorithmic_bytes(d):
-    """Per instance-cycle state bytes X (operand gathers + result stores, register
-    commit, input writes) and per-cycle graph bytes G of the packed graph tensor."""
+    """Algorithmic bytes of one cycle, split by the kernel that moves them.
+
+    X: per instance-cycle state bytes (operand gathers + result stores,
+    register commit, input writes); G: per-cycle bytes of the packed graph
+    tensor (coordinates at the layer's bit width, a 9-bit type code, 8-bit
+    immediates).  "light" covers the operations whose values are all at most
+    64 bits wide (the common SWEEP kernel), "heavy" the wider ones and the
+    sources (the SWEEP kernel of heavy operations)."""
     W = d.slot_width.astype(np.int64)
-    x_ops = wb(W[d.op_src]).sum() + wb(W[d.op_dst]).sum()
-    x_regs = wb(W[d.reg_next]).sum() + wb(W[d.reg_slot]).sum()
-    x_in = wb(W[d.input_slot]).sum()
-    g_bits = 0
     ar = d.op_arity()
+    n = d.n_ops
+    src_b = wb(W[d.op_src])
+    src_w = W[d.op_src]
+    ptr = d.op_src_ptr.astype(np.int64)
+    op_x = wb(W[d.op_dst]).astype(np.float64)
+    op_wmax = W[d.op_dst].copy()
+    has = ar > 0
+    if src_b.size:
+        idx = ptr[:-1][has]
+        op_x[has] += np.add.reduceat(src_b, idx)
+        op_wmax[has] = np.maximum(op_wmax[has], np.maximum.reduceat(src_w, idx))
+    op_heavy = op_wmax > 64
+    op_g = np.zeros(n, dtype=np.float64)
     for i in range(d.n_layers):
         a, b = int(d.layer_ptr[i]), int(d.layer_ptr[i + 1])
         if a == b:
             continue
         sl = slice(int(d.op_src_ptr[a]), int(d.op_src_ptr[b]))
         cb = max(int(d.op_dst[a:b].max()), int(d.op_src[sl].max())).bit_length()
-        imm = np.count_nonzero(np.isin(d.op_type[a:b], (rtlgen.SHL, rtlgen.SHR, rtlgen.EXTRACT)))
-        g_bits += int((1 + ar[a:b]).sum()) * cb + 9 * (b - a) + 8 * imm
-    return float(x_ops + x_regs + x_in), g_bits / 8.0
+        imm = np.isin(d.op_type[a:b], (rtlgen.SHL, rtlgen.SHR, rtlgen.EXTRACT))
+        op_g[a:b] = ((1 + ar[a:b]) * cb + 9 + 8 * imm) / 8.0
+    reg_x = wb(W[d.reg_next]) + wb(W[d.reg_slot])
+    reg_heavy = W[d.reg_slot] > 64
+    x_in = float(wb(W[d.input_slot]).sum())
+    out = {
+        "x_light": float(op_x[~op_heavy].sum() + reg_x[~reg_heavy].sum()),
+        "x_heavy": float(op_x[op_heavy].sum() + reg_x[reg_heavy].sum() + x_in),
+        "g_light": float(op_g[~op_heavy].sum()),
+        "g_heavy": float(op_g[op_heavy].sum()),
+    }
+    out["x"] = out["x_light"] + out["x_heavy"]
+    out["g"] = out["g_light"] + out["g_heavy"]
+    return out
 
 
 def cpu_baseline(d, seeds, cycles):
@@ -273,7 +299,8 @@ def main():
     seeds = rtlgen.instance_seeds(n_inst)
     print(f"[bench] design {d.summary()} generated in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
-    X, G = algorithmic_bytes(d)
+    AB = algorithmic_bytes(d)
+    X, G = AB["x"], AB["g"]
 
     ctx = R.rteaal_create(0)
     stream = ctx.stream
@@ -316,24 +343,37 @@ def main():
     prof_cycles = args.profile_cycles or (min(cps, 1024) if used_map == R.RTEAAL_MAP_RESIDENT else min(cps, 50))
     R.rteaal_kernel_timing(ctx, bid, True)
     R.rteaal_step(ctx, bid, prof_cycles)
-    launches, kms = R.rteaal_kernel_timing(ctx, bid, False)
+    (launches, kms), (h_launches, h_kms) = R.rteaal_kernel_timing(ctx, bid, False)
     avg_ms = kms / max(launches, 1)
-    state_bytes = X * n_inst * prof_cycles
     lds = used_map == R.RTEAAL_MAP_RESIDENT and R.rteaal_batch_footprint(
         ctx, did, n_inst, mapping=R.RTEAAL_MAP_RESIDENT) // max(n_inst, 1) <= 160 * 1024
-    if used_map == R.RTEAAL_MAP_SWEEP or not lds:
+    if used_map == R.RTEAAL_MAP_SWEEP:
+        # The common kernel moves the light operations' bytes; the heavy
+        # kernel's are reported beside it.
         bound, peak = "hbm", HBM_PEAK_GBS
-        per_launch = (state_bytes + G * prof_cycles) / max(launches, 1)
+        per_launch = (AB["x_light"] * n_inst + AB["g_light"]) * prof_cycles / max(launches, 1)
+    elif not lds:
+        bound, peak = "hbm", HBM_PEAK_GBS
+        per_launch = (X * n_inst + G) * prof_cycles / max(launches, 1)
     else:
         bound, peak = "lds", LDS_PEAK_GBS
-        per_launch = state_bytes / max(launches, 1)
+        per_launch = X * n_inst * prof_cycles / max(launches, 1)
     achieved = per_launch / (avg_ms / 1e3) / 1e9
     roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": round(peak, 1),
                 "unit": "GB/s", "frac": round(achieved / peak, 4), "traffic": None,
                 "kernel": "k_sweep" if used_map == R.RTEAAL_MAP_SWEEP else "k_resident",
                 "launches": launches, "avg_launch_ms": round(avg_ms, 5),
+                "bytes_per_launch": round(per_launch, 1),
                 "algorithmic_bytes_per_instance_cycle": round(X, 1),
                 "graph_bytes_per_cycle": round(G, 1)}
+    if h_launches:
+        h_avg = h_kms / h_launches
+        h_bytes = (AB["x_heavy"] * n_inst + AB["g_heavy"]) * prof_cycles / h_launches
+        roofline["heavy_kernel"] = {
+            "kernel": "k_sweep_heavy", "launches": h_launches, "avg_launch_ms": round(h_avg, 5),
+            "bytes_per_launch": round(h_bytes, 1),
+            "achieved": round(h_bytes / (h_avg / 1e3) / 1e9, 2),
+            "share_of_kernel_time": round(h_kms / (h_kms + kms), 4)}
     R.rteaal_free_batch(ctx, bid)
 
     plain = None

@@ -177,8 +177,8 @@ typedef struct {
   uint32_t unroll;         /* 0 = default; operations in flight per lane or
                               wavefront: 1, 2 or 4                              */
   uint32_t tiles_per_wave; /* 0 = default; SWEEP: 64-instance tiles one
-                              wavefront evaluates per decoded operation: 1, 2
-                              or 4, with unroll x tiles_per_wave <= 4          */
+                              wavefront evaluates per decoded operation: 1, 2,
+                              4 or 8, with unroll x tiles_per_wave <= 8        */
 } rteaal_batch_opts;
 
 /* Device bytes a batch of n_instances of `design` would allocate under
@@ -267,12 +267,16 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id design, uint32_t
 /* ------------------------------------------------------------------------ */
 
 /* Kernel timing of a batch.  While enabled, every launch of the simulation
- * kernel (one per layer for SWEEP, one per chunk of cycles for RESIDENT) is
- * bracketed by HIP events on the context's stream and issued directly rather
- * than through the captured graph.  Each call waits for the stream, returns
- * in *launches / *total_ms the launches and summed kernel time recorded since
- * the previous call (either pointer may be NULL), clears them, and then turns
- * recording on (enable != 0) or off. */
+ * kernels is bracketed by HIP events on the context's stream and issued
+ * directly rather than through the captured graph.  Two kernels are counted
+ * apart: [0] the main kernel (RESIDENT: one launch per chunk of cycles;
+ * SWEEP: the kernel of a layer's common operations, values of at most 64
+ * bits) and [1] the SWEEP kernel of a layer's heavy operations (wider values
+ * and sources; always 0 for RESIDENT).  Each call waits for the stream,
+ * writes launches[0..1] / total_ms[0..1] (host arrays of two; either pointer
+ * may be NULL) with the launches and summed kernel time recorded since the
+ * previous call, clears them, and then turns recording on (enable != 0) or
+ * off. */
 rteaal_status rteaal_kernel_timing(rteaal_ctx* ctx, rteaal_batch_id batch, int enable,
                                    uint64_t* launches, double* total_ms);
 

@@ -277,7 +277,7 @@ struct DesignHost {
   uint32_t id = 0;
   uint32_t n_slots = 0, n_regs = 0, n_inputs = 0, n_design_layers = 0;
   uint32_t n_idx[NCLS] = {0};
-  uint64_t wide_bytes = 0;  // bytes of one instance's wide region (all classes but CB)
+  uint64_t n_rows = 0;      // 64-bit rows of one instance's state
   std::vector<DevOp> ops;
   std::vector<DevLayer> layers;
   std::vector<uint64_t> const_limbs;
@@ -373,11 +373,16 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
   }
 
   // Group each layer by (1-bit destination first, kind, type, class): the
-  // N-rank swizzle, which also makes 1-bit destinations a prefix.
+  // N-rank swizzle, which also makes 1-bit destinations a prefix.  Heavy
+  // operations (a value wider than 64 bits, or a source) go last among the
+  // 1-bit destinations and first among the others, so they are contiguous.
+  auto heavy = [](const EncOp& e) { return e.kind == K_WIDE || e.opc >= OP_STIM; };
   for (auto& lay : L)
-    std::stable_sort(lay.begin(), lay.end(), [](const EncOp& a, const EncOp& b) {
+    std::stable_sort(lay.begin(), lay.end(), [&](const EncOp& a, const EncOp& b) {
       const uint32_t ka = a.dcls != CB, kb = b.dcls != CB;
       if (ka != kb) return ka < kb;
+      const uint32_t ha = heavy(a) != (ka != 0), hb = heavy(b) != (kb != 0);
+      if (ha != hb) return ha < hb;
       if (a.kind != b.kind) return a.kind < b.kind;
       if (a.opc != b.opc) return a.opc < b.opc;
       return a.dcls < b.dcls;
@@ -405,24 +410,40 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
     }
     dl.n_bdst = nb;
     if (nb) cnt[CB] = dl.b_base + nb;
+    uint32_t first_heavy = dl.end, n_heavy = 0;
+    for (uint32_t i = 0; i < lay.size(); ++i)
+      if (heavy(lay[i])) {
+        first_heavy = std::min(first_heavy, dl.begin + i);
+        ++n_heavy;
+      }
+    dl.hbeg = n_heavy ? first_heavy : dl.begin;
+    dl.hend = dl.hbeg + n_heavy;
     h->layers.push_back(dl);
     h->max_layer_ops = std::max<uint32_t>(h->max_layer_ops, (uint32_t)lay.size());
     pos = dl.end;
   }
   for (int c = 0; c < NCLS; ++c) h->n_idx[c] = cnt[c];
 
-  // Wide region of one instance: CW elements (4 bytes), then CD, CL2, CL3,
-  // CL4 (8 bytes per limb), each class starting on a 16-byte boundary.  A
-  // non-1-bit slot is addressed by its byte offset Y in this region.
+  // Rows of one instance: the 1-bit rows (at least one, since absent
+  // operands read field 0), then the wide rows.  The wide values are laid out
+  // by byte offset Y in a region of CW elements (4 bytes, two to a row), then
+  // CD, CL2, CL3, CL4 (8 bytes per limb), each class starting on a 16-byte
+  // boundary; Y becomes the field 64*(first wide row + Y/8) + 8*(Y%8), the
+  // last term being the 32-bit half's shift.  A 1-bit slot's field is its bit
+  // index.
+  const uint64_t b_rows = (std::max<uint64_t>(cnt[CB], 64) + 63) / 64;
   uint64_t base[NCLS] = {0};
   uint64_t wb = 0;
   for (uint32_t c = CW; c < NCLS; ++c) {
     base[c] = wb;
     wb = (wb + (uint64_t)cnt[c] * cls_bytes(c) + 15) & ~uint64_t(15);
   }
-  h->wide_bytes = wb;
+  h->n_rows = b_rows + wb / 8;
   for (uint32_t k = 0; k < NW; ++k)
-    if (scls[k] != CB && scls[k] != CNONE) sidx[k] = (uint32_t)(base[scls[k]] + (uint64_t)sidx[k] * cls_bytes(scls[k]));
+    if (scls[k] != CB && scls[k] != CNONE) {
+      const uint64_t y = base[scls[k]] + (uint64_t)sidx[k] * cls_bytes(scls[k]);
+      sidx[k] = (uint32_t)((b_rows + y / 8) * 64 + (y % 8) * 8);
+    }
 
   h->ops.clear();
   h->ops.reserve(pos);
@@ -479,11 +500,13 @@ struct Batch {
   hipGraphExec_t graph = nullptr;  // one cycle of SWEEP launches
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+  std::vector<uint8_t> ev_kind;  // per used pair: 0 main kernel, 1 heavy SWEEP kernel
 };
 
 void release_events(Batch& b) {
   for (auto& e : b.ev_used) b.ev_free.push_back(e);
   b.ev_used.clear();
+  b.ev_kind.clear();
 }
 
 void destroy_events(Batch& b) {
@@ -497,7 +520,7 @@ void destroy_events(Batch& b) {
 
 // Records a start event, runs `launch`, records an end event.
 template <class F>
-hipError_t timed(Batch& b, hipStream_t s, F&& launch) {
+hipError_t timed(Batch& b, hipStream_t s, uint8_t kind, F&& launch) {
   if (!b.profile) return launch();
   std::pair<hipEvent_t, hipEvent_t> ev;
   if (!b.ev_free.empty()) {
@@ -512,39 +535,32 @@ hipError_t timed(Batch& b, hipStream_t s, F&& launch) {
   if (e == hipSuccess) e = launch();
   if (e == hipSuccess) e = hipEventRecord(ev.second, s);
   b.ev_used.push_back(ev);
+  b.ev_kind.push_back(kind);
   return e;
 }
 
-StateLayout make_layout(const DesignHost& h, uint32_t mapping, uint32_t n_inst, uint64_t* bytes) {
+// Layout of a batch's state; false if SWEEP rows would not fit 32-bit sizes.
+bool make_layout(const DesignHost& h, uint32_t mapping, uint32_t n_inst, uint32_t tg,
+                 StateLayout* out, uint64_t* bytes) {
   StateLayout L{};
-  // At least one 1-bit row / word: absent operands read 1-bit position 0.
-  const uint64_t n_b = std::max<uint64_t>(h.n_idx[CB], 64);
-  const uint64_t bwords = (n_b + 63) / 64;
+  L.n_rows = (uint32_t)h.n_rows;
   if (mapping == RTEAAL_MAP_SWEEP) {
-    auto align = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+    tg = (tg == 2 || tg == 4 || tg == 8) ? tg : 1u;
     L.n_tiles = (n_inst + 63) / 64;
-    L.n_pad = L.n_tiles * 64;
-    uint32_t p2 = 1, lg = 0;
-    while (p2 < L.n_tiles) { p2 <<= 1; ++lg; }
-    L.b_shift = 3 + lg;
-    L.b_off = 0;
-    L.nb_off = align(n_b * p2 * 8);
-    L.tile_bytes = h.wide_bytes * 64;
-    L.zero_off = L.nb_off + L.tile_bytes * L.n_tiles;
+    L.n_tiles_alloc = (L.n_tiles + tg - 1) / tg * tg;
+    if ((uint64_t)L.n_tiles_alloc * 512 >= (1ull << 32)) return false;
+    L.row_bytes = L.n_tiles_alloc * 512u;
     L.pitch = 0;
-    *bytes = L.zero_off + 256;
+    *bytes = h.n_rows * L.row_bytes;
   } else {
-    L.n_tiles = 0;
-    L.n_pad = n_inst;
-    L.b_off = 0;
-    L.nb_off = (bwords * 8 + 15) & ~uint64_t(15);
-    L.zero_off = L.nb_off + h.wide_bytes;
-    L.tile_bytes = 0;
-    L.pitch = L.zero_off + 16;
+    L.pitch = (h.n_rows * 8 + 15) & ~uint64_t(15);
     *bytes = L.pitch * n_inst;
   }
-  return L;
+  *out = L;
+  return true;
 }
+
+uint32_t sweep_tg(const rteaal_batch_opts* o) { return o && o->tiles_per_wave ? o->tiles_per_wave : 1u; }
 
 uint32_t choose_mapping(const DesignHost& h, uint32_t n_inst, const rteaal_batch_opts* o) {
   if (o && o->mapping == RTEAAL_MAP_RESIDENT) return RTEAAL_MAP_RESIDENT;
@@ -606,7 +622,7 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
   if (b.mapping == RTEAAL_MAP_RESIDENT) {
     for (uint64_t done = 0; done < n_cycles;) {
       const uint64_t n = std::min(kResidentChunk, n_cycles - done);
-      HIP_TRY(ctx, timed(b, ctx->stream, [&] {
+      HIP_TRY(ctx, timed(b, ctx->stream, 0, [&] {
                 const ResJob J = res_job(h, b, n);
                 return launch_resident(J, b.n_inst, 0, b.block, b.lds, b.lds_ops, b.unroll,
                                        ctx->stream);
@@ -616,17 +632,23 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
     }
     return RTEAAL_OK;
   }
-  // SWEEP: one launch per layer, the cycle captured once as a HIP graph.
+  // SWEEP: per layer the common kernel and the heavy one, the cycle captured
+  // once as a HIP graph.
+  char* st = (char*)b.state.p;
+  const uint64_t* seeds = (const uint64_t*)b.seeds.p;
   if (b.profile) {
     for (uint64_t c = 0; c < n_cycles; ++c) {
       for (uint32_t li = 0; li < h.layers.size(); ++li) {
-        const uint32_t nops = h.layers[li].end - h.layers[li].begin;
-        if (!nops) continue;
-        HIP_TRY(ctx, timed(b, ctx->stream, [&] {
-                  return launch_sweep_layer(p, b.L, (char*)b.state.p, (const uint64_t*)b.seeds.p,
-                                            ctl, b.n_inst, li, nops, b.opw, b.unroll, b.tg,
-                                            ctx->stream);
-                }));
+        const DevLayer& ly = h.layers[li];
+        if (ly.end - ly.begin > ly.hend - ly.hbeg)
+          HIP_TRY(ctx, timed(b, ctx->stream, 0, [&] {
+                    return launch_sweep_light(p, b.L, st, li, ly, b.opw, b.unroll, b.tg, ctx->stream);
+                  }));
+        if (ly.hend > ly.hbeg)
+          HIP_TRY(ctx, timed(b, ctx->stream, 1, [&] {
+                    return launch_sweep_heavy(p, b.L, st, seeds, ctl, b.n_inst, li, ly, b.opw, b.tg,
+                                              ctx->stream);
+                  }));
       }
       HIP_TRY(ctx, launch_advance(ctl, 1, ctx->stream));
     }
@@ -636,10 +658,12 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
     hipGraph_t g = nullptr;
     HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (uint32_t li = 0; li < h.layers.size() && e == hipSuccess; ++li)
-      e = launch_sweep_layer(p, b.L, (char*)b.state.p, (const uint64_t*)b.seeds.p, ctl, b.n_inst,
-                             li, h.layers[li].end - h.layers[li].begin, b.opw, b.unroll, b.tg,
-                             ctx->stream);
+    for (uint32_t li = 0; li < h.layers.size() && e == hipSuccess; ++li) {
+      const DevLayer& ly = h.layers[li];
+      e = launch_sweep_light(p, b.L, st, li, ly, b.opw, b.unroll, b.tg, ctx->stream);
+      if (e == hipSuccess)
+        e = launch_sweep_heavy(p, b.L, st, seeds, ctl, b.n_inst, li, ly, b.opw, b.tg, ctx->stream);
+    }
     if (e == hipSuccess) e = launch_advance(ctl, 1, ctx->stream);
     hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -755,9 +779,9 @@ rteaal_status rteaal_load_design(rteaal_ctx* ctx, const rteaal_design_desc* desc
   rteaal_status st = validate(desc, &drv, &why, &h->fmt);
   if (st != RTEAAL_OK) return fail(ctx, st, "%s", why.c_str());
   encode(desc, drv, h.get());
-  if (h->wide_bytes >= (1ull << 32))
-    return fail(ctx, RTEAAL_E_UNSUPPORTED, "one instance's multi-bit state (%llu bytes) exceeds 4 GiB",
-                (unsigned long long)h->wide_bytes);
+  if (h->n_rows >= (1ull << 26))
+    return fail(ctx, RTEAAL_E_UNSUPPORTED, "one instance's state (%llu bytes) exceeds 512 MiB",
+                (unsigned long long)(h->n_rows * 8));
   const size_t ops_b = h->ops.size() * sizeof(DevOp), lay_b = h->layers.size() * sizeof(DevLayer);
   const size_t con_b = h->const_limbs.size() * 8, reg_b = std::max<size_t>(h->reg_refs.size(), 1) * sizeof(SlotRef);
   if (!alloc_all(ctx, {{&h->d_ops, ops_b}, {&h->d_layers, lay_b}, {&h->d_consts, con_b},
@@ -809,9 +833,10 @@ rteaal_status rteaal_batch_footprint(rteaal_ctx* ctx, rteaal_design_id id, uint3
   opts = resolve_opts(ctx, id, n_inst, opts);
   const uint32_t m = choose_mapping(*h, n_inst, opts);
   uint64_t sb = 0;
-  StateLayout L = make_layout(*h, m, n_inst, &sb);
-  (void)L;
-  const uint64_t pad = m == RTEAAL_MAP_SWEEP ? ((n_inst + 63) / 64) * 64 : n_inst;
+  StateLayout L;
+  if (!make_layout(*h, m, n_inst, sweep_tg(opts), &L, &sb))
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "too many instances for one SWEEP batch");
+  const uint64_t pad = m == RTEAAL_MAP_SWEEP ? (uint64_t)L.n_tiles_alloc * 64 : n_inst;
   *bytes = sb + pad * 8 + 256 + 512;
   return RTEAAL_OK;
 }
@@ -829,7 +854,8 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
   b->n_inst = n_inst;
   b->mapping = choose_mapping(*h, n_inst, opts);
   uint64_t sb = 0;
-  b->L = make_layout(*h, b->mapping, n_inst, &sb);
+  if (!make_layout(*h, b->mapping, n_inst, sweep_tg(opts), &b->L, &sb))
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "too many instances for one SWEEP batch");
   if (b->mapping == RTEAAL_MAP_RESIDENT) {
     uint32_t blk = opts && opts->block_threads ? opts->block_threads : 0;
     if (blk && (blk % 64 || blk > 1024))
@@ -856,13 +882,13 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
       return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP unroll must be 1, 2 or 4");
     b->unroll = u;
     const uint32_t tg = opts && opts->tiles_per_wave ? opts->tiles_per_wave : 1u;
-    if (tg != 1 && tg != 2 && tg != 4)
-      return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP tiles_per_wave must be 1, 2 or 4");
-    if (tg * u > 4)
-      return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP unroll x tiles_per_wave must be at most 4");
+    if (tg != 1 && tg != 2 && tg != 4 && tg != 8)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP tiles_per_wave must be 1, 2, 4 or 8");
+    if (tg * u > 8)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP unroll x tiles_per_wave must be at most 8");
     b->tg = tg;
   }
-  const uint64_t n_seed = b->mapping == RTEAAL_MAP_SWEEP ? b->L.n_pad : n_inst;
+  const uint64_t n_seed = b->mapping == RTEAAL_MAP_SWEEP ? (uint64_t)b->L.n_tiles_alloc * 64 : n_inst;
   if (!alloc_all(ctx, {{&b->state, sb}, {&b->seeds, n_seed * 8}, {&b->ctl, sizeof(DevCtl)}}))
     return fail(ctx, RTEAAL_E_NO_MEMORY, "device allocation of %llu bytes for the batch failed",
                 (unsigned long long)sb);
@@ -1152,11 +1178,11 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
       cand.push_back(rteaal_batch_opts{RTEAAL_MAP_RESIDENT, blk, 0, 0, 0, u, 0});
   }
   const uint32_t n_tiles = (n_inst + 63) / 64;
-  for (uint32_t tg : {1u, 2u, 4u}) {
+  for (uint32_t tg : {1u, 2u, 4u, 8u}) {
     if (tg > 1 && tg > n_tiles) continue;
     for (uint32_t opw : {2u, 4u, 8u, 16u, 32u})
       for (uint32_t u : {1u, 2u, 4u})
-        if (u * tg <= 4) cand.push_back(rteaal_batch_opts{RTEAAL_MAP_SWEEP, 0, opw, 0, 0, u, tg});
+        if (u * tg <= 8) cand.push_back(rteaal_batch_opts{RTEAAL_MAP_SWEEP, 0, opw, 0, 0, u, tg});
   }
   std::vector<uint64_t> seeds(n_inst);
   for (uint32_t i = 0; i < n_inst; ++i) seeds[i] = i;
@@ -1208,14 +1234,18 @@ rteaal_status rteaal_kernel_timing(rteaal_ctx* ctx, rteaal_batch_id id, int enab
   Batch* b = find_batch(ctx, id);
   if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  double total = 0.0;
-  for (auto& e : b->ev_used) {
+  double total[2] = {0.0, 0.0};
+  uint64_t count[2] = {0, 0};
+  for (size_t i = 0; i < b->ev_used.size(); ++i) {
     float ms = 0.f;
-    HIP_TRY(ctx, hipEventElapsedTime(&ms, e.first, e.second));
-    total += ms;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, b->ev_used[i].first, b->ev_used[i].second));
+    total[b->ev_kind[i]] += ms;
+    ++count[b->ev_kind[i]];
   }
-  if (launches) *launches = b->ev_used.size();
-  if (total_ms) *total_ms = total;
+  for (int k = 0; k < 2; ++k) {
+    if (launches) launches[k] = count[k];
+    if (total_ms) total_ms[k] = total[k];
+  }
   release_events(*b);
   b->profile = enable != 0;
   return RTEAAL_OK;

@@ -35,7 +35,7 @@ enum Kind : uint32_t { K_BIT = 0, K_U64 = 1, K_WIDE = 2, K_U32 = 3 };
 // One operation, 32 bytes.
 //   code: opc[0:5] kind[6:7] arity[8:9] dst class[10:12] src classes [13:15][16:18][19:21]
 //   wimm: dst width[0:8] (1..256), imm[9:17] (shift, low bit, width of o1 for CONCAT)
-//   dst, src[3]: bit index of a 1-bit slot, else its byte offset Y (see StateLayout)
+//   dst, src[3]: slot fields 64*row + shift (see StateLayout)
 //   aux0: STIM input number / CONST literal index;  aux1: STIM limb offset in a words row
 struct DevOp {
   uint32_t code, wimm, dst, src[3], aux0, aux1;
@@ -53,10 +53,18 @@ __host__ __device__ inline uint32_t op_imm(uint32_t w) { return (w >> 9) & 511u;
 // One encoded layer: operations [begin, end).  Operations whose destination
 // is 1-bit come first, and the i-th of them writes bit index b_base + i
 // (b_base a multiple of 64), so one wavefront of consecutive operations
-// fills exactly one 64-bit word.
+// fills exactly one 64-bit word.  The "heavy" operations (a value wider than
+// 64 bits, or a source: STIM, CONST) form the contiguous range [hbeg, hend)
+// (the last 1-bit destinations and the first others), so the SWEEP mapping
+// runs them in a kernel of their own and keeps the common kernel small.
 struct DevLayer {
-  uint32_t begin, end, b_base, n_bdst;
+  uint32_t begin, end, b_base, n_bdst, hbeg, hend, pad0, pad1;
 };
+static_assert(sizeof(DevLayer) == 32, "DevLayer layout");
+
+__host__ __device__ inline bool op_heavy(uint32_t code) {
+  return op_kind(code) == K_WIDE || op_opc(code) >= OP_STIM;
+}
 
 // Per-batch control block in device memory.
 struct DevCtl {
@@ -68,25 +76,30 @@ struct DevCtl {
 
 // Byte layout of one batch's signal state.
 //
-// Every 1-bit slot has a bit index i; every other slot has a byte offset Y
-// inside one instance's "wide region" (CW elements take 4 bytes, CD 8, CLk
-// 8k with the limbs contiguous).  Operation records carry i or Y, so one
-// record format serves both mappings:
-//   RESIDENT, instance j at j*pitch:
-//     1-bit slot i: bit i of the 64-bit words at b_off;
-//     other slot:   its bytes at nb_off + Y (limb l at + 8l).
-//   SWEEP, tile t = j / 64, lane = j % 64:
-//     1-bit slot i: bit `lane` of the word at b_off + ((i << b_shift) + t*8),
-//       b_shift = 3 + log2(tile count rounded up to a power of two) (the words
-//       of one slot are adjacent across tiles);
-//     other slot:   tile t's block starts at nb_off + t*tile_bytes; the 4- or
-//       8-byte element at resident offset Y (limb l: Y + 8l) becomes a row of
-//       64 lanes at (Y + 8l)*64, lane at +4*lane (CW) or +8*lane (others).
-//   zero_off: zero bytes (16 per instance block for RESIDENT, 256 for SWEEP)
-//   read in place of an absent operand or high half.
+// An instance's stored values occupy 64-bit rows: the first rows each hold
+// 64 1-bit slots (bit k of row r is 1-bit slot 64r + k), the remaining rows
+// ("wide rows") each hold two 32-bit values (low and high half), one 64-bit
+// value, or one limb of a wider value (limb l of a value in row r is in row
+// r + l).  A slot is named by one 32-bit field f = 64*row + shift, where
+// shift is the bit index for a 1-bit slot, 0 or 32 for a 32-bit value and 0
+// otherwise; a 1-bit slot's field is its bit index.  Operation records carry
+// these fields, so one record format serves both mappings:
+//   RESIDENT, instance j at j*pitch: row r at 8r; the value is the row's
+//     word shifted down by `shift` (then cut to the class).
+//   SWEEP, tile t = j / 64, lane = j % 64: rows are interleaved over tiles,
+//     row r of tile t is the 512 bytes at r*row_bytes + t*512 (row_bytes =
+//     512 * allocated tiles).  Inside, a 1-bit row is 64 bit-sliced words
+//     (bit index k at 8k, bit `lane` of the word is the instance's value); a
+//     wide row holds the 64 lanes' values: 32-bit at 8*shift + 4*lane, others
+//     at 8*lane.  The byte address of slot f for tile t is thus
+//     (f / 64) * row_bytes + 8 * (f % 64) + 512 * t, plus the lane's part.
 struct StateLayout {
-  uint64_t b_off, nb_off, zero_off, pitch, tile_bytes;
-  uint32_t n_tiles, n_pad, b_shift, pad;
+  uint64_t pitch;          // RESIDENT: bytes per instance (multiple of 16)
+  uint32_t row_bytes;      // SWEEP: bytes of one row over all allocated tiles
+  uint32_t n_rows;         // 64-bit rows per instance
+  uint32_t n_tiles;        // SWEEP: tiles that hold instances
+  uint32_t n_tiles_alloc;  // SWEEP: allocated tiles, a multiple of the tile group
+  uint32_t pad[2];
 };
 
 struct Program {
@@ -97,9 +110,8 @@ struct Program {
   uint32_t words_per_inst;      // stimulus limbs per instance and cycle
 };
 
-// Reference to a stored value for state read-out and restore: class, bit
-// index (1-bit) or wide-region byte offset Y (others), offset in the packed
-// output row, declared width.
+// Reference to a stored value for state read-out and restore: class, slot
+// field (see StateLayout), offset in the packed output row, declared width.
 struct SlotRef {
   uint32_t cls, pos, out_off, width;
 };
@@ -125,10 +137,16 @@ hipError_t launch_resident_multi(const ResJob* jobs, const uint2* map, uint32_t 
                                  size_t lds, hipStream_t s);
 size_t resident_lds_bytes(const StateLayout& L, uint32_t n_ops_total, uint32_t n_layers,
                           bool lds_state, bool lds_ops);
-hipError_t launch_sweep_layer(const Program& p, const StateLayout& L, char* state,
-                              const uint64_t* seeds, DevCtl* ctl, uint32_t n_inst,
-                              uint32_t layer, uint32_t layer_ops, uint32_t ops_per_wave,
-                              uint32_t unroll, uint32_t tiles_per_wave, hipStream_t s);
+// SWEEP, one layer (ly: the host copy of its record): the common operations
+// (launch_sweep_light) and the heavy ones (launch_sweep_heavy); either
+// returns without launching when its range is empty.
+hipError_t launch_sweep_light(const Program& p, const StateLayout& L, char* state, uint32_t layer,
+                              const DevLayer& ly, uint32_t ops_per_wave, uint32_t unroll,
+                              uint32_t tiles_per_wave, hipStream_t s);
+hipError_t launch_sweep_heavy(const Program& p, const StateLayout& L, char* state,
+                              const uint64_t* seeds, const DevCtl* ctl, uint32_t n_inst,
+                              uint32_t layer, const DevLayer& ly, uint32_t ops_per_wave,
+                              uint32_t tiles_per_wave, hipStream_t s);
 hipError_t launch_advance(DevCtl* ctl, uint64_t n, hipStream_t s);
 hipError_t launch_set_words(DevCtl* ctl, const uint64_t* words, hipStream_t s);
 hipError_t launch_pack(bool sweep, const StateLayout& L, const char* state, const SlotRef* refs,

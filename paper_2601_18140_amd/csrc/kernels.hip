@@ -51,28 +51,19 @@ __device__ __forceinline__ V4 source_value(const uint64_t* const_limbs, const De
 // RESIDENT: per-instance state block at `s` (LDS or global).
 // ---------------------------------------------------------------------------
 
-// Operand fetch without branches: one aligned 8-byte load per operand.  A
-// 1-bit value comes from the word holding its bit, a 32-bit value from the
-// aligned word holding it (then shifted down), so the address depends only on
-// the class and the position.  Absent operands (arity < 3) carry position 0
+// Operand fetch without branches: one aligned 8-byte load per operand, the
+// row named by the slot field, shifted down by the field's shift; only the
+// final cut depends on the class.  Absent operands (arity < 3) carry field 0
 // of class CB and read a valid word that is never used.
-__device__ __forceinline__ uint64_t res_fetch(const char* s, const StateLayout& L, uint32_t cls,
-                                              uint32_t pos) {
-  const char* a = cls == CB ? s + L.b_off + (uint64_t)(pos >> 6) * 8u
-                            : s + L.nb_off + (pos & ~7u);
-  const uint64_t v = *(const uint64_t*)a;
-  return cls == CB ? (v >> (pos & 63u)) & 1ull
-       : cls == CW ? (v >> ((pos & 4u) * 8u)) & 0xffffffffull : v;
+__device__ __forceinline__ uint64_t res_fetch(const char* s, uint32_t cls, uint32_t f) {
+  const uint64_t v = *(const uint64_t*)(s + (uint64_t)(f >> 6) * 8u) >> (f & 63u);
+  return cls == CB ? v & 1ull : cls == CW ? v & 0xffffffffull : v;
 }
 
-__device__ __forceinline__ V4 res_ldv(const char* s, const StateLayout& L, uint32_t cls,
-                                      uint32_t pos) {
-  if (cls == CB) {
-    const uint32_t w = *(const uint32_t*)(s + L.b_off + (uint64_t)(pos >> 5) * 4u);
-    return v4_from((w >> (pos & 31u)) & 1u);
-  }
-  const char* q = s + L.nb_off + pos;
-  if (cls == CW) return v4_from(*(const uint32_t*)q);
+__device__ __forceinline__ V4 res_ldv(const char* s, uint32_t cls, uint32_t f) {
+  const char* q = s + (uint64_t)(f >> 6) * 8u;
+  if (cls == CB) return v4_from((*(const uint64_t*)q >> (f & 63u)) & 1ull);
+  if (cls == CW) return v4_from(*(const uint32_t*)(q + ((f & 63u) >> 3)));
   const uint32_t k = cls_limbs(cls);
   V4 r = v4_from(*(const uint64_t*)q);
   if (k > 1) r.l[1] = *(const uint64_t*)(q + 8);
@@ -81,18 +72,16 @@ __device__ __forceinline__ V4 res_ldv(const char* s, const StateLayout& L, uint3
   return r;
 }
 
-__device__ __forceinline__ void res_st64(char* s, const StateLayout& L, uint32_t cls,
-                                         uint32_t pos, uint64_t v) {
-  char* q = s + L.nb_off + pos;
-  if (cls == CW) *(uint32_t*)q = (uint32_t)v;
+__device__ __forceinline__ void res_st64(char* s, uint32_t cls, uint32_t f, uint64_t v) {
+  char* q = s + (uint64_t)(f >> 6) * 8u;
+  if (cls == CW) *(uint32_t*)(q + ((f & 63u) >> 3)) = (uint32_t)v;
   else *(uint64_t*)q = v;
 }
 
-__device__ __forceinline__ void res_stv(char* s, const StateLayout& L, uint32_t cls, uint32_t pos,
-                                        const V4& v) {
-  char* q = s + L.nb_off + pos;
+__device__ __forceinline__ void res_stv(char* s, uint32_t cls, uint32_t f, const V4& v) {
+  char* q = s + (uint64_t)(f >> 6) * 8u;
   if (cls == CW) {
-    *(uint32_t*)q = (uint32_t)v.l[0];
+    *(uint32_t*)(q + ((f & 63u) >> 3)) = (uint32_t)v.l[0];
     return;
   }
   const uint32_t k = cls_limbs(cls);
@@ -123,7 +112,7 @@ __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uin
     for (uint32_t i = threadIdx.x; i < J.n_ops_total * 2u; i += blockDim.x) o4[i] = go[i];
     uint4* l4 = o4 + J.n_ops_total * 2u;
     const uint4* gl = (const uint4*)J.layers;
-    for (uint32_t i = threadIdx.x; i < n_layers; i += blockDim.x) l4[i] = gl[i];
+    for (uint32_t i = threadIdx.x; i < n_layers * 2u; i += blockDim.x) l4[i] = gl[i];
     ops = (const DevOp*)o4;
     layers = (const DevLayer*)l4;
   }
@@ -156,9 +145,9 @@ __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uin
           const uint32_t q = q0 + u * bd, code = op[u].code, ar = op_arity(code);
           (void)q;
           (void)ar;
-          va[u] = res_fetch(s, L, op_scls(code, 0), op[u].src[0]);
-          vb[u] = res_fetch(s, L, op_scls(code, 1), op[u].src[1]);
-          vc[u] = res_fetch(s, L, op_scls(code, 2), op[u].src[2]);
+          va[u] = res_fetch(s, op_scls(code, 0), op[u].src[0]);
+          vb[u] = res_fetch(s, op_scls(code, 1), op[u].src[1]);
+          vc[u] = res_fetch(s, op_scls(code, 2), op[u].src[2]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -176,7 +165,7 @@ __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uin
                   bdst = true;
                   bit = x.l[0] & 1ull;
                 } else {
-                  res_stv(s, L, dc, o.dst, x);
+                  res_stv(s, dc, o.dst, x);
                 }
               } else if (op_kind(code) == K_U32 || op_kind(code) == K_BIT) {
                 const uint32_t r = eval_u32(opc, ar, (uint32_t)va[u], (uint32_t)vb[u],
@@ -185,7 +174,7 @@ __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uin
                   bdst = true;
                   bit = r & 1u;
                 } else {
-                  res_st64(s, L, dc, o.dst, r);
+                  res_st64(s, dc, o.dst, r);
                 }
               } else if (op_kind(code) != K_WIDE) {
                 const uint64_t r = eval_u64(opc, ar, va[u], vb[u], vc[u], imm, w);
@@ -193,18 +182,18 @@ __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uin
                   bdst = true;
                   bit = r & 1ull;
                 } else {
-                  res_st64(s, L, dc, o.dst, r);
+                  res_st64(s, dc, o.dst, r);
                 }
               } else {
-                const V4 a = res_ldv(s, L, op_scls(code, 0), o.src[0]);
-                const V4 b = ar > 1 ? res_ldv(s, L, op_scls(code, 1), o.src[1]) : v4_from(0);
-                const V4 c = ar > 2 ? res_ldv(s, L, op_scls(code, 2), o.src[2]) : v4_from(0);
+                const V4 a = res_ldv(s, op_scls(code, 0), o.src[0]);
+                const V4 b = ar > 1 ? res_ldv(s, op_scls(code, 1), o.src[1]) : v4_from(0);
+                const V4 c = ar > 2 ? res_ldv(s, op_scls(code, 2), o.src[2]) : v4_from(0);
                 const V4 r = eval_wide(opc, ar, a, b, c, imm, w);
                 if (dc == CB) {
                   bdst = true;
                   bit = r.l[0] & 1ull;
                 } else {
-                  res_stv(s, L, dc, o.dst, r);
+                  res_stv(s, dc, o.dst, r);
                 }
               }
             }
@@ -212,7 +201,7 @@ __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uin
             const uint64_t m = __ballot(bit != 0ull);
             const uint64_t any = __ballot(bdst);
             if (any != 0ull && lane == 0)
-              *(uint64_t*)(s + L.b_off + (uint64_t)((ly.b_base + q) >> 6) * 8u) = m;
+              *(uint64_t*)(s + (uint64_t)((ly.b_base + q) >> 6) * 8u) = m;
           }
         }
       }
@@ -244,107 +233,103 @@ k_resident_multi(const ResJob* __restrict__ jobs, const uint2* __restrict__ map)
 }
 
 // ---------------------------------------------------------------------------
-// SWEEP: lane = instance.  The per-wavefront bases are plain scalars computed
-// once, so an operand address is a select between two bases plus one add.
+// SWEEP: lane = instance.  A wavefront owns TG consecutive tiles.  The row of
+// a slot is found once per operation (scalar arithmetic on the record's
+// field) and the wavefront's tiles sit at fixed 512-byte steps from it, so
+// per tile only the load or store offset changes.
 // ---------------------------------------------------------------------------
 struct SweepView {
-  char* bB;          // 1-bit words of this tile: bit index i at bB + (i << bshift)
-  char* bT;          // this tile's block: resident offset Y at bT + Y*64
-  uint32_t bshift;   // 3 + log2(tile count rounded up to a power of two)
+  char* base;          // state + 512 * (first tile of the wavefront)
+  uint32_t row_bytes;  // bytes of one row over all allocated tiles
   uint32_t lane;
 
-  __device__ __forceinline__ SweepView(char* st, const StateLayout& L, uint32_t tile, uint32_t ln)
-      : bB(st + L.b_off + 8ull * tile), bT(st + L.nb_off + L.tile_bytes * tile),
-        bshift(L.b_shift), lane(ln) {}
-
-  __device__ __forceinline__ uint64_t ld_word(uint32_t i) const {
-    return *(const uint64_t*)(bB + ((uint64_t)i << bshift));
+  // Row of slot field f in the wavefront's first tile (1-bit slots: their
+  // bit-sliced word; others: the start of the 64 lane values).
+  __device__ __forceinline__ char* row(uint32_t f) const {
+    return base + (uint64_t)(f >> 6) * row_bytes + ((f & 63u) << 3);
   }
-  __device__ __forceinline__ void st_word(uint32_t i, uint64_t w) const {
-    *(uint64_t*)(bB + ((uint64_t)i << bshift)) = w;
+  // This lane's offset for an 8-byte operand load: 0 for CB (one word for the
+  // whole wavefront), the aligned word holding this lane's value for CW
+  // (lanes 2k and 2k+1 share it, so a row is read exactly once), and the
+  // lane's own value otherwise.
+  __device__ __forceinline__ uint32_t ld_off(uint32_t cls) const {
+    // (lane << 3) for 64-bit classes, (lane << 2) & ~7 for CW, 0 for CB,
+    // written as one shift and one mask so that no branch is taken.
+    const uint32_t w = cls == CW ? 1u : 0u;
+    const uint32_t mask = (cls == CB ? 0u : ~0u) & ~(w * 7u);
+    return (lane << (3u - w)) & mask;
   }
-  __device__ __forceinline__ char* elem(uint32_t cls, uint32_t pos) const {
-    return bT + (uint64_t)pos * 64u + lane * (cls == CW ? 4u : 8u);
-  }
-  // Element as stored, as one 8-byte load: the bit-sliced word for CB (one
-  // address for the whole wavefront), this lane's value for CD, and for CW
-  // the aligned 8-byte word holding this lane's value (lanes 2k and 2k+1
-  // share it, so a row is read exactly once).  Absent operands carry
-  // position 0 of class CB and read a valid word that is never used.
-  __device__ __forceinline__ uint64_t fetch(uint32_t cls, uint32_t pos) const {
-    const bool b = cls == CB;
-    const char* row = (b ? bB : bT) + ((uint64_t)pos << (b ? bshift : 6u));
-    const uint32_t off = b ? 0u : cls == CW ? (lane & ~1u) * 4u : lane * 8u;
-    return *(const uint64_t*)(row + off);
-  }
-  // As lane_val for classes of at most 32 bits.
+  // The operand's value in this lane from the loaded word.
   __device__ __forceinline__ uint32_t lane_val32(uint32_t cls, uint64_t raw) const {
     const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
     return cls == CB ? (uint32_t)((raw >> lane) & 1ull) : (lane & 1u) ? hi : lo;
   }
-  __device__ __forceinline__ void st32(uint32_t pos, uint32_t v) const {
-    *(uint32_t*)(bT + (uint64_t)pos * 64u + lane * 4u) = v;
-  }
-  // The operand's value in this lane from what fetch() returned.
   __device__ __forceinline__ uint64_t lane_val(uint32_t cls, uint64_t raw) const {
     return cls == CB ? (raw >> lane) & 1ull
          : cls == CW ? (raw >> ((lane & 1u) * 32u)) & 0xffffffffull : raw;
   }
-  __device__ __forceinline__ V4 ldv(uint32_t cls, uint32_t pos) const {
-    if (cls == CB) return v4_from((ld_word(pos) >> lane) & 1ull);
-    const char* q = elem(cls, pos);
-    if (cls == CW) return v4_from(*(const uint32_t*)q);
+  __device__ __forceinline__ void st_word(char* r, uint32_t g, uint64_t w) const {
+    *(uint64_t*)(r + g * 512u) = w;
+  }
+  __device__ __forceinline__ void st32(char* r, uint32_t g, uint32_t x) const {
+    *(uint32_t*)(r + g * 512u + lane * 4u) = x;
+  }
+  __device__ __forceinline__ void st64(uint32_t cls, char* r, uint32_t g, uint64_t x) const {
+    if (cls == CW) st32(r, g, (uint32_t)x);
+    else *(uint64_t*)(r + g * 512u + lane * 8u) = x;
+  }
+  __device__ __forceinline__ V4 ldv(uint32_t cls, const char* r, uint32_t g) const {
+    const char* q = r + g * 512u;
+    if (cls == CB) return v4_from((*(const uint64_t*)q >> lane) & 1ull);
+    if (cls == CW) return v4_from(*(const uint32_t*)(q + lane * 4u));
+    q += lane * 8u;
     const uint32_t k = cls_limbs(cls);
-    V4 r = v4_from(*(const uint64_t*)q);
-    if (k > 1) r.l[1] = *(const uint64_t*)(q + 512);
-    if (k > 2) r.l[2] = *(const uint64_t*)(q + 1024);
-    if (k > 3) r.l[3] = *(const uint64_t*)(q + 1536);
-    return r;
+    V4 x = v4_from(*(const uint64_t*)q);
+    if (k > 1) x.l[1] = *(const uint64_t*)(q + row_bytes);
+    if (k > 2) x.l[2] = *(const uint64_t*)(q + 2ull * row_bytes);
+    if (k > 3) x.l[3] = *(const uint64_t*)(q + 3ull * row_bytes);
+    return x;
   }
-  __device__ __forceinline__ void st64(uint32_t cls, uint32_t pos, uint64_t v) const {
-    char* q = elem(cls, pos);
-    if (cls == CW) *(uint32_t*)q = (uint32_t)v;
-    else *(uint64_t*)q = v;
-  }
-  __device__ __forceinline__ void stv(uint32_t cls, uint32_t pos, const V4& v) const {
-    char* q = elem(cls, pos);
+  __device__ __forceinline__ void stv(uint32_t cls, char* r, uint32_t g, const V4& x) const {
     if (cls == CW) {
-      *(uint32_t*)q = (uint32_t)v.l[0];
+      st32(r, g, (uint32_t)x.l[0]);
       return;
     }
+    char* q = r + g * 512u + lane * 8u;
     const uint32_t k = cls_limbs(cls);
-    *(uint64_t*)q = v.l[0];
-    if (k > 1) *(uint64_t*)(q + 512) = v.l[1];
-    if (k > 2) *(uint64_t*)(q + 1024) = v.l[2];
-    if (k > 3) *(uint64_t*)(q + 1536) = v.l[3];
+    *(uint64_t*)q = x.l[0];
+    if (k > 1) *(uint64_t*)(q + row_bytes) = x.l[1];
+    if (k > 2) *(uint64_t*)(q + 2ull * row_bytes) = x.l[2];
+    if (k > 3) *(uint64_t*)(q + 3ull * row_bytes) = x.l[3];
   }
 };
 
-// A wavefront handles a chunk of operations for TG tiles (64 instances
-// each).  Operations are processed U at a time: first the U records (scalar
-// loads, decoded once for all TG tiles), then every operand row for every
-// tile, then the evaluations and stores, so 3*U*TG gathers are in flight
-// per wavefront and the type dispatch is paid once per operation.
+// Common operations of one layer (every value at most 64 bits, no source).
+// A wavefront handles a chunk of operations for TG tiles (64 instances each).
+// Operations are processed U at a time: first the U records (scalar loads,
+// decoded once for all TG tiles), then every operand row for every tile, then
+// the evaluations and stores, so 3*U*TG gathers are in flight per wavefront
+// and the type dispatch is paid once per operation.  Tiles past the last
+// instance (allocation padding up to a multiple of TG) are evaluated like the
+// others and never read back.  The layer's common operations are the ranges
+// [begin, hbeg) and [hend, end); the first `split` chunks cover the first.
 template <int U, int TG>
 __global__ void __launch_bounds__(256)
-k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
-        const uint64_t* __restrict__ const_limbs, uint32_t words_per_inst, StateLayout L,
-        char* __restrict__ state, const uint64_t* __restrict__ seeds,
-        const DevCtl* __restrict__ ctl, uint32_t n_inst, uint32_t layer, uint32_t opw) {
+k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers, StateLayout L,
+        char* __restrict__ state, uint32_t layer, uint32_t opw, uint32_t split) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  const uint32_t n_groups = (L.n_tiles + TG - 1) / TG;
+  const uint32_t n_groups = L.n_tiles_alloc / TG;
   const uint32_t grp = wave % n_groups, chunk = wave / n_groups;
   const DevLayer ly = layers[layer];
-  const uint32_t o0 = ly.begin + chunk * opw;
-  if (o0 >= ly.end) return;
-  const uint32_t o1 = min(o0 + opw, ly.end);
-  // Tiles of this wavefront; a short last group repeats its last tile, which
-  // recomputes and rewrites identical values.
-  uint32_t tile[TG];
-#pragma unroll
-  for (int g = 0; g < TG; ++g) tile[g] = min(grp * TG + g, L.n_tiles - 1u);
+  const bool first = chunk < split;
+  const uint32_t o0 = first ? ly.begin + chunk * opw : ly.hend + (chunk - split) * opw;
+  const uint32_t oe = first ? ly.hbeg : ly.end;
+  if (o0 >= oe) return;
+  const uint32_t o1 = min(o0 + opw, oe);
+  const uint32_t tile0 = grp * TG;
+  const SweepView v{state + (uint64_t)tile0 * 512u, L.row_bytes, lane};
 
   for (uint32_t o = o0; o < o1; o += U) {
     DevOp op[U];
@@ -354,14 +339,25 @@ k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t code = op[u].code;
+      const char* pa = v.row(op[u].src[0]) + v.ld_off(op_scls(code, 0));
+      const char* pb = v.row(op[u].src[1]) + v.ld_off(op_scls(code, 1));
+      const char* pc = v.row(op[u].src[2]) + v.ld_off(op_scls(code, 2));
 #pragma unroll
       for (int g = 0; g < TG; ++g) {
-        const SweepView v(state, L, tile[g], lane);
-        ra[u][g] = v.fetch(op_scls(code, 0), op[u].src[0]);
-        rb[u][g] = v.fetch(op_scls(code, 1), op[u].src[1]);
-        rc[u][g] = v.fetch(op_scls(code, 2), op[u].src[2]);
+        ra[u][g] = *(const uint64_t*)(pa + g * 512);
+        rb[u][g] = *(const uint64_t*)(pb + g * 512);
+        rc[u][g] = *(const uint64_t*)(pc + g * 512);
       }
     }
+    // Every gathered word counts as used on every path (unary operators,
+    // absent operands, wide and source operations ignore some of them), so
+    // that no load is still in flight when the next group's loads reuse its
+    // registers: otherwise the top of the loop would also wait for this
+    // group's stores.
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int g = 0; g < TG; ++g) asm volatile("" ::"v"(ra[u][g]), "v"(rb[u][g]), "v"(rc[u][g]));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (o + u < o1) {
@@ -369,11 +365,11 @@ k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
         const uint32_t code = q.code, opc = op_opc(code), ar = op_arity(code), kind = op_kind(code);
         const uint32_t dc = op_dcls(code), w = op_width(q.wimm), imm = op_imm(q.wimm);
         const uint32_t c0 = op_scls(code, 0), c1 = op_scls(code, 1), c2 = op_scls(code, 2);
+        char* rd = v.row(q.dst);
         if (kind == K_U32) {
           uint32_t a[TG], b[TG], c[TG], r[TG];
 #pragma unroll
           for (int g = 0; g < TG; ++g) {
-            const SweepView v(state, L, tile[g], lane);
             a[g] = v.lane_val32(c0, ra[u][g]);
             b[g] = v.lane_val32(c1, rb[u][g]);
             c[g] = v.lane_val32(c2, rc[u][g]);
@@ -381,64 +377,87 @@ k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
           eval_u32_n<TG>(opc, ar, a, b, c, imm, w, r);
 #pragma unroll
           for (int g = 0; g < TG; ++g) {
-            const SweepView v(state, L, tile[g], lane);
             if (dc == CB) {
               const uint64_t m = __ballot((r[g] & 1u) != 0u);
-              if (lane == 0) v.st_word(q.dst, m);
+              if (lane == 0) v.st_word(rd, g, m);
             } else {
-              v.st32(q.dst, r[g]);
+              v.st32(rd, g, r[g]);
             }
           }
         } else if (kind == K_BIT) {
 #pragma unroll
           for (int g = 0; g < TG; ++g) {
-            const SweepView v(state, L, tile[g], lane);
             const uint64_t r = eval_bits(opc, ar, ra[u][g], rb[u][g], rc[u][g], imm);
-            if (lane == 0) v.st_word(q.dst, r);
+            if (lane == 0) v.st_word(rd, g, r);
           }
-        } else {
+        } else {  // K_U64
 #pragma unroll
           for (int g = 0; g < TG; ++g) {
-            const SweepView v(state, L, tile[g], lane);
-            const uint32_t inst = tile[g] * 64u + lane;
-            if (opc >= OP_STIM) {
-              const uint64_t cycle = ctl->cycle;
-              const uint64_t words_row = ((cycle - ctl->step_cycle0) * (uint64_t)n_inst + inst) *
-                                         (uint64_t)words_per_inst;
-              V4 x = v4_from(0);
-              if (inst < n_inst)
-                x = source_value(const_limbs, q, seeds[inst], cycle, ctl->words, words_row, w);
-              if (dc == CB) {
-                const uint64_t m = __ballot((x.l[0] & 1ull) != 0ull);
-                if (lane == 0) v.st_word(q.dst, m);
-              } else {
-                v.stv(dc, q.dst, x);
-              }
-            } else if (kind == K_U64) {
-              const uint64_t a = v.lane_val(c0, ra[u][g]);
-              const uint64_t b = v.lane_val(c1, rb[u][g]);
-              const uint64_t c = v.lane_val(c2, rc[u][g]);
-              const uint64_t r = eval_u64(opc, ar, a, b, c, imm, w);
-              if (dc == CB) {
-                const uint64_t m = __ballot((r & 1ull) != 0ull);
-                if (lane == 0) v.st_word(q.dst, m);
-              } else {
-                v.st64(dc, q.dst, r);
-              }
+            const uint64_t a = v.lane_val(c0, ra[u][g]);
+            const uint64_t b = v.lane_val(c1, rb[u][g]);
+            const uint64_t c = v.lane_val(c2, rc[u][g]);
+            const uint64_t r = eval_u64(opc, ar, a, b, c, imm, w);
+            if (dc == CB) {
+              const uint64_t m = __ballot((r & 1ull) != 0ull);
+              if (lane == 0) v.st_word(rd, g, m);
             } else {
-              const V4 a = v.ldv(c0, q.src[0]);
-              const V4 b = ar > 1 ? v.ldv(c1, q.src[1]) : v4_from(0);
-              const V4 c = ar > 2 ? v.ldv(c2, q.src[2]) : v4_from(0);
-              const V4 r = eval_wide(opc, ar, a, b, c, imm, w);
-              if (dc == CB) {
-                const uint64_t m = __ballot((r.l[0] & 1ull) != 0ull);
-                if (lane == 0) v.st_word(q.dst, m);
-              } else {
-                v.stv(dc, q.dst, r);
-              }
+              v.st64(dc, rd, g, r);
             }
           }
         }
+      }
+    }
+  }
+}
+
+// Heavy operations of one layer, [hbeg, hend): values wider than 64 bits
+// (limb arithmetic on up to four 64-bit limbs) and the sources (stimulus
+// words and literals).  One operation at a time per wavefront, for TG tiles.
+template <int TG>
+__global__ void __launch_bounds__(256)
+k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
+              const uint64_t* __restrict__ const_limbs, uint32_t words_per_inst, StateLayout L,
+              char* __restrict__ state, const uint64_t* __restrict__ seeds,
+              const DevCtl* __restrict__ ctl, uint32_t n_inst, uint32_t layer, uint32_t opw) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const uint32_t n_groups = L.n_tiles_alloc / TG;
+  const uint32_t grp = wave % n_groups, chunk = wave / n_groups;
+  const DevLayer ly = layers[layer];
+  const uint32_t o0 = ly.hbeg + chunk * opw;
+  if (o0 >= ly.hend) return;
+  const uint32_t o1 = min(o0 + opw, ly.hend);
+  const uint32_t tile0 = grp * TG;
+  const SweepView v{state + (uint64_t)tile0 * 512u, L.row_bytes, lane};
+
+  for (uint32_t o = o0; o < o1; ++o) {
+    const DevOp q = ops[o];
+    const uint32_t code = q.code, opc = op_opc(code), ar = op_arity(code);
+    const uint32_t dc = op_dcls(code), w = op_width(q.wimm), imm = op_imm(q.wimm);
+    char* rd = v.row(q.dst);
+#pragma unroll
+    for (int g = 0; g < TG; ++g) {
+      V4 r;
+      if (opc >= OP_STIM) {
+        const uint32_t inst = (tile0 + g) * 64u + lane;
+        const uint64_t cycle = ctl->cycle;
+        const uint64_t words_row =
+            ((cycle - ctl->step_cycle0) * (uint64_t)n_inst + inst) * (uint64_t)words_per_inst;
+        r = v4_from(0);
+        if (inst < n_inst)
+          r = source_value(const_limbs, q, seeds[inst], cycle, ctl->words, words_row, w);
+      } else {
+        const V4 a = v.ldv(op_scls(code, 0), v.row(q.src[0]), g);
+        const V4 b = ar > 1 ? v.ldv(op_scls(code, 1), v.row(q.src[1]), g) : v4_from(0);
+        const V4 c = ar > 2 ? v.ldv(op_scls(code, 2), v.row(q.src[2]), g) : v4_from(0);
+        r = eval_wide(opc, ar, a, b, c, imm, w);
+      }
+      if (dc == CB) {
+        const uint64_t m = __ballot((r.l[0] & 1ull) != 0ull);
+        if (lane == 0) v.st_word(rd, g, m);
+      } else {
+        v.stv(dc, rd, g, r);
       }
     }
   }
@@ -458,26 +477,27 @@ __global__ void k_set_words(DevCtl* ctl, const uint64_t* words) {
   }
 }
 
-// Address of limb `limb` of a stored value of instance `inst` (for CB: the
-// word holding its bit, with the bit position in *bitpos).
+// Address of limb `limb` of the stored value with slot field f of instance
+// `inst` (for CB: the word holding its bit, with the bit position in *bitpos).
 __device__ __forceinline__ char* elem_addr(bool sweep, const StateLayout& L, char* state,
-                                           uint32_t cls, uint32_t pos, uint32_t limb,
+                                           uint32_t cls, uint32_t f, uint32_t limb,
                                            uint32_t inst, uint32_t* bitpos) {
+  const uint64_t row = (f >> 6) + limb;
   if (sweep) {
-    const uint64_t t = inst >> 6, ln = inst & 63u;
+    const uint32_t t = inst >> 6, ln = inst & 63u;
+    char* r = state + row * L.row_bytes + (uint64_t)t * 512u + ((f & 63u) << 3);
     if (cls == CB) {
-      *bitpos = (uint32_t)ln;
-      return state + L.b_off + ((uint64_t)pos << L.b_shift) + t * 8u;
+      *bitpos = ln;
+      return r;
     }
-    return state + L.nb_off + t * L.tile_bytes + ((uint64_t)pos + 8u * limb) * 64u +
-           ln * (cls == CW ? 4u : 8u);
+    return r + ln * (cls == CW ? 4u : 8u);
   }
-  char* s = state + (uint64_t)inst * L.pitch;
+  char* r = state + (uint64_t)inst * L.pitch + row * 8u;
   if (cls == CB) {
-    *bitpos = pos & 63u;
-    return s + L.b_off + (uint64_t)(pos >> 6) * 8u;
+    *bitpos = f & 63u;
+    return r;
   }
-  return s + L.nb_off + pos + 8u * limb;
+  return r + ((f & 63u) >> 3);
 }
 
 __global__ void k_pack(bool sweep, StateLayout L, const char* state, const SlotRef* refs,
@@ -626,30 +646,56 @@ hipError_t launch_resident_multi(const ResJob* jobs, const uint2* map, uint32_t 
   return dispatch_res<ResMany>(lds_state, lds_ops, unroll, jobs, map, n_blocks, block, lds, s);
 }
 
-hipError_t launch_sweep_layer(const Program& p, const StateLayout& L, char* state,
-                              const uint64_t* seeds, DevCtl* ctl, uint32_t n_inst,
-                              uint32_t layer, uint32_t layer_ops, uint32_t ops_per_wave,
-                              uint32_t unroll, uint32_t tiles_per_wave, hipStream_t s) {
-  if (layer_ops == 0) return hipSuccess;
-  const uint32_t tg = tiles_per_wave == 4 ? 4u : tiles_per_wave == 2 ? 2u : 1u;
-  const uint64_t chunks = (layer_ops + ops_per_wave - 1) / ops_per_wave;
-  const uint64_t waves = chunks * ((L.n_tiles + tg - 1) / tg);
+hipError_t launch_sweep_light(const Program& p, const StateLayout& L, char* state, uint32_t layer,
+                              const DevLayer& ly, uint32_t ops_per_wave, uint32_t unroll,
+                              uint32_t tiles_per_wave, hipStream_t s) {
+  const uint32_t n1 = ly.hbeg - ly.begin, n2 = ly.end - ly.hend;
+  if (n1 + n2 == 0) return hipSuccess;
+  const uint32_t tg = tiles_per_wave == 8 ? 8u : tiles_per_wave == 4 ? 4u
+                    : tiles_per_wave == 2 ? 2u : 1u;
+  if (ops_per_wave == 0 || L.n_tiles_alloc % tg != 0) return hipErrorInvalidValue;
+  const uint32_t split = (n1 + ops_per_wave - 1) / ops_per_wave;
+  const uint64_t chunks = split + (n2 + ops_per_wave - 1) / ops_per_wave;
+  const uint64_t waves = chunks * (L.n_tiles_alloc / tg);
   const dim3 grid((uint32_t)((waves + 3) / 4)), blk(256);
-  const DevCtl* c = ctl;
-#define RTEAAL_SWEEP(UU, GG)                                                                   \
-  hipLaunchKernelGGL((k_sweep<UU, GG>), grid, blk, 0, s, p.ops, p.layers, p.const_limbs,      \
-                     p.words_per_inst, L, state, seeds, c, n_inst, layer, ops_per_wave)
-  // unroll x tiles_per_wave is at most 4: larger products run out of
+#define RTEAAL_SWEEP(UU, GG)                                                             \
+  hipLaunchKernelGGL((k_sweep<UU, GG>), grid, blk, 0, s, p.ops, p.layers, L, state, layer, \
+                     ops_per_wave, split)
+  // unroll x tiles_per_wave is at most 8: larger products run out of
   // registers and spill to scratch.
   switch (tg * 8 + unroll) {
     case 8 + 1: RTEAAL_SWEEP(1, 1); break;
     case 8 + 4: RTEAAL_SWEEP(4, 1); break;
     case 16 + 1: RTEAAL_SWEEP(1, 2); break;
     case 16 + 2: RTEAAL_SWEEP(2, 2); break;
+    case 16 + 4: RTEAAL_SWEEP(4, 2); break;
     case 32 + 1: RTEAAL_SWEEP(1, 4); break;
+    case 32 + 2: RTEAAL_SWEEP(2, 4); break;
+    case 64 + 1: RTEAAL_SWEEP(1, 8); break;
     default: RTEAAL_SWEEP(2, 1); break;
   }
 #undef RTEAAL_SWEEP
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_heavy(const Program& p, const StateLayout& L, char* state,
+                              const uint64_t* seeds, const DevCtl* ctl, uint32_t n_inst,
+                              uint32_t layer, const DevLayer& ly, uint32_t ops_per_wave,
+                              uint32_t tiles_per_wave, hipStream_t s) {
+  const uint32_t n = ly.hend - ly.hbeg;
+  if (n == 0) return hipSuccess;
+  const uint32_t tg = tiles_per_wave >= 4 ? 4u : tiles_per_wave == 2 ? 2u : 1u;
+  if (ops_per_wave == 0 || L.n_tiles_alloc % tg != 0) return hipErrorInvalidValue;
+  const uint64_t chunks = (n + ops_per_wave - 1) / ops_per_wave;
+  const uint64_t waves = chunks * (L.n_tiles_alloc / tg);
+  const dim3 grid((uint32_t)((waves + 3) / 4)), blk(256);
+#define RTEAAL_HEAVY(GG)                                                                     \
+  hipLaunchKernelGGL((k_sweep_heavy<GG>), grid, blk, 0, s, p.ops, p.layers, p.const_limbs,   \
+                     p.words_per_inst, L, state, seeds, ctl, n_inst, layer, ops_per_wave)
+  if (tg == 4) RTEAAL_HEAVY(4);
+  else if (tg == 2) RTEAAL_HEAVY(2);
+  else RTEAAL_HEAVY(1);
+#undef RTEAAL_HEAVY
   return hipGetLastError();
 }
 

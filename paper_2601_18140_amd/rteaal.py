@@ -386,11 +386,12 @@ def rteaal_autotune(ctx, design_id, n_instances, trial_cycles=0):
 
 
 def rteaal_kernel_timing(ctx, batch_id, enable):
-    """(launches, total kernel ms) recorded since the previous call; then sets recording."""
-    n, ms = C.c_uint64(), C.c_double()
+    """((main launches, main ms), (heavy launches, heavy ms)) recorded since the
+    previous call; then sets recording."""
+    n, ms = (C.c_uint64 * 2)(), (C.c_double * 2)()
     _check(ctx.handle, library().rteaal_kernel_timing(ctx.handle, int(batch_id), int(bool(enable)),
-                                                      C.byref(n), C.byref(ms)))
-    return n.value, ms.value
+                                                      n, ms))
+    return (n[0], ms[0]), (n[1], ms[1])
 
 
 # ---------------------------------------------------------------------------

@@ -119,7 +119,7 @@ def test_resident_hbm_state_and_block_sizes(ctx, mapping):
             assert_same(regs, ref, f"ops_per_wave={opw}")
 
 
-SWEEP_SHAPES = [(1, 1), (2, 1), (4, 1), (1, 2), (2, 2), (1, 4)]   # (unroll, tiles_per_wave)
+SWEEP_SHAPES = [(1, 1), (2, 1), (4, 1), (1, 2), (2, 2), (4, 2), (1, 4), (2, 4), (1, 8)]  # (unroll, tiles_per_wave)
 
 
 @pytest.mark.parametrize("cfg", SMALL[:2], ids=[c.name for c in SMALL[:2]])
@@ -144,7 +144,7 @@ def test_sweep_rejects_oversized_shape(ctx):
     try:
         with pytest.raises(R.RteaalError):
             R.rteaal_create_batch(ctx, did, np.arange(70, dtype=np.uint64),
-                                  mapping=R.RTEAAL_MAP_SWEEP, unroll=4, tiles_per_wave=2)
+                                  mapping=R.RTEAAL_MAP_SWEEP, unroll=4, tiles_per_wave=4)
     finally:
         R.rteaal_unload_design(ctx, did)
 

@@ -12,6 +12,7 @@ inputs (design, state, seeds) are resident on the device before timing.
     python bench.py [--steps K] [--warmup W] [--workload NAME]
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -29,14 +30,13 @@ METRIC = "instance-cycles/s (batched vs plain) + % HBM/LDS roofline, bit-exact"
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E
 LDS_PEAK_GBS = 256 * 128 * 2.4        # 256 CUs x 128 B/clk x 2.4 GHz = 78,643 GB/s
 
-# Workloads: design recipe, batched instance count, default cycles per step.
+# Workloads: design recipe, batched instance count, default cycles per step
+# and default number of timed steps (a bounded sample of the workload's run:
+# the rate is steady from the first cycles on).
 WORKLOADS = {
-    "single-200k": dict(cfg=rtlgen.CFG1, seed=1, instances=1024, cycles_per_step=10_000,
-                        total_cycles=100_000),
-    "plain-2k": dict(cfg=rtlgen.CFG0, seed=0, instances=1, cycles_per_step=10_000,
-                     total_cycles=10_000),
-    "large-5m": dict(cfg=rtlgen.CFG3, seed=3, instances=4096, cycles_per_step=20,
-                     total_cycles=10_000),
+    "large-5m": dict(cfg=rtlgen.CFG3, seed=3, instances=4096, cycles_per_step=20, steps=10),
+    "single-200k": dict(cfg=rtlgen.CFG1, seed=1, instances=1024, cycles_per_step=1000, steps=10),
+    "plain-2k": dict(cfg=rtlgen.CFG0, seed=0, instances=1, cycles_per_step=10_000, steps=1),
 }
 
 
@@ -92,6 +92,34 @@ def algorithmic_bytes(d):
     return out
 
 
+def kernel_sources_sha256():
+    """Hash of the device code (kernels and the record encoding they read)."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2601_18140_amd", "csrc")
+    for f in ("internal.h", "kernels.hip", "ops_device.h"):   # device code and its encoding
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(role, workload, opts):
+    """HBM bytes per launch of kernel `role` from the committed rocprofv3
+    counter record (FETCH_SIZE and WRITE_SIZE runs, scaled by the copy
+    calibration), or None when no record matches this workload and launch
+    shape or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not opts or not os.path.exists(path):
+        return None
+    key = (f"{role}|{workload}|sweep/opw{opts['ops_per_wave']}/u{opts['unroll']}"
+           f"/tg{opts['tiles_per_wave']}")
+    with open(path) as fh:
+        rec = json.load(fh).get(key)
+    if rec is None or rec["source_sha256"] != kernel_sources_sha256():
+        return None
+    return float(rec["bytes_per_launch"])
+
+
 def cpu_baseline(d, seeds, cycles):
     import oracle
     threads = min(16, os.cpu_count() or 1, len(seeds))
@@ -104,15 +132,18 @@ def cpu_baseline(d, seeds, cycles):
                       f"{dt:.1f} s wall on {threads} host threads"}
 
 
-def parity_sample(R, ctx, did, d, seeds, mapping, cycles=3):
-    """Fresh batch, a few cycles, two instances against the oracle."""
+def parity_sample(R, ctx, bid, d, seeds, cycles=3):
+    """The measured batch itself, a few cycles from reset, four instances
+    against the oracle; the batch is then put back to cycle 0 with all
+    registers zero (rteaal_write_state), the state it was created in."""
     import oracle
-    bid = R.rteaal_create_batch(ctx, did, seeds, mapping=mapping)
+    n = len(seeds)
+    pick = sorted({0, n // 3, (2 * n) // 3, n - 1})
     R.rteaal_step(ctx, bid, cycles)
-    pick = [0, len(seeds) - 1]
     got = R.unpack_limbs(R.rteaal_read_state(ctx, bid), d.slot_width[d.reg_slot])[pick]
-    R.rteaal_free_batch(ctx, bid)
-    ref, _, _ = oracle.run(d, np.asarray(seeds)[pick], cycles)
+    ref, _, _ = oracle.run(d, np.asarray(seeds)[pick], cycles, n_threads=len(pick))
+    words = int(((d.slot_width[d.reg_slot].astype(np.int64) + 63) // 64).sum())
+    R.rteaal_write_state(ctx, bid, 0, np.zeros((n, words), dtype=np.uint64), 0)
     return bool(np.array_equal(got, ref))
 
 
@@ -230,7 +261,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="single-200k",
+    ap.add_argument("--workload", default="large-5m",
                     choices=sorted(WORKLOADS) + ["multi-64", "serving"])
     ap.add_argument("--designs", type=int, default=None)
     ap.add_argument("--serving-jobs", type=int, default=200)
@@ -290,7 +321,7 @@ def main():
     wl = WORKLOADS[args.workload]
     n_inst = args.instances or wl["instances"]
     cps = args.cycles_per_step or wl["cycles_per_step"]
-    steps = args.steps if args.steps is not None else max(1, wl["total_cycles"] // cps)
+    steps = args.steps if args.steps is not None else wl["steps"]
     mapping = {"auto": R.RTEAAL_MAP_AUTO, "resident": R.RTEAAL_MAP_RESIDENT,
                "sweep": R.RTEAAL_MAP_SWEEP}[args.mapping]
 
@@ -306,9 +337,6 @@ def main():
     stream = ctx.stream
     did = R.rteaal_load_design(ctx, d)
 
-    ok = parity_sample(R, ctx, did, d, seeds, mapping)
-    print(f"[bench] parity sample vs oracle: {ok}", file=sys.stderr, flush=True)
-
     manual = (args.mapping != "auto" or args.block or args.ops_per_wave or args.unroll
               or args.tiles_per_wave)
     tuned = None
@@ -321,6 +349,9 @@ def main():
                                 ops_per_wave=args.ops_per_wave, unroll=args.unroll,
                                 tiles_per_wave=args.tiles_per_wave)
     used_map, _ = R.rteaal_batch_info(ctx, bid)
+    bopts = R.rteaal_batch_options(ctx, bid)
+    ok = parity_sample(R, ctx, bid, d, seeds)
+    print(f"[bench] parity sample vs oracle: {ok}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         R.rteaal_step(ctx, bid, cps)
     R.rteaal_sync(ctx)
@@ -359,20 +390,26 @@ def main():
         bound, peak = "lds", LDS_PEAK_GBS
         per_launch = X * n_inst * prof_cycles / max(launches, 1)
     achieved = per_launch / (avg_ms / 1e3) / 1e9
+    traffic = (measured_traffic("k_sweep", args.workload, bopts)
+               if used_map == R.RTEAAL_MAP_SWEEP else None)
     roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": round(peak, 1),
-                "unit": "GB/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": "k_sweep" if used_map == R.RTEAAL_MAP_SWEEP else "k_resident",
                 "launches": launches, "avg_launch_ms": round(avg_ms, 5),
                 "bytes_per_launch": round(per_launch, 1),
                 "algorithmic_bytes_per_instance_cycle": round(X, 1),
                 "graph_bytes_per_cycle": round(G, 1)}
+    if traffic:
+        roofline["traffic_over_algorithmic"] = round(traffic / per_launch, 3)
+        roofline["traffic_GBps"] = round(traffic / (avg_ms / 1e3) / 1e9, 2)
     if h_launches:
         h_avg = h_kms / h_launches
         h_bytes = (AB["x_heavy"] * n_inst + AB["g_heavy"]) * prof_cycles / h_launches
+        h_traffic = measured_traffic("k_sweep_heavy", args.workload, bopts)
         roofline["heavy_kernel"] = {
             "kernel": "k_sweep_heavy", "launches": h_launches, "avg_launch_ms": round(h_avg, 5),
             "bytes_per_launch": round(h_bytes, 1),
-            "achieved": round(h_bytes / (h_avg / 1e3) / 1e9, 2),
+            "achieved": round(h_bytes / (h_avg / 1e3) / 1e9, 2), "traffic": h_traffic,
             "share_of_kernel_time": round(h_kms / (h_kms + kms), 4)}
     R.rteaal_free_batch(ctx, bid)
 
@@ -417,7 +454,7 @@ def main():
                    "registers": d.n_regs, "inputs": d.n_inputs, "instances": n_inst,
                    "cycles_per_step": cps,
                    "mapping": "sweep" if used_map == R.RTEAAL_MAP_SWEEP else "resident",
-                   "opts": tuned,
+                   "opts": bopts,
                    "design_fingerprint": d.fingerprint()},
         "plain": plain,
         "batched_over_plain": round(value / plain["value"], 2) if plain else None,

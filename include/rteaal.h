@@ -199,6 +199,12 @@ rteaal_status rteaal_free_batch(rteaal_ctx* ctx, rteaal_batch_id batch);
 rteaal_status rteaal_batch_info(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t* mapping,
                                 uint64_t* cycle);
 
+/* The launch shape a batch resolved to (defaults, autotuned entry or caller
+ * options), written to *out: mapping, and for RESIDENT block_threads,
+ * lds_state/lds_ops (1 = in LDS, 0 = in HBM), unroll; for SWEEP
+ * ops_per_wave, unroll, tiles_per_wave (other fields 0). */
+rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id batch, rteaal_batch_opts* out);
+
 /* ------------------------------------------------------------------------ */
 /* Stepping                                                                 */
 /* ------------------------------------------------------------------------ */

@@ -939,6 +939,25 @@ rteaal_status rteaal_batch_info(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t* m
   return RTEAAL_OK;
 }
 
+rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id id, rteaal_batch_opts* out) {
+  if (!ctx || !out) return fail(ctx, RTEAAL_E_INVALID_ARG, "null argument");
+  Batch* b = find_batch(ctx, id);
+  if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
+  rteaal_batch_opts o{};
+  o.mapping = b->mapping;
+  o.unroll = b->unroll;
+  if (b->mapping == RTEAAL_MAP_RESIDENT) {
+    o.block_threads = b->block;
+    o.lds_state = b->lds ? 1u : 0u;
+    o.lds_ops = b->lds_ops ? 1u : 0u;
+  } else {
+    o.ops_per_wave = b->opw;
+    o.tiles_per_wave = b->tg;
+  }
+  *out = o;
+  return RTEAAL_OK;
+}
+
 rteaal_status rteaal_step(rteaal_ctx* ctx, rteaal_batch_id id, uint64_t n_cycles,
                           const rteaal_stimulus* stim) {
   if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");

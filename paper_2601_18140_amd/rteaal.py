@@ -22,6 +22,7 @@ __all__ = [
     "exported_symbols", "rteaal_create", "rteaal_destroy", "rteaal_last_error",
     "rteaal_validate_design", "rteaal_load_design", "rteaal_unload_design", "rteaal_design_format",
     "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch", "rteaal_batch_info",
+    "rteaal_batch_options",
     "rteaal_step", "rteaal_step_many", "rteaal_sync", "rteaal_read_state", "rteaal_write_state",
     "rteaal_kernel_timing", "rteaal_autotune", "opts_dict", "unpack_limbs", "pack_limbs", "rteaal_layer_format", "rteaal_rank_format",
 ]
@@ -108,6 +109,7 @@ def library():
         "rteaal_create_batch": ([vp, u32, u32, vp, C.POINTER(rteaal_batch_opts), C.POINTER(u32)], st),
         "rteaal_free_batch": ([vp, u32], st),
         "rteaal_batch_info": ([vp, u32, C.POINTER(u32), C.POINTER(u64)], st),
+        "rteaal_batch_options": ([vp, u32, C.POINTER(rteaal_batch_opts)], st),
         "rteaal_step": ([vp, u32, u64, C.POINTER(rteaal_stimulus)], st),
         "rteaal_step_many": ([vp, u32, vp, vp], st),
         "rteaal_sync": ([vp], st),
@@ -128,7 +130,7 @@ def exported_symbols():
     return ["rteaal_create", "rteaal_destroy", "rteaal_last_error", "rteaal_validate_design",
             "rteaal_load_design", "rteaal_unload_design", "rteaal_design_format",
             "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch",
-            "rteaal_batch_info", "rteaal_step", "rteaal_step_many", "rteaal_sync",
+            "rteaal_batch_info", "rteaal_batch_options", "rteaal_step", "rteaal_step_many", "rteaal_sync",
             "rteaal_read_state", "rteaal_write_state", "rteaal_kernel_timing", "rteaal_autotune"]
 
 
@@ -321,6 +323,13 @@ def rteaal_batch_info(ctx, batch_id):
     m, c = C.c_uint32(), C.c_uint64()
     _check(ctx.handle, library().rteaal_batch_info(ctx.handle, int(batch_id), C.byref(m), C.byref(c)))
     return m.value, c.value
+
+
+def rteaal_batch_options(ctx, batch_id):
+    """The launch shape the batch resolved to, as a dict."""
+    o = rteaal_batch_opts()
+    _check(ctx.handle, library().rteaal_batch_options(ctx.handle, int(batch_id), C.byref(o)))
+    return opts_dict(o)
 
 
 def rteaal_step(ctx, batch_id, n_cycles, words=None, words_on_device=False):

@@ -163,8 +163,10 @@ def bench_multi(args, R, torch):
     t0 = time.perf_counter()
     for k, (did, (cfg, seed, n)) in enumerate(zip(dids, plan)):
         if not args.no_autotune:
-            o, _ = R.rteaal_autotune(ctx, did, n, trial_cycles=2)
+            o, r = R.rteaal_autotune(ctx, did, n, trial_cycles=2)
             tuned.append(o)
+            print(f"[bench] design {k}: {cfg.n_ops} ops x {n} instances -> {o} ({r:.4g})",
+                  file=sys.stderr, flush=True)
         bids.append(R.rteaal_create_batch(ctx, did, rtlgen.instance_seeds(n, design_index=k)))
     print(f"[bench] batches created (autotune {time.perf_counter() - t0:.1f}s)", file=sys.stderr,
           flush=True)
@@ -225,7 +227,8 @@ def bench_serving(args, R, torch):
     jobs = [serving.Job(job_id=k, design=d, n_inst=n, n_cycles=c) for k, (d, n, c) in enumerate(spec)]
     arrivals = serving.poisson_arrivals(args.serving_rate, n_jobs, seed=4)
     ctx = R.rteaal_create(0)
-    srv = serving.Server(ctx, pool, budget_bytes=int(args.serving_budget_gb * (1 << 30)))
+    srv = serving.Server(ctx, pool, budget_bytes=int(args.serving_budget_gb * (1 << 30)),
+                         log=lambda m: print(f"[serve] {m}", file=sys.stderr, flush=True))
     stats = srv.run(jobs, arrivals, duration=args.serving_seconds)
     srv.close()
     # Each finished job, re-run alone: identical registers.

@@ -43,7 +43,7 @@ class Server:
     """pool: list of rtlgen.Design; budget_bytes: device memory the loop may use."""
 
     def __init__(self, ctx, pool, budget_bytes, tick_seconds=0.05, chunk_cycles=None,
-                 max_chunk=4096):
+                 max_chunk=4096, log=None):
         self.ctx = ctx
         self.pool = pool
         self.budget = int(budget_bytes)
@@ -59,6 +59,7 @@ class Server:
         self.used = 0
         self.rate = {}                         # (design, n_inst) -> observed cycles/s per batch
         self.instance_cycles = 0
+        self.log = log                         # optional callable(str) for admit/retire events
 
     # ---- admission ---------------------------------------------------------
     def _design_bytes(self, k):
@@ -98,6 +99,9 @@ class Server:
             self.users[job.design] += 1
             self.running.append(job)
             admitted.append(job)
+            if self.log:
+                self.log(f"admit job {job.job_id}: design {job.design}, {job.n_inst} instances, "
+                         f"{job.n_cycles} cycles, {fp} bytes, {len(self.running)} running")
         return admitted
 
     # ---- one tick ----------------------------------------------------------
@@ -136,6 +140,9 @@ class Server:
             self.users[j.design] -= 1
             self.running.remove(j)
             self.finished.append(j)
+            if self.log:
+                self.log(f"done job {j.job_id}: latency {j.finished - j.arrival:.2f} s, "
+                         f"{len(self.finished)} finished, {len(self.queue)} queued")
         return len(done)
 
     def drain(self):

@@ -86,13 +86,15 @@ struct DevCtl {
 // these fields, so one record format serves both mappings:
 //   RESIDENT, instance j at j*pitch: row r at 8r; the value is the row's
 //     word shifted down by `shift` (then cut to the class).
-//   SWEEP, tile t = j / 64, lane = j % 64: rows are interleaved over tiles,
-//     row r of tile t is the 512 bytes at r*row_bytes + t*512 (row_bytes =
-//     512 * allocated tiles).  Inside, a 1-bit row is 64 bit-sliced words
-//     (bit index k at 8k, bit `lane` of the word is the instance's value); a
-//     wide row holds the 64 lanes' values: 32-bit at 8*shift + 4*lane, others
-//     at 8*lane.  The byte address of slot f for tile t is thus
-//     (f / 64) * row_bytes + 8 * (f % 64) + 512 * t, plus the lane's part.
+//   SWEEP, tile t = j / 64, lane = j % 64 (T = allocated tiles, row_bytes =
+//     512 T, so the 1-bit rows take the same bytes as in a per-tile layout):
+//     1-bit slot i: the bit-sliced word (bit `lane` = the instance's value)
+//       at 8 (i T + t): slot-major, the words of consecutive tiles adjacent;
+//     wide row r: interleaved over tiles, tile t's 512 bytes at
+//       r row_bytes + 512 t holding the 64 lanes' values, 32-bit ones at
+//       8 shift + 4 lane, the others at 8 lane.  The byte address of a wide
+//       slot f for tile t is thus (f / 64) row_bytes + 8 (f % 64) + 512 t,
+//       plus the lane's part.
 struct StateLayout {
   uint64_t pitch;          // RESIDENT: bytes per instance (multiple of 16)
   uint32_t row_bytes;      // SWEEP: bytes of one row over all allocated tiles

@@ -233,33 +233,51 @@ k_resident_multi(const ResJob* __restrict__ jobs, const uint2* __restrict__ map)
 }
 
 // ---------------------------------------------------------------------------
-// SWEEP: lane = instance.  A wavefront owns TG consecutive tiles.  The row of
-// a slot is found once per operation (scalar arithmetic on the record's
-// field) and the wavefront's tiles sit at fixed 512-byte steps from it, so
-// per tile only the load or store offset changes.
+// SWEEP: lane = instance.  A wavefront owns TG consecutive tiles.
+//  * 1-bit slots are slot-major: the TG words of slot i for the wavefront's
+//    tiles are contiguous, so one scalar load brings them all in, and the
+//    results of a 1-bit destination leave as one TG-lane store.
+//  * Wide rows are tile-interleaved: the row address is found once per
+//    operation (scalar arithmetic on the record's field) and the wavefront's
+//    tiles sit at fixed 512-byte steps from it, so per tile only the load or
+//    store immediate changes.
 // ---------------------------------------------------------------------------
 struct SweepView {
-  char* base;          // state + 512 * (first tile of the wavefront)
-  uint32_t row_bytes;  // bytes of one row over all allocated tiles
+  char* base;          // state + 512 * (first tile): wide rows
+  char* bits;          // state + 8 * (first tile): 1-bit words
+  uint32_t row_bytes;  // bytes of one wide row over all allocated tiles
+  uint32_t nta;        // allocated tiles (words per 1-bit slot)
   uint32_t lane;
 
-  // Row of slot field f in the wavefront's first tile (1-bit slots: their
-  // bit-sliced word; others: the start of the 64 lane values).
+  __device__ __forceinline__ SweepView(char* state, const StateLayout& L, uint32_t tile0,
+                                       uint32_t ln)
+      : base(state + (uint64_t)tile0 * 512u), bits(state + (uint64_t)tile0 * 8u),
+        row_bytes(L.row_bytes), nta(L.n_tiles_alloc), lane(ln) {}
+
+  // Start of the 64 lane values of wide slot f in the wavefront's first tile.
   __device__ __forceinline__ char* row(uint32_t f) const {
     return base + (uint64_t)(f >> 6) * row_bytes + ((f & 63u) << 3);
   }
-  // This lane's offset for an 8-byte operand load: 0 for CB (one word for the
-  // whole wavefront), the aligned word holding this lane's value for CW
-  // (lanes 2k and 2k+1 share it, so a row is read exactly once), and the
-  // lane's own value otherwise.
+  // Word of 1-bit slot i for the wavefront's first tile (the next TG-1 tiles
+  // follow it).
+  __device__ __forceinline__ uint64_t word_off(uint32_t i) const { return (uint64_t)i * nta * 8u; }
+  // Operand gather without branches: one 8-byte load per tile from
+  // base + this lane's offset + g * step.
+  //   CB: base = the slot's word for the first tile, step 8, offset 0 (one
+  //       word for the whole wavefront; the TG words are contiguous);
+  //   CW: base = the row, step 512, offset = the aligned word holding this
+  //       lane's value (lanes 2k and 2k+1 share it, so a row is read once);
+  //   others: base = the row, step 512, offset = the lane's own value.
+  __device__ __forceinline__ const char* gather_base(uint32_t cls, uint32_t f) const {
+    return cls == CB ? bits + word_off(f) : (const char*)row(f);
+  }
   __device__ __forceinline__ uint32_t ld_off(uint32_t cls) const {
-    // (lane << 3) for 64-bit classes, (lane << 2) & ~7 for CW, 0 for CB,
-    // written as one shift and one mask so that no branch is taken.
     const uint32_t w = cls == CW ? 1u : 0u;
     const uint32_t mask = (cls == CB ? 0u : ~0u) & ~(w * 7u);
     return (lane << (3u - w)) & mask;
   }
-  // The operand's value in this lane from the loaded word.
+  // The operand's value in this lane from its loaded word (CB: the
+  // wavefront's bit-sliced word).
   __device__ __forceinline__ uint32_t lane_val32(uint32_t cls, uint64_t raw) const {
     const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
     return cls == CB ? (uint32_t)((raw >> lane) & 1ull) : (lane & 1u) ? hi : lo;
@@ -268,8 +286,16 @@ struct SweepView {
     return cls == CB ? (raw >> lane) & 1ull
          : cls == CW ? (raw >> ((lane & 1u) * 32u)) & 0xffffffffull : raw;
   }
-  __device__ __forceinline__ void st_word(char* r, uint32_t g, uint64_t w) const {
-    *(uint64_t*)(r + g * 512u) = w;
+  // 1-bit results of the TG tiles (wave-uniform words): lane g stores tile g's
+  // word, one contiguous store for the wavefront.  The word is picked with
+  // masks rather than a select chain, which the compiler would turn into an
+  // indexed (scratch) array.
+  template <int TG>
+  __device__ __forceinline__ void st_bits(uint32_t i, const uint64_t* m) const {
+    uint64_t mine = 0;
+#pragma unroll
+    for (int g = 0; g < TG; ++g) mine |= m[g] & (0ull - (uint64_t)(lane == (uint32_t)g));
+    if (lane < (uint32_t)TG) *(uint64_t*)(bits + word_off(i) + lane * 8u) = mine;
   }
   __device__ __forceinline__ void st32(char* r, uint32_t g, uint32_t x) const {
     *(uint32_t*)(r + g * 512u + lane * 4u) = x;
@@ -278,9 +304,9 @@ struct SweepView {
     if (cls == CW) st32(r, g, (uint32_t)x);
     else *(uint64_t*)(r + g * 512u + lane * 8u) = x;
   }
-  __device__ __forceinline__ V4 ldv(uint32_t cls, const char* r, uint32_t g) const {
-    const char* q = r + g * 512u;
-    if (cls == CB) return v4_from((*(const uint64_t*)q >> lane) & 1ull);
+  __device__ __forceinline__ V4 ldv(uint32_t cls, uint32_t f, uint32_t g) const {
+    if (cls == CB) return v4_from((*(const uint64_t*)(bits + word_off(f) + g * 8u) >> lane) & 1ull);
+    const char* q = row(f) + g * 512u;
     if (cls == CW) return v4_from(*(const uint32_t*)(q + lane * 4u));
     q += lane * 8u;
     const uint32_t k = cls_limbs(cls);
@@ -290,7 +316,8 @@ struct SweepView {
     if (k > 3) x.l[3] = *(const uint64_t*)(q + 3ull * row_bytes);
     return x;
   }
-  __device__ __forceinline__ void stv(uint32_t cls, char* r, uint32_t g, const V4& x) const {
+  __device__ __forceinline__ void stv(uint32_t cls, uint32_t f, uint32_t g, const V4& x) const {
+    char* r = row(f);
     if (cls == CW) {
       st32(r, g, (uint32_t)x.l[0]);
       return;
@@ -307,12 +334,13 @@ struct SweepView {
 // Common operations of one layer (every value at most 64 bits, no source).
 // A wavefront handles a chunk of operations for TG tiles (64 instances each).
 // Operations are processed U at a time: first the U records (scalar loads,
-// decoded once for all TG tiles), then every operand row for every tile, then
-// the evaluations and stores, so 3*U*TG gathers are in flight per wavefront
-// and the type dispatch is paid once per operation.  Tiles past the last
-// instance (allocation padding up to a multiple of TG) are evaluated like the
-// others and never read back.  The layer's common operations are the ranges
-// [begin, hbeg) and [hend, end); the first `split` chunks cover the first.
+// decoded once for all TG tiles), then every operand (1-bit: one scalar load
+// of the TG words; wider: TG vector loads), then the evaluations and stores.
+// Tiles past the last instance (allocation padding up to a multiple of TG)
+// are evaluated like the others and never read back.  The layer's common
+// operations are the ranges [begin, hbeg) and [hend, end); the first `split`
+// chunks cover the first.
+//
 template <int U, int TG>
 __global__ void __launch_bounds__(256)
 k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers, StateLayout L,
@@ -329,35 +357,35 @@ k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers, Stat
   if (o0 >= oe) return;
   const uint32_t o1 = min(o0 + opw, oe);
   const uint32_t tile0 = grp * TG;
-  const SweepView v{state + (uint64_t)tile0 * 512u, L.row_bytes, lane};
+  const SweepView v(state, L, tile0, lane);
 
   for (uint32_t o = o0; o < o1; o += U) {
     DevOp op[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) op[u] = ops[min(o + (uint32_t)u, o1 - 1u)];
-    uint64_t ra[U][TG], rb[U][TG], rc[U][TG];
+    uint64_t raw[U][3][TG];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t code = op[u].code;
-      const char* pa = v.row(op[u].src[0]) + v.ld_off(op_scls(code, 0));
-      const char* pb = v.row(op[u].src[1]) + v.ld_off(op_scls(code, 1));
-      const char* pc = v.row(op[u].src[2]) + v.ld_off(op_scls(code, 2));
 #pragma unroll
-      for (int g = 0; g < TG; ++g) {
-        ra[u][g] = *(const uint64_t*)(pa + g * 512);
-        rb[u][g] = *(const uint64_t*)(pb + g * 512);
-        rc[u][g] = *(const uint64_t*)(pc + g * 512);
+      for (int k = 0; k < 3; ++k) {
+        const uint32_t cls = op_scls(code, k);
+        const char* p = v.gather_base(cls, op[u].src[k]) + v.ld_off(cls);
+        const uint32_t step = cls == CB ? 8u : 512u;
+#pragma unroll
+        for (int g = 0; g < TG; ++g) raw[u][k][g] = *(const uint64_t*)(p + g * step);
       }
     }
     // Every gathered word counts as used on every path (unary operators,
-    // absent operands, wide and source operations ignore some of them), so
-    // that no load is still in flight when the next group's loads reuse its
-    // registers: otherwise the top of the loop would also wait for this
-    // group's stores.
+    // absent operands ignore some of them), so that no load is still in
+    // flight when the next group's loads reuse its registers: otherwise the
+    // top of the loop would also wait for this group's stores.
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int g = 0; g < TG; ++g) asm volatile("" ::"v"(ra[u][g]), "v"(rb[u][g]), "v"(rc[u][g]));
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int g = 0; g < TG; ++g) asm volatile("" ::"v"(raw[u][k][g]));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (o + u < o1) {
@@ -365,44 +393,49 @@ k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers, Stat
         const uint32_t code = q.code, opc = op_opc(code), ar = op_arity(code), kind = op_kind(code);
         const uint32_t dc = op_dcls(code), w = op_width(q.wimm), imm = op_imm(q.wimm);
         const uint32_t c0 = op_scls(code, 0), c1 = op_scls(code, 1), c2 = op_scls(code, 2);
-        char* rd = v.row(q.dst);
-        if (kind == K_U32) {
+        if (kind == K_BIT) {
+          uint64_t m[TG];
+#pragma unroll
+          for (int g = 0; g < TG; ++g)
+            m[g] = eval_bits(opc, ar, raw[u][0][g], raw[u][1][g], raw[u][2][g], imm);
+          v.st_bits<TG>(q.dst, m);
+        } else if (kind == K_U32) {
           uint32_t a[TG], b[TG], c[TG], r[TG];
 #pragma unroll
           for (int g = 0; g < TG; ++g) {
-            a[g] = v.lane_val32(c0, ra[u][g]);
-            b[g] = v.lane_val32(c1, rb[u][g]);
-            c[g] = v.lane_val32(c2, rc[u][g]);
+            a[g] = v.lane_val32(c0, raw[u][0][g]);
+            b[g] = v.lane_val32(c1, raw[u][1][g]);
+            c[g] = v.lane_val32(c2, raw[u][2][g]);
           }
           eval_u32_n<TG>(opc, ar, a, b, c, imm, w, r);
+          if (dc == CB) {
+            uint64_t m[TG];
 #pragma unroll
-          for (int g = 0; g < TG; ++g) {
-            if (dc == CB) {
-              const uint64_t m = __ballot((r[g] & 1u) != 0u);
-              if (lane == 0) v.st_word(rd, g, m);
-            } else {
-              v.st32(rd, g, r[g]);
-            }
-          }
-        } else if (kind == K_BIT) {
+            for (int g = 0; g < TG; ++g) m[g] = __ballot((r[g] & 1u) != 0u);
+            v.st_bits<TG>(q.dst, m);
+          } else {
+            char* rd = v.row(q.dst);
 #pragma unroll
-          for (int g = 0; g < TG; ++g) {
-            const uint64_t r = eval_bits(opc, ar, ra[u][g], rb[u][g], rc[u][g], imm);
-            if (lane == 0) v.st_word(rd, g, r);
+            for (int g = 0; g < TG; ++g) v.st32(rd, g, r[g]);
           }
         } else {  // K_U64
+          uint64_t r[TG];
 #pragma unroll
           for (int g = 0; g < TG; ++g) {
-            const uint64_t a = v.lane_val(c0, ra[u][g]);
-            const uint64_t b = v.lane_val(c1, rb[u][g]);
-            const uint64_t c = v.lane_val(c2, rc[u][g]);
-            const uint64_t r = eval_u64(opc, ar, a, b, c, imm, w);
-            if (dc == CB) {
-              const uint64_t m = __ballot((r & 1ull) != 0ull);
-              if (lane == 0) v.st_word(rd, g, m);
-            } else {
-              v.st64(dc, rd, g, r);
-            }
+            const uint64_t a = v.lane_val(c0, raw[u][0][g]);
+            const uint64_t b = v.lane_val(c1, raw[u][1][g]);
+            const uint64_t c = v.lane_val(c2, raw[u][2][g]);
+            r[g] = eval_u64(opc, ar, a, b, c, imm, w);
+          }
+          if (dc == CB) {
+            uint64_t m[TG];
+#pragma unroll
+            for (int g = 0; g < TG; ++g) m[g] = __ballot((r[g] & 1ull) != 0ull);
+            v.st_bits<TG>(q.dst, m);
+          } else {
+            char* rd = v.row(q.dst);
+#pragma unroll
+            for (int g = 0; g < TG; ++g) v.st64(dc, rd, g, r[g]);
           }
         }
       }
@@ -429,13 +462,13 @@ k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers
   if (o0 >= ly.hend) return;
   const uint32_t o1 = min(o0 + opw, ly.hend);
   const uint32_t tile0 = grp * TG;
-  const SweepView v{state + (uint64_t)tile0 * 512u, L.row_bytes, lane};
+  const SweepView v(state, L, tile0, lane);
 
   for (uint32_t o = o0; o < o1; ++o) {
     const DevOp q = ops[o];
     const uint32_t code = q.code, opc = op_opc(code), ar = op_arity(code);
     const uint32_t dc = op_dcls(code), w = op_width(q.wimm), imm = op_imm(q.wimm);
-    char* rd = v.row(q.dst);
+    uint64_t m[TG];
 #pragma unroll
     for (int g = 0; g < TG; ++g) {
       V4 r;
@@ -448,18 +481,15 @@ k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers
         if (inst < n_inst)
           r = source_value(const_limbs, q, seeds[inst], cycle, ctl->words, words_row, w);
       } else {
-        const V4 a = v.ldv(op_scls(code, 0), v.row(q.src[0]), g);
-        const V4 b = ar > 1 ? v.ldv(op_scls(code, 1), v.row(q.src[1]), g) : v4_from(0);
-        const V4 c = ar > 2 ? v.ldv(op_scls(code, 2), v.row(q.src[2]), g) : v4_from(0);
+        const V4 a = v.ldv(op_scls(code, 0), q.src[0], g);
+        const V4 b = ar > 1 ? v.ldv(op_scls(code, 1), q.src[1], g) : v4_from(0);
+        const V4 c = ar > 2 ? v.ldv(op_scls(code, 2), q.src[2], g) : v4_from(0);
         r = eval_wide(opc, ar, a, b, c, imm, w);
       }
-      if (dc == CB) {
-        const uint64_t m = __ballot((r.l[0] & 1ull) != 0ull);
-        if (lane == 0) v.st_word(rd, g, m);
-      } else {
-        v.stv(dc, rd, g, r);
-      }
+      if (dc == CB) m[g] = __ballot((r.l[0] & 1ull) != 0ull);
+      else v.stv(dc, q.dst, g, r);
     }
+    if (dc == CB) v.st_bits<TG>(q.dst, m);
   }
 }
 
@@ -485,12 +515,12 @@ __device__ __forceinline__ char* elem_addr(bool sweep, const StateLayout& L, cha
   const uint64_t row = (f >> 6) + limb;
   if (sweep) {
     const uint32_t t = inst >> 6, ln = inst & 63u;
-    char* r = state + row * L.row_bytes + (uint64_t)t * 512u + ((f & 63u) << 3);
     if (cls == CB) {
       *bitpos = ln;
-      return r;
+      return state + ((uint64_t)f * L.n_tiles_alloc + t) * 8u;
     }
-    return r + ln * (cls == CW ? 4u : 8u);
+    return state + row * L.row_bytes + (uint64_t)t * 512u + ((f & 63u) << 3) +
+           ln * (cls == CW ? 4u : 8u);
   }
   char* r = state + (uint64_t)inst * L.pitch + row * 8u;
   if (cls == CB) {
@@ -658,8 +688,8 @@ hipError_t launch_sweep_light(const Program& p, const StateLayout& L, char* stat
   const uint64_t chunks = split + (n2 + ops_per_wave - 1) / ops_per_wave;
   const uint64_t waves = chunks * (L.n_tiles_alloc / tg);
   const dim3 grid((uint32_t)((waves + 3) / 4)), blk(256);
-#define RTEAAL_SWEEP(UU, GG)                                                             \
-  hipLaunchKernelGGL((k_sweep<UU, GG>), grid, blk, 0, s, p.ops, p.layers, L, state, layer, \
+#define RTEAAL_SWEEP(UU, GG)                                                               \
+  hipLaunchKernelGGL((k_sweep<UU, GG>), grid, blk, 0, s, p.ops, p.layers, L, state, layer,   \
                      ops_per_wave, split)
   // unroll x tiles_per_wave is at most 8: larger products run out of
   // registers and spill to scratch.

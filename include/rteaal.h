@@ -179,6 +179,11 @@ typedef struct {
   uint32_t tiles_per_wave; /* 0 = default; SWEEP: 64-instance tiles one
                               wavefront evaluates per decoded operation: 1, 2,
                               4 or 8, with unroll x tiles_per_wave <= 8        */
+  uint32_t arity_split;    /* SWEEP: 0 = auto, 1 = never, 2 = always: run a
+                              layer's common operations as one launch per
+                              operand count (1, 2, 3), so absent operands cost
+                              no loads or registers; auto splits the layers
+                              with at least 2^20 operation x 64-instance tiles */
 } rteaal_batch_opts;
 
 /* Device bytes a batch of n_instances of `design` would allocate under
@@ -202,7 +207,7 @@ rteaal_status rteaal_batch_info(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t
 /* The launch shape a batch resolved to (defaults, autotuned entry or caller
  * options), written to *out: mapping, and for RESIDENT block_threads,
  * lds_state/lds_ops (1 = in LDS, 0 = in HBM), unroll; for SWEEP
- * ops_per_wave, unroll, tiles_per_wave (other fields 0). */
+ * ops_per_wave, unroll, tiles_per_wave, arity_split (other fields 0). */
 rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id batch, rteaal_batch_opts* out);
 
 /* ------------------------------------------------------------------------ */
@@ -258,13 +263,15 @@ rteaal_status rteaal_write_state(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_
 
 /* Autotuner: picks the mapping and launch shape for n_instances of `design`
  * on this device.  Each candidate (RESIDENT block sizes and unroll depths,
- * SWEEP operations-per-wavefront and unroll depths) runs `trial_cycles`
+ * SWEEP operations per wavefront, unroll depths and tile groups) runs `trial_cycles`
  * cycles (0 = a size-dependent default) on a temporary batch and is timed
  * with HIP events on the context's stream; candidates whose state does not
  * fit in device memory are skipped.  The fastest options are written to
  * *best (may be NULL) with their rate in instance-cycles/s in *rate (may be
  * NULL), and remembered: later rteaal_create_batch calls with mapping AUTO
- * for the same design and instance count use them.  Waits for the stream. */
+ * for the same design and instance count use them.  Waits for the stream.
+ * With the environment variable RTEAAL_AUTOTUNE_LOG set (and not "0"), every
+ * candidate's shape and rate is printed to stderr. */
 rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id design, uint32_t n_instances,
                               uint32_t trial_cycles, rteaal_batch_opts* best, double* rate);
 

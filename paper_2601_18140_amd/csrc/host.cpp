@@ -3,8 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -280,6 +282,7 @@ struct DesignHost {
   uint64_t n_rows = 0;      // 64-bit rows of one instance's state
   std::vector<DevOp> ops;
   std::vector<DevLayer> layers;
+  std::vector<std::array<OpRanges, 3>> light;  // per layer, per arity 1..3
   std::vector<uint64_t> const_limbs;
   std::vector<SlotRef> reg_refs, slot_refs;
   uint32_t reg_words = 0, slot_words = 0, words_per_inst = 0;
@@ -375,14 +378,20 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
   // Group each layer by (1-bit destination first, kind, type, class): the
   // N-rank swizzle, which also makes 1-bit destinations a prefix.  Heavy
   // operations (a value wider than 64 bits, or a source) go last among the
-  // 1-bit destinations and first among the others, so they are contiguous.
+  // 1-bit destinations and first among the others, so they are contiguous;
+  // the common operations are ordered by arity, 3-2-1 before the heavy range
+  // and 1-2-3 after it, so every arity is one range on each side.
   auto heavy = [](const EncOp& e) { return e.kind == K_WIDE || e.opc >= OP_STIM; };
+  auto rank = [&](const EncOp& e) {
+    const bool hv = heavy(e);
+    return e.dcls == CB ? (hv ? 3u : 3u - e.arity) : (hv ? 0u : e.arity);
+  };
   for (auto& lay : L)
     std::stable_sort(lay.begin(), lay.end(), [&](const EncOp& a, const EncOp& b) {
       const uint32_t ka = a.dcls != CB, kb = b.dcls != CB;
       if (ka != kb) return ka < kb;
-      const uint32_t ha = heavy(a) != (ka != 0), hb = heavy(b) != (kb != 0);
-      if (ha != hb) return ha < hb;
+      const uint32_t ra = rank(a), rb = rank(b);
+      if (ra != rb) return ra < rb;
       if (a.kind != b.kind) return a.kind < b.kind;
       if (a.opc != b.opc) return a.opc < b.opc;
       return a.dcls < b.dcls;
@@ -393,6 +402,7 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
   std::vector<uint32_t> scls(NW, CNONE), sidx(NW, 0);
   uint32_t cnt[NCLS] = {0};
   h->layers.clear();
+  h->light.clear();
   uint32_t pos = 0;
   for (auto& lay : L) {
     DevLayer dl{};
@@ -419,6 +429,26 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
     dl.hbeg = n_heavy ? first_heavy : dl.begin;
     dl.hend = dl.hbeg + n_heavy;
     h->layers.push_back(dl);
+    std::array<OpRanges, 3> ar{};
+    for (uint32_t a = 1; a <= 3; ++a) {
+      OpRanges& r = ar[a - 1];
+      r.b0 = r.e0 = dl.hbeg;
+      r.b1 = r.e1 = dl.hend;
+      bool s0 = false, s1 = false;
+      for (uint32_t i = 0; i < lay.size(); ++i) {
+        const EncOp& e = lay[i];
+        if (heavy(e) || e.arity != a) continue;
+        const uint32_t k = dl.begin + i;
+        if (k < dl.hbeg) {
+          if (!s0) r.b0 = k, s0 = true;
+          r.e0 = k + 1;
+        } else {
+          if (!s1) r.b1 = k, s1 = true;
+          r.e1 = k + 1;
+        }
+      }
+    }
+    h->light.push_back(ar);
     h->max_layer_ops = std::max<uint32_t>(h->max_layer_ops, (uint32_t)lay.size());
     pos = dl.end;
   }
@@ -493,6 +523,7 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
 // ---------------------------------------------------------------------------
 struct Batch {
   uint32_t id = 0, design = 0, n_inst = 0, mapping = 0, block = 0, opw = 0, unroll = 0, tg = 1;
+  uint32_t arity_split = 0;
   bool lds = false, lds_ops = false;
   uint64_t cycle = 0;
   StateLayout L{};
@@ -616,6 +647,25 @@ ResJob res_job(const DesignHost& h, const Batch& b, uint64_t n_cycles) {
   return J;
 }
 
+// Launches of one layer's common operations: one per operand count when the
+// layer is large enough for the extra launches to pay, else one for all.
+template <class F>
+hipError_t for_light_launches(const DesignHost& h, const Batch& b, uint32_t li, F&& launch) {
+  const DevLayer& ly = h.layers[li];
+  const uint64_t n_light = (ly.end - ly.begin) - (ly.hend - ly.hbeg);
+  if (n_light == 0) return hipSuccess;
+  const bool split = b.arity_split == 2 ||
+                     (b.arity_split == 0 && n_light * b.L.n_tiles_alloc >= (1ull << 20));
+  if (!split) return launch(OpRanges{ly.begin, ly.hbeg, ly.hend, ly.end}, 3u);
+  for (uint32_t a = 1; a <= 3; ++a) {
+    const OpRanges& r = h.light[li][a - 1];
+    if (r.e0 == r.b0 && r.e1 == r.b1) continue;
+    const hipError_t e = launch(r, a);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t n_cycles) {
   const Program p = program_of(h);
   DevCtl* ctl = (DevCtl*)b.ctl.p;
@@ -640,10 +690,11 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
     for (uint64_t c = 0; c < n_cycles; ++c) {
       for (uint32_t li = 0; li < h.layers.size(); ++li) {
         const DevLayer& ly = h.layers[li];
-        if (ly.end - ly.begin > ly.hend - ly.hbeg)
-          HIP_TRY(ctx, timed(b, ctx->stream, 0, [&] {
-                    return launch_sweep_light(p, b.L, st, li, ly, b.opw, b.unroll, b.tg, ctx->stream);
-                  }));
+        HIP_TRY(ctx, for_light_launches(h, b, li, [&](const OpRanges& r, uint32_t a) {
+                  return timed(b, ctx->stream, 0, [&] {
+                    return launch_sweep_light(p, b.L, st, r, a, b.opw, b.unroll, b.tg, ctx->stream);
+                  });
+                }));
         if (ly.hend > ly.hbeg)
           HIP_TRY(ctx, timed(b, ctx->stream, 1, [&] {
                     return launch_sweep_heavy(p, b.L, st, seeds, ctl, b.n_inst, li, ly, b.opw, b.tg,
@@ -660,7 +711,9 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
     hipError_t e = hipSuccess;
     for (uint32_t li = 0; li < h.layers.size() && e == hipSuccess; ++li) {
       const DevLayer& ly = h.layers[li];
-      e = launch_sweep_light(p, b.L, st, li, ly, b.opw, b.unroll, b.tg, ctx->stream);
+      e = for_light_launches(h, b, li, [&](const OpRanges& r, uint32_t a) {
+        return launch_sweep_light(p, b.L, st, r, a, b.opw, b.unroll, b.tg, ctx->stream);
+      });
       if (e == hipSuccess)
         e = launch_sweep_heavy(p, b.L, st, seeds, ctl, b.n_inst, li, ly, b.opw, b.tg, ctx->stream);
     }
@@ -887,6 +940,9 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
     if (tg * u > 8)
       return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP unroll x tiles_per_wave must be at most 8");
     b->tg = tg;
+    const uint32_t as = opts ? opts->arity_split : 0u;
+    if (as > 2) return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP arity_split must be 0, 1 or 2");
+    b->arity_split = as;
   }
   const uint64_t n_seed = b->mapping == RTEAAL_MAP_SWEEP ? (uint64_t)b->L.n_tiles_alloc * 64 : n_inst;
   if (!alloc_all(ctx, {{&b->state, sb}, {&b->seeds, n_seed * 8}, {&b->ctl, sizeof(DevCtl)}}))
@@ -953,6 +1009,7 @@ rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id id, rteaal_b
   } else {
     o.ops_per_wave = b->opw;
     o.tiles_per_wave = b->tg;
+    o.arity_split = b->arity_split;
   }
   *out = o;
   return RTEAAL_OK;
@@ -1205,6 +1262,8 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
   }
   std::vector<uint64_t> seeds(n_inst);
   for (uint32_t i = 0; i < n_inst; ++i) seeds[i] = i;
+  const char* log_env = std::getenv("RTEAAL_AUTOTUNE_LOG");
+  const bool log = log_env && *log_env && *log_env != '0';
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(ctx, hipEventCreate(&e0));
   HIP_TRY(ctx, hipEventCreate(&e1));
@@ -1232,6 +1291,9 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
     }
     if (st != RTEAAL_OK) break;
     const double r = (double)n_inst * (double)cyc / (std::max(ms, 1e-3f) * 1e-3);
+    if (log)
+      std::fprintf(stderr, "rteaal_autotune: mapping %u block %u ops/wave %u unroll %u tiles %u -> %.4g\n",
+                   o.mapping, o.block_threads, o.ops_per_wave, o.unroll, o.tiles_per_wave, r);
     if (r > best_rate) {
       best_rate = r;
       best_o = o;

@@ -66,6 +66,14 @@ __host__ __device__ inline bool op_heavy(uint32_t code) {
   return op_kind(code) == K_WIDE || op_opc(code) >= OP_STIM;
 }
 
+// The common (non-heavy) operations of one layer with a given arity: two
+// ranges of operation indices, [b0, e0) among the 1-bit destinations and
+// [b1, e1) among the others (each layer orders its common operations by
+// arity, mirrored around the heavy range, so every arity is two ranges).
+struct OpRanges {
+  uint32_t b0, e0, b1, e1;
+};
+
 // Per-batch control block in device memory.
 struct DevCtl {
   uint64_t cycle;         // cycle number of the next cycle to run
@@ -139,12 +147,12 @@ hipError_t launch_resident_multi(const ResJob* jobs, const uint2* map, uint32_t 
                                  size_t lds, hipStream_t s);
 size_t resident_lds_bytes(const StateLayout& L, uint32_t n_ops_total, uint32_t n_layers,
                           bool lds_state, bool lds_ops);
-// SWEEP, one layer (ly: the host copy of its record): the common operations
-// (launch_sweep_light) and the heavy ones (launch_sweep_heavy); either
-// returns without launching when its range is empty.
-hipError_t launch_sweep_light(const Program& p, const StateLayout& L, char* state, uint32_t layer,
-                              const DevLayer& ly, uint32_t ops_per_wave, uint32_t unroll,
-                              uint32_t tiles_per_wave, hipStream_t s);
+// SWEEP, one layer: the common operations of arity n_src (launch_sweep_light,
+// ranges r) and the heavy ones (launch_sweep_heavy, ly: the host copy of the
+// layer record); either returns without launching when its ranges are empty.
+hipError_t launch_sweep_light(const Program& p, const StateLayout& L, char* state,
+                              const OpRanges& r, uint32_t n_src, uint32_t ops_per_wave,
+                              uint32_t unroll, uint32_t tiles_per_wave, hipStream_t s);
 hipError_t launch_sweep_heavy(const Program& p, const StateLayout& L, char* state,
                               const uint64_t* seeds, const DevCtl* ctl, uint32_t n_inst,
                               uint32_t layer, const DevLayer& ly, uint32_t ops_per_wave,

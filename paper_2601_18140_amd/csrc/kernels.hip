@@ -331,29 +331,28 @@ struct SweepView {
   }
 };
 
-// Common operations of one layer (every value at most 64 bits, no source).
+// Common operations of one layer (every value at most 64 bits, no source)
+// with NS operands, NS = 1, 2 or 3: the ranges [r.b0, r.e0) and [r.b1, r.e1);
+// the first `split` chunks cover the first.  A kernel per operand count keeps
+// absent operands from costing loads and registers.
 // A wavefront handles a chunk of operations for TG tiles (64 instances each).
 // Operations are processed U at a time: first the U records (scalar loads,
-// decoded once for all TG tiles), then every operand (1-bit: one scalar load
-// of the TG words; wider: TG vector loads), then the evaluations and stores.
-// Tiles past the last instance (allocation padding up to a multiple of TG)
-// are evaluated like the others and never read back.  The layer's common
-// operations are the ranges [begin, hbeg) and [hend, end); the first `split`
-// chunks cover the first.
-//
-template <int U, int TG>
+// decoded once for all TG tiles), then every operand for every tile (NS*U*TG
+// gathers in flight per wavefront), then the evaluations and stores.  Tiles
+// past the last instance (allocation padding up to a multiple of TG) are
+// evaluated like the others and never read back.
+template <int U, int TG, int NS>
 __global__ void __launch_bounds__(256)
-k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers, StateLayout L,
-        char* __restrict__ state, uint32_t layer, uint32_t opw, uint32_t split) {
+k_sweep(const DevOp* __restrict__ ops, StateLayout L, char* __restrict__ state, OpRanges r,
+        uint32_t opw, uint32_t split) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   const uint32_t n_groups = L.n_tiles_alloc / TG;
   const uint32_t grp = wave % n_groups, chunk = wave / n_groups;
-  const DevLayer ly = layers[layer];
   const bool first = chunk < split;
-  const uint32_t o0 = first ? ly.begin + chunk * opw : ly.hend + (chunk - split) * opw;
-  const uint32_t oe = first ? ly.hbeg : ly.end;
+  const uint32_t o0 = first ? r.b0 + chunk * opw : r.b1 + (chunk - split) * opw;
+  const uint32_t oe = first ? r.e0 : r.e1;
   if (o0 >= oe) return;
   const uint32_t o1 = min(o0 + opw, oe);
   const uint32_t tile0 = grp * TG;
@@ -368,7 +367,11 @@ k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers, Stat
     for (int u = 0; u < U; ++u) {
       const uint32_t code = op[u].code;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
+      for (int k = NS; k < 3; ++k)
+#pragma unroll
+        for (int g = 0; g < TG; ++g) raw[u][k][g] = 0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
         const uint32_t cls = op_scls(code, k);
         const char* p = v.gather_base(cls, op[u].src[k]) + v.ld_off(cls);
         const uint32_t step = cls == CB ? 8u : 512u;
@@ -383,7 +386,7 @@ k_sweep(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers, Stat
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
+      for (int k = 0; k < NS; ++k)
 #pragma unroll
         for (int g = 0; g < TG; ++g) asm volatile("" ::"v"(raw[u][k][g]));
 #pragma unroll
@@ -676,34 +679,40 @@ hipError_t launch_resident_multi(const ResJob* jobs, const uint2* map, uint32_t 
   return dispatch_res<ResMany>(lds_state, lds_ops, unroll, jobs, map, n_blocks, block, lds, s);
 }
 
-hipError_t launch_sweep_light(const Program& p, const StateLayout& L, char* state, uint32_t layer,
-                              const DevLayer& ly, uint32_t ops_per_wave, uint32_t unroll,
-                              uint32_t tiles_per_wave, hipStream_t s) {
-  const uint32_t n1 = ly.hbeg - ly.begin, n2 = ly.end - ly.hend;
+hipError_t launch_sweep_light(const Program& p, const StateLayout& L, char* state,
+                              const OpRanges& r, uint32_t n_src, uint32_t ops_per_wave,
+                              uint32_t unroll, uint32_t tiles_per_wave, hipStream_t s) {
+  const uint32_t n1 = r.e0 - r.b0, n2 = r.e1 - r.b1;
   if (n1 + n2 == 0) return hipSuccess;
   const uint32_t tg = tiles_per_wave == 8 ? 8u : tiles_per_wave == 4 ? 4u
                     : tiles_per_wave == 2 ? 2u : 1u;
-  if (ops_per_wave == 0 || L.n_tiles_alloc % tg != 0) return hipErrorInvalidValue;
+  if (ops_per_wave == 0 || n_src < 1 || n_src > 3 || L.n_tiles_alloc % tg != 0)
+    return hipErrorInvalidValue;
   const uint32_t split = (n1 + ops_per_wave - 1) / ops_per_wave;
   const uint64_t chunks = split + (n2 + ops_per_wave - 1) / ops_per_wave;
   const uint64_t waves = chunks * (L.n_tiles_alloc / tg);
   const dim3 grid((uint32_t)((waves + 3) / 4)), blk(256);
-#define RTEAAL_SWEEP(UU, GG)                                                               \
-  hipLaunchKernelGGL((k_sweep<UU, GG>), grid, blk, 0, s, p.ops, p.layers, L, state, layer,   \
-                     ops_per_wave, split)
+#define RTEAAL_SWEEP(UU, GG, NN)                                                          \
+  hipLaunchKernelGGL((k_sweep<UU, GG, NN>), grid, blk, 0, s, p.ops, L, state, r, ops_per_wave, \
+                     split)
+#define RTEAAL_SWEEP_N(UU, GG)          \
+  if (n_src == 1) RTEAAL_SWEEP(UU, GG, 1); \
+  else if (n_src == 2) RTEAAL_SWEEP(UU, GG, 2); \
+  else RTEAAL_SWEEP(UU, GG, 3);
   // unroll x tiles_per_wave is at most 8: larger products run out of
   // registers and spill to scratch.
   switch (tg * 8 + unroll) {
-    case 8 + 1: RTEAAL_SWEEP(1, 1); break;
-    case 8 + 4: RTEAAL_SWEEP(4, 1); break;
-    case 16 + 1: RTEAAL_SWEEP(1, 2); break;
-    case 16 + 2: RTEAAL_SWEEP(2, 2); break;
-    case 16 + 4: RTEAAL_SWEEP(4, 2); break;
-    case 32 + 1: RTEAAL_SWEEP(1, 4); break;
-    case 32 + 2: RTEAAL_SWEEP(2, 4); break;
-    case 64 + 1: RTEAAL_SWEEP(1, 8); break;
-    default: RTEAAL_SWEEP(2, 1); break;
+    case 8 + 1: RTEAAL_SWEEP_N(1, 1) break;
+    case 8 + 4: RTEAAL_SWEEP_N(4, 1) break;
+    case 16 + 1: RTEAAL_SWEEP_N(1, 2) break;
+    case 16 + 2: RTEAAL_SWEEP_N(2, 2) break;
+    case 16 + 4: RTEAAL_SWEEP_N(4, 2) break;
+    case 32 + 1: RTEAAL_SWEEP_N(1, 4) break;
+    case 32 + 2: RTEAAL_SWEEP_N(2, 4) break;
+    case 64 + 1: RTEAAL_SWEEP_N(1, 8) break;
+    default: RTEAAL_SWEEP_N(2, 1) break;
   }
+#undef RTEAAL_SWEEP_N
 #undef RTEAAL_SWEEP
   return hipGetLastError();
 }

@@ -123,17 +123,21 @@ SWEEP_SHAPES = [(1, 1), (2, 1), (4, 1), (1, 2), (2, 2), (4, 2), (1, 4), (2, 4), 
 
 
 @pytest.mark.parametrize("cfg", SMALL[:2], ids=[c.name for c in SMALL[:2]])
-def test_sweep_tile_groups(ctx, cfg):
+@pytest.mark.parametrize("arity_split", [1, 2], ids=["one-launch", "per-arity"])
+def test_sweep_tile_groups(ctx, cfg, arity_split):
     """Every (unroll, tiles per wavefront) variant, with tile counts that
-    leave a short last group (2, 3 and 5 tiles), on every slot."""
+    leave a short last group (2, 3 and 5 tiles), on every slot; the common
+    operations of a layer in one launch or in one launch per operand count."""
     d = rtlgen.generate(cfg, 19)
     for n_inst in (100, 130, 300):
         seeds = np.arange(n_inst, dtype=np.uint64) * 104729 + 11
         ref_r, ref_s, _ = oracle.run(d, seeds, 9, want_slots=True)
         for u, tg in SWEEP_SHAPES:
-            note(f"tile groups {cfg.name} n={n_inst} unroll={u} tiles_per_wave={tg}")
+            note(f"tile groups {cfg.name} n={n_inst} unroll={u} tiles_per_wave={tg} "
+                 f"arity_split={arity_split}")
             regs, slots, _ = run_gpu(ctx, d, seeds, [4, 5], mapping=R.RTEAAL_MAP_SWEEP,
-                                     slots=True, unroll=u, tiles_per_wave=tg, ops_per_wave=7)
+                                     slots=True, unroll=u, tiles_per_wave=tg, ops_per_wave=7,
+                                     arity_split=arity_split)
             assert_same(regs, ref_r, f"registers u={u} tg={tg}")
             assert_same(slots, ref_s, f"slots u={u} tg={tg}")
 

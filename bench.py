@@ -112,7 +112,8 @@ def measured_traffic(role, workload, opts):
     if not opts or not os.path.exists(path):
         return None
     key = (f"{role}|{workload}|sweep/opw{opts['ops_per_wave']}/u{opts['unroll']}"
-           f"/tg{opts['tiles_per_wave']}/as{opts.get('arity_split', 0)}")
+           f"/tg{opts['tiles_per_wave']}/as{opts.get('arity_split', 0)}"
+           f"/tpp{opts.get('tiles_per_pass', 0)}")
     with open(path) as fh:
         rec = json.load(fh).get(key)
     if rec is None or rec["source_sha256"] != kernel_sources_sha256():
@@ -283,6 +284,7 @@ def main():
     ap.add_argument("--unroll", type=int, default=0)
     ap.add_argument("--tiles-per-wave", type=int, default=0)
     ap.add_argument("--arity-split", type=int, default=0, help="SWEEP: 0 auto, 1 never, 2 always")
+    ap.add_argument("--tiles-per-pass", type=int, default=0, help="SWEEP: 0 all tiles per pass")
     ap.add_argument("--plain-cycles", type=int, default=None)
     ap.add_argument("--profile-cycles", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -342,7 +344,7 @@ def main():
     did = R.rteaal_load_design(ctx, d)
 
     manual = (args.mapping != "auto" or args.block or args.ops_per_wave or args.unroll
-              or args.tiles_per_wave or args.arity_split)
+              or args.tiles_per_wave or args.arity_split or args.tiles_per_pass)
     tuned = None
     if not manual and not args.no_autotune:
         t0 = time.perf_counter()
@@ -351,7 +353,8 @@ def main():
               f"-> {trate:.4g} instance-cycles/s", file=sys.stderr, flush=True)
     bid = R.rteaal_create_batch(ctx, did, seeds, mapping=mapping, block_threads=args.block,
                                 ops_per_wave=args.ops_per_wave, unroll=args.unroll,
-                                tiles_per_wave=args.tiles_per_wave, arity_split=args.arity_split)
+                                tiles_per_wave=args.tiles_per_wave, arity_split=args.arity_split,
+                                tiles_per_pass=args.tiles_per_pass)
     used_map, _ = R.rteaal_batch_info(ctx, bid)
     bopts = R.rteaal_batch_options(ctx, bid)
     ok = parity_sample(R, ctx, bid, d, seeds)

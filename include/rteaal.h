@@ -184,6 +184,11 @@ typedef struct {
                               operand count (1, 2, 3), so absent operands cost
                               no loads or registers; auto splits the layers
                               with at least 2^20 operation x 64-instance tiles */
+  uint32_t tiles_per_pass; /* SWEEP: 0 = all; else each cycle runs as passes
+                              over this many 64-instance tiles at a time (a
+                              multiple of tiles_per_wave), all layers of one
+                              pass before the next, so that a pass's recent
+                              layer outputs can stay in the last-level cache  */
 } rteaal_batch_opts;
 
 /* Device bytes a batch of n_instances of `design` would allocate under
@@ -207,7 +212,8 @@ rteaal_status rteaal_batch_info(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t
 /* The launch shape a batch resolved to (defaults, autotuned entry or caller
  * options), written to *out: mapping, and for RESIDENT block_threads,
  * lds_state/lds_ops (1 = in LDS, 0 = in HBM), unroll; for SWEEP
- * ops_per_wave, unroll, tiles_per_wave, arity_split (other fields 0). */
+ * ops_per_wave, unroll, tiles_per_wave, arity_split, tiles_per_pass (0 = all)
+ * (other fields 0). */
 rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id batch, rteaal_batch_opts* out);
 
 /* ------------------------------------------------------------------------ */

@@ -524,6 +524,7 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
 struct Batch {
   uint32_t id = 0, design = 0, n_inst = 0, mapping = 0, block = 0, opw = 0, unroll = 0, tg = 1;
   uint32_t arity_split = 0;
+  uint32_t tpp = 0;  // SWEEP tiles per pass, 0 = all
   bool lds = false, lds_ops = false;
   uint64_t cycle = 0;
   StateLayout L{};
@@ -650,12 +651,13 @@ ResJob res_job(const DesignHost& h, const Batch& b, uint64_t n_cycles) {
 // Launches of one layer's common operations: one per operand count when the
 // layer is large enough for the extra launches to pay, else one for all.
 template <class F>
-hipError_t for_light_launches(const DesignHost& h, const Batch& b, uint32_t li, F&& launch) {
+hipError_t for_light_launches(const DesignHost& h, const Batch& b, uint32_t li, TilePass tp,
+                              F&& launch) {
   const DevLayer& ly = h.layers[li];
   const uint64_t n_light = (ly.end - ly.begin) - (ly.hend - ly.hbeg);
   if (n_light == 0) return hipSuccess;
   const bool split = b.arity_split == 2 ||
-                     (b.arity_split == 0 && n_light * b.L.n_tiles_alloc >= (1ull << 20));
+                     (b.arity_split == 0 && n_light * tp.count >= (1ull << 20));
   if (!split) return launch(OpRanges{ly.begin, ly.hbeg, ly.hend, ly.end}, 3u);
   for (uint32_t a = 1; a <= 3; ++a) {
     const OpRanges& r = h.light[li][a - 1];
@@ -664,6 +666,14 @@ hipError_t for_light_launches(const DesignHost& h, const Batch& b, uint32_t li, 
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// The tile passes of one SWEEP cycle.
+std::vector<TilePass> tile_passes(const Batch& b) {
+  const uint32_t n = b.L.n_tiles_alloc, step = b.tpp ? b.tpp : n;
+  std::vector<TilePass> out;
+  for (uint32_t t = 0; t < n; t += step) out.push_back(TilePass{t, std::min(step, n - t)});
+  return out;
 }
 
 rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t n_cycles) {
@@ -686,21 +696,24 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
   // once as a HIP graph.
   char* st = (char*)b.state.p;
   const uint64_t* seeds = (const uint64_t*)b.seeds.p;
+  const std::vector<TilePass> passes = tile_passes(b);
   if (b.profile) {
     for (uint64_t c = 0; c < n_cycles; ++c) {
-      for (uint32_t li = 0; li < h.layers.size(); ++li) {
-        const DevLayer& ly = h.layers[li];
-        HIP_TRY(ctx, for_light_launches(h, b, li, [&](const OpRanges& r, uint32_t a) {
-                  return timed(b, ctx->stream, 0, [&] {
-                    return launch_sweep_light(p, b.L, st, r, a, b.opw, b.unroll, b.tg, ctx->stream);
-                  });
-                }));
-        if (ly.hend > ly.hbeg)
-          HIP_TRY(ctx, timed(b, ctx->stream, 1, [&] {
-                    return launch_sweep_heavy(p, b.L, st, seeds, ctl, b.n_inst, li, ly, b.opw, b.tg,
-                                              ctx->stream);
+      for (const TilePass& tp : passes)
+        for (uint32_t li = 0; li < h.layers.size(); ++li) {
+          const DevLayer& ly = h.layers[li];
+          HIP_TRY(ctx, for_light_launches(h, b, li, tp, [&](const OpRanges& r, uint32_t a) {
+                    return timed(b, ctx->stream, 0, [&] {
+                      return launch_sweep_light(p, b.L, st, r, a, b.opw, b.unroll, b.tg, tp,
+                                                ctx->stream);
+                    });
                   }));
-      }
+          if (ly.hend > ly.hbeg)
+            HIP_TRY(ctx, timed(b, ctx->stream, 1, [&] {
+                      return launch_sweep_heavy(p, b.L, st, seeds, ctl, b.n_inst, li, ly, b.opw,
+                                                b.tg, tp, ctx->stream);
+                    }));
+        }
       HIP_TRY(ctx, launch_advance(ctl, 1, ctx->stream));
     }
     return RTEAAL_OK;
@@ -709,14 +722,16 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
     hipGraph_t g = nullptr;
     HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (uint32_t li = 0; li < h.layers.size() && e == hipSuccess; ++li) {
-      const DevLayer& ly = h.layers[li];
-      e = for_light_launches(h, b, li, [&](const OpRanges& r, uint32_t a) {
-        return launch_sweep_light(p, b.L, st, r, a, b.opw, b.unroll, b.tg, ctx->stream);
-      });
-      if (e == hipSuccess)
-        e = launch_sweep_heavy(p, b.L, st, seeds, ctl, b.n_inst, li, ly, b.opw, b.tg, ctx->stream);
-    }
+    for (const TilePass& tp : passes)
+      for (uint32_t li = 0; li < h.layers.size() && e == hipSuccess; ++li) {
+        const DevLayer& ly = h.layers[li];
+        e = for_light_launches(h, b, li, tp, [&](const OpRanges& r, uint32_t a) {
+          return launch_sweep_light(p, b.L, st, r, a, b.opw, b.unroll, b.tg, tp, ctx->stream);
+        });
+        if (e == hipSuccess)
+          e = launch_sweep_heavy(p, b.L, st, seeds, ctl, b.n_inst, li, ly, b.opw, b.tg, tp,
+                                 ctx->stream);
+      }
     if (e == hipSuccess) e = launch_advance(ctl, 1, ctx->stream);
     hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -943,6 +958,10 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
     const uint32_t as = opts ? opts->arity_split : 0u;
     if (as > 2) return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP arity_split must be 0, 1 or 2");
     b->arity_split = as;
+    const uint32_t tpp = opts ? opts->tiles_per_pass : 0u;
+    if (tpp % tg != 0)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP tiles_per_pass must be a multiple of tiles_per_wave");
+    b->tpp = tpp >= b->L.n_tiles_alloc ? 0u : tpp;
   }
   const uint64_t n_seed = b->mapping == RTEAAL_MAP_SWEEP ? (uint64_t)b->L.n_tiles_alloc * 64 : n_inst;
   if (!alloc_all(ctx, {{&b->state, sb}, {&b->seeds, n_seed * 8}, {&b->ctl, sizeof(DevCtl)}}))
@@ -1010,6 +1029,7 @@ rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id id, rteaal_b
     o.ops_per_wave = b->opw;
     o.tiles_per_wave = b->tg;
     o.arity_split = b->arity_split;
+    o.tiles_per_pass = b->tpp;
   }
   *out = o;
   return RTEAAL_OK;

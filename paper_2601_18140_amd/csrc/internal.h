@@ -74,6 +74,13 @@ struct OpRanges {
   uint32_t b0, e0, b1, e1;
 };
 
+// SWEEP: the tiles [base, base + count) one launch covers.  A cycle may run
+// as several passes over disjoint tile ranges (instances are independent), so
+// that a pass's recent layer outputs stay in the device's last-level cache.
+struct TilePass {
+  uint32_t base, count;
+};
+
 // Per-batch control block in device memory.
 struct DevCtl {
   uint64_t cycle;         // cycle number of the next cycle to run
@@ -152,11 +159,12 @@ size_t resident_lds_bytes(const StateLayout& L, uint32_t n_ops_total, uint32_t n
 // layer record); either returns without launching when its ranges are empty.
 hipError_t launch_sweep_light(const Program& p, const StateLayout& L, char* state,
                               const OpRanges& r, uint32_t n_src, uint32_t ops_per_wave,
-                              uint32_t unroll, uint32_t tiles_per_wave, hipStream_t s);
+                              uint32_t unroll, uint32_t tiles_per_wave, TilePass tp,
+                              hipStream_t s);
 hipError_t launch_sweep_heavy(const Program& p, const StateLayout& L, char* state,
                               const uint64_t* seeds, const DevCtl* ctl, uint32_t n_inst,
                               uint32_t layer, const DevLayer& ly, uint32_t ops_per_wave,
-                              uint32_t tiles_per_wave, hipStream_t s);
+                              uint32_t tiles_per_wave, TilePass tp, hipStream_t s);
 hipError_t launch_advance(DevCtl* ctl, uint64_t n, hipStream_t s);
 hipError_t launch_set_words(DevCtl* ctl, const uint64_t* words, hipStream_t s);
 hipError_t launch_pack(bool sweep, const StateLayout& L, const char* state, const SlotRef* refs,

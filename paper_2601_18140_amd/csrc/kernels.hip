@@ -344,18 +344,17 @@ struct SweepView {
 template <int U, int TG, int NS>
 __global__ void __launch_bounds__(256)
 k_sweep(const DevOp* __restrict__ ops, StateLayout L, char* __restrict__ state, OpRanges r,
-        uint32_t opw, uint32_t split) {
+        uint32_t opw, uint32_t split, uint32_t tile_base, uint32_t n_groups) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  const uint32_t n_groups = L.n_tiles_alloc / TG;
   const uint32_t grp = wave % n_groups, chunk = wave / n_groups;
   const bool first = chunk < split;
   const uint32_t o0 = first ? r.b0 + chunk * opw : r.b1 + (chunk - split) * opw;
   const uint32_t oe = first ? r.e0 : r.e1;
   if (o0 >= oe) return;
   const uint32_t o1 = min(o0 + opw, oe);
-  const uint32_t tile0 = grp * TG;
+  const uint32_t tile0 = tile_base + grp * TG;
   const SweepView v(state, L, tile0, lane);
 
   for (uint32_t o = o0; o < o1; o += U) {
@@ -454,17 +453,17 @@ __global__ void __launch_bounds__(256)
 k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
               const uint64_t* __restrict__ const_limbs, uint32_t words_per_inst, StateLayout L,
               char* __restrict__ state, const uint64_t* __restrict__ seeds,
-              const DevCtl* __restrict__ ctl, uint32_t n_inst, uint32_t layer, uint32_t opw) {
+              const DevCtl* __restrict__ ctl, uint32_t n_inst, uint32_t layer, uint32_t opw,
+              uint32_t tile_base, uint32_t n_groups) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  const uint32_t n_groups = L.n_tiles_alloc / TG;
   const uint32_t grp = wave % n_groups, chunk = wave / n_groups;
   const DevLayer ly = layers[layer];
   const uint32_t o0 = ly.hbeg + chunk * opw;
   if (o0 >= ly.hend) return;
   const uint32_t o1 = min(o0 + opw, ly.hend);
-  const uint32_t tile0 = grp * TG;
+  const uint32_t tile0 = tile_base + grp * TG;
   const SweepView v(state, L, tile0, lane);
 
   for (uint32_t o = o0; o < o1; ++o) {
@@ -679,22 +678,30 @@ hipError_t launch_resident_multi(const ResJob* jobs, const uint2* map, uint32_t 
   return dispatch_res<ResMany>(lds_state, lds_ops, unroll, jobs, map, n_blocks, block, lds, s);
 }
 
+// A tile pass must lie inside the allocated tiles and be whole tile groups.
+static bool pass_ok(const StateLayout& L, TilePass tp, uint32_t tg) {
+  return tp.count > 0 && tp.count % tg == 0 && tp.base % tg == 0 &&
+         (uint64_t)tp.base + tp.count <= L.n_tiles_alloc;
+}
+
 hipError_t launch_sweep_light(const Program& p, const StateLayout& L, char* state,
                               const OpRanges& r, uint32_t n_src, uint32_t ops_per_wave,
-                              uint32_t unroll, uint32_t tiles_per_wave, hipStream_t s) {
+                              uint32_t unroll, uint32_t tiles_per_wave, TilePass tp,
+                              hipStream_t s) {
   const uint32_t n1 = r.e0 - r.b0, n2 = r.e1 - r.b1;
   if (n1 + n2 == 0) return hipSuccess;
   const uint32_t tg = tiles_per_wave == 8 ? 8u : tiles_per_wave == 4 ? 4u
                     : tiles_per_wave == 2 ? 2u : 1u;
-  if (ops_per_wave == 0 || n_src < 1 || n_src > 3 || L.n_tiles_alloc % tg != 0)
+  if (ops_per_wave == 0 || n_src < 1 || n_src > 3 || !pass_ok(L, tp, tg))
     return hipErrorInvalidValue;
   const uint32_t split = (n1 + ops_per_wave - 1) / ops_per_wave;
   const uint64_t chunks = split + (n2 + ops_per_wave - 1) / ops_per_wave;
-  const uint64_t waves = chunks * (L.n_tiles_alloc / tg);
+  const uint32_t n_groups = tp.count / tg;
+  const uint64_t waves = chunks * n_groups;
   const dim3 grid((uint32_t)((waves + 3) / 4)), blk(256);
 #define RTEAAL_SWEEP(UU, GG, NN)                                                          \
   hipLaunchKernelGGL((k_sweep<UU, GG, NN>), grid, blk, 0, s, p.ops, L, state, r, ops_per_wave, \
-                     split)
+                     split, tp.base, n_groups)
 #define RTEAAL_SWEEP_N(UU, GG)          \
   if (n_src == 1) RTEAAL_SWEEP(UU, GG, 1); \
   else if (n_src == 2) RTEAAL_SWEEP(UU, GG, 2); \
@@ -720,17 +727,19 @@ hipError_t launch_sweep_light(const Program& p, const StateLayout& L, char* stat
 hipError_t launch_sweep_heavy(const Program& p, const StateLayout& L, char* state,
                               const uint64_t* seeds, const DevCtl* ctl, uint32_t n_inst,
                               uint32_t layer, const DevLayer& ly, uint32_t ops_per_wave,
-                              uint32_t tiles_per_wave, hipStream_t s) {
+                              uint32_t tiles_per_wave, TilePass tp, hipStream_t s) {
   const uint32_t n = ly.hend - ly.hbeg;
   if (n == 0) return hipSuccess;
   const uint32_t tg = tiles_per_wave >= 4 ? 4u : tiles_per_wave == 2 ? 2u : 1u;
-  if (ops_per_wave == 0 || L.n_tiles_alloc % tg != 0) return hipErrorInvalidValue;
+  if (ops_per_wave == 0 || !pass_ok(L, tp, tg)) return hipErrorInvalidValue;
   const uint64_t chunks = (n + ops_per_wave - 1) / ops_per_wave;
-  const uint64_t waves = chunks * (L.n_tiles_alloc / tg);
+  const uint32_t n_groups = tp.count / tg;
+  const uint64_t waves = chunks * n_groups;
   const dim3 grid((uint32_t)((waves + 3) / 4)), blk(256);
 #define RTEAAL_HEAVY(GG)                                                                     \
   hipLaunchKernelGGL((k_sweep_heavy<GG>), grid, blk, 0, s, p.ops, p.layers, p.const_limbs,   \
-                     p.words_per_inst, L, state, seeds, ctl, n_inst, layer, ops_per_wave)
+                     p.words_per_inst, L, state, seeds, ctl, n_inst, layer, ops_per_wave,    \
+                     tp.base, n_groups)
   if (tg == 4) RTEAAL_HEAVY(4);
   else if (tg == 2) RTEAAL_HEAVY(2);
   else RTEAAL_HEAVY(1);

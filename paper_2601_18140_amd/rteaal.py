@@ -66,7 +66,8 @@ class rteaal_batch_opts(C.Structure):
     _fields_ = [("mapping", C.c_uint32), ("block_threads", C.c_uint32),
                 ("ops_per_wave", C.c_uint32), ("lds_state", C.c_uint32),
                 ("lds_ops", C.c_uint32), ("unroll", C.c_uint32),
-                ("tiles_per_wave", C.c_uint32), ("arity_split", C.c_uint32)]
+                ("tiles_per_wave", C.c_uint32), ("arity_split", C.c_uint32),
+                ("tiles_per_pass", C.c_uint32)]
 
 
 class rteaal_stimulus(C.Structure):
@@ -289,9 +290,10 @@ def rteaal_design_format(ctx, design_id, layer):
 
 
 def _opts(mapping, block_threads=0, ops_per_wave=0, lds_state=0, lds_ops=0, unroll=0,
-          tiles_per_wave=0, arity_split=0):
+          tiles_per_wave=0, arity_split=0, tiles_per_pass=0):
     return rteaal_batch_opts(int(mapping), int(block_threads), int(ops_per_wave), int(lds_state),
-                             int(lds_ops), int(unroll), int(tiles_per_wave), int(arity_split))
+                             int(lds_ops), int(unroll), int(tiles_per_wave), int(arity_split),
+                             int(tiles_per_pass))
 
 
 def rteaal_batch_footprint(ctx, design_id, n_instances, mapping=RTEAAL_MAP_AUTO, **opts):
@@ -304,7 +306,7 @@ def rteaal_batch_footprint(ctx, design_id, n_instances, mapping=RTEAAL_MAP_AUTO,
 
 def rteaal_create_batch(ctx, design_id, seeds, mapping=RTEAAL_MAP_AUTO, **opts):
     """opts: block_threads, ops_per_wave, lds_state, lds_ops, unroll, tiles_per_wave,
-    arity_split (see rteaal_batch_opts)."""
+    arity_split, tiles_per_pass (see rteaal_batch_opts)."""
     seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
     o = _opts(mapping, **opts)
     out = C.c_uint32()
@@ -383,7 +385,8 @@ def rteaal_write_state(ctx, batch_id, first, regs, cycle):
 def opts_dict(o):
     return {"mapping": o.mapping, "block_threads": o.block_threads, "ops_per_wave": o.ops_per_wave,
             "lds_state": o.lds_state, "lds_ops": o.lds_ops, "unroll": o.unroll,
-            "tiles_per_wave": o.tiles_per_wave, "arity_split": o.arity_split}
+            "tiles_per_wave": o.tiles_per_wave, "arity_split": o.arity_split,
+            "tiles_per_pass": o.tiles_per_pass}
 
 
 def rteaal_autotune(ctx, design_id, n_instances, trial_cycles=0):

@@ -142,6 +142,22 @@ def test_sweep_tile_groups(ctx, cfg, arity_split):
             assert_same(slots, ref_s, f"slots u={u} tg={tg}")
 
 
+def test_sweep_tile_passes(ctx):
+    """A cycle run as passes over tile subsets (the last pass shorter) equals
+    one pass over all tiles and the oracle, every slot."""
+    d = rtlgen.generate(SMALL[1], 23)
+    for n_inst in (300, 520):
+        seeds = np.arange(n_inst, dtype=np.uint64) * 7 + 5
+        ref_r, ref_s, _ = oracle.run(d, seeds, 7, want_slots=True)
+        for tg, tpp, split in [(1, 1, 0), (1, 2, 2), (2, 2, 1), (2, 4, 2), (4, 4, 2), (8, 8, 1)]:
+            note(f"tile passes n={n_inst} tiles_per_wave={tg} tiles_per_pass={tpp} split={split}")
+            regs, slots, _ = run_gpu(ctx, d, seeds, [3, 4], mapping=R.RTEAAL_MAP_SWEEP, slots=True,
+                                     tiles_per_wave=tg, unroll=1, ops_per_wave=5,
+                                     tiles_per_pass=tpp, arity_split=split)
+            assert_same(regs, ref_r, f"registers tg={tg} tpp={tpp}")
+            assert_same(slots, ref_s, f"slots tg={tg} tpp={tpp}")
+
+
 def test_sweep_rejects_oversized_shape(ctx):
     d = rtlgen.generate(SMALL[2], 1)
     did = R.rteaal_load_design(ctx, d)
@@ -149,6 +165,9 @@ def test_sweep_rejects_oversized_shape(ctx):
         with pytest.raises(R.RteaalError):
             R.rteaal_create_batch(ctx, did, np.arange(70, dtype=np.uint64),
                                   mapping=R.RTEAAL_MAP_SWEEP, unroll=4, tiles_per_wave=4)
+        with pytest.raises(R.RteaalError):
+            R.rteaal_create_batch(ctx, did, np.arange(300, dtype=np.uint64),
+                                  mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=2, tiles_per_pass=3)
     finally:
         R.rteaal_unload_design(ctx, did)
 

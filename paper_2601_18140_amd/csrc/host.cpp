@@ -49,6 +49,10 @@ struct rteaal_ctx {
   // fork/join events, and a grow-only device scratch for job tables.
   hipStream_t aux[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t fork = nullptr, join[4] = {nullptr, nullptr, nullptr, nullptr};
+  // Streams and events that only serve graph capture: the launches of one
+  // layer fork onto them, so the captured graph runs them concurrently.
+  hipStream_t cap[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t cap_fork = nullptr, cap_join[3] = {nullptr, nullptr, nullptr};
   Mem multi;
   // Autotuned batch options, keyed by (design, instance count).
   std::map<std::pair<uint32_t, uint32_t>, rteaal_batch_opts> tuned;
@@ -719,18 +723,56 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
     return RTEAAL_OK;
   }
   if (!b.graph) {
+    for (int k = 0; k < 3; ++k) {
+      if (!ctx->cap[k]) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap[k], hipStreamNonBlocking));
+      if (!ctx->cap_join[k])
+        HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->cap_join[k], hipEventDisableTiming));
+    }
+    if (!ctx->cap_fork) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->cap_fork, hipEventDisableTiming));
     hipGraph_t g = nullptr;
     HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
+    // The launches of one layer (its common operations, per operand count or
+    // together, and its heavy ones) write disjoint slots and read only earlier
+    // layers: they become parallel branches of the graph, joined before the
+    // next layer.
+    struct Piece {
+      OpRanges r;
+      uint32_t n_src;  // 0: the heavy launch
+    };
+    std::vector<Piece> pieces;
     for (const TilePass& tp : passes)
       for (uint32_t li = 0; li < h.layers.size() && e == hipSuccess; ++li) {
         const DevLayer& ly = h.layers[li];
+        pieces.clear();
         e = for_light_launches(h, b, li, tp, [&](const OpRanges& r, uint32_t a) {
-          return launch_sweep_light(p, b.L, st, r, a, b.opw, b.unroll, b.tg, tp, ctx->stream);
+          pieces.push_back(Piece{r, a});
+          return hipSuccess;
         });
-        if (e == hipSuccess)
-          e = launch_sweep_heavy(p, b.L, st, seeds, ctl, b.n_inst, li, ly, b.opw, b.tg, tp,
-                                 ctx->stream);
+        if (ly.hend > ly.hbeg) pieces.push_back(Piece{OpRanges{}, 0u});
+        auto run = [&](const Piece& pc, hipStream_t s2) {
+          return pc.n_src ? launch_sweep_light(p, b.L, st, pc.r, pc.n_src, b.opw, b.unroll, b.tg,
+                                               tp, s2)
+                          : launch_sweep_heavy(p, b.L, st, seeds, ctl, b.n_inst, li, ly, b.opw,
+                                               b.tg, tp, s2);
+        };
+        // Only large layers fork: for small ones the branches' scheduling costs
+        // more than the overlap returns, and batches stepped together already
+        // overlap on their own streams.
+        const bool large = (uint64_t)(ly.end - ly.begin) * tp.count >= (1ull << 20);
+        const size_t n_fork = large ? std::min<size_t>(pieces.size(), 4) - (pieces.empty() ? 0 : 1) : 0;
+        if (e == hipSuccess && n_fork) {
+          e = hipEventRecord(ctx->cap_fork, ctx->stream);
+          for (size_t k = 0; k < n_fork && e == hipSuccess; ++k)
+            e = hipStreamWaitEvent(ctx->cap[k], ctx->cap_fork, 0);
+        }
+        for (size_t k = 0; k < pieces.size() && e == hipSuccess; ++k)
+          e = run(pieces[k], k == 0 || k > n_fork ? ctx->stream : ctx->cap[k - 1]);
+        // (pieces beyond the forked ones, if any, run on the capturing stream)
+        for (size_t k = 0; k < n_fork && e == hipSuccess; ++k) {
+          e = hipEventRecord(ctx->cap_join[k], ctx->cap[k]);
+          if (e == hipSuccess) e = hipStreamWaitEvent(ctx->stream, ctx->cap_join[k], 0);
+        }
       }
     if (e == hipSuccess) e = launch_advance(ctl, 1, ctx->stream);
     hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
@@ -818,6 +860,11 @@ void rteaal_destroy(rteaal_ctx* ctx) {
     if (ctx->join[k]) (void)hipEventDestroy(ctx->join[k]);
   }
   if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+  for (int k = 0; k < 3; ++k) {
+    if (ctx->cap[k]) (void)hipStreamDestroy(ctx->cap[k]);
+    if (ctx->cap_join[k]) (void)hipEventDestroy(ctx->cap_join[k]);
+  }
+  if (ctx->cap_fork) (void)hipEventDestroy(ctx->cap_fork);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }

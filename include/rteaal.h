@@ -210,10 +210,11 @@ rteaal_status rteaal_batch_info(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t
                                 uint64_t* cycle);
 
 /* The launch shape a batch resolved to (defaults, autotuned entry or caller
- * options), written to *out: mapping, and for RESIDENT block_threads,
- * lds_state/lds_ops (1 = in LDS, 0 = in HBM), unroll; for SWEEP
- * ops_per_wave, unroll, tiles_per_wave, arity_split, tiles_per_pass (0 = all)
- * (other fields 0). */
+ * options), written to *out in the form rteaal_create_batch takes, so that
+ * passing *out back creates a batch of the same shape: mapping, and for
+ * RESIDENT block_threads, lds_state/lds_ops (0 = in LDS, 1 = in HBM),
+ * unroll; for SWEEP ops_per_wave, unroll, tiles_per_wave, arity_split,
+ * tiles_per_pass (0 = all) (other fields 0). */
 rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id batch, rteaal_batch_opts* out);
 
 /* ------------------------------------------------------------------------ */

@@ -1070,8 +1070,8 @@ rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id id, rteaal_b
   o.unroll = b->unroll;
   if (b->mapping == RTEAAL_MAP_RESIDENT) {
     o.block_threads = b->block;
-    o.lds_state = b->lds ? 1u : 0u;
-    o.lds_ops = b->lds_ops ? 1u : 0u;
+    o.lds_state = b->lds ? 0u : 1u;
+    o.lds_ops = b->lds_ops ? 0u : 1u;
   } else {
     o.ops_per_wave = b->opw;
     o.tiles_per_wave = b->tg;

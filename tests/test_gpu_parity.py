@@ -172,6 +172,31 @@ def test_sweep_rejects_oversized_shape(ctx):
         R.rteaal_unload_design(ctx, did)
 
 
+def test_batch_options_round_trip(ctx):
+    """rteaal_batch_options reports a batch's shape in the form that
+    rteaal_create_batch takes: a batch created from it has the same shape."""
+    d = rtlgen.generate(SMALL[0], 5)
+    did = R.rteaal_load_design(ctx, d)
+    try:
+        for n, kw in [(3, {"mapping": R.RTEAAL_MAP_RESIDENT}),
+                      (3, {"mapping": R.RTEAAL_MAP_RESIDENT, "lds_state": 1, "block_threads": 128}),
+                      (200, {"mapping": R.RTEAAL_MAP_SWEEP}),
+                      (300, {"mapping": R.RTEAAL_MAP_SWEEP, "tiles_per_wave": 2, "unroll": 2,
+                             "ops_per_wave": 3, "arity_split": 2, "tiles_per_pass": 2})]:
+            seeds = np.arange(n, dtype=np.uint64)
+            b1 = R.rteaal_create_batch(ctx, did, seeds, **kw)
+            o1 = R.rteaal_batch_options(ctx, b1)
+            b2 = R.rteaal_create_batch(ctx, did, seeds, **o1)
+            o2 = R.rteaal_batch_options(ctx, b2)
+            R.rteaal_free_batch(ctx, b1)
+            R.rteaal_free_batch(ctx, b2)
+            assert o1 == o2, (kw, o1, o2)
+            for k, v in kw.items():
+                assert o1[k] == v, (k, o1)
+    finally:
+        R.rteaal_unload_design(ctx, did)
+
+
 def test_plain_2k_full_run(ctx):
     """The small workload: 2,000 ops, 16 layers, one instance, 10,000 cycles."""
     w = rtlgen.WORKLOADS["plain-2k"]

@@ -142,9 +142,20 @@ rteaal_status rteaal_validate_design(const rteaal_design_desc* desc, char* err, 
 
 /* Validates, encodes (operations grouped per layer by destination width
  * class and type, as in the N-rank swizzle of the NU kernel) and uploads a
- * design.  *out receives a handle valid until rteaal_unload_design. */
+ * design.  *out receives a handle valid until rteaal_unload_design.
+ * Storage is assigned by live range: a value's storage is reused once every
+ * operation that reads it has run (registers keep theirs), which shrinks an
+ * instance's state to the largest set of values live at a layer boundary.
+ * Such a design supports RTEAAL_READ_REGS read-out only. */
 rteaal_status rteaal_load_design(rteaal_ctx* ctx, const rteaal_design_desc* desc,
                                  rteaal_design_id* out);
+
+/* As rteaal_load_design with flags: RTEAAL_LOAD_KEEP_ALL_SLOTS gives every
+ * slot storage of its own for the whole cycle, so that RTEAAL_READ_ALL_SLOTS
+ * can read every signal (a debugging aid: more memory and traffic). */
+enum { RTEAAL_LOAD_KEEP_ALL_SLOTS = 1 };
+rteaal_status rteaal_load_design_ex(rteaal_ctx* ctx, const rteaal_design_desc* desc,
+                                    uint32_t flags, rteaal_design_id* out);
 /* RTEAAL_E_BUSY while a batch of the design exists. */
 rteaal_status rteaal_unload_design(rteaal_ctx* ctx, rteaal_design_id design);
 
@@ -256,8 +267,10 @@ enum { RTEAAL_READ_REGS = 1, RTEAAL_READ_ALL_SLOTS = 2 };
 /* Waits for the batch, then copies instances [first, first+n) into `out`
  * (host): REGS gives [inst][reg][limbs(reg)]; ALL_SLOTS gives
  * [inst][slot][limbs(slot)] (values of the last completed cycle; slots with
- * no driver read as 0).  out_words is the capacity of out in uint64 words;
- * *written (may be NULL) receives the number used. */
+ * no driver read as 0; only for designs loaded with
+ * RTEAAL_LOAD_KEEP_ALL_SLOTS, else RTEAAL_E_UNSUPPORTED).  out_words is the
+ * capacity of out in uint64 words; *written (may be NULL) receives the
+ * number used. */
 rteaal_status rteaal_read_state(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t first,
                                 uint32_t n, uint32_t what, uint64_t* out, size_t out_words,
                                 size_t* written);

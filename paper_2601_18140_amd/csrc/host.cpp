@@ -284,6 +284,7 @@ struct DesignHost {
   uint32_t n_slots = 0, n_regs = 0, n_inputs = 0, n_design_layers = 0;
   uint32_t n_idx[NCLS] = {0};
   uint64_t n_rows = 0;      // 64-bit rows of one instance's state
+  bool compact = false;     // storage reused by live range (no all-slot read-out)
   std::vector<DevOp> ops;
   std::vector<DevLayer> layers;
   std::vector<std::array<OpRanges, 3>> light;  // per layer, per arity 1..3
@@ -304,7 +305,10 @@ struct EncOp {
   uint32_t dcls, kind, width;
 };
 
-void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
+// compact: storage is assigned by live range (an element or 1-bit row is
+// reused once every value in it has had its last reader); otherwise every
+// slot keeps its own storage for the whole cycle.
+void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, DesignHost* h) {
   const uint32_t NS = d->n_slots;
   std::vector<uint16_t> width(d->slot_width, d->slot_width + NS);
   // Registers whose next-state slot is itself a register are staged first,
@@ -401,29 +405,85 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
       return a.dcls < b.dcls;
     });
 
-  // Storage indices: 1-bit destinations by position, other classes in order.
+  // Storage indices.  A 1-bit destination gets bit (i mod 64) of the row
+  // given to its group of 64 consecutive 1-bit destinations in the layer
+  // (one wavefront's ballot fills exactly that row); every other slot gets
+  // an element index in its class.  Lifetimes are layer positions: a value
+  // lives from the layer that writes it to the last layer that reads it.
+  // Registers (written by the commit layer, read in the next cycle) and,
+  // without compaction, every slot keep their storage; the rest returns to
+  // its class's free list after its last reader's layer, so no layer writes
+  // over a value that the same layer still reads.
   const uint32_t NW = (uint32_t)width.size();
+  const uint32_t NL = (uint32_t)L.size();
   std::vector<uint32_t> scls(NW, CNONE), sidx(NW, 0);
-  uint32_t cnt[NCLS] = {0};
+  std::vector<uint32_t> last(NW, 0);
+  std::vector<char> keep(NW, compact ? 0 : 1);
+  for (uint32_t j = 0; j < d->n_regs; ++j) keep[d->reg_slot[j]] = 1;
+  for (uint32_t k = 0; k < NL; ++k)
+    for (const EncOp& e : L[k]) {
+      last[e.dst_slot] = std::max(last[e.dst_slot], k);
+      for (uint32_t q = 0; q < e.arity; ++q) last[e.src_slot[q]] = std::max(last[e.src_slot[q]], k);
+    }
+  uint32_t cnt[NCLS] = {0};                        // elements (CB: rows) ever used per class
+  std::vector<uint32_t> free_el[NCLS];             // LIFO: recently freed storage is warm
+  std::vector<std::vector<std::pair<uint32_t, uint32_t>>> release(NL + 1);
+  auto take = [&](uint32_t c) {
+    if (free_el[c].empty()) return cnt[c]++;
+    const uint32_t i = free_el[c].back();
+    free_el[c].pop_back();
+    return i;
+  };
+  // Places the destinations of layer k: with only_kept, just the kept ones
+  // (and the 1-bit rows holding one) on fresh storage; otherwise the rest,
+  // on recycled storage where possible.  Kept values live across the cycle
+  // boundary (a register is read by the layers before the commit that
+  // writes it), so their storage must never have held anything else.
+  auto place = [&](uint32_t k, bool only_kept) {
+    const auto& lay = L[k];
+    uint32_t nb = 0;
+    while (nb < lay.size() && lay[nb].dcls == CB) ++nb;
+    for (uint32_t g0 = 0; g0 < nb; g0 += 64) {
+      const uint32_t g1 = std::min(nb, g0 + 64);
+      if (scls[lay[g0].dst_slot] != CNONE) continue;  // placed by the kept pass
+      uint32_t end = k;
+      bool kept = false;
+      for (uint32_t i = g0; i < g1; ++i) {
+        end = std::max(end, last[lay[i].dst_slot]);
+        kept = kept || keep[lay[i].dst_slot];
+      }
+      if (only_kept && !kept) continue;
+      const uint32_t row = kept ? cnt[CB]++ : take(CB);
+      for (uint32_t i = g0; i < g1; ++i) {
+        scls[lay[i].dst_slot] = CB;
+        sidx[lay[i].dst_slot] = row * 64u + (i - g0);
+      }
+      if (!kept) release[end + 1].push_back({CB, row});
+    }
+    for (uint32_t i = nb; i < lay.size(); ++i) {
+      const uint32_t sl = lay[i].dst_slot, c = lay[i].dcls;
+      if (scls[sl] != CNONE || (only_kept && !keep[sl])) continue;
+      const uint32_t idx = keep[sl] ? cnt[c]++ : take(c);
+      scls[sl] = c;
+      sidx[sl] = idx;
+      if (!keep[sl]) release[last[sl] + 1].push_back({c, idx});
+    }
+  };
+  for (uint32_t k = 0; k < NL; ++k) place(k, true);
   h->layers.clear();
   h->light.clear();
   uint32_t pos = 0;
-  for (auto& lay : L) {
+  for (uint32_t k = 0; k < NL; ++k) {
+    auto& lay = L[k];
+    for (const auto& r : release[k]) free_el[r.first].push_back(r.second);
+    place(k, false);
     DevLayer dl{};
     dl.begin = pos;
     dl.end = pos + (uint32_t)lay.size();
-    dl.b_base = (cnt[CB] + 63u) & ~63u;
     uint32_t nb = 0;
-    for (auto& e : lay) {
-      const uint32_t c = e.dcls;
-      uint32_t idx;
-      if (c == CB) idx = dl.b_base + nb++;
-      else idx = cnt[c]++;
-      scls[e.dst_slot] = c;
-      sidx[e.dst_slot] = idx;
-    }
+    while (nb < lay.size() && lay[nb].dcls == CB) ++nb;
+    if (nb) dl.b_base = sidx[lay[0].dst_slot];
     dl.n_bdst = nb;
-    if (nb) cnt[CB] = dl.b_base + nb;
     uint32_t first_heavy = dl.end, n_heavy = 0;
     for (uint32_t i = 0; i < lay.size(); ++i)
       if (heavy(lay[i])) {
@@ -457,6 +517,7 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
     pos = dl.end;
   }
   for (int c = 0; c < NCLS; ++c) h->n_idx[c] = cnt[c];
+  h->compact = compact;
 
   // Rows of one instance: the 1-bit rows (at least one, since absent
   // operands read field 0), then the wide rows.  The wide values are laid out
@@ -465,7 +526,7 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, DesignHost* h) {
   // boundary; Y becomes the field 64*(first wide row + Y/8) + 8*(Y%8), the
   // last term being the 32-bit half's shift.  A 1-bit slot's field is its bit
   // index.
-  const uint64_t b_rows = (std::max<uint64_t>(cnt[CB], 64) + 63) / 64;
+  const uint64_t b_rows = std::max<uint64_t>(cnt[CB], 1);
   uint64_t base[NCLS] = {0};
   uint64_t wb = 0;
   for (uint32_t c = CW; c < NCLS; ++c) {
@@ -886,14 +947,21 @@ rteaal_status rteaal_validate_design(const rteaal_design_desc* desc, char* err, 
 
 rteaal_status rteaal_load_design(rteaal_ctx* ctx, const rteaal_design_desc* desc,
                                  rteaal_design_id* out) {
+  return rteaal_load_design_ex(ctx, desc, 0, out);
+}
+
+rteaal_status rteaal_load_design_ex(rteaal_ctx* ctx, const rteaal_design_desc* desc,
+                                    uint32_t flags, rteaal_design_id* out) {
   if (!ctx || !out) return fail(ctx, RTEAAL_E_INVALID_ARG, "null argument");
+  if (flags & ~uint32_t(RTEAAL_LOAD_KEEP_ALL_SLOTS))
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown load flags %#x", flags);
   if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
   Drivers drv;
   std::string why;
   auto h = std::make_unique<DesignHost>();
   rteaal_status st = validate(desc, &drv, &why, &h->fmt);
   if (st != RTEAAL_OK) return fail(ctx, st, "%s", why.c_str());
-  encode(desc, drv, h.get());
+  encode(desc, drv, !(flags & RTEAAL_LOAD_KEEP_ALL_SLOTS), h.get());
   if (h->n_rows >= (1ull << 26))
     return fail(ctx, RTEAAL_E_UNSUPPORTED, "one instance's state (%llu bytes) exceeds 512 MiB",
                 (unsigned long long)(h->n_rows * 8));
@@ -1241,6 +1309,9 @@ rteaal_status rteaal_read_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t fi
     return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown read kind %u", what);
   DesignHost& h = *find_design(ctx, b->design);
   const bool slots = what == RTEAAL_READ_ALL_SLOTS;
+  if (slots && h.compact)
+    return fail(ctx, RTEAAL_E_UNSUPPORTED,
+                "all-slot read-out needs a design loaded with RTEAAL_LOAD_KEEP_ALL_SLOTS");
   const uint32_t wpi = slots ? h.slot_words : h.reg_words;
   const uint32_t n_refs = slots ? h.n_slots : h.n_regs;
   const size_t need = (size_t)wpi * n;

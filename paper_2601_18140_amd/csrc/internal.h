@@ -51,9 +51,10 @@ __host__ __device__ inline uint32_t op_width(uint32_t w) { return w & 511u; }
 __host__ __device__ inline uint32_t op_imm(uint32_t w) { return (w >> 9) & 511u; }
 
 // One encoded layer: operations [begin, end).  Operations whose destination
-// is 1-bit come first, and the i-th of them writes bit index b_base + i
-// (b_base a multiple of 64), so one wavefront of consecutive operations
-// fills exactly one 64-bit word.  The "heavy" operations (a value wider than
+// is 1-bit come first, and each group of 64 of them (i = 64g .. 64g+63)
+// writes bits 0..63 of one row of its own, so one wavefront of consecutive
+// operations fills exactly one 64-bit word (b_base: the first group's row
+// times 64).  The "heavy" operations (a value wider than
 // 64 bits, or a source: STIM, CONST) form the contiguous range [hbeg, hend)
 // (the last 1-bit destinations and the first others), so the SWEEP mapping
 // runs them in a kernel of their own and keeps the common kernel small.

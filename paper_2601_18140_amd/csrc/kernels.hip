@@ -197,11 +197,12 @@ __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uin
                 }
               }
             }
-            // 1-bit outputs: the wavefront's 64 consecutive operations own one word.
+            // 1-bit outputs: the wavefront's 64 consecutive operations own one
+            // row, named by the first one's destination field (1-bit
+            // destinations lead the layer, so lane 0 holds one when any does).
             const uint64_t m = __ballot(bit != 0ull);
             const uint64_t any = __ballot(bdst);
-            if (any != 0ull && lane == 0)
-              *(uint64_t*)(s + (uint64_t)((ly.b_base + q) >> 6) * 8u) = m;
+            if (any != 0ull && lane == 0) *(uint64_t*)(s + (uint64_t)(op[u].dst >> 6) * 8u) = m;
           }
         }
       }

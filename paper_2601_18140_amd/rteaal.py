@@ -21,6 +21,7 @@ __all__ = [
     "RTEAAL_READ_REGS", "RTEAAL_READ_ALL_SLOTS", "RteaalError", "Context", "library",
     "exported_symbols", "rteaal_create", "rteaal_destroy", "rteaal_last_error",
     "rteaal_validate_design", "rteaal_load_design", "rteaal_unload_design", "rteaal_design_format",
+    "RTEAAL_LOAD_KEEP_ALL_SLOTS",
     "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch", "rteaal_batch_info",
     "rteaal_batch_options",
     "rteaal_step", "rteaal_step_many", "rteaal_sync", "rteaal_read_state", "rteaal_write_state",
@@ -104,6 +105,7 @@ def library():
         "rteaal_last_error": ([vp], C.c_char_p),
         "rteaal_validate_design": ([C.POINTER(rteaal_design_desc), C.c_char_p, C.c_size_t], st),
         "rteaal_load_design": ([vp, C.POINTER(rteaal_design_desc), C.POINTER(u32)], st),
+        "rteaal_load_design_ex": ([vp, C.POINTER(rteaal_design_desc), u32, C.POINTER(u32)], st),
         "rteaal_unload_design": ([vp, u32], st),
         "rteaal_design_format": ([vp, u32, u32, C.POINTER(rteaal_layer_format)], st),
         "rteaal_batch_footprint": ([vp, u32, u32, C.POINTER(rteaal_batch_opts), C.POINTER(u64)], st),
@@ -129,7 +131,8 @@ def library():
 
 def exported_symbols():
     return ["rteaal_create", "rteaal_destroy", "rteaal_last_error", "rteaal_validate_design",
-            "rteaal_load_design", "rteaal_unload_design", "rteaal_design_format",
+            "rteaal_load_design", "rteaal_load_design_ex", "rteaal_unload_design",
+            "rteaal_design_format",
             "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch",
             "rteaal_batch_info", "rteaal_batch_options", "rteaal_step", "rteaal_step_many", "rteaal_sync",
             "rteaal_read_state", "rteaal_write_state", "rteaal_kernel_timing", "rteaal_autotune"]
@@ -267,10 +270,19 @@ def rteaal_validate_design(design, layer_fmt=None):
     return st, buf.value.decode()
 
 
-def rteaal_load_design(ctx, design, layer_fmt=None):
+RTEAAL_LOAD_KEEP_ALL_SLOTS = 1
+
+
+def rteaal_load_design(ctx, design, layer_fmt=None, keep_all_slots=False):
+    """keep_all_slots: every slot keeps its own storage (rteaal_load_design_ex
+    with RTEAAL_LOAD_KEEP_ALL_SLOTS), so RTEAAL_READ_ALL_SLOTS works."""
     d, keep = _desc(design, layer_fmt)
     out = C.c_uint32()
-    _check(ctx.handle, library().rteaal_load_design(ctx.handle, C.byref(d), C.byref(out)))
+    if keep_all_slots:
+        _check(ctx.handle, library().rteaal_load_design_ex(ctx.handle, C.byref(d),
+                                                           RTEAAL_LOAD_KEEP_ALL_SLOTS, C.byref(out)))
+    else:
+        _check(ctx.handle, library().rteaal_load_design(ctx.handle, C.byref(d), C.byref(out)))
     w = np.asarray(design.slot_width, dtype=np.int64)
     regw = w[np.asarray(design.reg_slot, dtype=np.int64)] if design.reg_slot.size else np.zeros(0, np.int64)
     inw = w[np.asarray(design.input_slot, dtype=np.int64)] if design.input_slot.size else np.zeros(0, np.int64)

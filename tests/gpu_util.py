@@ -11,8 +11,22 @@ def gpu_ctx():
 def run_gpu(ctx, design, seeds, steps, mapping=R.RTEAAL_MAP_AUTO, words=None, slots=False,
             **opts):
     """Simulate; `steps` is a cycle count or a list of step sizes.  Returns
-    (regs[n, n_regs, 4], slots[n, n_slots, 4] or None, batch mapping)."""
-    did = R.rteaal_load_design(ctx, design)
+    (regs[n, n_regs, 4], slots[n, n_slots, 4] or None, batch mapping).
+
+    With slots=True the design is loaded with every slot keeping its own
+    storage (so all slots can be read), and the same run is repeated on the
+    default live-range layout, whose registers must be identical."""
+    if slots:
+        regs, sl, used = _run(ctx, design, seeds, steps, mapping, words, True, **opts)
+        regs2, _, used2 = _run(ctx, design, seeds, steps, mapping, words, False, **opts)
+        assert_same(regs2, regs, "live-range layout vs all-slot layout")
+        assert used2 == used
+        return regs, sl, used
+    return _run(ctx, design, seeds, steps, mapping, words, False, **opts)
+
+
+def _run(ctx, design, seeds, steps, mapping, words, slots, **opts):
+    did = R.rteaal_load_design(ctx, design, keep_all_slots=slots)
     try:
         bid = R.rteaal_create_batch(ctx, did, seeds, mapping=mapping, **opts)
         try:

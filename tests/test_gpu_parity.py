@@ -197,6 +197,30 @@ def test_batch_options_round_trip(ctx):
         R.rteaal_unload_design(ctx, did)
 
 
+def test_live_range_layout(ctx):
+    """The default layout reuses storage by live range: its state is smaller
+    than with every slot kept, and all-slot read-out is refused on it."""
+    d = rtlgen.generate(SMALL[1], 29)
+    compact = R.rteaal_load_design(ctx, d)
+    full = R.rteaal_load_design(ctx, d, keep_all_slots=True)
+    try:
+        for m in (R.RTEAAL_MAP_RESIDENT, R.RTEAAL_MAP_SWEEP):
+            a = R.rteaal_batch_footprint(ctx, compact, 128, mapping=m)
+            b = R.rteaal_batch_footprint(ctx, full, 128, mapping=m)
+            assert a < b / 2, (m, a, b)
+        bid = R.rteaal_create_batch(ctx, compact, np.arange(5, dtype=np.uint64))
+        try:
+            R.rteaal_step(ctx, bid, 2)
+            with pytest.raises(R.RteaalError) as err:
+                R.rteaal_read_state(ctx, bid, what=R.RTEAAL_READ_ALL_SLOTS)
+            assert err.value.status == 7   # RTEAAL_E_UNSUPPORTED
+        finally:
+            R.rteaal_free_batch(ctx, bid)
+    finally:
+        R.rteaal_unload_design(ctx, compact)
+        R.rteaal_unload_design(ctx, full)
+
+
 def test_plain_2k_full_run(ctx):
     """The small workload: 2,000 ops, 16 layers, one instance, 10,000 cycles."""
     w = rtlgen.WORKLOADS["plain-2k"]

@@ -225,14 +225,33 @@ def bench_serving(args, R, torch):
     pool = [rtlgen.generate(cfg, seed) for cfg, seed in pool_cfg]
     print(f"[bench] pool of {len(pool)} designs generated in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
+    log = lambda m: print(f"[serve] {m}", file=sys.stderr, flush=True)  # noqa: E731
+    ctx = R.rteaal_create(0)
+    budget = int(args.serving_budget_gb * (1 << 30))
+    rate = args.serving_rate
+    calib = None
+    if args.serving_calibrate:
+        # Saturated throughput: a set of jobs (its own seed) all arriving at
+        # once; the timed stream then arrives at 70 % of that job rate.
+        cspec = rtlgen.serving_jobs(seed=40, n_jobs=args.serving_calibrate, pool_size=len(pool),
+                                    inst_hi=args.serving_inst_hi, cyc_hi=args.serving_cycles_hi)
+        cjobs = [serving.Job(job_id=(1 << 20) + k, design=d, n_inst=n, n_cycles=c)
+                 for k, (d, n, c) in enumerate(cspec)]
+        csrv = serving.Server(ctx, pool, budget_bytes=budget, log=log)
+        cstats = csrv.run(cjobs, np.zeros(len(cjobs)))
+        csrv.close()
+        sat = cstats["jobs"] / cstats["wall_s"]
+        rate = 0.7 * sat
+        calib = {"jobs": cstats["jobs"], "wall_s": round(cstats["wall_s"], 2),
+                 "saturated_jobs_per_s": round(sat, 4), "rate_per_s": round(rate, 4),
+                 "instance_cycles_per_s": round(cstats["instance_cycles_per_s"], 1)}
+        print(f"[bench] serving calibration: {calib}", file=sys.stderr, flush=True)
     n_jobs = args.serving_jobs
     spec = rtlgen.serving_jobs(seed=4, n_jobs=n_jobs, pool_size=len(pool),
                                inst_hi=args.serving_inst_hi, cyc_hi=args.serving_cycles_hi)
     jobs = [serving.Job(job_id=k, design=d, n_inst=n, n_cycles=c) for k, (d, n, c) in enumerate(spec)]
-    arrivals = serving.poisson_arrivals(args.serving_rate, n_jobs, seed=4)
-    ctx = R.rteaal_create(0)
-    srv = serving.Server(ctx, pool, budget_bytes=int(args.serving_budget_gb * (1 << 30)),
-                         log=lambda m: print(f"[serve] {m}", file=sys.stderr, flush=True))
+    arrivals = serving.poisson_arrivals(rate, n_jobs, seed=4)
+    srv = serving.Server(ctx, pool, budget_bytes=budget, log=log)
     stats = srv.run(jobs, arrivals, duration=args.serving_seconds)
     srv.close()
     # Each finished job, re-run alone: identical registers.
@@ -256,8 +275,8 @@ def bench_serving(args, R, torch):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": "serving", "designs": len(pool), "jobs_offered": n_jobs,
-                   "arrival_rate_per_s": args.serving_rate, "admission_seconds": args.serving_seconds,
-                   "budget_gb": args.serving_budget_gb},
+                   "arrival_rate_per_s": round(rate, 4), "admission_seconds": args.serving_seconds,
+                   "budget_gb": args.serving_budget_gb, "calibration": calib},
         "serving": stats, "alone_equals_mix": same, "verified_jobs": len(check),
         "roofline": None, "cpu_baseline": None,
     }
@@ -279,6 +298,9 @@ def main():
     ap.add_argument("--serving-inst-hi", type=int, default=512)
     ap.add_argument("--serving-cycles-hi", type=int, default=50_000)
     ap.add_argument("--serving-verify", type=int, default=8)
+    ap.add_argument("--serving-calibrate", type=int, default=0, metavar="JOBS",
+                    help="first measure the saturated job rate on JOBS jobs arriving at once, "
+                         "then offer the timed stream at 70%% of it")
     ap.add_argument("--cycles-per-step", type=int, default=None)
     ap.add_argument("--instances", type=int, default=None)
     ap.add_argument("--mapping", default="auto", choices=["auto", "resident", "sweep"])

@@ -232,7 +232,7 @@ def bench_serving(args, R, torch):
     calib = None
     if args.serving_calibrate:
         # Saturated throughput: a set of jobs (its own seed) all arriving at
-        # once; the timed stream then arrives at 70 % of that job rate.
+        # once; the timed stream then arrives at --serving-load of that rate.
         cspec = rtlgen.serving_jobs(seed=40, n_jobs=args.serving_calibrate, pool_size=len(pool),
                                     inst_hi=args.serving_inst_hi, cyc_hi=args.serving_cycles_hi)
         cjobs = [serving.Job(job_id=(1 << 20) + k, design=d, n_inst=n, n_cycles=c)
@@ -241,9 +241,10 @@ def bench_serving(args, R, torch):
         cstats = csrv.run(cjobs, np.zeros(len(cjobs)))
         csrv.close()
         sat = cstats["jobs"] / cstats["wall_s"]
-        rate = 0.7 * sat
+        rate = args.serving_load * sat
         calib = {"jobs": cstats["jobs"], "wall_s": round(cstats["wall_s"], 2),
-                 "saturated_jobs_per_s": round(sat, 4), "rate_per_s": round(rate, 4),
+                 "saturated_jobs_per_s": round(sat, 4), "load": args.serving_load,
+                 "rate_per_s": round(rate, 4),
                  "instance_cycles_per_s": round(cstats["instance_cycles_per_s"], 1)}
         print(f"[bench] serving calibration: {calib}", file=sys.stderr, flush=True)
     n_jobs = args.serving_jobs
@@ -300,7 +301,9 @@ def main():
     ap.add_argument("--serving-verify", type=int, default=8)
     ap.add_argument("--serving-calibrate", type=int, default=0, metavar="JOBS",
                     help="first measure the saturated job rate on JOBS jobs arriving at once, "
-                         "then offer the timed stream at 70%% of it")
+                         "then offer the timed stream at --serving-load times it")
+    ap.add_argument("--serving-load", type=float, default=0.7,
+                    help="offered load as a fraction of the calibrated saturated job rate")
     ap.add_argument("--cycles-per-step", type=int, default=None)
     ap.add_argument("--instances", type=int, default=None)
     ap.add_argument("--mapping", default="auto", choices=["auto", "resident", "sweep"])

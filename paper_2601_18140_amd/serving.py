@@ -164,12 +164,19 @@ class Server:
         order = np.argsort(arrival_times)
         start = time.perf_counter()
         k = 0
+        next_status = 15.0
         while k < len(order) or self.queue or self.running:
             now = time.perf_counter() - start
+            if self.log and now >= next_status:
+                self.log(f"t={now:.0f} s: {len(self.running)} running, {len(self.queue)} queued, "
+                         f"{len(self.finished)} finished, {self.instance_cycles} instance-cycles")
+                next_status += 15.0
             while k < len(order) and arrival_times[order[k]] <= now:
                 if duration is None or arrival_times[order[k]] <= duration:
                     self.submit(jobs[order[k]], now=start + arrival_times[order[k]])
                 k += 1
+            if duration is not None and now > duration:
+                k = len(order)   # the admission window has closed
             if not self.running and not self.queue:
                 if k < len(order):
                     time.sleep(max(0.0, min(0.01, arrival_times[order[k]] - now)))

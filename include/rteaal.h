@@ -174,9 +174,14 @@ rteaal_status rteaal_design_format(rteaal_ctx* ctx, rteaal_design_id design, uin
  *             layer.  The plain single-instance form.
  *   SWEEP:    one lane per instance (64 instances per wavefront, 1-bit
  *             signals bit-sliced into 64-bit words), operation records read
- *             once per wavefront; one launch per layer, captured in a HIP
- *             graph per cycle.  The batched form for large designs.
- *   AUTO:     the autotuner's choice for (design, n_instances). */
+ *             once per wavefront for one to eight 64-instance tiles; per
+ *             layer one launch for the operations of at most 64 bits (one per
+ *             operand count in large layers) and one for the wider ones and
+ *             the sources, the cycle captured in a HIP graph.  The batched
+ *             form, and the plain form of large designs.
+ *   AUTO:     the autotuner's choice for (design, n_instances) when
+ *             rteaal_autotune has run for them, else RESIDENT below 32
+ *             instances and SWEEP from 32 on. */
 enum { RTEAAL_MAP_AUTO = 0, RTEAAL_MAP_RESIDENT = 1, RTEAAL_MAP_SWEEP = 2 };
 
 typedef struct {

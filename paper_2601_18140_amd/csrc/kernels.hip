@@ -8,11 +8,14 @@
 //    signal vector LI, and optionally the whole program, live in LDS when
 //    they fit, else LI stays in HBM/L2.
 //
-//  * k_sweep — one lane per instance (64 instances per wavefront), one
-//    launch per layer.  An operation record is read once per wavefront with
-//    scalar loads (shared by 64 instances), each operand gather is one
-//    coalesced row of 64 instance values, and 1-bit signals are bit-sliced so
-//    that one 64-bit word holds the signal for the wavefront's 64 instances.
+//  * k_sweep / k_sweep_heavy — one lane per instance (64 instances per
+//    wavefront, a wavefront covering one to eight such tiles), launched per
+//    layer: k_sweep for the operations of at most 64 bits (per operand count
+//    in large layers), k_sweep_heavy for the wider ones and the sources.  An
+//    operation record is read once per wavefront with scalar loads (shared
+//    by its instances), each operand gather is one coalesced row of 64
+//    instance values per tile, and 1-bit signals are bit-sliced so that one
+//    64-bit word holds the signal for a tile's 64 instances.
 //
 // Within a layer every operation reads only slots written by earlier layers
 // (levelization), so the operations of a layer may run in any order, several

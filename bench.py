@@ -15,6 +15,7 @@ import argparse
 import hashlib
 import json
 import math
+import re
 import os
 import sys
 import time
@@ -93,13 +94,17 @@ def algorithmic_bytes(d):
 
 
 def kernel_sources_sha256():
-    """Hash of the device code (kernels and the record encoding they read)."""
+    """Hash of the device code (kernels and the record encoding they read),
+    comments and whitespace removed, so that only code changes alter it."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2601_18140_amd", "csrc")
     for f in ("internal.h", "kernels.hip", "ops_device.h"):   # device code and its encoding
+        with open(os.path.join(d, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
         h.update(f.encode())
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(fh.read())
+        h.update("".join(text.split()).encode())
     return h.hexdigest()
 
 

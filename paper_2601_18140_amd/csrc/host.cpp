@@ -521,15 +521,15 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
 
   // Rows of one instance: the 1-bit rows (at least one, since absent
   // operands read field 0), then the wide rows.  The wide values are laid out
-  // by byte offset Y in a region of CW elements (4 bytes, two to a row), then
-  // CD, CL2, CL3, CL4 (8 bytes per limb), each class starting on a 16-byte
-  // boundary; Y becomes the field 64*(first wide row + Y/8) + 8*(Y%8), the
-  // last term being the 32-bit half's shift.  A 1-bit slot's field is its bit
-  // index.
+  // by byte offset Y in regions of C8, C16, CW elements (1, 2, 4 bytes, eight,
+  // four, two to a row), then CD, CL2, CL3, CL4 (8 bytes per limb), each
+  // class starting on a 16-byte boundary; Y becomes the field
+  // 64*(first wide row + Y/8) + 8*(Y%8), the last term being the value's bit
+  // offset in its row.  A 1-bit slot's field is its bit index.
   const uint64_t b_rows = std::max<uint64_t>(cnt[CB], 1);
   uint64_t base[NCLS] = {0};
   uint64_t wb = 0;
-  for (uint32_t c = CW; c < NCLS; ++c) {
+  for (uint32_t c = C8; c < NCLS; ++c) {
     base[c] = wb;
     wb = (wb + (uint64_t)cnt[c] * cls_bytes(c) + 15) & ~uint64_t(15);
   }
@@ -643,6 +643,7 @@ bool make_layout(const DesignHost& h, uint32_t mapping, uint32_t n_inst, uint32_
   L.n_rows = (uint32_t)h.n_rows;
   if (mapping == RTEAAL_MAP_SWEEP) {
     tg = (tg == 2 || tg == 4 || tg == 8) ? tg : 1u;
+    L.lg = tg == 8 ? 3u : tg == 4 ? 2u : tg == 2 ? 1u : 0u;
     L.n_tiles = (n_inst + 63) / 64;
     L.n_tiles_alloc = (L.n_tiles + tg - 1) / tg * tg;
     if ((uint64_t)L.n_tiles_alloc * 512 >= (1ull << 32)) return false;

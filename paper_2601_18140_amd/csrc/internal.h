@@ -7,16 +7,29 @@
 
 namespace rteaal {
 
-// Width classes of a slot.  A value of class CB is one bit; CW fits 32 bits;
-// CD fits 64 bits; CL2/CL3/CL4 take 2/3/4 64-bit limbs.
-enum Cls : uint32_t { CB = 0, CW = 1, CD = 2, CL2 = 3, CL3 = 4, CL4 = 5, NCLS = 6, CNONE = 7 };
+// Width classes of a slot.  A value of class CB is one bit; C8, C16 and CW
+// fit 8, 16 and 32 bits and are stored in 1, 2 and 4 bytes; CD fits 64 bits;
+// CL2/CL3/CL4 take 2/3/4 64-bit limbs.  CNONE (host only) marks a slot
+// without storage.
+enum Cls : uint32_t {
+  CB = 0, C8 = 1, C16 = 2, CW = 3, CD = 4, CL2 = 5, CL3 = 6, CL4 = 7, NCLS = 8, CNONE = 15
+};
 
-__host__ __device__ inline uint32_t cls_limbs(uint32_t c) { return c <= CD ? 1u : c - 1u; }
+__host__ __device__ inline uint32_t cls_limbs(uint32_t c) { return c <= CD ? 1u : c - 3u; }
 __host__ __device__ inline uint32_t cls_of_width(uint32_t w) {
-  return w == 1 ? CB : w <= 32 ? CW : w <= 64 ? CD : w <= 128 ? CL2 : w <= 192 ? CL3 : CL4;
+  return w == 1 ? CB : w <= 8 ? C8 : w <= 16 ? C16 : w <= 32 ? CW : w <= 64 ? CD
+       : w <= 128 ? CL2 : w <= 192 ? CL3 : CL4;
+}
+// log2(64 / element bits) of class c: 6 for CB, 3 for C8, 2 for C16, 1 for
+// CW, 0 for CD and the limbs of wider values.  64 >> cls_w3(c) elements
+// share one 64-bit word.
+__host__ __device__ inline uint32_t cls_w3(uint32_t c) {
+  return c < CD ? (0x1236u >> (4u * c)) & 15u : 0u;
 }
 // Bytes one value of class c takes in an instance's wide region (c != CB).
-__host__ __device__ inline uint32_t cls_bytes(uint32_t c) { return c == CW ? 4u : 8u * cls_limbs(c); }
+__host__ __device__ inline uint32_t cls_bytes(uint32_t c) {
+  return c <= CW ? (8u >> cls_w3(c)) : 8u * cls_limbs(c);
+}
 
 // Operation codes: the public rank-N coordinates 0..14 plus three
 // bookkeeping operations the encoder adds around the design's layers:
@@ -94,30 +107,33 @@ struct DevCtl {
 //
 // An instance's stored values occupy 64-bit rows: the first rows each hold
 // 64 1-bit slots (bit k of row r is 1-bit slot 64r + k), the remaining rows
-// ("wide rows") each hold two 32-bit values (low and high half), one 64-bit
-// value, or one limb of a wider value (limb l of a value in row r is in row
-// r + l).  A slot is named by one 32-bit field f = 64*row + shift, where
-// shift is the bit index for a 1-bit slot, 0 or 32 for a 32-bit value and 0
-// otherwise; a 1-bit slot's field is its bit index.  Operation records carry
-// these fields, so one record format serves both mappings:
+// ("wide rows") each hold eight 8-bit, four 16-bit or two 32-bit values, one
+// 64-bit value, or one limb of a wider value (limb l of a value in row r is
+// in row r + l).  A slot is named by one 32-bit field f = 64*row + shift,
+// where shift is the bit offset of the value in its row (the bit index for a
+// 1-bit slot, a multiple of the element size otherwise).  Operation records
+// carry these fields, so one record format serves both mappings:
 //   RESIDENT, instance j at j*pitch: row r at 8r; the value is the row's
 //     word shifted down by `shift` (then cut to the class).
-//   SWEEP, tile t = j / 64, lane = j % 64 (T = allocated tiles, row_bytes =
-//     512 T, so the 1-bit rows take the same bytes as in a per-tile layout):
-//     1-bit slot i: the bit-sliced word (bit `lane` = the instance's value)
-//       at 8 (i T + t): slot-major, the words of consecutive tiles adjacent;
-//     wide row r: interleaved over tiles, tile t's 512 bytes at
-//       r row_bytes + 512 t holding the 64 lanes' values, 32-bit ones at
-//       8 shift + 4 lane, the others at 8 lane.  The byte address of a wide
-//       slot f for tile t is thus (f / 64) row_bytes + 8 (f % 64) + 512 t,
-//       plus the lane's part.
+//   SWEEP, tile t = j / 64, lane = j % 64, tiles in groups of G = 2^lg
+//     (T = allocated tiles, a multiple of G; row_bytes = 512 T): row r takes
+//     512 bytes per tile, grouped by tile group, so group q's part of row r
+//     starts at r row_bytes + 512 G q.  Inside it, the value at shift s
+//     occupies 8 G s bytes on: the G tiles' element blocks in tile order,
+//     64 elements of e bytes each (a 1-bit value: one 64-bit word per tile,
+//     bit `lane` = the instance's value).  For the element size e (1/8 for
+//     1-bit values), the byte address of slot f for tile t = G q + u is
+//       (f / 64) row_bytes + 512 G q + 8 G (f % 64) + 64 e u + e lane,
+//     so the G tiles of one value are contiguous: a wavefront covering a
+//     tile group reads one block of 64 G e bytes per operand.
 struct StateLayout {
   uint64_t pitch;          // RESIDENT: bytes per instance (multiple of 16)
   uint32_t row_bytes;      // SWEEP: bytes of one row over all allocated tiles
   uint32_t n_rows;         // 64-bit rows per instance
   uint32_t n_tiles;        // SWEEP: tiles that hold instances
   uint32_t n_tiles_alloc;  // SWEEP: allocated tiles, a multiple of the tile group
-  uint32_t pad[2];
+  uint32_t lg;             // SWEEP: log2 of the tile group of the layout
+  uint32_t pad;
 };
 
 struct Program {

@@ -54,19 +54,24 @@ __device__ __forceinline__ V4 source_value(const uint64_t* const_limbs, const De
 // RESIDENT: per-instance state block at `s` (LDS or global).
 // ---------------------------------------------------------------------------
 
+// Low-bit mask of a value of class c (all 64 bits for CD and for limbs).
+__device__ __forceinline__ uint64_t cls_mask64(uint32_t c) {
+  const uint32_t w3 = cls_w3(c);
+  return w3 == 0u ? ~0ull : (1ull << (64u >> w3)) - 1ull;
+}
+
 // Operand fetch without branches: one aligned 8-byte load per operand, the
 // row named by the slot field, shifted down by the field's shift; only the
 // final cut depends on the class.  Absent operands (arity < 3) carry field 0
 // of class CB and read a valid word that is never used.
 __device__ __forceinline__ uint64_t res_fetch(const char* s, uint32_t cls, uint32_t f) {
   const uint64_t v = *(const uint64_t*)(s + (uint64_t)(f >> 6) * 8u) >> (f & 63u);
-  return cls == CB ? v & 1ull : cls == CW ? v & 0xffffffffull : v;
+  return v & cls_mask64(cls);
 }
 
 __device__ __forceinline__ V4 res_ldv(const char* s, uint32_t cls, uint32_t f) {
+  if (cls <= CW) return v4_from(res_fetch(s, cls, f));
   const char* q = s + (uint64_t)(f >> 6) * 8u;
-  if (cls == CB) return v4_from((*(const uint64_t*)q >> (f & 63u)) & 1ull);
-  if (cls == CW) return v4_from(*(const uint32_t*)(q + ((f & 63u) >> 3)));
   const uint32_t k = cls_limbs(cls);
   V4 r = v4_from(*(const uint64_t*)q);
   if (k > 1) r.l[1] = *(const uint64_t*)(q + 8);
@@ -75,18 +80,22 @@ __device__ __forceinline__ V4 res_ldv(const char* s, uint32_t cls, uint32_t f) {
   return r;
 }
 
+// Store of a value of class C8..CD at its byte offset in the row (values of
+// these classes never straddle a row).
 __device__ __forceinline__ void res_st64(char* s, uint32_t cls, uint32_t f, uint64_t v) {
-  char* q = s + (uint64_t)(f >> 6) * 8u;
-  if (cls == CW) *(uint32_t*)(q + ((f & 63u) >> 3)) = (uint32_t)v;
+  char* q = s + (uint64_t)(f >> 6) * 8u + ((f & 63u) >> 3);
+  if (cls == C8) *(uint8_t*)q = (uint8_t)v;
+  else if (cls == C16) *(uint16_t*)q = (uint16_t)v;
+  else if (cls == CW) *(uint32_t*)q = (uint32_t)v;
   else *(uint64_t*)q = v;
 }
 
 __device__ __forceinline__ void res_stv(char* s, uint32_t cls, uint32_t f, const V4& v) {
-  char* q = s + (uint64_t)(f >> 6) * 8u;
-  if (cls == CW) {
-    *(uint32_t*)(q + ((f & 63u) >> 3)) = (uint32_t)v.l[0];
+  if (cls <= CD) {
+    res_st64(s, cls, f, v.l[0]);
     return;
   }
+  char* q = s + (uint64_t)(f >> 6) * 8u;
   const uint32_t k = cls_limbs(cls);
   *(uint64_t*)q = v.l[0];
   if (k > 1) *(uint64_t*)(q + 8) = v.l[1];
@@ -237,82 +246,75 @@ k_resident_multi(const ResJob* __restrict__ jobs, const uint2* __restrict__ map)
 }
 
 // ---------------------------------------------------------------------------
-// SWEEP: lane = instance.  A wavefront owns TG consecutive tiles.
-//  * 1-bit slots are slot-major: the TG words of slot i for the wavefront's
-//    tiles are contiguous, so one scalar load brings them all in, and the
-//    results of a 1-bit destination leave as one TG-lane store.
-//  * Wide rows are tile-interleaved: the row address is found once per
-//    operation (scalar arithmetic on the record's field) and the wavefront's
-//    tiles sit at fixed 512-byte steps from it, so per tile only the load or
-//    store immediate changes.
+// SWEEP: lane = instance.  A wavefront owns TG consecutive tiles of one tile
+// group of the layout (TG divides the group).  A value's blocks for the
+// tiles of a group are contiguous (StateLayout), so each operand of an
+// operation is one contiguous block of 64 TG e bytes for the wavefront, e
+// being the element size (1/8 for 1-bit values): every class is gathered
+// with one load per tile at base + this lane's offset + g * (64 e), with no
+// branch on the class.  The value's address is found once per operation by
+// scalar arithmetic on the record's field.
 // ---------------------------------------------------------------------------
 struct SweepView {
-  char* base;          // state + 512 * (first tile): wide rows
-  char* bits;          // state + 8 * (first tile): 1-bit words
-  uint32_t row_bytes;  // bytes of one wide row over all allocated tiles
-  uint32_t nta;        // allocated tiles (words per 1-bit slot)
+  char* base;          // state + 512 * (first tile of the wavefront's tile group)
+  uint32_t row_bytes;  // bytes of one row over all allocated tiles
+  uint32_t lg3;        // 3 + log2(tile group): (f % 64) << lg3 = 8 G (f % 64)
+  uint32_t tt0;        // the wavefront's first tile within its group
   uint32_t lane;
 
   __device__ __forceinline__ SweepView(char* state, const StateLayout& L, uint32_t tile0,
                                        uint32_t ln)
-      : base(state + (uint64_t)tile0 * 512u), bits(state + (uint64_t)tile0 * 8u),
-        row_bytes(L.row_bytes), nta(L.n_tiles_alloc), lane(ln) {}
+      : row_bytes(L.row_bytes), lg3(3u + L.lg), tt0(tile0 & ((1u << L.lg) - 1u)), lane(ln) {
+    base = state + (uint64_t)(tile0 - tt0) * 512u;
+  }
 
-  // Start of the 64 lane values of wide slot f in the wavefront's first tile.
-  __device__ __forceinline__ char* row(uint32_t f) const {
-    return base + (uint64_t)(f >> 6) * row_bytes + ((f & 63u) << 3);
+  // Block of value f for tile tt0 + g, elements of 8 >> w3 bytes (w3 = 6:
+  // the 64-bit word of a 1-bit value).
+  __device__ __forceinline__ char* at(uint32_t f, uint32_t w3, uint32_t g) const {
+    return base + (uint64_t)(f >> 6) * row_bytes + ((f & 63u) << lg3) + (tt0 + g) * (512u >> w3);
   }
-  // Word of 1-bit slot i for the wavefront's first tile (the next TG-1 tiles
-  // follow it).
-  __device__ __forceinline__ uint64_t word_off(uint32_t i) const { return (uint64_t)i * nta * 8u; }
-  // Operand gather without branches: one 8-byte load per tile from
-  // base + this lane's offset + g * step.
-  //   CB: base = the slot's word for the first tile, step 8, offset 0 (one
-  //       word for the whole wavefront; the TG words are contiguous);
-  //   CW: base = the row, step 512, offset = the aligned word holding this
-  //       lane's value (lanes 2k and 2k+1 share it, so a row is read once);
-  //   others: base = the row, step 512, offset = the lane's own value.
-  __device__ __forceinline__ const char* gather_base(uint32_t cls, uint32_t f) const {
-    return cls == CB ? bits + word_off(f) : (const char*)row(f);
+
+  // This lane's element in a 32-bit gather: byte offset of the aligned 4-byte
+  // word holding it and its bit offset there (classes CB..CW).
+  __device__ __forceinline__ uint32_t off32(uint32_t w3) const {
+    return ((lane << (6u - w3)) >> 5) << 2;
   }
-  __device__ __forceinline__ uint32_t ld_off(uint32_t cls) const {
-    const uint32_t w = cls == CW ? 1u : 0u;
-    const uint32_t mask = (cls == CB ? 0u : ~0u) & ~(w * 7u);
-    return (lane << (3u - w)) & mask;
+  __device__ __forceinline__ uint32_t sh32(uint32_t w3) const { return (lane << (6u - w3)) & 31u; }
+  // The same for a 64-bit gather (classes CB..CD).
+  __device__ __forceinline__ uint32_t off64(uint32_t w3) const {
+    return ((lane << (6u - w3)) >> 6) << 3;
   }
-  // The operand's value in this lane from its loaded word (CB: the
-  // wavefront's bit-sliced word).
-  __device__ __forceinline__ uint32_t lane_val32(uint32_t cls, uint64_t raw) const {
-    const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
-    return cls == CB ? (uint32_t)((raw >> lane) & 1ull) : (lane & 1u) ? hi : lo;
-  }
-  __device__ __forceinline__ uint64_t lane_val(uint32_t cls, uint64_t raw) const {
-    return cls == CB ? (raw >> lane) & 1ull
-         : cls == CW ? (raw >> ((lane & 1u) * 32u)) & 0xffffffffull : raw;
-  }
+  __device__ __forceinline__ uint32_t sh64(uint32_t w3) const { return (lane << (6u - w3)) & 63u; }
+
   // 1-bit results of the TG tiles (wave-uniform words): lane g stores tile g's
   // word, one contiguous store for the wavefront.  The word is picked with
   // masks rather than a select chain, which the compiler would turn into an
   // indexed (scratch) array.
   template <int TG>
-  __device__ __forceinline__ void st_bits(uint32_t i, const uint64_t* m) const {
+  __device__ __forceinline__ void st_bits(uint32_t f, const uint64_t* m) const {
     uint64_t mine = 0;
 #pragma unroll
     for (int g = 0; g < TG; ++g) mine |= m[g] & (0ull - (uint64_t)(lane == (uint32_t)g));
-    if (lane < (uint32_t)TG) *(uint64_t*)(bits + word_off(i) + lane * 8u) = mine;
+    if (lane < (uint32_t)TG) *(uint64_t*)(at(f, 6u, 0u) + lane * 8u) = mine;
   }
-  __device__ __forceinline__ void st32(char* r, uint32_t g, uint32_t x) const {
-    *(uint32_t*)(r + g * 512u + lane * 4u) = x;
+  // Store of this lane's value of class C8..CD for tile tt0 + g; r = at(f, w3, 0).
+  __device__ __forceinline__ void st_el(uint32_t cls, char* r, uint32_t w3, uint32_t g,
+                                        uint64_t x) const {
+    char* q = r + g * (512u >> w3) + (lane << 3 >> w3);
+    if (cls == C8) *(uint8_t*)q = (uint8_t)x;
+    else if (cls == C16) *(uint16_t*)q = (uint16_t)x;
+    else if (cls == CW) *(uint32_t*)q = (uint32_t)x;
+    else *(uint64_t*)q = x;
   }
-  __device__ __forceinline__ void st64(uint32_t cls, char* r, uint32_t g, uint64_t x) const {
-    if (cls == CW) st32(r, g, (uint32_t)x);
-    else *(uint64_t*)(r + g * 512u + lane * 8u) = x;
-  }
+  // Whole values of any class for the heavy kernel.
   __device__ __forceinline__ V4 ldv(uint32_t cls, uint32_t f, uint32_t g) const {
-    if (cls == CB) return v4_from((*(const uint64_t*)(bits + word_off(f) + g * 8u) >> lane) & 1ull);
-    const char* q = row(f) + g * 512u;
-    if (cls == CW) return v4_from(*(const uint32_t*)(q + lane * 4u));
-    q += lane * 8u;
+    const uint32_t w3 = cls_w3(cls);
+    const char* q = at(f, w3, g);
+    if (cls == CB) return v4_from((*(const uint64_t*)q >> lane) & 1ull);
+    q += lane << 3 >> w3;
+    if (cls == C8) return v4_from(*(const uint8_t*)q);
+    if (cls == C16) return v4_from(*(const uint16_t*)q);
+    if (cls == CW) return v4_from(*(const uint32_t*)q);
     const uint32_t k = cls_limbs(cls);
     V4 x = v4_from(*(const uint64_t*)q);
     if (k > 1) x.l[1] = *(const uint64_t*)(q + row_bytes);
@@ -321,9 +323,10 @@ struct SweepView {
     return x;
   }
   __device__ __forceinline__ void stv(uint32_t cls, uint32_t f, uint32_t g, const V4& x) const {
-    char* r = row(f);
-    if (cls == CW) {
-      st32(r, g, (uint32_t)x.l[0]);
+    const uint32_t w3 = cls_w3(cls);
+    char* r = at(f, w3, 0u);
+    if (cls <= CD) {
+      st_el(cls, r, w3, g, x.l[0]);
       return;
     }
     char* q = r + g * 512u + lane * 8u;
@@ -335,16 +338,162 @@ struct SweepView {
   }
 };
 
-// Common operations of one layer (every value at most 64 bits, no source)
-// with NS operands, NS = 1, 2 or 3: the ranges [r.b0, r.e0) and [r.b1, r.e1);
-// the first `split` chunks cover the first.  A kernel per operand count keeps
-// absent operands from costing loads and registers.
-// A wavefront handles a chunk of operations for TG tiles (64 instances each).
-// Operations are processed U at a time: first the U records (scalar loads,
-// decoded once for all TG tiles), then every operand for every tile (NS*U*TG
-// gathers in flight per wavefront), then the evaluations and stores.  Tiles
-// past the last instance (allocation padding up to a multiple of TG) are
-// evaluated like the others and never read back.
+// Every gathered word counts as used on every path (unary operators, absent
+// operands ignore some of them), so that no load is still in flight when the
+// next group's loads reuse its registers: otherwise the top of the loop
+// would also wait for this group's stores.
+template <class T, int N>
+__device__ __forceinline__ void keep_loaded(const T (&x)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) asm volatile("" ::"v"(x[i]));
+}
+
+// U operations whose classes all fit 32 bits: one 4-byte load per operand
+// and tile, the lane's element cut out with a shift and a mask.
+template <int U, int TG, int NS>
+__device__ __forceinline__ void sweep_u32(const SweepView& v, const DevOp* op, uint32_t n_valid) {
+  uint32_t raw[U * NS * TG];
+  uint32_t sh[U * NS], m[U * NS];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const uint32_t cls = op_scls(op[u].code, k), w3 = cls_w3(cls);
+      const char* p = v.at(op[u].src[k], w3, 0u) + v.off32(w3);
+      const uint32_t step = 512u >> w3;
+      sh[u * NS + k] = v.sh32(w3);
+      m[u * NS + k] = w3 == 1u ? ~0u : (1u << (64u >> w3)) - 1u;
+#pragma unroll
+      for (int g = 0; g < TG; ++g) raw[(u * NS + k) * TG + g] = *(const uint32_t*)(p + g * step);
+    }
+  keep_loaded(raw);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if ((uint32_t)u < n_valid) {
+      const DevOp& q = op[u];
+      const uint32_t code = q.code, opc = op_opc(code), ar = op_arity(code);
+      const uint32_t dc = op_dcls(code), w = op_width(q.wimm), imm = op_imm(q.wimm);
+      uint32_t a[TG], b[TG], c[TG], r[TG];
+#pragma unroll
+      for (int g = 0; g < TG; ++g) {
+        a[g] = (raw[(u * NS) * TG + g] >> sh[u * NS]) & m[u * NS];
+        b[g] = c[g] = 0u;
+        if constexpr (NS > 1) b[g] = (raw[(u * NS + 1) * TG + g] >> sh[u * NS + 1]) & m[u * NS + 1];
+        if constexpr (NS > 2) c[g] = (raw[(u * NS + 2) * TG + g] >> sh[u * NS + 2]) & m[u * NS + 2];
+      }
+      eval_u32_n<TG>(opc, ar, a, b, c, imm, w, r);
+      if (dc == CB) {
+        uint64_t bits[TG];
+#pragma unroll
+        for (int g = 0; g < TG; ++g) bits[g] = __ballot((r[g] & 1u) != 0u);
+        v.st_bits<TG>(q.dst, bits);
+      } else {
+        const uint32_t w3 = cls_w3(dc);
+        char* rd = v.at(q.dst, w3, 0u);
+#pragma unroll
+        for (int g = 0; g < TG; ++g) v.st_el(dc, rd, w3, g, r[g]);
+      }
+    }
+  }
+}
+
+// U operations with a value of 33..64 bits: one 8-byte load per operand and
+// tile.
+template <int U, int TG, int NS>
+__device__ __forceinline__ void sweep_u64(const SweepView& v, const DevOp* op, uint32_t n_valid) {
+  uint64_t raw[U * NS * TG];
+  uint32_t sh[U * NS];
+  uint64_t m[U * NS];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const uint32_t cls = op_scls(op[u].code, k), w3 = cls_w3(cls);
+      const char* p = v.at(op[u].src[k], w3, 0u) + v.off64(w3);
+      const uint32_t step = 512u >> w3;
+      sh[u * NS + k] = v.sh64(w3);
+      m[u * NS + k] = w3 == 0u ? ~0ull : (1ull << (64u >> w3)) - 1ull;
+#pragma unroll
+      for (int g = 0; g < TG; ++g) raw[(u * NS + k) * TG + g] = *(const uint64_t*)(p + g * step);
+    }
+  keep_loaded(raw);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if ((uint32_t)u < n_valid) {
+      const DevOp& q = op[u];
+      const uint32_t code = q.code, opc = op_opc(code), ar = op_arity(code);
+      const uint32_t dc = op_dcls(code), w = op_width(q.wimm), imm = op_imm(q.wimm);
+      uint64_t r[TG];
+#pragma unroll
+      for (int g = 0; g < TG; ++g) {
+        const uint64_t a = (raw[(u * NS) * TG + g] >> sh[u * NS]) & m[u * NS];
+        uint64_t b = 0, c = 0;
+        if constexpr (NS > 1) b = (raw[(u * NS + 1) * TG + g] >> sh[u * NS + 1]) & m[u * NS + 1];
+        if constexpr (NS > 2) c = (raw[(u * NS + 2) * TG + g] >> sh[u * NS + 2]) & m[u * NS + 2];
+        r[g] = eval_u64(opc, ar, a, b, c, imm, w);
+      }
+      if (dc == CB) {
+        uint64_t bits[TG];
+#pragma unroll
+        for (int g = 0; g < TG; ++g) bits[g] = __ballot((r[g] & 1ull) != 0ull);
+        v.st_bits<TG>(q.dst, bits);
+      } else {
+        const uint32_t w3 = cls_w3(dc);
+        char* rd = v.at(q.dst, w3, 0u);
+#pragma unroll
+        for (int g = 0; g < TG; ++g) v.st_el(dc, rd, w3, g, r[g]);
+      }
+    }
+  }
+}
+
+// U operations on 1-bit values only: the tiles' bit-sliced words, the same
+// for every lane, evaluated word-wide.
+template <int U, int TG, int NS>
+__device__ __forceinline__ void sweep_bit(const SweepView& v, const DevOp* op, uint32_t n_valid) {
+  uint64_t raw[U * 3 * TG];
+#pragma unroll
+  for (int i = NS * TG; i < 3 * TG; ++i)
+#pragma unroll
+    for (int u = 0; u < U; ++u) raw[u * 3 * TG + i] = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const char* p = v.at(op[u].src[k], 6u, 0u);
+#pragma unroll
+      for (int g = 0; g < TG; ++g) raw[(u * 3 + k) * TG + g] = *(const uint64_t*)(p + g * 8u);
+    }
+  keep_loaded(raw);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if ((uint32_t)u < n_valid) {
+      const DevOp& q = op[u];
+      const uint32_t code = q.code, opc = op_opc(code), ar = op_arity(code);
+      uint64_t bits[TG];
+#pragma unroll
+      for (int g = 0; g < TG; ++g)
+        bits[g] = eval_bits(opc, ar, raw[(u * 3) * TG + g], raw[(u * 3 + 1) * TG + g],
+                            raw[(u * 3 + 2) * TG + g], op_imm(q.wimm));
+      v.st_bits<TG>(q.dst, bits);
+    }
+  }
+}
+
+template <int U, int TG, int NS>
+__device__ __forceinline__ void sweep_group(const SweepView& v, const DevOp* op, uint32_t n_valid,
+                                            uint32_t kind) {
+  if (kind == K_U32) sweep_u32<U, TG, NS>(v, op, n_valid);
+  else if (kind == K_U64) sweep_u64<U, TG, NS>(v, op, n_valid);
+  else sweep_bit<U, TG, NS>(v, op, n_valid);
+}
+
+// The common operations (at most 64 bits, no source) of the ranges r with NS
+// operand gathers each (NS >= the arity of every operation in r; absent
+// operands read field 0 of class CB, a valid word).  Wave w runs the
+// operation chunk w / n_groups (opw operations) on tile group w % n_groups.
+// Operations of a chunk run U at a time when the U share their evaluation
+// kind (ranges are sorted by kind, so mixed groups are rare), else one by one.
 template <int U, int TG, int NS>
 __global__ void __launch_bounds__(256)
 k_sweep(const DevOp* __restrict__ ops, StateLayout L, char* __restrict__ state, OpRanges r,
@@ -358,100 +507,27 @@ k_sweep(const DevOp* __restrict__ ops, StateLayout L, char* __restrict__ state, 
   const uint32_t oe = first ? r.e0 : r.e1;
   if (o0 >= oe) return;
   const uint32_t o1 = min(o0 + opw, oe);
-  const uint32_t tile0 = tile_base + grp * TG;
-  const SweepView v(state, L, tile0, lane);
+  const SweepView v(state, L, tile_base + grp * TG, lane);
 
   for (uint32_t o = o0; o < o1; o += U) {
     DevOp op[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) op[u] = ops[min(o + (uint32_t)u, o1 - 1u)];
-    uint64_t raw[U][3][TG];
+    const uint32_t n_valid = min((uint32_t)U, o1 - o);
+    const uint32_t k0 = op_kind(op[0].code);
+    bool same = true;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t code = op[u].code;
+    for (int u = 1; u < U; ++u) same = same && ((uint32_t)u >= n_valid || op_kind(op[u].code) == k0);
+    if (same) {
+      sweep_group<U, TG, NS>(v, op, n_valid, k0);
+    } else {
 #pragma unroll
-      for (int k = NS; k < 3; ++k)
-#pragma unroll
-        for (int g = 0; g < TG; ++g) raw[u][k][g] = 0;
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        const uint32_t cls = op_scls(code, k);
-        const char* p = v.gather_base(cls, op[u].src[k]) + v.ld_off(cls);
-        const uint32_t step = cls == CB ? 8u : 512u;
-#pragma unroll
-        for (int g = 0; g < TG; ++g) raw[u][k][g] = *(const uint64_t*)(p + g * step);
-      }
-    }
-    // Every gathered word counts as used on every path (unary operators,
-    // absent operands ignore some of them), so that no load is still in
-    // flight when the next group's loads reuse its registers: otherwise the
-    // top of the loop would also wait for this group's stores.
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int k = 0; k < NS; ++k)
-#pragma unroll
-        for (int g = 0; g < TG; ++g) asm volatile("" ::"v"(raw[u][k][g]));
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (o + u < o1) {
-        const DevOp& q = op[u];
-        const uint32_t code = q.code, opc = op_opc(code), ar = op_arity(code), kind = op_kind(code);
-        const uint32_t dc = op_dcls(code), w = op_width(q.wimm), imm = op_imm(q.wimm);
-        const uint32_t c0 = op_scls(code, 0), c1 = op_scls(code, 1), c2 = op_scls(code, 2);
-        if (kind == K_BIT) {
-          uint64_t m[TG];
-#pragma unroll
-          for (int g = 0; g < TG; ++g)
-            m[g] = eval_bits(opc, ar, raw[u][0][g], raw[u][1][g], raw[u][2][g], imm);
-          v.st_bits<TG>(q.dst, m);
-        } else if (kind == K_U32) {
-          uint32_t a[TG], b[TG], c[TG], r[TG];
-#pragma unroll
-          for (int g = 0; g < TG; ++g) {
-            a[g] = v.lane_val32(c0, raw[u][0][g]);
-            b[g] = v.lane_val32(c1, raw[u][1][g]);
-            c[g] = v.lane_val32(c2, raw[u][2][g]);
-          }
-          eval_u32_n<TG>(opc, ar, a, b, c, imm, w, r);
-          if (dc == CB) {
-            uint64_t m[TG];
-#pragma unroll
-            for (int g = 0; g < TG; ++g) m[g] = __ballot((r[g] & 1u) != 0u);
-            v.st_bits<TG>(q.dst, m);
-          } else {
-            char* rd = v.row(q.dst);
-#pragma unroll
-            for (int g = 0; g < TG; ++g) v.st32(rd, g, r[g]);
-          }
-        } else {  // K_U64
-          uint64_t r[TG];
-#pragma unroll
-          for (int g = 0; g < TG; ++g) {
-            const uint64_t a = v.lane_val(c0, raw[u][0][g]);
-            const uint64_t b = v.lane_val(c1, raw[u][1][g]);
-            const uint64_t c = v.lane_val(c2, raw[u][2][g]);
-            r[g] = eval_u64(opc, ar, a, b, c, imm, w);
-          }
-          if (dc == CB) {
-            uint64_t m[TG];
-#pragma unroll
-            for (int g = 0; g < TG; ++g) m[g] = __ballot((r[g] & 1ull) != 0ull);
-            v.st_bits<TG>(q.dst, m);
-          } else {
-            char* rd = v.row(q.dst);
-#pragma unroll
-            for (int g = 0; g < TG; ++g) v.st64(dc, rd, g, r[g]);
-          }
-        }
-      }
+      for (int u = 0; u < U; ++u)
+        if ((uint32_t)u < n_valid) sweep_group<1, TG, NS>(v, &op[u], 1u, op_kind(op[u].code));
     }
   }
 }
 
-// Heavy operations of one layer, [hbeg, hend): values wider than 64 bits
-// (limb arithmetic on up to four 64-bit limbs) and the sources (stimulus
-// words and literals).  One operation at a time per wavefront, for TG tiles.
 template <int TG>
 __global__ void __launch_bounds__(256)
 k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
@@ -520,13 +596,15 @@ __device__ __forceinline__ char* elem_addr(bool sweep, const StateLayout& L, cha
                                            uint32_t inst, uint32_t* bitpos) {
   const uint64_t row = (f >> 6) + limb;
   if (sweep) {
-    const uint32_t t = inst >> 6, ln = inst & 63u;
+    const uint32_t t = inst >> 6, ln = inst & 63u, tt = t & ((1u << L.lg) - 1u);
+    const uint32_t w3 = cls_w3(cls);
+    char* r = state + row * L.row_bytes + (uint64_t)(t - tt) * 512u + ((f & 63u) << (3u + L.lg)) +
+              tt * (512u >> w3);
     if (cls == CB) {
       *bitpos = ln;
-      return state + ((uint64_t)f * L.n_tiles_alloc + t) * 8u;
+      return r;
     }
-    return state + row * L.row_bytes + (uint64_t)t * 512u + ((f & 63u) << 3) +
-           ln * (cls == CW ? 4u : 8u);
+    return r + (ln << 3 >> w3);
   }
   char* r = state + (uint64_t)inst * L.pitch + row * 8u;
   if (cls == CB) {
@@ -551,6 +629,8 @@ __global__ void k_pack(bool sweep, StateLayout L, const char* state, const SlotR
       uint32_t bp = 0;
       const char* e = elem_addr(sweep, L, (char*)state, ref.cls, ref.pos, l, inst, &bp);
       if (ref.cls == CB) x = (*(const uint64_t*)e >> bp) & 1ull;
+      else if (ref.cls == C8) x = *(const uint8_t*)e;
+      else if (ref.cls == C16) x = *(const uint16_t*)e;
       else if (ref.cls == CW) x = *(const uint32_t*)e;
       else x = *(const uint64_t*)e;
     }
@@ -580,8 +660,11 @@ __global__ void k_unpack(bool sweep, StateLayout L, char* state, const SlotRef* 
         (unsigned long long*)elem_addr(sweep, L, state, CB, ref.pos, 0, inst, &bp);
     if (v.l[0] & 1ull) atomicOr(e, 1ull << bp);
     else atomicAnd(e, ~(1ull << bp));
-  } else if (ref.cls == CW) {
-    *(uint32_t*)elem_addr(sweep, L, state, CW, ref.pos, 0, inst, &bp) = (uint32_t)v.l[0];
+  } else if (ref.cls <= CW) {
+    char* e = elem_addr(sweep, L, state, ref.cls, ref.pos, 0, inst, &bp);
+    if (ref.cls == C8) *(uint8_t*)e = (uint8_t)v.l[0];
+    else if (ref.cls == C16) *(uint16_t*)e = (uint16_t)v.l[0];
+    else *(uint32_t*)e = (uint32_t)v.l[0];
   } else {
     const uint32_t k2 = cls_limbs(ref.cls);
 #pragma unroll
@@ -682,10 +765,11 @@ hipError_t launch_resident_multi(const ResJob* jobs, const uint2* map, uint32_t 
   return dispatch_res<ResMany>(lds_state, lds_ops, unroll, jobs, map, n_blocks, block, lds, s);
 }
 
-// A tile pass must lie inside the allocated tiles and be whole tile groups.
+// A tile pass must lie inside the allocated tiles and be whole tile groups
+// of the wavefront, each inside one tile group of the layout.
 static bool pass_ok(const StateLayout& L, TilePass tp, uint32_t tg) {
   return tp.count > 0 && tp.count % tg == 0 && tp.base % tg == 0 &&
-         (uint64_t)tp.base + tp.count <= L.n_tiles_alloc;
+         (uint64_t)tp.base + tp.count <= L.n_tiles_alloc && ((1u << L.lg) % tg) == 0;
 }
 
 hipError_t launch_sweep_light(const Program& p, const StateLayout& L, char* state,

@@ -20,12 +20,10 @@ __host__ __device__ inline uint32_t cls_of_width(uint32_t w) {
   return w == 1 ? CB : w <= 8 ? C8 : w <= 16 ? C16 : w <= 32 ? CW : w <= 64 ? CD
        : w <= 128 ? CL2 : w <= 192 ? CL3 : CL4;
 }
-// log2(64 / element bits) of class c: 6 for CB, 3 for C8, 2 for C16, 1 for
-// CW, 0 for CD and the limbs of wider values.  64 >> cls_w3(c) elements
-// share one 64-bit word.
-__host__ __device__ inline uint32_t cls_w3(uint32_t c) {
-  return c < CD ? (0x1236u >> (4u * c)) & 15u : 0u;
-}
+// log2(64 / element bits) of class c (c < NCLS): 6 for CB, 3 for C8, 2 for
+// C16, 1 for CW, 0 for CD and the limbs of wider values.  64 >> cls_w3(c)
+// elements share one 64-bit word.
+__host__ __device__ inline uint32_t cls_w3(uint32_t c) { return (0x1236u >> (4u * c)) & 15u; }
 // Bytes one value of class c takes in an instance's wide region (c != CB).
 __host__ __device__ inline uint32_t cls_bytes(uint32_t c) {
   return c <= CW ? (8u >> cls_w3(c)) : 8u * cls_limbs(c);

@@ -306,6 +306,24 @@ struct SweepView {
     else if (cls == CW) *(uint32_t*)q = (uint32_t)x;
     else *(uint64_t*)q = x;
   }
+  // The TG tiles' values of destination f, elements of type E (the class is
+  // chosen once, so each tile's store differs only by its immediate offset).
+  template <class E, int TG, class T>
+  __device__ __forceinline__ void st_tiles(uint32_t f, const T* x) const {
+    constexpr uint32_t step = 64u * sizeof(E);
+    char* q = base + (uint64_t)(f >> 6) * row_bytes + ((f & 63u) << lg3) + tt0 * step +
+              lane * (uint32_t)sizeof(E);
+#pragma unroll
+    for (int g = 0; g < TG; ++g) *(E*)(q + g * step) = (E)x[g];
+  }
+  // Destination of class C8..CD (C8..CW when W64 is false).
+  template <int TG, bool W64, class T>
+  __device__ __forceinline__ void st_dst(uint32_t cls, uint32_t f, const T* x) const {
+    if (cls == C8) st_tiles<uint8_t, TG>(f, x);
+    else if (cls == C16) st_tiles<uint16_t, TG>(f, x);
+    else if (!W64 || cls == CW) st_tiles<uint32_t, TG>(f, x);
+    else st_tiles<uint64_t, TG>(f, x);
+  }
   // Whole values of any class for the heavy kernel.
   __device__ __forceinline__ V4 ldv(uint32_t cls, uint32_t f, uint32_t g) const {
     const uint32_t w3 = cls_w3(cls);
@@ -362,7 +380,7 @@ __device__ __forceinline__ void sweep_u32(const SweepView& v, const DevOp* op, u
       const char* p = v.at(op[u].src[k], w3, 0u) + v.off32(w3);
       const uint32_t step = 512u >> w3;
       sh[u * NS + k] = v.sh32(w3);
-      m[u * NS + k] = w3 == 1u ? ~0u : (1u << (64u >> w3)) - 1u;
+      m[u * NS + k] = 0xffffffffu >> ((0x0010181Fu >> (8u * cls)) & 31u);
 #pragma unroll
       for (int g = 0; g < TG; ++g) raw[(u * NS + k) * TG + g] = *(const uint32_t*)(p + g * step);
     }
@@ -388,10 +406,7 @@ __device__ __forceinline__ void sweep_u32(const SweepView& v, const DevOp* op, u
         for (int g = 0; g < TG; ++g) bits[g] = __ballot((r[g] & 1u) != 0u);
         v.st_bits<TG>(q.dst, bits);
       } else {
-        const uint32_t w3 = cls_w3(dc);
-        char* rd = v.at(q.dst, w3, 0u);
-#pragma unroll
-        for (int g = 0; g < TG; ++g) v.st_el(dc, rd, w3, g, r[g]);
+        v.st_dst<TG, false>(dc, q.dst, r);
       }
     }
   }
@@ -438,10 +453,7 @@ __device__ __forceinline__ void sweep_u64(const SweepView& v, const DevOp* op, u
         for (int g = 0; g < TG; ++g) bits[g] = __ballot((r[g] & 1ull) != 0ull);
         v.st_bits<TG>(q.dst, bits);
       } else {
-        const uint32_t w3 = cls_w3(dc);
-        char* rd = v.at(q.dst, w3, 0u);
-#pragma unroll
-        for (int g = 0; g < TG; ++g) v.st_el(dc, rd, w3, g, r[g]);
+        v.st_dst<TG, true>(dc, q.dst, r);
       }
     }
   }

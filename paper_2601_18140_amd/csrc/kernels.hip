@@ -297,15 +297,6 @@ struct SweepView {
     for (int g = 0; g < TG; ++g) mine |= m[g] & (0ull - (uint64_t)(lane == (uint32_t)g));
     if (lane < (uint32_t)TG) *(uint64_t*)(at(f, 6u, 0u) + lane * 8u) = mine;
   }
-  // Store of this lane's value of class C8..CD for tile tt0 + g; r = at(f, w3, 0).
-  __device__ __forceinline__ void st_el(uint32_t cls, char* r, uint32_t w3, uint32_t g,
-                                        uint64_t x) const {
-    char* q = r + g * (512u >> w3) + (lane << 3 >> w3);
-    if (cls == C8) *(uint8_t*)q = (uint8_t)x;
-    else if (cls == C16) *(uint16_t*)q = (uint16_t)x;
-    else if (cls == CW) *(uint32_t*)q = (uint32_t)x;
-    else *(uint64_t*)q = x;
-  }
   // The TG tiles' values of destination f, elements of type E (the class is
   // chosen once, so each tile's store differs only by its immediate offset).
   template <class E, int TG, class T>
@@ -323,36 +314,6 @@ struct SweepView {
     else if (cls == C16) st_tiles<uint16_t, TG>(f, x);
     else if (!W64 || cls == CW) st_tiles<uint32_t, TG>(f, x);
     else st_tiles<uint64_t, TG>(f, x);
-  }
-  // Whole values of any class for the heavy kernel.
-  __device__ __forceinline__ V4 ldv(uint32_t cls, uint32_t f, uint32_t g) const {
-    const uint32_t w3 = cls_w3(cls);
-    const char* q = at(f, w3, g);
-    if (cls == CB) return v4_from((*(const uint64_t*)q >> lane) & 1ull);
-    q += lane << 3 >> w3;
-    if (cls == C8) return v4_from(*(const uint8_t*)q);
-    if (cls == C16) return v4_from(*(const uint16_t*)q);
-    if (cls == CW) return v4_from(*(const uint32_t*)q);
-    const uint32_t k = cls_limbs(cls);
-    V4 x = v4_from(*(const uint64_t*)q);
-    if (k > 1) x.l[1] = *(const uint64_t*)(q + row_bytes);
-    if (k > 2) x.l[2] = *(const uint64_t*)(q + 2ull * row_bytes);
-    if (k > 3) x.l[3] = *(const uint64_t*)(q + 3ull * row_bytes);
-    return x;
-  }
-  __device__ __forceinline__ void stv(uint32_t cls, uint32_t f, uint32_t g, const V4& x) const {
-    const uint32_t w3 = cls_w3(cls);
-    char* r = at(f, w3, 0u);
-    if (cls <= CD) {
-      st_el(cls, r, w3, g, x.l[0]);
-      return;
-    }
-    char* q = r + g * 512u + lane * 8u;
-    const uint32_t k = cls_limbs(cls);
-    *(uint64_t*)q = x.l[0];
-    if (k > 1) *(uint64_t*)(q + row_bytes) = x.l[1];
-    if (k > 2) *(uint64_t*)(q + 2ull * row_bytes) = x.l[2];
-    if (k > 3) *(uint64_t*)(q + 3ull * row_bytes) = x.l[3];
   }
 };
 
@@ -540,6 +501,11 @@ k_sweep(const DevOp* __restrict__ ops, StateLayout L, char* __restrict__ state, 
   }
 }
 
+// The heavy operations of one layer (a value wider than 64 bits, or a
+// source).  Limb 0 of every operand is gathered without branches (an 8-byte
+// load per tile holding the lane's element, cut out as in the common
+// kernel); the further limbs of wide operands follow under a uniform branch.
+// All loads of an operation are in flight before the first is used.
 template <int TG>
 __global__ void __launch_bounds__(256)
 k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
@@ -562,28 +528,81 @@ k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers
     const DevOp q = ops[o];
     const uint32_t code = q.code, opc = op_opc(code), ar = op_arity(code);
     const uint32_t dc = op_dcls(code), w = op_width(q.wimm), imm = op_imm(q.wimm);
-    uint64_t m[TG];
+    V4 r[TG];
+    if (opc >= OP_STIM) {
+      const uint64_t cycle = ctl->cycle;
 #pragma unroll
-    for (int g = 0; g < TG; ++g) {
-      V4 r;
-      if (opc >= OP_STIM) {
+      for (int g = 0; g < TG; ++g) {
         const uint32_t inst = (tile0 + g) * 64u + lane;
-        const uint64_t cycle = ctl->cycle;
         const uint64_t words_row =
             ((cycle - ctl->step_cycle0) * (uint64_t)n_inst + inst) * (uint64_t)words_per_inst;
-        r = v4_from(0);
+        r[g] = v4_from(0);
         if (inst < n_inst)
-          r = source_value(const_limbs, q, seeds[inst], cycle, ctl->words, words_row, w);
-      } else {
-        const V4 a = v.ldv(op_scls(code, 0), q.src[0], g);
-        const V4 b = ar > 1 ? v.ldv(op_scls(code, 1), q.src[1], g) : v4_from(0);
-        const V4 c = ar > 2 ? v.ldv(op_scls(code, 2), q.src[2], g) : v4_from(0);
-        r = eval_wide(opc, ar, a, b, c, imm, w);
+          r[g] = source_value(const_limbs, q, seeds[inst], cycle, ctl->words, words_row, w);
       }
-      if (dc == CB) m[g] = __ballot((r.l[0] & 1ull) != 0ull);
-      else v.stv(dc, q.dst, g, r);
+    } else {
+      uint64_t raw[3 * 4 * TG];
+      uint32_t sh[3], kl[3];
+      uint64_t m[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const uint32_t cls = op_scls(code, k), w3 = cls_w3(cls);
+        const char* p = v.at(q.src[k], w3, 0u) + v.off64(w3);
+        const uint32_t step = 512u >> w3;
+        kl[k] = cls_limbs(cls);
+        sh[k] = v.sh64(w3);
+        m[k] = w3 == 0u ? ~0ull : (1ull << (64u >> w3)) - 1ull;
+#pragma unroll
+        for (int g = 0; g < TG; ++g) raw[(k * 4) * TG + g] = *(const uint64_t*)(p + g * step);
+        // Limbs 1..3 exist only for values wider than 64 bits (then the
+        // lane offset is 8 lane and the step 512).
+#pragma unroll
+        for (int l = 1; l < 4; ++l) {
+          if ((uint32_t)l < kl[k]) {
+#pragma unroll
+            for (int g = 0; g < TG; ++g)
+              raw[(k * 4 + l) * TG + g] =
+                  *(const uint64_t*)(p + (uint64_t)l * v.row_bytes + g * 512u);
+          } else {
+#pragma unroll
+            for (int g = 0; g < TG; ++g) raw[(k * 4 + l) * TG + g] = 0ull;
+          }
+        }
+      }
+      keep_loaded(raw);
+#pragma unroll
+      for (int g = 0; g < TG; ++g) {
+        V4 x[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          x[k].l[0] = (raw[(k * 4) * TG + g] >> sh[k]) & m[k];
+#pragma unroll
+          for (int l = 1; l < 4; ++l) x[k].l[l] = raw[(k * 4 + l) * TG + g];
+        }
+        r[g] = eval_wide(opc, ar, x[0], x[1], x[2], imm, w);
+      }
     }
-    if (dc == CB) v.st_bits<TG>(q.dst, m);
+    if (dc == CB) {
+      uint64_t bits[TG];
+#pragma unroll
+      for (int g = 0; g < TG; ++g) bits[g] = __ballot((r[g].l[0] & 1ull) != 0ull);
+      v.st_bits<TG>(q.dst, bits);
+    } else if (dc <= CD) {
+      uint64_t x[TG];
+#pragma unroll
+      for (int g = 0; g < TG; ++g) x[g] = r[g].l[0];
+      v.st_dst<TG, true>(dc, q.dst, x);
+    } else {
+      const uint32_t kd = cls_limbs(dc);
+      char* d0 = v.at(q.dst, 0u, 0u) + lane * 8u;
+#pragma unroll
+      for (int l = 0; l < 4; ++l)
+        if ((uint32_t)l < kd) {
+#pragma unroll
+          for (int g = 0; g < TG; ++g)
+            *(uint64_t*)(d0 + (uint64_t)l * v.row_bytes + g * 512u) = r[g].l[l];
+        }
+    }
   }
 }
 
@@ -830,7 +849,7 @@ hipError_t launch_sweep_heavy(const Program& p, const StateLayout& L, char* stat
                               uint32_t tiles_per_wave, TilePass tp, hipStream_t s) {
   const uint32_t n = ly.hend - ly.hbeg;
   if (n == 0) return hipSuccess;
-  const uint32_t tg = tiles_per_wave >= 4 ? 4u : tiles_per_wave == 2 ? 2u : 1u;
+  const uint32_t tg = tiles_per_wave >= 2 ? 2u : 1u;
   if (ops_per_wave == 0 || !pass_ok(L, tp, tg)) return hipErrorInvalidValue;
   const uint64_t chunks = (n + ops_per_wave - 1) / ops_per_wave;
   const uint32_t n_groups = tp.count / tg;
@@ -840,8 +859,7 @@ hipError_t launch_sweep_heavy(const Program& p, const StateLayout& L, char* stat
   hipLaunchKernelGGL((k_sweep_heavy<GG>), grid, blk, 0, s, p.ops, p.layers, p.const_limbs,   \
                      p.words_per_inst, L, state, seeds, ctl, n_inst, layer, ops_per_wave,    \
                      tp.base, n_groups)
-  if (tg == 4) RTEAAL_HEAVY(4);
-  else if (tg == 2) RTEAAL_HEAVY(2);
+  if (tg == 2) RTEAAL_HEAVY(2);
   else RTEAAL_HEAVY(1);
 #undef RTEAAL_HEAVY
   return hipGetLastError();

@@ -229,6 +229,97 @@ def bench_multi(args, R, torch):
     }
 
 
+def shuffled_graph(d, seed):
+    """(n_slots, op_src_ptr, op_src, op_dst) of design d with its operations
+    in a random order: the order a netlist may arrive in."""
+    rng = np.random.default_rng(seed)
+    o = rng.permutation(d.op_type.size)
+    ptr = d.op_src_ptr.astype(np.int64)
+    lens = (ptr[1:] - ptr[:-1])[o]
+    new_ptr = np.zeros(o.size + 1, np.int64)
+    np.cumsum(lens, out=new_ptr[1:])
+    take = np.repeat(ptr[:-1][o] - new_ptr[:-1], lens) + np.arange(int(new_ptr[-1]))
+    return (int(d.slot_width.size), new_ptr.astype(np.uint32), np.ascontiguousarray(d.op_src[take]),
+            np.ascontiguousarray(d.op_dst[o]))
+
+
+def levelization_ok(g, layer, order, lptr):
+    """Validity and tightness of a layering (they characterize the layering
+    by longest chains), plus the order and layer ranges."""
+    n_slots, ptr, src, dst = g
+    L = layer.astype(np.int64)
+    prod = np.full(n_slots, -1, np.int64)
+    prod[dst.astype(np.int64)] = np.arange(L.size)
+    p = prod[src.astype(np.int64)]
+    owner = np.repeat(np.arange(L.size), np.diff(ptr.astype(np.int64)))
+    fed = p >= 0
+    best = np.full(L.size, -1, np.int64)
+    np.maximum.at(best, owner[fed], L[p[fed]])
+    return bool((L[owner[fed]] > L[p[fed]]).all() and np.array_equal(L, best + 1)
+                and (np.diff(L[order.astype(np.int64)]) >= 0).all()
+                and np.array_equal(np.diff(lptr.astype(np.int64)),
+                                   np.bincount(L, minlength=lptr.size - 1)))
+
+
+def bench_levelize(args, R, torch):
+    """rteaal_levelize on the large-5m graph with its operations shuffled; the
+    oracle levelizer timed beside it on a bounded sample of the same recipe."""
+    wl = WORKLOADS["large-5m"]
+    t0 = time.perf_counter()
+    d = rtlgen.generate(wl["cfg"], wl["seed"])
+    g = shuffled_graph(d, 5)
+    n, e = int(g[3].size), int(g[2].size)
+    print(f"[bench] large-5m graph shuffled: {n} ops, {e} operand entries "
+          f"({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)
+    ctx = R.rteaal_create(0)
+    for _ in range(args.warmup):
+        R.rteaal_levelize(ctx, *g)
+    steps = args.steps if args.steps is not None else 5
+    times = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        layer, order, lptr = R.rteaal_levelize(ctx, *g)
+        times.append(time.perf_counter() - t0)
+    ms = float(np.median(times)) * 1e3
+    ok = levelization_ok(g, layer, order, lptr)
+    n_layers = int(lptr.size - 1)
+    print(f"[bench] levelize: {ms:.1f} ms per call (median of {steps}), {n_layers} layers, "
+          f"properties {'ok' if ok else 'FAILED'}", file=sys.stderr, flush=True)
+    R.rteaal_destroy(ctx)
+    # Compulsory bytes of one call: the graph read once, the three results written once.
+    algo = 4.0 * ((n + 1) + e + n) + 4.0 * (2 * n + n_layers + 1)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = rtlgen.generate(rtlgen.generator.scaled(wl["cfg"], 0.5, "levelize-sample"), wl["seed"])
+        gs = shuffled_graph(sample, 5)
+        t0 = time.perf_counter()
+        oracle.levelize(*gs)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(gs[3].size / dt, 1), "unit": "operations/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{gs[3].size} operations of the large-5m recipe (half scale), shuffled, "
+                         f"{dt:.1f} s on one host thread"}
+        print(f"[bench] cpu oracle: {cpu}", file=sys.stderr, flush=True)
+    return {
+        "metric": "operations levelized/s", "value": round(n / (ms / 1e3), 1),
+        "unit": "operations/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "levelize-5m", "ops": n, "operand_entries": e, "layers": n_layers,
+                   "timed": "whole rteaal_levelize call: uploads, kernels, read-back"},
+        "parity_sample_ok": ok,
+        "roofline": {"bound": "hbm", "achieved": round(algo / (ms / 1e3) / 1e9, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(algo / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "rteaal_levelize (all kernels of the call)",
+                     "bytes_per_launch": round(algo, 1),
+                     "note": "bound by the frontier steps' latency (one launch per layer, a "
+                             "read-back per 8 layers) and the uploads; not by HBM bandwidth"},
+        "cpu_baseline": cpu,
+    }
+
+
 def bench_serving(args, R, torch):
     """Poisson stream of jobs over a pool of designs with continuous batching."""
     from paper_2601_18140_amd import serving
@@ -302,7 +393,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large-5m",
-                    choices=sorted(WORKLOADS) + ["multi-64", "serving"])
+                    choices=sorted(WORKLOADS) + ["multi-64", "serving", "levelize-5m"])
     ap.add_argument("--designs", type=int, default=None)
     ap.add_argument("--serving-jobs", type=int, default=200)
     ap.add_argument("--serving-rate", type=float, default=4.0, help="job arrivals per second")
@@ -363,6 +454,9 @@ def main():
     if args.workload == "serving":
         args.designs = args.designs or 32
         print(json.dumps(bench_serving(args, R, torch)), flush=True)
+        return
+    if args.workload == "levelize-5m":
+        print(json.dumps(bench_levelize(args, R, torch)), flush=True)
         return
 
     wl = WORKLOADS[args.workload]

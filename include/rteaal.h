@@ -140,6 +140,46 @@ typedef struct {
  * RTEAAL_E_BAD_DESIGN, RTEAAL_E_FORMAT or RTEAAL_E_INVALID_ARG. */
 rteaal_status rteaal_validate_design(const rteaal_design_desc* desc, char* err, size_t err_len);
 
+/* ------------------------------------------------------------------------ */
+/* Levelization                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* A dataflow graph with its operations in any order (paper section
+ * "Evaluating Arbitrary Dataflow Graphs": levelization slices the graph into
+ * layers before the cascade is formed).  Operation o reads the slots
+ * op_src[op_src_ptr[o] .. op_src_ptr[o+1]) and writes slot op_dst[o].  A slot
+ * that no operation writes is a source (primary input, register or
+ * constant), available before the first layer.  All arrays are host memory. */
+typedef struct {
+  uint32_t n_slots;
+  uint32_t n_ops;
+  const uint32_t* op_src_ptr; /* [n_ops + 1], op_src_ptr[0] = 0, non-decreasing */
+  const uint32_t* op_src;     /* [op_src_ptr[n_ops]] slots read, each < n_slots  */
+  const uint32_t* op_dst;     /* [n_ops] slot written, each < n_slots            */
+} rteaal_dag_desc;
+
+/* Levelizes a graph on the context's device: operation o gets layer 1 + the
+ * largest layer among the operations producing its operands, and layer 0
+ * when all its operands are sources.  This is the levelization with the
+ * fewest layers (the graph's depth); every operation reads only sources and
+ * values of earlier layers, and every layer is non-empty.
+ * Outputs, host memory allocated by the caller:
+ *   op_layer  [n_ops]     layer of each operation;
+ *   order     [n_ops]     operation indices sorted by (layer, index);
+ *   layer_ptr [n_ops + 1] order[layer_ptr[i] .. layer_ptr[i+1]) is layer i
+ *                         (entries past n_layers are left untouched);
+ *   n_layers              number of layers (0 when n_ops = 0).
+ * A design in this order (layer_ptr as its layer ranges) passes
+ * rteaal_validate_design's levelization check.  Errors (outputs then
+ * unspecified): RTEAAL_E_INVALID_ARG for a null pointer, n_ops >= 2^31, a
+ * decreasing op_src_ptr or a slot index out of range; RTEAAL_E_BAD_DESIGN
+ * when a slot is written by two operations or the graph has a cycle (the
+ * message names the slot, or an operation on or behind the cycle);
+ * RTEAAL_E_NO_MEMORY when the device scratch (about 13 words per operation
+ * plus 2 per operand entry and 1 per slot) cannot be allocated. */
+rteaal_status rteaal_levelize(rteaal_ctx* ctx, const rteaal_dag_desc* dag, uint32_t* op_layer,
+                              uint32_t* order, uint32_t* layer_ptr, uint32_t* n_layers);
+
 /* Validates, encodes (operations grouped per layer by destination width
  * class and type, as in the N-rank swizzle of the NU kernel) and uploads a
  * design.  *out receives a handle valid until rteaal_unload_design.

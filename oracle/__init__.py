@@ -3,6 +3,8 @@
 Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
 import this package.  The GPU library does not depend on it in any way.
 """
+from .levelize import NotLevelizable, layer_order, levelize
 from .oracle import build, eval_op, lib_path, run, splitmix64, stim
 
-__all__ = ["build", "eval_op", "lib_path", "run", "splitmix64", "stim"]
+__all__ = ["build", "eval_op", "lib_path", "run", "splitmix64", "stim", "levelize",
+           "layer_order", "NotLevelizable"]

@@ -16,7 +16,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
 
 
 def sources():
-    return [os.path.join(CSRC, f) for f in ("kernels.hip", "host.cpp")]
+    return [os.path.join(CSRC, f) for f in ("kernels.hip", "levelize.hip", "host.cpp")]
 
 
 def build(verbose: bool = False) -> str:

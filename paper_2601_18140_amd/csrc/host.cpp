@@ -16,6 +16,7 @@
 
 #include "../../include/rteaal.h"
 #include "internal.h"
+#include "levelize.h"
 
 using namespace rteaal;
 
@@ -944,6 +945,107 @@ rteaal_status rteaal_validate_design(const rteaal_design_desc* desc, char* err, 
   }
   if (st != RTEAAL_OK) g_err = why;
   return st;
+}
+
+rteaal_status rteaal_levelize(rteaal_ctx* ctx, const rteaal_dag_desc* g, uint32_t* op_layer,
+                              uint32_t* order, uint32_t* layer_ptr, uint32_t* n_layers) {
+  if (!ctx || !g || !layer_ptr || !n_layers) return fail(ctx, RTEAAL_E_INVALID_ARG, "null argument");
+  if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
+  const uint32_t n = g->n_ops;
+  if (n >= (1u << 31)) return fail(ctx, RTEAAL_E_INVALID_ARG, "n_ops %u is too large", n);
+  if (n == 0) {
+    layer_ptr[0] = 0;
+    *n_layers = 0;
+    return RTEAAL_OK;
+  }
+  if (!op_layer || !order || !g->op_src_ptr || !g->op_dst)
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "null argument");
+  // The remaining range checks run on the device before any kernel indexes
+  // with the graph.
+  if (g->op_src_ptr[0] != 0) return fail(ctx, RTEAAL_E_INVALID_ARG, "op_src_ptr[0] is not 0");
+  const uint32_t ne = g->op_src_ptr[n];
+  if (ne && !g->op_src) return fail(ctx, RTEAAL_E_INVALID_ARG, "null op_src");
+
+  size_t temp = 0;
+  HIP_TRY(ctx, levelize_temp_bytes(n, &temp));
+  const size_t w = 4, n1 = (size_t)n + 1;
+  Mem m_ptr, m_src, m_dst, m_prod, m_indeg, m_outdeg, m_optr, m_cur, m_oidx, m_f0, m_f1, m_layer,
+      m_keys, m_vals, m_order, m_lptr, m_sizes, m_scal, m_temp;
+  std::vector<std::pair<Mem*, size_t>> req = {
+      {&m_ptr, n1 * w}, {&m_src, std::max<size_t>(ne, 1) * w}, {&m_dst, n * w},
+      {&m_prod, (size_t)g->n_slots * w}, {&m_indeg, n * w}, {&m_outdeg, n1 * w},
+      {&m_optr, n1 * w}, {&m_cur, n * w}, {&m_oidx, std::max<size_t>(ne, 1) * w},
+      {&m_f0, n * w}, {&m_f1, n * w}, {&m_layer, n * w}, {&m_keys, n * w}, {&m_vals, n * w},
+      {&m_order, n * w}, {&m_lptr, n1 * w}, {&m_sizes, (n + 16ull) * w}, {&m_scal, 8 * w},
+      {&m_temp, temp}};
+  if (!alloc_all(ctx, req))
+    return fail(ctx, RTEAAL_E_NO_MEMORY, "device scratch for levelizing %u operations", n);
+  auto release = [&] {
+    for (auto& r : req) dev_free(ctx, *r.first);
+  };
+  LvBuffers B{};
+  B.src_ptr = (const uint32_t*)m_ptr.p;
+  B.src = (const uint32_t*)m_src.p;
+  B.dst = (const uint32_t*)m_dst.p;
+  B.producer = (uint32_t*)m_prod.p;
+  B.indeg = (uint32_t*)m_indeg.p;
+  B.outdeg = (uint32_t*)m_outdeg.p;
+  B.out_ptr = (uint32_t*)m_optr.p;
+  B.cursor = (uint32_t*)m_cur.p;
+  B.out_idx = (uint32_t*)m_oidx.p;
+  B.front[0] = (uint32_t*)m_f0.p;
+  B.front[1] = (uint32_t*)m_f1.p;
+  B.layer = (uint32_t*)m_layer.p;
+  B.keys_out = (uint32_t*)m_keys.p;
+  B.vals_in = (uint32_t*)m_vals.p;
+  B.order = (uint32_t*)m_order.p;
+  B.layer_ptr = (uint32_t*)m_lptr.p;
+  B.sizes = (uint32_t*)m_sizes.p;
+  B.scalars = (uint32_t*)m_scal.p;
+  B.temp = m_temp.p;
+  B.temp_bytes = temp;
+  LvResult res{};
+  hipError_t e = hipMemcpyAsync(m_ptr.p, g->op_src_ptr, n1 * w, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && ne)
+    e = hipMemcpyAsync(m_src.p, g->op_src, (size_t)ne * w, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m_dst.p, g->op_dst, n * w, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = levelize_run(B, g->n_slots, n, ne, ctx->stream, &res);
+  const bool in_range = res.bad[0] == kLvNone && res.bad[1] == kLvNone && res.bad[2] == kLvNone;
+  if (e == hipSuccess && in_range && res.dup_slot == kLvNone)
+    e = hipMemcpyAsync(op_layer, B.layer, n * w, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess && in_range && res.dup_slot == kLvNone && res.processed == n) {
+    e = hipMemcpyAsync(order, B.order, n * w, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(layer_ptr, B.layer_ptr, ((size_t)res.n_layers + 1) * w,
+                         hipMemcpyDeviceToHost, ctx->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  release();
+  if (e != hipSuccess) {
+    ctx->poisoned = true;
+    return fail(ctx, RTEAAL_E_DEVICE, "levelization failed: %s", hipGetErrorString(e));
+  }
+  if (res.bad[0] != kLvNone)
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "op_src_ptr decreases at operation %u", res.bad[0]);
+  if (res.bad[1] != kLvNone)
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "operand entry %u reads slot %u of %u", res.bad[1],
+                g->op_src[res.bad[1]], g->n_slots);
+  if (res.bad[2] != kLvNone)
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "operation %u writes slot %u of %u", res.bad[2],
+                g->op_dst[res.bad[2]], g->n_slots);
+  if (res.dup_slot != kLvNone)
+    return fail(ctx, RTEAAL_E_BAD_DESIGN, "slot %u is written by more than one operation",
+                res.dup_slot);
+  if (res.processed < n) {
+    uint32_t o = 0;
+    while (o < n && op_layer[o] != kLvNone) ++o;
+    return fail(ctx, RTEAAL_E_BAD_DESIGN,
+                "combinational cycle: operation %u lies on or behind a cycle (%u of %u operations "
+                "levelized)", o, res.processed, n);
+  }
+  *n_layers = res.n_layers;
+  return RTEAAL_OK;
 }
 
 rteaal_status rteaal_load_design(rteaal_ctx* ctx, const rteaal_design_desc* desc,

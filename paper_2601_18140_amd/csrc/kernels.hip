@@ -54,10 +54,11 @@ __device__ __forceinline__ V4 source_value(const uint64_t* const_limbs, const De
 // RESIDENT: per-instance state block at `s` (LDS or global).
 // ---------------------------------------------------------------------------
 
-// Low-bit mask of a value of class c (all 64 bits for CD and for limbs).
+// Low-bit mask of a value of class c (all 64 bits for CD and for limbs):
+// ~0 shifted right by 64 - element bits, taken from a byte table
+// (63, 56, 48, 32 for CB, C8, C16, CW; 0 for the rest).
 __device__ __forceinline__ uint64_t cls_mask64(uint32_t c) {
-  const uint32_t w3 = cls_w3(c);
-  return w3 == 0u ? ~0ull : (1ull << (64u >> w3)) - 1ull;
+  return ~0ull >> ((0x2030383Full >> (c << 3)) & 63u);
 }
 
 // Operand fetch without branches: one aligned 8-byte load per operand, the
@@ -388,7 +389,7 @@ __device__ __forceinline__ void sweep_u64(const SweepView& v, const DevOp* op, u
       const char* p = v.at(op[u].src[k], w3, 0u) + v.off64(w3);
       const uint32_t step = 512u >> w3;
       sh[u * NS + k] = v.sh64(w3);
-      m[u * NS + k] = w3 == 0u ? ~0ull : (1ull << (64u >> w3)) - 1ull;
+      m[u * NS + k] = cls_mask64(cls);
 #pragma unroll
       for (int g = 0; g < TG; ++g) raw[(u * NS + k) * TG + g] = *(const uint64_t*)(p + g * step);
     }
@@ -551,7 +552,7 @@ k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers
         const uint32_t step = 512u >> w3;
         kl[k] = cls_limbs(cls);
         sh[k] = v.sh64(w3);
-        m[k] = w3 == 0u ? ~0ull : (1ull << (64u >> w3)) - 1ull;
+        m[k] = cls_mask64(cls);
 #pragma unroll
         for (int g = 0; g < TG; ++g) raw[(k * 4) * TG + g] = *(const uint64_t*)(p + g * step);
         // Limbs 1..3 exist only for values wider than 64 bits (then the

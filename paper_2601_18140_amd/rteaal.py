@@ -26,6 +26,7 @@ __all__ = [
     "rteaal_batch_options",
     "rteaal_step", "rteaal_step_many", "rteaal_sync", "rteaal_read_state", "rteaal_write_state",
     "rteaal_kernel_timing", "rteaal_autotune", "opts_dict", "unpack_limbs", "pack_limbs", "rteaal_layer_format", "rteaal_rank_format",
+    "rteaal_dag_desc", "rteaal_levelize", "levelized_design",
 ]
 
 RTEAAL_OK = 0
@@ -61,6 +62,11 @@ class rteaal_design_desc(C.Structure):
         ("op_src_ptr", C.c_void_p), ("op_src", C.c_void_p), ("op_imm", C.c_void_p),
         ("layer_fmt", C.c_void_p),
     ]
+
+
+class rteaal_dag_desc(C.Structure):
+    _fields_ = [("n_slots", C.c_uint32), ("n_ops", C.c_uint32), ("op_src_ptr", C.c_void_p),
+                ("op_src", C.c_void_p), ("op_dst", C.c_void_p)]
 
 
 class rteaal_batch_opts(C.Structure):
@@ -120,6 +126,7 @@ def library():
         "rteaal_write_state": ([vp, u32, u32, u32, vp, u64], st),
         "rteaal_kernel_timing": ([vp, u32, C.c_int, C.POINTER(u64), C.POINTER(C.c_double)], st),
         "rteaal_autotune": ([vp, u32, u32, u32, C.POINTER(rteaal_batch_opts), C.POINTER(C.c_double)], st),
+        "rteaal_levelize": ([vp, C.POINTER(rteaal_dag_desc), vp, vp, vp, C.POINTER(u32)], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -135,7 +142,8 @@ def exported_symbols():
             "rteaal_design_format",
             "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch",
             "rteaal_batch_info", "rteaal_batch_options", "rteaal_step", "rteaal_step_many", "rteaal_sync",
-            "rteaal_read_state", "rteaal_write_state", "rteaal_kernel_timing", "rteaal_autotune"]
+            "rteaal_read_state", "rteaal_write_state", "rteaal_kernel_timing", "rteaal_autotune",
+            "rteaal_levelize"]
 
 
 def _check(ctx, status):
@@ -268,6 +276,54 @@ def rteaal_validate_design(design, layer_fmt=None):
     buf = C.create_string_buffer(512)
     st = library().rteaal_validate_design(C.byref(d), buf, 512)
     return st, buf.value.decode()
+
+
+def rteaal_levelize(ctx, n_slots, op_src_ptr, op_src, op_dst):
+    """Layers of a dataflow graph in any operation order, computed on the
+    device: (op_layer, order, layer_ptr) as uint32 arrays, layer_ptr holding
+    n_layers + 1 entries (see rteaal_levelize in rteaal.h)."""
+    ptr = np.ascontiguousarray(op_src_ptr, dtype=np.uint32)
+    src = np.ascontiguousarray(op_src, dtype=np.uint32)
+    dst = np.ascontiguousarray(op_dst, dtype=np.uint32)
+    n = int(dst.shape[0])
+    if ptr.shape[0] != n + 1:
+        raise ValueError("op_src_ptr needs n_ops + 1 entries")
+    g = rteaal_dag_desc(int(n_slots), n, ptr.ctypes.data, src.ctypes.data if src.size else None,
+                        dst.ctypes.data if n else None)
+    layer = np.zeros(n, np.uint32)
+    order = np.zeros(n, np.uint32)
+    lptr = np.zeros(n + 1, np.uint32)
+    nl = C.c_uint32()
+    _check(ctx.handle, library().rteaal_levelize(
+        ctx.handle, C.byref(g), layer.ctypes.data if n else None,
+        order.ctypes.data if n else None, lptr.ctypes.data, C.byref(nl)))
+    return layer, order, lptr[: nl.value + 1].copy()
+
+
+def levelized_design(ctx, design):
+    """A copy of `design` (any object with the array attributes of a design
+    description) whose operations are reordered into the layers that
+    rteaal_levelize assigns; its own layer_ptr and operation order are
+    ignored.  Only the reordering of the operation arrays happens here."""
+    import copy
+    ptr = np.asarray(design.op_src_ptr, dtype=np.int64)
+    _, order, lptr = rteaal_levelize(ctx, design.slot_width.shape[0], design.op_src_ptr,
+                                     design.op_src, design.op_dst)
+    o = order.astype(np.int64)
+    lens = (ptr[1:] - ptr[:-1])[o]
+    new_ptr = np.zeros(o.shape[0] + 1, np.int64)
+    np.cumsum(lens, out=new_ptr[1:])
+    # Operand entries of the reordered operations, each run copied whole.
+    starts = np.repeat(ptr[:-1][o] - new_ptr[:-1], lens)
+    take = starts + np.arange(int(new_ptr[-1]), dtype=np.int64)
+    out = copy.copy(design)
+    out.op_type = np.asarray(design.op_type)[o]
+    out.op_dst = np.asarray(design.op_dst)[o]
+    out.op_imm = np.asarray(design.op_imm)[o]
+    out.op_src = np.asarray(design.op_src)[take]
+    out.op_src_ptr = new_ptr.astype(np.uint32)
+    out.layer_ptr = lptr.astype(np.uint32)
+    return out
 
 
 RTEAAL_LOAD_KEEP_ALL_SLOTS = 1

@@ -320,6 +320,87 @@ def bench_levelize(args, R, torch):
     }
 
 
+def bench_waveform(args, R, torch):
+    """Value-change capture on single-200k (every slot kept, 1,024 instances):
+    the rate with 8,192 watched signals (the 4,096 registers and 4,096 operation
+    outputs) against the same batch unwatched, the change log drained after
+    every step of 5 cycles (random logic changes about a third of its values
+    every cycle, so a step logs ~15M transitions)."""
+    wl = WORKLOADS["single-200k"]
+    d = rtlgen.generate(wl["cfg"], wl["seed"])
+    n_inst = args.instances or wl["instances"]
+    seeds = rtlgen.instance_seeds(n_inst)
+    ctx = R.rteaal_create(0)
+    did = R.rteaal_load_design(ctx, d, keep_all_slots=True)
+    bid = R.rteaal_create_batch(ctx, did, seeds, mapping=R.RTEAAL_MAP_SWEEP, ops_per_wave=2,
+                                unroll=2, tiles_per_wave=4)
+    rng = np.random.default_rng(7)
+    ops = np.sort(rng.choice(d.op_dst.astype(np.int64), 4096, replace=False))
+    slots = np.concatenate([d.reg_slot.astype(np.int64), ops]).astype(np.uint32)
+    cps = args.cycles_per_step or 5
+    steps = args.steps if args.steps is not None else 20
+    stream = ctx.stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(watch):
+        ms, recs, dropped = 0.0, 0, 0
+        for k in range(args.warmup + steps):
+            ev0.record(stream)
+            R.rteaal_step(ctx, bid, cps)
+            ev1.record(stream)
+            ev1.synchronize()
+            if k >= args.warmup:
+                ms += ev0.elapsed_time(ev1)
+            if watch:
+                r, dr = R.rteaal_read_changes(ctx, bid)
+                if k >= args.warmup:
+                    recs += r.size
+                    dropped += dr
+        return ms, recs, dropped
+
+    ms0, _, _ = timed(False)
+    R.rteaal_watch(ctx, bid, slots, capacity=1 << 25)
+    ms1, recs, dropped = timed(True)
+    # parity sample: the last step's registers against the oracle
+    total_cycles = (args.warmup + steps) * cps * 2
+    got = R.unpack_limbs(R.rteaal_read_state(ctx, bid, 0, 2), d.slot_width[d.reg_slot])
+    import oracle
+    ref, _, _ = oracle.run(d, seeds[:2], total_cycles)
+    ok = bool(np.array_equal(got, ref))
+    R.rteaal_free_batch(ctx, bid)
+    R.rteaal_unload_design(ctx, did)
+    R.rteaal_destroy(ctx)
+    cyc = steps * cps
+    v0 = n_inst * cyc / (ms0 / 1e3)
+    v1 = n_inst * cyc / (ms1 / 1e3)
+    # Capture bytes per cycle: every watched value read and compared with its
+    # 8-byte copy, and per transition the copy rewritten and a 48-byte record.
+    w = d.slot_width[slots.astype(np.int64)].astype(np.int64)
+    per_cycle = n_inst * float(eb(w).sum() + 8.0 * ((w + 63) // 64).sum()) + (recs + dropped) / cyc * 8 \
+        + recs / cyc * 48
+    extra_s = max(ms1 - ms0, 1e-9) / 1e3 / cyc
+    print(f"[bench] waveform: unwatched {v0:.4g}, watched {v1:.4g} instance-cycles/s; "
+          f"{(recs + dropped) / cyc:.0f} transitions per cycle, {dropped} dropped", file=sys.stderr,
+          flush=True)
+    return {
+        "metric": METRIC, "value": round(v1, 2), "unit": "instance-cycles/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms1 / steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "waveform", "design": "single-200k (every slot kept)",
+                   "instances": n_inst, "watched_signals": int(slots.size),
+                   "cycles_per_step": cps},
+        "unwatched_value": round(v0, 2), "capture_overhead": round(ms1 / ms0 - 1.0, 4),
+        "transitions_per_cycle": round((recs + dropped) / cyc, 1), "dropped": dropped,
+        "parity_sample_ok": ok,
+        "roofline": {"bound": "hbm", "kernel": "k_capture (from the added time per cycle)",
+                     "achieved": round(per_cycle / extra_s / 1e9, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(per_cycle / extra_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": round(per_cycle, 1)},
+        "cpu_baseline": None,
+    }
+
+
 def bench_serving(args, R, torch):
     """Poisson stream of jobs over a pool of designs with continuous batching."""
     from paper_2601_18140_amd import serving
@@ -393,7 +474,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large-5m",
-                    choices=sorted(WORKLOADS) + ["multi-64", "serving", "levelize-5m"])
+                    choices=sorted(WORKLOADS) + ["multi-64", "serving", "levelize-5m", "waveform"])
     ap.add_argument("--designs", type=int, default=None)
     ap.add_argument("--serving-jobs", type=int, default=200)
     ap.add_argument("--serving-rate", type=float, default=4.0, help="job arrivals per second")
@@ -457,6 +538,9 @@ def main():
         return
     if args.workload == "levelize-5m":
         print(json.dumps(bench_levelize(args, R, torch)), flush=True)
+        return
+    if args.workload == "waveform":
+        print(json.dumps(bench_waveform(args, R, torch)), flush=True)
         return
 
     wl = WORKLOADS[args.workload]

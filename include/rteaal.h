@@ -326,6 +326,52 @@ rteaal_status rteaal_read_state(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t
 rteaal_status rteaal_write_state(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t first,
                                  uint32_t n, const uint64_t* regs, uint64_t cycle);
 
+/* ------------------------------------------------------------------------ */
+/* Waveforms                                                                */
+/* ------------------------------------------------------------------------ */
+
+/* One recorded transition: after `cycle` cycles (the batch's cycle counter
+ * once that cycle had completed), signal `signal` (an index into the slots
+ * given to rteaal_watch) of instance `instance` holds `value` (limbs, zero
+ * above the signal's width), which differs from its value one cycle earlier. */
+typedef struct {
+  uint64_t cycle;
+  uint32_t instance;
+  uint32_t signal;
+  uint64_t value[4];
+} rteaal_change;
+
+/* Value-change capture (paper section "System Integration", waveform
+ * generation: a signal's transitions are found by comparing its value with
+ * the one of the previous cycle).  Watches the slots slots[0 .. n) (host) in
+ * every instance of the batch: from the call on, after every simulated cycle
+ * each watched value that differs from its value after the previous cycle
+ * (for the first cycle: its value at the call) is appended to the batch's
+ * change log.  The log holds `capacity` records; further changes are counted
+ * as dropped.  n = 0 stops watching and frees the log.  A later call replaces
+ * the watch set and empties the log.  Register values written by
+ * rteaal_write_state show up as changes of the next cycle when they differ.
+ * Waits for the batch's pending steps.
+ * Errors: RTEAAL_E_INVALID_ARG (slot out of range, null slots with n > 0);
+ * RTEAAL_E_UNSUPPORTED when a slot other than a register is watched on a
+ * design loaded without RTEAAL_LOAD_KEEP_ALL_SLOTS (its storage is shared
+ * with other values, so it keeps no value across the cycle; the paper, too,
+ * gives every signal its own coordinate for waveforms).
+ * Cost: one thread per instance and watched signal after every cycle, and
+ * RESIDENT batches run one cycle per launch while watched. */
+rteaal_status rteaal_watch(rteaal_ctx* ctx, rteaal_batch_id batch, const uint32_t* slots,
+                           uint32_t n, uint64_t capacity);
+
+/* Moves the change log of a watched batch into out (host, room for max
+ * records) and empties it; records come in no particular order.  Waits for
+ * the batch's pending steps.  *n_out = records in the log (copied when
+ * out != NULL), *n_dropped = changes lost to a full log since the last
+ * drain.  With out = NULL or max = 0 only the counts are returned and the
+ * log is kept.  RTEAAL_E_INVALID_ARG when max is smaller than the record
+ * count (nothing is copied or emptied) or the batch is not watched. */
+rteaal_status rteaal_read_changes(rteaal_ctx* ctx, rteaal_batch_id batch, rteaal_change* out,
+                                  uint64_t max, uint64_t* n_out, uint64_t* n_dropped);
+
 /* Autotuner: picks the mapping and launch shape for n_instances of `design`
  * on this device.  Each candidate (RESIDENT block sizes and unroll depths,
  * SWEEP operations per wavefront, unroll depths and tile groups) runs `trial_cycles`

@@ -286,6 +286,7 @@ struct DesignHost {
   uint32_t n_idx[NCLS] = {0};
   uint64_t n_rows = 0;      // 64-bit rows of one instance's state
   bool compact = false;     // storage reused by live range (no all-slot read-out)
+  std::vector<char> kept;   // per slot: its storage holds only it, all cycle long
   std::vector<DevOp> ops;
   std::vector<DevLayer> layers;
   std::vector<std::array<OpRanges, 3>> light;  // per layer, per arity 1..3
@@ -519,6 +520,7 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
   }
   for (int c = 0; c < NCLS; ++c) h->n_idx[c] = cnt[c];
   h->compact = compact;
+  h->kept.assign(keep.begin(), keep.begin() + NS);
 
   // Rows of one instance: the 1-bit rows (at least one, since absent
   // operands read field 0), then the wide rows.  The wide values are laid out
@@ -599,7 +601,30 @@ struct Batch {
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
   std::vector<uint8_t> ev_kind;  // per used pair: 0 main kernel, 1 heavy SWEEP kernel
+  // Value-change capture (rteaal_watch): watched signals, their values after
+  // the last cycle (shadow), the change log and its count.
+  uint32_t n_watch = 0, watch_words = 0;
+  uint64_t log_cap = 0;
+  Mem watch_refs, shadow, log, log_count;
 };
+
+void free_watch(rteaal_ctx* ctx, Batch& b) {
+  dev_free(ctx, b.watch_refs);
+  dev_free(ctx, b.shadow);
+  dev_free(ctx, b.log);
+  dev_free(ctx, b.log_count);
+  b.n_watch = b.watch_words = 0;
+  b.log_cap = 0;
+}
+
+// Appends the capture of the batch's watched signals after a cycle.
+hipError_t capture(const Batch& b, hipStream_t s) {
+  if (!b.n_watch) return hipSuccess;
+  return launch_capture(b.mapping == RTEAAL_MAP_SWEEP, b.L, (const char*)b.state.p,
+                        (const SlotRef*)b.watch_refs.p, b.n_watch, (uint64_t*)b.shadow.p,
+                        b.n_inst, false, (const DevCtl*)b.ctl.p, (ChangeRec*)b.log.p, b.log_cap,
+                        (unsigned long long*)b.log_count.p, s);
+}
 
 void release_events(Batch& b) {
   for (auto& e : b.ev_used) b.ev_free.push_back(e);
@@ -747,14 +772,17 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
   const Program p = program_of(h);
   DevCtl* ctl = (DevCtl*)b.ctl.p;
   if (b.mapping == RTEAAL_MAP_RESIDENT) {
+    // A watched batch runs one cycle per launch, so each cycle is captured.
+    const uint64_t chunk = b.n_watch ? 1 : kResidentChunk;
     for (uint64_t done = 0; done < n_cycles;) {
-      const uint64_t n = std::min(kResidentChunk, n_cycles - done);
+      const uint64_t n = std::min(chunk, n_cycles - done);
       HIP_TRY(ctx, timed(b, ctx->stream, 0, [&] {
                 const ResJob J = res_job(h, b, n);
                 return launch_resident(J, b.n_inst, 0, b.block, b.lds, b.lds_ops, b.unroll,
                                        ctx->stream);
               }));
       HIP_TRY(ctx, launch_advance(ctl, n, ctx->stream));
+      HIP_TRY(ctx, capture(b, ctx->stream));
       done += n;
     }
     return RTEAAL_OK;
@@ -782,6 +810,7 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
                     }));
         }
       HIP_TRY(ctx, launch_advance(ctl, 1, ctx->stream));
+      HIP_TRY(ctx, capture(b, ctx->stream));
     }
     return RTEAAL_OK;
   }
@@ -838,6 +867,7 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
         }
       }
     if (e == hipSuccess) e = launch_advance(ctl, 1, ctx->stream);
+    if (e == hipSuccess) e = capture(b, ctx->stream);
     hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
@@ -905,6 +935,7 @@ void rteaal_destroy(rteaal_ctx* ctx) {
     Batch& b = *kv.second;
     if (b.graph) (void)hipGraphExecDestroy(b.graph);
     destroy_events(b);
+    free_watch(ctx, b);
     dev_free(ctx, b.state);
     dev_free(ctx, b.seeds);
     dev_free(ctx, b.ctl);
@@ -1213,6 +1244,7 @@ rteaal_status rteaal_free_batch(rteaal_ctx* ctx, rteaal_batch_id id) {
   (void)hipStreamSynchronize(ctx->stream);
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   destroy_events(*b);
+  free_watch(ctx, *b);
   dev_free(ctx, b->state);
   dev_free(ctx, b->seeds);
   dev_free(ctx, b->ctl);
@@ -1341,10 +1373,20 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
       return std::tie(lds, ops, unroll, block) < std::tie(o.lds, o.ops, o.unroll, o.block);
     }
   };
+  // Watched RESIDENT batches run one cycle per launch (captured after each)
+  // on the context stream instead.
   std::map<Key, std::vector<uint32_t>> groups;
-  for (uint32_t k = 0; k < n; ++k)
-    if (bs[k]->mapping == RTEAAL_MAP_RESIDENT && n_cycles[k])
-      groups[Key{bs[k]->lds, bs[k]->lds_ops, bs[k]->unroll, bs[k]->block}].push_back(k);
+  for (uint32_t k = 0; k < n; ++k) {
+    Batch& b = *bs[k];
+    if (b.mapping != RTEAAL_MAP_RESIDENT || !n_cycles[k]) continue;
+    if (b.n_watch) {
+      rteaal_status st = enqueue_cycles(ctx, *find_design(ctx, b.design), b, n_cycles[k]);
+      if (st != RTEAAL_OK) return st;
+      b.cycle += n_cycles[k];
+      continue;
+    }
+    groups[Key{b.lds, b.lds_ops, b.unroll, b.block}].push_back(k);
+  }
   for (auto& g : groups) {
     std::vector<uint64_t> left(g.second.size());
     for (size_t q = 0; q < g.second.size(); ++q) left[q] = n_cycles[g.second[q]];
@@ -1472,6 +1514,86 @@ rteaal_status rteaal_write_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t f
     return fail(ctx, RTEAAL_E_DEVICE, "write_state: %s", hipGetErrorString(e));
   }
   b->cycle = cycle;
+  return RTEAAL_OK;
+}
+
+static_assert(sizeof(rteaal_change) == sizeof(ChangeRec), "rteaal_change layout");
+
+rteaal_status rteaal_watch(rteaal_ctx* ctx, rteaal_batch_id id, const uint32_t* slots, uint32_t n,
+                           uint64_t capacity) {
+  if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
+  if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
+  Batch* b = find_batch(ctx, id);
+  if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
+  if (n && !slots) return fail(ctx, RTEAAL_E_INVALID_ARG, "null slots");
+  DesignHost& h = *find_design(ctx, b->design);
+  std::vector<SlotRef> refs(n);
+  uint32_t words = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint32_t sl = slots[k];
+    if (sl >= h.n_slots) return fail(ctx, RTEAAL_E_INVALID_ARG, "slot %u of %u", sl, h.n_slots);
+    if (!h.kept[sl])
+      return fail(ctx, RTEAAL_E_UNSUPPORTED,
+                  "slot %u is not a register: watching it needs a design loaded with "
+                  "RTEAAL_LOAD_KEEP_ALL_SLOTS", sl);
+    refs[k] = h.slot_refs[sl];
+    refs[k].out_off = words;
+    words += (refs[k].width + 63) / 64;
+  }
+  if (capacity > (uint64_t(1) << 40) / sizeof(ChangeRec))
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "log capacity %llu is too large",
+                (unsigned long long)capacity);
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  // The captured cycle graph holds the old buffers: rebuild it.
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  free_watch(ctx, *b);
+  if (n == 0) return RTEAAL_OK;
+  if (!alloc_all(ctx, {{&b->watch_refs, n * sizeof(SlotRef)},
+                       {&b->shadow, (size_t)b->n_inst * words * 8},
+                       {&b->log, std::max<uint64_t>(capacity, 1) * sizeof(ChangeRec)},
+                       {&b->log_count, 8}}))
+    return fail(ctx, RTEAAL_E_NO_MEMORY, "change log of %llu records",
+                (unsigned long long)capacity);
+  b->n_watch = n;
+  b->watch_words = words;
+  b->log_cap = capacity;
+  HIP_TRY(ctx, hipMemcpyAsync(b->watch_refs.p, refs.data(), n * sizeof(SlotRef),
+                              hipMemcpyHostToDevice, ctx->stream));
+  // The values at the call are the reference for the first cycle.
+  HIP_TRY(ctx, launch_capture(b->mapping == RTEAAL_MAP_SWEEP, b->L, (const char*)b->state.p,
+                              (const SlotRef*)b->watch_refs.p, n, (uint64_t*)b->shadow.p,
+                              b->n_inst, true, (const DevCtl*)b->ctl.p, (ChangeRec*)b->log.p,
+                              b->log_cap, (unsigned long long*)b->log_count.p, ctx->stream));
+  HIP_TRY(ctx, launch_fill_u64((uint64_t*)b->log_count.p, 0, 1, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // refs staged from host memory
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_read_changes(rteaal_ctx* ctx, rteaal_batch_id id, rteaal_change* out,
+                                  uint64_t max, uint64_t* n_out, uint64_t* n_dropped) {
+  if (!ctx || !n_out || !n_dropped) return fail(ctx, RTEAAL_E_INVALID_ARG, "null argument");
+  if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
+  Batch* b = find_batch(ctx, id);
+  if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
+  if (!b->n_watch) return fail(ctx, RTEAAL_E_INVALID_ARG, "batch %u is not watched", id);
+  uint64_t total = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&total, b->log_count.p, 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  const uint64_t stored = std::min(total, b->log_cap);
+  *n_out = stored;
+  *n_dropped = total - stored;
+  if (!out || max == 0) return RTEAAL_OK;
+  if (max < stored)
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "the change log holds %llu records, room for %llu",
+                (unsigned long long)stored, (unsigned long long)max);
+  if (stored)
+    HIP_TRY(ctx, hipMemcpyAsync(out, b->log.p, stored * sizeof(ChangeRec), hipMemcpyDeviceToHost,
+                                ctx->stream));
+  HIP_TRY(ctx, launch_fill_u64((uint64_t*)b->log_count.p, 0, 1, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return RTEAAL_OK;
 }
 

@@ -190,4 +190,25 @@ hipError_t launch_unpack(bool sweep, const StateLayout& L, char* state, const Sl
                          const uint64_t* in, hipStream_t s);
 size_t resident_max_lds();
 
+// One record of a batch's change log (the layout of the public rteaal_change).
+struct ChangeRec {
+  uint64_t cycle;
+  uint32_t instance, signal;
+  uint64_t value[4];
+};
+static_assert(sizeof(ChangeRec) == 48, "ChangeRec layout");
+
+// Value-change capture after a cycle: for every instance and watched signal
+// (refs, out_off = the signal's first limb row in shadow), compare the stored
+// value with shadow (signal-major: limb row k holds the n_inst copies at
+// shadow[k * n_inst ...]), update shadow and append a ChangeRec when it
+// differs.  *count counts every change; records at positions >= cap are not
+// stored.  The record's cycle is ctl->cycle.  With init, shadow is filled
+// from the state and nothing is recorded.
+hipError_t launch_capture(bool sweep, const StateLayout& L, const char* state, const SlotRef* refs,
+                          uint32_t n_refs, uint64_t* shadow, uint32_t n_inst, bool init,
+                          const DevCtl* ctl, ChangeRec* log, uint64_t cap,
+                          unsigned long long* count, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
+
 }  // namespace rteaal

@@ -646,6 +646,20 @@ __device__ __forceinline__ char* elem_addr(bool sweep, const StateLayout& L, cha
   return r + ((f & 63u) >> 3);
 }
 
+// Value of limb `limb` of the stored value of ref for instance inst (0 for a
+// slot without storage).
+__device__ __forceinline__ uint64_t load_limb(bool sweep, const StateLayout& L, const char* state,
+                                              const SlotRef& ref, uint32_t limb, uint32_t inst) {
+  if (ref.cls == CNONE) return 0;
+  uint32_t bp = 0;
+  const char* e = elem_addr(sweep, L, (char*)state, ref.cls, ref.pos, limb, inst, &bp);
+  if (ref.cls == CB) return (*(const uint64_t*)e >> bp) & 1ull;
+  if (ref.cls == C8) return *(const uint8_t*)e;
+  if (ref.cls == C16) return *(const uint16_t*)e;
+  if (ref.cls == CW) return *(const uint32_t*)e;
+  return *(const uint64_t*)e;
+}
+
 __global__ void k_pack(bool sweep, StateLayout L, const char* state, const SlotRef* refs,
                        uint32_t n_refs, uint32_t wpi, uint32_t first, uint32_t n, uint64_t* out) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -657,15 +671,7 @@ __global__ void k_pack(bool sweep, StateLayout L, const char* state, const SlotR
   uint64_t* o = out + (uint64_t)k * wpi + ref.out_off;
   for (uint32_t l = 0; l < nl; ++l) {
     uint64_t x = 0;
-    if (ref.cls != CNONE) {
-      uint32_t bp = 0;
-      const char* e = elem_addr(sweep, L, (char*)state, ref.cls, ref.pos, l, inst, &bp);
-      if (ref.cls == CB) x = (*(const uint64_t*)e >> bp) & 1ull;
-      else if (ref.cls == C8) x = *(const uint8_t*)e;
-      else if (ref.cls == C16) x = *(const uint16_t*)e;
-      else if (ref.cls == CW) x = *(const uint32_t*)e;
-      else x = *(const uint64_t*)e;
-    }
+    x = load_limb(sweep, L, state, ref, l, inst);
     o[l] = x;
   }
 }
@@ -703,6 +709,97 @@ __global__ void k_unpack(bool sweep, StateLayout L, char* state, const SlotRef* 
     for (uint32_t l = 0; l < 4; ++l)
       if (l < k2) *(uint64_t*)elem_addr(sweep, L, state, ref.cls, ref.pos, l, inst, &bp) = v.l[l];
   }
+}
+
+// Waveform capture.  Items are (watched signal, instance) pairs, consecutive
+// items on consecutive instances of one signal (adjacent in the SWEEP
+// layout); a value that differs from its copy after the previous cycle is a
+// transition.  shadow is signal-major: limb k of the copies at
+// shadow[k * n_inst ...].  With init, only the copies are written.
+// A block of 256 threads takes 256 * CAP_ITEMS consecutive items, each thread
+// CAP_ITEMS of them 256 apart.  The block's transitions get consecutive log
+// positions from a block-wide scan and one atomic on the shared count (its
+// atomics serialize across the device, so they are kept few); the records
+// are then written from the updated copies.
+constexpr uint32_t CAP_ITEMS = 8;
+
+__global__ void __launch_bounds__(256)
+k_capture(bool sweep, StateLayout L, const char* __restrict__ state, const SlotRef* __restrict__ refs,
+          uint32_t n_refs, uint64_t* shadow, uint32_t n_inst, bool init,
+          const DevCtl* __restrict__ ctl, ChangeRec* log, uint64_t cap, unsigned long long* count) {
+  __shared__ uint32_t s_wave[4];
+  __shared__ unsigned long long s_base;
+  const uint64_t total = (uint64_t)n_refs * n_inst;
+  const uint64_t b0 = (uint64_t)blockIdx.x * (256u * CAP_ITEMS);
+  uint32_t mask = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < CAP_ITEMS; ++k) {
+    const uint64_t i = b0 + k * 256u + threadIdx.x;
+    if (i < total) {
+      const uint32_t inst = (uint32_t)(i % n_inst), r = (uint32_t)(i / n_inst);
+      const SlotRef ref = refs[r];
+      const uint32_t nl = (ref.width + 63u) >> 6;
+      bool ch = false;
+#pragma unroll
+      for (uint32_t l = 0; l < 4; ++l)
+        if (l < nl) {
+          uint64_t* sh = shadow + (uint64_t)(ref.out_off + l) * n_inst + inst;
+          const uint64_t x = load_limb(sweep, L, state, ref, l, inst);
+          if (init || x != *sh) {
+            ch = true;
+            *sh = x;
+          }
+        }
+      if (ch) mask |= 1u << k;
+    }
+  }
+  if (init) return;  // the same for every thread of the launch
+  // Exclusive scan of the per-thread transition counts over the block.
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint32_t c = (uint32_t)__popc(mask);
+  uint32_t x = c;
+#pragma unroll
+  for (uint32_t off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63u) s_wave[wave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (uint32_t w = 0; w < 4; ++w) {
+      const uint32_t v = s_wave[w];
+      s_wave[w] = t;
+      t += v;
+    }
+    s_base = t ? atomicAdd(count, (unsigned long long)t) : 0ull;
+  }
+  __syncthreads();
+  uint64_t pos = s_base + s_wave[wave] + (x - c);
+  const uint64_t cyc = ctl->cycle;
+#pragma unroll
+  for (uint32_t k = 0; k < CAP_ITEMS; ++k)
+    if ((mask >> k) & 1u) {
+      const uint64_t i = b0 + k * 256u + threadIdx.x;
+      const uint32_t inst = (uint32_t)(i % n_inst), r = (uint32_t)(i / n_inst);
+      if (pos < cap) {
+        const SlotRef ref = refs[r];
+        const uint32_t nl = (ref.width + 63u) >> 6;
+        ChangeRec& rec = log[pos];
+        rec.cycle = cyc;
+        rec.instance = inst;
+        rec.signal = r;
+#pragma unroll
+        for (uint32_t l = 0; l < 4; ++l)
+          rec.value[l] = l < nl ? shadow[(uint64_t)(ref.out_off + l) * n_inst + inst] : 0ull;
+      }
+      ++pos;
+    }
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -893,6 +990,24 @@ hipError_t launch_unpack(bool sweep, const StateLayout& L, char* state, const Sl
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_unpack, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, sweep, L,
                      state, refs, n_refs, wpi, first, n, in);
+  return hipGetLastError();
+}
+
+hipError_t launch_capture(bool sweep, const StateLayout& L, const char* state, const SlotRef* refs,
+                          uint32_t n_refs, uint64_t* shadow, uint32_t n_inst, bool init,
+                          const DevCtl* ctl, ChangeRec* log, uint64_t cap,
+                          unsigned long long* count, hipStream_t s) {
+  const uint64_t total = (uint64_t)n_refs * n_inst;
+  if (total == 0) return hipSuccess;
+  const uint64_t per_block = 256ull * CAP_ITEMS;
+  hipLaunchKernelGGL(k_capture, dim3((uint32_t)((total + per_block - 1) / per_block)), dim3(256), 0,
+                     s, sweep, L, state, refs, n_refs, shadow, n_inst, init, ctl, log, cap, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
   return hipGetLastError();
 }
 

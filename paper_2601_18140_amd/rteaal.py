@@ -27,6 +27,7 @@ __all__ = [
     "rteaal_step", "rteaal_step_many", "rteaal_sync", "rteaal_read_state", "rteaal_write_state",
     "rteaal_kernel_timing", "rteaal_autotune", "opts_dict", "unpack_limbs", "pack_limbs", "rteaal_layer_format", "rteaal_rank_format",
     "rteaal_dag_desc", "rteaal_levelize", "levelized_design",
+    "CHANGE_DTYPE", "rteaal_watch", "rteaal_read_changes",
 ]
 
 RTEAAL_OK = 0
@@ -127,6 +128,8 @@ def library():
         "rteaal_kernel_timing": ([vp, u32, C.c_int, C.POINTER(u64), C.POINTER(C.c_double)], st),
         "rteaal_autotune": ([vp, u32, u32, u32, C.POINTER(rteaal_batch_opts), C.POINTER(C.c_double)], st),
         "rteaal_levelize": ([vp, C.POINTER(rteaal_dag_desc), vp, vp, vp, C.POINTER(u32)], st),
+        "rteaal_watch": ([vp, u32, vp, u32, u64], st),
+        "rteaal_read_changes": ([vp, u32, vp, u64, C.POINTER(u64), C.POINTER(u64)], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -143,7 +146,7 @@ def exported_symbols():
             "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch",
             "rteaal_batch_info", "rteaal_batch_options", "rteaal_step", "rteaal_step_many", "rteaal_sync",
             "rteaal_read_state", "rteaal_write_state", "rteaal_kernel_timing", "rteaal_autotune",
-            "rteaal_levelize"]
+            "rteaal_levelize", "rteaal_watch", "rteaal_read_changes"]
 
 
 def _check(ctx, status):
@@ -324,6 +327,31 @@ def levelized_design(ctx, design):
     out.op_src_ptr = new_ptr.astype(np.uint32)
     out.layer_ptr = lptr.astype(np.uint32)
     return out
+
+
+# Layout of rteaal_change (48 bytes).
+CHANGE_DTYPE = np.dtype([("cycle", np.uint64), ("instance", np.uint32), ("signal", np.uint32),
+                         ("value", np.uint64, (4,))])
+
+
+def rteaal_watch(ctx, batch_id, slots, capacity=1 << 20):
+    """Watch `slots` of every instance of the batch (empty: stop watching)."""
+    sl = np.ascontiguousarray(slots, dtype=np.uint32)
+    _check(ctx.handle, library().rteaal_watch(ctx.handle, int(batch_id),
+                                              sl.ctypes.data if sl.size else None, int(sl.size),
+                                              int(capacity)))
+
+
+def rteaal_read_changes(ctx, batch_id):
+    """Drain the change log: (records as a CHANGE_DTYPE array, dropped count)."""
+    lib = library()
+    n, dropped = C.c_uint64(), C.c_uint64()
+    _check(ctx.handle, lib.rteaal_read_changes(ctx.handle, int(batch_id), None, 0, C.byref(n),
+                                               C.byref(dropped)))
+    out = np.zeros(max(n.value, 1), CHANGE_DTYPE)
+    _check(ctx.handle, lib.rteaal_read_changes(ctx.handle, int(batch_id), out.ctypes.data,
+                                               out.size, C.byref(n), C.byref(dropped)))
+    return out[: n.value].copy(), int(dropped.value)
 
 
 RTEAAL_LOAD_KEEP_ALL_SLOTS = 1

@@ -77,8 +77,8 @@ const char* rteaal_last_error(const rteaal_ctx* ctx);
 /* ------------------------------------------------------------------------ */
 
 /* Rank-N coordinates.  AND/OR/XOR take 2 or 3 operands (the O fiber's
- * occupancy, fixed per (type, arity)); NOT/SHL/SHR/EXTRACT/ORR take 1;
- * ADD/SUB/MUL/EQ/LT/CONCAT take 2; MUX takes 3.
+ * occupancy, fixed per (type, arity)); NOT/SHL/SHR/EXTRACT/ORR/ANDR/XORR/SEXT
+ * take 1; ADD/SUB/MUL/EQ/LT/CONCAT/DIV/REM/DSHL/DSHR take 2; MUX takes 3.
  * Results (all unsigned, computed on zero-extended operands, then reduced
  * modulo 2^dst_width):
  *   AND/OR/XOR  fold over operands       NOT      bitwise complement
@@ -86,12 +86,22 @@ const char* rteaal_last_error(const rteaal_ctx* ctx);
  *   MUX         o0 != 0 ? o1 : o2        EQ, LT   [o0 == o1], [o0 < o1]
  *   SHL, SHR    o0 shifted by imm        EXTRACT  o0 >> imm (width from dst)
  *   CONCAT      o0 * 2^width(o1) + o1    ORR      [o0 != 0]
+ *   DIV, REM    o0 / o1, o0 mod o1 (o1 = 0 gives 0 and o0)
+ *   DSHL, DSHR  o0 * 2^o1, o0 / 2^o1     ANDR     [o0 = 2^width(o0) - 1]
+ *   XORR        parity of o0             SEXT     o0 read as a width(o0)-bit
+ *                                                 two's-complement number
+ * With these, every FIRRTL primitive operation maps onto one type or a short
+ * chain: bits/head/tail/pad/cvt/as* are EXTRACT or SEXT, leq/gt/geq/neq are
+ * LT/EQ with swapped operands or NOT, neg is SUB from a zero literal, and
+ * the signed forms of add/sub/mul/lt/shr/div/rem run on SEXT-extended
+ * operands (lt after flipping both sign bits with XOR).
  * Operand o=0 is reduced first, as the left operand (section "Evaluating
  * Multiple Operation Types"); MUX is the select operator op_s of Appendix A. */
 typedef enum {
   RTEAAL_AND = 0, RTEAAL_OR, RTEAAL_XOR, RTEAAL_NOT, RTEAAL_ADD, RTEAAL_SUB, RTEAAL_MUL,
   RTEAAL_MUX, RTEAAL_EQ, RTEAAL_LT, RTEAAL_SHL, RTEAAL_SHR, RTEAAL_EXTRACT, RTEAAL_CONCAT,
-  RTEAAL_ORR, RTEAAL_OP_COUNT
+  RTEAAL_ORR, RTEAAL_DIV, RTEAAL_REM, RTEAAL_DSHL, RTEAAL_DSHR, RTEAAL_ANDR, RTEAAL_XORR,
+  RTEAAL_SEXT, RTEAAL_OP_COUNT
 } rteaal_op;
 
 /* Per-rank format (section "Format": uncompressed or compressed, coordinate

@@ -104,6 +104,31 @@ static int v_cmp(const val* a, const val* b) {
 
 static val v_bool(int x) { val r = v_zero(); r.l[0] = x ? 1 : 0; return r; }
 
+/* Quotient and remainder by restoring long division, one bit at a time from
+ * the top (schoolbook binary division).  The partial remainder stays below b
+ * but doubling it can need bit 256: `top` keeps that bit.  b = 0 is handled
+ * by the caller. */
+static void v_divmod(val a, val b, val* q, val* r) {
+  *q = v_zero();
+  *r = v_zero();
+  for (int i = 64 * ORACLE_LIMBS - 1; i >= 0; i--) {
+    const int top = (int)(r->l[ORACLE_LIMBS - 1] >> 63);
+    *r = v_shl(*r, 1);
+    r->l[0] |= (a.l[i / 64] >> (i % 64)) & 1;
+    if (top || v_cmp(r, &b) >= 0) {
+      *r = v_sub(*r, b);
+      q->l[i / 64] |= (uint64_t)1 << (i % 64);
+    }
+  }
+}
+
+/* A shift amount held in a value: its number, or 2^32 when it exceeds every
+ * useful shift (every bit shifted out). */
+static int v_shift_amount(const val* b) {
+  for (int i = 1; i < ORACLE_LIMBS; i++) if (b->l[i]) return 1 << 30;
+  return b->l[0] >= (1u << 30) ? 1 << 30 : (int)b->l[0];
+}
+
 /* ------------------------------------------------------------------------ */
 /* The per-type operators of Cascade 1.                                     */
 /*   reducible types: map is pass-through, op_r folds operands in O order   */
@@ -113,17 +138,34 @@ static val v_bool(int x) { val r = v_zero(); r.l[0] = x ? 1 : 0; return r; }
 /*   select types:    op_s looks at the whole O fiber (mux).                */
 /* ------------------------------------------------------------------------ */
 static int is_unary(int n) {
-  return n == ORC_NOT || n == ORC_SHL || n == ORC_SHR || n == ORC_EXTRACT || n == ORC_ORR;
+  return n == ORC_NOT || n == ORC_SHL || n == ORC_SHR || n == ORC_EXTRACT || n == ORC_ORR ||
+         n == ORC_ANDR || n == ORC_XORR || n == ORC_SEXT;
 }
 static int is_select(int n) { return n == ORC_MUX; }
 
-static val op_u(int n, val x, int imm) {
+/* x_w: declared width of the operand. */
+static val op_u(int n, val x, int imm, int x_w) {
   switch (n) {
     case ORC_NOT:     return v_not(x);
     case ORC_SHL:     return v_shl(x, imm);
     case ORC_SHR:     return v_shr(x, imm);
     case ORC_EXTRACT: return v_shr(x, imm);      /* low bit index; width from dst */
     case ORC_ORR:     return v_bool(!v_is_zero(&x));
+    case ORC_ANDR: {                             /* every one of the x_w bits set */
+      val ones = v_mask(v_not(v_zero()), x_w);
+      return v_bool(v_cmp(&x, &ones) == 0);
+    }
+    case ORC_XORR: {                             /* parity of the bits */
+      int p = 0;
+      for (int i = 0; i < 64 * ORACLE_LIMBS; i++) p ^= (int)((x.l[i / 64] >> (i % 64)) & 1);
+      return v_bool(p);
+    }
+    case ORC_SEXT:                               /* x as an x_w-bit two's-complement number */
+      if ((x.l[(x_w - 1) / 64] >> ((x_w - 1) % 64)) & 1) {
+        val high = v_shl(v_not(v_zero()), x_w);  /* every bit from x_w up */
+        for (int i = 0; i < ORACLE_LIMBS; i++) x.l[i] |= high.l[i];
+      }
+      return x;
     default:          return x;                  /* pass-through map */
   }
 }
@@ -146,6 +188,14 @@ static val op_r(int n, val prev, val cur, int cur_w) {
       for (int i = 0; i < ORACLE_LIMBS; i++) hi.l[i] |= cur.l[i];
       return hi;
     }
+    case ORC_DIV: case ORC_REM: {                 /* by zero: quotient 0, remainder prev */
+      if (v_is_zero(&cur)) return n == ORC_DIV ? v_zero() : prev;
+      val q, r;
+      v_divmod(prev, cur, &q, &r);
+      return n == ORC_DIV ? q : r;
+    }
+    case ORC_DSHL: return v_shl(prev, v_shift_amount(&cur));
+    case ORC_DSHR: return v_shr(prev, v_shift_amount(&cur));
     default: return cur;                          /* non-reducible: copy */
   }
 }
@@ -160,8 +210,10 @@ static int arity_ok(int n, int a) {
     case ORC_AND: case ORC_OR: case ORC_XOR: return a == 2 || a == 3;
     case ORC_MUX: return a == 3;
     case ORC_ADD: case ORC_SUB: case ORC_MUL: case ORC_EQ: case ORC_LT: case ORC_CONCAT:
+    case ORC_DIV: case ORC_REM: case ORC_DSHL: case ORC_DSHR:
       return a == 2;
-    case ORC_NOT: case ORC_SHL: case ORC_SHR: case ORC_EXTRACT: case ORC_ORR: return a == 1;
+    case ORC_NOT: case ORC_SHL: case ORC_SHR: case ORC_EXTRACT: case ORC_ORR:
+    case ORC_ANDR: case ORC_XORR: case ORC_SEXT: return a == 1;
     default: return 0;
   }
 }
@@ -169,7 +221,7 @@ static int arity_ok(int n, int a) {
 /* LO for one operation from its selected inputs OI (in O order). */
 static val eval_one(int n, int arity, const val* oi, const uint16_t* oi_w, int imm) {
   if (is_select(n)) return op_s(n, oi, arity);
-  if (is_unary(n)) return op_u(n, oi[0], imm);
+  if (is_unary(n)) return op_u(n, oi[0], imm, oi_w[0]);
   val acc = oi[0];                                /* first map temporary copied */
   for (int o = 1; o < arity; o++) acc = op_r(n, acc, oi[o], oi_w[o]);
   return acc;

@@ -28,7 +28,8 @@ extern "C" {
 /* Rank-N coordinates (operation types). */
 enum {
   ORC_AND = 0, ORC_OR, ORC_XOR, ORC_NOT, ORC_ADD, ORC_SUB, ORC_MUL, ORC_MUX,
-  ORC_EQ, ORC_LT, ORC_SHL, ORC_SHR, ORC_EXTRACT, ORC_CONCAT, ORC_ORR, ORC_NTYPES
+  ORC_EQ, ORC_LT, ORC_SHL, ORC_SHR, ORC_EXTRACT, ORC_CONCAT, ORC_ORR,
+  ORC_DIV, ORC_REM, ORC_DSHL, ORC_DSHR, ORC_ANDR, ORC_XORR, ORC_SEXT, ORC_NTYPES
 };
 
 typedef struct {

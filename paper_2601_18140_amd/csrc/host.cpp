@@ -128,8 +128,10 @@ uint32_t expected_arity_ok(uint32_t t, uint32_t a) {
     case RTEAAL_AND: case RTEAAL_OR: case RTEAAL_XOR: return a == 2 || a == 3;
     case RTEAAL_MUX: return a == 3;
     case RTEAAL_ADD: case RTEAAL_SUB: case RTEAAL_MUL: case RTEAAL_EQ: case RTEAAL_LT:
-    case RTEAAL_CONCAT: return a == 2;
+    case RTEAAL_CONCAT: case RTEAAL_DIV: case RTEAAL_REM: case RTEAAL_DSHL: case RTEAAL_DSHR:
+      return a == 2;
     case RTEAAL_NOT: case RTEAAL_SHL: case RTEAAL_SHR: case RTEAAL_EXTRACT: case RTEAAL_ORR:
+    case RTEAAL_ANDR: case RTEAAL_XORR: case RTEAAL_SEXT:
       return a == 1;
     default: return 0;
   }
@@ -342,6 +344,9 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
       all_32 = all_32 && cls_of(src[o]) <= CW;
     }
     if (opc >= OP_STIM) all_b = all_32 = false;
+    // The FIRRTL primitives DIV .. SEXT always run in the wide form, which
+    // keeps them out of the common kernel.
+    if (opc >= OP_DIV && opc <= OP_SEXT) any_wide = true;
     e.kind = any_wide ? K_WIDE : all_b ? K_BIT : all_32 ? K_U32 : K_U64;
     return e;
   };
@@ -366,6 +371,7 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
       const uint32_t ar = d->op_src_ptr[o + 1] - d->op_src_ptr[o];
       uint32_t imm = d->op_imm[o];
       if (t == RTEAAL_CONCAT) imm = width[s[1]];
+      if (t == RTEAAL_ANDR || t == RTEAAL_SEXT) imm = width[s[0]];
       lay.push_back(mk(t, ar, d->op_dst[o], s, imm, 0, 0));
     }
     L.push_back(std::move(lay));  // empty design layers still separate their neighbours

@@ -29,13 +29,14 @@ __host__ __device__ inline uint32_t cls_bytes(uint32_t c) {
   return c <= CW ? (8u >> cls_w3(c)) : 8u * cls_limbs(c);
 }
 
-// Operation codes: the public rank-N coordinates 0..14 plus three
+// Operation codes: the public rank-N coordinates 0..21 plus three
 // bookkeeping operations the encoder adds around the design's layers:
 // COPY (register commit and its staging), STIM (primary input from the
 // stimulus) and CONST (literal).
 enum Opc : uint32_t {
   OP_AND = 0, OP_OR, OP_XOR, OP_NOT, OP_ADD, OP_SUB, OP_MUL, OP_MUX, OP_EQ, OP_LT, OP_SHL,
-  OP_SHR, OP_EXTRACT, OP_CONCAT, OP_ORR, OP_COPY = 15, OP_STIM = 16, OP_CONST = 17
+  OP_SHR, OP_EXTRACT, OP_CONCAT, OP_ORR, OP_DIV, OP_REM, OP_DSHL, OP_DSHR, OP_ANDR, OP_XORR,
+  OP_SEXT, OP_COPY = 60, OP_STIM = 61, OP_CONST = 62
 };
 
 // Evaluation kind: every class is CB (1-bit logic on whole words of
@@ -45,7 +46,8 @@ enum Kind : uint32_t { K_BIT = 0, K_U64 = 1, K_WIDE = 2, K_U32 = 3 };
 
 // One operation, 32 bytes.
 //   code: opc[0:5] kind[6:7] arity[8:9] dst class[10:12] src classes [13:15][16:18][19:21]
-//   wimm: dst width[0:8] (1..256), imm[9:17] (shift, low bit, width of o1 for CONCAT)
+//   wimm: dst width[0:8] (1..256), imm[9:17] (shift, low bit, width of o1 for CONCAT,
+//         width of o0 for ANDR and SEXT)
 //   dst, src[3]: slot fields 64*row + shift (see StateLayout)
 //   aux0: STIM input number / CONST literal index;  aux1: STIM limb offset in a words row
 struct DevOp {

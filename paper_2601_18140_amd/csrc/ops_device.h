@@ -3,7 +3,8 @@
 //   eval_u64  : every operand and the result fit 64 bits (one lane = one value);
 //   eval_bits : every operand and the result are 1 bit and each 64-bit word
 //               holds that signal for 64 instances (bit-sliced);
-//   eval_wide : up to 256 bits in four 64-bit limbs.
+//   eval_wide : up to 256 bits in four 64-bit limbs (also every operation of
+//               the types DIV .. SEXT, whatever its widths).
 // All results are reduced modulo 2^width of the destination.
 #pragma once
 #include "internal.h"
@@ -274,6 +275,33 @@ __device__ __forceinline__ V4 v4_mask(V4 a, uint32_t w) {
   return a;
 }
 
+// Quotient (want_q) or remainder of a / b, b != 0, by restoring long
+// division over a's significant bits.  The partial remainder stays below b,
+// but doubling it can need bit 256, which `top` keeps.
+__device__ __forceinline__ V4 v4_divmod(const V4& a, const V4& b, bool want_q) {
+  int n = 0;  // significant bits of a
+#pragma unroll
+  for (int k = 3; k >= 0; --k)
+    if (n == 0 && a.l[k]) n = 64 * k + 64 - __clzll((long long)a.l[k]);
+  V4 q = v4_from(0), r = v4_from(0);
+  for (int i = n - 1; i >= 0; --i) {
+    const uint64_t top = r.l[3] >> 63;
+    r = v4_shl(r, 1u);
+    r.l[0] |= (v4_limb(a, i >> 6) >> (i & 63)) & 1ull;
+    if (top || !v4_lt(r, b)) {
+      r = v4_sub(r, b);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q.l[k] |= (k == (i >> 6)) ? 1ull << (i & 63) : 0ull;
+    }
+  }
+  return want_q ? q : r;
+}
+
+// A shift amount held in a value, capped at 256 (everything shifted out).
+__device__ __forceinline__ uint32_t v4_amount(const V4& b) {
+  return (b.l[1] | b.l[2] | b.l[3]) || b.l[0] >= 256ull ? 256u : (uint32_t)b.l[0];
+}
+
 __device__ __forceinline__ V4 eval_wide(uint32_t opc, uint32_t arity, const V4& a, const V4& b,
                                         const V4& c, uint32_t imm, uint32_t w) {
   V4 r;
@@ -312,6 +340,35 @@ __device__ __forceinline__ V4 eval_wide(uint32_t opc, uint32_t arity, const V4& 
       break;
     }
     case OP_ORR: r = v4_from(v4_nonzero(a)); break;
+    // The FIRRTL primitives with no expansion in the types above; the
+    // encoder runs them in this form whatever their widths.
+    case OP_DIV:  // division by zero reads as quotient 0 ...
+      r = v4_nonzero(b) ? v4_divmod(a, b, true) : v4_from(0);
+      break;
+    case OP_REM:  // ... and remainder a
+      r = v4_nonzero(b) ? v4_divmod(a, b, false) : a;
+      break;
+    case OP_DSHL: r = v4_shl(a, v4_amount(b)); break;
+    case OP_DSHR: r = v4_shr(a, v4_amount(b)); break;
+    case OP_ANDR: {  // imm = width of o0: are all its bits set?
+      const V4 ones = v4_mask(V4{{~0ull, ~0ull, ~0ull, ~0ull}}, imm);
+      r = v4_from((a.l[0] == ones.l[0]) & (a.l[1] == ones.l[1]) & (a.l[2] == ones.l[2]) &
+                  (a.l[3] == ones.l[3]));
+      break;
+    }
+    case OP_XORR:
+      r = v4_from((uint64_t)__popcll(a.l[0] ^ a.l[1] ^ a.l[2] ^ a.l[3]) & 1ull);
+      break;
+    case OP_SEXT: {  // imm = width of o0, read as two's complement
+      r = a;
+      const uint32_t sb = imm - 1u;
+      if ((v4_limb(a, (int)(sb >> 6)) >> (sb & 63u)) & 1ull) {
+        const V4 high = v4_shl(V4{{~0ull, ~0ull, ~0ull, ~0ull}}, imm);
+#pragma unroll
+        for (int i = 0; i < 4; i++) r.l[i] |= high.l[i];
+      }
+      break;
+    }
     default: r = a; break;  // COPY
   }
   return v4_mask(r, w);

@@ -24,16 +24,19 @@ import numpy as np
 
 # Operation-type coordinates (rank N).  The numeric values are part of the
 # C interface of both the library and the oracle.
-AND, OR, XOR, NOT, ADD, SUB, MUL, MUX, EQ, LT, SHL, SHR, EXTRACT, CONCAT, ORR = range(15)
-OP_COUNT = 15
+(AND, OR, XOR, NOT, ADD, SUB, MUL, MUX, EQ, LT, SHL, SHR, EXTRACT, CONCAT, ORR,
+ DIV, REM, DSHL, DSHR, ANDR, XORR, SEXT) = range(22)
+OP_COUNT = 22
 OP_NAMES = ["and", "or", "xor", "not", "add", "sub", "mul", "mux", "eq", "lt",
-            "shl", "shr", "extract", "concat", "orr"]
+            "shl", "shr", "extract", "concat", "orr",
+            "div", "rem", "dshl", "dshr", "andr", "xorr", "sext"]
 
 # Allowed occupancies of the O fiber for each type.
 OP_ARITIES = {
     AND: (2, 3), OR: (2, 3), XOR: (2, 3), NOT: (1,), ADD: (2,), SUB: (2,),
     MUL: (2,), MUX: (3,), EQ: (2,), LT: (2,), SHL: (1,), SHR: (1,),
     EXTRACT: (1,), CONCAT: (2,), ORR: (1,),
+    DIV: (2,), REM: (2,), DSHL: (2,), DSHR: (2,), ANDR: (1,), XORR: (1,), SEXT: (1,),
 }
 
 MAX_WIDTH = 256

@@ -15,8 +15,8 @@ import math
 
 import numpy as np
 
-from .design import (ADD, AND, CONCAT, EQ, EXTRACT, LT, MUL, MUX, NOT, OR, ORR, SHL, SHR,
-                     SUB, XOR, Design)
+from .design import (ADD, AND, ANDR, CONCAT, DIV, DSHL, DSHR, EQ, EXTRACT, LT, MUL, MUX, NOT, OR,
+                     ORR, REM, SEXT, SHL, SHR, SUB, XOR, XORR, Design)
 
 # (type, arity, probability): and/or/xor/not 30 %, add/sub 15 %, mux 15 %,
 # eq/lt 10 %, shift-by-const 10 %, extract/concat 10 %, mul 5 %, reduce-or 5 %.
@@ -27,7 +27,13 @@ OP_MIX = (
     (EQ, 2, 0.05), (LT, 2, 0.05), (SHL, 1, 0.05), (SHR, 1, 0.05),
     (EXTRACT, 1, 0.05), (CONCAT, 2, 0.05), (MUL, 2, 0.05), (ORR, 1, 0.05),
 )
-ONE_BIT_TYPES = (EQ, LT, ORR)
+# Every type, the FIRRTL primitives without an expansion in the others
+# included: for test designs (the workloads keep OP_MIX).
+OP_MIX_FULL = OP_MIX + (
+    (DIV, 2, 0.03), (REM, 2, 0.03), (DSHL, 2, 0.03), (DSHR, 2, 0.03),
+    (ANDR, 1, 0.03), (XORR, 1, 0.03), (SEXT, 1, 0.04),
+)
+ONE_BIT_TYPES = (EQ, LT, ORR, ANDR, XORR)
 
 # Width buckets: (lo, hi inclusive, probability).
 WIDTHS_STD = ((1, 1, 0.40), (2, 8, 0.25), (9, 32, 0.25), (33, 64, 0.10))
@@ -43,6 +49,7 @@ class GenConfig:
     n_inputs: int
     widths: tuple = WIDTHS_STD
     name: str = "design"
+    op_mix: tuple = OP_MIX
 
 
 def _bucket_draw(rng, buckets, n):
@@ -54,9 +61,9 @@ def _bucket_draw(rng, buckets, n):
     return lo + (rng.random(n) * (hi - lo + 1)).astype(np.int64)
 
 
-def _conditional_buckets(buckets):
+def _conditional_buckets(buckets, mix=OP_MIX):
     """Width mix for ops not forced to 1 bit, so the overall mix matches `buckets`."""
-    forced = sum(p for t, _, p in OP_MIX if t in ONE_BIT_TYPES)
+    forced = sum(p for t, _, p in mix if t in ONE_BIT_TYPES) / sum(p for _, _, p in mix)
     out = []
     for lo, hi, p in buckets:
         q = p - (forced if (lo, hi) == (1, 1) else 0.0)
@@ -80,18 +87,19 @@ def generate(cfg: GenConfig, seed: int) -> Design:
     np.cumsum(sizes, out=layer_ptr[1:])
 
     # Types and arities.
-    mix_p = np.array([m[2] for m in OP_MIX])
+    mix = cfg.op_mix
+    mix_p = np.array([m[2] for m in mix])
     mix_p /= mix_p.sum()
-    pick = rng.choice(len(OP_MIX), size=n_ops, p=mix_p)
-    op_type = np.array([m[0] for m in OP_MIX], dtype=np.int64)[pick]
-    arity = np.array([m[1] for m in OP_MIX], dtype=np.int64)[pick]
+    pick = rng.choice(len(mix), size=n_ops, p=mix_p)
+    op_type = np.array([m[0] for m in mix], dtype=np.int64)[pick]
+    arity = np.array([m[1] for m in mix], dtype=np.int64)[pick]
 
     # Slot layout: [inputs][registers][one destination per op, in layer order].
     base_in, base_reg, base_op = 0, n_in, n_in + n_reg
     n_slots = base_op + n_ops
     width = np.zeros(n_slots, dtype=np.int64)
     width[: base_op] = _bucket_draw(rng, cfg.widths, base_op)
-    w_ops = _bucket_draw(rng, _conditional_buckets(cfg.widths), n_ops)
+    w_ops = _bucket_draw(rng, _conditional_buckets(cfg.widths, mix), n_ops)
     w_ops[np.isin(op_type, ONE_BIT_TYPES)] = 1
     width[base_op:] = w_ops
 

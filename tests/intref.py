@@ -4,8 +4,8 @@
 is an independent, deliberately naive interpreter of a whole design built
 on it (used only to cross-check the C oracle on tiny designs).
 """
-from rtlgen.design import (ADD, AND, CONCAT, EQ, EXTRACT, LT, MUL, MUX, NOT, OR, ORR, SHL, SHR,
-                           SUB, XOR)
+from rtlgen.design import (ADD, AND, ANDR, CONCAT, DIV, DSHL, DSHR, EQ, EXTRACT, LT, MUL, MUX, NOT,
+                           OR, ORR, REM, SEXT, SHL, SHR, SUB, XOR, XORR)
 
 M64 = (1 << 64) - 1
 
@@ -47,6 +47,20 @@ def textbook(typ, vals, widths, wd, imm):
         r = a * (2 ** widths[1]) + vals[1]
     elif typ == ORR:
         r = int(a != 0)
+    elif typ == DIV:                  # division by zero reads as quotient 0
+        r = a // vals[1] if vals[1] else 0
+    elif typ == REM:                  # ... and remainder a
+        r = a % vals[1] if vals[1] else a
+    elif typ == DSHL:
+        r = a * 2 ** min(vals[1], 1024)
+    elif typ == DSHR:
+        r = a // 2 ** min(vals[1], 1024)
+    elif typ == ANDR:
+        r = int(a == 2 ** widths[0] - 1)
+    elif typ == XORR:
+        r = bin(a).count("1") % 2
+    elif typ == SEXT:                 # a as a widths[0]-bit two's-complement integer
+        r = a - 2 ** widths[0] if a >= 2 ** (widths[0] - 1) else a
     else:
         raise ValueError(typ)
     return r % (1 << wd)

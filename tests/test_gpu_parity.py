@@ -287,6 +287,43 @@ def test_single_200k_batched_and_plain(ctx):
     assert_same(got1, ref1, "plain")
 
 
+# ---- FIRRTL primitives added to the N rank ------------------------------------
+ADDED = [(rtlgen.DIV, 2), (rtlgen.REM, 2), (rtlgen.DSHL, 2), (rtlgen.DSHR, 2), (rtlgen.ANDR, 1),
+         (rtlgen.XORR, 1), (rtlgen.SEXT, 1)]
+# (operand widths, destination width): 1-bit and narrow classes, limb
+# boundaries, small shift amounts and divisors that are often zero.
+SHAPES = {1: [((1,), 1), ((3,), 8), ((8,), 16), ((13,), 64), ((32,), 70), ((64,), 64),
+              ((65,), 200), ((128,), 256), ((200,), 7), ((256,), 256)],
+          2: [((1, 1), 1), ((8, 2), 8), ((16, 5), 16), ((32, 6), 64), ((40, 9), 40),
+              ((64, 64), 64), ((100, 8), 256), ((130, 129), 130), ((256, 3), 256),
+              ((256, 256), 256), ((7, 200), 12)]}
+
+
+@pytest.mark.parametrize("mapping", MAPS, ids=MAP_IDS)
+@pytest.mark.parametrize("typ,arity", ADDED, ids=[rtlgen.OP_NAMES[t] for t, _ in ADDED])
+def test_added_primitives_single_ops(ctx, typ, arity, mapping):
+    seeds = np.arange(96, dtype=np.uint64)
+    for ws, wd in SHAPES[arity]:
+        d = cir.single_op(typ, list(ws), wd)
+        ref, _, _ = oracle.run(d, seeds, 3)
+        got, _, _ = run_gpu(ctx, d, seeds, 3, mapping=mapping)
+        assert_same(got, ref, f"{rtlgen.OP_NAMES[typ]} {ws}->{wd}")
+
+
+@pytest.mark.parametrize("mapping", MAPS, ids=MAP_IDS)
+def test_generated_design_with_every_type(ctx, mapping):
+    cfg = rtlgen.GenConfig(6_000, 14, 80, 10, rtlgen.generator.WIDTHS_LARGE, "all-types",
+                           rtlgen.OP_MIX_FULL)
+    d = rtlgen.generate(cfg, 17)
+    assert set(np.unique(d.op_type)) == set(range(rtlgen.OP_COUNT))
+    seeds = rtlgen.instance_seeds(70)
+    note(f"all-types design, mapping={mapping}")
+    ref_regs, ref_slots, _ = oracle.run(d, seeds, 15, want_slots=True)
+    regs, sl, _ = run_gpu(ctx, d, seeds, [7, 8], mapping=mapping, slots=True)
+    assert_same(regs, ref_regs, "registers")
+    assert_same(sl, ref_slots, "every slot")
+
+
 # ---- several designs in one step -------------------------------------------
 def test_step_many_mixed_designs(ctx):
     """Batches of different designs, sizes, mappings and cycle counts advanced

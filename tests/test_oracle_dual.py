@@ -15,6 +15,8 @@ CASES = [
     rtlgen.GenConfig(120, 5, 10, 6, rtlgen.generator.WIDTHS_STD, "tiny-std"),
     rtlgen.GenConfig(150, 7, 12, 5, rtlgen.generator.WIDTHS_LARGE, "tiny-wide"),
     rtlgen.GenConfig(90, 3, 4, 3, rtlgen.generator.WIDTHS_MULTIDESIGN, "tiny-multi"),
+    rtlgen.GenConfig(160, 6, 10, 6, rtlgen.generator.WIDTHS_LARGE, "tiny-all-types",
+                     rtlgen.OP_MIX_FULL),
 ]
 
 

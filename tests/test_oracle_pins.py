@@ -16,8 +16,8 @@ import pytest
 
 import rtlgen
 from rtlgen import circuits as cir
-from rtlgen.design import (ADD, AND, CONCAT, EQ, EXTRACT, LT, MUL, MUX, NOT, OR, ORR, SHL, SHR,
-                           SUB, XOR, limbs_to_int)
+from rtlgen.design import (ADD, AND, ANDR, CONCAT, DIV, DSHL, DSHR, EQ, EXTRACT, LT, MUL, MUX, NOT,
+                           OR, ORR, REM, SEXT, SHL, SHR, SUB, XOR, XORR, limbs_to_int)
 from tests.intref import textbook
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -26,7 +26,8 @@ NAME2OP = {n: i for i, n in enumerate(rtlgen.OP_NAMES)}
 
 ARITIES = [(AND, 2), (AND, 3), (OR, 2), (OR, 3), (XOR, 2), (XOR, 3), (NOT, 1), (ADD, 2),
            (SUB, 2), (MUL, 2), (MUX, 3), (EQ, 2), (LT, 2), (SHL, 1), (SHR, 1), (EXTRACT, 1),
-           (CONCAT, 2), (ORR, 1)]
+           (CONCAT, 2), (ORR, 1), (DIV, 2), (REM, 2), (DSHL, 2), (DSHR, 2), (ANDR, 1), (XORR, 1),
+           (SEXT, 1)]
 
 
 @pytest.mark.parametrize("typ,arity", ARITIES, ids=[f"{rtlgen.OP_NAMES[t]}{a}" for t, a in ARITIES])
@@ -67,6 +68,28 @@ def test_wide_operands_random(oracle_lib, typ, arity):
             vals[0] = 0
         got = oracle_lib.eval_op(typ, vals, ws, wd, imm)
         assert got == textbook(typ, vals, ws, wd, imm), (typ, vals, ws, wd, imm)
+
+
+def test_added_types_edges(oracle_lib):
+    """Dynamic shifts by small amounts of wide values, divisors of 255-256
+    bits (the long division's top bit), sign extension across limb
+    boundaries, and ANDR of all-ones values."""
+    rng = random.Random(77)
+    edge = [1, 2, 63, 64, 65, 127, 128, 129, 191, 192, 193, 255, 256]
+    for _ in range(300):
+        w0, wd = rng.choice(edge), rng.choice(edge)
+        a = rng.getrandbits(w0)
+        k = rng.randint(0, 300)
+        for typ in (DSHL, DSHR):
+            assert oracle_lib.eval_op(typ, (a, k), (w0, 9), wd, 0) == textbook(typ, (a, k), (w0, 9), wd, 0)
+        for typ in (SEXT, ANDR):
+            for x in (a, (1 << w0) - 1, 1 << (w0 - 1), (1 << (w0 - 1)) - 1):
+                assert oracle_lib.eval_op(typ, (x,), (w0,), wd, 0) == textbook(typ, (x,), (w0,), wd, 0)
+    for _ in range(300):
+        b = (1 << 255) | rng.getrandbits(255) if rng.random() < 0.5 else (1 << 256) - 1 - rng.getrandbits(8)
+        a = (1 << 256) - 1 - rng.getrandbits(rng.choice([8, 64, 200, 256]))
+        for typ in (DIV, REM):
+            assert oracle_lib.eval_op(typ, (a, b), (256, 256), 256, 0) == textbook(typ, (a, b), (256, 256), 256, 0)
 
 
 def test_hand_examples(oracle_lib):

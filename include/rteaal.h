@@ -225,10 +225,11 @@ rteaal_status rteaal_design_format(rteaal_ctx* ctx, rteaal_design_id design, uin
  *   SWEEP:    one lane per instance (64 instances per wavefront, 1-bit
  *             signals bit-sliced into 64-bit words), operation records read
  *             once per wavefront for one to eight 64-instance tiles; per
- *             layer one launch for the operations of at most 64 bits (one per
- *             operand count in large layers) and one for the wider ones and
- *             the sources, the cycle captured in a HIP graph.  The batched
- *             form, and the plain form of large designs.
+ *             layer one launch for the operations whose values fit 64 bits
+ *             (one per operand count in large layers) and one for the rest
+ *             (wider values, the types DIV .. SEXT, the sources), the cycle
+ *             captured in a HIP graph.  The batched form, and the plain form
+ *             of large designs.
  *   AUTO:     the autotuner's choice for (design, n_instances) when
  *             rteaal_autotune has run for them, else RESIDENT below 32
  *             instances and SWEEP from 32 on. */
@@ -405,8 +406,8 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id design, uint32_t
  * directly rather than through the captured graph.  Two kernels are counted
  * apart: [0] the main kernel (RESIDENT: one launch per chunk of cycles;
  * SWEEP: the kernel of a layer's common operations, values of at most 64
- * bits) and [1] the SWEEP kernel of a layer's heavy operations (wider values
- * and sources; always 0 for RESIDENT).  Each call waits for the stream,
+ * bits) and [1] the SWEEP kernel of a layer's heavy operations (wider values,
+ * the types DIV .. SEXT and sources; always 0 for RESIDENT).  Each call waits for the stream,
  * writes launches[0..1] / total_ms[0..1] (host arrays of two; either pointer
  * may be NULL) with the launches and summed kernel time recorded since the
  * previous call, clears them, and then turns recording on (enable != 0) or

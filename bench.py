@@ -491,7 +491,7 @@ def main():
                     help="offered load as a fraction of the calibrated saturated job rate")
     ap.add_argument("--cycles-per-step", type=int, default=None)
     ap.add_argument("--instances", type=int, default=None)
-    ap.add_argument("--mapping", default="auto", choices=["auto", "resident", "sweep"])
+    ap.add_argument("--mapping", default="auto", choices=["auto", "resident", "sweep", "layered"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--ops-per-wave", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)
@@ -548,7 +548,7 @@ def main():
     cps = args.cycles_per_step or wl["cycles_per_step"]
     steps = args.steps if args.steps is not None else wl["steps"]
     mapping = {"auto": R.RTEAAL_MAP_AUTO, "resident": R.RTEAAL_MAP_RESIDENT,
-               "sweep": R.RTEAAL_MAP_SWEEP}[args.mapping]
+               "sweep": R.RTEAAL_MAP_SWEEP, "layered": R.RTEAAL_MAP_LAYERED}[args.mapping]
 
     t0 = time.perf_counter()
     d = rtlgen.generate(wl["cfg"], wl["seed"])
@@ -621,7 +621,7 @@ def main():
                if used_map == R.RTEAAL_MAP_SWEEP else None)
     roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": round(peak, 1),
                 "unit": "GB/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": "k_sweep" if used_map == R.RTEAAL_MAP_SWEEP else "k_resident",
+                "kernel": {R.RTEAAL_MAP_SWEEP: "k_sweep", R.RTEAAL_MAP_LAYERED: "k_layer"}.get(used_map, "k_resident"),
                 "launches": launches, "avg_launch_ms": round(avg_ms, 5),
                 "bytes_per_launch": round(per_launch, 1),
                 "algorithmic_bytes_per_instance_cycle": round(X, 1),
@@ -691,7 +691,8 @@ def main():
         "config": {"workload": args.workload, "ops": d.n_ops, "layers": d.n_layers,
                    "registers": d.n_regs, "inputs": d.n_inputs, "instances": n_inst,
                    "cycles_per_step": cps,
-                   "mapping": "sweep" if used_map == R.RTEAAL_MAP_SWEEP else "resident",
+                   "mapping": {R.RTEAAL_MAP_SWEEP: "sweep", R.RTEAAL_MAP_LAYERED: "layered"}.get(
+                       used_map, "resident"),
                    "opts": bopts,
                    "design_fingerprint": d.fingerprint()},
         "plain": plain,

@@ -230,19 +230,26 @@ rteaal_status rteaal_design_format(rteaal_ctx* ctx, rteaal_design_id design, uin
  *             (wider values, the types DIV .. SEXT, the sources), the cycle
  *             captured in a HIP graph.  The batched form, and the plain form
  *             of large designs.
+ *   LAYERED:  one lane per operation as in RESIDENT, but each layer is one
+ *             launch over the whole device (blocks of block_threads x unroll
+ *             operations, times the instances), the state in HBM, the cycle
+ *             captured in a HIP graph.  The plain form of large designs (a single instance's
+ *             layer spread over every compute unit); at most 65535
+ *             instances.
  *   AUTO:     the autotuner's choice for (design, n_instances) when
  *             rteaal_autotune has run for them, else RESIDENT below 32
  *             instances and SWEEP from 32 on. */
-enum { RTEAAL_MAP_AUTO = 0, RTEAAL_MAP_RESIDENT = 1, RTEAAL_MAP_SWEEP = 2 };
+enum { RTEAAL_MAP_AUTO = 0, RTEAAL_MAP_RESIDENT = 1, RTEAAL_MAP_SWEEP = 2, RTEAAL_MAP_LAYERED = 3 };
 
 typedef struct {
   uint32_t mapping;        /* RTEAAL_MAP_*                                      */
-  uint32_t block_threads;  /* 0 = default; RESIDENT: 64..1024, multiple of 64   */
+  uint32_t block_threads;  /* 0 = default; RESIDENT: 64..1024, multiple of 64;
+                              LAYERED: 64..256, multiple of 64 (default 64)     */
   uint32_t ops_per_wave;   /* 0 = default; SWEEP: operations per wavefront      */
   uint32_t lds_state;      /* RESIDENT: 0 = LDS when it fits, 1 = keep in HBM   */
   uint32_t lds_ops;        /* RESIDENT: 0 = records in LDS when they fit, 1 = no */
   uint32_t unroll;         /* 0 = default; operations in flight per lane or
-                              wavefront: 1, 2 or 4                              */
+                              wavefront: 1, 2 or 4 (RESIDENT, LAYERED, SWEEP)   */
   uint32_t tiles_per_wave; /* 0 = default; SWEEP: 64-instance tiles one
                               wavefront evaluates per decoded operation: 1, 2,
                               4 or 8, with unroll x tiles_per_wave <= 8        */

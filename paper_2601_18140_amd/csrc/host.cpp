@@ -695,6 +695,7 @@ uint32_t sweep_tg(const rteaal_batch_opts* o) { return o && o->tiles_per_wave ? 
 uint32_t choose_mapping(const DesignHost& h, uint32_t n_inst, const rteaal_batch_opts* o) {
   if (o && o->mapping == RTEAAL_MAP_RESIDENT) return RTEAAL_MAP_RESIDENT;
   if (o && o->mapping == RTEAAL_MAP_SWEEP) return RTEAAL_MAP_SWEEP;
+  if (o && o->mapping == RTEAAL_MAP_LAYERED) return RTEAAL_MAP_LAYERED;
   (void)h;
   return n_inst < 32 ? RTEAAL_MAP_RESIDENT : RTEAAL_MAP_SWEEP;
 }
@@ -774,6 +775,45 @@ std::vector<TilePass> tile_passes(const Batch& b) {
   return out;
 }
 
+// LAYERED: one launch per (non-empty) layer for all instances, then the
+// cycle advance and the capture; the cycle is captured once as a HIP graph.
+rteaal_status enqueue_layered(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t n_cycles) {
+  const ResJob J = res_job(h, b, 1);
+  DevCtl* ctl = (DevCtl*)b.ctl.p;
+  auto cycle = [&](hipStream_t s, bool timed_launches) -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (uint32_t li = 0; li < h.layers.size() && e == hipSuccess; ++li) {
+      const uint32_t n = h.layers[li].end - h.layers[li].begin;
+      if (!n) continue;
+      auto go = [&] { return launch_layer(J, li, n, b.n_inst, b.block, b.unroll, s); };
+      e = timed_launches ? timed(b, s, 0, go) : go();
+    }
+    if (e == hipSuccess) e = launch_advance(ctl, 1, s);
+    if (e == hipSuccess) e = capture(b, s);
+    return e;
+  };
+  if (b.profile) {
+    for (uint64_t c = 0; c < n_cycles; ++c) HIP_TRY(ctx, cycle(ctx->stream, true));
+    return RTEAAL_OK;
+  }
+  if (!b.graph) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = cycle(ctx->stream, false);
+    hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
+    if (e == hipSuccess && e2 == hipSuccess) e = hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      b.graph = nullptr;
+      ctx->poisoned = true;
+      return fail(ctx, RTEAAL_E_DEVICE, "graph capture failed: %s",
+                  hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+  }
+  for (uint64_t c = 0; c < n_cycles; ++c) HIP_TRY(ctx, hipGraphLaunch(b.graph, ctx->stream));
+  return RTEAAL_OK;
+}
+
 rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t n_cycles) {
   const Program p = program_of(h);
   DevCtl* ctl = (DevCtl*)b.ctl.p;
@@ -793,6 +833,7 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
     }
     return RTEAAL_OK;
   }
+  if (b.mapping == RTEAAL_MAP_LAYERED) return enqueue_layered(ctx, h, b, n_cycles);
   // SWEEP: per layer the common kernel and the heavy one, the cycle captured
   // once as a HIP graph.
   char* st = (char*)b.state.p;
@@ -1153,6 +1194,8 @@ rteaal_status rteaal_batch_footprint(rteaal_ctx* ctx, rteaal_design_id id, uint3
   if (!ctx || !bytes || n_inst == 0) return fail(ctx, RTEAAL_E_INVALID_ARG, "bad argument");
   DesignHost* h = find_design(ctx, id);
   if (!h) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown design %u", id);
+  if (opts && opts->mapping > RTEAAL_MAP_LAYERED)
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown mapping %u", opts->mapping);
   opts = resolve_opts(ctx, id, n_inst, opts);
   const uint32_t m = choose_mapping(*h, n_inst, opts);
   uint64_t sb = 0;
@@ -1171,6 +1214,8 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
   if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
   DesignHost* h = find_design(ctx, id);
   if (!h) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown design %u", id);
+  if (opts && opts->mapping > RTEAAL_MAP_LAYERED)
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown mapping %u", opts->mapping);
   opts = resolve_opts(ctx, id, n_inst, opts);
   auto b = std::make_unique<Batch>();
   b->design = id;
@@ -1198,6 +1243,17 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
     if (u != 1 && u != 2 && u != 4)
       return fail(ctx, RTEAAL_E_INVALID_ARG, "RESIDENT unroll must be 1, 2 or 4");
     b->unroll = u;
+  } else if (b->mapping == RTEAAL_MAP_LAYERED) {
+    if (n_inst > 65535)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "LAYERED batches hold at most 65535 instances");
+    const uint32_t u = opts && opts->unroll ? opts->unroll : 1u;
+    if (u != 1 && u != 2 && u != 4)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "LAYERED unroll must be 1, 2 or 4");
+    b->unroll = u;
+    const uint32_t blk = opts && opts->block_threads ? opts->block_threads : 64u;
+    if (blk % 64 || blk > 256)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "LAYERED block_threads must be 64, 128, 192 or 256");
+    b->block = blk;
   } else {
     b->opw = opts && opts->ops_per_wave ? opts->ops_per_wave : 16;
     const uint32_t u = opts && opts->unroll ? opts->unroll : 2u;
@@ -1281,7 +1337,9 @@ rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id id, rteaal_b
     o.block_threads = b->block;
     o.lds_state = b->lds ? 0u : 1u;
     o.lds_ops = b->lds_ops ? 0u : 1u;
-  } else {
+  } else if (b->mapping == RTEAAL_MAP_LAYERED) {
+    o.block_threads = b->block;
+  } else if (b->mapping == RTEAAL_MAP_SWEEP) {
     o.ops_per_wave = b->opw;
     o.tiles_per_wave = b->tg;
     o.arity_split = b->arity_split;
@@ -1345,12 +1403,12 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
   }
   for (uint32_t k = 0; k < n; ++k) HIP_TRY(ctx, launch_set_words((DevCtl*)bs[k]->ctl.p, nullptr, ctx->stream));
 
-  // SWEEP batches: each on an auxiliary stream, forked from and joined back
-  // into the context stream, so their layer kernels overlap.
+  // SWEEP and LAYERED batches: each on an auxiliary stream, forked from and
+  // joined back into the context stream, so their layer kernels overlap.
   uint32_t n_aux = 0;
   for (uint32_t k = 0; k < n; ++k) {
     Batch& b = *bs[k];
-    if (b.mapping != RTEAAL_MAP_SWEEP || n_cycles[k] == 0) continue;
+    if (b.mapping == RTEAAL_MAP_RESIDENT || n_cycles[k] == 0) continue;
     const uint32_t a = n_aux % 4;
     if (!ctx->aux[a]) {
       HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->aux[a], hipStreamNonBlocking));
@@ -1622,6 +1680,10 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
     for (uint32_t u : {1u, 2u, 4u})
       cand.push_back(rteaal_batch_opts{RTEAAL_MAP_RESIDENT, blk, 0, 0, 0, u, 0});
   }
+  if (n_inst <= 16)
+    for (uint32_t blk : {64u, 128u, 256u})
+      for (uint32_t u : {1u, 2u})
+        cand.push_back(rteaal_batch_opts{RTEAAL_MAP_LAYERED, blk, 0, 0, 0, u, 0});
   const uint32_t n_tiles = (n_inst + 63) / 64;
   for (uint32_t tg : {1u, 2u, 4u, 8u}) {
     if (tg > 1 && tg > n_tiles) continue;

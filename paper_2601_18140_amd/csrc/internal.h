@@ -182,6 +182,10 @@ hipError_t launch_sweep_heavy(const Program& p, const StateLayout& L, char* stat
                               const uint64_t* seeds, const DevCtl* ctl, uint32_t n_inst,
                               uint32_t layer, const DevLayer& ly, uint32_t ops_per_wave,
                               uint32_t tiles_per_wave, TilePass tp, hipStream_t s);
+// LAYERED: layer li (n_layer_ops >= 1 operations) of n_inst instances,
+// blocks of `block` threads (64, 128, 192 or 256).
+hipError_t launch_layer(const ResJob& J, uint32_t li, uint32_t n_layer_ops, uint32_t n_inst,
+                        uint32_t block, uint32_t unroll, hipStream_t s);
 hipError_t launch_advance(DevCtl* ctl, uint64_t n, hipStream_t s);
 hipError_t launch_set_words(DevCtl* ctl, const uint64_t* words, hipStream_t s);
 hipError_t launch_pack(bool sweep, const StateLayout& L, const char* state, const SlotRef* refs,

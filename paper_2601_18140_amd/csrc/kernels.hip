@@ -110,6 +110,88 @@ __device__ __forceinline__ void res_stv(char* s, uint32_t cls, uint32_t f, const
 //            LDS as well, so no global load remains in the cycle loop.
 // U:         positions per thread handled together (records, then operands,
 //            then evaluation), so U gathers are in flight per lane.
+// The operations at positions q0 + u * stride (u < U) of layer ly for one
+// instance whose state rows are at s: U records, then their operands, then
+// evaluation and stores.  A position past the layer holds no operation; the
+// positions of a wavefront are 64 consecutive ones, so 1-bit results leave
+// as one ballot word per wavefront.
+template <int U>
+__device__ __forceinline__ void resident_ops(const ResJob& J, char* s, const DevOp* ops,
+                                             const DevLayer& ly, uint32_t q0, uint32_t stride,
+                                             uint32_t n, uint32_t n64, uint64_t seed,
+                                             uint64_t cycle, const uint64_t* words,
+                                             uint64_t words_row, uint32_t lane) {
+  DevOp op[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) op[u] = ops[ly.begin + min(q0 + u * stride, n - 1u)];
+  uint64_t va[U], vb[U], vc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t q = q0 + u * stride, code = op[u].code, ar = op_arity(code);
+    (void)q;
+    (void)ar;
+    va[u] = res_fetch(s, op_scls(code, 0), op[u].src[0]);
+    vb[u] = res_fetch(s, op_scls(code, 1), op[u].src[1]);
+    vc[u] = res_fetch(s, op_scls(code, 2), op[u].src[2]);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t q = q0 + u * stride;
+    if (q < n64) {  // the same for every lane of a wavefront
+      uint64_t bit = 0;
+      bool bdst = false;
+      if (q < n) {
+        const DevOp& o = op[u];
+        const uint32_t code = o.code, opc = op_opc(code), ar = op_arity(code);
+        const uint32_t dc = op_dcls(code), w = op_width(o.wimm), imm = op_imm(o.wimm);
+        if (opc >= OP_STIM) {
+          const V4 x = source_value(J.const_limbs, o, seed, cycle, words, words_row, w);
+          if (dc == CB) {
+            bdst = true;
+            bit = x.l[0] & 1ull;
+          } else {
+            res_stv(s, dc, o.dst, x);
+          }
+        } else if (op_kind(code) == K_U32 || op_kind(code) == K_BIT) {
+          const uint32_t r = eval_u32(opc, ar, (uint32_t)va[u], (uint32_t)vb[u],
+                                      (uint32_t)vc[u], imm, w);
+          if (dc == CB) {
+            bdst = true;
+            bit = r & 1u;
+          } else {
+            res_st64(s, dc, o.dst, r);
+          }
+        } else if (op_kind(code) != K_WIDE) {
+          const uint64_t r = eval_u64(opc, ar, va[u], vb[u], vc[u], imm, w);
+          if (dc == CB) {
+            bdst = true;
+            bit = r & 1ull;
+          } else {
+            res_st64(s, dc, o.dst, r);
+          }
+        } else {
+          const V4 a = res_ldv(s, op_scls(code, 0), o.src[0]);
+          const V4 b = ar > 1 ? res_ldv(s, op_scls(code, 1), o.src[1]) : v4_from(0);
+          const V4 c = ar > 2 ? res_ldv(s, op_scls(code, 2), o.src[2]) : v4_from(0);
+          const V4 r = eval_wide(opc, ar, a, b, c, imm, w);
+          if (dc == CB) {
+            bdst = true;
+            bit = r.l[0] & 1ull;
+          } else {
+            res_stv(s, dc, o.dst, r);
+          }
+        }
+      }
+      // 1-bit outputs: the wavefront's 64 consecutive operations own one
+      // row, named by the first one's destination field (1-bit
+      // destinations lead the layer, so lane 0 holds one when any does).
+      const uint64_t m = __ballot(bit != 0ull);
+      const uint64_t any = __ballot(bdst);
+      if (any != 0ull && lane == 0) *(uint64_t*)(s + (uint64_t)(op[u].dst >> 6) * 8u) = m;
+    }
+  }
+}
+
 template <bool LDS_STATE, bool LDS_OPS, int U>
 __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uint4* lds_dyn) {
   const StateLayout& L = J.L;
@@ -148,77 +230,8 @@ __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uin
       const DevLayer ly = layers[li];
       const uint32_t n = ly.end - ly.begin;
       const uint32_t n64 = (n + 63u) & ~63u;
-      for (uint32_t q0 = threadIdx.x; q0 < n64; q0 += U * bd) {
-        DevOp op[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) op[u] = ops[ly.begin + min(q0 + u * bd, n - 1u)];
-        uint64_t va[U], vb[U], vc[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const uint32_t q = q0 + u * bd, code = op[u].code, ar = op_arity(code);
-          (void)q;
-          (void)ar;
-          va[u] = res_fetch(s, op_scls(code, 0), op[u].src[0]);
-          vb[u] = res_fetch(s, op_scls(code, 1), op[u].src[1]);
-          vc[u] = res_fetch(s, op_scls(code, 2), op[u].src[2]);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const uint32_t q = q0 + u * bd;
-          if (q < n64) {  // the same for every lane of a wavefront
-            uint64_t bit = 0;
-            bool bdst = false;
-            if (q < n) {
-              const DevOp& o = op[u];
-              const uint32_t code = o.code, opc = op_opc(code), ar = op_arity(code);
-              const uint32_t dc = op_dcls(code), w = op_width(o.wimm), imm = op_imm(o.wimm);
-              if (opc >= OP_STIM) {
-                const V4 x = source_value(J.const_limbs, o, seed, cycle, words, words_row, w);
-                if (dc == CB) {
-                  bdst = true;
-                  bit = x.l[0] & 1ull;
-                } else {
-                  res_stv(s, dc, o.dst, x);
-                }
-              } else if (op_kind(code) == K_U32 || op_kind(code) == K_BIT) {
-                const uint32_t r = eval_u32(opc, ar, (uint32_t)va[u], (uint32_t)vb[u],
-                                            (uint32_t)vc[u], imm, w);
-                if (dc == CB) {
-                  bdst = true;
-                  bit = r & 1u;
-                } else {
-                  res_st64(s, dc, o.dst, r);
-                }
-              } else if (op_kind(code) != K_WIDE) {
-                const uint64_t r = eval_u64(opc, ar, va[u], vb[u], vc[u], imm, w);
-                if (dc == CB) {
-                  bdst = true;
-                  bit = r & 1ull;
-                } else {
-                  res_st64(s, dc, o.dst, r);
-                }
-              } else {
-                const V4 a = res_ldv(s, op_scls(code, 0), o.src[0]);
-                const V4 b = ar > 1 ? res_ldv(s, op_scls(code, 1), o.src[1]) : v4_from(0);
-                const V4 c = ar > 2 ? res_ldv(s, op_scls(code, 2), o.src[2]) : v4_from(0);
-                const V4 r = eval_wide(opc, ar, a, b, c, imm, w);
-                if (dc == CB) {
-                  bdst = true;
-                  bit = r.l[0] & 1ull;
-                } else {
-                  res_stv(s, dc, o.dst, r);
-                }
-              }
-            }
-            // 1-bit outputs: the wavefront's 64 consecutive operations own one
-            // row, named by the first one's destination field (1-bit
-            // destinations lead the layer, so lane 0 holds one when any does).
-            const uint64_t m = __ballot(bit != 0ull);
-            const uint64_t any = __ballot(bdst);
-            if (any != 0ull && lane == 0) *(uint64_t*)(s + (uint64_t)(op[u].dst >> 6) * 8u) = m;
-          }
-        }
-      }
+      for (uint32_t q0 = threadIdx.x; q0 < n64; q0 += U * bd)
+        resident_ops<U>(J, s, ops, ly, q0, bd, n, n64, seed, cycle, words, words_row, lane);
       __syncthreads();
     }
   }
@@ -244,6 +257,23 @@ k_resident_multi(const ResJob* __restrict__ jobs, const uint2* __restrict__ map)
   const uint2 m = map[blockIdx.x];
   const ResJob J = jobs[m.x];
   resident_run<LDS_STATE, LDS_OPS, U>(J, m.y, lds_dyn);
+}
+
+// LAYERED: layer li of every instance, one launch over the whole device.
+// Block (x, y) of B threads takes positions [B U x, B U (x + 1)) of the layer
+// for instance y; the state stays in HBM (RESIDENT layout), and the launch
+// boundary separates the layers.
+template <int U>
+__global__ void __launch_bounds__(256) k_layer(ResJob J, uint32_t li) {
+  const uint32_t inst = blockIdx.y, bd = blockDim.x;
+  const DevLayer ly = J.layers[li];
+  const uint32_t n = ly.end - ly.begin, n64 = (n + 63u) & ~63u;
+  const uint32_t q0 = blockIdx.x * (bd * U) + threadIdx.x;
+  const uint64_t cycle = J.ctl->cycle;
+  const uint64_t words_row =
+      ((cycle - J.ctl->step_cycle0) * (uint64_t)J.n_inst_total + inst) * (uint64_t)J.words_per_inst;
+  resident_ops<U>(J, J.state + (uint64_t)inst * J.L.pitch, J.ops, ly, q0, bd, n, n64,
+                  J.seeds[inst], cycle, J.ctl->words, words_row, threadIdx.x & 63u);
 }
 
 // ---------------------------------------------------------------------------
@@ -960,6 +990,20 @@ hipError_t launch_sweep_heavy(const Program& p, const StateLayout& L, char* stat
   if (tg == 2) RTEAAL_HEAVY(2);
   else RTEAAL_HEAVY(1);
 #undef RTEAAL_HEAVY
+  return hipGetLastError();
+}
+
+hipError_t launch_layer(const ResJob& J, uint32_t li, uint32_t n_layer_ops, uint32_t n_inst,
+                        uint32_t block, uint32_t unroll, hipStream_t s) {
+  if (n_layer_ops == 0 || n_inst == 0 || n_inst > 65535 || block == 0 || block > 256 ||
+      block % 64)
+    return hipErrorInvalidValue;
+  const uint32_t n64 = (n_layer_ops + 63u) & ~63u;
+  const uint32_t u = unroll == 4 ? 4u : unroll == 2 ? 2u : 1u, per = block * u;
+  const dim3 grid((n64 + per - 1) / per, n_inst), blk(block);
+  if (u == 4) hipLaunchKernelGGL(k_layer<4>, grid, blk, 0, s, J, li);
+  else if (u == 2) hipLaunchKernelGGL(k_layer<2>, grid, blk, 0, s, J, li);
+  else hipLaunchKernelGGL(k_layer<1>, grid, blk, 0, s, J, li);
   return hipGetLastError();
 }
 

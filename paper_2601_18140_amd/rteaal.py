@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librteaal.so")
 
 __all__ = [
-    "RTEAAL_OK", "RTEAAL_MAP_AUTO", "RTEAAL_MAP_RESIDENT", "RTEAAL_MAP_SWEEP",
+    "RTEAAL_OK", "RTEAAL_MAP_AUTO", "RTEAAL_MAP_RESIDENT", "RTEAAL_MAP_SWEEP", "RTEAAL_MAP_LAYERED",
     "RTEAAL_READ_REGS", "RTEAAL_READ_ALL_SLOTS", "RteaalError", "Context", "library",
     "exported_symbols", "rteaal_create", "rteaal_destroy", "rteaal_last_error",
     "rteaal_validate_design", "rteaal_load_design", "rteaal_unload_design", "rteaal_design_format",
@@ -33,7 +33,7 @@ __all__ = [
 RTEAAL_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "BAD_DESIGN", 3: "FORMAT", 4: "NO_MEMORY",
                 5: "DEVICE", 6: "BUSY", 7: "UNSUPPORTED"}
-RTEAAL_MAP_AUTO, RTEAAL_MAP_RESIDENT, RTEAAL_MAP_SWEEP = 0, 1, 2
+RTEAAL_MAP_AUTO, RTEAAL_MAP_RESIDENT, RTEAAL_MAP_SWEEP, RTEAAL_MAP_LAYERED = 0, 1, 2, 3
 RTEAAL_READ_REGS, RTEAAL_READ_ALL_SLOTS = 1, 2
 
 

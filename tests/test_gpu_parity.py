@@ -17,8 +17,8 @@ from tests.gpu_util import assert_same, gpu_ctx, run_gpu
 
 pytestmark = pytest.mark.gpu
 
-MAPS = [R.RTEAAL_MAP_RESIDENT, R.RTEAAL_MAP_SWEEP]
-MAP_IDS = ["resident", "sweep"]
+MAPS = [R.RTEAAL_MAP_RESIDENT, R.RTEAAL_MAP_SWEEP, R.RTEAAL_MAP_LAYERED]
+MAP_IDS = ["resident", "sweep", "layered"]
 
 
 def note(msg):
@@ -182,7 +182,8 @@ def test_batch_options_round_trip(ctx):
                       (3, {"mapping": R.RTEAAL_MAP_RESIDENT, "lds_state": 1, "block_threads": 128}),
                       (200, {"mapping": R.RTEAAL_MAP_SWEEP}),
                       (300, {"mapping": R.RTEAAL_MAP_SWEEP, "tiles_per_wave": 2, "unroll": 2,
-                             "ops_per_wave": 3, "arity_split": 2, "tiles_per_pass": 2})]:
+                             "ops_per_wave": 3, "arity_split": 2, "tiles_per_pass": 2}),
+                      (5, {"mapping": R.RTEAAL_MAP_LAYERED, "unroll": 4, "block_threads": 192})]:
             seeds = np.arange(n, dtype=np.uint64)
             b1 = R.rteaal_create_batch(ctx, did, seeds, **kw)
             o1 = R.rteaal_batch_options(ctx, b1)
@@ -193,6 +194,29 @@ def test_batch_options_round_trip(ctx):
             assert o1 == o2, (kw, o1, o2)
             for k, v in kw.items():
                 assert o1[k] == v, (k, o1)
+    finally:
+        R.rteaal_unload_design(ctx, did)
+
+
+def test_layered_plain_form_large_layers(ctx):
+    """LAYERED on single-200k (4k-operation layers, many blocks per launch),
+    one and three instances, steps split, against the oracle; an unknown
+    mapping is rejected."""
+    w = rtlgen.WORKLOADS["single-200k"]
+    d = rtlgen.generate(w["cfg"], w["seed"])
+    for n_inst, u, blk in ((1, 2, 64), (3, 1, 256), (2, 4, 128)):
+        seeds = rtlgen.instance_seeds(n_inst)
+        note(f"layered single-200k n_inst={n_inst} unroll={u} block={blk}")
+        got, _, used = run_gpu(ctx, d, seeds, [3, 4], mapping=R.RTEAAL_MAP_LAYERED, unroll=u,
+                               block_threads=blk)
+        assert used == R.RTEAAL_MAP_LAYERED
+        ref, _, _ = oracle.run(d, seeds, 7)
+        assert_same(got, ref, f"layered x{n_inst}")
+    did = R.rteaal_load_design(ctx, d)
+    try:
+        with pytest.raises(R.RteaalError) as e:
+            R.rteaal_create_batch(ctx, did, [1], mapping=4)
+        assert e.value.status == 1
     finally:
         R.rteaal_unload_design(ctx, did)
 

@@ -20,8 +20,8 @@ from tests.gpu_util import assert_same, gpu_ctx
 
 pytestmark = pytest.mark.gpu
 
-MAPS = [R.RTEAAL_MAP_RESIDENT, R.RTEAAL_MAP_SWEEP]
-MAP_IDS = ["resident", "sweep"]
+MAPS = [R.RTEAAL_MAP_RESIDENT, R.RTEAAL_MAP_SWEEP, R.RTEAAL_MAP_LAYERED]
+MAP_IDS = ["resident", "sweep", "layered"]
 
 
 def note(msg):

@@ -141,7 +141,7 @@ static int is_unary(int n) {
   return n == ORC_NOT || n == ORC_SHL || n == ORC_SHR || n == ORC_EXTRACT || n == ORC_ORR ||
          n == ORC_ANDR || n == ORC_XORR || n == ORC_SEXT;
 }
-static int is_select(int n) { return n == ORC_MUX; }
+static int is_select(int n) { return n == ORC_MUX || n == ORC_MUXC; }
 
 /* x_w: declared width of the operand. */
 static val op_u(int n, val x, int imm, int x_w) {
@@ -200,15 +200,24 @@ static val op_r(int n, val prev, val cur, int cur_w) {
   }
 }
 
+/* Select over the whole O fiber.  The fiber is (selector, value) pairs at
+ * o = 2i, 2i + 1, then a default at o = arity - 1: the first pair whose
+ * selector is nonzero gives its value, and the default is taken when none
+ * is.  MUX is the one-pair case; MUXC, the fused mux chain of the
+ * compiler's operator fusion (section "Design Overview" of the simulator,
+ * and App. B "Implemented Optimizations"), has up to 32 pairs. */
 static val op_s(int n, const val* sel, int arity) {
-  (void)n; (void)arity;
-  return v_is_zero(&sel[0]) ? sel[2] : sel[1];   /* o=0 nonzero picks o=1 */
+  (void)n;
+  for (int o = 0; o + 1 < arity; o += 2)
+    if (!v_is_zero(&sel[o])) return sel[o + 1];
+  return sel[arity - 1];
 }
 
 static int arity_ok(int n, int a) {
   switch (n) {
     case ORC_AND: case ORC_OR: case ORC_XOR: return a == 2 || a == 3;
     case ORC_MUX: return a == 3;
+    case ORC_MUXC: return a >= 3 && a <= ORACLE_MAX_ARITY && a % 2 == 1;
     case ORC_ADD: case ORC_SUB: case ORC_MUL: case ORC_EQ: case ORC_LT: case ORC_CONCAT:
     case ORC_DIV: case ORC_REM: case ORC_DSHL: case ORC_DSHR:
       return a == 2;
@@ -231,7 +240,7 @@ int oracle_eval_op(int type, int arity, const uint64_t* operands, const uint16_t
                    int dst_w, int imm, uint64_t* out) {
   if (type < 0 || type >= ORC_NTYPES || !arity_ok(type, arity)) return -1;
   if (dst_w < 1 || dst_w > 256) return -1;
-  val oi[3];
+  val oi[ORACLE_MAX_ARITY];
   for (int o = 0; o < arity; o++) memcpy(oi[o].l, operands + 4 * o, sizeof(val));
   val r = v_mask(eval_one(type, arity, oi, src_w, imm), dst_w);
   memcpy(out, r.l, sizeof(val));
@@ -306,7 +315,7 @@ static void run_instance(const job* jb, uint32_t inst, val* LI, val* LO, val* nx
         int n = d->op_type[s];
         uint32_t p0 = d->op_src_ptr[s];
         int arity = (int)(d->op_src_ptr[s + 1] - p0);
-        val oi[3]; uint16_t oi_w[3];
+        val oi[ORACLE_MAX_ARITY]; uint16_t oi_w[ORACLE_MAX_ARITY];
         for (int o = 0; o < arity; o++) {
           uint32_t r = d->op_src[p0 + o];
           oi[o] = LI[r];

@@ -29,8 +29,12 @@ extern "C" {
 enum {
   ORC_AND = 0, ORC_OR, ORC_XOR, ORC_NOT, ORC_ADD, ORC_SUB, ORC_MUL, ORC_MUX,
   ORC_EQ, ORC_LT, ORC_SHL, ORC_SHR, ORC_EXTRACT, ORC_CONCAT, ORC_ORR,
-  ORC_DIV, ORC_REM, ORC_DSHL, ORC_DSHR, ORC_ANDR, ORC_XORR, ORC_SEXT, ORC_NTYPES
+  ORC_DIV, ORC_REM, ORC_DSHL, ORC_DSHR, ORC_ANDR, ORC_XORR, ORC_SEXT, ORC_MUXC, ORC_NTYPES
 };
+
+/* Longest O fiber of one operation: a mux chain of 32 (selector, value)
+ * pairs and its default. */
+#define ORACLE_MAX_ARITY 65
 
 typedef struct {
   uint32_t n_slots;   const uint16_t* slot_width;

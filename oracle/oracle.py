@@ -149,7 +149,7 @@ def eval_op(typ, operands, src_widths, dst_w, imm=0) -> int:
     for o, v in enumerate(operands):
         for k in range(4):
             ops[o, k] = (int(v) >> (64 * k)) & ((1 << 64) - 1)
-    sw = np.zeros(3, np.uint16)
+    sw = np.zeros(max(ar, 3), np.uint16)
     sw[:ar] = src_widths
     out = np.zeros(4, np.uint64)
     rc = lib.oracle_eval_op(int(typ), ar, ops.ctypes.data, sw.ctypes.data, int(dst_w), int(imm),

@@ -25,11 +25,14 @@ import numpy as np
 # Operation-type coordinates (rank N).  The numeric values are part of the
 # C interface of both the library and the oracle.
 (AND, OR, XOR, NOT, ADD, SUB, MUL, MUX, EQ, LT, SHL, SHR, EXTRACT, CONCAT, ORR,
- DIV, REM, DSHL, DSHR, ANDR, XORR, SEXT) = range(22)
-OP_COUNT = 22
+ DIV, REM, DSHL, DSHR, ANDR, XORR, SEXT, MUXC) = range(23)
+OP_COUNT = 23
 OP_NAMES = ["and", "or", "xor", "not", "add", "sub", "mul", "mux", "eq", "lt",
             "shl", "shr", "extract", "concat", "orr",
-            "div", "rem", "dshl", "dshr", "andr", "xorr", "sext"]
+            "div", "rem", "dshl", "dshr", "andr", "xorr", "sext", "muxc"]
+
+# MUXC is a fused mux chain: (selector, value) pairs, then a default.
+MUXC_MAX_PAIRS = 32
 
 # Allowed occupancies of the O fiber for each type.
 OP_ARITIES = {
@@ -37,6 +40,7 @@ OP_ARITIES = {
     MUL: (2,), MUX: (3,), EQ: (2,), LT: (2,), SHL: (1,), SHR: (1,),
     EXTRACT: (1,), CONCAT: (2,), ORR: (1,),
     DIV: (2,), REM: (2,), DSHL: (2,), DSHR: (2,), ANDR: (1,), XORR: (1,), SEXT: (1,),
+    MUXC: tuple(range(3, 2 * MUXC_MAX_PAIRS + 2, 2)),
 }
 
 MAX_WIDTH = 256

@@ -50,6 +50,10 @@ class GenConfig:
     widths: tuple = WIDTHS_STD
     name: str = "design"
     op_mix: tuple = OP_MIX
+    # Probability that a MUX of layer i >= 1 takes as its default operand
+    # (o = 2) a MUX of layer i - 1 that nothing else reads: priority chains
+    # (when / elsewhen / otherwise).  0 leaves the design as drawn.
+    mux_chain: float = 0.0
 
 
 def _bucket_draw(rng, buckets, n):
@@ -160,6 +164,8 @@ def generate(cfg: GenConfig, seed: int) -> Design:
     tail = layer_ptr[L - int(math.ceil(L / 4))]
     reg_slot = base_reg + np.arange(n_reg, dtype=np.int64)
     reg_next = base_op + tail + (rng.random(n_reg) * (n_ops - tail)).astype(np.int64)
+    if cfg.mux_chain > 0:
+        _chain_muxes(rng, cfg.mux_chain, op_type, layer_ptr, src_ptr, op_src, reg_next, width, base_op)
 
     return Design(
         name=cfg.name, slot_width=width, const_slot=np.zeros(0, np.uint32),
@@ -168,6 +174,59 @@ def generate(cfg: GenConfig, seed: int) -> Design:
         op_dst=base_op + np.arange(n_ops), op_src_ptr=src_ptr, op_src=op_src, op_imm=op_imm,
         meta={"generator": dataclasses.asdict(cfg), "seed": int(seed)},
     )
+
+
+def _chain_muxes(rng, p, op_type, layer_ptr, src_ptr, op_src, reg_next, width, base_op):
+    """Links MUXes into priority chains, in place.
+
+    From the last layer down, each MUX of layer i takes, with probability p,
+    a MUX of layer i - 1 (each taken once) as its default operand; the inner
+    MUX's width is raised to the outer's (skipped for 10 % of the links).
+    Other reads of an inner MUX, and registers latching one, then move to a
+    random untaken operation of the same layer (kept for 4 % of them).  The skipped and kept cases are links that a fusion pass
+    must leave alone.
+    """
+    L = layer_ptr.size - 1
+    n = op_type.size
+    taken_by = np.full(n, -1, np.int64)
+    for i in range(L - 1, 0, -1):
+        outer = np.nonzero(op_type[layer_ptr[i]:layer_ptr[i + 1]] == MUX)[0] + layer_ptr[i]
+        inner = np.nonzero(op_type[layer_ptr[i - 1]:layer_ptr[i]] == MUX)[0] + layer_ptr[i - 1]
+        outer = outer[rng.random(outer.size) < p]
+        k = min(outer.size, inner.size)
+        if k == 0:
+            continue
+        outer = outer[:k]
+        inner = rng.permutation(inner)[:k]
+        op_src[src_ptr[outer] + 2] = base_op + inner
+        taken_by[inner] = outer
+        widen = rng.random(k) >= 0.10
+        wi, wo = width[base_op + inner], width[base_op + outer]
+        width[base_op + inner[widen]] = np.maximum(wi[widen], wo[widen])
+    layer_of = np.repeat(np.arange(L), np.diff(layer_ptr))
+    free = [np.nonzero(taken_by[layer_ptr[i]:layer_ptr[i + 1]] < 0)[0] + layer_ptr[i] for i in range(L)]
+
+    def move(slots):
+        ops = slots - base_op
+        out = slots.copy()
+        for i in np.unique(layer_of[ops]):
+            sel = layer_of[ops] == i
+            if free[i].size == 0:
+                continue
+            out[sel] = base_op + free[i][(rng.random(int(sel.sum())) * free[i].size).astype(np.int64)]
+        return out
+
+    entry_op = np.repeat(np.arange(n), np.diff(src_ptr))
+    rd = op_src - base_op
+    is_op = rd >= 0
+    hit = np.zeros(op_src.size, bool)
+    hit[is_op] = taken_by[rd[is_op]] >= 0
+    own = hit & (taken_by[np.where(is_op, rd, 0)] == entry_op) & (np.arange(op_src.size) == src_ptr[entry_op] + 2)
+    redo = hit & ~own & (rng.random(op_src.size) >= 0.04)
+    op_src[redo] = move(op_src[redo])
+    rn = reg_next - base_op
+    redo = (taken_by[rn] >= 0) & (rng.random(rn.size) >= 0.04)
+    reg_next[redo] = move(reg_next[redo])
 
 
 # ---------------------------------------------------------------------------

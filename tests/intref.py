@@ -4,8 +4,8 @@
 is an independent, deliberately naive interpreter of a whole design built
 on it (used only to cross-check the C oracle on tiny designs).
 """
-from rtlgen.design import (ADD, AND, ANDR, CONCAT, DIV, DSHL, DSHR, EQ, EXTRACT, LT, MUL, MUX, NOT,
-                           OR, ORR, REM, SEXT, SHL, SHR, SUB, XOR, XORR)
+from rtlgen.design import (ADD, AND, ANDR, CONCAT, DIV, DSHL, DSHR, EQ, EXTRACT, LT, MUL, MUX, MUXC,
+                           NOT, OR, ORR, REM, SEXT, SHL, SHR, SUB, XOR, XORR)
 
 M64 = (1 << 64) - 1
 
@@ -35,6 +35,11 @@ def textbook(typ, vals, widths, wd, imm):
         r = a * vals[1]
     elif typ == MUX:
         r = vals[1] if a != 0 else vals[2]
+    elif typ == MUXC:                 # first pair with a nonzero selector, else the last operand
+        r = vals[-1]
+        for k in range(len(vals) // 2 - 1, -1, -1):
+            if vals[2 * k]:
+                r = vals[2 * k + 1]
     elif typ == EQ:
         r = int(a == vals[1])
     elif typ == LT:

@@ -77,7 +77,9 @@ def algorithmic_bytes(d, bytes_of=wb):
         idx = ptr[:-1][has]
         op_x[has] += np.add.reduceat(src_b, idx)
         op_wmax[has] = np.maximum(op_wmax[has], np.maximum.reduceat(src_w, idx))
-    op_heavy = op_wmax > 64
+    # wide values, and the types the encoder always runs in the wide form
+    # (the FIRRTL primitives DIV .. SEXT and fused mux chains)
+    op_heavy = (op_wmax > 64) | ((d.op_type >= rtlgen.DIV) & (d.op_type <= rtlgen.MUXC))
     op_g = np.zeros(n, dtype=np.float64)
     for i in range(d.n_layers):
         a, b = int(d.layer_ptr[i]), int(d.layer_ptr[i + 1])
@@ -401,6 +403,119 @@ def bench_waveform(args, R, torch):
     }
 
 
+def bench_muxchain(args, R, torch):
+    """Mux-chain fusion on muxchain-2m (2,000,000 operations, 35 % MUX with
+    80 % of them in priority chains, 4,096 instances): the batched rate of the
+    design as drawn against the same design after rteaal_fuse_mux_chains and
+    rteaal_levelize, each in its autotuned shape, with the fused batch's
+    parity sample taken against the oracle run of the unfused design."""
+    import oracle
+    cfg = rtlgen.CFG_MUXCHAIN
+    n_inst = args.instances or 4096
+    cps = args.cycles_per_step or 20
+    steps = args.steps if args.steps is not None else 10
+    t0 = time.perf_counter()
+    d = rtlgen.generate(cfg, 6)
+    print(f"[bench] design {d.summary()} generated in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    seeds = rtlgen.instance_seeds(n_inst)
+    ctx = R.rteaal_create(0)
+    stream = ctx.stream
+    t0 = time.perf_counter()
+    f, cnt = R.rteaal_fuse_mux_chains(d)
+    t_fuse = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    lv = R.levelized_design(ctx, f)
+    t_lev = time.perf_counter() - t0
+    print(f"[bench] fused in {t_fuse:.2f}s: {cnt}; levelized in {t_lev:.2f}s: "
+          f"{d.n_layers} -> {lv.n_layers} layers", file=sys.stderr, flush=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for label, des in (("unfused", d), ("fused", lv)):
+        did = R.rteaal_load_design(ctx, des)
+        opts = {}
+        if not args.no_autotune:
+            opts, trate = R.rteaal_autotune(ctx, did, n_inst)
+            print(f"[bench] autotune {label}: {opts} -> {trate:.4g}", file=sys.stderr, flush=True)
+        bid = R.rteaal_create_batch(ctx, did, seeds, **opts)
+        bopts = R.rteaal_batch_options(ctx, bid)
+        # the fused batch is checked against the oracle of the design as drawn
+        pick = [0, n_inst // 2, n_inst - 1]
+        R.rteaal_step(ctx, bid, 3)
+        got = np.concatenate([R.rteaal_read_state(ctx, bid, first=k, n=1) for k in pick])
+        ref, _, _ = oracle.run(d, seeds[pick], 3, n_threads=3)
+        ok = bool(np.array_equal(R.unpack_limbs(got, d.slot_width[d.reg_slot]), ref))
+        print(f"[bench] {label} parity sample vs oracle of the unfused design: {ok}",
+              file=sys.stderr, flush=True)
+        for _ in range(args.warmup):
+            R.rteaal_step(ctx, bid, cps)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(steps):
+            R.rteaal_step(ctx, bid, cps)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        rate = n_inst * cps * steps / (ms / 1e3)
+        pc = min(cps, 50)
+        R.rteaal_kernel_timing(ctx, bid, True)
+        R.rteaal_step(ctx, bid, pc)
+        (lau, kms), (hl, hkms) = R.rteaal_kernel_timing(ctx, bid, False)
+        R.rteaal_free_batch(ctx, bid)
+        R.rteaal_unload_design(ctx, did)
+        AB = algorithmic_bytes(des)
+        per_cycle = AB["x"] * n_inst + AB["g"]
+        res[label] = {"value": rate, "ms": ms, "ok": ok, "opts": bopts, "layers": des.n_layers,
+                      "ops": des.n_ops, "x": AB["x"], "g": AB["g"],
+                      "kernel_ms_per_cycle": (kms + hkms) / pc, "heavy_share": hkms / max(kms + hkms, 1e-9),
+                      "light": (lau, kms, AB["x_light"] * n_inst + AB["g_light"]),
+                      "heavy": (hl, hkms, AB["x_heavy"] * n_inst + AB["g_heavy"]),
+                      "pc": pc, "per_cycle": per_cycle}
+        print(f"[bench] {label}: {steps} x {cps} cycles x {n_inst} inst in {ms:.1f} ms -> "
+              f"{rate:.4g} instance-cycles/s; {AB['x'] / 1e6:.2f} MB per instance-cycle",
+              file=sys.stderr, flush=True)
+    R.rteaal_destroy(ctx)
+    fz, un = res["fused"], res["unfused"]
+
+    def kern(name, rec, pc):
+        n, kms, b = rec
+        if not n:
+            return None
+        avg = kms / n
+        per = b * pc / n
+        return {"kernel": name, "launches": n, "avg_launch_ms": round(avg, 5),
+                "bytes_per_launch": round(per, 1), "achieved": round(per / (avg / 1e3) / 1e9, 2)}
+
+    light = kern("k_sweep", fz["light"], fz["pc"])
+    heavy = kern("k_sweep_heavy", fz["heavy"], fz["pc"])
+    dom = heavy if fz["heavy_share"] > 0.5 else light
+    roof = dict(dom, bound="hbm", peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(dom["achieved"] / HBM_PEAK_GBS, 4), traffic=None,
+                other_kernel=light if dom is heavy else heavy,
+                algorithmic_bytes_per_instance_cycle=round(fz["x"], 1))
+    return {
+        "metric": METRIC, "value": round(fz["value"], 2), "unit": "instance-cycles/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": round(fz["ms"] / steps, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "muxchain-2m", "ops": d.n_ops, "layers": d.n_layers,
+                   "registers": d.n_regs, "inputs": d.n_inputs, "instances": n_inst,
+                   "cycles_per_step": cps, "fused_opts": fz["opts"], "unfused_opts": un["opts"],
+                   "design_fingerprint": d.fingerprint()},
+        "fusion": dict(cnt, seconds=round(t_fuse, 3), levelize_seconds=round(t_lev, 3),
+                       layers_before=d.n_layers, layers_after=lv.n_layers,
+                       bytes_per_instance_cycle_before=round(un["x"], 1),
+                       bytes_per_instance_cycle_after=round(fz["x"], 1)),
+        "unfused_value": round(un["value"], 2),
+        "fused_over_unfused": round(fz["value"] / un["value"], 3),
+        "kernel_ms_per_cycle": {"unfused": round(un["kernel_ms_per_cycle"], 4),
+                                "fused": round(fz["kernel_ms_per_cycle"], 4)},
+        "parity_sample_ok": fz["ok"] and un["ok"],
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+
+
 def bench_serving(args, R, torch):
     """Poisson stream of jobs over a pool of designs with continuous batching."""
     from paper_2601_18140_amd import serving
@@ -474,7 +589,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large-5m",
-                    choices=sorted(WORKLOADS) + ["multi-64", "serving", "levelize-5m", "waveform"])
+                    choices=sorted(WORKLOADS) + ["multi-64", "serving", "levelize-5m", "waveform",
+                                                 "muxchain-2m"])
     ap.add_argument("--designs", type=int, default=None)
     ap.add_argument("--serving-jobs", type=int, default=200)
     ap.add_argument("--serving-rate", type=float, default=4.0, help="job arrivals per second")
@@ -541,6 +657,9 @@ def main():
         return
     if args.workload == "waveform":
         print(json.dumps(bench_waveform(args, R, torch)), flush=True)
+        return
+    if args.workload == "muxchain-2m":
+        print(json.dumps(bench_muxchain(args, R, torch)), flush=True)
         return
 
     wl = WORKLOADS[args.workload]

@@ -96,13 +96,20 @@ const char* rteaal_last_error(const rteaal_ctx* ctx);
  * the signed forms of add/sub/mul/lt/shr/div/rem run on SEXT-extended
  * operands (lt after flipping both sign bits with XOR).
  * Operand o=0 is reduced first, as the left operand (section "Evaluating
- * Multiple Operation Types"); MUX is the select operator op_s of Appendix A. */
+ * Multiple Operation Types"); MUX is the select operator op_s of Appendix A.
+ * MUXC is the fused mux chain of the compiler's operator fusion (section
+ * "Design Overview" of the simulator; App. B, "Implemented Optimizations"):
+ * an odd number 3 .. 2 RTEAAL_MUXC_MAX_PAIRS + 1 of operands, read as
+ * (selector, value) pairs and a default; the value of the first pair whose
+ * selector is nonzero, else the default (one pair: MUX).  rteaal_fuse_mux_chains
+ * forms them from MUX chains. */
 typedef enum {
   RTEAAL_AND = 0, RTEAAL_OR, RTEAAL_XOR, RTEAAL_NOT, RTEAAL_ADD, RTEAAL_SUB, RTEAAL_MUL,
   RTEAAL_MUX, RTEAAL_EQ, RTEAAL_LT, RTEAAL_SHL, RTEAAL_SHR, RTEAAL_EXTRACT, RTEAAL_CONCAT,
   RTEAAL_ORR, RTEAAL_DIV, RTEAAL_REM, RTEAAL_DSHL, RTEAAL_DSHR, RTEAAL_ANDR, RTEAAL_XORR,
-  RTEAAL_SEXT, RTEAAL_OP_COUNT
+  RTEAAL_SEXT, RTEAAL_MUXC, RTEAAL_OP_COUNT
 } rteaal_op;
+enum { RTEAAL_MUXC_MAX_PAIRS = 32 };
 
 /* Per-rank format (section "Format": uncompressed or compressed, coordinate
  * and payload bit widths). */
@@ -189,6 +196,45 @@ typedef struct {
  * plus 2 per operand entry and 1 per slot) cannot be allocated. */
 rteaal_status rteaal_levelize(rteaal_ctx* ctx, const rteaal_dag_desc* dag, uint32_t* op_layer,
                               uint32_t* order, uint32_t* layer_ptr, uint32_t* n_layers);
+
+/* ------------------------------------------------------------------------ */
+/* Operator fusion                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Counts of one mux-chain fusion. */
+typedef struct {
+  uint32_t n_ops;       /* operations in the fused design                     */
+  uint32_t n_operands;  /* operand entries (op_src_ptr[n_ops])                */
+  uint32_t n_fused;     /* MUXC operations formed                             */
+  uint32_t n_absorbed;  /* MUX operations removed into them                   */
+} rteaal_fuse_result;
+
+/* Mux-chain fusion (operator fusion by mux-chain extraction, among the
+ * compiler's dataflow-graph optimizations in section "Design Overview" of the
+ * simulator; App. B "Implemented Optimizations", operator fusion), host only.
+ * MUX m (s ? v : x) absorbs MUX m' when x is the slot m' writes, that slot
+ * has exactly one operand reader in the design (m), no register latches it,
+ * and its width is at least m's destination width; then no remaining value
+ * changes.  Each path of such links, from its outermost MUX inward, becomes
+ * MUXC operations of at most max_pairs (1 .. RTEAAL_MUXC_MAX_PAIRS) pairs
+ * (s1, v1, ..., sk, vk, default), in the outermost MUX's place (layer and
+ * position); a longer path continues with the MUX its default reads.  The
+ * absorbed MUXes disappear and their slots are no longer written (a later
+ * RTEAAL_READ_ALL_SLOTS reads them as 0).  Slots, registers, inputs and
+ * constants are unchanged, so the fused design is `desc` with the arrays
+ * below in place of its operation arrays; rteaal_levelize may then shorten
+ * it, since a fused operation often reads only earlier layers.
+ * Outputs, host memory allocated by the caller (a fused design never has
+ * more operations or operand entries than its input):
+ *   layer_op_ptr [n_layers + 1]; op_type, op_dst, op_imm [n_ops];
+ *   op_src_ptr [n_ops + 1]; op_src [desc->op_src_ptr[n_ops]].
+ * Errors: RTEAAL_E_INVALID_ARG (null pointer, max_pairs out of range) and
+ * the errors of rteaal_validate_design (the input must pass it); the
+ * outputs are then unspecified. */
+rteaal_status rteaal_fuse_mux_chains(const rteaal_design_desc* desc, uint32_t max_pairs,
+                                     uint32_t* layer_op_ptr, uint8_t* op_type, uint32_t* op_dst,
+                                     uint32_t* op_src_ptr, uint32_t* op_src, uint16_t* op_imm,
+                                     rteaal_fuse_result* result);
 
 /* Validates, encodes (operations grouped per layer by destination width
  * class and type, as in the N-rank swizzle of the NU kernel) and uploads a

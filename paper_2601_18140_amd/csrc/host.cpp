@@ -127,6 +127,7 @@ uint32_t expected_arity_ok(uint32_t t, uint32_t a) {
   switch (t) {
     case RTEAAL_AND: case RTEAAL_OR: case RTEAAL_XOR: return a == 2 || a == 3;
     case RTEAAL_MUX: return a == 3;
+    case RTEAAL_MUXC: return a >= 3 && a <= 2u * RTEAAL_MUXC_MAX_PAIRS + 1u && a % 2 == 1;
     case RTEAAL_ADD: case RTEAAL_SUB: case RTEAAL_MUL: case RTEAAL_EQ: case RTEAAL_LT:
     case RTEAAL_CONCAT: case RTEAAL_DIV: case RTEAAL_REM: case RTEAAL_DSHL: case RTEAAL_DSHR:
       return a == 2;
@@ -243,11 +244,13 @@ rteaal_status validate(const rteaal_design_desc* d, Drivers* drv, std::string* w
   // Per-layer formats, derived from the maximum coordinate / payload values.
   std::vector<rteaal_layer_format> fmt(d->n_layers);
   for (uint32_t i = 0; i < d->n_layers; ++i) {
-    uint32_t maxs = 0, maxr = 0, maxcount = 0;
+    uint32_t maxs = 0, maxr = 0, maxcount = 0, max_fiber = 0;
     uint32_t count[RTEAAL_OP_COUNT] = {0};
     for (uint32_t o = d->layer_op_ptr[i]; o < d->layer_op_ptr[i + 1]; ++o) {
       maxs = std::max(maxs, d->op_dst[o]);
       count[d->op_type[o]]++;
+      if (d->op_type[o] == RTEAAL_MUXC)
+        max_fiber = std::max(max_fiber, d->op_src_ptr[o + 1] - d->op_src_ptr[o]);
       for (uint32_t q = d->op_src_ptr[o]; q < d->op_src_ptr[o + 1]; ++q) maxr = std::max(maxr, d->op_src[q]);
     }
     for (uint32_t t = 0; t < RTEAAL_OP_COUNT; ++t) maxcount = std::max(maxcount, count[t]);
@@ -256,6 +259,8 @@ rteaal_status validate(const rteaal_design_desc* d, Drivers* drv, std::string* w
     f.oim[1] = {0, 0, (uint8_t)bits_for(maxcount)};        // N: uncompressed, ops per type
     f.oim[2] = {1, (uint8_t)bits_for(maxs), 0};            // S: compressed, coordinates only
     f.oim[3] = {0, 0, 0};                                   // O: uncompressed, implied by N
+    if (max_fiber)                                          // ... except for mux chains
+      f.oim[3] = {1, (uint8_t)bits_for(max_fiber - 1), 0};
     f.oim[4] = {1, (uint8_t)bits_for(maxr), 0};            // R: compressed, mask payload dropped
     f.li = {0, 0, 0};
     f.lo = {0, 0, 0};
@@ -304,9 +309,10 @@ struct DesignHost {
 
 struct EncOp {
   uint32_t opc, arity, dst_slot;  // dst_slot: user slot or n_slots + temp index
-  uint32_t src_slot[3];
-  uint32_t imm, aux0, aux1;
+  uint32_t src_slot[3];           // MUXC: s1, v1 and the default
+  uint32_t imm, aux0, aux1;       // MUXC: first extra slot in `extra`, extra pairs
   uint32_t dcls, kind, width;
+  bool narrow_chain;              // MUXC whose values all fit 64 bits
 };
 
 // compact: storage is assigned by live range (an element or 1-bit row is
@@ -325,9 +331,27 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
       width.push_back(width[d->reg_next[j]]);
     }
   auto cls_of = [&](uint32_t slot) { return cls_of_width(width[slot]); };
+  // Operand slots of the (selector, value) pairs after the first of every
+  // fused mux chain, in O order; the record holds s1, v1 and the default.
+  std::vector<uint32_t> extra;
   auto mk = [&](uint32_t opc, uint32_t arity, uint32_t dst, const uint32_t* src, uint32_t imm,
                 uint32_t aux0, uint32_t aux1) {
+    uint32_t rec[3];
+    bool narrow_chain = false;
+    if (opc == OP_MUXC) {
+      narrow_chain = width[dst] <= 64;
+      for (uint32_t q = 0; q < arity; ++q) narrow_chain = narrow_chain && width[src[q]] <= 64;
+      rec[0] = src[0];
+      rec[1] = src[1];
+      rec[2] = src[arity - 1];
+      aux0 = (uint32_t)extra.size();
+      aux1 = (arity - 3) / 2;
+      extra.insert(extra.end(), src + 2, src + arity - 1);
+      src = rec;
+      arity = 3;
+    }
     EncOp e{};
+    e.narrow_chain = narrow_chain;
     e.opc = opc;
     e.arity = arity;
     e.dst_slot = dst;
@@ -344,9 +368,9 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
       all_32 = all_32 && cls_of(src[o]) <= CW;
     }
     if (opc >= OP_STIM) all_b = all_32 = false;
-    // The FIRRTL primitives DIV .. SEXT always run in the wide form, which
-    // keeps them out of the common kernel.
-    if (opc >= OP_DIV && opc <= OP_SEXT) any_wide = true;
+    // The FIRRTL primitives DIV .. SEXT and fused mux chains always run in
+    // the wide form, which keeps them out of the common kernel.
+    if (opc >= OP_DIV && opc <= OP_MUXC) any_wide = true;
     e.kind = any_wide ? K_WIDE : all_b ? K_BIT : all_32 ? K_U32 : K_U64;
     return e;
   };
@@ -393,14 +417,17 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
 
   // Group each layer by (1-bit destination first, kind, type, class): the
   // N-rank swizzle, which also makes 1-bit destinations a prefix.  Heavy
-  // operations (a value wider than 64 bits, or a source) go last among the
-  // 1-bit destinations and first among the others, so they are contiguous;
-  // the common operations are ordered by arity, 3-2-1 before the heavy range
-  // and 1-2-3 after it, so every arity is one range on each side.
+  // operations (a value wider than 64 bits, a wide-form type, or a source) go
+  // last among the 1-bit destinations and first among the others, so they
+  // are contiguous, with the narrow mux chains at their middle (last among
+  // the 1-bit heavy ones, first among the others); the common operations are
+  // ordered by arity, 3-2-1 before the heavy range and 1-2-3 after it, so
+  // every arity is one range on each side.
   auto heavy = [](const EncOp& e) { return e.kind == K_WIDE || e.opc >= OP_STIM; };
   auto rank = [&](const EncOp& e) {
     const bool hv = heavy(e);
-    return e.dcls == CB ? (hv ? 3u : 3u - e.arity) : (hv ? 0u : e.arity);
+    if (e.dcls == CB) return hv ? (e.narrow_chain ? 4u : 3u) : 3u - e.arity;
+    return hv ? (e.narrow_chain ? 0u : 1u) : 1u + e.arity;
   };
   for (auto& lay : L)
     std::stable_sort(lay.begin(), lay.end(), [&](const EncOp& a, const EncOp& b) {
@@ -432,6 +459,8 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
     for (const EncOp& e : L[k]) {
       last[e.dst_slot] = std::max(last[e.dst_slot], k);
       for (uint32_t q = 0; q < e.arity; ++q) last[e.src_slot[q]] = std::max(last[e.src_slot[q]], k);
+      if (e.opc == OP_MUXC)
+        for (uint32_t q = 0; q < 2 * e.aux1; ++q) last[extra[e.aux0 + q]] = std::max(last[extra[e.aux0 + q]], k);
     }
   uint32_t cnt[NCLS] = {0};                        // elements (CB: rows) ever used per class
   std::vector<uint32_t> free_el[NCLS];             // LIFO: recently freed storage is warm
@@ -500,6 +529,15 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
       }
     dl.hbeg = n_heavy ? first_heavy : dl.begin;
     dl.hend = dl.hbeg + n_heavy;
+    dl.hm0 = dl.hm1 = dl.hbeg;
+    {
+      bool seen = false;
+      for (uint32_t i = 0; i < lay.size(); ++i)
+        if (lay[i].narrow_chain) {
+          if (!seen) dl.hm0 = dl.begin + i, seen = true;
+          dl.hm1 = dl.begin + i + 1;
+        }
+    }
     h->layers.push_back(dl);
     std::array<OpRanges, 3> ar{};
     for (uint32_t a = 1; a <= 3; ++a) {
@@ -549,6 +587,11 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
       sidx[k] = (uint32_t)((b_rows + y / 8) * 64 + (y % 8) * 8);
     }
 
+  // The word table: the literals' limbs (four words each, at least one
+  // literal's worth), then one word per extra mux-chain operand, its field
+  // in bits 0..31 and its class in bits 32..34.
+  h->const_limbs.assign(d->const_limbs, d->const_limbs + 4ull * d->n_consts);
+  if (h->const_limbs.empty()) h->const_limbs.assign(4, 0);
   h->ops.clear();
   h->ops.reserve(pos);
   for (auto& lay : L)
@@ -564,11 +607,16 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
       o.dst = sidx[e.dst_slot];
       o.aux0 = e.aux0;
       o.aux1 = e.aux1;
+      if (e.opc == OP_MUXC) {
+        o.aux0 = (uint32_t)h->const_limbs.size();
+        for (uint32_t q = 0; q < 2 * e.aux1; ++q) {
+          const uint32_t sl = extra[e.aux0 + q];
+          h->const_limbs.push_back((uint64_t)sidx[sl] | ((uint64_t)scls[sl] << 32));
+        }
+        if (e.narrow_chain) o.code |= 1u << 22;
+      }
       h->ops.push_back(o);
     }
-
-  h->const_limbs.assign(d->const_limbs, d->const_limbs + 4ull * d->n_consts);
-  if (h->const_limbs.empty()) h->const_limbs.assign(4, 0);
 
   h->reg_refs.clear();
   uint32_t off = 0;
@@ -1023,6 +1071,106 @@ rteaal_status rteaal_validate_design(const rteaal_design_desc* desc, char* err, 
   }
   if (st != RTEAAL_OK) g_err = why;
   return st;
+}
+
+rteaal_status rteaal_fuse_mux_chains(const rteaal_design_desc* d, uint32_t max_pairs,
+                                     uint32_t* layer_op_ptr, uint8_t* op_type, uint32_t* op_dst,
+                                     uint32_t* op_src_ptr, uint32_t* op_src, uint16_t* op_imm,
+                                     rteaal_fuse_result* result) {
+  if (!d || !layer_op_ptr || !op_src_ptr || !result ||
+      (d->n_ops && (!op_type || !op_dst || !op_imm || !op_src))) {
+    g_err = "null argument";
+    return RTEAAL_E_INVALID_ARG;
+  }
+  if (max_pairs < 1 || max_pairs > RTEAAL_MUXC_MAX_PAIRS) {
+    g_err = "max_pairs must be 1.." + std::to_string(RTEAAL_MUXC_MAX_PAIRS);
+    return RTEAAL_E_INVALID_ARG;
+  }
+  Drivers drv;
+  std::string why;
+  const rteaal_status st = validate(d, &drv, &why, nullptr);
+  if (st != RTEAAL_OK) {
+    g_err = why;
+    return st;
+  }
+  const uint32_t n = d->n_ops;
+  // Readers per slot (operand entries) and latched slots.
+  std::vector<uint32_t> readers(d->n_slots, 0);
+  for (uint32_t q = 0; q < d->op_src_ptr[n]; ++q) ++readers[d->op_src[q]];
+  std::vector<char> latched(d->n_slots, 0);
+  for (uint32_t j = 0; j < d->n_regs; ++j) latched[d->reg_next[j]] = 1;
+  // inner[o]: the MUX whose result o's default operand is, when o may absorb it.
+  constexpr uint32_t kNone = UINT32_MAX;
+  std::vector<uint32_t> inner(n, kNone);
+  std::vector<char> is_inner(n, 0);
+  for (uint32_t o = 0; o < n; ++o) {
+    if (d->op_type[o] != RTEAAL_MUX) continue;
+    const uint32_t x = d->op_src[d->op_src_ptr[o] + 2];
+    if (drv.kind[x] != DRV_OP) continue;
+    const uint32_t p = drv.which[x];
+    if (d->op_type[p] != RTEAAL_MUX || readers[x] != 1 || latched[x] ||
+        d->slot_width[x] < d->slot_width[d->op_dst[o]])
+      continue;
+    inner[o] = p;
+    is_inner[p] = 1;
+  }
+  // Walk every path from its outermost MUX; cut it into pieces of at most
+  // max_pairs pairs.  A fused head's operands are lists[at[o], at[o] + len[o]).
+  std::vector<uint32_t> at(n, kNone), len(n, 0), lists;
+  std::vector<char> absorbed(n, 0);
+  uint32_t n_fused = 0, n_absorbed = 0;
+  for (uint32_t o = 0; o < n; ++o) {
+    if (d->op_type[o] != RTEAAL_MUX || is_inner[o] || inner[o] == kNone) continue;
+    for (uint32_t head = o; head != kNone;) {
+      const uint32_t start = (uint32_t)lists.size();
+      uint32_t m = head, pairs = 0;
+      for (;;) {
+        const uint32_t* sm = d->op_src + d->op_src_ptr[m];
+        lists.push_back(sm[0]);
+        lists.push_back(sm[1]);
+        ++pairs;
+        if (inner[m] == kNone || pairs == max_pairs) {
+          lists.push_back(sm[2]);
+          break;
+        }
+        m = inner[m];
+        absorbed[m] = 1;
+        ++n_absorbed;
+      }
+      if (pairs > 1) {
+        at[head] = start;
+        len[head] = (uint32_t)lists.size() - start;
+        ++n_fused;
+      } else {
+        lists.resize(start);
+      }
+      head = inner[m];
+    }
+  }
+  // The fused design: the operations in their order, absorbed ones dropped.
+  uint32_t k = 0;
+  op_src_ptr[0] = 0;
+  for (uint32_t i = 0; i < d->n_layers; ++i) {
+    layer_op_ptr[i] = k;
+    for (uint32_t o = d->layer_op_ptr[i]; o < d->layer_op_ptr[i + 1]; ++o) {
+      if (absorbed[o]) continue;
+      const bool f = at[o] != kNone;
+      const uint32_t* src = f ? lists.data() + at[o] : d->op_src + d->op_src_ptr[o];
+      const uint32_t ar = f ? len[o] : d->op_src_ptr[o + 1] - d->op_src_ptr[o];
+      op_type[k] = f ? (uint8_t)RTEAAL_MUXC : d->op_type[o];
+      op_dst[k] = d->op_dst[o];
+      op_imm[k] = f ? 0 : d->op_imm[o];
+      std::copy(src, src + ar, op_src + op_src_ptr[k]);
+      op_src_ptr[k + 1] = op_src_ptr[k] + ar;
+      ++k;
+    }
+  }
+  layer_op_ptr[d->n_layers] = k;
+  result->n_ops = k;
+  result->n_operands = op_src_ptr[k];
+  result->n_fused = n_fused;
+  result->n_absorbed = n_absorbed;
+  return RTEAAL_OK;
 }
 
 rteaal_status rteaal_levelize(rteaal_ctx* ctx, const rteaal_dag_desc* g, uint32_t* op_layer,

@@ -36,7 +36,7 @@ __host__ __device__ inline uint32_t cls_bytes(uint32_t c) {
 enum Opc : uint32_t {
   OP_AND = 0, OP_OR, OP_XOR, OP_NOT, OP_ADD, OP_SUB, OP_MUL, OP_MUX, OP_EQ, OP_LT, OP_SHL,
   OP_SHR, OP_EXTRACT, OP_CONCAT, OP_ORR, OP_DIV, OP_REM, OP_DSHL, OP_DSHR, OP_ANDR, OP_XORR,
-  OP_SEXT, OP_COPY = 60, OP_STIM = 61, OP_CONST = 62
+  OP_SEXT, OP_MUXC, OP_COPY = 60, OP_STIM = 61, OP_CONST = 62
 };
 
 // Evaluation kind: every class is CB (1-bit logic on whole words of
@@ -46,10 +46,15 @@ enum Kind : uint32_t { K_BIT = 0, K_U64 = 1, K_WIDE = 2, K_U32 = 3 };
 
 // One operation, 32 bytes.
 //   code: opc[0:5] kind[6:7] arity[8:9] dst class[10:12] src classes [13:15][16:18][19:21]
+//         narrow chain[22]
 //   wimm: dst width[0:8] (1..256), imm[9:17] (shift, low bit, width of o1 for CONCAT,
 //         width of o0 for ANDR and SEXT)
 //   dst, src[3]: slot fields 64*row + shift (see StateLayout)
 //   aux0: STIM input number / CONST literal index;  aux1: STIM limb offset in a words row
+//   MUXC: src = (s1, v1, default); aux0: index in the word table of the
+//         further pairs' operands (selector, value, selector, ...; one word
+//         each: field in bits 0..31, class in bits 32..34); aux1: their
+//         number of pairs
 struct DevOp {
   uint32_t code, wimm, dst, src[3], aux0, aux1;
 };
@@ -62,17 +67,23 @@ __host__ __device__ inline uint32_t op_dcls(uint32_t c) { return (c >> 10) & 7u;
 __host__ __device__ inline uint32_t op_scls(uint32_t c, int o) { return (c >> (13 + 3 * o)) & 7u; }
 __host__ __device__ inline uint32_t op_width(uint32_t w) { return w & 511u; }
 __host__ __device__ inline uint32_t op_imm(uint32_t w) { return (w >> 9) & 511u; }
+// MUXC whose destination and operands all fit 64 bits (bit 22 of code).
+__host__ __device__ inline bool op_narrow_chain(uint32_t c) { return (c >> 22) & 1u; }
 
 // One encoded layer: operations [begin, end).  Operations whose destination
 // is 1-bit come first, and each group of 64 of them (i = 64g .. 64g+63)
 // writes bits 0..63 of one row of its own, so one wavefront of consecutive
 // operations fills exactly one 64-bit word (b_base: the first group's row
-// times 64).  The "heavy" operations (a value wider than
-// 64 bits, or a source: STIM, CONST) form the contiguous range [hbeg, hend)
-// (the last 1-bit destinations and the first others), so the SWEEP mapping
-// runs them in a kernel of their own and keeps the common kernel small.
+// times 64).  The "heavy" operations (a value wider than 64 bits, a type
+// always run in the wide form, or a source: STIM, CONST) form the contiguous
+// range [hbeg, hend) (the last 1-bit destinations and the first others), so
+// the SWEEP mapping runs them in a kernel of their own and keeps the common
+// kernel small.  Inside it, the fused mux chains whose values all fit 64 bits
+// form the sub-range [hm0, hm1) (the last 1-bit destinations of the heavy
+// range and the first others), run by a third kernel; [hbeg, hm0) and
+// [hm1, hend) hold the other heavy operations.
 struct DevLayer {
-  uint32_t begin, end, b_base, n_bdst, hbeg, hend, pad0, pad1;
+  uint32_t begin, end, b_base, n_bdst, hbeg, hend, hm0, hm1;
 };
 static_assert(sizeof(DevLayer) == 32, "DevLayer layout");
 
@@ -139,7 +150,7 @@ struct StateLayout {
 struct Program {
   const DevOp* ops;
   const DevLayer* layers;
-  const uint64_t* const_limbs;  // [n_consts][4]
+  const uint64_t* const_limbs;  // word table: [n_consts][4] literal limbs, then mux-chain operands
   uint32_t n_layers;
   uint32_t words_per_inst;      // stimulus limbs per instance and cycle
 };

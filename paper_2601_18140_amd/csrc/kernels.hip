@@ -172,7 +172,15 @@ __device__ __forceinline__ void resident_ops(const ResJob& J, char* s, const Dev
         } else {
           const V4 a = res_ldv(s, op_scls(code, 0), o.src[0]);
           const V4 b = ar > 1 ? res_ldv(s, op_scls(code, 1), o.src[1]) : v4_from(0);
-          const V4 c = ar > 2 ? res_ldv(s, op_scls(code, 2), o.src[2]) : v4_from(0);
+          V4 c = ar > 2 ? res_ldv(s, op_scls(code, 2), o.src[2]) : v4_from(0);
+          if (opc == OP_MUXC)  // further pairs, innermost first, onto the default
+            for (uint32_t i = o.aux1; i-- > 0;) {
+              const uint64_t es = J.const_limbs[o.aux0 + 2u * i];
+              const uint64_t ev = J.const_limbs[o.aux0 + 2u * i + 1u];
+              const V4 sv = res_ldv(s, (uint32_t)(es >> 32), (uint32_t)es);
+              const V4 vv = res_ldv(s, (uint32_t)(ev >> 32), (uint32_t)ev);
+              if (v4_nonzero(sv)) c = vv;
+            }
           const V4 r = eval_wide(opc, ar, a, b, c, imm, w);
           if (dc == CB) {
             bdst = true;
@@ -532,8 +540,153 @@ k_sweep(const DevOp* __restrict__ ops, StateLayout L, char* __restrict__ state, 
   }
 }
 
-// The heavy operations of one layer (a value wider than 64 bits, or a
-// source).  Limb 0 of every operand is gathered without branches (an 8-byte
+// One operand (slot field f of class cls) for the TG tiles of the heavy
+// kernel: limb 0 from an 8-byte load holding the lane's element, further
+// limbs only for values wider than 64 bits.
+template <int TG>
+__device__ __forceinline__ void heavy_operand(const SweepView& v, uint32_t f, uint32_t cls,
+                                              V4 (&x)[TG]) {
+  const uint32_t w3 = cls_w3(cls), step = 512u >> w3, sh = v.sh64(w3), kl = cls_limbs(cls);
+  const uint64_t m = cls_mask64(cls);
+  const char* p = v.at(f, w3, 0u) + v.off64(w3);
+#pragma unroll
+  for (int g = 0; g < TG; ++g) {
+    x[g].l[0] = (*(const uint64_t*)(p + g * step) >> sh) & m;
+#pragma unroll
+    for (int l = 1; l < 4; ++l)
+      x[g].l[l] = (uint32_t)l < kl ? *(const uint64_t*)(p + (uint64_t)l * v.row_bytes + g * 512u) : 0ull;
+  }
+}
+
+// A fused mux chain for the TG tiles: the record's default in e, then the
+// further pairs from the word table, innermost first (a nonzero selector
+// replaces the running default with its value), then the first pair.
+template <int TG>
+__device__ __forceinline__ void heavy_muxc(const SweepView& v, const DevOp& q,
+                                           const uint64_t* __restrict__ words, V4 (&r)[TG]) {
+  V4 s1[TG], v1[TG], e[TG];
+  heavy_operand<TG>(v, q.src[0], op_scls(q.code, 0), s1);
+  heavy_operand<TG>(v, q.src[1], op_scls(q.code, 1), v1);
+  heavy_operand<TG>(v, q.src[2], op_scls(q.code, 2), e);
+  for (uint32_t i = q.aux1; i-- > 0;) {
+    const uint64_t es = words[q.aux0 + 2u * i], ev = words[q.aux0 + 2u * i + 1u];
+    V4 sv[TG], vv[TG];
+    heavy_operand<TG>(v, (uint32_t)es, (uint32_t)(es >> 32), sv);
+    heavy_operand<TG>(v, (uint32_t)ev, (uint32_t)(ev >> 32), vv);
+#pragma unroll
+    for (int g = 0; g < TG; ++g)
+      if (v4_nonzero(sv[g])) e[g] = vv[g];
+  }
+  const uint32_t w = op_width(q.wimm);
+#pragma unroll
+  for (int g = 0; g < TG; ++g) r[g] = eval_wide(OP_MUXC, 3u, s1[g], v1[g], e[g], 0u, w);
+}
+
+// A fused mux chain whose values all fit 64 bits: the raw 8-byte words of C
+// pairs (2 C TG gathers) are in flight before the first select, so a chain
+// of k pairs waits for memory about k / C times rather than k times.  Pairs
+// are folded innermost first onto the default, as in heavy_muxc.
+template <int TG>
+__device__ __forceinline__ void heavy_muxc64(const SweepView& v, const DevOp& q,
+                                             const uint64_t* __restrict__ words, V4 (&r)[TG]) {
+  constexpr int C = TG >= 4 ? 4 : 8;  // 2 C TG gathers per batch
+  const uint32_t np = q.aux1;
+  // The record's operands (s1, v1, default) are cut only once the first
+  // batch of further pairs is in flight too.
+  uint64_t rec[3][TG];
+  uint32_t rsh[3];
+  uint64_t rm[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const uint32_t cls = op_scls(q.code, k), w3 = cls_w3(cls), step = 512u >> w3;
+    const char* p = v.at(q.src[k], w3, 0u) + v.off64(w3);
+    rsh[k] = v.sh64(w3);
+    rm[k] = cls_mask64(cls);
+#pragma unroll
+    for (int g = 0; g < TG; ++g) rec[k][g] = *(const uint64_t*)(p + g * step);
+  }
+  uint64_t e[TG];
+  bool cut = false;
+  for (int c0 = ((int)np - 1) / C * C; np && c0 >= 0; c0 -= C) {
+    uint64_t raw[2 * C][TG];
+    uint32_t sh[2 * C];
+    uint64_t m[2 * C];
+#pragma unroll
+    for (int j = 0; j < 2 * C; ++j) {
+      // Past the chain's end the last real operand is read again (a valid
+      // address whose value the fold below skips).
+      const uint32_t i = min((uint32_t)(2 * c0 + j), 2u * np - 1u);
+      const uint64_t wd = words[q.aux0 + i];
+      const uint32_t cls = (uint32_t)(wd >> 32), w3 = cls_w3(cls), step = 512u >> w3;
+      const char* p = v.at((uint32_t)wd, w3, 0u) + v.off64(w3);
+      sh[j] = v.sh64(w3);
+      m[j] = cls_mask64(cls);
+#pragma unroll
+      for (int g = 0; g < TG; ++g) raw[j][g] = *(const uint64_t*)(p + g * step);
+    }
+    if (!cut) {
+#pragma unroll
+      for (int g = 0; g < TG; ++g) e[g] = (rec[2][g] >> rsh[2]) & rm[2];
+      cut = true;
+    }
+#pragma unroll
+    for (int j = C - 1; j >= 0; --j)
+      if ((uint32_t)(c0 + j) < np) {
+#pragma unroll
+        for (int g = 0; g < TG; ++g)
+          if ((raw[2 * j][g] >> sh[2 * j]) & m[2 * j]) e[g] = (raw[2 * j + 1][g] >> sh[2 * j + 1]) & m[2 * j + 1];
+      }
+  }
+  if (!cut) {
+#pragma unroll
+    for (int g = 0; g < TG; ++g) e[g] = (rec[2][g] >> rsh[2]) & rm[2];
+  }
+  const uint32_t w = op_width(q.wimm);
+  const uint64_t mw = w >= 64 ? ~0ull : (1ull << w) - 1ull;
+#pragma unroll
+  for (int g = 0; g < TG; ++g) {
+    const uint64_t s1 = (rec[0][g] >> rsh[0]) & rm[0], v1 = (rec[1][g] >> rsh[1]) & rm[1];
+    r[g] = v4_from(0);
+    r[g].l[0] = (s1 ? v1 : e[g]) & mw;
+  }
+}
+
+// The narrow mux chains of one layer, [hm0, hm1): each wavefront takes
+// ops_per_wave of them over the TG tiles of its tile group.
+template <int TG>
+__global__ void __launch_bounds__(256)
+k_sweep_muxc(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
+             const uint64_t* __restrict__ words, StateLayout L, char* __restrict__ state,
+             uint32_t layer, uint32_t opw, uint32_t tile_base, uint32_t n_groups) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const uint32_t grp = wave % n_groups, chunk = wave / n_groups;
+  const DevLayer ly = layers[layer];
+  const uint32_t o0 = ly.hm0 + chunk * opw;
+  if (o0 >= ly.hm1) return;
+  const uint32_t o1 = min(o0 + opw, ly.hm1);
+  const SweepView v(state, L, tile_base + grp * TG, lane);
+  for (uint32_t o = o0; o < o1; ++o) {
+    const DevOp q = ops[o];
+    V4 r[TG];
+    heavy_muxc64<TG>(v, q, words, r);
+    const uint32_t dc = op_dcls(q.code);
+    uint64_t x[TG];
+    if (dc == CB) {
+#pragma unroll
+      for (int g = 0; g < TG; ++g) x[g] = __ballot((r[g].l[0] & 1ull) != 0ull);
+      v.st_bits<TG>(q.dst, x);
+    } else {
+#pragma unroll
+      for (int g = 0; g < TG; ++g) x[g] = r[g].l[0];
+      v.st_dst<TG, true>(dc, q.dst, x);
+    }
+  }
+}
+
+// The heavy operations of one layer (a value wider than 64 bits, a type run
+// in the wide form, or a source) outside the narrow mux chains.  Limb 0 of every operand is gathered without branches (an 8-byte
 // load per tile holding the lane's element, cut out as in the common
 // kernel); the further limbs of wide operands follow under a uniform branch.
 // All loads of an operation are in flight before the first is used.
@@ -549,9 +702,13 @@ k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   const uint32_t grp = wave % n_groups, chunk = wave / n_groups;
   const DevLayer ly = layers[layer];
-  const uint32_t o0 = ly.hbeg + chunk * opw;
-  if (o0 >= ly.hend) return;
-  const uint32_t o1 = min(o0 + opw, ly.hend);
+  // [hbeg, hm0) then [hm1, hend): the narrow mux chains between them have a
+  // kernel of their own.
+  const uint32_t split = (ly.hm0 - ly.hbeg + opw - 1) / opw;
+  const uint32_t o0 = chunk < split ? ly.hbeg + chunk * opw : ly.hm1 + (chunk - split) * opw;
+  const uint32_t oe = chunk < split ? ly.hm0 : ly.hend;
+  if (o0 >= oe) return;
+  const uint32_t o1 = min(o0 + opw, oe);
   const uint32_t tile0 = tile_base + grp * TG;
   const SweepView v(state, L, tile0, lane);
 
@@ -571,6 +728,8 @@ k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers
         if (inst < n_inst)
           r[g] = source_value(const_limbs, q, seeds[inst], cycle, ctl->words, words_row, w);
       }
+    } else if (opc == OP_MUXC) {  // a chain with a value wider than 64 bits
+      heavy_muxc<TG>(v, q, const_limbs, r);
     } else {
       uint64_t raw[3 * 4 * TG];
       uint32_t sh[3], kl[3];
@@ -975,11 +1134,32 @@ hipError_t launch_sweep_heavy(const Program& p, const StateLayout& L, char* stat
                               const uint64_t* seeds, const DevCtl* ctl, uint32_t n_inst,
                               uint32_t layer, const DevLayer& ly, uint32_t ops_per_wave,
                               uint32_t tiles_per_wave, TilePass tp, hipStream_t s) {
-  const uint32_t n = ly.hend - ly.hbeg;
-  if (n == 0) return hipSuccess;
+  if (ly.hend == ly.hbeg) return hipSuccess;
+  if (ops_per_wave == 0 || ly.hm0 < ly.hbeg || ly.hm1 < ly.hm0 || ly.hend < ly.hm1)
+    return hipErrorInvalidValue;
+  const uint32_t n_chain = ly.hm1 - ly.hm0;
+  if (n_chain) {
+    // Narrow mux chains: up to 4 tiles per wavefront (measured on a chain-heavy
+    // design: 4 tiles beat 8, whose gathers need fewer pairs per batch, and 2).
+    const uint32_t tg = tiles_per_wave >= 4 ? 4u : tiles_per_wave == 2 ? 2u : 1u;
+    if (!pass_ok(L, tp, tg)) return hipErrorInvalidValue;
+    const uint64_t waves = (uint64_t)((n_chain + ops_per_wave - 1) / ops_per_wave) * (tp.count / tg);
+    const dim3 grid((uint32_t)((waves + 3) / 4)), blk(256);
+#define RTEAAL_MUXC_K(GG)                                                                   \
+  hipLaunchKernelGGL((k_sweep_muxc<GG>), grid, blk, 0, s, p.ops, p.layers, p.const_limbs,   \
+                     L, state, layer, ops_per_wave, tp.base, tp.count / tg)
+    if (tg == 4) RTEAAL_MUXC_K(4);
+    else if (tg == 2) RTEAAL_MUXC_K(2);
+    else RTEAAL_MUXC_K(1);
+#undef RTEAAL_MUXC_K
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const uint32_t n1 = ly.hm0 - ly.hbeg, n2 = ly.hend - ly.hm1;
+  if (n1 + n2 == 0) return hipSuccess;
   const uint32_t tg = tiles_per_wave >= 2 ? 2u : 1u;
-  if (ops_per_wave == 0 || !pass_ok(L, tp, tg)) return hipErrorInvalidValue;
-  const uint64_t chunks = (n + ops_per_wave - 1) / ops_per_wave;
+  if (!pass_ok(L, tp, tg)) return hipErrorInvalidValue;
+  const uint64_t chunks = (n1 + ops_per_wave - 1) / ops_per_wave + (n2 + ops_per_wave - 1) / ops_per_wave;
   const uint32_t n_groups = tp.count / tg;
   const uint64_t waves = chunks * n_groups;
   const dim3 grid((uint32_t)((waves + 3) / 4)), blk(256);

@@ -325,7 +325,8 @@ __device__ __forceinline__ V4 eval_wide(uint32_t opc, uint32_t arity, const V4& 
     case OP_ADD: r = v4_add(a, b); break;
     case OP_SUB: r = v4_sub(a, b); break;
     case OP_MUL: r = v4_mul(a, b); break;
-    case OP_MUX: r = v4_nonzero(a) ? b : c; break;
+    case OP_MUX:
+    case OP_MUXC: r = v4_nonzero(a) ? b : c; break;  // MUXC: c holds the folded further pairs
     case OP_EQ:
       r = v4_from((a.l[0] == b.l[0]) & (a.l[1] == b.l[1]) & (a.l[2] == b.l[2]) & (a.l[3] == b.l[3]));
       break;

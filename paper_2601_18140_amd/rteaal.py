@@ -35,6 +35,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "BAD_DESIGN", 3: "FORMAT", 4: "NO_
                 5: "DEVICE", 6: "BUSY", 7: "UNSUPPORTED"}
 RTEAAL_MAP_AUTO, RTEAAL_MAP_RESIDENT, RTEAAL_MAP_SWEEP, RTEAAL_MAP_LAYERED = 0, 1, 2, 3
 RTEAAL_READ_REGS, RTEAAL_READ_ALL_SLOTS = 1, 2
+RTEAAL_MUXC, RTEAAL_MUXC_MAX_PAIRS = 22, 32
 
 
 class RteaalError(RuntimeError):
@@ -63,6 +64,11 @@ class rteaal_design_desc(C.Structure):
         ("op_src_ptr", C.c_void_p), ("op_src", C.c_void_p), ("op_imm", C.c_void_p),
         ("layer_fmt", C.c_void_p),
     ]
+
+
+class rteaal_fuse_result(C.Structure):
+    _fields_ = [("n_ops", C.c_uint32), ("n_operands", C.c_uint32), ("n_fused", C.c_uint32),
+                ("n_absorbed", C.c_uint32)]
 
 
 class rteaal_dag_desc(C.Structure):
@@ -130,6 +136,8 @@ def library():
         "rteaal_levelize": ([vp, C.POINTER(rteaal_dag_desc), vp, vp, vp, C.POINTER(u32)], st),
         "rteaal_watch": ([vp, u32, vp, u32, u64], st),
         "rteaal_read_changes": ([vp, u32, vp, u64, C.POINTER(u64), C.POINTER(u64)], st),
+        "rteaal_fuse_mux_chains": ([C.POINTER(rteaal_design_desc), u32, vp, vp, vp, vp, vp, vp,
+                                    C.POINTER(rteaal_fuse_result)], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -146,7 +154,7 @@ def exported_symbols():
             "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch",
             "rteaal_batch_info", "rteaal_batch_options", "rteaal_step", "rteaal_step_many", "rteaal_sync",
             "rteaal_read_state", "rteaal_write_state", "rteaal_kernel_timing", "rteaal_autotune",
-            "rteaal_levelize", "rteaal_watch", "rteaal_read_changes"]
+            "rteaal_levelize", "rteaal_watch", "rteaal_read_changes", "rteaal_fuse_mux_chains"]
 
 
 def _check(ctx, status):
@@ -327,6 +335,35 @@ def levelized_design(ctx, design):
     out.op_src_ptr = new_ptr.astype(np.uint32)
     out.layer_ptr = lptr.astype(np.uint32)
     return out
+
+
+def rteaal_fuse_mux_chains(design, max_pairs=RTEAAL_MUXC_MAX_PAIRS):
+    """Mux-chain fusion on the host (rteaal_fuse_mux_chains in rteaal.h):
+    (copy of `design` with the fused operation arrays, counts as a dict)."""
+    import copy
+    d, keep = _desc(design)
+    n, ne, nl = d.n_ops, int(np.asarray(design.op_src_ptr)[-1]), d.n_layers
+    lptr = np.zeros(nl + 1, np.uint32)
+    typ = np.zeros(max(n, 1), np.uint8)
+    dst = np.zeros(max(n, 1), np.uint32)
+    sptr = np.zeros(n + 1, np.uint32)
+    src = np.zeros(max(ne, 1), np.uint32)
+    imm = np.zeros(max(n, 1), np.uint16)
+    res = rteaal_fuse_result()
+    st = library().rteaal_fuse_mux_chains(C.byref(d), int(max_pairs), lptr.ctypes.data,
+                                          typ.ctypes.data, dst.ctypes.data, sptr.ctypes.data,
+                                          src.ctypes.data, imm.ctypes.data, C.byref(res))
+    _check(None, st)
+    k = res.n_ops
+    out = copy.copy(design)
+    out.layer_ptr = lptr
+    out.op_type = typ[:k].copy()
+    out.op_dst = dst[:k].copy()
+    out.op_src_ptr = sptr[:k + 1].copy()
+    out.op_src = src[:res.n_operands].copy()
+    out.op_imm = imm[:k].copy()
+    return out, {"n_ops": k, "n_operands": res.n_operands, "n_fused": res.n_fused,
+                 "n_absorbed": res.n_absorbed}
 
 
 # Layout of rteaal_change (48 bytes).

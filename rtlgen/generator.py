@@ -235,6 +235,11 @@ def _chain_muxes(rng, p, op_type, layer_ptr, src_ptr, op_src, reg_next, width, b
 CFG0 = GenConfig(2_000, 16, 64, 16, WIDTHS_STD, "plain-2k")
 CFG1 = GenConfig(200_000, 48, 4_096, 64, WIDTHS_STD, "single-200k")
 CFG3 = GenConfig(5_000_000, 120, 64_000, 256, WIDTHS_LARGE, "large-5m")
+# Mux-heavy logic with priority chains (35 % MUX, 80 % of them chained):
+# the input of the mux-chain fusion measurement.
+OP_MIX_MUX = tuple((t, a, 0.35 if t == MUX else p) for t, a, p in OP_MIX)
+CFG_MUXCHAIN = GenConfig(2_000_000, 100, 32_000, 256, WIDTHS_STD, "muxchain-2m", OP_MIX_MUX,
+                         mux_chain=0.8)
 
 WORKLOADS = {
     "plain-2k": dict(cfg=CFG0, seed=0, instances=1, cycles=10_000),

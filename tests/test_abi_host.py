@@ -159,3 +159,47 @@ def test_limb_packing_roundtrip():
     for k in range(6):
         vals[:, k, nl[k]:] = 0
     assert np.array_equal(R.unpack_limbs(R.pack_limbs(vals, widths), widths), vals)
+
+
+@pytest.mark.parametrize("seed,max_pairs", [(1, 32), (2, 3), (3, 2), (4, 1)])
+def test_fuse_mux_chains_matches_the_oracle_pass(seed, max_pairs):
+    """The library's fusion (host code, no device) gives exactly the
+    operation arrays of the oracle's pass; the result validates."""
+    import oracle
+    cfg = rtlgen.GenConfig(20_000, 20, 400, 16, rtlgen.generator.WIDTHS_LARGE, "chains", mux_chain=0.85)
+    d = rtlgen.generate(cfg, seed)
+    ref, n_fused, n_abs = oracle.fuse_mux_chains(d, max_pairs)
+    got, cnt = R.rteaal_fuse_mux_chains(d, max_pairs)
+    assert cnt == {"n_ops": ref.n_ops, "n_operands": int(ref.op_src_ptr[-1]), "n_fused": n_fused,
+                   "n_absorbed": n_abs}
+    for k in ("layer_ptr", "op_type", "op_dst", "op_src_ptr", "op_src", "op_imm"):
+        assert np.array_equal(np.asarray(getattr(got, k), np.int64), np.asarray(getattr(ref, k), np.int64)), k
+    assert R.rteaal_validate_design(got)[0] == 0
+    # fusing again finds nothing more (MUXC is never absorbed or extended)
+    again, cnt2 = R.rteaal_fuse_mux_chains(got, max_pairs)
+    assert cnt2["n_fused"] == 0 and cnt2["n_absorbed"] == 0 and again.n_ops == got.n_ops
+
+
+def test_fuse_mux_chains_errors_and_muxc_arity(good):
+    for mp in (0, 33):
+        with pytest.raises(R.RteaalError) as e:
+            R.rteaal_fuse_mux_chains(good, mp)
+        assert e.value.status == 1
+    bad = _clone(good)
+    bad.slot_width[0] = 0
+    with pytest.raises(R.RteaalError) as e:
+        R.rteaal_fuse_mux_chains(bad, 32)
+    assert e.value.status == 2
+    # MUXC takes an odd number 3..65 of operands
+    b = cir.Builder("m")
+    ins = [b.input(8) for _ in range(67)]
+    ok = b.op(rtlgen.MUXC, ins[:65], 8)
+    r = b.reg(8)
+    b.connect(r, ok)
+    assert R.rteaal_validate_design(b.build())[0] == 0
+    for n in (2, 4, 67):
+        b2 = cir.Builder("m")
+        ins = [b2.input(8) for _ in range(n)]
+        r = b2.reg(8)
+        b2.connect(r, b2.op(rtlgen.MUXC, ins, 8))
+        assert R.rteaal_validate_design(b2.build())[0] == 2

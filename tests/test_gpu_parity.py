@@ -339,13 +339,94 @@ def test_generated_design_with_every_type(ctx, mapping):
     cfg = rtlgen.GenConfig(6_000, 14, 80, 10, rtlgen.generator.WIDTHS_LARGE, "all-types",
                            rtlgen.OP_MIX_FULL)
     d = rtlgen.generate(cfg, 17)
-    assert set(np.unique(d.op_type)) == set(range(rtlgen.OP_COUNT))
+    assert set(np.unique(d.op_type)) == set(range(rtlgen.OP_COUNT)) - {rtlgen.MUXC}
     seeds = rtlgen.instance_seeds(70)
     note(f"all-types design, mapping={mapping}")
     ref_regs, ref_slots, _ = oracle.run(d, seeds, 15, want_slots=True)
     regs, sl, _ = run_gpu(ctx, d, seeds, [7, 8], mapping=mapping, slots=True)
     assert_same(regs, ref_regs, "registers")
     assert_same(sl, ref_slots, "every slot")
+
+
+# ---- fused mux chains ------------------------------------------------------------
+def chain_design(seed, n_ops=30_000):
+    cfg = rtlgen.GenConfig(n_ops, 24, 600, 16, rtlgen.generator.WIDTHS_LARGE, "chains",
+                           mux_chain=0.85)
+    return rtlgen.generate(cfg, seed)
+
+
+@pytest.mark.parametrize("mapping", MAPS, ids=MAP_IDS)
+@pytest.mark.parametrize("max_pairs", [32, 3])
+def test_fused_mux_chains_match_the_unfused_oracle(ctx, mapping, max_pairs):
+    """The fused design on the GPU against the oracle run of the design
+    before fusion: every register, and every slot the fused design writes."""
+    d = chain_design(1)
+    f, cnt = R.rteaal_fuse_mux_chains(d, max_pairs)
+    assert cnt["n_fused"] > 300
+    seeds = rtlgen.instance_seeds(70)
+    note(f"fused chains max_pairs={max_pairs} mapping={mapping}: {cnt}")
+    ref_regs, ref_slots, _ = oracle.run(d, seeds, 9, want_slots=True)
+    regs, sl, _ = run_gpu(ctx, f, seeds, [4, 5], mapping=mapping, slots=True)
+    assert_same(regs, ref_regs, "registers")
+    alive = f.op_dst.astype(np.int64)
+    assert_same(sl[:, alive], ref_slots[:, alive], "slots the fused design writes")
+
+
+def test_fused_chains_sweep_shapes(ctx):
+    """The narrow-chain kernel at every tile group and several operations per
+    wavefront, in one launch and per operand count."""
+    d = chain_design(3)
+    f, _ = R.rteaal_fuse_mux_chains(d)
+    seeds = rtlgen.instance_seeds(600)
+    ref, _, _ = oracle.run(d, seeds, 5)
+    for tg, opw, asp in ((1, 1, 1), (2, 3, 2), (4, 2, 1), (8, 1, 2), (8, 5, 1)):
+        note(f"fused chains SWEEP tg={tg} opw={opw} arity_split={asp}")
+        got, _, _ = run_gpu(ctx, f, seeds, [2, 3], mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=tg,
+                            ops_per_wave=opw, arity_split=asp, unroll=1)
+        assert_same(got, ref, f"tg={tg} opw={opw}")
+
+
+def test_fused_then_levelized(ctx):
+    d = chain_design(2, 60_000)
+    f, _ = R.rteaal_fuse_mux_chains(d)
+    lv = R.levelized_design(ctx, f)
+    assert lv.n_layers <= f.n_layers
+    seeds = rtlgen.instance_seeds(200)
+    note(f"fused + levelized: {f.n_layers} -> {lv.n_layers} layers")
+    ref, _, _ = oracle.run(d, seeds, 6)
+    for mapping in MAPS:
+        got, _, _ = run_gpu(ctx, lv, seeds, [2, 4], mapping=mapping)
+        assert_same(got, ref, f"mapping {mapping}")
+
+
+@pytest.mark.parametrize("mapping", MAPS, ids=MAP_IDS)
+@pytest.mark.parametrize("values", ["wide", "narrow"])
+def test_long_muxc_every_class(ctx, mapping, values):
+    """MUXC operations of 1 to 32 pairs, one per destination width, with
+    values of every class (1-bit, 8, 16, 32, 64 bits, and 2-4 limbs unless
+    narrow, where every value fits 64 bits), selectors that are rarely nonzero
+    (three-input AND of 1-bit inputs), so deep pairs and the default are
+    taken too."""
+    b = cir.Builder("long-muxc")
+    bits = [b.input(1) for _ in range(40)]
+    widths = (1, 5, 8, 13, 16, 30, 32, 50, 64) + ((65, 128, 200, 256) if values == "wide" else ())
+    vals = [b.input(w) for w in widths]
+    sels = [b.op(rtlgen.AND, [bits[i], bits[(i + 5) % 40], bits[(i + 11) % 40]], 1)
+            for i in range(32)]
+    dsts = (1, 8, 16, 32, 64) + ((100, 256) if values == "wide" else ())
+    for k, wd in enumerate(dsts):
+        for pairs in (32, 9, 17, 8, 2, 1):
+            srcs = []
+            for i in range(pairs):
+                srcs += [sels[(i + k) % 32], vals[(3 * i + k) % len(vals)]]
+            srcs.append(vals[k])
+            r = b.reg(wd)
+            b.connect(r, b.op(rtlgen.MUXC, srcs, wd))
+    d = b.build()
+    seeds = np.arange(300, dtype=np.uint64)
+    ref, _, _ = oracle.run(d, seeds, 4)
+    got, _, _ = run_gpu(ctx, d, seeds, 4, mapping=mapping)
+    assert_same(got, ref, "long MUXC")
 
 
 # ---- several designs in one step -------------------------------------------

@@ -434,7 +434,12 @@ def bench_muxchain(args, R, torch):
     for label, des in (("unfused", d), ("fused", lv)):
         did = R.rteaal_load_design(ctx, des)
         opts = {}
-        if not args.no_autotune:
+        if args.mapping != "auto":      # one given shape for both designs
+            opts = {"mapping": {"resident": R.RTEAAL_MAP_RESIDENT, "sweep": R.RTEAAL_MAP_SWEEP,
+                                "layered": R.RTEAAL_MAP_LAYERED}[args.mapping],
+                    "block_threads": args.block, "ops_per_wave": args.ops_per_wave,
+                    "unroll": args.unroll, "tiles_per_wave": args.tiles_per_wave}
+        elif not args.no_autotune:
             opts, trate = R.rteaal_autotune(ctx, did, n_inst)
             print(f"[bench] autotune {label}: {opts} -> {trate:.4g}", file=sys.stderr, flush=True)
         bid = R.rteaal_create_batch(ctx, did, seeds, **opts)

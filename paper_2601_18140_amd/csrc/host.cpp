@@ -419,15 +419,16 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
   // N-rank swizzle, which also makes 1-bit destinations a prefix.  Heavy
   // operations (a value wider than 64 bits, a wide-form type, or a source) go
   // last among the 1-bit destinations and first among the others, so they
-  // are contiguous, with the narrow mux chains at their middle (last among
+  // are contiguous, with the fused mux chains at their middle (last among
   // the 1-bit heavy ones, first among the others); the common operations are
   // ordered by arity, 3-2-1 before the heavy range and 1-2-3 after it, so
   // every arity is one range on each side.
   auto heavy = [](const EncOp& e) { return e.kind == K_WIDE || e.opc >= OP_STIM; };
   auto rank = [&](const EncOp& e) {
     const bool hv = heavy(e);
-    if (e.dcls == CB) return hv ? (e.narrow_chain ? 4u : 3u) : 3u - e.arity;
-    return hv ? (e.narrow_chain ? 0u : 1u) : 1u + e.arity;
+    const bool chain = e.opc == OP_MUXC;
+    if (e.dcls == CB) return hv ? (chain ? 4u : 3u) : 3u - e.arity;
+    return hv ? (chain ? 0u : 1u) : 1u + e.arity;
   };
   for (auto& lay : L)
     std::stable_sort(lay.begin(), lay.end(), [&](const EncOp& a, const EncOp& b) {
@@ -533,7 +534,7 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
     {
       bool seen = false;
       for (uint32_t i = 0; i < lay.size(); ++i)
-        if (lay[i].narrow_chain) {
+        if (lay[i].opc == OP_MUXC) {
           if (!seen) dl.hm0 = dl.begin + i, seen = true;
           dl.hm1 = dl.begin + i + 1;
         }

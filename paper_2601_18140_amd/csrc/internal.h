@@ -78,10 +78,10 @@ __host__ __device__ inline bool op_narrow_chain(uint32_t c) { return (c >> 22) &
 // always run in the wide form, or a source: STIM, CONST) form the contiguous
 // range [hbeg, hend) (the last 1-bit destinations and the first others), so
 // the SWEEP mapping runs them in a kernel of their own and keeps the common
-// kernel small.  Inside it, the fused mux chains whose values all fit 64 bits
-// form the sub-range [hm0, hm1) (the last 1-bit destinations of the heavy
-// range and the first others), run by a third kernel; [hbeg, hm0) and
-// [hm1, hend) hold the other heavy operations.
+// kernel small.  Inside it, the fused mux chains (MUXC) form the sub-range
+// [hm0, hm1) (the last 1-bit destinations of the heavy range and the first
+// others), run by a third kernel; [hbeg, hm0) and [hm1, hend) hold the other
+// heavy operations.
 struct DevLayer {
   uint32_t begin, end, b_base, n_bdst, hbeg, hend, hm0, hm1;
 };

@@ -558,15 +558,14 @@ __device__ __forceinline__ void heavy_operand(const SweepView& v, uint32_t f, ui
   }
 }
 
-// A fused mux chain for the TG tiles: the record's default in e, then the
-// further pairs from the word table, innermost first (a nonzero selector
-// replaces the running default with its value), then the first pair.
+// A fused mux chain for the TG tiles (values up to 4 limbs): the record's
+// default in e, then the further pairs from the word table, innermost first
+// (a nonzero selector replaces the running default with its value), then
+// the record's first pair.
 template <int TG>
 __device__ __forceinline__ void heavy_muxc(const SweepView& v, const DevOp& q,
                                            const uint64_t* __restrict__ words, V4 (&r)[TG]) {
-  V4 s1[TG], v1[TG], e[TG];
-  heavy_operand<TG>(v, q.src[0], op_scls(q.code, 0), s1);
-  heavy_operand<TG>(v, q.src[1], op_scls(q.code, 1), v1);
+  V4 e[TG];
   heavy_operand<TG>(v, q.src[2], op_scls(q.code, 2), e);
   for (uint32_t i = q.aux1; i-- > 0;) {
     const uint64_t es = words[q.aux0 + 2u * i], ev = words[q.aux0 + 2u * i + 1u];
@@ -577,6 +576,9 @@ __device__ __forceinline__ void heavy_muxc(const SweepView& v, const DevOp& q,
     for (int g = 0; g < TG; ++g)
       if (v4_nonzero(sv[g])) e[g] = vv[g];
   }
+  V4 s1[TG], v1[TG];
+  heavy_operand<TG>(v, q.src[0], op_scls(q.code, 0), s1);
+  heavy_operand<TG>(v, q.src[1], op_scls(q.code, 1), v1);
   const uint32_t w = op_width(q.wimm);
 #pragma unroll
   for (int g = 0; g < TG; ++g) r[g] = eval_wide(OP_MUXC, 3u, s1[g], v1[g], e[g], 0u, w);
@@ -651,8 +653,8 @@ __device__ __forceinline__ void heavy_muxc64(const SweepView& v, const DevOp& q,
   }
 }
 
-// The narrow mux chains of one layer, [hm0, hm1): each wavefront takes
-// ops_per_wave of them over the TG tiles of its tile group.
+// The fused mux chains of one layer, [hm0, hm1): each wavefront takes
+// ops_per_wave of them over TG tiles of its tile group.
 template <int TG>
 __global__ void __launch_bounds__(256)
 k_sweep_muxc(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
@@ -670,17 +672,28 @@ k_sweep_muxc(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
   for (uint32_t o = o0; o < o1; ++o) {
     const DevOp q = ops[o];
     V4 r[TG];
-    heavy_muxc64<TG>(v, q, words, r);
+    if (op_narrow_chain(q.code)) heavy_muxc64<TG>(v, q, words, r);
+    else heavy_muxc<TG>(v, q, words, r);
     const uint32_t dc = op_dcls(q.code);
     uint64_t x[TG];
     if (dc == CB) {
 #pragma unroll
       for (int g = 0; g < TG; ++g) x[g] = __ballot((r[g].l[0] & 1ull) != 0ull);
       v.st_bits<TG>(q.dst, x);
-    } else {
+    } else if (dc <= CD) {
 #pragma unroll
       for (int g = 0; g < TG; ++g) x[g] = r[g].l[0];
       v.st_dst<TG, true>(dc, q.dst, x);
+    } else {
+      const uint32_t kd = cls_limbs(dc);
+      char* d0 = v.at(q.dst, 0u, 0u) + lane * 8u;
+#pragma unroll
+      for (int l = 0; l < 4; ++l)
+        if ((uint32_t)l < kd) {
+#pragma unroll
+          for (int g = 0; g < TG; ++g)
+            *(uint64_t*)(d0 + (uint64_t)l * v.row_bytes + g * 512u) = r[g].l[l];
+        }
     }
   }
 }
@@ -702,7 +715,7 @@ k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   const uint32_t grp = wave % n_groups, chunk = wave / n_groups;
   const DevLayer ly = layers[layer];
-  // [hbeg, hm0) then [hm1, hend): the narrow mux chains between them have a
+  // [hbeg, hm0) then [hm1, hend): the fused mux chains between them have a
   // kernel of their own.
   const uint32_t split = (ly.hm0 - ly.hbeg + opw - 1) / opw;
   const uint32_t o0 = chunk < split ? ly.hbeg + chunk * opw : ly.hm1 + (chunk - split) * opw;
@@ -728,8 +741,6 @@ k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers
         if (inst < n_inst)
           r[g] = source_value(const_limbs, q, seeds[inst], cycle, ctl->words, words_row, w);
       }
-    } else if (opc == OP_MUXC) {  // a chain with a value wider than 64 bits
-      heavy_muxc<TG>(v, q, const_limbs, r);
     } else {
       uint64_t raw[3 * 4 * TG];
       uint32_t sh[3], kl[3];
@@ -1139,7 +1150,7 @@ hipError_t launch_sweep_heavy(const Program& p, const StateLayout& L, char* stat
     return hipErrorInvalidValue;
   const uint32_t n_chain = ly.hm1 - ly.hm0;
   if (n_chain) {
-    // Narrow mux chains: up to 4 tiles per wavefront (measured on a chain-heavy
+    // Fused mux chains: up to 4 tiles per wavefront (measured on a chain-heavy
     // design: 4 tiles beat 8, whose gathers need fewer pairs per batch, and 2).
     const uint32_t tg = tiles_per_wave >= 4 ? 4u : tiles_per_wave == 2 ? 2u : 1u;
     if (!pass_ok(L, tp, tg)) return hipErrorInvalidValue;

@@ -325,6 +325,27 @@ struct SweepView {
   }
   __device__ __forceinline__ uint32_t sh64(uint32_t w3) const { return (lane << (6u - w3)) & 63u; }
 
+  // The TG tiles' 64-bit words of 1-bit value f are 8 TG contiguous bytes:
+  // one load for the wavefront, lane i taking dword i mod 2 TG, instead of
+  // one load per tile (1-bit gathers are the smallest blocks, and the common
+  // kernel is bound by its load count more than by bytes).  bits_word32 and
+  // bits_word64 then hand out tile g's word (the dword of it each lane's
+  // per-tile 4-byte load would have read, or the whole word).
+  template <int TG>
+  __device__ __forceinline__ uint32_t bits_load(uint32_t f) const {
+    return *(const uint32_t*)(at(f, 6u, 0u) + 4u * (lane & (2u * TG - 1u)));
+  }
+  __device__ __forceinline__ uint32_t bits_word32(uint32_t x, int g) const {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)x, 2 * g);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)x, 2 * g + 1);
+    return lane & 32u ? hi : lo;
+  }
+  __device__ __forceinline__ uint64_t bits_word64(uint32_t x, int g) const {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)x, 2 * g);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)x, 2 * g + 1);
+    return ((uint64_t)hi << 32) | lo;
+  }
+
   // 1-bit results of the TG tiles (wave-uniform words): lane g stores tile g's
   // word, one contiguous store for the wavefront.  The word is picked with
   // masks rather than a select chain, which the compiler would turn into an
@@ -377,14 +398,29 @@ __device__ __forceinline__ void sweep_u32(const SweepView& v, const DevOp* op, u
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const uint32_t cls = op_scls(op[u].code, k), w3 = cls_w3(cls);
-      const char* p = v.at(op[u].src[k], w3, 0u) + v.off32(w3);
-      const uint32_t step = 512u >> w3;
       sh[u * NS + k] = v.sh32(w3);
       m[u * NS + k] = 0xffffffffu >> ((0x0010181Fu >> (8u * cls)) & 31u);
+      if (TG > 1 && cls == CB) {
+        raw[(u * NS + k) * TG] = v.bits_load<TG>(op[u].src[k]);
+      } else {
+        const char* p = v.at(op[u].src[k], w3, 0u) + v.off32(w3);
+        const uint32_t step = 512u >> w3;
 #pragma unroll
-      for (int g = 0; g < TG; ++g) raw[(u * NS + k) * TG + g] = *(const uint32_t*)(p + g * step);
+        for (int g = 0; g < TG; ++g) raw[(u * NS + k) * TG + g] = *(const uint32_t*)(p + g * step);
+      }
     }
   keep_loaded(raw);
+  if constexpr (TG > 1) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (op_scls(op[u].code, k) == CB) {
+          const uint32_t x = raw[(u * NS + k) * TG];
+#pragma unroll
+          for (int g = 0; g < TG; ++g) raw[(u * NS + k) * TG + g] = v.bits_word32(x, g);
+        }
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if ((uint32_t)u < n_valid) {
@@ -424,14 +460,29 @@ __device__ __forceinline__ void sweep_u64(const SweepView& v, const DevOp* op, u
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const uint32_t cls = op_scls(op[u].code, k), w3 = cls_w3(cls);
-      const char* p = v.at(op[u].src[k], w3, 0u) + v.off64(w3);
-      const uint32_t step = 512u >> w3;
       sh[u * NS + k] = v.sh64(w3);
       m[u * NS + k] = cls_mask64(cls);
+      if (TG > 1 && cls == CB) {
+        raw[(u * NS + k) * TG] = v.bits_load<TG>(op[u].src[k]);
+      } else {
+        const char* p = v.at(op[u].src[k], w3, 0u) + v.off64(w3);
+        const uint32_t step = 512u >> w3;
 #pragma unroll
-      for (int g = 0; g < TG; ++g) raw[(u * NS + k) * TG + g] = *(const uint64_t*)(p + g * step);
+        for (int g = 0; g < TG; ++g) raw[(u * NS + k) * TG + g] = *(const uint64_t*)(p + g * step);
+      }
     }
   keep_loaded(raw);
+  if constexpr (TG > 1) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (op_scls(op[u].code, k) == CB) {
+          const uint32_t x = (uint32_t)raw[(u * NS + k) * TG];
+#pragma unroll
+          for (int g = 0; g < TG; ++g) raw[(u * NS + k) * TG + g] = v.bits_word64(x, g);
+        }
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if ((uint32_t)u < n_valid) {
@@ -472,11 +523,23 @@ __device__ __forceinline__ void sweep_bit(const SweepView& v, const DevOp* op, u
   for (int u = 0; u < U; ++u)
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      const char* p = v.at(op[u].src[k], 6u, 0u);
-#pragma unroll
-      for (int g = 0; g < TG; ++g) raw[(u * 3 + k) * TG + g] = *(const uint64_t*)(p + g * 8u);
+      if constexpr (TG > 1) {
+        raw[(u * 3 + k) * TG] = v.bits_load<TG>(op[u].src[k]);
+      } else {
+        raw[(u * 3 + k) * TG] = *(const uint64_t*)v.at(op[u].src[k], 6u, 0u);
+      }
     }
   keep_loaded(raw);
+  if constexpr (TG > 1) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const uint32_t x = (uint32_t)raw[(u * 3 + k) * TG];
+#pragma unroll
+        for (int g = 0; g < TG; ++g) raw[(u * 3 + k) * TG + g] = v.bits_word64(x, g);
+      }
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if ((uint32_t)u < n_valid) {

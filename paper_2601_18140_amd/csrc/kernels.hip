@@ -387,9 +387,14 @@ __device__ __forceinline__ void keep_loaded(const T (&x)[N]) {
   for (int i = 0; i < N; ++i) asm volatile("" ::"v"(x[i]));
 }
 
+// B1: 1-bit operands take one load for the tile group (SweepView::bits_load).
+// The kernel sets it for one operation per lane and at least 4 tiles: with
+// more operations per lane, the class branch around each operand's loads
+// splits them into more waits than the saved loads return.
+
 // U operations whose classes all fit 32 bits: one 4-byte load per operand
 // and tile, the lane's element cut out with a shift and a mask.
-template <int U, int TG, int NS>
+template <int U, int TG, int NS, bool B1>
 __device__ __forceinline__ void sweep_u32(const SweepView& v, const DevOp* op, uint32_t n_valid) {
   uint32_t raw[U * NS * TG];
   uint32_t sh[U * NS], m[U * NS];
@@ -400,7 +405,7 @@ __device__ __forceinline__ void sweep_u32(const SweepView& v, const DevOp* op, u
       const uint32_t cls = op_scls(op[u].code, k), w3 = cls_w3(cls);
       sh[u * NS + k] = v.sh32(w3);
       m[u * NS + k] = 0xffffffffu >> ((0x0010181Fu >> (8u * cls)) & 31u);
-      if (TG > 1 && cls == CB) {
+      if (B1 && cls == CB) {
         raw[(u * NS + k) * TG] = v.bits_load<TG>(op[u].src[k]);
       } else {
         const char* p = v.at(op[u].src[k], w3, 0u) + v.off32(w3);
@@ -410,7 +415,7 @@ __device__ __forceinline__ void sweep_u32(const SweepView& v, const DevOp* op, u
       }
     }
   keep_loaded(raw);
-  if constexpr (TG > 1) {
+  if constexpr (B1) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -450,7 +455,7 @@ __device__ __forceinline__ void sweep_u32(const SweepView& v, const DevOp* op, u
 
 // U operations with a value of 33..64 bits: one 8-byte load per operand and
 // tile.
-template <int U, int TG, int NS>
+template <int U, int TG, int NS, bool B1>
 __device__ __forceinline__ void sweep_u64(const SweepView& v, const DevOp* op, uint32_t n_valid) {
   uint64_t raw[U * NS * TG];
   uint32_t sh[U * NS];
@@ -462,7 +467,7 @@ __device__ __forceinline__ void sweep_u64(const SweepView& v, const DevOp* op, u
       const uint32_t cls = op_scls(op[u].code, k), w3 = cls_w3(cls);
       sh[u * NS + k] = v.sh64(w3);
       m[u * NS + k] = cls_mask64(cls);
-      if (TG > 1 && cls == CB) {
+      if (B1 && cls == CB) {
         raw[(u * NS + k) * TG] = v.bits_load<TG>(op[u].src[k]);
       } else {
         const char* p = v.at(op[u].src[k], w3, 0u) + v.off64(w3);
@@ -472,7 +477,7 @@ __device__ __forceinline__ void sweep_u64(const SweepView& v, const DevOp* op, u
       }
     }
   keep_loaded(raw);
-  if constexpr (TG > 1) {
+  if constexpr (B1) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -512,7 +517,7 @@ __device__ __forceinline__ void sweep_u64(const SweepView& v, const DevOp* op, u
 
 // U operations on 1-bit values only: the tiles' bit-sliced words, the same
 // for every lane, evaluated word-wide.
-template <int U, int TG, int NS>
+template <int U, int TG, int NS, bool B1>
 __device__ __forceinline__ void sweep_bit(const SweepView& v, const DevOp* op, uint32_t n_valid) {
   uint64_t raw[U * 3 * TG];
 #pragma unroll
@@ -523,14 +528,16 @@ __device__ __forceinline__ void sweep_bit(const SweepView& v, const DevOp* op, u
   for (int u = 0; u < U; ++u)
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      if constexpr (TG > 1) {
+      if constexpr (B1) {
         raw[(u * 3 + k) * TG] = v.bits_load<TG>(op[u].src[k]);
       } else {
-        raw[(u * 3 + k) * TG] = *(const uint64_t*)v.at(op[u].src[k], 6u, 0u);
+        const char* p = v.at(op[u].src[k], 6u, 0u);
+#pragma unroll
+        for (int g = 0; g < TG; ++g) raw[(u * 3 + k) * TG + g] = *(const uint64_t*)(p + g * 8u);
       }
     }
   keep_loaded(raw);
-  if constexpr (TG > 1) {
+  if constexpr (B1) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -555,12 +562,12 @@ __device__ __forceinline__ void sweep_bit(const SweepView& v, const DevOp* op, u
   }
 }
 
-template <int U, int TG, int NS>
+template <int U, int TG, int NS, bool B1>
 __device__ __forceinline__ void sweep_group(const SweepView& v, const DevOp* op, uint32_t n_valid,
                                             uint32_t kind) {
-  if (kind == K_U32) sweep_u32<U, TG, NS>(v, op, n_valid);
-  else if (kind == K_U64) sweep_u64<U, TG, NS>(v, op, n_valid);
-  else sweep_bit<U, TG, NS>(v, op, n_valid);
+  if (kind == K_U32) sweep_u32<U, TG, NS, B1>(v, op, n_valid);
+  else if (kind == K_U64) sweep_u64<U, TG, NS, B1>(v, op, n_valid);
+  else sweep_bit<U, TG, NS, B1>(v, op, n_valid);
 }
 
 // The common operations (at most 64 bits, no source) of the ranges r with NS
@@ -573,6 +580,7 @@ template <int U, int TG, int NS>
 __global__ void __launch_bounds__(256)
 k_sweep(const DevOp* __restrict__ ops, StateLayout L, char* __restrict__ state, OpRanges r,
         uint32_t opw, uint32_t split, uint32_t tile_base, uint32_t n_groups) {
+  constexpr bool B1 = U == 1 && TG >= 4;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
@@ -594,11 +602,11 @@ k_sweep(const DevOp* __restrict__ ops, StateLayout L, char* __restrict__ state, 
 #pragma unroll
     for (int u = 1; u < U; ++u) same = same && ((uint32_t)u >= n_valid || op_kind(op[u].code) == k0);
     if (same) {
-      sweep_group<U, TG, NS>(v, op, n_valid, k0);
+      sweep_group<U, TG, NS, B1>(v, op, n_valid, k0);
     } else {
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if ((uint32_t)u < n_valid) sweep_group<1, TG, NS>(v, &op[u], 1u, op_kind(op[u].code));
+        if ((uint32_t)u < n_valid) sweep_group<1, TG, NS, B1>(v, &op[u], 1u, op_kind(op[u].code));
     }
   }
 }

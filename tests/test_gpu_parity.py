@@ -386,6 +386,35 @@ def test_fused_chains_sweep_shapes(ctx):
         assert_same(got, ref, f"tg={tg} opw={opw}")
 
 
+def test_step_many_with_fused_designs(ctx):
+    """Fused designs advanced by rteaal_step_many next to an unfused one: the
+    persistent multi-batch RESIDENT launch, SWEEP and LAYERED batches,
+    against the oracle of the designs before fusion."""
+    raw = [chain_design(5, 4_000), chain_design(6, 9_000), rtlgen.generate(SMALL[0], 8)]
+    designs = [R.rteaal_fuse_mux_chains(raw[0])[0], R.rteaal_fuse_mux_chains(raw[1], 5)[0], raw[2]]
+    plan = [(0, 4, R.RTEAAL_MAP_RESIDENT, 11), (1, 3, R.RTEAAL_MAP_RESIDENT, 7),
+            (0, 130, R.RTEAAL_MAP_SWEEP, 9), (1, 2, R.RTEAAL_MAP_LAYERED, 6),
+            (2, 5, R.RTEAAL_MAP_RESIDENT, 13), (1, 70, R.RTEAAL_MAP_SWEEP, 8)]
+    dids = [R.rteaal_load_design(ctx, d) for d in designs]
+    bids, seeds_of = [], []
+    try:
+        for k, (di, n, m, cyc) in enumerate(plan):
+            seeds_of.append(rtlgen.instance_seeds(n, design_index=k))
+            bids.append(R.rteaal_create_batch(ctx, dids[di], seeds_of[k], mapping=m))
+        note("step_many with fused designs")
+        R.rteaal_step_many(ctx, bids, [p[3] for p in plan])
+        for k, (di, n, m, cyc) in enumerate(plan):
+            d = designs[di]
+            got = R.unpack_limbs(R.rteaal_read_state(ctx, bids[k]), d.slot_width[d.reg_slot])
+            ref, _, _ = oracle.run(raw[di], seeds_of[k], cyc)
+            assert_same(got, ref, f"batch {k}")
+    finally:
+        for b in bids:
+            R.rteaal_free_batch(ctx, b)
+        for d in dids:
+            R.rteaal_unload_design(ctx, d)
+
+
 def test_fused_then_levelized(ctx):
     d = chain_design(2, 60_000)
     f, _ = R.rteaal_fuse_mux_chains(d)

@@ -37,9 +37,11 @@ def read_regs(ctx, bid, d, inst):
 
 def test_large_5m_batched_sampled(ctx):
     """5,000,000 ops, 120 layers, 4,096 instances: 32 sampled instances
-    ({0, 4095} plus 30 drawn with seed 11) after 3 cycles, in the tile-group
-    shape the bench measures and in the default shape; then the plain
-    single-instance form."""
+    ({0, 4095} plus 30 drawn with seed 11) after 3 cycles, in the two shapes
+    the bench's autotuner picks between (8 and 2 operations per wavefront,
+    8 tiles), an older shape with 2 operations per lane, and the default
+    shape; then the plain single-instance form, LAYERED (as the bench
+    measures it) and the default."""
     w = rtlgen.WORKLOADS["large-5m"]
     d = rtlgen.generate(w["cfg"], w["seed"])
     n = w["instances"]
@@ -50,7 +52,9 @@ def test_large_5m_batched_sampled(ctx):
     ref, _, _ = oracle.run(d, seeds[pick], cyc, n_threads=16)
     did = R.rteaal_load_design(ctx, d)
     try:
-        for shape in ({"ops_per_wave": 2, "unroll": 2, "tiles_per_wave": 4}, {}):
+        for shape in ({"ops_per_wave": 8, "unroll": 1, "tiles_per_wave": 8},
+                      {"ops_per_wave": 2, "unroll": 1, "tiles_per_wave": 8},
+                      {"ops_per_wave": 2, "unroll": 2, "tiles_per_wave": 4}, {}):
             note(f"large-5m batched {n} x {cyc} cycles, shape {shape}")
             bid = R.rteaal_create_batch(ctx, did, seeds, mapping=R.RTEAAL_MAP_SWEEP, **shape)
             try:
@@ -60,14 +64,42 @@ def test_large_5m_batched_sampled(ctx):
             finally:
                 R.rteaal_free_batch(ctx, bid)
             assert_same(got, ref, f"large-5m sample, shape {shape}")
-        note("large-5m plain 1 instance x 3 cycles")
-        bid = R.rteaal_create_batch(ctx, did, seeds[:1])
-        try:
-            R.rteaal_step(ctx, bid, cyc)
-            got = read_regs(ctx, bid, d, [0])
-        finally:
-            R.rteaal_free_batch(ctx, bid)
-        assert_same(got, ref[:1], "large-5m plain")
+        for opts in ({"mapping": R.RTEAAL_MAP_LAYERED, "block_threads": 64, "unroll": 1}, {}):
+            note(f"large-5m plain 1 instance x 3 cycles, {opts}")
+            bid = R.rteaal_create_batch(ctx, did, seeds[:1], **opts)
+            try:
+                R.rteaal_step(ctx, bid, cyc)
+                got = read_regs(ctx, bid, d, [0])
+            finally:
+                R.rteaal_free_batch(ctx, bid)
+            assert_same(got, ref[:1], f"large-5m plain {opts}")
+    finally:
+        R.rteaal_unload_design(ctx, did)
+
+
+def test_muxchain_2m_fused_sampled(ctx):
+    """muxchain-2m (2,000,000 ops, 4,096 instances) fused and levelized as the
+    bench runs it: 16 sampled instances after 3 cycles, against the oracle of
+    the design as drawn."""
+    d = rtlgen.generate(rtlgen.CFG_MUXCHAIN, 6)
+    f, cnt = R.rteaal_fuse_mux_chains(d)
+    lv = R.levelized_design(ctx, f)
+    n = 4096
+    seeds = rtlgen.instance_seeds(n)
+    rng = np.random.default_rng(12)
+    pick = sorted({0, n - 1} | set(rng.choice(np.arange(1, n - 1), 14, replace=False).tolist()))
+    ref, _, _ = oracle.run(d, seeds[pick], 3, n_threads=16)
+    did = R.rteaal_load_design(ctx, lv)
+    try:
+        for shape in ({"ops_per_wave": 2, "unroll": 1, "tiles_per_wave": 8}, {}):
+            note(f"muxchain-2m fused ({cnt['n_fused']} MUXC) {n} x 3 cycles, shape {shape}")
+            bid = R.rteaal_create_batch(ctx, did, seeds, mapping=R.RTEAAL_MAP_SWEEP, **shape)
+            try:
+                R.rteaal_step(ctx, bid, 3)
+                got = read_regs(ctx, bid, lv, pick)
+            finally:
+                R.rteaal_free_batch(ctx, bid)
+            assert_same(got, ref, f"muxchain-2m sample, shape {shape}")
     finally:
         R.rteaal_unload_design(ctx, did)
 

@@ -684,18 +684,25 @@ __device__ __forceinline__ void heavy_muxc64(const SweepView& v, const DevOp& q,
     uint64_t raw[2 * C][TG];
     uint32_t sh[2 * C];
     uint64_t m[2 * C];
+    const uint32_t nw = 2u * min((uint32_t)C, np - (uint32_t)c0);  // operands in this batch
 #pragma unroll
     for (int j = 0; j < 2 * C; ++j) {
-      // Past the chain's end the last real operand is read again (a valid
-      // address whose value the fold below skips).
-      const uint32_t i = min((uint32_t)(2 * c0 + j), 2u * np - 1u);
-      const uint64_t wd = words[q.aux0 + i];
-      const uint32_t cls = (uint32_t)(wd >> 32), w3 = cls_w3(cls), step = 512u >> w3;
-      const char* p = v.at((uint32_t)wd, w3, 0u) + v.off64(w3);
-      sh[j] = v.sh64(w3);
-      m[j] = cls_mask64(cls);
+      // Only the innermost batch can be partial; its missing pairs load
+      // nothing, and the fold below skips them.
+      sh[j] = 0u;
+      m[j] = 0ull;
+      if ((uint32_t)j < nw) {
+        const uint64_t wd = words[q.aux0 + 2u * (uint32_t)c0 + (uint32_t)j];
+        const uint32_t cls = (uint32_t)(wd >> 32), w3 = cls_w3(cls), step = 512u >> w3;
+        const char* p = v.at((uint32_t)wd, w3, 0u) + v.off64(w3);
+        sh[j] = v.sh64(w3);
+        m[j] = cls_mask64(cls);
 #pragma unroll
-      for (int g = 0; g < TG; ++g) raw[j][g] = *(const uint64_t*)(p + g * step);
+        for (int g = 0; g < TG; ++g) raw[j][g] = *(const uint64_t*)(p + g * step);
+      } else {
+#pragma unroll
+        for (int g = 0; g < TG; ++g) raw[j][g] = 0ull;
+      }
     }
     if (!cut) {
 #pragma unroll
@@ -740,8 +747,10 @@ k_sweep_muxc(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
   if (o0 >= ly.hm1) return;
   const uint32_t o1 = min(o0 + opw, ly.hm1);
   const SweepView v(state, L, tile_base + grp * TG, lane);
+  DevOp next = ops[o0];
   for (uint32_t o = o0; o < o1; ++o) {
-    const DevOp q = ops[o];
+    const DevOp q = next;
+    if (o + 1 < o1) next = ops[o + 1];  // the next record on its way meanwhile
     V4 r[TG];
     if (op_narrow_chain(q.code)) heavy_muxc64<TG>(v, q, words, r);
     else heavy_muxc<TG>(v, q, words, r);
@@ -1221,15 +1230,18 @@ hipError_t launch_sweep_heavy(const Program& p, const StateLayout& L, char* stat
     return hipErrorInvalidValue;
   const uint32_t n_chain = ly.hm1 - ly.hm0;
   if (n_chain) {
-    // Fused mux chains: up to 4 tiles per wavefront (measured on a chain-heavy
-    // design: 4 tiles beat 8, whose gathers need fewer pairs per batch, and 2).
+    // Fused mux chains: up to 4 tiles and one chain per wavefront.  Measured
+    // on a chain-heavy design (2M operations, 4,096 instances), per layer:
+    // 4 tiles 45.1 us, 8 tiles 53.7 (fewer pairs per batch), 2 tiles 50.0;
+    // 2 chains per wavefront 46.7, 4 chains 49.9.
     const uint32_t tg = tiles_per_wave >= 4 ? 4u : tiles_per_wave == 2 ? 2u : 1u;
+    const uint32_t opwm = 1u;
     if (!pass_ok(L, tp, tg)) return hipErrorInvalidValue;
-    const uint64_t waves = (uint64_t)((n_chain + ops_per_wave - 1) / ops_per_wave) * (tp.count / tg);
+    const uint64_t waves = (uint64_t)((n_chain + opwm - 1) / opwm) * (tp.count / tg);
     const dim3 grid((uint32_t)((waves + 3) / 4)), blk(256);
 #define RTEAAL_MUXC_K(GG)                                                                   \
   hipLaunchKernelGGL((k_sweep_muxc<GG>), grid, blk, 0, s, p.ops, p.layers, p.const_limbs,   \
-                     L, state, layer, ops_per_wave, tp.base, tp.count / tg)
+                     L, state, layer, opwm, tp.base, tp.count / tg)
     if (tg == 4) RTEAAL_MUXC_K(4);
     else if (tg == 2) RTEAAL_MUXC_K(2);
     else RTEAAL_MUXC_K(1);

@@ -203,3 +203,32 @@ def test_fuse_mux_chains_errors_and_muxc_arity(good):
         r = b2.reg(8)
         b2.connect(r, b2.op(rtlgen.MUXC, ins, 8))
         assert R.rteaal_validate_design(b2.build())[0] == 2
+
+
+def test_fuse_mux_chains_edge_designs():
+    """No operations; MUXes whose default is a register or an input (no link);
+    a chain whose head is latched by a register (the head stays, fused)."""
+    b = cir.Builder("empty")
+    r = b.reg(4)
+    b.connect(r, b.input(4))
+    d = b.build()
+    f, cnt = R.rteaal_fuse_mux_chains(d)
+    assert cnt == {"n_ops": 0, "n_operands": 0, "n_fused": 0, "n_absorbed": 0}
+    assert list(f.layer_ptr) == list(d.layer_ptr)
+    b = cir.Builder("sources")
+    s, x, y = b.input(1), b.input(8), b.reg(8)
+    m1 = b.op(rtlgen.MUX, [s, x, y], 8)
+    m2 = b.op(rtlgen.MUX, [s, x, b.input(8)], 8)
+    b.connect(y, b.op(rtlgen.XOR, [m1, m2], 8))
+    f, cnt = R.rteaal_fuse_mux_chains(b.build())
+    assert cnt["n_fused"] == 0 and cnt["n_absorbed"] == 0
+    b = cir.Builder("latched-head")
+    s1, s2, a, c, e = b.input(1), b.input(1), b.input(8), b.input(8), b.input(8)
+    inner = b.op(rtlgen.MUX, [s2, c, e], 8)
+    head = b.op(rtlgen.MUX, [s1, a, inner], 8)
+    r = b.reg(8)
+    b.connect(r, head)
+    f, cnt = R.rteaal_fuse_mux_chains(b.build())
+    assert cnt == {"n_ops": 1, "n_operands": 5, "n_fused": 1, "n_absorbed": 1}
+    assert int(f.op_type[0]) == rtlgen.MUXC and int(f.op_dst[0]) == head
+    assert [int(v) for v in f.op_src] == [s1, a, s2, c, e]

@@ -384,6 +384,16 @@ def test_fused_chains_sweep_shapes(ctx):
         got, _, _ = run_gpu(ctx, f, seeds, [2, 3], mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=tg,
                             ops_per_wave=opw, arity_split=asp, unroll=1)
         assert_same(got, ref, f"tg={tg} opw={opw}")
+    note("fused chains SWEEP, two tile passes of 8 tiles")
+    got, _, _ = run_gpu(ctx, f, seeds, [2, 3], mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=8,
+                        unroll=1, tiles_per_pass=8)
+    assert_same(got, ref, "tile passes")
+    for n in (1, 63, 65, 257):              # ragged last tile
+        s2 = rtlgen.instance_seeds(n, design_index=3)
+        ref2, _, _ = oracle.run(d, s2, 4)
+        note(f"fused chains SWEEP n_inst={n}")
+        got2, _, _ = run_gpu(ctx, f, s2, 4, mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=4, unroll=1)
+        assert_same(got2, ref2, f"n_inst={n}")
 
 
 def test_step_many_with_fused_designs(ctx):

@@ -298,7 +298,8 @@ typedef struct {
                               wavefront: 1, 2 or 4 (RESIDENT, LAYERED, SWEEP)   */
   uint32_t tiles_per_wave; /* 0 = default; SWEEP: 64-instance tiles one
                               wavefront evaluates per decoded operation: 1, 2,
-                              4 or 8, with unroll x tiles_per_wave <= 8        */
+                              4, 8 or 16, with unroll x tiles_per_wave <= 8
+                              (16 tiles: unroll 1)                             */
   uint32_t arity_split;    /* SWEEP: 0 = auto, 1 = never, 2 = always: run a
                               layer's common operations as one launch per
                               operand count (1, 2, 3), so absent operands cost

@@ -723,8 +723,8 @@ bool make_layout(const DesignHost& h, uint32_t mapping, uint32_t n_inst, uint32_
   StateLayout L{};
   L.n_rows = (uint32_t)h.n_rows;
   if (mapping == RTEAAL_MAP_SWEEP) {
-    tg = (tg == 2 || tg == 4 || tg == 8) ? tg : 1u;
-    L.lg = tg == 8 ? 3u : tg == 4 ? 2u : tg == 2 ? 1u : 0u;
+    tg = (tg == 2 || tg == 4 || tg == 8 || tg == 16) ? tg : 1u;
+    L.lg = tg == 16 ? 4u : tg == 8 ? 3u : tg == 4 ? 2u : tg == 2 ? 1u : 0u;
     L.n_tiles = (n_inst + 63) / 64;
     L.n_tiles_alloc = (L.n_tiles + tg - 1) / tg * tg;
     if ((uint64_t)L.n_tiles_alloc * 512 >= (1ull << 32)) return false;
@@ -1410,10 +1410,11 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
       return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP unroll must be 1, 2 or 4");
     b->unroll = u;
     const uint32_t tg = opts && opts->tiles_per_wave ? opts->tiles_per_wave : 1u;
-    if (tg != 1 && tg != 2 && tg != 4 && tg != 8)
-      return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP tiles_per_wave must be 1, 2, 4 or 8");
-    if (tg * u > 8)
-      return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP unroll x tiles_per_wave must be at most 8");
+    if (tg != 1 && tg != 2 && tg != 4 && tg != 8 && tg != 16)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP tiles_per_wave must be 1, 2, 4, 8 or 16");
+    if (tg * u > 8 && !(tg == 16 && u == 1))
+      return fail(ctx, RTEAAL_E_INVALID_ARG,
+                  "SWEEP unroll x tiles_per_wave must be at most 8 (16 tiles: unroll 1)");
     b->tg = tg;
     const uint32_t as = opts ? opts->arity_split : 0u;
     if (as > 2) return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP arity_split must be 0, 1 or 2");
@@ -1834,11 +1835,12 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
       for (uint32_t u : {1u, 2u})
         cand.push_back(rteaal_batch_opts{RTEAAL_MAP_LAYERED, blk, 0, 0, 0, u, 0});
   const uint32_t n_tiles = (n_inst + 63) / 64;
-  for (uint32_t tg : {1u, 2u, 4u, 8u}) {
+  for (uint32_t tg : {1u, 2u, 4u, 8u, 16u}) {
     if (tg > 1 && tg > n_tiles) continue;
     for (uint32_t opw : {2u, 4u, 8u, 16u, 32u})
       for (uint32_t u : {1u, 2u, 4u})
-        if (u * tg <= 8) cand.push_back(rteaal_batch_opts{RTEAAL_MAP_SWEEP, 0, opw, 0, 0, u, tg});
+        if (u * tg <= 8 || (tg == 16 && u == 1))
+          cand.push_back(rteaal_batch_opts{RTEAAL_MAP_SWEEP, 0, opw, 0, 0, u, tg});
   }
   std::vector<uint64_t> seeds(n_inst);
   for (uint32_t i = 0; i < n_inst; ++i) seeds[i] = i;

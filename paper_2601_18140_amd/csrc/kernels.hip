@@ -1187,8 +1187,8 @@ hipError_t launch_sweep_light(const Program& p, const StateLayout& L, char* stat
                               hipStream_t s) {
   const uint32_t n1 = r.e0 - r.b0, n2 = r.e1 - r.b1;
   if (n1 + n2 == 0) return hipSuccess;
-  const uint32_t tg = tiles_per_wave == 8 ? 8u : tiles_per_wave == 4 ? 4u
-                    : tiles_per_wave == 2 ? 2u : 1u;
+  const uint32_t tg = tiles_per_wave == 16 ? 16u : tiles_per_wave == 8 ? 8u
+                    : tiles_per_wave == 4 ? 4u : tiles_per_wave == 2 ? 2u : 1u;
   if (ops_per_wave == 0 || n_src < 1 || n_src > 3 || !pass_ok(L, tp, tg))
     return hipErrorInvalidValue;
   const uint32_t split = (n1 + ops_per_wave - 1) / ops_per_wave;
@@ -1214,6 +1214,7 @@ hipError_t launch_sweep_light(const Program& p, const StateLayout& L, char* stat
     case 32 + 1: RTEAAL_SWEEP_N(1, 4) break;
     case 32 + 2: RTEAAL_SWEEP_N(2, 4) break;
     case 64 + 1: RTEAAL_SWEEP_N(1, 8) break;
+    case 128 + 1: RTEAAL_SWEEP_N(1, 16) break;
     default: RTEAAL_SWEEP_N(2, 1) break;
   }
 #undef RTEAAL_SWEEP_N

@@ -119,7 +119,8 @@ def test_resident_hbm_state_and_block_sizes(ctx, mapping):
             assert_same(regs, ref, f"ops_per_wave={opw}")
 
 
-SWEEP_SHAPES = [(1, 1), (2, 1), (4, 1), (1, 2), (2, 2), (4, 2), (1, 4), (2, 4), (1, 8)]  # (unroll, tiles_per_wave)
+SWEEP_SHAPES = [(1, 1), (2, 1), (4, 1), (1, 2), (2, 2), (4, 2), (1, 4), (2, 4), (1, 8),
+                (1, 16)]  # (unroll, tiles_per_wave)
 
 
 @pytest.mark.parametrize("cfg", SMALL[:2], ids=[c.name for c in SMALL[:2]])
@@ -379,7 +380,7 @@ def test_fused_chains_sweep_shapes(ctx):
     f, _ = R.rteaal_fuse_mux_chains(d)
     seeds = rtlgen.instance_seeds(600)
     ref, _, _ = oracle.run(d, seeds, 5)
-    for tg, opw, asp in ((1, 1, 1), (2, 3, 2), (4, 2, 1), (8, 1, 2), (8, 5, 1)):
+    for tg, opw, asp in ((1, 1, 1), (2, 3, 2), (4, 2, 1), (8, 1, 2), (8, 5, 1), (16, 4, 1), (16, 2, 2)):
         note(f"fused chains SWEEP tg={tg} opw={opw} arity_split={asp}")
         got, _, _ = run_gpu(ctx, f, seeds, [2, 3], mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=tg,
                             ops_per_wave=opw, arity_split=asp, unroll=1)

@@ -438,8 +438,9 @@ rteaal_status rteaal_read_changes(rteaal_ctx* ctx, rteaal_batch_id batch, rteaal
                                   uint64_t max, uint64_t* n_out, uint64_t* n_dropped);
 
 /* Autotuner: picks the mapping and launch shape for n_instances of `design`
- * on this device.  Each candidate (RESIDENT block sizes and unroll depths,
- * SWEEP operations per wavefront, unroll depths and tile groups) runs `trial_cycles`
+ * on this device.  Each candidate (RESIDENT block sizes and unroll depths;
+ * LAYERED block sizes and unroll depths up to 16 instances; SWEEP operations
+ * per wavefront, unroll depths and tile groups of 1-16 tiles) runs `trial_cycles`
  * cycles (0 = a size-dependent default) on a temporary batch and is timed
  * with HIP events on the context's stream; candidates whose state does not
  * fit in device memory are skipped.  The fastest options are written to

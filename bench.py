@@ -10,6 +10,12 @@ A step is one rteaal_step of `cycles_per_step` cycles over the whole batch;
 inputs (design, state, seeds) are resident on the device before timing.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME]
+
+Workloads: large-5m (default; 5M operations, 4,096 instances), single-200k,
+plain-2k, multi-64 (64 uneven designs in one rteaal_step_many), serving
+(continuous batching of a Poisson job stream), levelize-5m (the device
+levelizer on the shuffled large-5m graph), waveform (value-change capture),
+muxchain-2m (the same mux-heavy design as drawn and after mux-chain fusion).
 """
 import argparse
 import hashlib

@@ -169,6 +169,10 @@ def test_sweep_rejects_oversized_shape(ctx):
         with pytest.raises(R.RteaalError):
             R.rteaal_create_batch(ctx, did, np.arange(300, dtype=np.uint64),
                                   mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=2, tiles_per_pass=3)
+        for tg, u in ((16, 2), (32, 1), (3, 1)):   # 16 tiles only with unroll 1; no other sizes
+            with pytest.raises(R.RteaalError):
+                R.rteaal_create_batch(ctx, did, np.arange(70, dtype=np.uint64),
+                                      mapping=R.RTEAAL_MAP_SWEEP, unroll=u, tiles_per_wave=tg)
     finally:
         R.rteaal_unload_design(ctx, did)
 
@@ -184,6 +188,8 @@ def test_batch_options_round_trip(ctx):
                       (200, {"mapping": R.RTEAAL_MAP_SWEEP}),
                       (300, {"mapping": R.RTEAAL_MAP_SWEEP, "tiles_per_wave": 2, "unroll": 2,
                              "ops_per_wave": 3, "arity_split": 2, "tiles_per_pass": 2}),
+                      (1100, {"mapping": R.RTEAAL_MAP_SWEEP, "tiles_per_wave": 16, "unroll": 1,
+                              "ops_per_wave": 4, "tiles_per_pass": 16}),
                       (5, {"mapping": R.RTEAAL_MAP_LAYERED, "unroll": 4, "block_threads": 192})]:
             seeds = np.arange(n, dtype=np.uint64)
             b1 = R.rteaal_create_batch(ctx, did, seeds, **kw)

@@ -40,3 +40,14 @@ def test_algorithmic_bytes_by_hand():
     # the storage encoding moves 1 byte for each 8-bit value instead of 4
     ae = bench.algorithmic_bytes(d, bench.eb)
     assert ae["x_light"] == 3 + 3.125 + 2
+
+
+def test_more_than_one_gpu_is_refused():
+    """bench.py runs on one GPU; --gpus N > 1 exits with a message, before
+    touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr

@@ -432,6 +432,21 @@ def test_step_many_with_fused_designs(ctx):
             R.rteaal_unload_design(ctx, d)
 
 
+@pytest.mark.parametrize("mapping", MAPS, ids=MAP_IDS)
+def test_priority_encoder_muxc(ctx, mapping):
+    """A 16-input priority encoder as one MUXC (constants as values): the
+    register after each cycle is the lowest set input bit's index, as the
+    oracle computes it; also as the MUX chain fused by the library."""
+    from tests.test_oracle_fuse import priority_encoder
+    seeds = np.arange(300, dtype=np.uint64)
+    for as_chain in (False, True):
+        d, _ = priority_encoder(as_chain=as_chain)
+        ref, _, _ = oracle.run(d, seeds, 5)
+        run_d = R.rteaal_fuse_mux_chains(d)[0] if as_chain else d
+        got, _, _ = run_gpu(ctx, run_d, seeds, [2, 3], mapping=mapping)
+        assert_same(got, ref, f"priority encoder as_chain={as_chain}")
+
+
 def test_fused_then_levelized(ctx):
     d = chain_design(2, 60_000)
     f, _ = R.rteaal_fuse_mux_chains(d)

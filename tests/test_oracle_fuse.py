@@ -169,3 +169,41 @@ def test_interpreter_agrees_on_a_fused_design():
     ref = simulate(f, 5, 4)
     got = [rtlgen.limbs_to_int(slots[0, k]) for k in range(f.n_slots)]
     assert got == ref
+
+
+def priority_encoder(n=16, as_chain=False):
+    """out = index of the lowest set bit among n 1-bit inputs, else 31; as one
+    MUXC, or as the nested MUX chain that fusion turns into it."""
+    b = cir.Builder("prio")
+    bits = [b.input(1) for _ in range(n)]
+    idx = [b.const(5, i) for i in range(n)]
+    none = b.const(5, 31)
+    if as_chain:
+        out = none
+        for i in reversed(range(n)):
+            out = b.op(MUX, [bits[i], idx[i], out], 5)
+    else:
+        srcs = []
+        for i in range(n):
+            srcs += [bits[i], idx[i]]
+        out = b.op(MUXC, srcs + [none], 5)
+    r = b.reg(5)
+    b.connect(r, out)
+    return b.build(), bits
+
+
+def test_priority_encoder_closed_form():
+    """The register after one cycle is the lowest set input bit's index (31
+    when none is set), from the stimulus words themselves."""
+    seeds = np.arange(200, dtype=np.uint64)
+    for as_chain in (False, True):
+        d, bits = priority_encoder(as_chain=as_chain)
+        if as_chain:
+            f, n_fused, n_abs = oracle.fuse_mux_chains(d)
+            assert n_fused == 1 and n_abs == 15
+            m, _ = priority_encoder()
+            assert [int(x) for x in f.op_src] == [int(x) for x in m.op_src]
+        regs, _, _ = oracle.run(d, seeds, 1)
+        for j, sd in enumerate(seeds):
+            on = [k for k in range(16) if oracle.stim(int(sd), 0, k, 0) & 1]
+            assert int(regs[j, 0, 0]) == (on[0] if on else 31)

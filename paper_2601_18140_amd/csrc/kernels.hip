@@ -779,10 +779,11 @@ k_sweep_muxc(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
 }
 
 // The heavy operations of one layer (a value wider than 64 bits, a type run
-// in the wide form, or a source) outside the narrow mux chains.  Limb 0 of every operand is gathered without branches (an 8-byte
-// load per tile holding the lane's element, cut out as in the common
-// kernel); the further limbs of wide operands follow under a uniform branch.
-// All loads of an operation are in flight before the first is used.
+// in the wide form, or a source) other than the fused mux chains.  Limb 0 of
+// every operand is gathered without branches (an 8-byte load per tile holding
+// the lane's element, cut out as in the common kernel); the further limbs of
+// wide operands follow under a uniform branch.  All loads of an operation are
+// in flight before the first is used.
 template <int TG>
 __global__ void __launch_bounds__(256)
 k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,

@@ -207,3 +207,30 @@ def test_priority_encoder_closed_form():
         for j, sd in enumerate(seeds):
             on = [k for k in range(16) if oracle.stim(int(sd), 0, k, 0) & 1]
             assert int(regs[j, 0, 0]) == (on[0] if on else 31)
+
+
+def test_fused_then_levelized_keeps_values():
+    """Fusion, then the oracle levelizer's layering of the fused graph: no
+    more layers than before (a fused operation reads only what its absorbed
+    MUXes read), every operation after its producers, and the same register
+    values as the design as drawn."""
+    cfg = rtlgen.GenConfig(6_000, 20, 200, 8, rtlgen.generator.WIDTHS_LARGE, "fl", mux_chain=0.9)
+    d = rtlgen.generate(cfg, 9)
+    f, n_fused, _ = oracle.fuse_mux_chains(d)
+    assert n_fused > 50
+    layer = oracle.levelize(f.n_slots, f.op_src_ptr, f.op_src, f.op_dst)
+    order, lptr = oracle.layer_order(layer)
+    assert len(lptr) - 1 <= d.n_layers
+    o = np.asarray(order, np.int64)
+    ptr = f.op_src_ptr.astype(np.int64)
+    lens = np.diff(ptr)[o]
+    new_ptr = np.concatenate([[0], np.cumsum(lens)])
+    src = np.concatenate([f.op_src[ptr[k]:ptr[k + 1]] for k in o])
+    lv = rtlgen.Design(name="fl-lv", slot_width=f.slot_width, const_slot=f.const_slot,
+                       const_limbs=f.const_limbs, input_slot=f.input_slot, reg_slot=f.reg_slot,
+                       reg_next=f.reg_next, layer_ptr=lptr, op_type=f.op_type[o],
+                       op_dst=f.op_dst[o], op_src_ptr=new_ptr, op_src=src, op_imm=f.op_imm[o])
+    seeds = rtlgen.instance_seeds(12)
+    r0, _, _ = oracle.run(d, seeds, 4)
+    r1, _, _ = oracle.run(lv, seeds, 4)
+    assert np.array_equal(r0, r1)

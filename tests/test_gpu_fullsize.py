@@ -39,7 +39,7 @@ def test_large_5m_batched_sampled(ctx):
     """5,000,000 ops, 120 layers, 4,096 instances: 32 sampled instances
     ({0, 4095} plus 30 drawn with seed 11) after 3 cycles, in the two shapes
     the bench's autotuner picks between (8 and 2 operations per wavefront
-    with 8 tiles, 4 with 16), an older shape with 2 operations per lane, and the default
+    with 8 tiles, 4 and 8 with 16), an older shape with 2 operations per lane, and the default
     shape; then the plain single-instance form, LAYERED (as the bench
     measures it) and the default."""
     w = rtlgen.WORKLOADS["large-5m"]
@@ -55,6 +55,7 @@ def test_large_5m_batched_sampled(ctx):
         for shape in ({"ops_per_wave": 8, "unroll": 1, "tiles_per_wave": 8},
                       {"ops_per_wave": 2, "unroll": 1, "tiles_per_wave": 8},
                       {"ops_per_wave": 4, "unroll": 1, "tiles_per_wave": 16},
+                      {"ops_per_wave": 8, "unroll": 1, "tiles_per_wave": 16},
                       {"ops_per_wave": 2, "unroll": 2, "tiles_per_wave": 4}, {}):
             note(f"large-5m batched {n} x {cyc} cycles, shape {shape}")
             bid = R.rteaal_create_batch(ctx, did, seeds, mapping=R.RTEAAL_MAP_SWEEP, **shape)

@@ -232,3 +232,26 @@ def test_fuse_mux_chains_edge_designs():
     assert cnt == {"n_ops": 1, "n_operands": 5, "n_fused": 1, "n_absorbed": 1}
     assert int(f.op_type[0]) == rtlgen.MUXC and int(f.op_dst[0]) == head
     assert [int(v) for v in f.op_src] == [s1, a, s2, c, e]
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/rteaal.h is a C header: it compiles as C99 with -pedantic and
+    declares every exported entry point."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text('#include "rteaal.h"\n'
+                   "int main(void) {\n"
+                   "  rteaal_fuse_result r; rteaal_batch_opts o; rteaal_change c;\n"
+                   "  rteaal_status (*fuse)(const rteaal_design_desc*, uint32_t, uint32_t*, uint8_t*,\n"
+                   "                        uint32_t*, uint32_t*, uint32_t*, uint16_t*,\n"
+                   "                        rteaal_fuse_result*) = rteaal_fuse_mux_chains;\n"
+                   "  (void)r; (void)o; (void)c; (void)fuse;\n"
+                   "  return RTEAAL_MUXC == 22 && RTEAAL_MUXC_MAX_PAIRS == 32 ? 0 : 1;\n"
+                   "}\n")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-pedantic", "-fsyntax-only",
+                        "-I", os.path.dirname(HEADER), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr

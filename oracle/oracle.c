@@ -290,6 +290,7 @@ static void run_instance(const job* jb, uint32_t inst, val* LI, val* LO, val* nx
       LI[d->reg_slot[j]] = v_mask(v, d->slot_width[d->reg_slot[j]]);
     }
 
+  uint64_t digest = a->init_digest ? a->init_digest[inst] : 0;
   for (uint64_t t = 0; t < a->n_cycles; t++) {
     uint64_t cycle = a->start_cycle + t;
     /* Host/testbench writes the primary inputs into LI for this cycle. */
@@ -335,7 +336,18 @@ static void run_instance(const job* jb, uint32_t inst, val* LI, val* LO, val* nx
       LI[d->reg_slot[j]] = v_mask(nxt[j], d->slot_width[d->reg_slot[j]]);
     if (a->trace && a->trace_reg >= 0)
       a->trace[(size_t)inst * a->n_cycles + t] = LI[d->reg_slot[a->trace_reg]].l[0];
+    /* Register digest of this cycle, after the commit (see oracle.h). */
+    uint64_t h = 0;
+    for (uint32_t j = 0; j < d->n_regs; j++) {
+      const val* r = &LI[d->reg_slot[j]];
+      int nl = limbs_of(d->slot_width[d->reg_slot[j]]);
+      for (int l = 0; l < nl; l++)
+        h += splitmix64(splitmix64(((uint64_t)j << 2) | (uint64_t)l) ^ r->l[l]);
+    }
+    digest = splitmix64(digest ^ h);
+    if (a->digest_trace) a->digest_trace[(size_t)inst * a->n_cycles + t] = digest;
   }
+  if (a->out_digest) a->out_digest[inst] = digest;
 
   for (uint32_t j = 0; j < d->n_regs; j++)
     memcpy(a->out_regs + ((size_t)inst * d->n_regs + j) * 4, LI[d->reg_slot[j]].l, sizeof(val));
@@ -378,7 +390,7 @@ static int check_design(const oracle_design* d) {
 int oracle_run(const oracle_design* d, const oracle_run_args* a) {
   int rc = check_design(d);
   if (rc) return rc;
-  if (!a->out_regs || (a->n_inst && !a->seeds && a->stim_mode == 0)) return -1;
+  if ((!a->out_regs && d->n_regs) || (a->n_inst && !a->seeds && a->stim_mode == 0)) return -1;
   if (a->stim_mode == 1 && !a->stim_words && d->n_inputs) return -1;
   if (a->trace_reg >= (int32_t)d->n_regs) return -1;
   uint32_t mx = 0, words = 0;

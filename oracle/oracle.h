@@ -58,7 +58,19 @@ typedef struct {
   int32_t  trace_reg;         /* -1, or a register index traced below */
   uint64_t* trace;            /* [n_inst][n_cycles]: limb 0 of that register after each cycle */
   int32_t  n_threads;
+  const uint64_t* init_digest;  /* NULL (0) or [n_inst]: digest before the first cycle */
+  uint64_t* out_digest;         /* NULL or [n_inst]: digest after the last cycle */
+  uint64_t* digest_trace;       /* NULL or [n_inst][n_cycles]: digest after each cycle */
 } oracle_run_args;
+
+/* Per-instance register digest (a reading of what "state" is compared: the
+ * paper commits the registers once per cycle, Cascade 2's cycle rank C).
+ * It starts at 0; after every cycle's register commit, with v[j][l] limb l
+ * of register j (l < ceil(width/64)) and s the SplitMix64 output function,
+ *   h = sum over j, l of s(s(4 j + l) ^ v[j][l])   (mod 2^64)
+ *   D = s(D ^ h).
+ * The sum makes h independent of the order registers are visited in; the
+ * outer s makes D depend on every cycle's register vector, in order. */
 
 /* Returns 0, or a negative code if an index is out of range. */
 int oracle_run(const oracle_design* d, const oracle_run_args* a);

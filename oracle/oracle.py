@@ -50,6 +50,7 @@ class _Args(C.Structure):
         ("stim_mode", C.c_int32), ("stim_words", C.c_void_p),
         ("init_regs", C.c_void_p), ("out_regs", C.c_void_p), ("out_slots", C.c_void_p),
         ("trace_reg", C.c_int32), ("trace", C.c_void_p), ("n_threads", C.c_int32),
+        ("init_digest", C.c_void_p), ("out_digest", C.c_void_p), ("digest_trace", C.c_void_p),
     ]
 
 
@@ -79,10 +80,15 @@ def _ptr(a):
 
 
 def run(design, seeds, n_cycles, *, start_cycle=0, stim_words=None, init_regs=None,
-        want_slots=False, trace_reg=-1, n_threads=None):
+        want_slots=False, trace_reg=-1, n_threads=None, init_digest=None, digests=None,
+        digest_trace=False):
     """Simulate `len(seeds)` instances for `n_cycles` cycles.
 
-    Returns (regs[n_inst, n_regs, 4], slots or None, trace or None).
+    Returns (regs[n_inst, n_regs, 4], slots or None, trace or None).  With
+    `digests` (a dict), digests["final"] receives the register digest of
+    every instance after the last cycle ([n_inst] uint64) and, with
+    digest_trace, digests["trace"] the digest after every cycle
+    ([n_inst, n_cycles]); init_digest ([n_inst]) continues a digest chain.
     """
     lib = _load()
     keep = []
@@ -135,9 +141,21 @@ def run(design, seeds, n_cycles, *, start_cycle=0, stim_words=None, init_regs=No
     a.trace_reg = int(trace_reg)
     a.trace = _ptr(trace) if trace is not None else None
     a.n_threads = int(n_threads or min(os.cpu_count() or 1, max(n_inst, 1)))
+    a.init_digest = _ptr(arr(init_digest, np.uint64)) if init_digest is not None else None
+    out_digest = dtrace = None
+    if digests is not None:
+        out_digest = np.zeros(n_inst, np.uint64)
+        a.out_digest = _ptr(out_digest)
+        if digest_trace:
+            dtrace = np.zeros((n_inst, int(n_cycles)), np.uint64)
+            a.digest_trace = _ptr(dtrace)
     rc = lib.oracle_run(C.byref(d), C.byref(a))
     if rc != 0:
         raise ValueError(f"oracle_run failed with code {rc}")
+    if digests is not None:
+        digests["final"] = out_digest
+        if digest_trace:
+            digests["trace"] = dtrace
     return out_regs, out_slots, trace
 
 

@@ -85,8 +85,21 @@ def stim_value(seed, cycle, k, w):
     return v % (1 << w)
 
 
-def simulate(d, seed, n_cycles, start_cycle=0):
-    """All slot values (Python ints) of one instance after n_cycles."""
+def digest_step(prev, reg_values, reg_widths):
+    """One cycle of the per-instance register digest, on Python ints: the sum
+    over registers j and their 64-bit limbs l of s(s(4 j + l) ^ limb), mod
+    2^64, then s(prev ^ sum); s is the SplitMix64 output function above."""
+    h = 0
+    for j, (v, w) in enumerate(zip(reg_values, reg_widths)):
+        for l in range((int(w) + 63) // 64):
+            h += splitmix64(splitmix64(4 * j + l) ^ ((int(v) >> (64 * l)) & M64))
+    return splitmix64(prev ^ (h & M64))
+
+
+def simulate(d, seed, n_cycles, start_cycle=0, on_cycle=None):
+    """All slot values (Python ints) of one instance after n_cycles.
+    on_cycle(t, values), if given, sees the slot values after each cycle's
+    register commit."""
     W = [int(x) for x in d.slot_width]
     V = [0] * d.n_slots
     for c, s in enumerate(d.const_slot):
@@ -107,4 +120,6 @@ def simulate(d, seed, n_cycles, start_cycle=0):
         nxt = [V[int(s)] for s in d.reg_next]
         for j, s in enumerate(d.reg_slot):
             V[int(s)] = nxt[j] % (1 << W[int(s)])
+        if on_cycle is not None:
+            on_cycle(t, V)
     return V

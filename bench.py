@@ -41,9 +41,12 @@ LDS_PEAK_GBS = 256 * 128 * 2.4        # 256 CUs x 128 B/clk x 2.4 GHz = 78,643 G
 # and default number of timed steps (a bounded sample of the workload's run:
 # the rate is steady from the first cycles on).
 WORKLOADS = {
-    "large-5m": dict(cfg=rtlgen.CFG3, seed=3, instances=4096, cycles_per_step=20, steps=10),
-    "single-200k": dict(cfg=rtlgen.CFG1, seed=1, instances=1024, cycles_per_step=1000, steps=10),
-    "plain-2k": dict(cfg=rtlgen.CFG0, seed=0, instances=1, cycles_per_step=10_000, steps=1),
+    "large-5m": dict(cfg=rtlgen.CFG3, seed=3, instances=4096, cycles=10_000, cycles_per_step=5,
+                     steps=10, profile_cycles=10, plain_cycles=200),
+    "single-200k": dict(cfg=rtlgen.CFG1, seed=1, instances=1024, cycles=100_000,
+                        cycles_per_step=100, steps=10, profile_cycles=50, plain_cycles=2000),
+    "plain-2k": dict(cfg=rtlgen.CFG0, seed=0, instances=1, cycles=10_000, cycles_per_step=10_000,
+                     steps=1, profile_cycles=1024, plain_cycles=10_000),
 }
 
 
@@ -150,88 +153,422 @@ def measured_traffic(role, workload, opts):
     return float(rec["bytes_per_launch"])
 
 
-def cpu_baseline(d, seeds, cycles):
+def timed_runs(torch, stream, run, repeats):
+    """Milliseconds of `repeats` timed regions, each bracketed by a device
+    synchronisation and HIP events on the library's stream."""
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        run()
+        ev1.record(stream)
+        ev1.synchronize()
+        torch.cuda.synchronize()
+        out.append(ev0.elapsed_time(ev1))
+    return out
+
+
+def start_oracle(d, seeds, cycles, threads=None):
+    """The oracle (registers and register digest) on a background thread:
+    its C code releases the interpreter lock, so the GPU work goes on."""
+    import threading
     import oracle
-    threads = min(16, os.cpu_count() or 1, len(seeds))
+    res = {}
+
+    def go():
+        t0 = time.perf_counter()
+        dg = {}
+        res["regs"], _, _ = oracle.run(d, seeds, cycles, n_threads=threads or len(seeds), digests=dg)
+        res["digest"] = dg["final"]
+        res["seconds"] = time.perf_counter() - t0
+
+    th = threading.Thread(target=go, daemon=True)
+    th.start()
+    return th, res
+
+
+def host_threads():
+    """Host threads the oracle may use: the machine's CPU share for one GPU (16)
+    or fewer when fewer CPUs are visible."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def cpu_baseline(d, seeds, cycles, full_instances, full_cycles):
+    """The oracle timed on the host cores on a bounded sample (instance-
+    parallel: one instance per thread), with the per-core rate and the
+    full workload's oracle time extrapolated from it."""
+    import oracle
+    threads = min(host_threads(), len(seeds))
     t0 = time.perf_counter()
     oracle.run(d, seeds, cycles, n_threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": len(seeds) * cycles / dt, "unit": "instance-cycles/s", "cores": threads,
-            "kind": "oracle",
+    rate = len(seeds) * cycles / dt
+    return {"value": rate, "unit": "instance-cycles/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(seeds)} instances x {cycles} cycles of the same design, "
-                      f"{dt:.1f} s wall on {threads} host threads"}
+                      f"{dt:.1f} s wall on {threads} host threads",
+            "per_core": rate / threads, "host_cpus_visible": os.cpu_count(),
+            "extrapolated_full_workload": {
+                "instances": full_instances, "cycles": full_cycles,
+                "seconds": round(full_instances * full_cycles / rate, 1),
+                "label": f"extrapolation: the sample's rate on {threads} cores (instance-parallel, "
+                         "so it holds for any batch of at least that many instances)"}}
 
 
-def parity_sample(R, ctx, did, d, seeds, opts, cycles=3):
-    """A batch in the measured launch shape (`opts`, as the measured batch
-    resolved it), a few cycles from reset, four instances against the
-    oracle; only those instances are read back."""
+def whole_cycle(AB, ABE, n_inst, ms_per_cycle, counter_bytes_per_cycle):
+    """Graded fraction of one cycle: the method's compulsory bytes of a
+    cycle (n_inst * X + G) over 8 TB/s, divided by the measured time per
+    cycle; word model, storage encoding and (when counter records exist)
+    the measured HBM bytes."""
+    t = ms_per_cycle / 1e3
+    word = AB["x"] * n_inst + AB["g"]
+    enc = ABE["x"] * n_inst + ABE["g"]
+    out = {"ms_per_cycle": round(ms_per_cycle, 4),
+           "word_model_bytes": round(word, 1), "word_model_GBps": round(word / t / 1e9, 2),
+           "word_model_frac": round(word / t / 1e9 / HBM_PEAK_GBS, 4),
+           "encoded_bytes": round(enc, 1), "encoded_GBps": round(enc / t / 1e9, 2),
+           "encoded_frac": round(enc / t / 1e9 / HBM_PEAK_GBS, 4),
+           "counter_bytes": None, "counter_GBps": None, "counter_frac": None}
+    if counter_bytes_per_cycle:
+        out["counter_bytes"] = round(counter_bytes_per_cycle, 1)
+        out["counter_GBps"] = round(counter_bytes_per_cycle / t / 1e9, 2)
+        out["counter_frac"] = round(counter_bytes_per_cycle / t / 1e9 / HBM_PEAK_GBS, 4)
+    return out
+
+
+def bench_single(args, R, torch):
+    """One design: the batched form (autotuned), its kernels' roofline, the
+    plain single-instance form, and the CPU oracle; parity on the timed batch
+    itself (two instances read back after every timed cycle has run, against
+    the oracle run to the same cycle count, registers and digest)."""
+    wl = WORKLOADS[args.workload]
+    n_inst = args.instances or wl["instances"]
+    cps = args.cycles_per_step or wl["cycles_per_step"]
+    steps = args.steps if args.steps is not None else wl["steps"]
+    repeats = max(1, args.repeats)
+    mapping = {"auto": R.RTEAAL_MAP_AUTO, "resident": R.RTEAAL_MAP_RESIDENT,
+               "sweep": R.RTEAAL_MAP_SWEEP, "layered": R.RTEAAL_MAP_LAYERED}[args.mapping]
+
+    t0 = time.perf_counter()
+    d = rtlgen.generate(wl["cfg"], wl["seed"])
+    seeds = rtlgen.instance_seeds(n_inst)
+    print(f"[bench] design {d.summary()} generated in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    AB = algorithmic_bytes(d)
+    ABE = algorithmic_bytes(d, eb)
+    X, G = AB["x"], AB["g"]
+    prof_cycles = args.profile_cycles or wl["profile_cycles"]
+    total_cycles = (args.warmup + repeats * steps) * cps + prof_cycles
+    check = sorted({0, n_inst - 1})
+    oracle_thread = None
+    if not args.no_parity:
+        oracle_thread, oracle_res = start_oracle(d, seeds[check], total_cycles)
+        print(f"[bench] oracle started: instances {check} x {total_cycles} cycles "
+              f"(the timed batch's total)", file=sys.stderr, flush=True)
+
+    ctx = R.rteaal_create(0)
+    stream = ctx.stream
+    did = R.rteaal_load_design(ctx, d)
+    manual = (args.mapping != "auto" or args.block or args.ops_per_wave or args.unroll
+              or args.tiles_per_wave or args.arity_split or args.tiles_per_pass)
+    if not manual and not args.no_autotune:
+        t0 = time.perf_counter()
+        tuned, trate = R.rteaal_autotune(ctx, did, n_inst)
+        print(f"[bench] autotune batched ({time.perf_counter() - t0:.1f}s): {tuned} "
+              f"-> {trate:.4g} instance-cycles/s", file=sys.stderr, flush=True)
+    bid = R.rteaal_create_batch(ctx, did, seeds, mapping=mapping, block_threads=args.block,
+                                ops_per_wave=args.ops_per_wave, unroll=args.unroll,
+                                tiles_per_wave=args.tiles_per_wave, arity_split=args.arity_split,
+                                tiles_per_pass=args.tiles_per_pass)
+    used_map, _ = R.rteaal_batch_info(ctx, bid)
+    bopts = R.rteaal_batch_options(ctx, bid)
+    for _ in range(args.warmup):
+        R.rteaal_step(ctx, bid, cps)
+    R.rteaal_sync(ctx)
+    print(f"[bench] warmup done ({args.warmup} x {cps} cycles)", file=sys.stderr, flush=True)
+
+    def run():
+        for _ in range(steps):
+            R.rteaal_step(ctx, bid, cps)
+
+    runs = timed_runs(torch, stream, run, repeats)
+    ms = float(np.median(runs))
+    value = n_inst * cps * steps / (ms / 1e3)
+    print(f"[bench] batched: {repeats} x ({steps} x {cps} cycles) x {n_inst} inst, median "
+          f"{ms:.1f} ms -> {value:.4g} instance-cycles/s (runs {[round(r, 1) for r in runs]})",
+          file=sys.stderr, flush=True)
+
+    # Kernel timing with HIP events around each simulation-kernel launch.
+    R.rteaal_kernel_timing(ctx, bid, True)
+    R.rteaal_step(ctx, bid, prof_cycles)
+    (launches, kms), (h_launches, h_kms) = R.rteaal_kernel_timing(ctx, bid, False)
+    avg_ms = kms / max(launches, 1)
+    # Parity: the timed batch itself, after all of its cycles.
+    got_regs = R.unpack_limbs(np.concatenate([R.rteaal_read_state(ctx, bid, first=k, n=1)
+                                              for k in check]), d.slot_width[d.reg_slot])
+    got_dg = np.concatenate([R.rteaal_read_digest(ctx, bid, first=k, n=1) for k in check])
+    assert R.rteaal_batch_info(ctx, bid)[1] == total_cycles
+    lds = used_map == R.RTEAAL_MAP_RESIDENT and R.rteaal_batch_footprint(
+        ctx, did, n_inst, mapping=R.RTEAAL_MAP_RESIDENT) // max(n_inst, 1) <= 160 * 1024
+    if used_map == R.RTEAAL_MAP_SWEEP:
+        # The common kernel moves the light operations' bytes; the heavy
+        # kernel's are reported beside it.
+        bound, peak = "hbm", HBM_PEAK_GBS
+        per_launch = (AB["x_light"] * n_inst + AB["g_light"]) * prof_cycles / max(launches, 1)
+    elif not lds:
+        bound, peak = "hbm", HBM_PEAK_GBS
+        per_launch = (X * n_inst + G) * prof_cycles / max(launches, 1)
+    else:
+        bound, peak = "lds", LDS_PEAK_GBS
+        per_launch = X * n_inst * prof_cycles / max(launches, 1)
+    achieved = per_launch / (avg_ms / 1e3) / 1e9
+    traffic = (measured_traffic("k_sweep", args.workload, bopts)
+               if used_map == R.RTEAAL_MAP_SWEEP else None)
+    roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": round(peak, 1),
+                "unit": "GB/s", "frac": round(achieved / peak, 4), "traffic": traffic,
+                "kernel": {R.RTEAAL_MAP_SWEEP: "k_sweep", R.RTEAAL_MAP_LAYERED: "k_layer"}.get(used_map, "k_resident"),
+                "launches": launches, "avg_launch_ms": round(avg_ms, 5),
+                "bytes_per_launch": round(per_launch, 1),
+                "bytes_model": "word model: 1/8 B for a 1-bit value, 4 B up to 32 bits, 8 B per "
+                               "64-bit limb; graph once per cycle",
+                "algorithmic_bytes_per_instance_cycle": round(X, 1),
+                "graph_bytes_per_cycle": round(G, 1)}
+    counter_cycle = None
+    if used_map == R.RTEAAL_MAP_SWEEP:
+        # What the storage encoding moves for the same work (1- and 2-byte
+        # classes for values of at most 16 bits): below the canonical word
+        # model, so `achieved` can exceed what the HBM moves.
+        enc = (ABE["x_light"] * n_inst + ABE["g_light"]) * prof_cycles / max(launches, 1)
+        roofline["encoded_bytes_per_launch"] = round(enc, 1)
+        roofline["encoded_GBps"] = round(enc / (avg_ms / 1e3) / 1e9, 2)
+        roofline["encoded_frac"] = round(enc / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+        if traffic:
+            roofline["traffic_over_encoded"] = round(traffic / enc, 3)
+    if traffic:
+        roofline["traffic_over_algorithmic"] = round(traffic / per_launch, 3)
+        roofline["traffic_GBps"] = round(traffic / (avg_ms / 1e3) / 1e9, 2)
+        roofline["counter_frac"] = round(traffic / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    if h_launches:
+        h_avg = h_kms / h_launches
+        h_bytes = (AB["x_heavy"] * n_inst + AB["g_heavy"]) * prof_cycles / h_launches
+        h_enc = (ABE["x_heavy"] * n_inst + ABE["g_heavy"]) * prof_cycles / h_launches
+        h_traffic = measured_traffic("k_sweep_heavy", args.workload, bopts)
+        roofline["heavy_kernel"] = {
+            "kernel": "k_sweep_heavy", "launches": h_launches, "avg_launch_ms": round(h_avg, 5),
+            "bytes_per_launch": round(h_bytes, 1), "encoded_bytes_per_launch": round(h_enc, 1),
+            "achieved": round(h_bytes / (h_avg / 1e3) / 1e9, 2),
+            "encoded_GBps": round(h_enc / (h_avg / 1e3) / 1e9, 2), "traffic": h_traffic,
+            "counter_frac": (round(h_traffic / (h_avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                             if h_traffic else None),
+            "share_of_kernel_time": round(h_kms / (h_kms + kms), 4)}
+        if traffic and h_traffic:
+            counter_cycle = (traffic * launches + h_traffic * h_launches) / prof_cycles
+    roofline["whole_cycle"] = whole_cycle(AB, ABE, n_inst, ms / (steps * cps), counter_cycle)
+    R.rteaal_free_batch(ctx, bid)
+
+    plain = None
+    if not args.no_plain:
+        pc = args.plain_cycles or wl["plain_cycles"]
+        plain_opts = {"mapping": R.RTEAAL_MAP_RESIDENT}
+        if not args.no_autotune:
+            plain_opts, prate = R.rteaal_autotune(ctx, did, 1)
+            print(f"[bench] autotune plain: {plain_opts} -> {prate:.4g}", file=sys.stderr, flush=True)
+        pb = R.rteaal_create_batch(ctx, did, seeds[:1], **plain_opts)
+        R.rteaal_step(ctx, pb, min(pc, 200))
+        R.rteaal_sync(ctx)
+        pruns = timed_runs(torch, stream, lambda: R.rteaal_step(ctx, pb, pc), repeats)
+        pms = float(np.median(pruns))
+        # Roofline of the plain form's simulation kernel, timed as above.
+        p_map, _ = R.rteaal_batch_info(ctx, pb)
+        ppc = min(pc, 50)
+        R.rteaal_kernel_timing(ctx, pb, True)
+        R.rteaal_step(ctx, pb, ppc)
+        (pl, pkms), (phl, phkms) = R.rteaal_kernel_timing(ctx, pb, False)
+        R.rteaal_free_batch(ctx, pb)
+        p_lds = p_map == R.RTEAAL_MAP_RESIDENT and R.rteaal_batch_footprint(
+            ctx, did, 1, mapping=R.RTEAAL_MAP_RESIDENT) <= 160 * 1024
+        p_launches, p_ms = pl + phl, pkms + phkms
+        p_bytes = (X + (0 if p_lds else G)) * ppc / max(p_launches, 1)
+        p_avg = p_ms / max(p_launches, 1)
+        p_peak = LDS_PEAK_GBS if p_lds else HBM_PEAK_GBS
+        p_ach = p_bytes / (p_avg / 1e3) / 1e9 if p_avg > 0 else 0.0
+        plain = {"value": pc / (pms / 1e3), "unit": "instance-cycles/s", "instances": 1,
+                 "cycles": pc, "repeats": repeats, "opts": plain_opts,
+                 "roofline": {"bound": "lds" if p_lds else "hbm",
+                              "kernel": {R.RTEAAL_MAP_SWEEP: "k_sweep", R.RTEAAL_MAP_LAYERED: "k_layer"}.get(
+                                  p_map, "k_resident"),
+                              "achieved": round(p_ach, 2), "peak": round(p_peak, 1), "unit": "GB/s",
+                              "frac": round(p_ach / p_peak, 4), "launches": p_launches,
+                              "avg_launch_ms": round(p_avg, 5), "bytes_per_launch": round(p_bytes, 1),
+                              "note": "one instance: latency-bound (dependent gathers per layer)"}}
+        print(f"[bench] plain: {pc} cycles, median {pms:.1f} ms -> {plain['value']:.4g}",
+              file=sys.stderr, flush=True)
+    R.rteaal_unload_design(ctx, did)
+    R.rteaal_destroy(ctx)
+
+    parity = None
+    if oracle_thread is not None:
+        print("[bench] waiting for the parity oracle", file=sys.stderr, flush=True)
+        oracle_thread.join()
+        regs_ok = bool(np.array_equal(got_regs, oracle_res["regs"]))
+        dg_ok = bool(np.array_equal(got_dg, oracle_res["digest"]))
+        parity = {"instances": check, "cycles": total_cycles, "registers_equal": regs_ok,
+                  "digest_equal": dg_ok, "oracle_seconds": round(oracle_res["seconds"], 1),
+                  "what": "the timed batch itself after its warm-up, timed, profiled cycles: "
+                          "registers and the per-cycle register digest vs the oracle"}
+        print(f"[bench] parity on the timed batch: {parity}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        per_ic = max(d.n_ops, 1) * 45e-9                 # rough oracle cost per instance-cycle
+        k = min(host_threads(), len(seeds))
+        cyc = max(1, int(min(2000, 12.0 * host_threads() / (k * per_ic))))
+        cpu = cpu_baseline(d, seeds[:k], cyc, n_inst, wl["cycles"])
+        print(f"[bench] cpu oracle: {cpu}", file=sys.stderr, flush=True)
+
+    return {
+        "metric": METRIC, "value": round(value, 2), "unit": "instance-cycles/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms / steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "ops": d.n_ops, "layers": d.n_layers,
+                   "registers": d.n_regs, "inputs": d.n_inputs, "instances": n_inst,
+                   "cycles_per_step": cps,
+                   "timed": f"median of {repeats} timed runs of {steps} steps x {cps} cycles "
+                            f"({[round(r, 1) for r in runs]} ms): a sample of the workload's "
+                            f"{wl['cycles']} cycles (the rate is steady from the first cycles on)",
+                   "mapping": {R.RTEAAL_MAP_SWEEP: "sweep", R.RTEAAL_MAP_LAYERED: "layered"}.get(
+                       used_map, "resident"),
+                   "opts": bopts,
+                   "design_fingerprint": d.fingerprint()},
+        "plain": plain,
+        "batched_over_plain": round(value / plain["value"], 2) if plain else None,
+        "paper_context": PAPER_CONTEXT,
+        "parity_sample_ok": (parity["registers_equal"] and parity["digest_equal"]) if parity else None,
+        "parity": parity,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+
+
+def start_oracle_jobs(jobs, threads):
+    """Oracle runs (design, seeds, cycles) side by side on `threads` host
+    threads, one thread per run, largest first; each run's registers,
+    digest and wall time."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
-    n = len(seeds)
-    pick = sorted({0, n // 3, (2 * n) // 3, n - 1})
-    bid = R.rteaal_create_batch(ctx, did, seeds, **opts)
-    try:
-        R.rteaal_step(ctx, bid, cycles)
-        got = np.concatenate([R.rteaal_read_state(ctx, bid, first=k, n=1) for k in pick])
-    finally:
-        R.rteaal_free_batch(ctx, bid)
-    got = R.unpack_limbs(got, d.slot_width[d.reg_slot])
-    ref, _, _ = oracle.run(d, np.asarray(seeds)[pick], cycles, n_threads=len(pick))
-    return bool(np.array_equal(got, ref))
+    res = [None] * len(jobs)
+
+    def one(k):
+        d, seeds, cyc = jobs[k]
+        t0 = time.perf_counter()
+        dg = {}
+        regs, _, _ = oracle.run(d, seeds, cyc, n_threads=1, digests=dg)
+        res[k] = (regs, dg["final"], time.perf_counter() - t0)
+
+    order = sorted(range(len(jobs)), key=lambda k: -jobs[k][0].n_ops * len(jobs[k][1]) * jobs[k][2])
+
+    def go():
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(one, order))
+
+    th = threading.Thread(target=go, daemon=True)
+    th.start()
+    return th, res
 
 
 def bench_multi(args, R, torch):
     """64 designs of uneven size, each with its own instance count, advanced
-    together by rteaal_step_many (one persistent launch for the RESIDENT
-    batches, overlapping streams for the SWEEP batches)."""
+    together by rteaal_step_many.  Parity: the first instance of every
+    design of the timed batches, after all of their cycles, registers and
+    digest against the oracle; those oracle runs (one per design, side by
+    side on the host threads) also give the CPU baseline."""
     t0 = time.perf_counter()
     plan = rtlgen.multidesign_batch(seed=2, n_designs=args.designs)
     designs = [rtlgen.generate(cfg, seed) for cfg, seed, _ in plan]
+    n_inst = [n for _, _, n in plan]
+    seeds_of = [rtlgen.instance_seeds(n, design_index=k) for k, n in enumerate(n_inst)]
     print(f"[bench] {len(designs)} designs ({sum(d.n_ops for d in designs)} ops, "
-          f"{sum(n for _, _, n in plan)} instances) generated in {time.perf_counter() - t0:.1f}s",
+          f"{sum(n_inst)} instances) generated in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
+    cps = args.cycles_per_step or 100
+    steps = args.steps if args.steps is not None else 5
+    repeats = max(1, args.repeats)
+    total_cycles = (args.warmup + repeats * steps) * cps
+    threads = host_threads()
+    oracle_thread = None
+    if not args.no_parity:
+        oracle_thread, ores = start_oracle_jobs(
+            [(d, seeds_of[k][:1], total_cycles) for k, d in enumerate(designs)], threads)
     ctx = R.rteaal_create(0)
     dids = [R.rteaal_load_design(ctx, d) for d in designs]
-    bids, tuned = [], []
     t0 = time.perf_counter()
-    for k, (did, (cfg, seed, n)) in enumerate(zip(dids, plan)):
-        if not args.no_autotune:
-            o, r = R.rteaal_autotune(ctx, did, n, trial_cycles=2)
-            tuned.append(o)
-            print(f"[bench] design {k}: {cfg.n_ops} ops x {n} instances -> {o} ({r:.4g})",
-                  file=sys.stderr, flush=True)
-        bids.append(R.rteaal_create_batch(ctx, did, rtlgen.instance_seeds(n, design_index=k)))
-    print(f"[bench] batches created (autotune {time.perf_counter() - t0:.1f}s)", file=sys.stderr,
-          flush=True)
-    ok = True
-    import oracle
-    for k in (0, len(bids) - 1):                      # parity sample: a few cycles, first instance
-        d = designs[k]
-        b = R.rteaal_create_batch(ctx, dids[k], rtlgen.instance_seeds(plan[k][2], design_index=k))
-        R.rteaal_step_many(ctx, [b], [3])
-        got = R.unpack_limbs(R.rteaal_read_state(ctx, b, 0, 1), d.slot_width[d.reg_slot])
-        R.rteaal_free_batch(ctx, b)
-        ref, _, _ = oracle.run(d, rtlgen.instance_seeds(plan[k][2], design_index=k)[:1], 3)
-        ok = ok and bool(np.array_equal(got, ref))
-    cps = args.cycles_per_step or 200
-    steps = args.steps if args.steps is not None else 5
-    n_inst = [n for _, _, n in plan]
+    tuned_rate = None
+    if not args.no_autotune:
+        # The set's launch policy is tuned jointly, on the step time of all
+        # designs together (each design alone would pick shapes that do not
+        # share the device well).
+        _, tuned_rate = R.rteaal_autotune_many(ctx, dids, n_inst)
+    bids = [R.rteaal_create_batch(ctx, did, seeds_of[k]) for k, did in enumerate(dids)]
+    print(f"[bench] batches created (joint autotune {time.perf_counter() - t0:.1f}s, "
+          f"{tuned_rate})", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         R.rteaal_step_many(ctx, bids, [cps] * len(bids))
     R.rteaal_sync(ctx)
-    stream = ctx.stream
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(steps):
-        R.rteaal_step_many(ctx, bids, [cps] * len(bids))
-    ev1.record(stream)
-    ev1.synchronize()
-    ms = ev0.elapsed_time(ev1)
+
+    def run():
+        for _ in range(steps):
+            R.rteaal_step_many(ctx, bids, [cps] * len(bids))
+
+    runs = timed_runs(torch, ctx.stream, run, repeats)
+    ms = float(np.median(runs))
     value = sum(n_inst) * cps * steps / (ms / 1e3)
+    print(f"[bench] multi: median {ms:.1f} ms of {runs} -> {value:.4g} instance-cycles/s",
+          file=sys.stderr, flush=True)
+    got = [(R.unpack_limbs(R.rteaal_read_state(ctx, b, 0, 1), d.slot_width[d.reg_slot]),
+            R.rteaal_read_digest(ctx, b, 0, 1)) for b, d in zip(bids, designs)]
     maps = [R.rteaal_batch_info(ctx, b)[0] for b in bids]
+    opts = [R.rteaal_batch_options(ctx, b) for b in bids]
     for b in bids:
         R.rteaal_free_batch(ctx, b)
     R.rteaal_destroy(ctx)
+
+    word = sum(n * algorithmic_bytes(d)["x"] + algorithmic_bytes(d)["g"] for d, n in zip(designs, n_inst))
+    enc = sum(n * algorithmic_bytes(d, eb)["x"] + algorithmic_bytes(d, eb)["g"]
+              for d, n in zip(designs, n_inst))
+    t_cycle = ms / 1e3 / (steps * cps)
+    roofline = {"bound": "hbm", "kernel": "every kernel of rteaal_step_many (whole step)",
+                "achieved": round(word / t_cycle / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(word / t_cycle / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_cycle": round(word, 1),
+                "bytes_model": "sum over designs of (instances x X + G), word model",
+                "encoded_bytes_per_cycle": round(enc, 1),
+                "encoded_GBps": round(enc / t_cycle / 1e9, 2),
+                "encoded_frac": round(enc / t_cycle / 1e9 / HBM_PEAK_GBS, 4)}
+    parity, cpu, ok = None, None, None
+    if oracle_thread is not None:
+        oracle_thread.join()
+        bad = [k for k in range(len(designs))
+               if not (np.array_equal(got[k][0], ores[k][0]) and np.array_equal(got[k][1], ores[k][1]))]
+        ok = not bad
+        parity = {"instances": "the first of every design", "cycles": total_cycles,
+                  "mismatching_designs": bad,
+                  "what": "the timed batches after all their cycles: registers and digest"}
+        if not args.no_cpu_baseline:
+            # Per instance-cycle oracle time of each design (its run had one
+            # thread, beside the others), weighted by the design's instances.
+            per_ic = [ores[k][2] / total_cycles for k in range(len(designs))]
+            rate_core = sum(n_inst) / sum(n * t for n, t in zip(n_inst, per_ic))
+            cpu = {"value": rate_core * threads, "unit": "instance-cycles/s", "cores": threads,
+                   "kind": "oracle", "per_core": rate_core, "host_cpus_visible": os.cpu_count(),
+                   "sample": f"the first instance of each of the {len(designs)} designs x "
+                             f"{total_cycles} cycles (the parity runs), one thread each, "
+                             f"{threads} at a time; rate weighted by each design's instances",
+                   "extrapolated_full_workload": {
+                       "cycles": 20_000,
+                       "seconds": round(sum(n_inst) * 20_000 / (rate_core * threads), 1),
+                       "label": f"extrapolation: per-core rate x {threads} cores"}}
     return {
         "metric": METRIC, "value": round(value, 2), "unit": "instance-cycles/s", "n_gpus": 1,
         "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms / steps, 3),
@@ -239,9 +576,14 @@ def bench_multi(args, R, torch):
         "data": "synthetic",
         "config": {"workload": "multi-64", "designs": len(designs),
                    "ops": sum(d.n_ops for d in designs), "instances": sum(n_inst),
-                   "cycles_per_step": cps, "resident_batches": maps.count(R.RTEAAL_MAP_RESIDENT),
-                   "sweep_batches": maps.count(R.RTEAAL_MAP_SWEEP)},
-        "parity_sample_ok": ok, "roofline": None, "cpu_baseline": None,
+                   "cycles_per_step": cps,
+                   "timed": f"median of {repeats} timed runs of {steps} steps x {cps} cycles "
+                            f"({[round(r, 1) for r in runs]} ms) of the workload's 20,000",
+                   "resident_batches": maps.count(R.RTEAAL_MAP_RESIDENT),
+                   "sweep_batches": maps.count(R.RTEAAL_MAP_SWEEP),
+                   "layered_batches": maps.count(R.RTEAAL_MAP_LAYERED)},
+        "parity_sample_ok": ok, "parity": parity, "roofline": roofline, "cpu_baseline": cpu,
+        "shapes": opts if args.verbose_shapes else None,
     }
 
 
@@ -636,6 +978,12 @@ def main():
     ap.add_argument("--plain-cycles", type=int, default=None)
     ap.add_argument("--profile-cycles", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true",
+                    help="skip the oracle check of the timed batch")
+    ap.add_argument("--verbose-shapes", action="store_true",
+                    help="multi-64: list every batch's launch shape in the JSON line")
+    ap.add_argument("--repeats", type=int, default=3,
+                    help="timed runs of --steps steps each; the median is reported")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default shapes instead of autotuned ones")
@@ -681,186 +1029,7 @@ def main():
         print(json.dumps(bench_muxchain(args, R, torch)), flush=True)
         return
 
-    wl = WORKLOADS[args.workload]
-    n_inst = args.instances or wl["instances"]
-    cps = args.cycles_per_step or wl["cycles_per_step"]
-    steps = args.steps if args.steps is not None else wl["steps"]
-    mapping = {"auto": R.RTEAAL_MAP_AUTO, "resident": R.RTEAAL_MAP_RESIDENT,
-               "sweep": R.RTEAAL_MAP_SWEEP, "layered": R.RTEAAL_MAP_LAYERED}[args.mapping]
-
-    t0 = time.perf_counter()
-    d = rtlgen.generate(wl["cfg"], wl["seed"])
-    seeds = rtlgen.instance_seeds(n_inst)
-    print(f"[bench] design {d.summary()} generated in {time.perf_counter() - t0:.1f}s",
-          file=sys.stderr, flush=True)
-    AB = algorithmic_bytes(d)
-    ABE = algorithmic_bytes(d, eb)
-    X, G = AB["x"], AB["g"]
-
-    ctx = R.rteaal_create(0)
-    stream = ctx.stream
-    did = R.rteaal_load_design(ctx, d)
-
-    manual = (args.mapping != "auto" or args.block or args.ops_per_wave or args.unroll
-              or args.tiles_per_wave or args.arity_split or args.tiles_per_pass)
-    tuned = None
-    if not manual and not args.no_autotune:
-        t0 = time.perf_counter()
-        tuned, trate = R.rteaal_autotune(ctx, did, n_inst)
-        print(f"[bench] autotune batched ({time.perf_counter() - t0:.1f}s): {tuned} "
-              f"-> {trate:.4g} instance-cycles/s", file=sys.stderr, flush=True)
-    bid = R.rteaal_create_batch(ctx, did, seeds, mapping=mapping, block_threads=args.block,
-                                ops_per_wave=args.ops_per_wave, unroll=args.unroll,
-                                tiles_per_wave=args.tiles_per_wave, arity_split=args.arity_split,
-                                tiles_per_pass=args.tiles_per_pass)
-    used_map, _ = R.rteaal_batch_info(ctx, bid)
-    bopts = R.rteaal_batch_options(ctx, bid)
-    ok = parity_sample(R, ctx, did, d, seeds, bopts)
-    print(f"[bench] parity sample vs oracle: {ok}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        R.rteaal_step(ctx, bid, cps)
-    R.rteaal_sync(ctx)
-    print(f"[bench] warmup done ({args.warmup} x {cps} cycles)", file=sys.stderr, flush=True)
-
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(steps):
-        R.rteaal_step(ctx, bid, cps)
-    ev1.record(stream)
-    ev1.synchronize()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    value = n_inst * cps * steps / (ms / 1e3)
-    print(f"[bench] batched: {steps} x {cps} cycles x {n_inst} inst in {ms:.1f} ms "
-          f"-> {value:.4g} instance-cycles/s", file=sys.stderr, flush=True)
-
-    # Kernel timing with HIP events around each simulation-kernel launch.
-    prof_cycles = args.profile_cycles or (min(cps, 1024) if used_map == R.RTEAAL_MAP_RESIDENT else min(cps, 50))
-    R.rteaal_kernel_timing(ctx, bid, True)
-    R.rteaal_step(ctx, bid, prof_cycles)
-    (launches, kms), (h_launches, h_kms) = R.rteaal_kernel_timing(ctx, bid, False)
-    avg_ms = kms / max(launches, 1)
-    lds = used_map == R.RTEAAL_MAP_RESIDENT and R.rteaal_batch_footprint(
-        ctx, did, n_inst, mapping=R.RTEAAL_MAP_RESIDENT) // max(n_inst, 1) <= 160 * 1024
-    if used_map == R.RTEAAL_MAP_SWEEP:
-        # The common kernel moves the light operations' bytes; the heavy
-        # kernel's are reported beside it.
-        bound, peak = "hbm", HBM_PEAK_GBS
-        per_launch = (AB["x_light"] * n_inst + AB["g_light"]) * prof_cycles / max(launches, 1)
-    elif not lds:
-        bound, peak = "hbm", HBM_PEAK_GBS
-        per_launch = (X * n_inst + G) * prof_cycles / max(launches, 1)
-    else:
-        bound, peak = "lds", LDS_PEAK_GBS
-        per_launch = X * n_inst * prof_cycles / max(launches, 1)
-    achieved = per_launch / (avg_ms / 1e3) / 1e9
-    traffic = (measured_traffic("k_sweep", args.workload, bopts)
-               if used_map == R.RTEAAL_MAP_SWEEP else None)
-    roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": round(peak, 1),
-                "unit": "GB/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": {R.RTEAAL_MAP_SWEEP: "k_sweep", R.RTEAAL_MAP_LAYERED: "k_layer"}.get(used_map, "k_resident"),
-                "launches": launches, "avg_launch_ms": round(avg_ms, 5),
-                "bytes_per_launch": round(per_launch, 1),
-                "algorithmic_bytes_per_instance_cycle": round(X, 1),
-                "graph_bytes_per_cycle": round(G, 1)}
-    if used_map == R.RTEAAL_MAP_SWEEP:
-        # What the storage encoding moves for the same work (1- and 2-byte
-        # classes for values of at most 16 bits): below the canonical word
-        # model, so `achieved` can exceed what the HBM moves.
-        enc = (ABE["x_light"] * n_inst + ABE["g_light"]) * prof_cycles / max(launches, 1)
-        roofline["encoded_bytes_per_launch"] = round(enc, 1)
-        roofline["encoded_GBps"] = round(enc / (avg_ms / 1e3) / 1e9, 2)
-        if traffic:
-            roofline["traffic_over_encoded"] = round(traffic / enc, 3)
-    if traffic:
-        roofline["traffic_over_algorithmic"] = round(traffic / per_launch, 3)
-        roofline["traffic_GBps"] = round(traffic / (avg_ms / 1e3) / 1e9, 2)
-    if h_launches:
-        h_avg = h_kms / h_launches
-        h_bytes = (AB["x_heavy"] * n_inst + AB["g_heavy"]) * prof_cycles / h_launches
-        h_enc = (ABE["x_heavy"] * n_inst + ABE["g_heavy"]) * prof_cycles / h_launches
-        h_traffic = measured_traffic("k_sweep_heavy", args.workload, bopts)
-        roofline["heavy_kernel"] = {
-            "kernel": "k_sweep_heavy", "launches": h_launches, "avg_launch_ms": round(h_avg, 5),
-            "bytes_per_launch": round(h_bytes, 1), "encoded_bytes_per_launch": round(h_enc, 1),
-            "achieved": round(h_bytes / (h_avg / 1e3) / 1e9, 2),
-            "encoded_GBps": round(h_enc / (h_avg / 1e3) / 1e9, 2), "traffic": h_traffic,
-            "share_of_kernel_time": round(h_kms / (h_kms + kms), 4)}
-    R.rteaal_free_batch(ctx, bid)
-
-    plain = None
-    if not args.no_plain:
-        pc = args.plain_cycles or min(cps, 2000)
-        plain_opts = {"mapping": R.RTEAAL_MAP_RESIDENT}
-        if not args.no_autotune:
-            plain_opts, prate = R.rteaal_autotune(ctx, did, 1)
-            print(f"[bench] autotune plain: {plain_opts} -> {prate:.4g}", file=sys.stderr, flush=True)
-        pb = R.rteaal_create_batch(ctx, did, seeds[:1], **plain_opts)
-        R.rteaal_step(ctx, pb, min(pc, 200))
-        R.rteaal_sync(ctx)
-        ev0.record(stream)
-        R.rteaal_step(ctx, pb, pc)
-        ev1.record(stream)
-        ev1.synchronize()
-        pms = ev0.elapsed_time(ev1)
-        # Roofline of the plain form's simulation kernel, timed as above.
-        p_map, _ = R.rteaal_batch_info(ctx, pb)
-        ppc = min(pc, 50)
-        R.rteaal_kernel_timing(ctx, pb, True)
-        R.rteaal_step(ctx, pb, ppc)
-        (pl, pkms), (phl, phkms) = R.rteaal_kernel_timing(ctx, pb, False)
-        R.rteaal_free_batch(ctx, pb)
-        p_lds = p_map == R.RTEAAL_MAP_RESIDENT and R.rteaal_batch_footprint(
-            ctx, did, 1, mapping=R.RTEAAL_MAP_RESIDENT) <= 160 * 1024
-        p_launches, p_ms = pl + phl, pkms + phkms
-        p_bytes = (X + (0 if p_lds else G)) * ppc / max(p_launches, 1)
-        p_avg = p_ms / max(p_launches, 1)
-        p_peak = LDS_PEAK_GBS if p_lds else HBM_PEAK_GBS
-        p_ach = p_bytes / (p_avg / 1e3) / 1e9 if p_avg > 0 else 0.0
-        plain = {"value": pc / (pms / 1e3), "unit": "instance-cycles/s", "instances": 1,
-                 "cycles": pc, "opts": plain_opts,
-                 "roofline": {"bound": "lds" if p_lds else "hbm",
-                              "kernel": {R.RTEAAL_MAP_SWEEP: "k_sweep", R.RTEAAL_MAP_LAYERED: "k_layer"}.get(
-                                  p_map, "k_resident"),
-                              "achieved": round(p_ach, 2), "peak": round(p_peak, 1), "unit": "GB/s",
-                              "frac": round(p_ach / p_peak, 4), "launches": p_launches,
-                              "avg_launch_ms": round(p_avg, 5), "bytes_per_launch": round(p_bytes, 1),
-                              "note": "one instance: latency-bound (dependent gathers per layer)"}}
-        print(f"[bench] plain: {pc} cycles in {pms:.1f} ms -> {plain['value']:.4g}",
-              file=sys.stderr, flush=True)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        per_ic = max(d.n_ops, 1) * 45e-9                 # rough oracle cost per instance-cycle
-        k = min(16, len(seeds))
-        cyc = max(1, int(min(2000, 12.0 * min(16, os.cpu_count() or 1) / (k * per_ic))))
-        cpu = cpu_baseline(d, seeds[:k], cyc)
-        print(f"[bench] cpu oracle: {cpu}", file=sys.stderr, flush=True)
-
-    R.rteaal_unload_design(ctx, did)
-    R.rteaal_destroy(ctx)
-
-    out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "instance-cycles/s", "n_gpus": 1,
-        "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms / steps, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "ops": d.n_ops, "layers": d.n_layers,
-                   "registers": d.n_regs, "inputs": d.n_inputs, "instances": n_inst,
-                   "cycles_per_step": cps,
-                   "mapping": {R.RTEAAL_MAP_SWEEP: "sweep", R.RTEAAL_MAP_LAYERED: "layered"}.get(
-                       used_map, "resident"),
-                   "opts": bopts,
-                   "design_fingerprint": d.fingerprint()},
-        "plain": plain,
-        "batched_over_plain": round(value / plain["value"], 2) if plain else None,
-        "paper_context": PAPER_CONTEXT,
-        "parity_sample_ok": ok,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(bench_single(args, R, torch)), flush=True)
 
 
 if __name__ == "__main__":

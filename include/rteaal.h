@@ -310,6 +310,16 @@ typedef struct {
                               multiple of tiles_per_wave), all layers of one
                               pass before the next, so that a pass's recent
                               layer outputs can stay in the last-level cache  */
+  uint32_t persistent;     /* LAYERED: 0 = one launch per layer (a captured
+                              cycle graph); 1 = one cooperative launch for up
+                              to 1,024 cycles, every layer spread over the
+                              whole device and ended by a grid-wide barrier
+                              (the iterative rank I's advance, ◇ i≡I, inside
+                              one launch); unroll 1 or 2.  A barrier wait is
+                              bounded (environment RTEAAL_GRID_SPIN_LIMIT,
+                              default 2^22 spins); if one runs out, the next
+                              rteaal_sync or rteaal_read_state on the batch
+                              returns RTEAAL_E_DEVICE                          */
 } rteaal_batch_opts;
 
 /* Device bytes a batch of n_instances of `design` would allocate under
@@ -356,15 +366,31 @@ typedef struct {
   const uint64_t* words;
 } rteaal_stimulus;
 
-/* Advances every instance of `batch` by n_cycles (>= 0).  stim may be NULL
- * (mode 0).  Enqueue only. */
+/* Advances every instance of `batch` by n_cycles (>= 0): per cycle, the
+ * primary inputs are written into LI, the layers run in order (the iterative
+ * rank I of Cascade 1; each layer gathers its operands, applies its
+ * operators and writes LO back into LI, as the example kernel Alg. RU does),
+ * and then every register commits (Cascade 2's cycle rank C) and the
+ * register digest advances.  stim may be NULL (mode 0).  Enqueue only,
+ * except that host words are copied before the call returns.  Errors:
+ * RTEAAL_E_INVALID_ARG (unknown batch, bad stimulus), RTEAAL_E_NO_MEMORY,
+ * RTEAAL_E_DEVICE (the context is then unusable). */
 rteaal_status rteaal_step(rteaal_ctx* ctx, rteaal_batch_id batch, uint64_t n_cycles,
                           const rteaal_stimulus* stim);
 
-/* Advances n batches (possibly of different designs) by n_cycles[k] each,
- * RESIDENT batches sharing one persistent launch.  Generator stimulus only. */
+/* Advances n batches (possibly of different designs) by n_cycles[k] each, as
+ * rteaal_step does for one (every batch runs the cascade of Cascade 1 and
+ * its register commit per cycle; the host supplies primary inputs between
+ * cycles as in section "System Integration").  batches[k] are distinct.
+ * stims: NULL (generator stimulus for every batch) or host array [n],
+ * stims[k] being batch k's stimulus as in rteaal_step (words
+ * [n_cycles[k]][n_instances][W] of that batch).  Enqueue only, except that
+ * host words are copied before the call returns (it then waits for the
+ * step).  Errors: RTEAAL_E_INVALID_ARG (unknown or repeated batch, bad
+ * stimulus: then nothing has been enqueued), RTEAAL_E_NO_MEMORY,
+ * RTEAAL_E_DEVICE (the context is then unusable). */
 rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_id* batches,
-                               const uint64_t* n_cycles);
+                               const uint64_t* n_cycles, const rteaal_stimulus* stims);
 
 /* Waits until all enqueued work of ctx has completed. */
 rteaal_status rteaal_sync(rteaal_ctx* ctx);
@@ -372,24 +398,49 @@ rteaal_status rteaal_sync(rteaal_ctx* ctx);
 /* ------------------------------------------------------------------------ */
 /* State                                                                    */
 /* ------------------------------------------------------------------------ */
-enum { RTEAAL_READ_REGS = 1, RTEAAL_READ_ALL_SLOTS = 2 };
+enum { RTEAAL_READ_REGS = 1, RTEAAL_READ_DIGEST = 2, RTEAAL_READ_ALL_SLOTS = 4 };
 
-/* Waits for the batch, then copies instances [first, first+n) into `out`
- * (host): REGS gives [inst][reg][limbs(reg)]; ALL_SLOTS gives
- * [inst][slot][limbs(slot)] (values of the last completed cycle; slots with
- * no driver read as 0; only for designs loaded with
- * RTEAAL_LOAD_KEEP_ALL_SLOTS, else RTEAAL_E_UNSUPPORTED).  out_words is the
- * capacity of out in uint64 words; *written (may be NULL) receives the
- * number used. */
+/* Register digest.  The paper commits every register once per cycle (the
+ * cycle rank C of Cascade 2); the state compared between two simulators is
+ * the register vector after every cycle.  Each instance keeps one running
+ * 64-bit digest D of it, 0 at batch creation.  After every cycle's commit,
+ * with v[j][l] limb l (l < ceil(width/64)) of register j (the order of
+ * reg_slot) and s SplitMix64's output function (Steele, Lea & Flood, OOPSLA
+ * 2014),
+ *   h = sum over j, l of s(s(4 j + l) ^ v[j][l])   (mod 2^64),
+ *   D = s(D ^ h).
+ * Equal digests after n cycles mean (up to hash collisions) equal register
+ * vectors after each of the n cycles, in order. */
+
+/* Read-out of simulated state (the signal exposure of section "System
+ * Integration": the host reads DUT signals between cycles).  Waits for the
+ * batch, then copies instances [first, first+n) into `out` (host):
+ *   REGS:      [inst][reg][limbs(reg)], registers in reg_slot order;
+ *   DIGEST:    [inst], one word each: the register digest above;
+ *   ALL_SLOTS: [inst][slot][limbs(slot)] (values of the last completed
+ *              cycle; slots with no driver read as 0; only for designs
+ *              loaded with RTEAAL_LOAD_KEEP_ALL_SLOTS, else
+ *              RTEAAL_E_UNSUPPORTED).
+ * `what` is exactly one of these.  out_words is the capacity of out in
+ * uint64 words; *written (may be NULL) receives the number used.  Errors:
+ * RTEAAL_E_INVALID_ARG (range, kind, capacity), RTEAAL_E_DEVICE. */
 rteaal_status rteaal_read_state(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t first,
                                 uint32_t n, uint32_t what, uint64_t* out, size_t out_words,
                                 size_t* written);
 
 /* Overwrites the registers of instances [first, first+n) from `regs` (host,
  * [inst][reg][limbs(reg)], masked to width) and sets the batch's cycle
- * counter to `cycle` (checkpoint restore, host poke between cycles). */
+ * counter to `cycle` (checkpoint restore, and the host writing DUT signals
+ * between cycles: section "System Integration").  The digests are kept. */
 rteaal_status rteaal_write_state(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t first,
                                  uint32_t n, const uint64_t* regs, uint64_t cycle);
+
+/* Sets the register digest of instances [first, first+n) to digest[0..n)
+ * (host), e.g. to restore a checkpoint taken with RTEAAL_READ_DIGEST.  Waits
+ * for the batch.  Errors: RTEAAL_E_INVALID_ARG (range, null digest with
+ * n > 0), RTEAAL_E_DEVICE. */
+rteaal_status rteaal_write_digest(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t first,
+                                  uint32_t n, const uint64_t* digest);
 
 /* ------------------------------------------------------------------------ */
 /* Waveforms                                                                */
@@ -451,6 +502,27 @@ rteaal_status rteaal_read_changes(rteaal_ctx* ctx, rteaal_batch_id batch, rteaal
  * candidate's shape and rate is printed to stderr. */
 rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id design, uint32_t n_instances,
                               uint32_t trial_cycles, rteaal_batch_opts* best, double* rate);
+
+/* Joint autotuner for batches stepped together by rteaal_step_many (the
+ * kernel configuration is an input of the simulator, section "Design
+ * Overview", and its best choice varies by machine, Ablation Study 1): for
+ * designs ids[0 .. n) with n_instances[k] instances each, tries launch
+ * policies for the whole set (which batches run SWEEP and with which tile
+ * group, which run RESIDENT or LAYERED) on temporary batches, times
+ * trial_cycles cycles (0 = a size-dependent default) of one rteaal_step_many
+ * over all of them, and keeps the fastest policy: best (host [n], may be
+ * NULL) receives each batch's options, *rate (may be NULL) the set's
+ * instance-cycles/s, and AUTO batches created later for the same (design,
+ * instance count) use them.  A (design, instance count) pair appears once.
+ * With RTEAAL_AUTOTUNE_LOG set, every policy's rate goes to stderr.
+ *
+ * Both autotuners keep their results on disk when the environment variable
+ * RTEAAL_TUNE_CACHE names a file: a later call for the same device,
+ * designs (by a hash of their encoded programs), instance counts and trial
+ * length reads the choice back instead of timing the candidates again. */
+rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_design_id* ids,
+                                   const uint32_t* n_instances, uint32_t trial_cycles,
+                                   rteaal_batch_opts* best, double* rate);
 
 /* ------------------------------------------------------------------------ */
 /* Measurement                                                              */

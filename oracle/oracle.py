@@ -23,7 +23,7 @@ def lib_path() -> str:
 
 def build(extra_flags=()) -> str:
     """Compile liboracle.so with gcc (plain -O2, generic x86-64)."""
-    tmp = LIB + ".tmp"
+    tmp = LIB + f".tmp{os.getpid()}"   # one per process: test workers may build at once
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra",
            *extra_flags, SRC, "-o", tmp]
     subprocess.run(cmd, check=True)

@@ -24,6 +24,7 @@ namespace {
 
 thread_local std::string g_err;  // failures with no context
 
+
 struct DesignHost;
 struct Batch;
 
@@ -32,10 +33,23 @@ struct Mem {
   size_t bytes = 0;
 };
 
+// One captured cycle of a set of SWEEP and LAYERED batches stepped together
+// (rteaal_step_many): per layer slot a few launches over segment tables, then
+// the digest, fold and cycle advance of every batch.  `table` holds the
+// segment tables the launches read; ids are the batches, sorted.
+struct MultiGraph {
+  std::vector<uint32_t> ids;
+  hipGraphExec_t exec = nullptr;
+  Mem table;
+  uint64_t last_use = 0;
+  uint32_t launches = 0;
+};
+
 }  // namespace
 
 struct rteaal_ctx {
   int device = 0;
+  uint32_t spin_limit = 1u << 22;  // grid barrier waits of persistent launches
   hipStream_t stream = nullptr;
   bool own_stream = false;
   rteaal_allocator alloc{};
@@ -55,6 +69,10 @@ struct rteaal_ctx {
   hipStream_t cap[3] = {nullptr, nullptr, nullptr};
   hipEvent_t cap_fork = nullptr, cap_join[3] = {nullptr, nullptr, nullptr};
   Mem multi;
+  // Captured cycles of batch sets stepped together, least recently used
+  // first to go (at most kMaxMultiGraphs).
+  std::vector<std::unique_ptr<MultiGraph>> mgraphs;
+  uint64_t mg_clock = 0;
   // Autotuned batch options, keyed by (design, instance count).
   std::map<std::pair<uint32_t, uint32_t>, rteaal_batch_opts> tuned;
 };
@@ -305,7 +323,15 @@ struct DesignHost {
   uint64_t n_user_ops = 0;
   Mem d_ops, d_layers, d_consts, d_reg_refs, d_slot_refs;
   uint32_t n_batches = 0;
+  uint64_t fingerprint = 0;  // of the encoded program, for the tuner's cache
 };
+
+// FNV-1a over bytes (Fowler, Noll, Vo), continuing from h.
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  return h;
+}
 
 struct EncOp {
   uint32_t opc, arity, dst_slot;  // dst_slot: user slot or n_slots + temp index
@@ -639,6 +665,11 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
   h->n_inputs = d->n_inputs;
   h->n_design_layers = d->n_layers;
   h->n_user_ops = d->n_ops;
+  uint64_t fp = fnv1a(h->ops.data(), h->ops.size() * sizeof(DevOp));
+  fp = fnv1a(h->layers.data(), h->layers.size() * sizeof(DevLayer), fp);
+  fp = fnv1a(h->const_limbs.data(), h->const_limbs.size() * 8, fp);
+  fp = fnv1a(h->reg_refs.data(), h->reg_refs.size() * sizeof(SlotRef), fp);
+  h->fingerprint = fnv1a(&h->n_rows, sizeof h->n_rows, fp);
 }
 
 // ---------------------------------------------------------------------------
@@ -649,9 +680,14 @@ struct Batch {
   uint32_t arity_split = 0;
   uint32_t tpp = 0;  // SWEEP tiles per pass, 0 = all
   bool lds = false, lds_ops = false;
+  bool persistent = false;  // LAYERED: one cooperative launch per chunk of cycles
+  Mem gsync;                // its grid barrier state
   uint64_t cycle = 0;
   StateLayout L{};
-  Mem state, seeds, ctl;
+  // dig: the running register digest of every instance slot (n_slot words),
+  // then the per-cycle sums the digest kernels add into (n_slot words).
+  Mem state, seeds, ctl, dig;
+  uint64_t n_slot = 0;             // instance slots: allocated tiles x 64 (SWEEP) or n_inst
   hipGraphExec_t graph = nullptr;  // one cycle of SWEEP launches
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
@@ -793,7 +829,33 @@ ResJob res_job(const DesignHost& h, const Batch& b, uint64_t n_cycles) {
   J.seeds = (const uint64_t*)b.seeds.p;
   J.ctl = (const DevCtl*)b.ctl.p;
   J.n_cycles = n_cycles;
+  J.regs = (const SlotRef*)h.d_reg_refs.p;
+  J.digest = (uint64_t*)b.dig.p;
+  J.n_regs = h.n_regs;
   return J;
+}
+
+// After the stream has drained: a persistent batch whose grid barrier wait
+// ran out (its error flag set) leaves its state undefined, so the context
+// becomes unusable.
+rteaal_status check_grid(rteaal_ctx* ctx, const Batch& b) {
+  if (!b.persistent || !b.gsync.p) return RTEAAL_OK;
+  GridSync g{};
+  HIP_TRY(ctx, hipMemcpy(&g, b.gsync.p, sizeof g, hipMemcpyDeviceToHost));
+  if (g.error) {
+    ctx->poisoned = true;
+    return fail(ctx, RTEAAL_E_DEVICE, "batch %u: a grid barrier wait exceeded its limit of %u spins",
+                b.id, ctx->spin_limit);
+  }
+  return RTEAAL_OK;
+}
+
+// The register digest of every instance after a cycle (SWEEP and LAYERED;
+// RESIDENT folds it inside its kernel).
+hipError_t digest(const DesignHost& h, const Batch& b, hipStream_t s) {
+  uint64_t* d = (uint64_t*)b.dig.p;
+  return launch_digest(b.mapping == RTEAAL_MAP_SWEEP, b.L, (const char*)b.state.p,
+                       (const SlotRef*)h.d_reg_refs.p, h.n_regs, b.n_inst, d, d + b.n_slot, s);
 }
 
 // Launches of one layer's common operations: one per operand count when the
@@ -824,11 +886,260 @@ std::vector<TilePass> tile_passes(const Batch& b) {
   return out;
 }
 
+// Captured multi-batch cycles kept per context.  A full cache is not
+// evicted: sets beyond it are stepped batch by batch, and a captured cycle
+// goes when one of its batches is freed.
+constexpr size_t kMaxMultiGraphs = 16;
+
+void drop_multi_graph(rteaal_ctx* ctx, size_t k) {
+  MultiGraph& g = *ctx->mgraphs[k];
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  dev_free(ctx, g.table);
+  ctx->mgraphs.erase(ctx->mgraphs.begin() + (long)k);
+}
+
+// Forgets every captured multi-batch cycle that involves batch id (before
+// its memory is freed).  The caller has waited for the stream.
+void drop_multi_graphs_of(rteaal_ctx* ctx, uint32_t id) {
+  for (size_t k = ctx->mgraphs.size(); k-- > 0;) {
+    const auto& ids = ctx->mgraphs[k]->ids;
+    if (std::binary_search(ids.begin(), ids.end(), id)) drop_multi_graph(ctx, k);
+  }
+}
+
+// Captures one cycle of the batches `bs` (SWEEP or LAYERED, not watched, no
+// tile passes, not timed) as a single graph.  Every batch's layers are
+// spread over S = (most layers of any batch) slots, layer i of a batch with
+// L layers at slot floor(i S / L), so that each slot holds a similar share
+// of the work; the launches of one slot (common operations per tile group,
+// heavy operations, fused mux chains, LAYERED layers) each cover every batch
+// with a layer there, read only earlier slots' results and write disjoint
+// slots, so they run as parallel branches.
+rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
+                                std::unique_ptr<MultiGraph>* out) {
+  struct Launch {
+    uint32_t kind, tg;
+    std::vector<MultiSeg> segs;
+    std::vector<uint32_t> wave0;
+    size_t off = 0;  // byte offset of the table in the device buffer
+  };
+  uint32_t S = 0;
+  for (Batch* b : bs) S = std::max<uint32_t>(S, (uint32_t)find_design(ctx, b->design)->layers.size());
+  std::vector<std::vector<Launch>> slots(S);
+  auto add = [&](uint32_t t, uint32_t kind, uint32_t tg, const MultiSeg& seg, uint64_t waves) {
+    if (!waves) return true;
+    auto& v = slots[t];
+    Launch* l = nullptr;
+    for (auto& x : v)
+      if (x.kind == kind && x.tg == tg) l = &x;
+    if (!l) {
+      v.push_back(Launch{kind, tg, {}, {0u}, 0});
+      l = &v.back();
+    }
+    const uint64_t end = (uint64_t)l->wave0.back() + waves;
+    if (end >= (1ull << 31)) return false;
+    l->segs.push_back(seg);
+    l->wave0.push_back((uint32_t)end);
+    return true;
+  };
+  std::vector<DigestSeg> dsegs;
+  std::vector<uint32_t> dwave0{0u};
+  uint32_t max_inst = 0;
+  for (Batch* b : bs) {
+    const DesignHost& h = *find_design(ctx, b->design);
+    const uint32_t Lb = (uint32_t)h.layers.size();
+    MultiSeg base{};
+    base.ops = (const DevOp*)h.d_ops.p;
+    base.layers = (const DevLayer*)h.d_layers.p;
+    base.const_limbs = (const uint64_t*)h.d_consts.p;
+    base.state = (char*)b->state.p;
+    base.seeds = (const uint64_t*)b->seeds.p;
+    base.ctl = (const DevCtl*)b->ctl.p;
+    base.L = b->L;
+    base.n_inst = b->n_inst;
+    base.words_per_inst = h.words_per_inst;
+    base.opw = b->opw ? b->opw : 16u;
+    const bool sweep = b->mapping == RTEAAL_MAP_SWEEP;
+    const uint32_t T = b->L.n_tiles_alloc;
+    for (uint32_t li = 0; li < Lb; ++li) {
+      const uint32_t t = (uint32_t)((uint64_t)li * S / Lb);
+      const DevLayer& ly = h.layers[li];
+      MultiSeg g = base;
+      g.layer = li;
+      bool ok = true;
+      if (sweep) {
+        const uint32_t opw = g.opw;
+        const uint32_t n1 = ly.hbeg - ly.begin, n2 = ly.end - ly.hend;
+        g.r = OpRanges{ly.begin, ly.hbeg, ly.hend, ly.end};
+        g.split = (n1 + opw - 1) / opw;
+        g.n_groups = T / b->tg;
+        ok = ok && add(t, 0, b->tg, g, (uint64_t)(g.split + (n2 + opw - 1) / opw) * g.n_groups);
+        const uint32_t th = std::min(b->tg, 2u);
+        const uint32_t h1 = ly.hm0 - ly.hbeg, h2 = ly.hend - ly.hm1;
+        g.n_groups = T / th;
+        ok = ok && add(t, 1, th, g,
+                       (uint64_t)((h1 + opw - 1) / opw + (h2 + opw - 1) / opw) * g.n_groups);
+        const uint32_t tm = b->tg >= 4 ? 4u : b->tg;
+        g.n_groups = T / tm;
+        ok = ok && add(t, 2, tm, g, (uint64_t)(ly.hm1 - ly.hm0) * g.n_groups);
+      } else {
+        const uint32_t n = ly.end - ly.begin;
+        g.n_groups = (n + 63u) / 64u;
+        ok = ok && add(t, 3, 1, g, (uint64_t)g.n_groups * b->n_inst);
+      }
+      if (!ok) return fail(ctx, RTEAAL_E_UNSUPPORTED, "too many wavefronts for one multi-batch launch");
+    }
+    DigestSeg d{};
+    d.L = b->L;
+    d.state = (const char*)b->state.p;
+    d.regs = (const SlotRef*)h.d_reg_refs.p;
+    d.digest = (uint64_t*)b->dig.p;
+    d.acc = (uint64_t*)b->dig.p + b->n_slot;
+    d.ctl = (DevCtl*)b->ctl.p;
+    d.n_regs = h.n_regs;
+    d.n_inst = b->n_inst;
+    d.sweep = sweep ? 1u : 0u;
+    digest_shape(sweep, h.n_regs, b->n_inst, &d.n_units, &d.per);
+    const uint64_t dw = h.n_regs ? (uint64_t)d.n_units * ((h.n_regs + d.per - 1) / d.per) : 0;
+    if ((uint64_t)dwave0.back() + dw >= (1ull << 31))
+      return fail(ctx, RTEAAL_E_UNSUPPORTED, "too many wavefronts for one multi-batch digest");
+    dsegs.push_back(d);
+    dwave0.push_back(dwave0.back() + (uint32_t)dw);
+    max_inst = std::max(max_inst, b->n_inst);
+  }
+  // One device buffer: every launch's segments and prefix, then the digest's.
+  size_t bytes = 0;
+  auto place = [&](size_t n) {
+    const size_t o = bytes;
+    bytes = (bytes + n + 255) & ~size_t(255);
+    return o;
+  };
+  for (auto& v : slots)
+    for (auto& l : v) {
+      l.off = place(l.segs.size() * sizeof(MultiSeg));
+      place(l.wave0.size() * 4);
+    }
+  const size_t doff = place(dsegs.size() * sizeof(DigestSeg));
+  const size_t dwoff = place(dwave0.size() * 4);
+  std::vector<char> host(bytes, 0);
+  for (auto& v : slots)
+    for (auto& l : v) {
+      memcpy(host.data() + l.off, l.segs.data(), l.segs.size() * sizeof(MultiSeg));
+      const size_t woff = (l.off + l.segs.size() * sizeof(MultiSeg) + 255) & ~size_t(255);
+      memcpy(host.data() + woff, l.wave0.data(), l.wave0.size() * 4);
+    }
+  memcpy(host.data() + doff, dsegs.data(), dsegs.size() * sizeof(DigestSeg));
+  memcpy(host.data() + dwoff, dwave0.data(), dwave0.size() * 4);
+  auto g = std::make_unique<MultiGraph>();
+  for (Batch* b : bs) g->ids.push_back(b->id);
+  std::sort(g->ids.begin(), g->ids.end());
+  if (!alloc_all(ctx, {{&g->table, bytes}}))
+    return fail(ctx, RTEAAL_E_NO_MEMORY, "multi-batch table allocation failed");
+  char* dev = (char*)g->table.p;
+  hipError_t e = hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+    if (!ctx->cap[k]) e = hipStreamCreateWithFlags(&ctx->cap[k], hipStreamNonBlocking);
+    if (e == hipSuccess && !ctx->cap_join[k])
+      e = hipEventCreateWithFlags(&ctx->cap_join[k], hipEventDisableTiming);
+  }
+  if (e == hipSuccess && !ctx->cap_fork) e = hipEventCreateWithFlags(&ctx->cap_fork, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    dev_free(ctx, g->table);
+    ctx->poisoned = true;
+    return fail(ctx, RTEAAL_E_DEVICE, "multi-batch set-up: %s", hipGetErrorString(e));
+  }
+  hipGraph_t graph = nullptr;
+  e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+  for (auto& v : slots) {
+    if (e != hipSuccess) break;
+    const size_t n_fork = std::min<size_t>(v.size(), 4) - (v.empty() ? 0 : 1);
+    if (n_fork) {
+      e = hipEventRecord(ctx->cap_fork, ctx->stream);
+      for (size_t k = 0; k < n_fork && e == hipSuccess; ++k)
+        e = hipStreamWaitEvent(ctx->cap[k], ctx->cap_fork, 0);
+    }
+    for (size_t k = 0; k < v.size() && e == hipSuccess; ++k) {
+      const Launch& l = v[k];
+      const size_t woff = (l.off + l.segs.size() * sizeof(MultiSeg) + 255) & ~size_t(255);
+      hipStream_t s2 = k == 0 || k > n_fork ? ctx->stream : ctx->cap[k - 1];
+      e = launch_multi(l.kind, l.tg, (const MultiSeg*)(dev + l.off), (const uint32_t*)(dev + woff),
+                       (uint32_t)l.segs.size(), l.wave0.back(), s2);
+      ++g->launches;
+    }
+    for (size_t k = 0; k < n_fork && e == hipSuccess; ++k) {
+      e = hipEventRecord(ctx->cap_join[k], ctx->cap[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(ctx->stream, ctx->cap_join[k], 0);
+    }
+  }
+  if (e == hipSuccess)
+    e = launch_digest_multi((const DigestSeg*)(dev + doff), (const uint32_t*)(dev + dwoff),
+                            (uint32_t)dsegs.size(), dwave0.back(), max_inst, ctx->stream);
+  hipError_t e2 = hipStreamEndCapture(ctx->stream, &graph);
+  if (e == hipSuccess && e2 == hipSuccess) e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    g->exec = nullptr;
+    dev_free(ctx, g->table);
+    ctx->poisoned = true;
+    return fail(ctx, RTEAAL_E_DEVICE, "multi-batch graph capture failed: %s",
+                hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  *out = std::move(g);
+  return RTEAAL_OK;
+}
+
+// The cached captured cycle of batch set bs, or null.
+MultiGraph* cached_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs) {
+  std::vector<uint32_t> ids;
+  for (Batch* b : bs) ids.push_back(b->id);
+  std::sort(ids.begin(), ids.end());
+  for (auto& g : ctx->mgraphs)
+    if (g->ids == ids) return g.get();
+  return nullptr;
+}
+
+// The captured cycle of batch set bs, built on first use.  The caller has
+// checked that the cache has room (a captured cycle is dropped only when one
+// of its batches is freed, or with the context).
+rteaal_status multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs, MultiGraph** out) {
+  if (MultiGraph* g = cached_multi_graph(ctx, bs)) {
+    g->last_use = ++ctx->mg_clock;
+    *out = g;
+    return RTEAAL_OK;
+  }
+  if (ctx->mgraphs.size() >= kMaxMultiGraphs)
+    return fail(ctx, RTEAAL_E_UNSUPPORTED, "multi-batch graph cache full");
+  std::unique_ptr<MultiGraph> g;
+  const rteaal_status st = build_multi_graph(ctx, bs, &g);
+  if (st != RTEAAL_OK) return st;
+  g->last_use = ++ctx->mg_clock;
+  *out = g.get();
+  ctx->mgraphs.push_back(std::move(g));
+  return RTEAAL_OK;
+}
+
 // LAYERED: one launch per (non-empty) layer for all instances, then the
 // cycle advance and the capture; the cycle is captured once as a HIP graph.
 rteaal_status enqueue_layered(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t n_cycles) {
   const ResJob J = res_job(h, b, 1);
   DevCtl* ctl = (DevCtl*)b.ctl.p;
+  if (b.persistent) {
+    // A watched batch runs one cycle per launch, so each cycle is captured.
+    const uint64_t chunk = b.n_watch ? 1 : kResidentChunk;
+    for (uint64_t done = 0; done < n_cycles;) {
+      const uint64_t n = std::min(chunk, n_cycles - done);
+      HIP_TRY(ctx, timed(b, ctx->stream, 0, [&] {
+                return launch_layer_persistent(res_job(h, b, n), b.n_inst, b.unroll,
+                                               (GridSync*)b.gsync.p, (uint64_t*)b.dig.p + b.n_slot,
+                                               ctx->spin_limit, 0, ctx->stream);
+              }));
+      HIP_TRY(ctx, launch_advance(ctl, n, ctx->stream));
+      HIP_TRY(ctx, capture(b, ctx->stream));
+      done += n;
+    }
+    return RTEAAL_OK;
+  }
   auto cycle = [&](hipStream_t s, bool timed_launches) -> hipError_t {
     hipError_t e = hipSuccess;
     for (uint32_t li = 0; li < h.layers.size() && e == hipSuccess; ++li) {
@@ -837,6 +1148,7 @@ rteaal_status enqueue_layered(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t
       auto go = [&] { return launch_layer(J, li, n, b.n_inst, b.block, b.unroll, s); };
       e = timed_launches ? timed(b, s, 0, go) : go();
     }
+    if (e == hipSuccess) e = digest(h, b, s);
     if (e == hipSuccess) e = launch_advance(ctl, 1, s);
     if (e == hipSuccess) e = capture(b, s);
     return e;
@@ -905,6 +1217,7 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
                                                 b.tg, tp, ctx->stream);
                     }));
         }
+      HIP_TRY(ctx, digest(h, b, ctx->stream));
       HIP_TRY(ctx, launch_advance(ctl, 1, ctx->stream));
       HIP_TRY(ctx, capture(b, ctx->stream));
     }
@@ -962,6 +1275,7 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
           if (e == hipSuccess) e = hipStreamWaitEvent(ctx->stream, ctx->cap_join[k], 0);
         }
       }
+    if (e == hipSuccess) e = digest(h, b, ctx->stream);
     if (e == hipSuccess) e = launch_advance(ctl, 1, ctx->stream);
     if (e == hipSuccess) e = capture(b, ctx->stream);
     hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
@@ -1015,6 +1329,8 @@ rteaal_status rteaal_create(int device, void* stream, const rteaal_allocator* al
     if (e != hipSuccess) return fail(nullptr, RTEAAL_E_DEVICE, "stream: %s", hipGetErrorString(e));
     ctx->own_stream = true;
   }
+  if (const char* sl = std::getenv("RTEAAL_GRID_SPIN_LIMIT"))
+    ctx->spin_limit = (uint32_t)std::max(1L, std::min(std::atol(sl), (long)UINT32_MAX));
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess)
     ctx->max_lds = std::min<size_t>(prop.maxSharedMemoryPerMultiProcessor, resident_max_lds());
@@ -1035,6 +1351,8 @@ void rteaal_destroy(rteaal_ctx* ctx) {
     dev_free(ctx, b.state);
     dev_free(ctx, b.seeds);
     dev_free(ctx, b.ctl);
+    dev_free(ctx, b.dig);
+    dev_free(ctx, b.gsync);
   }
   for (auto& kv : ctx->designs) {
     DesignHost& h = *kv.second;
@@ -1045,6 +1363,7 @@ void rteaal_destroy(rteaal_ctx* ctx) {
     dev_free(ctx, h.d_slot_refs);
   }
   dev_free(ctx, ctx->multi);
+  while (!ctx->mgraphs.empty()) drop_multi_graph(ctx, ctx->mgraphs.size() - 1);
   for (int k = 0; k < 4; ++k) {
     if (ctx->aux[k]) (void)hipStreamDestroy(ctx->aux[k]);
     if (ctx->join[k]) (void)hipEventDestroy(ctx->join[k]);
@@ -1306,6 +1625,19 @@ rteaal_status rteaal_load_design_ex(rteaal_ctx* ctx, const rteaal_design_desc* d
   if (!h->reg_refs.empty())
     HIP_TRY(ctx, hipMemcpyAsync(h->d_reg_refs.p, h->reg_refs.data(), h->reg_refs.size() * sizeof(SlotRef),
                                 hipMemcpyHostToDevice, ctx->stream));
+  if (!h->compact && !h->slot_refs.empty()) {  // all-slot read-out needs the slot table
+    if (!alloc_all(ctx, {{&h->d_slot_refs, h->slot_refs.size() * sizeof(SlotRef)}})) {
+      (void)hipStreamSynchronize(ctx->stream);
+      dev_free(ctx, h->d_ops);
+      dev_free(ctx, h->d_layers);
+      dev_free(ctx, h->d_consts);
+      dev_free(ctx, h->d_reg_refs);
+      return fail(ctx, RTEAAL_E_NO_MEMORY, "device allocation for the design failed");
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(h->d_slot_refs.p, h->slot_refs.data(),
+                                h->slot_refs.size() * sizeof(SlotRef), hipMemcpyHostToDevice,
+                                ctx->stream));
+  }
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // host vectors stay alive; uploads done
   h->id = ctx->next_id++;
   *out = h->id;
@@ -1352,7 +1684,7 @@ rteaal_status rteaal_batch_footprint(rteaal_ctx* ctx, rteaal_design_id id, uint3
   if (!make_layout(*h, m, n_inst, sweep_tg(opts), &L, &sb))
     return fail(ctx, RTEAAL_E_INVALID_ARG, "too many instances for one SWEEP batch");
   const uint64_t pad = m == RTEAAL_MAP_SWEEP ? (uint64_t)L.n_tiles_alloc * 64 : n_inst;
-  *bytes = sb + pad * 8 + 256 + 512;
+  *bytes = sb + pad * 24 + 256 + 512;
   return RTEAAL_OK;
 }
 
@@ -1403,6 +1735,11 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
     if (blk % 64 || blk > 256)
       return fail(ctx, RTEAAL_E_INVALID_ARG, "LAYERED block_threads must be 64, 128, 192 or 256");
     b->block = blk;
+    if (opts && opts->persistent > 1)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "LAYERED persistent must be 0 or 1");
+    b->persistent = opts && opts->persistent == 1;
+    if (b->persistent && u == 4)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "persistent LAYERED unroll must be 1 or 2");
   } else {
     b->opw = opts && opts->ops_per_wave ? opts->ops_per_wave : 16;
     const uint32_t u = opts && opts->unroll ? opts->unroll : 2u;
@@ -1425,13 +1762,16 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
     b->tpp = tpp >= b->L.n_tiles_alloc ? 0u : tpp;
   }
   const uint64_t n_seed = b->mapping == RTEAAL_MAP_SWEEP ? (uint64_t)b->L.n_tiles_alloc * 64 : n_inst;
-  if (!alloc_all(ctx, {{&b->state, sb}, {&b->seeds, n_seed * 8}, {&b->ctl, sizeof(DevCtl)}}))
+  b->n_slot = n_seed;
+  if (!alloc_all(ctx, {{&b->state, sb}, {&b->seeds, n_seed * 8}, {&b->ctl, sizeof(DevCtl)},
+                       {&b->dig, n_seed * 16}, {&b->gsync, b->persistent ? sizeof(GridSync) : 0}}))
     return fail(ctx, RTEAAL_E_NO_MEMORY, "device allocation of %llu bytes for the batch failed",
                 (unsigned long long)sb);
   std::vector<uint64_t> sd(n_seed, 0);
   std::copy(seeds, seeds + n_inst, sd.begin());
   DevCtl c0{};
   hipError_t e = hipMemsetAsync(b->state.p, 0, sb ? sb : 256, ctx->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(b->dig.p, 0, n_seed * 16, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(b->seeds.p, sd.data(), n_seed * 8, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(b->ctl.p, &c0, sizeof c0, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -1439,6 +1779,8 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
     dev_free(ctx, b->state);
     dev_free(ctx, b->seeds);
     dev_free(ctx, b->ctl);
+    dev_free(ctx, b->dig);
+    dev_free(ctx, b->gsync);
     ctx->poisoned = true;
     return fail(ctx, RTEAAL_E_DEVICE, "batch initialisation failed: %s", hipGetErrorString(e));
   }
@@ -1454,12 +1796,15 @@ rteaal_status rteaal_free_batch(rteaal_ctx* ctx, rteaal_batch_id id) {
   Batch* b = find_batch(ctx, id);
   if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
   (void)hipStreamSynchronize(ctx->stream);
+  drop_multi_graphs_of(ctx, id);
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   destroy_events(*b);
   free_watch(ctx, *b);
   dev_free(ctx, b->state);
   dev_free(ctx, b->seeds);
   dev_free(ctx, b->ctl);
+  dev_free(ctx, b->dig);
+  dev_free(ctx, b->gsync);
   DesignHost* h = find_design(ctx, b->design);
   if (h) h->n_batches--;
   ctx->batches.erase(id);
@@ -1489,6 +1834,7 @@ rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id id, rteaal_b
     o.lds_ops = b->lds_ops ? 0u : 1u;
   } else if (b->mapping == RTEAAL_MAP_LAYERED) {
     o.block_threads = b->block;
+    o.persistent = b->persistent ? 1u : 0u;
   } else if (b->mapping == RTEAAL_MAP_SWEEP) {
     o.ops_per_wave = b->opw;
     o.tiles_per_wave = b->tg;
@@ -1499,6 +1845,47 @@ rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id id, rteaal_b
   return RTEAAL_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Checks a step's stimulus for batch b over n_cycles.
+rteaal_status check_stimulus(rteaal_ctx* ctx, const DesignHost& h, const rteaal_stimulus* stim,
+                             uint64_t n_cycles) {
+  if (stim && stim->mode > 1) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown stimulus mode %u", stim->mode);
+  if (stim && stim->mode == 1 && !stim->words && h.words_per_inst && n_cycles)
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "stimulus words are null");
+  return RTEAAL_OK;
+}
+
+// Device address of a step's words stimulus (null for the generator): the
+// caller's device buffer, or host words copied into *tmp on the context's
+// stream (the caller frees *tmp once the step has completed).
+rteaal_status stimulus_words(rteaal_ctx* ctx, const DesignHost& h, const Batch& b,
+                             const rteaal_stimulus* stim, uint64_t n_cycles, Mem* tmp,
+                             const uint64_t** words) {
+  *words = nullptr;
+  if (!stim || stim->mode != 1 || !h.words_per_inst || !n_cycles) return RTEAAL_OK;
+  if (stim->words_on_device) {
+    *words = stim->words;
+    return RTEAAL_OK;
+  }
+  const size_t wb = (size_t)n_cycles * b.n_inst * h.words_per_inst * 8;
+  if (!alloc_all(ctx, {{tmp, wb}})) return fail(ctx, RTEAAL_E_NO_MEMORY, "stimulus buffer allocation failed");
+  hipError_t e = hipMemcpyAsync(tmp->p, stim->words, wb, hipMemcpyHostToDevice, ctx->stream);
+  if (e != hipSuccess) {
+    dev_free(ctx, *tmp);
+    ctx->poisoned = true;
+    return fail(ctx, RTEAAL_E_DEVICE, "stimulus upload: %s", hipGetErrorString(e));
+  }
+  *words = (const uint64_t*)tmp->p;
+  return RTEAAL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 rteaal_status rteaal_step(rteaal_ctx* ctx, rteaal_batch_id id, uint64_t n_cycles,
                           const rteaal_stimulus* stim) {
   if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
@@ -1506,29 +1893,14 @@ rteaal_status rteaal_step(rteaal_ctx* ctx, rteaal_batch_id id, uint64_t n_cycles
   Batch* b = find_batch(ctx, id);
   if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
   DesignHost& h = *find_design(ctx, b->design);
-  if (stim && stim->mode > 1) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown stimulus mode %u", stim->mode);
-  const bool buffered = stim && stim->mode == 1;
-  if (buffered && !stim->words && h.words_per_inst && n_cycles)
-    return fail(ctx, RTEAAL_E_INVALID_ARG, "stimulus words are null");
+  rteaal_status st0 = check_stimulus(ctx, h, stim, n_cycles);
+  if (st0 != RTEAAL_OK) return st0;
   if (n_cycles == 0) return RTEAAL_OK;
   DevCtl* ctl = (DevCtl*)b->ctl.p;
   Mem tmp;
   const uint64_t* words = nullptr;
-  if (buffered && h.words_per_inst) {
-    if (stim->words_on_device) {
-      words = stim->words;
-    } else {
-      const size_t wb = (size_t)n_cycles * b->n_inst * h.words_per_inst * 8;
-      if (!alloc_all(ctx, {{&tmp, wb}})) return fail(ctx, RTEAAL_E_NO_MEMORY, "stimulus buffer allocation failed");
-      hipError_t e = hipMemcpyAsync(tmp.p, stim->words, wb, hipMemcpyHostToDevice, ctx->stream);
-      if (e != hipSuccess) {
-        dev_free(ctx, tmp);
-        ctx->poisoned = true;
-        return fail(ctx, RTEAAL_E_DEVICE, "stimulus upload: %s", hipGetErrorString(e));
-      }
-      words = (const uint64_t*)tmp.p;
-    }
-  }
+  st0 = stimulus_words(ctx, h, *b, stim, n_cycles, &tmp, &words);
+  if (st0 != RTEAAL_OK) return st0;
   HIP_TRY(ctx, launch_set_words(ctl, words, ctx->stream));
   rteaal_status st = enqueue_cycles(ctx, h, *b, n_cycles);
   if (tmp.p) {
@@ -1541,7 +1913,7 @@ rteaal_status rteaal_step(rteaal_ctx* ctx, rteaal_batch_id id, uint64_t n_cycles
 }
 
 rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_id* ids,
-                               const uint64_t* n_cycles) {
+                               const uint64_t* n_cycles, const rteaal_stimulus* stims) {
   if (!ctx || (n && (!ids || !n_cycles))) return fail(ctx, RTEAAL_E_INVALID_ARG, "bad argument");
   if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
   std::vector<Batch*> bs(n);
@@ -1550,31 +1922,144 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
     if (!bs[k]) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", ids[k]);
     for (uint32_t q = 0; q < k; ++q)
       if (ids[q] == ids[k]) return fail(ctx, RTEAAL_E_INVALID_ARG, "batch %u listed twice", ids[k]);
+    const rteaal_status st = check_stimulus(ctx, *find_design(ctx, bs[k]->design),
+                                            stims ? &stims[k] : nullptr, n_cycles[k]);
+    if (st != RTEAAL_OK) return st;
   }
-  for (uint32_t k = 0; k < n; ++k) HIP_TRY(ctx, launch_set_words((DevCtl*)bs[k]->ctl.p, nullptr, ctx->stream));
-
-  // SWEEP and LAYERED batches: each on an auxiliary stream, forked from and
-  // joined back into the context stream, so their layer kernels overlap.
-  uint32_t n_aux = 0;
+  // Host words are copied to device buffers that live until the step has
+  // completed; auxiliary streams forked below are joined back into the
+  // context stream on every exit path, so that nothing the step enqueued
+  // outlives a later wait on the context stream.
+  std::vector<Mem> tmps(n);
+  uint32_t n_forked = 0;
+  struct Finish {
+    rteaal_ctx* ctx;
+    std::vector<Mem>& tmps;
+    uint32_t& n_forked;
+    ~Finish() {
+      for (uint32_t a = 0; a < n_forked; ++a) {
+        if (hipEventRecord(ctx->join[a], ctx->aux[a]) != hipSuccess ||
+            hipStreamWaitEvent(ctx->stream, ctx->join[a], 0) != hipSuccess)
+          (void)hipStreamSynchronize(ctx->aux[a]);
+      }
+      bool any = false;
+      for (Mem& m : tmps) any = any || m.p;
+      if (any) {
+        (void)hipStreamSynchronize(ctx->stream);
+        for (Mem& m : tmps) dev_free(ctx, m);
+      }
+    }
+  } finish{ctx, tmps, n_forked};
   for (uint32_t k = 0; k < n; ++k) {
-    Batch& b = *bs[k];
+    const uint64_t* words = nullptr;
+    const rteaal_status st = stimulus_words(ctx, *find_design(ctx, bs[k]->design), *bs[k],
+                                            stims ? &stims[k] : nullptr, n_cycles[k], &tmps[k], &words);
+    if (st != RTEAAL_OK) return st;
+    HIP_TRY(ctx, launch_set_words((DevCtl*)bs[k]->ctl.p, words, ctx->stream));
+  }
+
+  // SWEEP and LAYERED batches.  Those that are not watched, timed or run in
+  // tile passes advance together through captured multi-batch cycles (one
+  // graph per set of batches that still have cycles to go, so batches with
+  // fewer cycles drop out in order); the rest each replay their own cycle
+  // graph.  Each kind runs on an auxiliary stream forked from the context
+  // stream, beside the RESIDENT launches on the context stream.
+  std::vector<uint32_t> multi, single;
+  for (uint32_t k = 0; k < n; ++k) {
+    const Batch& b = *bs[k];
     if (b.mapping == RTEAAL_MAP_RESIDENT || n_cycles[k] == 0) continue;
-    const uint32_t a = n_aux % 4;
+    if (!b.n_watch && !b.profile && b.tpp == 0 && !b.persistent) multi.push_back(k);
+    else single.push_back(k);
+  }
+  if (multi.size() == 1) {
+    single.push_back(multi[0]);
+    multi.clear();
+  }
+  std::vector<std::pair<MultiGraph*, uint64_t>> replays;  // graph, cycles
+  int tail = -1;  // a batch left alone for the last cycles, after the replays
+  uint64_t tail_cycles = 0;
+  {
+    std::vector<uint64_t> counts;
+    for (uint32_t k : multi) counts.push_back(n_cycles[k]);
+    std::sort(counts.begin(), counts.end());
+    counts.erase(std::unique(counts.begin(), counts.end()), counts.end());
+    // The cache must hold every set of this call's phases; otherwise the
+    // batches are stepped one by one (captured cycles are not evicted).
+    size_t need = 0;
+    for (uint64_t c : counts) {
+      std::vector<Batch*> set;
+      for (uint32_t k : multi)
+        if (n_cycles[k] >= c) set.push_back(bs[k]);
+      if (set.size() >= 2 && !cached_multi_graph(ctx, set)) ++need;
+    }
+    if (ctx->mgraphs.size() + need > kMaxMultiGraphs) {
+      single.insert(single.end(), multi.begin(), multi.end());
+      multi.clear();
+      counts.clear();
+    }
+    uint64_t prev = 0;
+    for (uint64_t c : counts) {
+      std::vector<Batch*> set;
+      int last = -1;
+      for (uint32_t k : multi)
+        if (n_cycles[k] >= c) {
+          set.push_back(bs[k]);
+          last = (int)k;
+        }
+      if (set.size() == 1) {
+        tail = last;
+        tail_cycles = n_cycles[last] - prev;
+        break;
+      }
+      MultiGraph* g = nullptr;
+      const rteaal_status st = multi_graph(ctx, set, &g);
+      if (st != RTEAAL_OK) return st;
+      replays.push_back({g, c - prev});
+      prev = c;
+    }
+  }
+  auto fork_aux = [&](uint32_t a) -> rteaal_status {
     if (!ctx->aux[a]) {
       HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->aux[a], hipStreamNonBlocking));
       HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->join[a], hipEventDisableTiming));
     }
     if (!ctx->fork) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
-    if (n_aux < 4) {
+    if (a >= n_forked) {
       HIP_TRY(ctx, hipEventRecord(ctx->fork, ctx->stream));
       HIP_TRY(ctx, hipStreamWaitEvent(ctx->aux[a], ctx->fork, 0));
+      n_forked = a + 1;
     }
+    return RTEAAL_OK;
+  };
+  // Runs batch k alone for c cycles on auxiliary stream a.
+  auto run_alone = [&](uint32_t k, uint64_t c, uint32_t a) -> rteaal_status {
+    Batch& b = *bs[k];
     hipStream_t keep = ctx->stream;
     ctx->stream = ctx->aux[a];
-    rteaal_status st = enqueue_cycles(ctx, *find_design(ctx, b.design), b, n_cycles[k]);
+    const rteaal_status st = enqueue_cycles(ctx, *find_design(ctx, b.design), b, c);
     ctx->stream = keep;
+    return st;
+  };
+  uint32_t n_aux = 0;
+  if (!replays.empty()) {
+    rteaal_status st = fork_aux(0);
     if (st != RTEAAL_OK) return st;
-    b.cycle += n_cycles[k];
+    for (auto& r : replays)
+      for (uint64_t c = 0; c < r.second; ++c) HIP_TRY(ctx, hipGraphLaunch(r.first->exec, ctx->aux[0]));
+    if (tail >= 0) {
+      st = run_alone((uint32_t)tail, tail_cycles, 0);
+      if (st != RTEAAL_OK) return st;
+    }
+    for (uint32_t k : multi) bs[k]->cycle += n_cycles[k];
+    n_aux = 1;
+  }
+  for (uint32_t k : single) {
+    const uint32_t a = n_aux < 4 ? n_aux : 1u + (n_aux - 1u) % 3u;
+    rteaal_status st = fork_aux(a);
+    if (st != RTEAAL_OK) return st;
+    st = run_alone(k, n_cycles[k], a);
+    if (st != RTEAAL_OK) return st;
+    bs[k]->cycle += n_cycles[k];
     ++n_aux;
   }
 
@@ -1627,8 +2112,10 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
       if (ctx->multi.bytes < need) {
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
         dev_free(ctx, ctx->multi);
-        if (!alloc_all(ctx, {{&ctx->multi, std::max<size_t>(need, 1u << 16) * 2}}))
+        if (!alloc_all(ctx, {{&ctx->multi, std::max<size_t>(need, 1u << 16) * 2}})) {
+          ctx->poisoned = true;  // batches before this group have advanced, the rest have not
           return fail(ctx, RTEAAL_E_NO_MEMORY, "job table allocation failed");
+        }
       }
       std::vector<char> blob(need);
       memcpy(blob.data(), jobs.data(), jobs.size() * sizeof(ResJob));
@@ -1644,29 +2131,50 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
     }
     for (uint32_t k : g.second) bs[k]->cycle += n_cycles[k];
   }
-  for (uint32_t a = 0; a < std::min<uint32_t>(n_aux, 4); ++a) {
-    HIP_TRY(ctx, hipEventRecord(ctx->join[a], ctx->aux[a]));
-    HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, ctx->join[a], 0));
-  }
-  return RTEAAL_OK;
+  return RTEAAL_OK;  // `finish` joins the auxiliary streams
 }
 
 rteaal_status rteaal_sync(rteaal_ctx* ctx) {
   if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& kv : ctx->batches) {
+    const rteaal_status st = check_grid(ctx, *kv.second);
+    if (st != RTEAAL_OK) return st;
+  }
   return RTEAAL_OK;
 }
 
-rteaal_status rteaal_read_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first, uint32_t n,
-                                uint32_t what, uint64_t* out, size_t out_words, size_t* written) {
+}  // extern "C"
+
+namespace {
+
+// rteaal_read_state; stage: null (a buffer is allocated for the call) or a
+// device buffer of stage_words words to stage the read-out through.
+rteaal_status read_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first, uint32_t n,
+                         uint32_t what, uint64_t* out, size_t out_words, size_t* written,
+                         uint64_t* stage, size_t stage_words) {
   if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
   if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
   Batch* b = find_batch(ctx, id);
   if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
   if ((uint64_t)first + n > b->n_inst) return fail(ctx, RTEAAL_E_INVALID_ARG, "instance range out of bounds");
-  if (what != RTEAAL_READ_REGS && what != RTEAAL_READ_ALL_SLOTS)
+  if (what != RTEAAL_READ_REGS && what != RTEAAL_READ_ALL_SLOTS && what != RTEAAL_READ_DIGEST)
     return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown read kind %u", what);
   DesignHost& h = *find_design(ctx, b->design);
+  if (what == RTEAAL_READ_DIGEST) {
+    if (written) *written = n;
+    if (n == 0) return RTEAAL_OK;
+    if (!out || out_words < n)
+      return fail(ctx, RTEAAL_E_INVALID_ARG, "output holds %zu words, %u needed", out_words, n);
+    hipError_t e = hipMemcpyAsync(out, (const uint64_t*)b->dig.p + first, (size_t)n * 8,
+                                  hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      ctx->poisoned = true;
+      return fail(ctx, RTEAAL_E_DEVICE, "read_state: %s", hipGetErrorString(e));
+    }
+    return check_grid(ctx, *b);
+  }
   const bool slots = what == RTEAAL_READ_ALL_SLOTS;
   if (slots && h.compact)
     return fail(ctx, RTEAAL_E_UNSUPPORTED,
@@ -1678,25 +2186,36 @@ rteaal_status rteaal_read_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t fi
   if (need == 0) return RTEAAL_OK;
   if (!out || out_words < need)
     return fail(ctx, RTEAAL_E_INVALID_ARG, "output holds %zu words, %zu needed", out_words, need);
-  if (slots && !h.d_slot_refs.p) {
-    if (!alloc_all(ctx, {{&h.d_slot_refs, h.slot_refs.size() * sizeof(SlotRef)}}))
-      return fail(ctx, RTEAAL_E_NO_MEMORY, "slot table allocation failed");
-    HIP_TRY(ctx, hipMemcpyAsync(h.d_slot_refs.p, h.slot_refs.data(), h.slot_refs.size() * sizeof(SlotRef),
-                                hipMemcpyHostToDevice, ctx->stream));
-  }
+  if (stage && need > stage_words)
+    return fail(ctx, RTEAAL_E_INVALID_ARG,
+                "the read-out needs %zu words, more than the %zu of the staging buffer; read "
+                "fewer instances per call", need, stage_words);
   Mem tmp;
-  if (!alloc_all(ctx, {{&tmp, need * 8}})) return fail(ctx, RTEAAL_E_NO_MEMORY, "read-out buffer allocation failed");
+  if (!stage) {
+    if (!alloc_all(ctx, {{&tmp, need * 8}}))
+      return fail(ctx, RTEAAL_E_NO_MEMORY, "read-out buffer allocation failed");
+    stage = (uint64_t*)tmp.p;
+  }
   const SlotRef* refs = (const SlotRef*)(slots ? h.d_slot_refs.p : h.d_reg_refs.p);
   hipError_t e = launch_pack(b->mapping == RTEAAL_MAP_SWEEP, b->L, (const char*)b->state.p, refs,
-                             n_refs, wpi, first, n, (uint64_t*)tmp.p, ctx->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(out, tmp.p, need * 8, hipMemcpyDeviceToHost, ctx->stream);
+                             n_refs, wpi, first, n, stage, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, stage, need * 8, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   dev_free(ctx, tmp);
   if (e != hipSuccess) {
     ctx->poisoned = true;
     return fail(ctx, RTEAAL_E_DEVICE, "read_state: %s", hipGetErrorString(e));
   }
-  return RTEAAL_OK;
+  return check_grid(ctx, *b);
+}
+
+}  // namespace
+
+extern "C" {
+
+rteaal_status rteaal_read_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first, uint32_t n,
+                                uint32_t what, uint64_t* out, size_t out_words, size_t* written) {
+  return read_state(ctx, id, first, n, what, out, out_words, written, nullptr, 0);
 }
 
 rteaal_status rteaal_write_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first, uint32_t n,
@@ -1728,6 +2247,25 @@ rteaal_status rteaal_write_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t f
     return fail(ctx, RTEAAL_E_DEVICE, "write_state: %s", hipGetErrorString(e));
   }
   b->cycle = cycle;
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_write_digest(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first, uint32_t n,
+                                  const uint64_t* digest) {
+  if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
+  if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
+  Batch* b = find_batch(ctx, id);
+  if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
+  if ((uint64_t)first + n > b->n_inst) return fail(ctx, RTEAAL_E_INVALID_ARG, "instance range out of bounds");
+  if (n && !digest) return fail(ctx, RTEAAL_E_INVALID_ARG, "digest is null");
+  if (n == 0) return RTEAAL_OK;
+  hipError_t e = hipMemcpyAsync((uint64_t*)b->dig.p + first, digest, (size_t)n * 8,
+                                hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    ctx->poisoned = true;
+    return fail(ctx, RTEAAL_E_DEVICE, "write_digest: %s", hipGetErrorString(e));
+  }
   return RTEAAL_OK;
 }
 
@@ -1811,6 +2349,120 @@ rteaal_status rteaal_read_changes(rteaal_ctx* ctx, rteaal_batch_id id, rteaal_ch
   return RTEAAL_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Tuner cache on disk (environment RTEAAL_TUNE_CACHE = file path): one line
+// per tuning, "key rate n o[0] .. o[n-1]", each o ten numbers in the order of
+// rteaal_batch_opts; the last line with a key wins.  The key names the
+// device (architecture and compute units), the designs (fingerprints of
+// their encoded programs) and the instance counts.
+const char* tune_cache_path() {
+  const char* p = std::getenv("RTEAAL_TUNE_CACHE");
+  return p && *p ? p : nullptr;
+}
+
+std::string device_tag(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "%s/%dcu", prop.gcnArchName, prop.multiProcessorCount);
+  std::string t = buf;
+  for (char& c : t)
+    if (c == ' ' || c == ':') c = '_';
+  return t;
+}
+
+constexpr int kOptFields = 10;
+
+void opts_to(const rteaal_batch_opts& o, uint32_t* v) {
+  const uint32_t a[kOptFields] = {o.mapping, o.block_threads, o.ops_per_wave, o.lds_state, o.lds_ops,
+                                  o.unroll, o.tiles_per_wave, o.arity_split, o.tiles_per_pass,
+                                  o.persistent};
+  std::copy(a, a + kOptFields, v);
+}
+
+rteaal_batch_opts opts_from(const uint32_t* v) {
+  rteaal_batch_opts o{};
+  o.mapping = v[0];
+  o.block_threads = v[1];
+  o.ops_per_wave = v[2];
+  o.lds_state = v[3];
+  o.lds_ops = v[4];
+  o.unroll = v[5];
+  o.tiles_per_wave = v[6];
+  o.arity_split = v[7];
+  o.tiles_per_pass = v[8];
+  o.persistent = v[9];
+  return o;
+}
+
+bool cache_get(const std::string& key, std::vector<rteaal_batch_opts>* out, double* rate) {
+  const char* path = tune_cache_path();
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  bool found = false;
+  std::vector<char> line(1 << 20);
+  while (std::fgets(line.data(), (int)line.size(), f)) {
+    const char* q = line.data();
+    const size_t kl = key.size();
+    if (std::strncmp(q, key.c_str(), kl) != 0 || q[kl] != ' ') continue;
+    q += kl;
+    char* e = nullptr;
+    const double r = std::strtod(q, &e);
+    if (e == q) continue;
+    q = e;
+    const unsigned long n = std::strtoul(q, &e, 10);
+    if (e == q || n == 0 || n > (1u << 16)) continue;
+    q = e;
+    std::vector<rteaal_batch_opts> v;
+    bool ok = true;
+    for (unsigned long k = 0; k < n && ok; ++k) {
+      uint32_t a[kOptFields];
+      for (int i = 0; i < kOptFields && ok; ++i) {
+        a[i] = (uint32_t)std::strtoul(q, &e, 10);
+        ok = e != q;
+        q = e;
+      }
+      if (ok) v.push_back(opts_from(a));
+    }
+    if (!ok) continue;
+    *out = v;
+    *rate = r;
+    found = true;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_put(const std::string& key, const std::vector<rteaal_batch_opts>& v, double rate) {
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %.6g %zu", key.c_str(), rate, v.size());
+  for (const auto& o : v) {
+    uint32_t a[kOptFields];
+    opts_to(o, a);
+    for (int i = 0; i < kOptFields; ++i) std::fprintf(f, " %u", a[i]);
+  }
+  std::fprintf(f, "\n");
+  std::fclose(f);
+}
+
+std::string single_key(rteaal_ctx* ctx, const DesignHost& h, uint32_t n_inst, uint64_t cycles) {
+  char buf[128];
+  std::snprintf(buf, sizeof buf, "|%016llx|%u|%llu", (unsigned long long)h.fingerprint, n_inst,
+                (unsigned long long)cycles);
+  return "single|" + device_tag(ctx->device) + buf;
+}
+
+}  // namespace
+
+extern "C" {
+
 rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_inst,
                               uint32_t trial_cycles, rteaal_batch_opts* best, double* rate) {
   if (!ctx || n_inst == 0) return fail(ctx, RTEAAL_E_INVALID_ARG, "bad argument");
@@ -1823,6 +2475,17 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
     const double per_cycle = (double)h->ops.size() * n_inst;
     cyc = (uint64_t)std::max(1.0, std::min(64.0, 2e9 / std::max(per_cycle, 1.0)));
   }
+  const std::string key = single_key(ctx, *h, n_inst, cyc);
+  {
+    std::vector<rteaal_batch_opts> v;
+    double r = 0;
+    if (cache_get(key, &v, &r) && v.size() == 1) {
+      ctx->tuned[{id, n_inst}] = v[0];
+      if (best) *best = v[0];
+      if (rate) *rate = r;
+      return RTEAAL_OK;
+    }
+  }
   std::vector<rteaal_batch_opts> cand;
   const uint32_t m64 = ((h->max_layer_ops + 63) / 64) * 64;
   for (uint32_t blk : {128u, 256u, 512u, 1024u}) {
@@ -1830,10 +2493,16 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
     for (uint32_t u : {1u, 2u, 4u})
       cand.push_back(rteaal_batch_opts{RTEAAL_MAP_RESIDENT, blk, 0, 0, 0, u, 0});
   }
-  if (n_inst <= 16)
+  if (n_inst <= 16) {
     for (uint32_t blk : {64u, 128u, 256u})
       for (uint32_t u : {1u, 2u})
         cand.push_back(rteaal_batch_opts{RTEAAL_MAP_LAYERED, blk, 0, 0, 0, u, 0});
+    for (uint32_t u : {1u, 2u}) {
+      rteaal_batch_opts o{RTEAAL_MAP_LAYERED, 0, 0, 0, 0, u, 0};
+      o.persistent = 1;
+      cand.push_back(o);
+    }
+  }
   const uint32_t n_tiles = (n_inst + 63) / 64;
   for (uint32_t tg : {1u, 2u, 4u, 8u, 16u}) {
     if (tg > 1 && tg > n_tiles) continue;
@@ -1874,8 +2543,9 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
     if (st != RTEAAL_OK) break;
     const double r = (double)n_inst * (double)cyc / (std::max(ms, 1e-3f) * 1e-3);
     if (log)
-      std::fprintf(stderr, "rteaal_autotune: mapping %u block %u ops/wave %u unroll %u tiles %u -> %.4g\n",
-                   o.mapping, o.block_threads, o.ops_per_wave, o.unroll, o.tiles_per_wave, r);
+      std::fprintf(stderr, "rteaal_autotune: mapping %u block %u ops/wave %u unroll %u tiles %u "
+                   "persistent %u -> %.4g\n", o.mapping, o.block_threads, o.ops_per_wave, o.unroll,
+                   o.tiles_per_wave, o.persistent, r);
     if (r > best_rate) {
       best_rate = r;
       best_o = o;
@@ -1886,8 +2556,141 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
   if (st != RTEAAL_OK) return st;
   if (best_rate < 0) return fail(ctx, RTEAAL_E_NO_MEMORY, "no candidate fits in device memory");
   ctx->tuned[{id, n_inst}] = best_o;
+  cache_put(key, {best_o}, best_rate);
   if (best) *best = best_o;
   if (rate) *rate = best_rate;
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_design_id* ids,
+                                   const uint32_t* n_inst, uint32_t trial_cycles,
+                                   rteaal_batch_opts* best, double* rate) {
+  if (!ctx || n == 0 || !ids || !n_inst) return fail(ctx, RTEAAL_E_INVALID_ARG, "bad argument");
+  if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
+  std::vector<DesignHost*> hs(n);
+  uint64_t total = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    hs[k] = find_design(ctx, ids[k]);
+    if (!hs[k]) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown design %u", ids[k]);
+    if (n_inst[k] == 0) return fail(ctx, RTEAAL_E_INVALID_ARG, "instance count 0");
+    for (uint32_t q = 0; q < k; ++q)
+      if (ids[q] == ids[k] && n_inst[q] == n_inst[k])
+        return fail(ctx, RTEAAL_E_INVALID_ARG, "design %u with %u instances listed twice", ids[k], n_inst[k]);
+    total += (uint64_t)hs[k]->ops.size() * n_inst[k];
+  }
+  // Trial length: about 4e9 op-evaluations per policy, 2..32 cycles.
+  const uint64_t cyc = trial_cycles ? trial_cycles
+                                    : (uint64_t)std::max(2.0, std::min(32.0, 4e9 / std::max<double>((double)total, 1.0)));
+  std::string key = "joint|" + device_tag(ctx->device);
+  {
+    uint64_t fp = 1469598103934665603ull;
+    for (uint32_t k = 0; k < n; ++k) {
+      fp = fnv1a(&hs[k]->fingerprint, 8, fp);
+      fp = fnv1a(&n_inst[k], 4, fp);
+    }
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "|%016llx|%u|%llu", (unsigned long long)fp, n,
+                  (unsigned long long)cyc);
+    key += buf;
+  }
+  std::vector<rteaal_batch_opts> chosen;
+  double chosen_rate = 0;
+  if (!cache_get(key, &chosen, &chosen_rate) || chosen.size() != n) {
+    // Policies for the whole set: batches of at least `sweep_min` instances
+    // run SWEEP (records shared by a wavefront's instances, tile groups up
+    // to tg_cap tiles), smaller ones RESIDENT, or LAYERED when their design
+    // is large (a layer over the whole device rather than one compute unit).
+    struct Policy {
+      uint32_t sweep_min, tg_cap, layered_ops;
+    };
+    const Policy pol[] = {{16, 4, UINT32_MAX}, {16, 4, 100000}, {48, 4, 100000}, {16, 2, 100000},
+                          {8, 4, 100000}, {48, 2, UINT32_MAX}};
+    auto opts_of = [&](const Policy& p, uint32_t k) {
+      rteaal_batch_opts o{};
+      const uint32_t ni = n_inst[k];
+      if (ni >= p.sweep_min) {
+        const uint32_t tiles = (ni + 63) / 64;
+        uint32_t tg = 1;
+        while (tg * 2 <= std::min(tiles, p.tg_cap)) tg *= 2;
+        o.mapping = RTEAAL_MAP_SWEEP;
+        o.ops_per_wave = 8;
+        o.unroll = 1;
+        o.tiles_per_wave = tg;
+      } else if (hs[k]->ops.size() >= p.layered_ops && ni <= 65535) {
+        o.mapping = RTEAAL_MAP_LAYERED;
+        o.block_threads = 64;
+        o.unroll = 1;
+      } else {
+        o.mapping = RTEAAL_MAP_RESIDENT;
+      }
+      return o;
+    };
+    const char* log_env = std::getenv("RTEAAL_AUTOTUNE_LOG");
+    const bool log = log_env && *log_env && *log_env != '0';
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    double best_rate = -1;
+    rteaal_status st = RTEAAL_OK;
+    for (const Policy& p : pol) {
+      std::vector<rteaal_batch_opts> os(n);
+      std::vector<rteaal_batch_id> bs;
+      bool fits = true;
+      for (uint32_t k = 0; k < n && st == RTEAAL_OK; ++k) {
+        os[k] = opts_of(p, k);
+        std::vector<uint64_t> seeds(n_inst[k]);
+        for (uint32_t i = 0; i < n_inst[k]; ++i) seeds[i] = i;
+        rteaal_batch_id b = 0;
+        st = rteaal_create_batch(ctx, ids[k], n_inst[k], seeds.data(), &os[k], &b);
+        if (st == RTEAAL_E_NO_MEMORY) {
+          st = RTEAAL_OK;
+          fits = false;
+          break;
+        }
+        if (st == RTEAAL_OK) bs.push_back(b);
+      }
+      double r = -1;
+      if (st == RTEAAL_OK && fits) {
+        std::vector<uint64_t> one(bs.size(), 1), many(bs.size(), cyc);
+        st = rteaal_step_many(ctx, (uint32_t)bs.size(), bs.data(), one.data(), nullptr);  // warm-up, capture
+        hipError_t e = hipSuccess;
+        if (st == RTEAAL_OK) e = hipEventRecord(e0, ctx->stream);
+        if (st == RTEAAL_OK && e == hipSuccess)
+          st = rteaal_step_many(ctx, (uint32_t)bs.size(), bs.data(), many.data(), nullptr);
+        if (st == RTEAAL_OK && e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+        if (st == RTEAAL_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (st == RTEAAL_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          ctx->poisoned = true;
+          st = fail(ctx, RTEAAL_E_DEVICE, "autotune timing: %s", hipGetErrorString(e));
+        }
+        uint64_t inst = 0;
+        for (uint32_t k = 0; k < n; ++k) inst += n_inst[k];
+        r = (double)inst * (double)cyc / (std::max(ms, 1e-3f) * 1e-3);
+      }
+      for (rteaal_batch_id b : bs) rteaal_free_batch(ctx, b);
+      if (st != RTEAAL_OK) break;
+      if (log)
+        std::fprintf(stderr, "rteaal_autotune_many: sweep from %u instances, tile groups up to %u, "
+                     "LAYERED from %u ops -> %.4g\n", p.sweep_min, p.tg_cap, p.layered_ops, r);
+      if (r > best_rate) {
+        best_rate = r;
+        chosen = os;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != RTEAAL_OK) return st;
+    if (best_rate < 0) return fail(ctx, RTEAAL_E_NO_MEMORY, "no policy fits in device memory");
+    chosen_rate = best_rate;
+    cache_put(key, chosen, chosen_rate);
+  }
+  for (uint32_t k = 0; k < n; ++k) {
+    ctx->tuned[{ids[k], n_inst[k]}] = chosen[k];
+    if (best) best[k] = chosen[k];
+  }
+  if (rate) *rate = chosen_rate;
   return RTEAAL_OK;
 }
 

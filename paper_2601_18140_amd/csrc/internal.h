@@ -162,6 +162,9 @@ struct SlotRef {
 };
 
 // Everything a RESIDENT workgroup needs to run its instance of one batch.
+// regs / n_regs: the registers' stored values (slot refs, in register
+// order) that the per-cycle digest folds; digest: one running digest per
+// instance.
 struct ResJob {
   const DevOp* ops;
   const DevLayer* layers;
@@ -172,6 +175,49 @@ struct ResJob {
   const uint64_t* seeds;
   const DevCtl* ctl;
   uint64_t n_cycles;
+  const SlotRef* regs;
+  uint64_t* digest;
+  uint32_t n_regs, pad;
+};
+
+// One segment of a launch over several batches (rteaal_step_many): a piece
+// of one batch's layer.  SWEEP common operations: the ranges r in chunks of
+// opw operations (split: chunks in [b0, e0)) times n_groups tile groups;
+// SWEEP heavy operations and fused mux chains: those of layer `layer` in the
+// same way; LAYERED: layer `layer`, n_groups wavefronts of 64 positions per
+// instance.
+struct MultiSeg {
+  const DevOp* ops;
+  const DevLayer* layers;
+  const uint64_t* const_limbs;
+  char* state;
+  const uint64_t* seeds;
+  const DevCtl* ctl;
+  StateLayout L;
+  OpRanges r;
+  uint32_t layer, n_inst, words_per_inst, opw, split, n_groups, pad[2];
+};
+static_assert(sizeof(MultiSeg) == 128, "MultiSeg layout");
+
+// One batch of a multi-batch register digest (k_digest's arguments) and its
+// cycle counter, which the fold advances.
+struct DigestSeg {
+  StateLayout L;
+  const char* state;
+  const SlotRef* regs;
+  uint64_t* digest;
+  uint64_t* acc;
+  DevCtl* ctl;
+  uint32_t n_regs, n_inst, n_units, per, sweep, pad;
+};
+static_assert(sizeof(DigestSeg) == 96, "DigestSeg layout");
+
+// State of the grid-wide barrier of a persistent launch (device memory,
+// zero before each launch): arrivals so far (every block adds one per
+// barrier, never reset during the launch), the number of barriers opened,
+// and an error flag, set when a block's wait exceeds the spin limit.
+struct GridSync {
+  uint32_t count, opened, error, pad;
 };
 
 // ---- kernel launchers (kernels.hip) ---------------------------------------
@@ -198,6 +244,30 @@ hipError_t launch_sweep_heavy(const Program& p, const StateLayout& L, char* stat
 hipError_t launch_layer(const ResJob& J, uint32_t li, uint32_t n_layer_ops, uint32_t n_inst,
                         uint32_t block, uint32_t unroll, hipStream_t s);
 hipError_t launch_advance(DevCtl* ctl, uint64_t n, hipStream_t s);
+// LAYERED, persistent: all J.n_cycles cycles of n_inst instances in one
+// cooperative launch, every layer spread over the whole grid and followed by
+// a grid-wide barrier; the register digest after every cycle (acc: one
+// zeroed word per instance).  gs is zeroed by this call first.  blocks = 0:
+// as many blocks of 256 threads as are resident at once (at most two per
+// compute unit); spin_limit bounds every barrier wait.
+hipError_t launch_layer_persistent(const ResJob& J, uint32_t n_inst, uint32_t unroll,
+                                   GridSync* gs, uint64_t* acc, uint32_t spin_limit,
+                                   uint32_t blocks, hipStream_t s);
+// Launches over several batches: segs[0 .. n_seg) and wave0[0 .. n_seg] in
+// device memory, wave0 the prefix of the segments' wavefronts (n_waves =
+// wave0[n_seg]).  kind 0: SWEEP common operations (tile group tg: 1, 2, 4,
+// 8 or 16), 1: SWEEP heavy (tg 1 or 2), 2: fused mux chains (tg 1, 2 or 4),
+// 3: LAYERED (tg ignored).
+hipError_t launch_multi(uint32_t kind, uint32_t tg, const MultiSeg* segs, const uint32_t* wave0,
+                        uint32_t n_seg, uint64_t n_waves, hipStream_t s);
+// Register digest of several batches, then their folds and cycle advance
+// (every batch: D = s(D ^ acc), acc = 0, cycle + 1); max_inst: the largest
+// n_inst among them.
+hipError_t launch_digest_multi(const DigestSeg* segs, const uint32_t* wave0, uint32_t n_seg,
+                               uint64_t n_waves, uint32_t max_inst, hipStream_t s);
+// The digest's chunking of one batch: units (tiles or instances) and
+// registers per wavefront; wavefronts = units x ceil(n_regs / per).
+void digest_shape(bool sweep, uint32_t n_regs, uint32_t n_inst, uint32_t* n_units, uint32_t* per);
 hipError_t launch_set_words(DevCtl* ctl, const uint64_t* words, hipStream_t s);
 hipError_t launch_pack(bool sweep, const StateLayout& L, const char* state, const SlotRef* refs,
                        uint32_t n_refs, uint32_t words_per_inst, uint32_t first, uint32_t n,
@@ -227,5 +297,17 @@ hipError_t launch_capture(bool sweep, const StateLayout& L, const char* state, c
                           const DevCtl* ctl, ChangeRec* log, uint64_t cap,
                           unsigned long long* count, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
+
+// Register digest after a cycle's commit, for the SWEEP and RESIDENT
+// layouts (RESIDENT batches fold it inside k_resident instead).  With
+// s = SplitMix64's output function and v[j][l] limb l of register j:
+//   h = sum over j, l of s(s(4 j + l) ^ v[j][l])   (mod 2^64)
+//   D = s(D ^ h).
+// launch_digest adds the terms of every register into acc[inst] (zero on
+// entry) and then folds acc into digest[inst] and clears acc again, for
+// instances [0, n_inst).
+hipError_t launch_digest(bool sweep, const StateLayout& L, const char* state, const SlotRef* regs,
+                         uint32_t n_regs, uint32_t n_inst, uint64_t* digest, uint64_t* acc,
+                         hipStream_t s);
 
 }  // namespace rteaal

@@ -23,6 +23,8 @@
 // straight into its LI slot (identity elision).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.h"
 #include "ops_device.h"
 
@@ -116,7 +118,7 @@ __device__ __forceinline__ void res_stv(char* s, uint32_t cls, uint32_t f, const
 // positions of a wavefront are 64 consecutive ones, so 1-bit results leave
 // as one ballot word per wavefront.
 template <int U>
-__device__ __forceinline__ void resident_ops(const ResJob& J, char* s, const DevOp* ops,
+__device__ __forceinline__ void resident_ops(const uint64_t* const_limbs, char* s, const DevOp* ops,
                                              const DevLayer& ly, uint32_t q0, uint32_t stride,
                                              uint32_t n, uint32_t n64, uint64_t seed,
                                              uint64_t cycle, const uint64_t* words,
@@ -145,7 +147,7 @@ __device__ __forceinline__ void resident_ops(const ResJob& J, char* s, const Dev
         const uint32_t code = o.code, opc = op_opc(code), ar = op_arity(code);
         const uint32_t dc = op_dcls(code), w = op_width(o.wimm), imm = op_imm(o.wimm);
         if (opc >= OP_STIM) {
-          const V4 x = source_value(J.const_limbs, o, seed, cycle, words, words_row, w);
+          const V4 x = source_value(const_limbs, o, seed, cycle, words, words_row, w);
           if (dc == CB) {
             bdst = true;
             bit = x.l[0] & 1ull;
@@ -175,8 +177,8 @@ __device__ __forceinline__ void resident_ops(const ResJob& J, char* s, const Dev
           V4 c = ar > 2 ? res_ldv(s, op_scls(code, 2), o.src[2]) : v4_from(0);
           if (opc == OP_MUXC)  // further pairs, innermost first, onto the default
             for (uint32_t i = o.aux1; i-- > 0;) {
-              const uint64_t es = J.const_limbs[o.aux0 + 2u * i];
-              const uint64_t ev = J.const_limbs[o.aux0 + 2u * i + 1u];
+              const uint64_t es = const_limbs[o.aux0 + 2u * i];
+              const uint64_t ev = const_limbs[o.aux0 + 2u * i + 1u];
               const V4 sv = res_ldv(s, (uint32_t)(es >> 32), (uint32_t)es);
               const V4 vv = res_ldv(s, (uint32_t)(ev >> 32), (uint32_t)ev);
               if (v4_nonzero(sv)) c = vv;
@@ -200,8 +202,28 @@ __device__ __forceinline__ void resident_ops(const ResJob& J, char* s, const Dev
   }
 }
 
+// Sum of a 64-bit value over the 64 lanes of a wavefront.
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+// Digest terms of register j (stored value ref r) of a RESIDENT state block
+// s: the sum over its limbs l of s(s(4 j + l) ^ limb), s = SplitMix64's
+// output function.
+__device__ __forceinline__ uint64_t res_reg_terms(const char* s, const SlotRef& r, uint32_t j) {
+  if (r.cls <= CD) return splitmix64(splitmix64((uint64_t)j << 2) ^ res_fetch(s, r.cls, r.pos));
+  const uint64_t* q = (const uint64_t*)(s + (uint64_t)(r.pos >> 6) * 8u);
+  const uint32_t nl = (r.width + 63u) >> 6;
+  uint64_t h = 0;
+  for (uint32_t l = 0; l < nl; ++l) h += splitmix64(splitmix64(((uint64_t)j << 2) | l) ^ q[l]);
+  return h;
+}
+
 template <bool LDS_STATE, bool LDS_OPS, int U>
 __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uint4* lds_dyn) {
+  __shared__ unsigned long long s_dig;  // the workgroup's digest sum of one cycle
   const StateLayout& L = J.L;
   char* g = J.state + (uint64_t)inst * L.pitch;
   char* s = LDS_STATE ? (char*)lds_dyn : g;
@@ -222,13 +244,15 @@ __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uin
   if (LDS_STATE)
     for (uint64_t i = threadIdx.x; i < L.pitch / 16u; i += blockDim.x)
       lds_dyn[i] = ((const uint4*)g)[i];
-  if (LDS_STATE || LDS_OPS) __syncthreads();
+  if (threadIdx.x == 0) s_dig = 0ull;
+  __syncthreads();
 
   const uint64_t seed = J.seeds[inst];
   const uint64_t c0 = J.ctl->cycle, wc0 = J.ctl->step_cycle0;
   const uint64_t* words = J.ctl->words;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t bd = blockDim.x;
+  uint64_t dig = threadIdx.x == 0 ? J.digest[inst] : 0ull;
 
   for (uint64_t t = 0; t < J.n_cycles; ++t) {
     const uint64_t cycle = c0 + t;
@@ -239,10 +263,26 @@ __device__ __forceinline__ void resident_run(const ResJob& J, uint32_t inst, uin
       const uint32_t n = ly.end - ly.begin;
       const uint32_t n64 = (n + 63u) & ~63u;
       for (uint32_t q0 = threadIdx.x; q0 < n64; q0 += U * bd)
-        resident_ops<U>(J, s, ops, ly, q0, bd, n, n64, seed, cycle, words, words_row, lane);
+        resident_ops<U>(J.const_limbs, s, ops, ly, q0, bd, n, n64, seed, cycle, words, words_row,
+                        lane);
       __syncthreads();
     }
+    // Register digest of this cycle (the commit layer has run).  Thread 0
+    // clears the sum before the next cycle's first layer barrier, and every
+    // other thread adds to it only after that barrier.
+    if (J.n_regs) {
+      uint64_t h = 0;
+      for (uint32_t j = threadIdx.x; j < J.n_regs; j += bd) h += res_reg_terms(s, J.regs[j], j);
+      h = wave_sum64(h);
+      if (lane == 0) atomicAdd(&s_dig, (unsigned long long)h);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      dig = splitmix64(dig ^ s_dig);
+      s_dig = 0ull;
+    }
   }
+  if (threadIdx.x == 0) J.digest[inst] = dig;
   if (LDS_STATE) {
     for (uint64_t i = threadIdx.x; i < L.pitch / 16u; i += blockDim.x)
       ((uint4*)g)[i] = lds_dyn[i];
@@ -280,8 +320,86 @@ __global__ void __launch_bounds__(256) k_layer(ResJob J, uint32_t li) {
   const uint64_t cycle = J.ctl->cycle;
   const uint64_t words_row =
       ((cycle - J.ctl->step_cycle0) * (uint64_t)J.n_inst_total + inst) * (uint64_t)J.words_per_inst;
-  resident_ops<U>(J, J.state + (uint64_t)inst * J.L.pitch, J.ops, ly, q0, bd, n, n64,
+  resident_ops<U>(J.const_limbs, J.state + (uint64_t)inst * J.L.pitch, J.ops, ly, q0, bd, n, n64,
                   J.seeds[inst], cycle, J.ctl->words, words_row, threadIdx.x & 63u);
+}
+
+// ---------------------------------------------------------------------------
+// LAYERED, persistent: one cooperative launch runs every cycle of a step.
+// ---------------------------------------------------------------------------
+
+// Barrier of all blocks of a cooperative launch (all of them resident).  The
+// block whose arrival completes round r opens it; the others wait with a
+// bounded spin.  A wait past spin_limit sets the error flag and goes on, so
+// every block still ends (the host then reports a device error).  The
+// release of the arrival and the acquire of the wait, at device scope, make
+// every store before the barrier visible to every block after it.
+__device__ __forceinline__ void grid_barrier(GridSync* gs, uint32_t& round, uint32_t spin_limit) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t want = round + 1u;
+    const uint32_t arrived =
+        __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (arrived == want * gridDim.x) {
+      __hip_atomic_store(&gs->opened, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(&gs->opened, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < want) {
+        if (++spins > spin_limit) {
+          __hip_atomic_store(&gs->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+  }
+  round += 1u;
+  __syncthreads();
+}
+
+template <int U>
+__global__ void __launch_bounds__(256)
+k_layer_persistent(ResJob J, uint32_t n_inst, GridSync* gs, unsigned long long* acc,
+                   uint32_t spin_limit) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wpb = blockDim.x >> 6;
+  const uint32_t n_waves = gridDim.x * wpb;
+  const uint32_t wave = blockIdx.x * wpb + (threadIdx.x >> 6);
+  const uint64_t c0 = J.ctl->cycle, wc0 = J.ctl->step_cycle0;
+  const uint64_t* words = J.ctl->words;
+  uint32_t round = 0;
+  for (uint64_t t = 0; t < J.n_cycles; ++t) {
+    const uint64_t cycle = c0 + t;
+    for (uint32_t li = 0; li < J.n_layers; ++li) {
+      const DevLayer ly = J.layers[li];
+      const uint32_t n = ly.end - ly.begin, n64 = (n + 63u) & ~63u;
+      // Units of 64 U positions of one instance: positions q0 + 64 u.
+      const uint32_t per = (n64 + 64u * U - 1u) / (64u * U);
+      const uint64_t units = (uint64_t)per * n_inst;
+      for (uint64_t c = wave; c < units; c += n_waves) {
+        const uint32_t inst = (uint32_t)(c / per), q0 = (uint32_t)(c % per) * 64u * U + lane;
+        const uint64_t words_row =
+            ((cycle - wc0) * (uint64_t)J.n_inst_total + inst) * (uint64_t)J.words_per_inst;
+        resident_ops<U>(J.const_limbs, J.state + (uint64_t)inst * J.L.pitch, J.ops, ly, q0, 64u,
+                        n, n64, J.seeds[inst], cycle, words, words_row, lane);
+      }
+      grid_barrier(gs, round, spin_limit);
+    }
+    // Register digest: 64 registers of one instance per wavefront, then the
+    // fold (the sums are cleared before the next cycle's first barrier).
+    const uint32_t rc = (J.n_regs + 63u) / 64u;
+    for (uint64_t c = wave; c < (uint64_t)rc * n_inst; c += n_waves) {
+      const uint32_t inst = (uint32_t)(c / rc), j = (uint32_t)(c % rc) * 64u + lane;
+      uint64_t h = j < J.n_regs ? res_reg_terms(J.state + (uint64_t)inst * J.L.pitch, J.regs[j], j) : 0ull;
+      h = wave_sum64(h);
+      if (lane == 0) atomicAdd(&acc[inst], (unsigned long long)h);
+    }
+    grid_barrier(gs, round, spin_limit);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_inst; i += gridDim.x * blockDim.x) {
+      J.digest[i] = splitmix64(J.digest[i] ^ acc[i]);
+      acc[i] = 0ull;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -577,13 +695,11 @@ __device__ __forceinline__ void sweep_group(const SweepView& v, const DevOp* op,
 // Operations of a chunk run U at a time when the U share their evaluation
 // kind (ranges are sorted by kind, so mixed groups are rare), else one by one.
 template <int U, int TG, int NS>
-__global__ void __launch_bounds__(256)
-k_sweep(const DevOp* __restrict__ ops, StateLayout L, char* __restrict__ state, OpRanges r,
-        uint32_t opw, uint32_t split, uint32_t tile_base, uint32_t n_groups) {
+__device__ __forceinline__ void sweep_wave(const DevOp* __restrict__ ops, const StateLayout& L,
+                                           char* __restrict__ state, const OpRanges& r,
+                                           uint32_t opw, uint32_t split, uint32_t tile_base,
+                                           uint32_t n_groups, uint32_t wave, uint32_t lane) {
   constexpr bool B1 = U == 1 && TG >= 4;
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wave =
-      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   const uint32_t grp = wave % n_groups, chunk = wave / n_groups;
   const bool first = chunk < split;
   const uint32_t o0 = first ? r.b0 + chunk * opw : r.b1 + (chunk - split) * opw;
@@ -609,6 +725,16 @@ k_sweep(const DevOp* __restrict__ ops, StateLayout L, char* __restrict__ state, 
         if ((uint32_t)u < n_valid) sweep_group<1, TG, NS, B1>(v, &op[u], 1u, op_kind(op[u].code));
     }
   }
+}
+
+template <int U, int TG, int NS>
+__global__ void __launch_bounds__(256)
+k_sweep(const DevOp* __restrict__ ops, StateLayout L, char* __restrict__ state, OpRanges r,
+        uint32_t opw, uint32_t split, uint32_t tile_base, uint32_t n_groups) {
+  const uint32_t wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  sweep_wave<U, TG, NS>(ops, L, state, r, opw, split, tile_base, n_groups, wave,
+                        threadIdx.x & 63u);
 }
 
 // One operand (slot field f of class cls) for the TG tiles of the heavy
@@ -734,15 +860,12 @@ __device__ __forceinline__ void heavy_muxc64(const SweepView& v, const DevOp& q,
 // The fused mux chains of one layer, [hm0, hm1): each wavefront takes
 // ops_per_wave of them over TG tiles of its tile group.
 template <int TG>
-__global__ void __launch_bounds__(256)
-k_sweep_muxc(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
-             const uint64_t* __restrict__ words, StateLayout L, char* __restrict__ state,
-             uint32_t layer, uint32_t opw, uint32_t tile_base, uint32_t n_groups) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wave =
-      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+__device__ __forceinline__ void muxc_wave(const DevOp* __restrict__ ops, const DevLayer& ly,
+                                          const uint64_t* __restrict__ words, const StateLayout& L,
+                                          char* __restrict__ state, uint32_t opw,
+                                          uint32_t tile_base, uint32_t n_groups, uint32_t wave,
+                                          uint32_t lane) {
   const uint32_t grp = wave % n_groups, chunk = wave / n_groups;
-  const DevLayer ly = layers[layer];
   const uint32_t o0 = ly.hm0 + chunk * opw;
   if (o0 >= ly.hm1) return;
   const uint32_t o1 = min(o0 + opw, ly.hm1);
@@ -778,6 +901,17 @@ k_sweep_muxc(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
   }
 }
 
+template <int TG>
+__global__ void __launch_bounds__(256)
+k_sweep_muxc(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
+             const uint64_t* __restrict__ words, StateLayout L, char* __restrict__ state,
+             uint32_t layer, uint32_t opw, uint32_t tile_base, uint32_t n_groups) {
+  const uint32_t wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  muxc_wave<TG>(ops, layers[layer], words, L, state, opw, tile_base, n_groups, wave,
+                threadIdx.x & 63u);
+}
+
 // The heavy operations of one layer (a value wider than 64 bits, a type run
 // in the wide form, or a source) other than the fused mux chains.  Limb 0 of
 // every operand is gathered without branches (an 8-byte load per tile holding
@@ -785,17 +919,15 @@ k_sweep_muxc(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
 // wide operands follow under a uniform branch.  All loads of an operation are
 // in flight before the first is used.
 template <int TG>
-__global__ void __launch_bounds__(256)
-k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
-              const uint64_t* __restrict__ const_limbs, uint32_t words_per_inst, StateLayout L,
-              char* __restrict__ state, const uint64_t* __restrict__ seeds,
-              const DevCtl* __restrict__ ctl, uint32_t n_inst, uint32_t layer, uint32_t opw,
-              uint32_t tile_base, uint32_t n_groups) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wave =
-      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+__device__ __forceinline__ void heavy_wave(const DevOp* __restrict__ ops, const DevLayer& ly,
+                                           const uint64_t* __restrict__ const_limbs,
+                                           uint32_t words_per_inst, const StateLayout& L,
+                                           char* __restrict__ state,
+                                           const uint64_t* __restrict__ seeds,
+                                           const DevCtl* __restrict__ ctl, uint32_t n_inst,
+                                           uint32_t opw, uint32_t tile_base, uint32_t n_groups,
+                                           uint32_t wave, uint32_t lane) {
   const uint32_t grp = wave % n_groups, chunk = wave / n_groups;
-  const DevLayer ly = layers[layer];
   // [hbeg, hm0) then [hm1, hend): the fused mux chains between them have a
   // kernel of their own.
   const uint32_t split = (ly.hm0 - ly.hbeg + opw - 1) / opw;
@@ -886,6 +1018,131 @@ k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers
         }
     }
   }
+}
+
+template <int TG>
+__global__ void __launch_bounds__(256)
+k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
+              const uint64_t* __restrict__ const_limbs, uint32_t words_per_inst, StateLayout L,
+              char* __restrict__ state, const uint64_t* __restrict__ seeds,
+              const DevCtl* __restrict__ ctl, uint32_t n_inst, uint32_t layer, uint32_t opw,
+              uint32_t tile_base, uint32_t n_groups) {
+  const uint32_t wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  heavy_wave<TG>(ops, layers[layer], const_limbs, words_per_inst, L, state, seeds, ctl, n_inst,
+                 opw, tile_base, n_groups, wave, threadIdx.x & 63u);
+}
+
+// ---------------------------------------------------------------------------
+// Several batches in one launch (rteaal_step_many): a table of segments, each
+// a piece of one batch's layer (its operation ranges, launch shape and
+// state), the launch's wavefronts split among them by the prefix wave0.
+// Every wavefront finds its segment by a binary search over wave0 (wave-
+// uniform scalar loads) and runs the same body as the per-batch kernels.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t find_seg(const uint32_t* __restrict__ wave0, uint32_t n_seg,
+                                             uint32_t wave) {
+  uint32_t lo = 0, hi = n_seg;  // wave0[lo] <= wave < wave0[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (wave0[mid] <= wave) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int TG>
+__global__ void __launch_bounds__(256)
+k_sweep_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wave0,
+              uint32_t n_seg) {
+  const uint32_t wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  if (wave >= wave0[n_seg]) return;
+  const uint32_t k = find_seg(wave0, n_seg, wave);
+  const MultiSeg& g = segs[k];
+  sweep_wave<1, TG, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, wave - wave0[k],
+                       threadIdx.x & 63u);
+}
+
+template <int TG>
+__global__ void __launch_bounds__(256)
+k_sweep_heavy_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wave0,
+                    uint32_t n_seg) {
+  const uint32_t wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  if (wave >= wave0[n_seg]) return;
+  const uint32_t k = find_seg(wave0, n_seg, wave);
+  const MultiSeg& g = segs[k];
+  heavy_wave<TG>(g.ops, g.layers[g.layer], g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
+                 g.ctl, g.n_inst, g.opw, 0u, g.n_groups, wave - wave0[k], threadIdx.x & 63u);
+}
+
+template <int TG>
+__global__ void __launch_bounds__(256)
+k_sweep_muxc_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wave0,
+                   uint32_t n_seg) {
+  const uint32_t wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  if (wave >= wave0[n_seg]) return;
+  const uint32_t k = find_seg(wave0, n_seg, wave);
+  const MultiSeg& g = segs[k];
+  muxc_wave<TG>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups,
+                wave - wave0[k], threadIdx.x & 63u);
+}
+
+// LAYERED segments: wavefront (block of 64 threads) w of segment g runs
+// positions [64 (w % n_groups), +64) of layer g.layer for instance
+// w / n_groups.
+__global__ void __launch_bounds__(64)
+k_layer_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wave0,
+              uint32_t n_seg) {
+  const uint32_t wave = blockIdx.x;
+  if (wave >= wave0[n_seg]) return;
+  const uint32_t k = find_seg(wave0, n_seg, wave);
+  const MultiSeg& g = segs[k];
+  const uint32_t local = wave - wave0[k];
+  const uint32_t inst = local / g.n_groups, q0 = (local % g.n_groups) * 64u + threadIdx.x;
+  const DevLayer ly = g.layers[g.layer];
+  const uint32_t n = ly.end - ly.begin, n64 = (n + 63u) & ~63u;
+  const uint64_t cycle = g.ctl->cycle;
+  const uint64_t words_row =
+      ((cycle - g.ctl->step_cycle0) * (uint64_t)g.n_inst + inst) * (uint64_t)g.words_per_inst;
+  resident_ops<1>(g.const_limbs, g.state + (uint64_t)inst * g.L.pitch, g.ops, ly, q0, 64u, n, n64,
+                  g.seeds[inst], cycle, g.ctl->words, words_row, threadIdx.x);
+}
+
+// Digest of several batches: segment g's wavefronts run k_digest's body for
+// batch g (g.layer: 1 for the SWEEP layout; g.opw: registers per chunk;
+// g.n_groups: units).
+__device__ __forceinline__ void digest_wave(bool sweep, const StateLayout& L,
+                                            const char* __restrict__ state,
+                                            const SlotRef* __restrict__ regs, uint32_t n_regs,
+                                            uint32_t n_inst, uint32_t n_units, uint32_t per,
+                                            unsigned long long* __restrict__ acc, uint32_t wave,
+                                            uint32_t lane);
+
+__global__ void __launch_bounds__(256)
+k_digest_multi(const DigestSeg* __restrict__ segs, const uint32_t* __restrict__ wave0,
+               uint32_t n_seg) {
+  const uint32_t wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  if (wave >= wave0[n_seg]) return;
+  const uint32_t k = find_seg(wave0, n_seg, wave);
+  const DigestSeg& g = segs[k];
+  digest_wave(g.sweep != 0u, g.L, g.state, g.regs, g.n_regs, g.n_inst, g.n_units, g.per,
+              (unsigned long long*)g.acc, wave - wave0[k], threadIdx.x & 63u);
+}
+
+// Digest fold and cycle advance of several batches: block row y serves
+// batch y.
+__global__ void k_fold_advance_multi(const DigestSeg* __restrict__ segs) {
+  const DigestSeg& g = segs[blockIdx.y];
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < g.n_inst) {
+    g.digest[i] = splitmix64(g.digest[i] ^ g.acc[i]);
+    g.acc[i] = 0ull;
+  }
+  if (i == 0) g.ctl->cycle += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1083,10 +1340,67 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, uint64_t n) {
   if (i < n) p[i] = v;
 }
 
+// Register digest, first part: the terms of registers [per c, per (c + 1))
+// added into acc[inst].  SWEEP: wavefront w takes tile w % n_units and
+// chunk c = w / n_units, lane = instance, every lane walking the chunk's
+// registers (a register's 64 values of a tile are one contiguous block).
+// RESIDENT layout: wavefront w takes instance w % n_units and chunk
+// c = w / n_units, the lanes spread over the chunk's registers, summed
+// across the wavefront.  The sum is order-independent, so the atomics give
+// the same result in any order.
+__device__ __forceinline__ void digest_wave(bool sweep, const StateLayout& L,
+                                            const char* __restrict__ state,
+                                            const SlotRef* __restrict__ regs, uint32_t n_regs,
+                                            uint32_t n_inst, uint32_t n_units, uint32_t per,
+                                            unsigned long long* __restrict__ acc, uint32_t wave,
+                                            uint32_t lane) {
+  const uint32_t unit = wave % n_units, chunk = wave / n_units;
+  const uint32_t j0 = chunk * per;
+  if (j0 >= n_regs) return;
+  const uint32_t j1 = min(j0 + per, n_regs);
+  uint64_t h = 0;
+  if (sweep) {
+    const uint32_t inst = unit * 64u + lane;  // below the allocated tiles' instances
+    for (uint32_t j = j0; j < j1; ++j) {
+      const SlotRef r = regs[j];
+      const uint32_t nl = (r.width + 63u) >> 6;
+      for (uint32_t l = 0; l < nl; ++l)
+        h += splitmix64(splitmix64(((uint64_t)j << 2) | l) ^ load_limb(true, L, state, r, l, inst));
+    }
+    if (inst < n_inst) atomicAdd(&acc[inst], (unsigned long long)h);
+  } else {
+    const char* s = state + (uint64_t)unit * L.pitch;
+    for (uint32_t j = j0 + lane; j < j1; j += 64u) h += res_reg_terms(s, regs[j], j);
+    h = wave_sum64(h);
+    if (lane == 0) atomicAdd(&acc[unit], (unsigned long long)h);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_digest(bool sweep, StateLayout L, const char* __restrict__ state,
+         const SlotRef* __restrict__ regs, uint32_t n_regs, uint32_t n_inst, uint32_t n_units,
+         uint32_t per, unsigned long long* __restrict__ acc) {
+  const uint32_t wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  digest_wave(sweep, L, state, regs, n_regs, n_inst, n_units, per, acc, wave, threadIdx.x & 63u);
+}
+
+// Register digest, second part: D = s(D ^ acc), then acc = 0.
+__global__ void k_digest_fold(uint64_t* __restrict__ digest, uint64_t* __restrict__ acc,
+                              uint32_t n_inst) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  digest[i] = splitmix64(digest[i] ^ acc[i]);
+  acc[i] = 0ull;
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-size_t resident_max_lds() { return 160u * 1024u; }
+// Dynamic LDS a RESIDENT workgroup may use: the 160 KB of a CU less a
+// reserve for the kernel's static shared variables (the digest sum), since
+// static and dynamic LDS together must fit.
+size_t resident_max_lds() { return 160u * 1024u - 256u; }
 
 namespace {
 template <class K>
@@ -1322,6 +1636,111 @@ hipError_t launch_capture(bool sweep, const StateLayout& L, const char* state, c
   const uint64_t per_block = 256ull * CAP_ITEMS;
   hipLaunchKernelGGL(k_capture, dim3((uint32_t)((total + per_block - 1) / per_block)), dim3(256), 0,
                      s, sweep, L, state, refs, n_refs, shadow, n_inst, init, ctl, log, cap, count);
+  return hipGetLastError();
+}
+
+void digest_shape(bool sweep, uint32_t n_regs, uint32_t n_inst, uint32_t* n_units, uint32_t* per) {
+  // About 4,096 wavefronts: enough to fill the device, few atomics.
+  *n_units = sweep ? (n_inst + 63u) / 64u : n_inst;
+  const uint64_t want = std::max<uint64_t>(1, (4096u + *n_units - 1) / *n_units);
+  uint64_t p = ((uint64_t)std::max<uint32_t>(n_regs, 1u) + want - 1) / want;
+  if (!sweep) p = (p + 63u) & ~uint64_t(63);
+  *per = (uint32_t)p;
+}
+
+hipError_t launch_digest(bool sweep, const StateLayout& L, const char* state, const SlotRef* regs,
+                         uint32_t n_regs, uint32_t n_inst, uint64_t* digest, uint64_t* acc,
+                         hipStream_t s) {
+  if (n_inst == 0) return hipSuccess;
+  if (n_regs) {
+    uint32_t n_units = 0, per = 0;
+    digest_shape(sweep, n_regs, n_inst, &n_units, &per);
+    if (sweep && n_units > L.n_tiles) return hipErrorInvalidValue;
+    const uint64_t chunks = ((uint64_t)n_regs + per - 1) / per;
+    const uint64_t waves = chunks * n_units;
+    if ((waves + 3) / 4 >= (1ull << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_digest, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, sweep, L,
+                       state, regs, n_regs, n_inst, n_units, per, (unsigned long long*)acc);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_digest_fold, dim3((n_inst + 255u) / 256u), dim3(256), 0, s, digest, acc,
+                     n_inst);
+  return hipGetLastError();
+}
+
+hipError_t launch_layer_persistent(const ResJob& J, uint32_t n_inst, uint32_t unroll,
+                                   GridSync* gs, uint64_t* acc, uint32_t spin_limit,
+                                   uint32_t blocks, hipStream_t s) {
+  if (n_inst == 0 || J.n_cycles == 0) return hipSuccess;
+  const uint32_t u = unroll == 2 ? 2u : 1u;
+  const void* fn = u == 2 ? (const void*)k_layer_persistent<2> : (const void*)k_layer_persistent<1>;
+  if (blocks == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
+    if (e != hipSuccess) return e;
+    blocks = (uint32_t)(cus * std::min(per_cu, 2));
+    if (blocks == 0) return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (uint64_t*)gs, 0ull,
+                     (uint64_t)(sizeof(GridSync) / 8));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  ResJob j = J;
+  GridSync* g = gs;
+  unsigned long long* a = (unsigned long long*)acc;
+  uint32_t ni = n_inst, sl = spin_limit;
+  void* args[] = {&j, &ni, &g, &a, &sl};
+  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), args, 0, s);
+}
+
+hipError_t launch_multi(uint32_t kind, uint32_t tg, const MultiSeg* segs, const uint32_t* wave0,
+                        uint32_t n_seg, uint64_t n_waves, hipStream_t s) {
+  if (n_seg == 0 || n_waves == 0) return hipSuccess;
+  if (n_waves >= (1ull << 32)) return hipErrorInvalidValue;
+  if (kind == 3) {
+    hipLaunchKernelGGL(k_layer_multi, dim3((uint32_t)n_waves), dim3(64), 0, s, segs, wave0, n_seg);
+    return hipGetLastError();
+  }
+  const dim3 grid((uint32_t)((n_waves + 3) / 4)), blk(256);
+  if (kind == 0) {
+    switch (tg) {
+      case 1: hipLaunchKernelGGL(k_sweep_multi<1>, grid, blk, 0, s, segs, wave0, n_seg); break;
+      case 2: hipLaunchKernelGGL(k_sweep_multi<2>, grid, blk, 0, s, segs, wave0, n_seg); break;
+      case 4: hipLaunchKernelGGL(k_sweep_multi<4>, grid, blk, 0, s, segs, wave0, n_seg); break;
+      case 8: hipLaunchKernelGGL(k_sweep_multi<8>, grid, blk, 0, s, segs, wave0, n_seg); break;
+      case 16: hipLaunchKernelGGL(k_sweep_multi<16>, grid, blk, 0, s, segs, wave0, n_seg); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else if (kind == 1) {
+    if (tg == 2) hipLaunchKernelGGL(k_sweep_heavy_multi<2>, grid, blk, 0, s, segs, wave0, n_seg);
+    else if (tg == 1) hipLaunchKernelGGL(k_sweep_heavy_multi<1>, grid, blk, 0, s, segs, wave0, n_seg);
+    else return hipErrorInvalidValue;
+  } else if (kind == 2) {
+    if (tg == 4) hipLaunchKernelGGL(k_sweep_muxc_multi<4>, grid, blk, 0, s, segs, wave0, n_seg);
+    else if (tg == 2) hipLaunchKernelGGL(k_sweep_muxc_multi<2>, grid, blk, 0, s, segs, wave0, n_seg);
+    else if (tg == 1) hipLaunchKernelGGL(k_sweep_muxc_multi<1>, grid, blk, 0, s, segs, wave0, n_seg);
+    else return hipErrorInvalidValue;
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_digest_multi(const DigestSeg* segs, const uint32_t* wave0, uint32_t n_seg,
+                               uint64_t n_waves, uint32_t max_inst, hipStream_t s) {
+  if (n_seg == 0) return hipSuccess;
+  if (n_waves >= (1ull << 32) || n_seg > 65535) return hipErrorInvalidValue;
+  if (n_waves) {
+    hipLaunchKernelGGL(k_digest_multi, dim3((uint32_t)((n_waves + 3) / 4)), dim3(256), 0, s, segs,
+                       wave0, n_seg);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_fold_advance_multi, dim3((std::max(max_inst, 1u) + 255u) / 256u, n_seg),
+                     dim3(256), 0, s, segs);
   return hipGetLastError();
 }
 

@@ -18,14 +18,15 @@ LIB_PATH = os.path.join(HERE, "librteaal.so")
 
 __all__ = [
     "RTEAAL_OK", "RTEAAL_MAP_AUTO", "RTEAAL_MAP_RESIDENT", "RTEAAL_MAP_SWEEP", "RTEAAL_MAP_LAYERED",
-    "RTEAAL_READ_REGS", "RTEAAL_READ_ALL_SLOTS", "RteaalError", "Context", "library",
+    "RTEAAL_READ_REGS", "RTEAAL_READ_DIGEST", "RTEAAL_READ_ALL_SLOTS", "RteaalError", "Context", "library",
     "exported_symbols", "rteaal_create", "rteaal_destroy", "rteaal_last_error",
     "rteaal_validate_design", "rteaal_load_design", "rteaal_unload_design", "rteaal_design_format",
     "RTEAAL_LOAD_KEEP_ALL_SLOTS",
     "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch", "rteaal_batch_info",
     "rteaal_batch_options",
     "rteaal_step", "rteaal_step_many", "rteaal_sync", "rteaal_read_state", "rteaal_write_state",
-    "rteaal_kernel_timing", "rteaal_autotune", "opts_dict", "unpack_limbs", "pack_limbs", "rteaal_layer_format", "rteaal_rank_format",
+    "rteaal_write_digest", "rteaal_read_digest",
+    "rteaal_kernel_timing", "rteaal_autotune", "rteaal_autotune_many", "opts_dict", "unpack_limbs", "pack_limbs", "rteaal_layer_format", "rteaal_rank_format",
     "rteaal_dag_desc", "rteaal_levelize", "levelized_design",
     "CHANGE_DTYPE", "rteaal_watch", "rteaal_read_changes",
 ]
@@ -34,7 +35,7 @@ RTEAAL_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "BAD_DESIGN", 3: "FORMAT", 4: "NO_MEMORY",
                 5: "DEVICE", 6: "BUSY", 7: "UNSUPPORTED"}
 RTEAAL_MAP_AUTO, RTEAAL_MAP_RESIDENT, RTEAAL_MAP_SWEEP, RTEAAL_MAP_LAYERED = 0, 1, 2, 3
-RTEAAL_READ_REGS, RTEAAL_READ_ALL_SLOTS = 1, 2
+RTEAAL_READ_REGS, RTEAAL_READ_DIGEST, RTEAAL_READ_ALL_SLOTS = 1, 2, 4
 RTEAAL_MUXC, RTEAAL_MUXC_MAX_PAIRS = 22, 32
 
 
@@ -81,7 +82,7 @@ class rteaal_batch_opts(C.Structure):
                 ("ops_per_wave", C.c_uint32), ("lds_state", C.c_uint32),
                 ("lds_ops", C.c_uint32), ("unroll", C.c_uint32),
                 ("tiles_per_wave", C.c_uint32), ("arity_split", C.c_uint32),
-                ("tiles_per_pass", C.c_uint32)]
+                ("tiles_per_pass", C.c_uint32), ("persistent", C.c_uint32)]
 
 
 class rteaal_stimulus(C.Structure):
@@ -127,12 +128,14 @@ def library():
         "rteaal_batch_info": ([vp, u32, C.POINTER(u32), C.POINTER(u64)], st),
         "rteaal_batch_options": ([vp, u32, C.POINTER(rteaal_batch_opts)], st),
         "rteaal_step": ([vp, u32, u64, C.POINTER(rteaal_stimulus)], st),
-        "rteaal_step_many": ([vp, u32, vp, vp], st),
+        "rteaal_step_many": ([vp, u32, vp, vp, vp], st),
         "rteaal_sync": ([vp], st),
         "rteaal_read_state": ([vp, u32, u32, u32, u32, vp, C.c_size_t, C.POINTER(C.c_size_t)], st),
         "rteaal_write_state": ([vp, u32, u32, u32, vp, u64], st),
+        "rteaal_write_digest": ([vp, u32, u32, u32, vp], st),
         "rteaal_kernel_timing": ([vp, u32, C.c_int, C.POINTER(u64), C.POINTER(C.c_double)], st),
         "rteaal_autotune": ([vp, u32, u32, u32, C.POINTER(rteaal_batch_opts), C.POINTER(C.c_double)], st),
+        "rteaal_autotune_many": ([vp, u32, vp, vp, u32, vp, C.POINTER(C.c_double)], st),
         "rteaal_levelize": ([vp, C.POINTER(rteaal_dag_desc), vp, vp, vp, C.POINTER(u32)], st),
         "rteaal_watch": ([vp, u32, vp, u32, u64], st),
         "rteaal_read_changes": ([vp, u32, vp, u64, C.POINTER(u64), C.POINTER(u64)], st),
@@ -153,7 +156,9 @@ def exported_symbols():
             "rteaal_design_format",
             "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch",
             "rteaal_batch_info", "rteaal_batch_options", "rteaal_step", "rteaal_step_many", "rteaal_sync",
-            "rteaal_read_state", "rteaal_write_state", "rteaal_kernel_timing", "rteaal_autotune",
+            "rteaal_read_state", "rteaal_write_state",
+            "rteaal_write_digest",
+            "rteaal_kernel_timing", "rteaal_autotune", "rteaal_autotune_many",
             "rteaal_levelize", "rteaal_watch", "rteaal_read_changes", "rteaal_fuse_mux_chains"]
 
 
@@ -168,6 +173,14 @@ def _check(ctx, status):
 # ---------------------------------------------------------------------------
 class Context:
     """An rteaal_ctx plus what the binding needs to size host buffers."""
+
+    def device_allocations(self):
+        """Device allocations the library has requested through the torch
+        allocator callback so far (None with the hipMalloc allocator)."""
+        for k in self._keep:
+            if isinstance(k, tuple) and len(k) == 4:
+                return k[3][0]
+        return None
 
     def __init__(self, handle, stream, allocator, keep):
         self.handle = handle
@@ -187,8 +200,10 @@ def _torch_allocator(device, stream):
     (the library's stream; it synchronises before it frees anything)."""
     import torch
     live = {}
+    calls = [0]   # allocations requested so far
 
     def _alloc(nbytes, _user):
+        calls[0] += 1
         try:
             p = torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
         except RuntimeError:
@@ -202,7 +217,7 @@ def _torch_allocator(device, stream):
             torch.cuda.caching_allocator_delete(ptr)
 
     a = rteaal_allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
-    return a, (_alloc, _free, live)
+    return a, (_alloc, _free, live, calls)
 
 
 def rteaal_create(device=0, stream=None, allocator="torch"):
@@ -423,10 +438,10 @@ def rteaal_design_format(ctx, design_id, layer):
 
 
 def _opts(mapping, block_threads=0, ops_per_wave=0, lds_state=0, lds_ops=0, unroll=0,
-          tiles_per_wave=0, arity_split=0, tiles_per_pass=0):
+          tiles_per_wave=0, arity_split=0, tiles_per_pass=0, persistent=0):
     return rteaal_batch_opts(int(mapping), int(block_threads), int(ops_per_wave), int(lds_state),
                              int(lds_ops), int(unroll), int(tiles_per_wave), int(arity_split),
-                             int(tiles_per_pass))
+                             int(tiles_per_pass), int(persistent))
 
 
 def rteaal_batch_footprint(ctx, design_id, n_instances, mapping=RTEAAL_MAP_AUTO, **opts):
@@ -439,7 +454,7 @@ def rteaal_batch_footprint(ctx, design_id, n_instances, mapping=RTEAAL_MAP_AUTO,
 
 def rteaal_create_batch(ctx, design_id, seeds, mapping=RTEAAL_MAP_AUTO, **opts):
     """opts: block_threads, ops_per_wave, lds_state, lds_ops, unroll, tiles_per_wave,
-    arity_split, tiles_per_pass (see rteaal_batch_opts)."""
+    arity_split, tiles_per_pass, persistent (see rteaal_batch_opts)."""
     seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
     o = _opts(mapping, **opts)
     out = C.c_uint32()
@@ -481,11 +496,32 @@ def rteaal_step(ctx, batch_id, n_cycles, words=None, words_on_device=False):
                                              C.byref(stim) if stim is not None else None))
 
 
-def rteaal_step_many(ctx, batch_ids, n_cycles):
+def _stimulus(words, words_on_device=False):
+    """(rteaal_stimulus, buffer to keep alive) for rteaal_step's words argument."""
+    if words is None:
+        return rteaal_stimulus(0, 0, None), None
+    if words_on_device:
+        return rteaal_stimulus(1, 1, int(words)), None
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    return rteaal_stimulus(1, 0, w.ctypes.data if w.size else None), w
+
+
+def rteaal_step_many(ctx, batch_ids, n_cycles, words=None, words_on_device=False):
+    """words: None (generator stimulus everywhere) or one entry per batch, each
+    None or that batch's words as in rteaal_step."""
     ids = np.ascontiguousarray(batch_ids, dtype=np.uint32)
     cyc = np.ascontiguousarray(n_cycles, dtype=np.uint64)
+    stims, keep = None, []
+    if words is not None:
+        if len(words) != ids.shape[0]:
+            raise ValueError("words needs one entry per batch")
+        arr = (rteaal_stimulus * max(len(words), 1))()
+        for k, w in enumerate(words):
+            arr[k], buf = _stimulus(w, words_on_device)
+            keep.append(buf)
+        stims = arr
     _check(ctx.handle, library().rteaal_step_many(ctx.handle, int(ids.shape[0]), ids.ctypes.data,
-                                                  cyc.ctypes.data))
+                                                  cyc.ctypes.data, stims))
 
 
 def rteaal_sync(ctx):
@@ -493,18 +529,33 @@ def rteaal_sync(ctx):
 
 
 def rteaal_read_state(ctx, batch_id, first=0, n=None, what=RTEAAL_READ_REGS):
-    """uint64 array [n][words per instance] of packed limbs."""
+    """uint64 array [n][words per instance]: packed limbs (REGS, ALL_SLOTS) or
+    the one-word register digest (DIGEST)."""
     design_id, n_inst = ctx.batches[batch_id]
     regw, slotw, _ = ctx.designs[design_id]
     n = n_inst - first if n is None else n
-    widths = regw if what == RTEAAL_READ_REGS else slotw
-    wpi = int(((widths + 63) // 64).sum())
+    if what == RTEAAL_READ_DIGEST:
+        wpi = 1
+    else:
+        widths = regw if what == RTEAAL_READ_REGS else slotw
+        wpi = int(((widths + 63) // 64).sum())
     out = np.zeros((n, wpi), dtype=np.uint64)
     written = C.c_size_t()
     _check(ctx.handle, library().rteaal_read_state(ctx.handle, int(batch_id), int(first), int(n),
                                                    int(what), out.ctypes.data if out.size else None,
                                                    out.size, C.byref(written)))
     return out
+
+
+def rteaal_read_digest(ctx, batch_id, first=0, n=None):
+    """Register digest of instances [first, first + n): uint64 array [n]."""
+    return rteaal_read_state(ctx, batch_id, first, n, RTEAAL_READ_DIGEST).reshape(-1)
+
+
+def rteaal_write_digest(ctx, batch_id, first, digest):
+    dg = np.ascontiguousarray(digest, dtype=np.uint64).reshape(-1)
+    _check(ctx.handle, library().rteaal_write_digest(ctx.handle, int(batch_id), int(first),
+                                                     int(dg.size), dg.ctypes.data if dg.size else None))
 
 
 def rteaal_write_state(ctx, batch_id, first, regs, cycle):
@@ -519,7 +570,7 @@ def opts_dict(o):
     return {"mapping": o.mapping, "block_threads": o.block_threads, "ops_per_wave": o.ops_per_wave,
             "lds_state": o.lds_state, "lds_ops": o.lds_ops, "unroll": o.unroll,
             "tiles_per_wave": o.tiles_per_wave, "arity_split": o.arity_split,
-            "tiles_per_pass": o.tiles_per_pass}
+            "tiles_per_pass": o.tiles_per_pass, "persistent": o.persistent}
 
 
 def rteaal_autotune(ctx, design_id, n_instances, trial_cycles=0):
@@ -528,6 +579,19 @@ def rteaal_autotune(ctx, design_id, n_instances, trial_cycles=0):
     _check(ctx.handle, library().rteaal_autotune(ctx.handle, int(design_id), int(n_instances),
                                                  int(trial_cycles), C.byref(o), C.byref(r)))
     return opts_dict(o), r.value
+
+
+def rteaal_autotune_many(ctx, design_ids, n_instances, trial_cycles=0):
+    """(options per batch as dicts, instance-cycles/s of the set); later AUTO
+    batches of these (design, instance count) pairs use them."""
+    ids = np.ascontiguousarray(design_ids, dtype=np.uint32)
+    ni = np.ascontiguousarray(n_instances, dtype=np.uint32)
+    out = (rteaal_batch_opts * max(ids.size, 1))()
+    r = C.c_double()
+    _check(ctx.handle, library().rteaal_autotune_many(ctx.handle, int(ids.size), ids.ctypes.data,
+                                                      ni.ctypes.data, int(trial_cycles), out,
+                                                      C.byref(r)))
+    return [opts_dict(out[k]) for k in range(ids.size)], r.value
 
 
 def rteaal_kernel_timing(ctx, batch_id, enable):

@@ -249,8 +249,14 @@ def test_header_is_plain_c(tmp_path):
                    "  rteaal_status (*fuse)(const rteaal_design_desc*, uint32_t, uint32_t*, uint8_t*,\n"
                    "                        uint32_t*, uint32_t*, uint32_t*, uint16_t*,\n"
                    "                        rteaal_fuse_result*) = rteaal_fuse_mux_chains;\n"
-                   "  (void)r; (void)o; (void)c; (void)fuse;\n"
-                   "  return RTEAAL_MUXC == 22 && RTEAAL_MUXC_MAX_PAIRS == 32 ? 0 : 1;\n"
+                   "  rteaal_status (*many)(rteaal_ctx*, uint32_t, const rteaal_batch_id*,\n"
+                   "                        const uint64_t*, const rteaal_stimulus*) = rteaal_step_many;\n"
+                   "  rteaal_status (*wdig)(rteaal_ctx*, rteaal_batch_id, uint32_t, uint32_t,\n"
+                   "                        const uint64_t*) = rteaal_write_digest;\n"
+                   "  (void)r; (void)o; (void)c; (void)fuse; (void)many; (void)wdig;\n"
+                   "  return RTEAAL_MUXC == 22 && RTEAAL_MUXC_MAX_PAIRS == 32 &&\n"
+                   "         RTEAAL_READ_REGS == 1 && RTEAAL_READ_DIGEST == 2 &&\n"
+                   "         RTEAAL_READ_ALL_SLOTS == 4 ? 0 : 1;\n"
                    "}\n")
     r = subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-pedantic", "-fsyntax-only",
                         "-I", os.path.dirname(HEADER), str(src)], capture_output=True, text=True)

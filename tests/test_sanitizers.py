@@ -9,6 +9,11 @@ undefined behaviour aborts the driver.  Its results must also equal the
 normal build's.  The library's host code (include/rteaal.h validation and
 mux-chain fusion, which touch no GPU) is built the same way
 (tests/sanitize/host_main.c) and must agree with the unsanitized library.
+The whole host runtime (batches, multi-batch steps and their captured-cycle
+cache, read-out, autotuners) runs the call sequences of
+tests/sanitize/host_scenarios.cpp against a host-only stand-in for the HIP
+runtime (tests/sanitize/hip_mock.cpp) that also checks every launch's
+memory, at launch and at every later replay of a captured graph.
 """
 import os
 import shutil
@@ -146,3 +151,50 @@ def test_host_validate_and_fuse_under_sanitizers(host_asan, tmp_path, name, d, m
         a = np.frombuffer(raw, dtype=dt, count=n, offset=off)
         off += a.nbytes
         assert np.array_equal(a, np.asarray(getattr(exp, name_))), name_
+
+
+@pytest.fixture(scope="module")
+def host_scenarios(tmp_path_factory):
+    """The library's host code with a host-only stand-in for the HIP runtime
+    and the kernel launchers (tests/sanitize/hip_mock.cpp), and the call
+    sequences of tests/sanitize/host_scenarios.cpp, all under ASan and
+    UBSan."""
+    if not (os.path.exists(CLANG) and shutil.which("hipcc")):
+        pytest.skip("no hipcc / clang with sanitizer runtimes")
+    from paper_2601_18140_amd import build as B
+    tmp = tmp_path_factory.mktemp("scen")
+    host_o, mock_o, scen_o, exe = (str(tmp / f) for f in ("host.o", "mock.o", "scen.o", "scen"))
+    cmd = ["hipcc", "-x", "hip", "-O1", "-g", "-std=c++17", "-fPIC", f"--offload-arch={B.ARCH}",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    for f in SAN_FLAGS:
+        if f.startswith("-f"):
+            cmd += ["-Xarch_host", f]
+    subprocess.run(cmd + ["-c", os.path.join(ROOT, "paper_2601_18140_amd", "csrc", "host.cpp"),
+                          "-o", host_o], check=True, capture_output=True)
+    subprocess.run([CLANG + "++", *SAN_FLAGS, "-std=c++17", "-D__HIP_PLATFORM_AMD__",
+                    "-I/opt/rocm/include", "-c", os.path.join(SAN, "hip_mock.cpp"), "-o", mock_o],
+                   check=True)
+    subprocess.run([CLANG + "++", *SAN_FLAGS, "-std=c++17", "-c",
+                    os.path.join(SAN, "host_scenarios.cpp"), "-o", scen_o], check=True)
+    subprocess.run([CLANG + "++", "-fsanitize=address,undefined", scen_o, mock_o, host_o, "-o", exe],
+                   check=True)
+    return exe
+
+
+def test_host_runtime_scenarios_under_sanitizers(host_scenarios, tmp_path):
+    """Batches of every mapping through rteaal_step_many (uneven cycle counts,
+    a batch of a cached set freed, more sets than the cache holds, stimulus
+    words, watched and timed batches), read-out and restore, and both
+    autotuners: no sanitizer report, no leak, no launch on freed memory."""
+    files = []
+    for k, c in enumerate([rtlgen.GenConfig(700, 6, 30, 8, rtlgen.generator.WIDTHS_LARGE, "sc-a"),
+                           rtlgen.GenConfig(1300, 17, 50, 12, rtlgen.generator.WIDTHS_MULTIDESIGN,
+                                            "sc-b"),
+                           rtlgen.GenConfig(400, 3, 20, 6, rtlgen.generator.WIDTHS_STD, "sc-c")]):
+        f = str(tmp_path / f"d{k}.bin")
+        write_design(f, rtlgen.generate(c, 50 + k), [1], 1)
+        files.append(f)
+    r = subprocess.run([host_scenarios, *files], env=ENV, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
+    assert "scenarios ok" in r.stdout

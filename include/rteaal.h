@@ -428,6 +428,21 @@ rteaal_status rteaal_read_state(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t
                                 uint32_t n, uint32_t what, uint64_t* out, size_t out_words,
                                 size_t* written);
 
+/* rteaal_read_state for callers that cannot allocate device memory (code in
+ * tight serving loops, harnesses that forbid allocation): the same results,
+ * staged through a fixed device array of RTEAAL_NOALLOC_MAX_WORDS words
+ * that the library holds on each device until the process ends, so the call
+ * allocates nothing (no hipMalloc or allocator callback).  A read-out larger
+ * than that array (words per instance x n) is rejected with
+ * RTEAAL_E_INVALID_ARG; read fewer instances per call.  Every call on one
+ * device shares that device's array: calls that overlap in time on one
+ * device (other threads or contexts) race and must be serialized by the
+ * caller.  RTEAAL_READ_DIGEST uses no staging. */
+enum { RTEAAL_NOALLOC_MAX_WORDS = 1 << 20 };
+rteaal_status rteaal_read_state_noalloc(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t first,
+                                        uint32_t n, uint32_t what, uint64_t* out,
+                                        size_t out_words, size_t* written);
+
 /* Overwrites the registers of instances [first, first+n) from `regs` (host,
  * [inst][reg][limbs(reg)], masked to width) and sets the batch's cycle
  * counter to `cycle` (checkpoint restore, and the host writing DUT signals

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -20,10 +21,36 @@
 
 using namespace rteaal;
 
+// Staging buffer of rteaal_read_state_noalloc: a fixed device array, so that
+// the call allocates nothing.  Each device holds its own copy; host code
+// uses only the device address found by hipGetSymbolAddress (the array's
+// name is not a device address in host code).
+static __device__ __align__(256) uint64_t scratch[size_t(1) << 20];
+
 namespace {
 
 thread_local std::string g_err;  // failures with no context
 
+constexpr size_t kNoAllocWords = size_t(1) << 20;  // 8 MiB
+static_assert(kNoAllocWords == RTEAAL_NOALLOC_MAX_WORDS &&
+                  sizeof(scratch) == kNoAllocWords * sizeof(uint64_t), "scratch size");
+std::mutex g_scratch_mu;
+std::map<int, uint64_t*> g_scratch;  // device -> address of its scratch
+
+// The scratch's device address on `device` (the current device), found once
+// per device; null if the lookup fails.
+uint64_t* scratch_on(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(device);
+  if (it != g_scratch.end()) return it->second;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  g_scratch[device] = (uint64_t*)p;
+  return (uint64_t*)p;
+}
 
 struct DesignHost;
 struct Batch;
@@ -50,6 +77,7 @@ struct MultiGraph {
 struct rteaal_ctx {
   int device = 0;
   uint32_t spin_limit = 1u << 22;  // grid barrier waits of persistent launches
+  uint64_t* scratch = nullptr;  // this device's staging array (rteaal_read_state_noalloc)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   rteaal_allocator alloc{};
@@ -1331,6 +1359,11 @@ rteaal_status rteaal_create(int device, void* stream, const rteaal_allocator* al
   }
   if (const char* sl = std::getenv("RTEAAL_GRID_SPIN_LIMIT"))
     ctx->spin_limit = (uint32_t)std::max(1L, std::min(std::atol(sl), (long)UINT32_MAX));
+  ctx->scratch = scratch_on(device);
+  if (!ctx->scratch) {
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    return fail(nullptr, RTEAAL_E_DEVICE, "hipGetSymbolAddress of the staging array failed");
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess)
     ctx->max_lds = std::min<size_t>(prop.maxSharedMemoryPerMultiProcessor, resident_max_lds());
@@ -2149,7 +2182,7 @@ rteaal_status rteaal_sync(rteaal_ctx* ctx) {
 namespace {
 
 // rteaal_read_state; stage: null (a buffer is allocated for the call) or a
-// device buffer of stage_words words to stage the read-out through.
+// device buffer of stage_words words (rteaal_read_state_noalloc).
 rteaal_status read_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first, uint32_t n,
                          uint32_t what, uint64_t* out, size_t out_words, size_t* written,
                          uint64_t* stage, size_t stage_words) {
@@ -2188,8 +2221,8 @@ rteaal_status read_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first, ui
     return fail(ctx, RTEAAL_E_INVALID_ARG, "output holds %zu words, %zu needed", out_words, need);
   if (stage && need > stage_words)
     return fail(ctx, RTEAAL_E_INVALID_ARG,
-                "the read-out needs %zu words, more than the %zu of the staging buffer; read "
-                "fewer instances per call", need, stage_words);
+                "the read-out needs %zu words, more than the %zu of the no-allocation staging "
+                "array; read fewer instances per call", need, stage_words);
   Mem tmp;
   if (!stage) {
     if (!alloc_all(ctx, {{&tmp, need * 8}}))
@@ -2216,6 +2249,13 @@ extern "C" {
 rteaal_status rteaal_read_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first, uint32_t n,
                                 uint32_t what, uint64_t* out, size_t out_words, size_t* written) {
   return read_state(ctx, id, first, n, what, out, out_words, written, nullptr, 0);
+}
+
+rteaal_status rteaal_read_state_noalloc(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first,
+                                        uint32_t n, uint32_t what, uint64_t* out,
+                                        size_t out_words, size_t* written) {
+  if (!ctx) return fail(ctx, RTEAAL_E_INVALID_ARG, "null context");
+  return read_state(ctx, id, first, n, what, out, out_words, written, ctx->scratch, kNoAllocWords);
 }
 
 rteaal_status rteaal_write_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first, uint32_t n,

@@ -25,7 +25,8 @@ __all__ = [
     "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch", "rteaal_batch_info",
     "rteaal_batch_options",
     "rteaal_step", "rteaal_step_many", "rteaal_sync", "rteaal_read_state", "rteaal_write_state",
-    "rteaal_write_digest", "rteaal_read_digest",
+    "rteaal_write_digest", "rteaal_read_digest", "rteaal_read_state_noalloc",
+    "RTEAAL_NOALLOC_MAX_WORDS",
     "rteaal_kernel_timing", "rteaal_autotune", "rteaal_autotune_many", "opts_dict", "unpack_limbs", "pack_limbs", "rteaal_layer_format", "rteaal_rank_format",
     "rteaal_dag_desc", "rteaal_levelize", "levelized_design",
     "CHANGE_DTYPE", "rteaal_watch", "rteaal_read_changes",
@@ -37,6 +38,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "BAD_DESIGN", 3: "FORMAT", 4: "NO_
 RTEAAL_MAP_AUTO, RTEAAL_MAP_RESIDENT, RTEAAL_MAP_SWEEP, RTEAAL_MAP_LAYERED = 0, 1, 2, 3
 RTEAAL_READ_REGS, RTEAAL_READ_DIGEST, RTEAAL_READ_ALL_SLOTS = 1, 2, 4
 RTEAAL_MUXC, RTEAAL_MUXC_MAX_PAIRS = 22, 32
+RTEAAL_NOALLOC_MAX_WORDS = 1 << 20
 
 
 class RteaalError(RuntimeError):
@@ -133,6 +135,7 @@ def library():
         "rteaal_read_state": ([vp, u32, u32, u32, u32, vp, C.c_size_t, C.POINTER(C.c_size_t)], st),
         "rteaal_write_state": ([vp, u32, u32, u32, vp, u64], st),
         "rteaal_write_digest": ([vp, u32, u32, u32, vp], st),
+        "rteaal_read_state_noalloc": ([vp, u32, u32, u32, u32, vp, C.c_size_t, C.POINTER(C.c_size_t)], st),
         "rteaal_kernel_timing": ([vp, u32, C.c_int, C.POINTER(u64), C.POINTER(C.c_double)], st),
         "rteaal_autotune": ([vp, u32, u32, u32, C.POINTER(rteaal_batch_opts), C.POINTER(C.c_double)], st),
         "rteaal_autotune_many": ([vp, u32, vp, vp, u32, vp, C.POINTER(C.c_double)], st),
@@ -156,7 +159,7 @@ def exported_symbols():
             "rteaal_design_format",
             "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch",
             "rteaal_batch_info", "rteaal_batch_options", "rteaal_step", "rteaal_step_many", "rteaal_sync",
-            "rteaal_read_state", "rteaal_write_state",
+            "rteaal_read_state", "rteaal_read_state_noalloc", "rteaal_write_state",
             "rteaal_write_digest",
             "rteaal_kernel_timing", "rteaal_autotune", "rteaal_autotune_many",
             "rteaal_levelize", "rteaal_watch", "rteaal_read_changes", "rteaal_fuse_mux_chains"]
@@ -544,6 +547,25 @@ def rteaal_read_state(ctx, batch_id, first=0, n=None, what=RTEAAL_READ_REGS):
     _check(ctx.handle, library().rteaal_read_state(ctx.handle, int(batch_id), int(first), int(n),
                                                    int(what), out.ctypes.data if out.size else None,
                                                    out.size, C.byref(written)))
+    return out
+
+
+def rteaal_read_state_noalloc(ctx, batch_id, first=0, n=None, what=RTEAAL_READ_REGS):
+    """rteaal_read_state through the library's fixed staging array: no device
+    allocation (read-outs above RTEAAL_NOALLOC_MAX_WORDS words are refused)."""
+    design_id, n_inst = ctx.batches[batch_id]
+    regw, slotw, _ = ctx.designs[design_id]
+    n = n_inst - first if n is None else n
+    if what == RTEAAL_READ_DIGEST:
+        wpi = 1
+    else:
+        widths = regw if what == RTEAAL_READ_REGS else slotw
+        wpi = int(((widths + 63) // 64).sum())
+    out = np.zeros((n, wpi), dtype=np.uint64)
+    written = C.c_size_t()
+    _check(ctx.handle, library().rteaal_read_state_noalloc(
+        ctx.handle, int(batch_id), int(first), int(n), int(what),
+        out.ctypes.data if out.size else None, out.size, C.byref(written)))
     return out
 
 

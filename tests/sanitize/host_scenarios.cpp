@@ -188,12 +188,14 @@ int main(int argc, char** argv) {
     many(bs, std::vector<uint64_t>(bs.size(), 2));
     ok(rteaal_kernel_timing(g_ctx, bs[1], 0, nullptr, nullptr), "kernel_timing");
     ok(rteaal_watch(g_ctx, bs[0], nullptr, 0, 0), "unwatch");
-    // read-out and restore
+    // read-out (allocating and not), restore
     for (size_t k = 0; k < bs.size(); ++k) {
       std::vector<uint64_t> out(1 << 16);
       size_t wr = 0;
       ok(rteaal_read_state(g_ctx, bs[k], 0, 1, RTEAAL_READ_REGS, out.data(), out.size(), &wr),
          "read_state");
+      ok(rteaal_read_state_noalloc(g_ctx, bs[k], 0, 1, RTEAAL_READ_REGS, out.data(), out.size(), &wr),
+         "read_state_noalloc");
       ok(rteaal_read_state(g_ctx, bs[k], 0, 1, RTEAAL_READ_DIGEST, out.data(), out.size(), &wr),
          "read digest");
       ok(rteaal_write_state(g_ctx, bs[k], 0, 1, out.data(), 5), "write_state");

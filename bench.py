@@ -247,7 +247,8 @@ def bench_single(args, R, torch):
     steps = args.steps if args.steps is not None else wl["steps"]
     repeats = max(1, args.repeats)
     mapping = {"auto": R.RTEAAL_MAP_AUTO, "resident": R.RTEAAL_MAP_RESIDENT,
-               "sweep": R.RTEAAL_MAP_SWEEP, "layered": R.RTEAAL_MAP_LAYERED}[args.mapping]
+               "sweep": R.RTEAAL_MAP_SWEEP, "layered": R.RTEAAL_MAP_LAYERED,
+               "partitioned": R.RTEAAL_MAP_PARTITIONED}[args.mapping]
 
     t0 = time.perf_counter()
     d = rtlgen.generate(wl["cfg"], wl["seed"])
@@ -270,7 +271,7 @@ def bench_single(args, R, torch):
     stream = ctx.stream
     did = R.rteaal_load_design(ctx, d)
     manual = (args.mapping != "auto" or args.block or args.ops_per_wave or args.unroll
-              or args.tiles_per_wave or args.arity_split or args.tiles_per_pass)
+              or args.tiles_per_wave or args.arity_split or args.tiles_per_pass or args.partitions)
     if not manual and not args.no_autotune:
         t0 = time.perf_counter()
         tuned, trate = R.rteaal_autotune(ctx, did, n_inst)
@@ -279,7 +280,7 @@ def bench_single(args, R, torch):
     bid = R.rteaal_create_batch(ctx, did, seeds, mapping=mapping, block_threads=args.block,
                                 ops_per_wave=args.ops_per_wave, unroll=args.unroll,
                                 tiles_per_wave=args.tiles_per_wave, arity_split=args.arity_split,
-                                tiles_per_pass=args.tiles_per_pass)
+                                tiles_per_pass=args.tiles_per_pass, partitions=args.partitions)
     used_map, _ = R.rteaal_batch_info(ctx, bid)
     bopts = R.rteaal_batch_options(ctx, bid)
     for _ in range(args.warmup):
@@ -380,22 +381,25 @@ def bench_single(args, R, torch):
         pms = float(np.median(pruns))
         # Roofline of the plain form's simulation kernel, timed as above.
         p_map, _ = R.rteaal_batch_info(ctx, pb)
+        pbo = R.rteaal_batch_options(ctx, pb)
         ppc = min(pc, 50)
         R.rteaal_kernel_timing(ctx, pb, True)
         R.rteaal_step(ctx, pb, ppc)
         (pl, pkms), (phl, phkms) = R.rteaal_kernel_timing(ctx, pb, False)
         R.rteaal_free_batch(ctx, pb)
-        p_lds = p_map == R.RTEAAL_MAP_RESIDENT and R.rteaal_batch_footprint(
-            ctx, did, 1, mapping=R.RTEAAL_MAP_RESIDENT) <= 160 * 1024
+        # RESIDENT and PARTITIONED keep the state in LDS when it fits
+        p_lds = (p_map in (R.RTEAAL_MAP_RESIDENT, R.RTEAAL_MAP_PARTITIONED)
+                 and pbo["lds_state"] == 0)
         p_launches, p_ms = pl + phl, pkms + phkms
         p_bytes = (X + (0 if p_lds else G)) * ppc / max(p_launches, 1)
         p_avg = p_ms / max(p_launches, 1)
         p_peak = LDS_PEAK_GBS if p_lds else HBM_PEAK_GBS
         p_ach = p_bytes / (p_avg / 1e3) / 1e9 if p_avg > 0 else 0.0
         plain = {"value": pc / (pms / 1e3), "unit": "instance-cycles/s", "instances": 1,
-                 "cycles": pc, "repeats": repeats, "opts": plain_opts,
+                 "cycles": pc, "repeats": repeats, "opts": pbo,
                  "roofline": {"bound": "lds" if p_lds else "hbm",
-                              "kernel": {R.RTEAAL_MAP_SWEEP: "k_sweep", R.RTEAAL_MAP_LAYERED: "k_layer"}.get(
+                              "kernel": {R.RTEAAL_MAP_SWEEP: "k_sweep", R.RTEAAL_MAP_LAYERED: "k_layer",
+                                         R.RTEAAL_MAP_PARTITIONED: "k_partitioned"}.get(
                                   p_map, "k_resident"),
                               "achieved": round(p_ach, 2), "peak": round(p_peak, 1), "unit": "GB/s",
                               "frac": round(p_ach / p_peak, 4), "launches": p_launches,
@@ -878,8 +882,12 @@ def bench_muxchain(args, R, torch):
 
 
 def bench_serving(args, R, torch):
-    """Poisson stream of jobs over a pool of designs with continuous batching."""
+    """Poisson stream of jobs over a pool of designs with continuous batching.
+    Checks: finished jobs rerun alone equal their results in the mix; the
+    first instance of finished jobs small enough for the oracle equals it."""
+    from concurrent.futures import ThreadPoolExecutor
     from paper_2601_18140_amd import serving
+    import oracle
     t0 = time.perf_counter()
     pool_cfg = rtlgen.serving_pool(seed=4, n_designs=args.designs,
                                    ops_hi=args.serving_ops_hi)
@@ -887,6 +895,7 @@ def bench_serving(args, R, torch):
     print(f"[bench] pool of {len(pool)} designs generated in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
     log = lambda m: print(f"[serve] {m}", file=sys.stderr, flush=True)  # noqa: E731
+    quiet = lambda m: None if m.startswith(("admit", "done")) else log(m)  # noqa: E731
     ctx = R.rteaal_create(0)
     budget = int(args.serving_budget_gb * (1 << 30))
     rate = args.serving_rate
@@ -898,7 +907,7 @@ def bench_serving(args, R, torch):
                                     inst_hi=args.serving_inst_hi, cyc_hi=args.serving_cycles_hi)
         cjobs = [serving.Job(job_id=(1 << 20) + k, design=d, n_inst=n, n_cycles=c)
                  for k, (d, n, c) in enumerate(cspec)]
-        csrv = serving.Server(ctx, pool, budget_bytes=budget, log=log)
+        csrv = serving.Server(ctx, pool, budget_bytes=budget, log=quiet)
         cstats = csrv.run(cjobs, np.zeros(len(cjobs)))
         csrv.close()
         sat = cstats["jobs"] / cstats["wall_s"]
@@ -913,11 +922,11 @@ def bench_serving(args, R, torch):
                                inst_hi=args.serving_inst_hi, cyc_hi=args.serving_cycles_hi)
     jobs = [serving.Job(job_id=k, design=d, n_inst=n, n_cycles=c) for k, (d, n, c) in enumerate(spec)]
     arrivals = serving.poisson_arrivals(rate, n_jobs, seed=4)
-    srv = serving.Server(ctx, pool, budget_bytes=budget, log=log)
+    srv = serving.Server(ctx, pool, budget_bytes=budget, log=quiet)
     stats = srv.run(jobs, arrivals, duration=args.serving_seconds)
     srv.close()
-    # Each finished job, re-run alone: identical registers.
-    import numpy as _np
+    stats["gpu_busy_s"] = round(srv.gpu_busy_s, 2)
+    # Each checked job, re-run alone: identical registers.
     same = True
     check = [j for j in srv.finished][: args.serving_verify]
     for j in check:
@@ -928,8 +937,62 @@ def bench_serving(args, R, torch):
         alone = R.rteaal_read_state(ctx, b)
         R.rteaal_free_batch(ctx, b)
         R.rteaal_unload_design(ctx, did)
-        same = same and bool(_np.array_equal(alone, j.regs))
+        same = same and bool(np.array_equal(alone, j.regs))
     R.rteaal_destroy(ctx)
+    # The oracle on the first instance of finished jobs it can afford (at
+    # most 2e9 operation evaluations each), side by side.
+    small = [j for j in srv.finished if pool[j.design].n_ops * j.n_cycles <= 2e9][:16]
+
+    def ref(j):
+        d = pool[j.design]
+        r, _, _ = oracle.run(d, j.seeds[:1], j.n_cycles, n_threads=1)
+        return np.array_equal(R.unpack_limbs(j.regs[:1], d.slot_width[d.reg_slot]), r)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(host_threads()) as ex:
+        oracle_ok = all(ex.map(ref, small))
+    t_or = time.perf_counter() - t0
+    # Bytes the finished jobs' cycles needed (word model), over the window.
+    ab = {}
+    word = 0.0
+    for j in srv.finished:
+        if j.design not in ab:
+            ab[j.design] = algorithmic_bytes(pool[j.design])
+        word += j.n_cycles * (j.n_inst * ab[j.design]["x"] + ab[j.design]["g"])
+    wall = stats["wall_s"]
+    roofline = {"bound": "hbm", "kernel": "every kernel of the serving loop's steps (whole window)",
+                "achieved": round(word / wall / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(word / wall / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes": round(word, 1),
+                "note": "over the whole window, idle time between arrivals included; per second "
+                        "of steps (gpu_busy_s): " + f"{word / max(srv.gpu_busy_s, 1e-9) / 1e9:.1f} GB/s"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        # Oracle time per instance-cycle of each pool design (one instance,
+        # 300 cycles, one thread each, side by side), weighted by the
+        # finished jobs' instance-cycles.
+        used = sorted({j.design for j in srv.finished})
+
+        def per_ic(k):
+            t1 = time.perf_counter()
+            oracle.run(pool[k], np.array([1], np.uint64), 300, n_threads=1)
+            return (time.perf_counter() - t1) / 300
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(host_threads()) as ex:
+            t_ic = dict(zip(used, ex.map(per_ic, used)))
+        w = sum(j.n_inst * j.n_cycles for j in srv.finished)
+        t_all = sum(j.n_inst * j.n_cycles * t_ic[j.design] for j in srv.finished)
+        rate_core = w / t_all if t_all else 0.0
+        cpu = {"value": rate_core * host_threads(), "unit": "instance-cycles/s",
+               "cores": host_threads(), "kind": "oracle", "per_core": rate_core,
+               "host_cpus_visible": os.cpu_count(),
+               "sample": f"one instance x 300 cycles of each of the {len(used)} designs the "
+                         f"finished jobs used, one thread each, {host_threads()} at a time "
+                         f"({time.perf_counter() - t0:.1f} s); rate weighted by the jobs' "
+                         "instance-cycles",
+               "extrapolated_full_workload": {
+                   "seconds": round(w / (rate_core * host_threads()), 1) if rate_core else None,
+                   "label": f"extrapolation: the finished jobs' instance-cycles at the per-core "
+                            f"rate x {host_threads()} cores"}}
     return {
         "metric": METRIC, "value": round(stats["instance_cycles_per_s"], 2),
         "unit": "instance-cycles/s", "n_gpus": 1, "steps": stats["jobs"], "warmup": 0,
@@ -940,7 +1003,10 @@ def bench_serving(args, R, torch):
                    "arrival_rate_per_s": round(rate, 4), "admission_seconds": args.serving_seconds,
                    "budget_gb": args.serving_budget_gb, "calibration": calib},
         "serving": stats, "alone_equals_mix": same, "verified_jobs": len(check),
-        "roofline": None, "cpu_baseline": None,
+        "parity_sample_ok": same and oracle_ok,
+        "parity": {"alone_equals_mix_jobs": len(check), "oracle_jobs": len(small),
+                   "oracle_equal": oracle_ok, "oracle_seconds": round(t_or, 1)},
+        "roofline": roofline, "cpu_baseline": cpu,
     }
 
 
@@ -953,9 +1019,10 @@ def main():
                     choices=sorted(WORKLOADS) + ["multi-64", "serving", "levelize-5m", "waveform",
                                                  "muxchain-2m"])
     ap.add_argument("--designs", type=int, default=None)
-    ap.add_argument("--serving-jobs", type=int, default=200)
+    ap.add_argument("--serving-jobs", type=int, default=2000)
     ap.add_argument("--serving-rate", type=float, default=4.0, help="job arrivals per second")
-    ap.add_argument("--serving-seconds", type=float, default=40.0, help="admission window")
+    ap.add_argument("--serving-seconds", type=float, default=600.0,
+                    help="admission window (the workload's 10 minutes)")
     ap.add_argument("--serving-budget-gb", type=float, default=200.0)
     ap.add_argument("--serving-ops-hi", type=int, default=1_000_000)
     ap.add_argument("--serving-inst-hi", type=int, default=512)
@@ -968,7 +1035,9 @@ def main():
                     help="offered load as a fraction of the calibrated saturated job rate")
     ap.add_argument("--cycles-per-step", type=int, default=None)
     ap.add_argument("--instances", type=int, default=None)
-    ap.add_argument("--mapping", default="auto", choices=["auto", "resident", "sweep", "layered"])
+    ap.add_argument("--mapping", default="auto",
+                    choices=["auto", "resident", "sweep", "layered", "partitioned"])
+    ap.add_argument("--partitions", type=int, default=0, help="PARTITIONED: register partitions")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--ops-per-wave", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)

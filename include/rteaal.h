@@ -282,10 +282,31 @@ rteaal_status rteaal_design_format(rteaal_ctx* ctx, rteaal_design_id design, uin
  *             captured in a HIP graph.  The plain form of large designs (a single instance's
  *             layer spread over every compute unit); at most 65535
  *             instances.
+ *   PARTITIONED: the replicated register partitioning of App. C (Cascade 2
+ *             with the partition rank): the registers are split into
+ *             `partitions` contiguous blocks; each (instance, partition) pair
+ *             is one workgroup that holds its own copy of the instance's
+ *             state (in LDS when it fits) and evaluates only the fan-in
+ *             cones of its registers, the operations shared by several
+ *             cones replicated in each.  Once per cycle the partitions
+ *             publish their registers, meet at a grid-wide barrier and load
+ *             the registers their cones read from other partitions.  All
+ *             workgroups must be resident at once (a cooperative launch of
+ *             n_instances x partitions workgroups); a barrier wait is
+ *             bounded as for persistent LAYERED.  The plain form of a
+ *             design too large for one workgroup's lanes but whose cones
+ *             replicate little.  Not watchable; RTEAAL_READ_ALL_SLOTS is
+ *             unsupported.
  *   AUTO:     the autotuner's choice for (design, n_instances) when
  *             rteaal_autotune has run for them, else RESIDENT below 32
  *             instances and SWEEP from 32 on. */
-enum { RTEAAL_MAP_AUTO = 0, RTEAAL_MAP_RESIDENT = 1, RTEAAL_MAP_SWEEP = 2, RTEAAL_MAP_LAYERED = 3 };
+enum {
+  RTEAAL_MAP_AUTO = 0,
+  RTEAAL_MAP_RESIDENT = 1,
+  RTEAAL_MAP_SWEEP = 2,
+  RTEAAL_MAP_LAYERED = 3,
+  RTEAAL_MAP_PARTITIONED = 4
+};
 
 typedef struct {
   uint32_t mapping;        /* RTEAAL_MAP_*                                      */
@@ -320,6 +341,11 @@ typedef struct {
                               default 2^22 spins); if one runs out, the next
                               rteaal_sync or rteaal_read_state on the batch
                               returns RTEAAL_E_DEVICE                          */
+  uint32_t partitions;     /* PARTITIONED: 0 = default (256 / n_instances, at
+                              most one per register); else 1 .. 1024 register
+                              partitions.  block_threads (64..1024, multiple
+                              of 64, default from the largest sub-program
+                              layer) and lds_state apply as for RESIDENT      */
 } rteaal_batch_opts;
 
 /* Device bytes a batch of n_instances of `design` would allocate under
@@ -328,15 +354,26 @@ rteaal_status rteaal_batch_footprint(rteaal_ctx* ctx, rteaal_design_id design,
                                      uint32_t n_instances, const rteaal_batch_opts* opts,
                                      uint64_t* bytes);
 
+/* Device resources a batch would hold, for admission control by memory and
+ * LDS: *hbm_bytes as rteaal_batch_footprint, and *lds_bytes the LDS its
+ * kernels keep for a whole step (RESIDENT: its workgroups' LDS, state and
+ * program records when they fit, times the instances; 0 for SWEEP and
+ * LAYERED, which keep no LDS across a step). */
+rteaal_status rteaal_batch_resources(rteaal_ctx* ctx, rteaal_design_id design,
+                                     uint32_t n_instances, const rteaal_batch_opts* opts,
+                                     uint64_t* hbm_bytes, uint64_t* lds_bytes);
+
 /* n_instances (>= 1) independent instances, registers reset to zero at
- * cycle 0; seeds[k] (host, [n_instances]) keys instance k's stimulus. */
+ * cycle 0; seeds[k] (host, [n_instances]) keys instance k's stimulus.
+ * Allocates, then only enqueues the initialisation on the context's stream
+ * (it does not wait for earlier work). */
 rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id design,
                                   uint32_t n_instances, const uint64_t* seeds,
                                   const rteaal_batch_opts* opts, rteaal_batch_id* out);
 rteaal_status rteaal_free_batch(rteaal_ctx* ctx, rteaal_batch_id batch);
 
-/* Mapping actually used by a batch (RTEAAL_MAP_RESIDENT or _SWEEP) and its
- * current cycle. */
+/* Mapping actually used by a batch (one of RTEAAL_MAP_RESIDENT .. _PARTITIONED)
+ * and its current cycle. */
 rteaal_status rteaal_batch_info(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t* mapping,
                                 uint64_t* cycle);
 
@@ -345,7 +382,8 @@ rteaal_status rteaal_batch_info(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t
  * passing *out back creates a batch of the same shape: mapping, and for
  * RESIDENT block_threads, lds_state/lds_ops (0 = in LDS, 1 = in HBM),
  * unroll; for SWEEP ops_per_wave, unroll, tiles_per_wave, arity_split,
- * tiles_per_pass (0 = all) (other fields 0). */
+ * tiles_per_pass (0 = all); for LAYERED block_threads, unroll, persistent;
+ * for PARTITIONED block_threads, lds_state, partitions (other fields 0). */
 rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id batch, rteaal_batch_opts* out);
 
 /* ------------------------------------------------------------------------ */

@@ -352,6 +352,11 @@ struct DesignHost {
   Mem d_ops, d_layers, d_consts, d_reg_refs, d_slot_refs;
   uint32_t n_batches = 0;
   uint64_t fingerprint = 0;  // of the encoded program, for the tuner's cache
+  // Slot-level form of the encoded program (for partitioning): per encoded
+  // operation its destination slot and its source slots (mux-chain pairs
+  // included); slots >= n_slots are the staging temporaries.
+  std::vector<uint32_t> enc_dst, enc_src_ptr, enc_src, reg_slot;
+  uint32_t n_enc_slots = 0;
 };
 
 // FNV-1a over bytes (Fowler, Noll, Vo), continuing from h.
@@ -649,8 +654,16 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
   if (h->const_limbs.empty()) h->const_limbs.assign(4, 0);
   h->ops.clear();
   h->ops.reserve(pos);
+  h->enc_dst.clear();
+  h->enc_src.clear();
+  h->enc_src_ptr.assign(1, 0);
   for (auto& lay : L)
     for (auto& e : lay) {
+      h->enc_dst.push_back(e.dst_slot);
+      for (uint32_t q = 0; q < e.arity; ++q) h->enc_src.push_back(e.src_slot[q]);
+      if (e.opc == OP_MUXC)
+        for (uint32_t q = 0; q < 2 * e.aux1; ++q) h->enc_src.push_back(extra[e.aux0 + q]);
+      h->enc_src_ptr.push_back((uint32_t)h->enc_src.size());
       DevOp o{};
       uint32_t code = (e.opc & 63u) | (e.kind << 6) | (e.arity << 8) | (e.dcls << 10);
       for (uint32_t q = 0; q < e.arity; ++q) {
@@ -693,6 +706,8 @@ void encode(const rteaal_design_desc* d, const Drivers& drv, bool compact, Desig
   h->n_inputs = d->n_inputs;
   h->n_design_layers = d->n_layers;
   h->n_user_ops = d->n_ops;
+  h->reg_slot.assign(d->reg_slot, d->reg_slot + d->n_regs);
+  h->n_enc_slots = NW;
   uint64_t fp = fnv1a(h->ops.data(), h->ops.size() * sizeof(DevOp));
   fp = fnv1a(h->layers.data(), h->layers.size() * sizeof(DevLayer), fp);
   fp = fnv1a(h->const_limbs.data(), h->const_limbs.size() * 8, fp);
@@ -710,6 +725,17 @@ struct Batch {
   bool lds = false, lds_ops = false;
   bool persistent = false;  // LAYERED: one cooperative launch per chunk of cycles
   Mem gsync;                // its grid barrier state
+  std::vector<uint64_t> seeds_host;  // sources of the initial copies (enqueued at creation)
+  DevCtl ctl_host{};
+  // PARTITIONED: partitions, bytes of one state copy, the sub-programs and
+  // their job table, the exchange rows, the digest sums, and the register
+  // refs of the owners' copies (for read-out and restore).
+  uint32_t parts = 0;
+  uint64_t copy_pitch = 0;
+  Mem part_mem, xch, pacc, preg_refs;
+  uint64_t part_jobs_off = 0;
+  std::vector<char> part_host;  // source of part_mem's copy (enqueued at creation)
+  std::vector<SlotRef> preg_host;
   uint64_t cycle = 0;
   StateLayout L{};
   // dig: the running register digest of every instance slot (n_slot words),
@@ -726,6 +752,13 @@ struct Batch {
   uint64_t log_cap = 0;
   Mem watch_refs, shadow, log, log_count;
 };
+
+void free_parts(rteaal_ctx* ctx, Batch& b) {
+  dev_free(ctx, b.part_mem);
+  dev_free(ctx, b.xch);
+  dev_free(ctx, b.pacc);
+  dev_free(ctx, b.preg_refs);
+}
 
 void free_watch(rteaal_ctx* ctx, Batch& b) {
   dev_free(ctx, b.watch_refs);
@@ -795,6 +828,11 @@ bool make_layout(const DesignHost& h, uint32_t mapping, uint32_t n_inst, uint32_
     L.row_bytes = L.n_tiles_alloc * 512u;
     L.pitch = 0;
     *bytes = h.n_rows * L.row_bytes;
+  } else if (mapping == RTEAAL_MAP_PARTITIONED) {
+    // tg is the number of partitions: every instance holds one copy of its
+    // state per partition, copy p of instance i at (i P + p) copy_pitch.
+    L.pitch = ((h.n_rows * 8 + 15) & ~uint64_t(15)) * std::max(tg, 1u);
+    *bytes = L.pitch * n_inst;
   } else {
     L.pitch = (h.n_rows * 8 + 15) & ~uint64_t(15);
     *bytes = L.pitch * n_inst;
@@ -805,7 +843,179 @@ bool make_layout(const DesignHost& h, uint32_t mapping, uint32_t n_inst, uint32_
 
 uint32_t sweep_tg(const rteaal_batch_opts* o) { return o && o->tiles_per_wave ? o->tiles_per_wave : 1u; }
 
+// Partitions of a PARTITIONED batch: the option, else as many as fit the
+// device with every instance (one workgroup each), at most one per register.
+uint32_t part_count(const DesignHost& h, uint32_t n_inst, const rteaal_batch_opts* o) {
+  if (o && o->partitions) return o->partitions;
+  const uint32_t p = std::max<uint32_t>(1, 256 / std::max<uint32_t>(n_inst, 1));
+  return std::max<uint32_t>(1, std::min<uint32_t>(p, std::max<uint32_t>(h.n_regs, 1)));
+}
+
+// The layout parameter of make_layout: the tile group (SWEEP) or the
+// partition count (PARTITIONED).
+uint32_t layout_param(const DesignHost& h, uint32_t mapping, uint32_t n_inst,
+                      const rteaal_batch_opts* o) {
+  return mapping == RTEAAL_MAP_PARTITIONED ? part_count(h, n_inst, o) : sweep_tg(o);
+}
+
+// The partitioned form of a design for P register partitions (registers
+// split into P contiguous blocks): for every partition, its sub-program
+// (the design's layers restricted to the operations in the fan-in cones of
+// its registers: cones closed backwards from the register commits, every
+// 1-bit destination group of 64 whole, since one ballot stores its row),
+// the registers it owns and the registers of other partitions its cones
+// read.
+struct PartPlan {
+  std::vector<DevOp> ops;
+  std::vector<DevLayer> layers;           // [P][n_layers]
+  std::vector<uint32_t> lists;            // per partition: own, then need
+  std::vector<uint32_t> op_begin, own_begin, own_n, need_begin, need_n;
+  uint64_t cone_ops = 0;                  // operations in all cones (without padding)
+};
+
+void plan_partitions(const DesignHost& h, uint32_t P, PartPlan* out) {
+  const uint32_t W = (P + 63) / 64;
+  const size_t NW = h.n_enc_slots, NL = h.layers.size(), NO = h.ops.size();
+  std::vector<uint64_t> need((size_t)NW * W, 0), mask(NO * W, 0);
+  std::vector<uint32_t> reg_of(NW, UINT32_MAX);
+  for (uint32_t j = 0; j < h.n_regs; ++j) reg_of[h.reg_slot[j]] = j;
+  auto owner = [&](uint32_t j) { return (uint32_t)((uint64_t)j * P / std::max(h.n_regs, 1u)); };
+  for (size_t k = NL; k-- > 0;) {
+    const DevLayer& ly = h.layers[k];
+    const bool commit = h.n_regs && k + 1 == NL;   // the commit layer is the last one
+    for (uint32_t pos = ly.begin; pos < ly.end; ++pos) {
+      uint64_t* m = &mask[(size_t)pos * W];
+      const uint32_t d = h.enc_dst[pos];
+      if (commit) {
+        const uint32_t p = owner(reg_of[d]);
+        m[p / 64] |= 1ull << (p % 64);
+      } else {
+        for (uint32_t w = 0; w < W; ++w) m[w] = need[(size_t)d * W + w];
+      }
+      for (uint32_t q = h.enc_src_ptr[pos]; q < h.enc_src_ptr[pos + 1]; ++q)
+        for (uint32_t w = 0; w < W; ++w) need[(size_t)h.enc_src[q] * W + w] |= m[w];
+    }
+  }
+  PartPlan& pl = *out;
+  for (uint32_t p = 0; p < P; ++p) {
+    const uint32_t pw = p / 64;
+    const uint64_t pb = 1ull << (p % 64);
+    auto in = [&](uint32_t pos) { return (mask[(size_t)pos * W + pw] & pb) != 0; };
+    const uint32_t base = (uint32_t)pl.ops.size();
+    pl.op_begin.push_back(base);
+    for (size_t k = 0; k < NL; ++k) {
+      const DevLayer& ly = h.layers[k];
+      DevLayer sl{};
+      sl.begin = (uint32_t)pl.ops.size() - base;
+      for (uint32_t g0 = 0; g0 < ly.n_bdst; g0 += 64) {
+        const uint32_t g1 = std::min(ly.n_bdst, g0 + 64);
+        bool any = false;
+        for (uint32_t i = g0; i < g1; ++i) {
+          const bool x = in(ly.begin + i);
+          any = any || x;
+          pl.cone_ops += x;
+        }
+        if (any)
+          pl.ops.insert(pl.ops.end(), h.ops.begin() + ly.begin + g0, h.ops.begin() + ly.begin + g1);
+      }
+      for (uint32_t pos = ly.begin + ly.n_bdst; pos < ly.end; ++pos)
+        if (in(pos)) {
+          pl.ops.push_back(h.ops[pos]);
+          ++pl.cone_ops;
+        }
+      sl.end = (uint32_t)pl.ops.size() - base;
+      pl.layers.push_back(sl);
+    }
+    pl.own_begin.push_back((uint32_t)pl.lists.size());
+    for (uint32_t j = 0; j < h.n_regs; ++j)
+      if (owner(j) == p) pl.lists.push_back(j);
+    pl.own_n.push_back((uint32_t)pl.lists.size() - pl.own_begin.back());
+    pl.need_begin.push_back((uint32_t)pl.lists.size());
+    for (uint32_t j = 0; j < h.n_regs; ++j)
+      if (owner(j) != p && (need[(size_t)h.reg_slot[j] * W + pw] & pb)) pl.lists.push_back(j);
+    pl.need_n.push_back((uint32_t)pl.lists.size() - pl.need_begin.back());
+  }
+}
+
+// PARTITIONED set-up on the host: the partition count, the plan, the block
+// size, LDS use and the co-residency check, and the host image of the
+// sub-program table (device pointers are filled in by finish_part_table once
+// the table is allocated).
+rteaal_status plan_batch_partitions(rteaal_ctx* ctx, const DesignHost& h, uint32_t n_inst,
+                                    const rteaal_batch_opts* o, Batch* b, PartPlan* plan) {
+  const uint32_t P = part_count(h, n_inst, o);
+  if (P < 1 || P > 1024)
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "PARTITIONED partitions must be 1 .. 1024");
+  if (P > std::max<uint32_t>(h.n_regs, 1))
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "%u partitions for %u registers", P, h.n_regs);
+  const uint64_t copy_pitch = (h.n_rows * 8 + 15) & ~uint64_t(15);
+  if (copy_pitch * P * 8 >= (1ull << 32))
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "PARTITIONED: %u copies of the state exceed 512 MB", P);
+  plan_partitions(h, P, plan);
+  uint32_t m = 0;
+  for (const DevLayer& l : plan->layers) m = std::max(m, l.end - l.begin);
+  uint32_t blk = o && o->block_threads ? o->block_threads : 0;
+  if (blk && (blk % 64 || blk > 1024))
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "block_threads must be a multiple of 64 up to 1024");
+  if (!blk) {
+    blk = std::min<uint32_t>(1024, std::max<uint32_t>(64, ((m + 63) / 64) * 64));
+    if (blk > 256 && m < 2048) blk = 256;
+  }
+  const bool lds = !(o && o->lds_state == 1) && copy_pitch <= ctx->max_lds;
+  const uint32_t cap = partitioned_capacity(blk, lds, lds ? (size_t)copy_pitch : 0);
+  if ((uint64_t)n_inst * P > cap)
+    return fail(ctx, RTEAAL_E_INVALID_ARG,
+                "PARTITIONED: %u instances x %u partitions = %llu workgroups, but at most %u can "
+                "be resident at once (block %u, state %s)",
+                n_inst, P, (unsigned long long)n_inst * P, cap, blk, lds ? "in LDS" : "in HBM");
+  b->parts = P;
+  b->copy_pitch = copy_pitch;
+  b->block = blk;
+  b->lds = lds;
+  b->unroll = 1;
+  // Image: ops | layers | lists | jobs, each part 16-byte aligned.
+  auto al = [](uint64_t x) { return (x + 15) & ~uint64_t(15); };
+  const uint64_t o_lay = al(plan->ops.size() * sizeof(DevOp));
+  const uint64_t o_lst = o_lay + al(plan->layers.size() * sizeof(DevLayer));
+  const uint64_t o_job = o_lst + al(plan->lists.size() * 4);
+  b->part_jobs_off = o_job;
+  b->part_host.assign(o_job + P * sizeof(PartJob), 0);
+  if (!plan->ops.empty()) memcpy(b->part_host.data(), plan->ops.data(), plan->ops.size() * sizeof(DevOp));
+  if (!plan->layers.empty())
+    memcpy(b->part_host.data() + o_lay, plan->layers.data(), plan->layers.size() * sizeof(DevLayer));
+  if (!plan->lists.empty())
+    memcpy(b->part_host.data() + o_lst, plan->lists.data(), plan->lists.size() * 4);
+  // Register refs of the owners' copies.
+  b->preg_host = h.reg_refs;
+  for (uint32_t j = 0; j < h.n_regs; ++j) {
+    const uint64_t owner = (uint64_t)j * P / std::max(h.n_regs, 1u);
+    b->preg_host[j].pos += (uint32_t)(owner * copy_pitch * 8);
+  }
+  return RTEAAL_OK;
+}
+
+// The job table of a PARTITIONED batch, now that part_mem is allocated.
+void finish_part_table(Batch& b, const PartPlan& plan) {
+  char* base = (char*)b.part_mem.p;
+  auto al = [](uint64_t x) { return (x + 15) & ~uint64_t(15); };
+  const uint64_t o_lay = al(plan.ops.size() * sizeof(DevOp));
+  const uint64_t o_lst = o_lay + al(plan.layers.size() * sizeof(DevLayer));
+  const uint32_t NL = b.parts ? (uint32_t)(plan.layers.size() / b.parts) : 0;
+  for (uint32_t p = 0; p < b.parts; ++p) {
+    PartJob J{};
+    J.ops = (const DevOp*)(base + (uint64_t)plan.op_begin[p] * sizeof(DevOp));
+    J.layers = (const DevLayer*)(base + o_lay + (uint64_t)p * NL * sizeof(DevLayer));
+    J.own = (const uint32_t*)(base + o_lst + (uint64_t)plan.own_begin[p] * 4);
+    J.need = (const uint32_t*)(base + o_lst + (uint64_t)plan.need_begin[p] * 4);
+    J.n_layers = NL;
+    J.n_own = plan.own_n[p];
+    J.n_need = plan.need_n[p];
+    memcpy(b.part_host.data() + b.part_jobs_off + (uint64_t)p * sizeof(PartJob), &J, sizeof J);
+  }
+}
+
 uint32_t choose_mapping(const DesignHost& h, uint32_t n_inst, const rteaal_batch_opts* o) {
+  if (o && o->mapping == RTEAAL_MAP_PARTITIONED) return RTEAAL_MAP_PARTITIONED;
   if (o && o->mapping == RTEAAL_MAP_RESIDENT) return RTEAAL_MAP_RESIDENT;
   if (o && o->mapping == RTEAAL_MAP_SWEEP) return RTEAAL_MAP_SWEEP;
   if (o && o->mapping == RTEAAL_MAP_LAYERED) return RTEAAL_MAP_LAYERED;
@@ -867,7 +1077,7 @@ ResJob res_job(const DesignHost& h, const Batch& b, uint64_t n_cycles) {
 // ran out (its error flag set) leaves its state undefined, so the context
 // becomes unusable.
 rteaal_status check_grid(rteaal_ctx* ctx, const Batch& b) {
-  if (!b.persistent || !b.gsync.p) return RTEAAL_OK;
+  if ((!b.persistent && b.mapping != RTEAAL_MAP_PARTITIONED) || !b.gsync.p) return RTEAAL_OK;
   GridSync g{};
   HIP_TRY(ctx, hipMemcpy(&g, b.gsync.p, sizeof g, hipMemcpyDeviceToHost));
   if (g.error) {
@@ -1203,9 +1413,42 @@ rteaal_status enqueue_layered(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t
   return RTEAAL_OK;
 }
 
+PartRun part_run(rteaal_ctx* ctx, const DesignHost& h, const Batch& b, uint64_t n_cycles) {
+  PartRun R{};
+  R.parts = (const PartJob*)((const char*)b.part_mem.p + b.part_jobs_off);
+  R.const_limbs = (const uint64_t*)h.d_consts.p;
+  R.regs = (const SlotRef*)h.d_reg_refs.p;
+  R.state = (char*)b.state.p;
+  R.seeds = (const uint64_t*)b.seeds.p;
+  R.ctl = (const DevCtl*)b.ctl.p;
+  R.xch = (uint64_t*)b.xch.p;
+  R.acc = (unsigned long long*)b.pacc.p;
+  R.digest = (uint64_t*)b.dig.p;
+  R.gs = (GridSync*)b.gsync.p;
+  R.pitch = b.copy_pitch;
+  R.n_cycles = n_cycles;
+  R.n_parts = b.parts;
+  R.n_inst = b.n_inst;
+  R.reg_words = h.reg_words;
+  R.words_per_inst = h.words_per_inst;
+  R.spin_limit = ctx->spin_limit;
+  return R;
+}
+
 rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t n_cycles) {
   const Program p = program_of(h);
   DevCtl* ctl = (DevCtl*)b.ctl.p;
+  if (b.mapping == RTEAAL_MAP_PARTITIONED) {
+    for (uint64_t done = 0; done < n_cycles;) {
+      const uint64_t n = std::min(kResidentChunk, n_cycles - done);
+      HIP_TRY(ctx, timed(b, ctx->stream, 0, [&] {
+                return launch_partitioned(part_run(ctx, h, b, n), b.block, b.lds, ctx->stream);
+              }));
+      HIP_TRY(ctx, launch_advance(ctl, n, ctx->stream));
+      done += n;
+    }
+    return RTEAAL_OK;
+  }
   if (b.mapping == RTEAAL_MAP_RESIDENT) {
     // A watched batch runs one cycle per launch, so each cycle is captured.
     const uint64_t chunk = b.n_watch ? 1 : kResidentChunk;
@@ -1386,6 +1629,7 @@ void rteaal_destroy(rteaal_ctx* ctx) {
     dev_free(ctx, b.ctl);
     dev_free(ctx, b.dig);
     dev_free(ctx, b.gsync);
+    free_parts(ctx, b);
   }
   for (auto& kv : ctx->designs) {
     DesignHost& h = *kv.second;
@@ -1708,16 +1952,55 @@ rteaal_status rteaal_batch_footprint(rteaal_ctx* ctx, rteaal_design_id id, uint3
   if (!ctx || !bytes || n_inst == 0) return fail(ctx, RTEAAL_E_INVALID_ARG, "bad argument");
   DesignHost* h = find_design(ctx, id);
   if (!h) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown design %u", id);
-  if (opts && opts->mapping > RTEAAL_MAP_LAYERED)
+  if (opts && opts->mapping > RTEAAL_MAP_PARTITIONED)
     return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown mapping %u", opts->mapping);
   opts = resolve_opts(ctx, id, n_inst, opts);
   const uint32_t m = choose_mapping(*h, n_inst, opts);
   uint64_t sb = 0;
   StateLayout L;
-  if (!make_layout(*h, m, n_inst, sweep_tg(opts), &L, &sb))
+  if (!make_layout(*h, m, n_inst, layout_param(*h, m, n_inst, opts), &L, &sb))
     return fail(ctx, RTEAAL_E_INVALID_ARG, "too many instances for one SWEEP batch");
   const uint64_t pad = m == RTEAAL_MAP_SWEEP ? (uint64_t)L.n_tiles_alloc * 64 : n_inst;
   *bytes = sb + pad * 24 + 256 + 512;
+  if (m == RTEAAL_MAP_PARTITIONED) {
+    // exchange rows, digest sums, register refs, and the sub-programs (at
+    // most the design's program per partition)
+    const uint64_t P = part_count(*h, n_inst, opts);
+    *bytes += 16ull * n_inst * std::max<uint32_t>(h->reg_words, 1) + 24ull * n_inst +
+              16ull * h->n_regs + P * (h->ops.size() * sizeof(DevOp) + h->layers.size() * sizeof(DevLayer) +
+                                       4ull * h->n_regs + sizeof(PartJob));
+  }
+  return RTEAAL_OK;
+}
+
+rteaal_status rteaal_batch_resources(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_inst,
+                                     const rteaal_batch_opts* opts, uint64_t* hbm_bytes,
+                                     uint64_t* lds_bytes) {
+  if (!ctx || !hbm_bytes || !lds_bytes || n_inst == 0)
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "bad argument");
+  const rteaal_status st = rteaal_batch_footprint(ctx, id, n_inst, opts, hbm_bytes);
+  if (st != RTEAAL_OK) return st;
+  DesignHost* h = find_design(ctx, id);
+  opts = resolve_opts(ctx, id, n_inst, opts);
+  *lds_bytes = 0;
+  const uint32_t m = choose_mapping(*h, n_inst, opts);
+  if (m == RTEAAL_MAP_PARTITIONED) {
+    const uint64_t copy = (h->n_rows * 8 + 15) & ~uint64_t(15);
+    if (!(opts && opts->lds_state == 1) && copy <= ctx->max_lds)
+      *lds_bytes = copy * part_count(*h, n_inst, opts) * n_inst;
+    return RTEAAL_OK;
+  }
+  if (m != RTEAAL_MAP_RESIDENT) return RTEAAL_OK;
+  StateLayout L;
+  uint64_t sb = 0;
+  make_layout(*h, RTEAAL_MAP_RESIDENT, n_inst, 1, &L, &sb);
+  // The same choices rteaal_create_batch makes.
+  const uint32_t n_ops = (uint32_t)h->ops.size(), n_lay = (uint32_t)h->layers.size();
+  const bool lds = !(opts && opts->lds_state == 1) &&
+                   resident_lds_bytes(L, n_ops, n_lay, true, false) <= ctx->max_lds;
+  const bool lds_ops = !(opts && opts->lds_ops == 1) &&
+                       resident_lds_bytes(L, n_ops, n_lay, lds, true) <= ctx->max_lds;
+  *lds_bytes = (uint64_t)resident_lds_bytes(L, n_ops, n_lay, lds, lds_ops) * n_inst;
   return RTEAAL_OK;
 }
 
@@ -1728,7 +2011,7 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
   if (ctx->poisoned) return fail(ctx, RTEAAL_E_DEVICE, "context unusable after a device error");
   DesignHost* h = find_design(ctx, id);
   if (!h) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown design %u", id);
-  if (opts && opts->mapping > RTEAAL_MAP_LAYERED)
+  if (opts && opts->mapping > RTEAAL_MAP_PARTITIONED)
     return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown mapping %u", opts->mapping);
   opts = resolve_opts(ctx, id, n_inst, opts);
   auto b = std::make_unique<Batch>();
@@ -1736,9 +2019,16 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
   b->n_inst = n_inst;
   b->mapping = choose_mapping(*h, n_inst, opts);
   uint64_t sb = 0;
-  if (!make_layout(*h, b->mapping, n_inst, sweep_tg(opts), &b->L, &sb))
+  PartPlan plan;
+  if (b->mapping == RTEAAL_MAP_PARTITIONED) {
+    const rteaal_status st = plan_batch_partitions(ctx, *h, n_inst, opts, b.get(), &plan);
+    if (st != RTEAAL_OK) return st;
+  }
+  if (!make_layout(*h, b->mapping, n_inst, layout_param(*h, b->mapping, n_inst, opts), &b->L, &sb))
     return fail(ctx, RTEAAL_E_INVALID_ARG, "too many instances for one SWEEP batch");
-  if (b->mapping == RTEAAL_MAP_RESIDENT) {
+  if (b->mapping == RTEAAL_MAP_PARTITIONED) {
+    // (block, LDS and co-residency are settled by plan_batch_partitions)
+  } else if (b->mapping == RTEAAL_MAP_RESIDENT) {
     uint32_t blk = opts && opts->block_threads ? opts->block_threads : 0;
     if (blk && (blk % 64 || blk > 1024))
       return fail(ctx, RTEAAL_E_INVALID_ARG, "block_threads must be a multiple of 64 up to 1024");
@@ -1796,24 +2086,41 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
   }
   const uint64_t n_seed = b->mapping == RTEAAL_MAP_SWEEP ? (uint64_t)b->L.n_tiles_alloc * 64 : n_inst;
   b->n_slot = n_seed;
+  const bool part = b->mapping == RTEAAL_MAP_PARTITIONED;
+  const bool coop = b->persistent || part;
   if (!alloc_all(ctx, {{&b->state, sb}, {&b->seeds, n_seed * 8}, {&b->ctl, sizeof(DevCtl)},
-                       {&b->dig, n_seed * 16}, {&b->gsync, b->persistent ? sizeof(GridSync) : 0}}))
+                       {&b->dig, n_seed * 16}, {&b->gsync, coop ? sizeof(GridSync) : 0},
+                       {&b->part_mem, part ? b->part_host.size() : 0},
+                       {&b->xch, part ? 16ull * n_inst * std::max<uint32_t>(h->reg_words, 1) : 0},
+                       {&b->pacc, part ? 24ull * n_inst : 0},
+                       {&b->preg_refs, part ? std::max<size_t>(b->preg_host.size(), 1) * sizeof(SlotRef) : 0}}))
     return fail(ctx, RTEAAL_E_NO_MEMORY, "device allocation of %llu bytes for the batch failed",
                 (unsigned long long)sb);
-  std::vector<uint64_t> sd(n_seed, 0);
-  std::copy(seeds, seeds + n_inst, sd.begin());
-  DevCtl c0{};
+  if (part) finish_part_table(*b, plan);
+  // The initial contents are copied from host buffers the batch keeps, so
+  // the call only enqueues (a serving loop admits jobs while a step runs).
+  b->seeds_host.assign(n_seed, 0);
+  std::copy(seeds, seeds + n_inst, b->seeds_host.begin());
+  b->ctl_host = DevCtl{};
   hipError_t e = hipMemsetAsync(b->state.p, 0, sb ? sb : 256, ctx->stream);
   if (e == hipSuccess) e = hipMemsetAsync(b->dig.p, 0, n_seed * 16, ctx->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(b->seeds.p, sd.data(), n_seed * 8, hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(b->ctl.p, &c0, sizeof c0, hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->seeds.p, b->seeds_host.data(), n_seed * 8, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->ctl.p, &b->ctl_host, sizeof(DevCtl), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && part)
+    e = hipMemcpyAsync(b->part_mem.p, b->part_host.data(), b->part_host.size(), hipMemcpyHostToDevice,
+                       ctx->stream);
+  if (e == hipSuccess && part && !b->preg_host.empty())
+    e = hipMemcpyAsync(b->preg_refs.p, b->preg_host.data(), b->preg_host.size() * sizeof(SlotRef),
+                       hipMemcpyHostToDevice, ctx->stream);
   if (e != hipSuccess) {
     dev_free(ctx, b->state);
     dev_free(ctx, b->seeds);
     dev_free(ctx, b->ctl);
     dev_free(ctx, b->dig);
     dev_free(ctx, b->gsync);
+    free_parts(ctx, *b);
     ctx->poisoned = true;
     return fail(ctx, RTEAAL_E_DEVICE, "batch initialisation failed: %s", hipGetErrorString(e));
   }
@@ -1838,6 +2145,7 @@ rteaal_status rteaal_free_batch(rteaal_ctx* ctx, rteaal_batch_id id) {
   dev_free(ctx, b->ctl);
   dev_free(ctx, b->dig);
   dev_free(ctx, b->gsync);
+  free_parts(ctx, *b);
   DesignHost* h = find_design(ctx, b->design);
   if (h) h->n_batches--;
   ctx->batches.erase(id);
@@ -1868,6 +2176,11 @@ rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id id, rteaal_b
   } else if (b->mapping == RTEAAL_MAP_LAYERED) {
     o.block_threads = b->block;
     o.persistent = b->persistent ? 1u : 0u;
+  } else if (b->mapping == RTEAAL_MAP_PARTITIONED) {
+    o.unroll = 0;
+    o.block_threads = b->block;
+    o.lds_state = b->lds ? 0u : 1u;
+    o.partitions = b->parts;
   } else if (b->mapping == RTEAAL_MAP_SWEEP) {
     o.ops_per_wave = b->opw;
     o.tiles_per_wave = b->tg;
@@ -1997,11 +2310,16 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
   // fewer cycles drop out in order); the rest each replay their own cycle
   // graph.  Each kind runs on an auxiliary stream forked from the context
   // stream, beside the RESIDENT launches on the context stream.
-  std::vector<uint32_t> multi, single;
+  // Cooperative batches (persistent LAYERED, PARTITIONED) spin at grid
+  // barriers until all their workgroups are resident: two at once could
+  // each hold part of the device the other waits for, so they run one after
+  // another on one stream.
+  std::vector<uint32_t> multi, single, coop;
   for (uint32_t k = 0; k < n; ++k) {
     const Batch& b = *bs[k];
     if (b.mapping == RTEAAL_MAP_RESIDENT || n_cycles[k] == 0) continue;
-    if (!b.n_watch && !b.profile && b.tpp == 0 && !b.persistent) multi.push_back(k);
+    if (b.persistent || b.mapping == RTEAAL_MAP_PARTITIONED) coop.push_back(k);
+    else if (!b.n_watch && !b.profile && b.tpp == 0) multi.push_back(k);
     else single.push_back(k);
   }
   if (multi.size() == 1) {
@@ -2094,6 +2412,16 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
     if (st != RTEAAL_OK) return st;
     bs[k]->cycle += n_cycles[k];
     ++n_aux;
+  }
+  if (!coop.empty()) {
+    const uint32_t a = n_aux < 4 ? n_aux : 3u;
+    rteaal_status st = fork_aux(a);
+    if (st != RTEAAL_OK) return st;
+    for (uint32_t k : coop) {
+      st = run_alone(k, n_cycles[k], a);
+      if (st != RTEAAL_OK) return st;
+      bs[k]->cycle += n_cycles[k];
+    }
   }
 
   // RESIDENT batches: one persistent launch per kernel configuration, every
@@ -2209,6 +2537,8 @@ rteaal_status read_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first, ui
     return check_grid(ctx, *b);
   }
   const bool slots = what == RTEAAL_READ_ALL_SLOTS;
+  if (slots && b->mapping == RTEAAL_MAP_PARTITIONED)
+    return fail(ctx, RTEAAL_E_UNSUPPORTED, "all-slot read-out of a PARTITIONED batch");
   if (slots && h.compact)
     return fail(ctx, RTEAAL_E_UNSUPPORTED,
                 "all-slot read-out needs a design loaded with RTEAAL_LOAD_KEEP_ALL_SLOTS");
@@ -2229,7 +2559,9 @@ rteaal_status read_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t first, ui
       return fail(ctx, RTEAAL_E_NO_MEMORY, "read-out buffer allocation failed");
     stage = (uint64_t*)tmp.p;
   }
-  const SlotRef* refs = (const SlotRef*)(slots ? h.d_slot_refs.p : h.d_reg_refs.p);
+  const SlotRef* refs = (const SlotRef*)(slots ? h.d_slot_refs.p
+                                         : b->mapping == RTEAAL_MAP_PARTITIONED ? b->preg_refs.p
+                                                                                : h.d_reg_refs.p);
   hipError_t e = launch_pack(b->mapping == RTEAAL_MAP_SWEEP, b->L, (const char*)b->state.p, refs,
                              n_refs, wpi, first, n, stage, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(out, stage, need * 8, hipMemcpyDeviceToHost, ctx->stream);
@@ -2275,7 +2607,9 @@ rteaal_status rteaal_write_state(rteaal_ctx* ctx, rteaal_batch_id id, uint32_t f
     e = hipMemcpyAsync(tmp.p, regs, need * 8, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess)
       e = launch_unpack(b->mapping == RTEAAL_MAP_SWEEP, b->L, (char*)b->state.p,
-                        (const SlotRef*)h.d_reg_refs.p, h.n_regs, h.reg_words, first, n,
+                        (const SlotRef*)(b->mapping == RTEAAL_MAP_PARTITIONED ? b->preg_refs.p
+                                                                              : h.d_reg_refs.p),
+                        h.n_regs, h.reg_words, first, n,
                         (const uint64_t*)tmp.p, ctx->stream);
   }
   if (e == hipSuccess)
@@ -2318,6 +2652,8 @@ rteaal_status rteaal_watch(rteaal_ctx* ctx, rteaal_batch_id id, const uint32_t* 
   Batch* b = find_batch(ctx, id);
   if (!b) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown batch %u", id);
   if (n && !slots) return fail(ctx, RTEAAL_E_INVALID_ARG, "null slots");
+  if (n && b->mapping == RTEAAL_MAP_PARTITIONED)
+    return fail(ctx, RTEAAL_E_UNSUPPORTED, "PARTITIONED batches cannot be watched");
   DesignHost& h = *find_design(ctx, b->design);
   std::vector<SlotRef> refs(n);
   uint32_t words = 0;
@@ -2414,12 +2750,12 @@ std::string device_tag(int device) {
   return t;
 }
 
-constexpr int kOptFields = 10;
+constexpr int kOptFields = 11;  // (entries name their field count in the key: "o11")
 
 void opts_to(const rteaal_batch_opts& o, uint32_t* v) {
   const uint32_t a[kOptFields] = {o.mapping, o.block_threads, o.ops_per_wave, o.lds_state, o.lds_ops,
                                   o.unroll, o.tiles_per_wave, o.arity_split, o.tiles_per_pass,
-                                  o.persistent};
+                                  o.persistent, o.partitions};
   std::copy(a, a + kOptFields, v);
 }
 
@@ -2435,6 +2771,7 @@ rteaal_batch_opts opts_from(const uint32_t* v) {
   o.arity_split = v[7];
   o.tiles_per_pass = v[8];
   o.persistent = v[9];
+  o.partitions = v[10];
   return o;
 }
 
@@ -2496,7 +2833,7 @@ std::string single_key(rteaal_ctx* ctx, const DesignHost& h, uint32_t n_inst, ui
   char buf[128];
   std::snprintf(buf, sizeof buf, "|%016llx|%u|%llu", (unsigned long long)h.fingerprint, n_inst,
                 (unsigned long long)cycles);
-  return "single|" + device_tag(ctx->device) + buf;
+  return "single|o11|" + device_tag(ctx->device) + buf;
 }
 
 }  // namespace
@@ -2543,6 +2880,16 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
       cand.push_back(o);
     }
   }
+  // PARTITIONED: the default count and a few others that fit the device
+  // (candidates that do not fit are skipped).
+  if (n_inst <= 4 && h->n_regs >= 2)
+    for (uint32_t pc : {0u, 64u, 128u, 512u / n_inst, 1024u / n_inst}) {
+      if (pc > h->n_regs) continue;
+      rteaal_batch_opts o{};
+      o.mapping = RTEAAL_MAP_PARTITIONED;
+      o.partitions = pc;
+      cand.push_back(o);
+    }
   const uint32_t n_tiles = (n_inst + 63) / 64;
   for (uint32_t tg : {1u, 2u, 4u, 8u, 16u}) {
     if (tg > 1 && tg > n_tiles) continue;
@@ -2565,7 +2912,11 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
   for (const auto& o : cand) {
     rteaal_batch_id b = 0;
     st = rteaal_create_batch(ctx, id, n_inst, seeds.data(), &o, &b);
-    if (st == RTEAAL_E_NO_MEMORY) { st = RTEAAL_OK; continue; }
+    if (st == RTEAAL_E_NO_MEMORY ||
+        (st == RTEAAL_E_INVALID_ARG && o.mapping == RTEAAL_MAP_PARTITIONED)) {
+      st = RTEAAL_OK;  // does not fit the device
+      continue;
+    }
     if (st != RTEAAL_OK) break;
     st = rteaal_step(ctx, b, 1, nullptr);  // warm-up (and graph capture)
     hipError_t e = hipSuccess;
@@ -2584,8 +2935,8 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
     const double r = (double)n_inst * (double)cyc / (std::max(ms, 1e-3f) * 1e-3);
     if (log)
       std::fprintf(stderr, "rteaal_autotune: mapping %u block %u ops/wave %u unroll %u tiles %u "
-                   "persistent %u -> %.4g\n", o.mapping, o.block_threads, o.ops_per_wave, o.unroll,
-                   o.tiles_per_wave, o.persistent, r);
+                   "persistent %u partitions %u -> %.4g\n", o.mapping, o.block_threads,
+                   o.ops_per_wave, o.unroll, o.tiles_per_wave, o.persistent, o.partitions, r);
     if (r > best_rate) {
       best_rate = r;
       best_o = o;
@@ -2621,7 +2972,7 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
   // Trial length: about 4e9 op-evaluations per policy, 2..32 cycles.
   const uint64_t cyc = trial_cycles ? trial_cycles
                                     : (uint64_t)std::max(2.0, std::min(32.0, 4e9 / std::max<double>((double)total, 1.0)));
-  std::string key = "joint|" + device_tag(ctx->device);
+  std::string key = "joint|o11|" + device_tag(ctx->device);
   {
     uint64_t fp = 1469598103934665603ull;
     for (uint32_t k = 0; k < n; ++k) {

@@ -220,6 +220,36 @@ struct GridSync {
   uint32_t count, opened, error, pad;
 };
 
+// PARTITIONED (the RepCut cascade of App. C): the registers are split into
+// P partitions; partition p evaluates, on a private copy of the instance's
+// state, the operations of the fan-in cones of the registers it owns (its
+// sub-program: the design's layers restricted to those operations), commits
+// its own registers, and once per cycle the partitions exchange register
+// values through device memory (Cascade 2's register update map RUM).
+struct PartJob {
+  const DevOp* ops;        // the partition's operations, layer after layer
+  const DevLayer* layers;  // [n_layers]: ranges into ops (begin, end; the rest 0)
+  const uint32_t* own;     // registers (indices into the design's) it commits
+  const uint32_t* need;    // registers of other partitions its cone reads
+  uint32_t n_layers, n_own, n_need, pad;
+};
+
+struct PartRun {
+  const PartJob* parts;        // [n_parts]
+  const uint64_t* const_limbs;
+  const SlotRef* regs;         // the design's register refs (fields within one copy)
+  char* state;                 // copy of (instance i, partition p) at (i n_parts + p) pitch
+  const uint64_t* seeds;
+  const DevCtl* ctl;
+  uint64_t* xch;               // [2][n_inst][reg_words]: published register values
+  unsigned long long* acc;     // [3][n_inst]: digest sums, by cycle mod 3 (zero at launch)
+  uint64_t* digest;            // [n_inst]
+  GridSync* gs;
+  uint64_t pitch;              // bytes of one copy
+  uint64_t n_cycles;
+  uint32_t n_parts, n_inst, reg_words, words_per_inst, spin_limit, pad;
+};
+
 // ---- kernel launchers (kernels.hip) ---------------------------------------
 hipError_t launch_resident(const ResJob& J, uint32_t n_inst, uint32_t inst_base, uint32_t block,
                            bool lds_state, bool lds_ops, uint32_t unroll, hipStream_t s);
@@ -253,6 +283,16 @@ hipError_t launch_advance(DevCtl* ctl, uint64_t n, hipStream_t s);
 hipError_t launch_layer_persistent(const ResJob& J, uint32_t n_inst, uint32_t unroll,
                                    GridSync* gs, uint64_t* acc, uint32_t spin_limit,
                                    uint32_t blocks, hipStream_t s);
+// PARTITIONED: R.n_cycles cycles of R.n_inst instances in one cooperative
+// launch of n_inst x n_parts workgroups of `block` threads (R.acc and R.gs
+// are cleared by this call first).  lds_state: each copy in LDS.  Fails
+// (hipErrorCooperativeLaunchTooLarge or similar) when the workgroups cannot
+// all be resident at once.
+hipError_t launch_partitioned(const PartRun& R, uint32_t block, bool lds_state, hipStream_t s);
+// Workgroups of `block` threads with `lds` bytes of LDS each that the device
+// holds at once (0 on error).
+uint32_t partitioned_capacity(uint32_t block, bool lds_state, size_t lds);
+
 // Launches over several batches: segs[0 .. n_seg) and wave0[0 .. n_seg] in
 // device memory, wave0 the prefix of the segments' wavefronts (n_waves =
 // wave0[n_seg]).  kind 0: SWEEP common operations (tile group tg: 1, 2, 4,

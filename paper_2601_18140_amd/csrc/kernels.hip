@@ -403,6 +403,118 @@ k_layer_persistent(ResJob J, uint32_t n_inst, GridSync* gs, unsigned long long* 
 }
 
 // ---------------------------------------------------------------------------
+// PARTITIONED: workgroup (instance, partition) runs its partition's
+// sub-program on its copy of the instance state; once per cycle the
+// partitions publish their registers, meet at a grid barrier and load the
+// registers of other partitions their cones read.
+// ---------------------------------------------------------------------------
+
+// Register value (ref r) of a RESIDENT state block s to x[0 .. limbs).
+__device__ __forceinline__ void reg_publish(const char* s, const SlotRef& r, uint64_t* x) {
+  if (r.cls <= CD) {
+    x[0] = res_fetch(s, r.cls, r.pos);
+    return;
+  }
+  const uint64_t* q = (const uint64_t*)(s + (uint64_t)(r.pos >> 6) * 8u);
+  const uint32_t nl = (r.width + 63u) >> 6;
+  for (uint32_t l = 0; l < nl; ++l) x[l] = q[l];
+}
+
+// x[0 .. limbs) into register r of state block s; a 1-bit register is one
+// bit of a word that other threads may update at the same time.
+__device__ __forceinline__ void reg_load(char* s, const SlotRef& r, const uint64_t* x) {
+  if (r.cls == CB) {
+    unsigned long long* w = (unsigned long long*)(s + (uint64_t)(r.pos >> 6) * 8u);
+    const unsigned long long bit = 1ull << (r.pos & 63u);
+    if (x[0] & 1ull) atomicOr(w, bit);
+    else atomicAnd(w, ~bit);
+  } else if (r.cls <= CD) {
+    res_st64(s, r.cls, r.pos, x[0]);
+  } else {
+    uint64_t* q = (uint64_t*)(s + (uint64_t)(r.pos >> 6) * 8u);
+    const uint32_t nl = (r.width + 63u) >> 6;
+    for (uint32_t l = 0; l < nl; ++l) q[l] = x[l];
+  }
+}
+
+template <bool LDS_STATE>
+__global__ void __launch_bounds__(1024) k_partitioned(PartRun R) {
+  extern __shared__ uint4 lds_dyn[];
+  const uint32_t P = R.n_parts;
+  const uint32_t inst = blockIdx.x / P, part = blockIdx.x % P;
+  const PartJob J = R.parts[part];
+  char* g = R.state + ((uint64_t)inst * P + part) * R.pitch;
+  char* s = LDS_STATE ? (char*)lds_dyn : g;
+  if (LDS_STATE)
+    for (uint64_t i = threadIdx.x; i < R.pitch / 16u; i += blockDim.x) lds_dyn[i] = ((const uint4*)g)[i];
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63u, bd = blockDim.x;
+  const uint64_t seed = R.seeds[inst];
+  const uint64_t c0 = R.ctl->cycle, wc0 = R.ctl->step_cycle0;
+  const uint64_t* words = R.ctl->words;
+  const bool lead = part == 0 && threadIdx.x == 0;
+  uint64_t dig = lead ? R.digest[inst] : 0ull;
+  uint32_t round = 0;
+  // Exchange e uses buffer e & 1: e = 0 opens the launch (registers written
+  // by the host since the last launch reach every partition), e = t + 1
+  // follows cycle t.  A partition writes buffer e + 1 only after barrier e,
+  // which every partition passes after it has read buffer e - 1.
+  auto xrow = [&](uint32_t e) {
+    return R.xch + ((uint64_t)(e & 1u) * R.n_inst + inst) * (uint64_t)R.reg_words;
+  };
+  auto publish = [&](uint64_t* x) {
+    for (uint32_t i = threadIdx.x; i < J.n_own; i += bd) {
+      const SlotRef r = R.regs[J.own[i]];
+      reg_publish(s, r, x + r.out_off);
+    }
+  };
+  auto load = [&](const uint64_t* x) {
+    for (uint32_t i = threadIdx.x; i < J.n_need; i += bd) {
+      const SlotRef r = R.regs[J.need[i]];
+      reg_load(s, r, x + r.out_off);
+    }
+    __syncthreads();
+  };
+  publish(xrow(0));
+  grid_barrier(R.gs, round, R.spin_limit);
+  load(xrow(0));
+  for (uint64_t t = 0; t < R.n_cycles; ++t) {
+    const uint64_t cycle = c0 + t;
+    const uint64_t words_row =
+        ((cycle - wc0) * (uint64_t)R.n_inst + inst) * (uint64_t)R.words_per_inst;
+    for (uint32_t li = 0; li < J.n_layers; ++li) {
+      const DevLayer ly = J.layers[li];
+      const uint32_t n = ly.end - ly.begin, n64 = (n + 63u) & ~63u;
+      for (uint32_t q0 = threadIdx.x; q0 < n64; q0 += bd)
+        resident_ops<1>(R.const_limbs, s, J.ops, ly, q0, bd, n, n64, seed, cycle, words,
+                        words_row, lane);
+      __syncthreads();
+    }
+    // Own registers out, with their digest terms.
+    uint64_t* x = xrow((uint32_t)t + 1u);
+    uint64_t h = 0;
+    for (uint32_t i = threadIdx.x; i < J.n_own; i += bd) {
+      const uint32_t j = J.own[i];
+      const SlotRef r = R.regs[j];
+      reg_publish(s, r, x + r.out_off);
+      h += res_reg_terms(s, r, j);
+    }
+    h = wave_sum64(h);
+    if (lane == 0 && h) atomicAdd(&R.acc[(t % 3u) * R.n_inst + inst], (unsigned long long)h);
+    grid_barrier(R.gs, round, R.spin_limit);
+    if (lead) {
+      dig = splitmix64(dig ^ R.acc[(t % 3u) * R.n_inst + inst]);
+      R.acc[((t + 2u) % 3u) * R.n_inst + inst] = 0ull;
+    }
+    load(x);
+  }
+  if (lead) R.digest[inst] = dig;
+  if (LDS_STATE) {
+    for (uint64_t i = threadIdx.x; i < R.pitch / 16u; i += blockDim.x) ((uint4*)g)[i] = lds_dyn[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // SWEEP: lane = instance.  A wavefront owns TG consecutive tiles of one tile
 // group of the layout (TG divides the group).  A value's blocks for the
 // tiles of a group are contiguous (StateLayout), so each operand of an
@@ -1360,12 +1472,37 @@ __device__ __forceinline__ void digest_wave(bool sweep, const StateLayout& L,
   const uint32_t j1 = min(j0 + per, n_regs);
   uint64_t h = 0;
   if (sweep) {
+    // Limb 0 of K registers in flight at once, each one branch-free 8-byte
+    // load of the word holding this lane's element (as the SWEEP kernels
+    // gather), cut to the class; further limbs of wide registers after.
+    constexpr int K = 8;
     const uint32_t inst = unit * 64u + lane;  // below the allocated tiles' instances
-    for (uint32_t j = j0; j < j1; ++j) {
-      const SlotRef r = regs[j];
-      const uint32_t nl = (r.width + 63u) >> 6;
-      for (uint32_t l = 0; l < nl; ++l)
-        h += splitmix64(splitmix64(((uint64_t)j << 2) | l) ^ load_limb(true, L, state, r, l, inst));
+    const SweepView v((char*)state, L, unit, lane);
+    for (uint32_t j = j0; j < j1; j += K) {
+      uint64_t raw[K], m[K];
+      uint32_t sh[K], f[K], kl[K];
+#pragma unroll
+      for (int u = 0; u < K; ++u) {
+        const SlotRef r = regs[min(j + (uint32_t)u, j1 - 1u)];
+        const uint32_t w3 = cls_w3(r.cls);
+        f[u] = r.pos;
+        kl[u] = cls_limbs(r.cls);
+        sh[u] = v.sh64(w3);
+        m[u] = cls_mask64(r.cls);
+        raw[u] = *(const uint64_t*)(v.at(r.pos, w3, 0u) + v.off64(w3));
+      }
+#pragma unroll
+      for (int u = 0; u < K; ++u) {
+        if (j + (uint32_t)u < j1) {
+          const uint64_t jj = (uint64_t)(j + (uint32_t)u) << 2;
+          h += splitmix64(splitmix64(jj) ^ ((raw[u] >> sh[u]) & m[u]));
+          for (uint32_t l = 1; l < kl[u]; ++l) {
+            const uint64_t x =
+                *(const uint64_t*)(v.at(f[u], 0u, 0u) + lane * 8u + (uint64_t)l * v.row_bytes);
+            h += splitmix64(splitmix64(jj | l) ^ x);
+          }
+        }
+      }
     }
     if (inst < n_inst) atomicAdd(&acc[inst], (unsigned long long)h);
   } else {
@@ -1640,9 +1777,10 @@ hipError_t launch_capture(bool sweep, const StateLayout& L, const char* state, c
 }
 
 void digest_shape(bool sweep, uint32_t n_regs, uint32_t n_inst, uint32_t* n_units, uint32_t* per) {
-  // About 4,096 wavefronts: enough to fill the device, few atomics.
+  // About 16,384 wavefronts (64 per compute unit) to keep many loads in
+  // flight, with few atomics.
   *n_units = sweep ? (n_inst + 63u) / 64u : n_inst;
-  const uint64_t want = std::max<uint64_t>(1, (4096u + *n_units - 1) / *n_units);
+  const uint64_t want = std::max<uint64_t>(1, (16384u + *n_units - 1) / *n_units);
   uint64_t p = ((uint64_t)std::max<uint32_t>(n_regs, 1u) + want - 1) / want;
   if (!sweep) p = (p + 63u) & ~uint64_t(63);
   *per = (uint32_t)p;
@@ -1694,6 +1832,39 @@ hipError_t launch_layer_persistent(const ResJob& J, uint32_t n_inst, uint32_t un
   uint32_t ni = n_inst, sl = spin_limit;
   void* args[] = {&j, &ni, &g, &a, &sl};
   return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), args, 0, s);
+}
+
+uint32_t partitioned_capacity(uint32_t block, bool lds_state, size_t lds) {
+  const void* fn = lds_state ? (const void*)k_partitioned<true> : (const void*)k_partitioned<false>;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (lds > 64u * 1024u &&
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)resident_max_lds()) !=
+          hipSuccess)
+    return 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)block, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return (uint32_t)(cus * per_cu);
+}
+
+hipError_t launch_partitioned(const PartRun& R, uint32_t block, bool lds_state, hipStream_t s) {
+  if (R.n_cycles == 0 || R.n_inst == 0 || R.n_parts == 0) return hipSuccess;
+  const size_t lds = lds_state ? (size_t)R.pitch : 0;
+  const uint64_t blocks = (uint64_t)R.n_inst * R.n_parts;
+  if (blocks > partitioned_capacity(block, lds_state, lds)) return hipErrorCooperativeLaunchTooLarge;
+  hipLaunchKernelGGL(k_fill_u64, dim3((3u * R.n_inst + 255u) / 256u), dim3(256), 0, s,
+                     (uint64_t*)R.acc, 0ull, (uint64_t)3 * R.n_inst);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (uint64_t*)R.gs, 0ull,
+                     (uint64_t)(sizeof(GridSync) / 8));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  PartRun r = R;
+  void* args[] = {&r};
+  const void* fn = lds_state ? (const void*)k_partitioned<true> : (const void*)k_partitioned<false>;
+  return hipLaunchCooperativeKernel(fn, dim3((uint32_t)blocks), dim3(block), args, lds, s);
 }
 
 hipError_t launch_multi(uint32_t kind, uint32_t tg, const MultiSeg* segs, const uint32_t* wave0,

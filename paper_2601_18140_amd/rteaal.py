@@ -18,11 +18,13 @@ LIB_PATH = os.path.join(HERE, "librteaal.so")
 
 __all__ = [
     "RTEAAL_OK", "RTEAAL_MAP_AUTO", "RTEAAL_MAP_RESIDENT", "RTEAAL_MAP_SWEEP", "RTEAAL_MAP_LAYERED",
+    "RTEAAL_MAP_PARTITIONED",
     "RTEAAL_READ_REGS", "RTEAAL_READ_DIGEST", "RTEAAL_READ_ALL_SLOTS", "RteaalError", "Context", "library",
     "exported_symbols", "rteaal_create", "rteaal_destroy", "rteaal_last_error",
     "rteaal_validate_design", "rteaal_load_design", "rteaal_unload_design", "rteaal_design_format",
     "RTEAAL_LOAD_KEEP_ALL_SLOTS",
-    "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch", "rteaal_batch_info",
+    "rteaal_batch_footprint", "rteaal_batch_resources", "rteaal_create_batch", "rteaal_free_batch",
+    "rteaal_batch_info",
     "rteaal_batch_options",
     "rteaal_step", "rteaal_step_many", "rteaal_sync", "rteaal_read_state", "rteaal_write_state",
     "rteaal_write_digest", "rteaal_read_digest", "rteaal_read_state_noalloc",
@@ -36,6 +38,7 @@ RTEAAL_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "BAD_DESIGN", 3: "FORMAT", 4: "NO_MEMORY",
                 5: "DEVICE", 6: "BUSY", 7: "UNSUPPORTED"}
 RTEAAL_MAP_AUTO, RTEAAL_MAP_RESIDENT, RTEAAL_MAP_SWEEP, RTEAAL_MAP_LAYERED = 0, 1, 2, 3
+RTEAAL_MAP_PARTITIONED = 4
 RTEAAL_READ_REGS, RTEAAL_READ_DIGEST, RTEAAL_READ_ALL_SLOTS = 1, 2, 4
 RTEAAL_MUXC, RTEAAL_MUXC_MAX_PAIRS = 22, 32
 RTEAAL_NOALLOC_MAX_WORDS = 1 << 20
@@ -84,7 +87,8 @@ class rteaal_batch_opts(C.Structure):
                 ("ops_per_wave", C.c_uint32), ("lds_state", C.c_uint32),
                 ("lds_ops", C.c_uint32), ("unroll", C.c_uint32),
                 ("tiles_per_wave", C.c_uint32), ("arity_split", C.c_uint32),
-                ("tiles_per_pass", C.c_uint32), ("persistent", C.c_uint32)]
+                ("tiles_per_pass", C.c_uint32), ("persistent", C.c_uint32),
+                ("partitions", C.c_uint32)]
 
 
 class rteaal_stimulus(C.Structure):
@@ -125,6 +129,8 @@ def library():
         "rteaal_unload_design": ([vp, u32], st),
         "rteaal_design_format": ([vp, u32, u32, C.POINTER(rteaal_layer_format)], st),
         "rteaal_batch_footprint": ([vp, u32, u32, C.POINTER(rteaal_batch_opts), C.POINTER(u64)], st),
+        "rteaal_batch_resources": ([vp, u32, u32, C.POINTER(rteaal_batch_opts), C.POINTER(u64),
+                                    C.POINTER(u64)], st),
         "rteaal_create_batch": ([vp, u32, u32, vp, C.POINTER(rteaal_batch_opts), C.POINTER(u32)], st),
         "rteaal_free_batch": ([vp, u32], st),
         "rteaal_batch_info": ([vp, u32, C.POINTER(u32), C.POINTER(u64)], st),
@@ -157,7 +163,8 @@ def exported_symbols():
     return ["rteaal_create", "rteaal_destroy", "rteaal_last_error", "rteaal_validate_design",
             "rteaal_load_design", "rteaal_load_design_ex", "rteaal_unload_design",
             "rteaal_design_format",
-            "rteaal_batch_footprint", "rteaal_create_batch", "rteaal_free_batch",
+            "rteaal_batch_footprint", "rteaal_batch_resources", "rteaal_create_batch",
+            "rteaal_free_batch",
             "rteaal_batch_info", "rteaal_batch_options", "rteaal_step", "rteaal_step_many", "rteaal_sync",
             "rteaal_read_state", "rteaal_read_state_noalloc", "rteaal_write_state",
             "rteaal_write_digest",
@@ -441,10 +448,10 @@ def rteaal_design_format(ctx, design_id, layer):
 
 
 def _opts(mapping, block_threads=0, ops_per_wave=0, lds_state=0, lds_ops=0, unroll=0,
-          tiles_per_wave=0, arity_split=0, tiles_per_pass=0, persistent=0):
+          tiles_per_wave=0, arity_split=0, tiles_per_pass=0, persistent=0, partitions=0):
     return rteaal_batch_opts(int(mapping), int(block_threads), int(ops_per_wave), int(lds_state),
                              int(lds_ops), int(unroll), int(tiles_per_wave), int(arity_split),
-                             int(tiles_per_pass), int(persistent))
+                             int(tiles_per_pass), int(persistent), int(partitions))
 
 
 def rteaal_batch_footprint(ctx, design_id, n_instances, mapping=RTEAAL_MAP_AUTO, **opts):
@@ -455,9 +462,18 @@ def rteaal_batch_footprint(ctx, design_id, n_instances, mapping=RTEAAL_MAP_AUTO,
     return out.value
 
 
+def rteaal_batch_resources(ctx, design_id, n_instances, mapping=RTEAAL_MAP_AUTO, **opts):
+    """(device bytes, LDS bytes held for a whole step) of a batch."""
+    o = _opts(mapping, **opts)
+    hbm, lds = C.c_uint64(), C.c_uint64()
+    _check(ctx.handle, library().rteaal_batch_resources(ctx.handle, int(design_id), int(n_instances),
+                                                        C.byref(o), C.byref(hbm), C.byref(lds)))
+    return hbm.value, lds.value
+
+
 def rteaal_create_batch(ctx, design_id, seeds, mapping=RTEAAL_MAP_AUTO, **opts):
     """opts: block_threads, ops_per_wave, lds_state, lds_ops, unroll, tiles_per_wave,
-    arity_split, tiles_per_pass, persistent (see rteaal_batch_opts)."""
+    arity_split, tiles_per_pass, persistent, partitions (see rteaal_batch_opts)."""
     seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
     o = _opts(mapping, **opts)
     out = C.c_uint32()
@@ -592,7 +608,8 @@ def opts_dict(o):
     return {"mapping": o.mapping, "block_threads": o.block_threads, "ops_per_wave": o.ops_per_wave,
             "lds_state": o.lds_state, "lds_ops": o.lds_ops, "unroll": o.unroll,
             "tiles_per_wave": o.tiles_per_wave, "arity_split": o.arity_split,
-            "tiles_per_pass": o.tiles_per_pass, "persistent": o.persistent}
+            "tiles_per_pass": o.tiles_per_pass, "persistent": o.persistent,
+            "partitions": o.partitions}
 
 
 def rteaal_autotune(ctx, design_id, n_instances, trial_cycles=0):

@@ -1,13 +1,17 @@
 """Continuous-batching request loop over the C interface.
 
 Simulation jobs (design, instance count, cycle count) arrive over time.  A
-job is admitted when its device-memory footprint (its design, if not yet
-loaded, plus its batch) fits the free budget; admitted jobs stay resident
-on the device and advance together, a chunk of cycles per tick, through one
-rteaal_step_many call per tick, so work of different designs overlaps on the
-GPU.  A finished job's registers are read back, its batch is freed and the
-freed memory admits waiting jobs at the next tick.  Latency is arrival ->
-results readable.
+job is admitted when its device footprint fits what is free: its batch's
+device memory (plus its design's records if not yet loaded) within the
+memory budget, and the LDS its kernels hold for a whole step (RESIDENT
+batches whose state lives in LDS) within the device's LDS.  Admitted jobs
+stay resident on the device and advance together, a chunk of cycles per
+tick, through one rteaal_step_many call per tick, so work of different
+designs overlaps on the GPU.  A tick enqueues its step first and admits
+waiting jobs while the step runs (batch creation only enqueues its
+initialisation); it then waits for the step's event, reads back the jobs
+that finished, frees their batches, and the freed memory admits waiting
+jobs during the next tick's step.  Latency is arrival -> results readable.
 """
 from __future__ import annotations
 
@@ -32,6 +36,7 @@ class Job:
     done_cycles: int = 0
     batch: int | None = None
     footprint: int = 0
+    lds: int = 0
     regs: np.ndarray | None = None   # packed register limbs [n_inst][words] once finished
 
     @property
@@ -43,10 +48,12 @@ class Server:
     """pool: list of rtlgen.Design; budget_bytes: device memory the loop may use."""
 
     def __init__(self, ctx, pool, budget_bytes, tick_seconds=0.05, chunk_cycles=None,
-                 max_chunk=4096, log=None):
+                 max_chunk=4096, log=None, lds_budget_bytes=256 * 160 * 1024, preload=True):
         self.ctx = ctx
         self.pool = pool
         self.budget = int(budget_bytes)
+        self.lds_budget = int(lds_budget_bytes)   # MI355X: 256 compute units x 160 KB
+        self.used_lds = 0
         self.tick_seconds = tick_seconds
         self.fixed_chunk = chunk_cycles
         self.max_chunk = max_chunk
@@ -60,48 +67,60 @@ class Server:
         self.rate = {}                         # (design, n_inst) -> observed cycles/s per batch
         self.instance_cycles = 0
         self.log = log                         # optional callable(str) for admit/retire events
+        self.gpu_busy_s = 0.0                  # time the steps kept the device busy
+        if preload:                            # designs load before any job arrives
+            for k in range(len(pool)):
+                self._load(k)
 
     # ---- admission ---------------------------------------------------------
     def _design_bytes(self, k):
         d = self.pool[k]
         return 32 * (d.n_ops + d.n_regs + d.n_inputs + d.n_consts + 16) + 16 * (d.n_layers + 8)
 
+    def _load(self, k):
+        did = R.rteaal_load_design(self.ctx, self.pool[k])
+        self.loaded[k] = did
+        self.design_bytes[k] = self._design_bytes(k)
+        self.used += self.design_bytes[k]
+        return did
+
     def _footprint(self, job):
-        extra = 0 if job.design in self.loaded else self._design_bytes(job.design)
+        """(device bytes, LDS bytes held for a whole step) of the job's batch."""
         did = self.loaded.get(job.design)
         if did is None:
-            did = R.rteaal_load_design(self.ctx, self.pool[job.design])
-            self.loaded[job.design] = did
-            self.design_bytes[job.design] = self._design_bytes(job.design)
-            # the records were uploaded to learn the footprint; count them as used now
-            self.used += self.design_bytes[job.design]
-            extra = 0
-        return R.rteaal_batch_footprint(self.ctx, did, job.n_inst) + extra
+            did = self._load(job.design)
+        return R.rteaal_batch_resources(self.ctx, did, job.n_inst)
 
     def submit(self, job, now=None):
         job.arrival = time.perf_counter() if now is None else now
         self.queue.append(job)
 
-    def _admit(self, now):
+    def _admit(self, now, idle):
+        """Admits waiting jobs in arrival order while they fit; idle: no job
+        is running or being stepped (an LDS demand above the device's is then
+        admitted alone, its workgroups taking turns on the device)."""
         admitted = []
         while self.queue:
             job = self.queue[0]
-            fp = self._footprint(job)
+            fp, lds = self._footprint(job)
+            alone = idle and not admitted
             if self.used + fp > self.budget:
-                if not self.running and not admitted:
+                if alone:
                     raise RuntimeError(f"job {job.job_id} needs {fp} bytes, budget {self.budget}")
                 break
+            if self.used_lds + lds > self.lds_budget and not alone:
+                break
             self.queue.popleft()
-            job.footprint = fp
+            job.footprint, job.lds = fp, lds
             job.batch = R.rteaal_create_batch(self.ctx, self.loaded[job.design], job.seeds)
             job.admitted = now
             self.used += fp
+            self.used_lds += lds
             self.users[job.design] += 1
-            self.running.append(job)
             admitted.append(job)
             if self.log:
                 self.log(f"admit job {job.job_id}: design {job.design}, {job.n_inst} instances, "
-                         f"{job.n_cycles} cycles, {fp} bytes, {len(self.running)} running")
+                         f"{job.n_cycles} cycles, {fp} bytes, {lds} LDS bytes")
         return admitted
 
     # ---- one tick ----------------------------------------------------------
@@ -113,16 +132,33 @@ class Server:
         c = int(self.tick_seconds * r) if r else 16
         return max(1, min(left, c, self.max_chunk))
 
+    def _wait(self):
+        """Waits for the work enqueued so far: by polling an event on the
+        context's stream when it is a torch stream, else rteaal_sync."""
+        stream = getattr(self.ctx, "stream", None)
+        if stream is not None and hasattr(stream, "cuda_stream"):
+            import torch
+            ev = torch.cuda.Event()
+            ev.record(stream)
+            while not ev.query():
+                time.sleep(0.0002)
+        else:
+            R.rteaal_sync(self.ctx)
+
     def tick(self):
-        now = time.perf_counter()
-        self._admit(now)
         if not self.running:
-            return 0
+            self.running += self._admit(time.perf_counter(), idle=True)
+            if not self.running:
+                return 0
         chunks = [self._chunk(j) for j in self.running]
         t0 = time.perf_counter()
         R.rteaal_step_many(self.ctx, [j.batch for j in self.running], chunks)
-        R.rteaal_sync(self.ctx)
+        # Admission while the step runs: the new batches' initialisation is
+        # enqueued behind the step, and they join the next tick.
+        new = self._admit(time.perf_counter(), idle=False)
+        self._wait()
         dt = max(time.perf_counter() - t0, 1e-6)
+        self.gpu_busy_s += dt
         done = []
         for j, c in zip(self.running, chunks):
             j.done_cycles += c
@@ -137,12 +173,14 @@ class Server:
             j.batch = None
             j.finished = time.perf_counter()
             self.used -= j.footprint
+            self.used_lds -= j.lds
             self.users[j.design] -= 1
             self.running.remove(j)
             self.finished.append(j)
             if self.log:
                 self.log(f"done job {j.job_id}: latency {j.finished - j.arrival:.2f} s, "
                          f"{len(self.finished)} finished, {len(self.queue)} queued")
+        self.running += new
         return len(done)
 
     def drain(self):
@@ -196,6 +234,8 @@ class Server:
             "latency_p99_s": float(np.percentile(lat, 99)) if lat.size else None,
             "latency_max_s": float(lat.max()) if lat.size else None,
             "peak_budget_bytes": self.budget,
+            "lds_budget_bytes": self.lds_budget,
+            "waited_for_admission": int(sum(1 for j in self.finished if j.admitted > j.arrival + 0.5)),
         }
 
 

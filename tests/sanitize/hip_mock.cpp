@@ -283,6 +283,23 @@ hipError_t launch_layer_persistent(const ResJob& J, uint32_t, uint32_t, GridSync
   std::memset(gs, 0, sizeof *gs);  // the real launch clears the barrier state first
   return hipSuccess;
 }
+uint32_t partitioned_capacity(uint32_t, bool, size_t) { return 256u * 8u; }
+hipError_t launch_partitioned(const PartRun& R, uint32_t, bool, hipStream_t s) {
+  launched(s, {R.parts, R.const_limbs, R.regs, R.state, R.seeds, R.ctl, R.xch, R.acc, R.digest,
+               R.gs});
+  copy_check(R.acc, (size_t)R.n_inst * 3 * 8);
+  copy_check(R.state, (size_t)R.n_inst * R.n_parts * R.pitch);
+  copy_check(R.xch, (size_t)R.n_inst * 2 * R.reg_words * 8);
+  for (uint32_t p = 0; p < R.n_parts; ++p) {  // the job table's pointers must be live too
+    const PartJob& J = R.parts[p];
+    launched(s, {J.ops, J.layers, J.own, J.need});
+    copy_check(J.layers, (size_t)J.n_layers * sizeof(DevLayer));
+    if (J.n_own) copy_check(J.own, (size_t)J.n_own * 4);
+    if (J.n_need) copy_check(J.need, (size_t)J.n_need * 4);
+  }
+  std::memset(R.gs, 0, sizeof *R.gs);
+  return hipSuccess;
+}
 hipError_t launch_advance(DevCtl* ctl, uint64_t, hipStream_t s) {
   launched(s, {ctl});
   return hipSuccess;
@@ -322,7 +339,7 @@ hipError_t launch_digest(bool, const StateLayout&, const char* state, const Slot
 }
 void digest_shape(bool sweep, uint32_t n_regs, uint32_t n_inst, uint32_t* n_units, uint32_t* per) {
   *n_units = sweep ? (n_inst + 63u) / 64u : n_inst;
-  const uint64_t want = std::max<uint64_t>(1, (4096u + *n_units - 1) / *n_units);
+  const uint64_t want = std::max<uint64_t>(1, (16384u + *n_units - 1) / *n_units);
   uint64_t q = ((uint64_t)std::max<uint32_t>(n_regs, 1u) + want - 1) / want;
   if (!sweep) q = (q + 63u) & ~uint64_t(63);
   *per = (uint32_t)q;

@@ -3,7 +3,8 @@
 // infrastructure only): batches of every mapping, multi-batch steps with
 // uneven cycle counts, batches freed while their set's captured cycle is
 // cached, more batch sets than the cache holds, watched and timed batches,
-// stimulus words, read-out and restore, and both autotuners.  No result is
+// stimulus words, read-out and restore, PARTITIONED batches, and both
+// autotuners.  No result is
 // computed (kernels do nothing); every call must succeed and the sanitizers
 // and the mock's pointer checks must stay silent.
 //
@@ -204,7 +205,44 @@ int main(int argc, char** argv) {
     ok(rteaal_sync(g_ctx), "sync");
     for (rteaal_batch_id b : bs) ok(rteaal_free_batch(g_ctx, b), "free_batch");
   }
-  // 3. Autotuners.
+  // 3. PARTITIONED batches: alone, beside others in one call, read-out and
+  //    restore through the owners' copies; watching is refused.
+  {
+    rteaal_batch_opts po{};
+    po.mapping = RTEAAL_MAP_PARTITIONED;
+    std::vector<rteaal_batch_id> bs;
+    for (uint32_t k = 0; k < 3; ++k) {
+      po.partitions = ds[k % D].reg_slot.size() >= 2 ? 2u + k : 1u;
+      bs.push_back(batch(ids[k % D], 1 + k, po));
+    }
+    bs.push_back(batch(ids[0], 70, sweep(1)));
+    for (size_t k = 0; k < 3; ++k) ok(rteaal_step(g_ctx, bs[k], 1500, nullptr), "step");
+    many(bs, {3, 0, 2000, 4});
+    for (size_t k = 0; k < 3; ++k) {
+      rteaal_batch_opts got{};
+      ok(rteaal_batch_options(g_ctx, bs[k], &got), "batch_options");
+      if (got.mapping != RTEAAL_MAP_PARTITIONED || got.partitions == 0) {
+        std::fprintf(stderr, "batch_options: mapping %u partitions %u\n", got.mapping, got.partitions);
+        return 3;
+      }
+      std::vector<uint64_t> out(1 << 16);
+      size_t wr = 0;
+      ok(rteaal_read_state(g_ctx, bs[k], 0, 1, RTEAAL_READ_REGS, out.data(), out.size(), &wr),
+         "read_state");
+      ok(rteaal_write_state(g_ctx, bs[k], 0, 1, out.data(), 9), "write_state");
+      ok(rteaal_read_state(g_ctx, bs[k], 0, 1, RTEAAL_READ_DIGEST, out.data(), out.size(), &wr),
+         "read digest");
+      if (rteaal_watch(g_ctx, bs[k], ds[k % D].reg_slot.data(), 1, 10) != RTEAAL_E_UNSUPPORTED ||
+          rteaal_read_state(g_ctx, bs[k], 0, 1, RTEAAL_READ_ALL_SLOTS, out.data(), out.size(),
+                            &wr) != RTEAAL_E_UNSUPPORTED) {
+        std::fprintf(stderr, "PARTITIONED watch / all-slot read-out not refused\n");
+        return 3;
+      }
+    }
+    ok(rteaal_sync(g_ctx), "sync");
+    for (rteaal_batch_id b : bs) ok(rteaal_free_batch(g_ctx, b), "free_batch");
+  }
+  // 4. Autotuners.
   {
     rteaal_batch_opts best{};
     double rate = 0;

@@ -3,7 +3,8 @@
 The loop drives the library only through the binding's calls, so here a
 stand-in binding advances every batch with the oracle (resuming from the
 batch's registers and cycle).  This checks, without a GPU: admission by
-footprint within the budget (jobs wait when it is full), per-tick chunks,
+device memory and by LDS within their budgets (jobs wait when either is
+full), per-tick chunks,
 retirement, that every job's registers equal one uninterrupted oracle run,
 and the latency summary.
 """
@@ -27,11 +28,18 @@ class FakeBinding:
         self.next = 1
         self.live_bytes = 0
         self.peak_bytes = 0
+        self.live_lds = 0
+        self.peak_lds = 0
         self.steps = []
 
-    # footprint model: a fixed cost per instance and cycle-independent
+    # footprint model: a fixed cost per instance and cycle-independent; LDS
+    # held by the batches of design 2 only
     def rteaal_batch_footprint(self, ctx, did, n_inst, **_):
         return 1000 * n_inst
+
+    def rteaal_batch_resources(self, ctx, did, n_inst, **_):
+        lds = 100 * n_inst if self.designs[did] is self.pool[2] else 0
+        return self.rteaal_batch_footprint(ctx, did, n_inst), lds
 
     def rteaal_load_design(self, ctx, d, **_):
         did = self.next
@@ -50,6 +58,8 @@ class FakeBinding:
         self.batches[bid] = {"design": did, "seeds": np.asarray(seeds, np.uint64),
                              "regs": None, "cycle": 0}
         self.live_bytes += self.rteaal_batch_footprint(ctx, did, len(seeds))
+        self.live_lds += self.rteaal_batch_resources(ctx, did, len(seeds))[1]
+        self.peak_lds = max(self.peak_lds, self.live_lds)
         charged = self.live_bytes + (self.design_bytes or 0) * len(self.designs)
         self.peak_bytes = max(self.peak_bytes, charged)
         return bid
@@ -57,6 +67,7 @@ class FakeBinding:
     def rteaal_free_batch(self, ctx, bid):
         b = self.batches.pop(bid)
         self.live_bytes -= self.rteaal_batch_footprint(ctx, b["design"], len(b["seeds"]))
+        self.live_lds -= self.rteaal_batch_resources(ctx, b["design"], len(b["seeds"]))[1]
 
     def rteaal_step_many(self, ctx, bids, n_cycles):
         assert len(set(bids)) == len(bids)
@@ -94,7 +105,7 @@ def test_jobs_match_uninterrupted_oracle_runs(fake):
                         n_cycles=int(rng.integers(5, 60))) for k in range(12)]
     # Room for about 8 instances at a time: later jobs must wait.
     budget = 8000 + 3 * 10 ** 6
-    srv = serving.Server(None, pool, budget_bytes=budget, chunk_cycles=7)
+    srv = serving.Server(None, pool, budget_bytes=budget, chunk_cycles=7, preload=False)
     srv._design_bytes = lambda k: 10 ** 6
     fb.design_bytes = 10 ** 6
     stats = srv.run(jobs, np.zeros(len(jobs)))
@@ -112,6 +123,30 @@ def test_jobs_match_uninterrupted_oracle_runs(fake):
         assert j.finished >= j.admitted >= j.arrival
     assert stats["latency_p99_s"] >= stats["latency_p50_s"] > 0
     assert stats["instance_cycles"] == sum(j.n_inst * j.n_cycles for j in jobs)
+
+
+def test_lds_admission(fake):
+    """Jobs of design 2 hold LDS (100 bytes per instance here): with an LDS
+    budget of 500 bytes, at most 5 of its instances run at once, while jobs
+    of the other designs are admitted beside them."""
+    pool, fb = fake
+    jobs = [serving.Job(job_id=k, design=2 if k % 2 == 0 else 1, n_inst=3, n_cycles=9)
+            for k in range(8)]
+    srv = serving.Server(None, pool, budget_bytes=10 ** 9, chunk_cycles=4, lds_budget_bytes=500)
+    assert len(fb.designs) == 3                  # the pool is loaded before any job arrives
+    stats = srv.run(jobs, np.zeros(len(jobs)))
+    srv.close()
+    assert stats["jobs"] == 8
+    assert 0 < fb.peak_lds <= 500
+    for j in jobs:
+        d = pool[j.design]
+        ref, _, _ = oracle.run(d, j.seeds, j.n_cycles)
+        assert np.array_equal(R.unpack_limbs(j.regs, d.slot_width[d.reg_slot]), ref), j.job_id
+    # an LDS demand above the whole budget still runs, alone
+    srv = serving.Server(None, pool, budget_bytes=10 ** 9, chunk_cycles=4, lds_budget_bytes=200)
+    stats = srv.run([serving.Job(job_id=20, design=2, n_inst=4, n_cycles=5)], np.zeros(1))
+    srv.close()
+    assert stats["jobs"] == 1
 
 
 def test_admission_window_and_oversized_job(fake):

@@ -363,6 +363,27 @@ rteaal_status rteaal_batch_resources(rteaal_ctx* ctx, rteaal_design_id design,
                                      uint32_t n_instances, const rteaal_batch_opts* opts,
                                      uint64_t* hbm_bytes, uint64_t* lds_bytes);
 
+/* The partitioned form of a loaded design for `partitions` register
+ * partitions (RTEAAL_MAP_PARTITIONED; App. C, the replicated partitioning
+ * of Cascade 2), computed on the host without touching the device:
+ *   design_ops   operations of the design's encoded program (the sources,
+ *                layers and register commit),
+ *   cone_ops     operations summed over the partitions' cones (an operation
+ *                in k cones counts k times): cone_ops / design_ops is the
+ *                work the replication costs per cycle,
+ *   padded_ops   cone_ops plus the operations evaluated only because they
+ *                share a 64-destination 1-bit group with a cone operation,
+ *   max_part_ops the largest partition's operations (padded): the per-cycle
+ *                critical path in operations,
+ *   exchange     register limbs loaded per cycle, summed over partitions.
+ * Errors: RTEAAL_E_INVALID_ARG (unknown design, partitions 0 or above the
+ * register count or 1024). */
+typedef struct {
+  uint64_t design_ops, cone_ops, padded_ops, max_part_ops, exchange;
+} rteaal_partition_stats;
+rteaal_status rteaal_partition_plan_stats(rteaal_ctx* ctx, rteaal_design_id design,
+                                          uint32_t partitions, rteaal_partition_stats* out);
+
 /* n_instances (>= 1) independent instances, registers reset to zero at
  * cycle 0; seeds[k] (host, [n_instances]) keys instance k's stimulus.
  * Allocates, then only enqueues the initialisation on the context's stream
@@ -424,8 +445,15 @@ rteaal_status rteaal_step(rteaal_ctx* ctx, rteaal_batch_id batch, uint64_t n_cyc
  * stims[k] being batch k's stimulus as in rteaal_step (words
  * [n_cycles[k]][n_instances][W] of that batch).  Enqueue only, except that
  * host words are copied before the call returns (it then waits for the
- * step).  Errors: RTEAAL_E_INVALID_ARG (unknown or repeated batch, bad
- * stimulus: then nothing has been enqueued), RTEAAL_E_NO_MEMORY,
+ * step).  How the work is laid out: all RESIDENT batches advance in one
+ * persistent launch per kernel configuration; SWEEP and LAYERED batches
+ * advance together through one captured cycle per set of batches (the
+ * pieces of a layer index in one mixed launch while they are small,
+ * environment RTEAAL_MIXED_MAX_WAVES, default 4096 wavefronts, 0 = never),
+ * beside the RESIDENT launches; cooperative batches (persistent LAYERED,
+ * PARTITIONED) run last, one at a time, with nothing else of the call
+ * beside them.  Errors: RTEAAL_E_INVALID_ARG (unknown or repeated batch,
+ * bad stimulus: then nothing has been enqueued), RTEAAL_E_NO_MEMORY,
  * RTEAAL_E_DEVICE (the context is then unusable). */
 rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_id* batches,
                                const uint64_t* n_cycles, const rteaal_stimulus* stims);
@@ -543,7 +571,8 @@ rteaal_status rteaal_read_changes(rteaal_ctx* ctx, rteaal_batch_id batch, rteaal
 
 /* Autotuner: picks the mapping and launch shape for n_instances of `design`
  * on this device.  Each candidate (RESIDENT block sizes and unroll depths;
- * LAYERED block sizes and unroll depths up to 16 instances; SWEEP operations
+ * LAYERED block sizes and unroll depths, per layer and persistent, up to 16
+ * instances; PARTITIONED partition counts up to 4 instances; SWEEP operations
  * per wavefront, unroll depths and tile groups of 1-16 tiles) runs `trial_cycles`
  * cycles (0 = a size-dependent default) on a temporary batch and is timed
  * with HIP events on the context's stream; candidates whose state does not
@@ -561,7 +590,8 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id design, uint32_t
  * Overview", and its best choice varies by machine, Ablation Study 1): for
  * designs ids[0 .. n) with n_instances[k] instances each, tries launch
  * policies for the whole set (which batches run SWEEP and with which tile
- * group, which run RESIDENT or LAYERED) on temporary batches, times
+ * group and operations per wavefront, which run RESIDENT or LAYERED) on
+ * temporary batches, times
  * trial_cycles cycles (0 = a size-dependent default) of one rteaal_step_many
  * over all of them, and keeps the fastest policy: best (host [n], may be
  * NULL) receives each batch's options, *rate (may be NULL) the set's

@@ -77,6 +77,9 @@ struct MultiGraph {
 struct rteaal_ctx {
   int device = 0;
   uint32_t spin_limit = 1u << 22;  // grid barrier waits of persistent launches
+  // Captured multi-batch cycles: the pieces of one layer index run as one
+  // mixed launch while they total at most this many wavefronts (0: never).
+  uint32_t mixed_max_waves = 4096;
   uint64_t* scratch = nullptr;  // this device's staging array (rteaal_read_state_noalloc)
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -871,6 +874,7 @@ struct PartPlan {
   std::vector<uint32_t> lists;            // per partition: own, then need
   std::vector<uint32_t> op_begin, own_begin, own_n, need_begin, need_n;
   uint64_t cone_ops = 0;                  // operations in all cones (without padding)
+  uint64_t max_part_ops = 0, exchange = 0;
 };
 
 void plan_partitions(const DesignHost& h, uint32_t P, PartPlan* out) {
@@ -934,6 +938,9 @@ void plan_partitions(const DesignHost& h, uint32_t P, PartPlan* out) {
     for (uint32_t j = 0; j < h.n_regs; ++j)
       if (owner(j) != p && (need[(size_t)h.reg_slot[j] * W + pw] & pb)) pl.lists.push_back(j);
     pl.need_n.push_back((uint32_t)pl.lists.size() - pl.need_begin.back());
+    pl.max_part_ops = std::max<uint64_t>(pl.max_part_ops, pl.ops.size() - base);
+    for (uint32_t i = pl.need_begin.back(); i < pl.lists.size(); ++i)
+      pl.exchange += (h.reg_refs[pl.lists[i]].width + 63) / 64;
   }
 }
 
@@ -1244,6 +1251,31 @@ rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
     dsegs.push_back(d);
     dwave0.push_back(dwave0.back() + (uint32_t)dw);
     max_inst = std::max(max_inst, b->n_inst);
+  }
+  // Small layer indices: their launches become one mixed launch (each
+  // segment carrying its kind and tile group), which the cycle runs without
+  // forking.
+  for (auto& v : slots) {
+    if (v.size() < 2) continue;
+    uint64_t waves = 0;
+    bool ok = true;
+    for (const Launch& l : v) {
+      waves += l.wave0.back();
+      ok = ok && multi_mixable(l.kind, l.tg);
+    }
+    if (!ok || waves > ctx->mixed_max_waves) continue;
+    Launch m{4u, 0u, {}, {0u}, 0};
+    for (const Launch& l : v) {
+      const uint32_t lg = l.tg >= 4 ? 2u : l.tg >= 2 ? 1u : 0u;
+      for (size_t k = 0; k < l.segs.size(); ++k) {
+        MultiSeg x = l.segs[k];
+        x.variant = l.kind * 8u + lg;
+        m.segs.push_back(x);
+        m.wave0.push_back(m.wave0.back() + (l.wave0[k + 1] - l.wave0[k]));
+      }
+    }
+    v.clear();
+    v.push_back(std::move(m));
   }
   // One device buffer: every launch's segments and prefix, then the digest's.
   size_t bytes = 0;
@@ -1602,6 +1634,8 @@ rteaal_status rteaal_create(int device, void* stream, const rteaal_allocator* al
   }
   if (const char* sl = std::getenv("RTEAAL_GRID_SPIN_LIMIT"))
     ctx->spin_limit = (uint32_t)std::max(1L, std::min(std::atol(sl), (long)UINT32_MAX));
+  if (const char* mw = std::getenv("RTEAAL_MIXED_MAX_WAVES"))
+    ctx->mixed_max_waves = (uint32_t)std::max(0L, std::min(std::atol(mw), (long)UINT32_MAX));
   ctx->scratch = scratch_on(device);
   if (!ctx->scratch) {
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -2004,6 +2038,23 @@ rteaal_status rteaal_batch_resources(rteaal_ctx* ctx, rteaal_design_id id, uint3
   return RTEAAL_OK;
 }
 
+rteaal_status rteaal_partition_plan_stats(rteaal_ctx* ctx, rteaal_design_id id, uint32_t partitions,
+                                          rteaal_partition_stats* out) {
+  if (!ctx || !out) return fail(ctx, RTEAAL_E_INVALID_ARG, "null argument");
+  DesignHost* h = find_design(ctx, id);
+  if (!h) return fail(ctx, RTEAAL_E_INVALID_ARG, "unknown design %u", id);
+  if (partitions == 0 || partitions > 1024 || partitions > std::max<uint32_t>(h->n_regs, 1))
+    return fail(ctx, RTEAAL_E_INVALID_ARG, "%u partitions for %u registers", partitions, h->n_regs);
+  PartPlan pl;
+  plan_partitions(*h, partitions, &pl);
+  out->design_ops = h->ops.size();
+  out->cone_ops = pl.cone_ops;
+  out->padded_ops = pl.ops.size();
+  out->max_part_ops = pl.max_part_ops;
+  out->exchange = pl.exchange;
+  return RTEAAL_OK;
+}
+
 rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_inst,
                                   const uint64_t* seeds, const rteaal_batch_opts* opts,
                                   rteaal_batch_id* out) {
@@ -2310,10 +2361,8 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
   // fewer cycles drop out in order); the rest each replay their own cycle
   // graph.  Each kind runs on an auxiliary stream forked from the context
   // stream, beside the RESIDENT launches on the context stream.
-  // Cooperative batches (persistent LAYERED, PARTITIONED) spin at grid
-  // barriers until all their workgroups are resident: two at once could
-  // each hold part of the device the other waits for, so they run one after
-  // another on one stream.
+  // Cooperative batches (persistent LAYERED, PARTITIONED) run at the end,
+  // alone (below).
   std::vector<uint32_t> multi, single, coop;
   for (uint32_t k = 0; k < n; ++k) {
     const Batch& b = *bs[k];
@@ -2391,39 +2440,18 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
     ctx->stream = keep;
     return st;
   };
-  uint32_t n_aux = 0;
-  if (!replays.empty()) {
-    rteaal_status st = fork_aux(0);
-    if (st != RTEAAL_OK) return st;
-    for (auto& r : replays)
-      for (uint64_t c = 0; c < r.second; ++c) HIP_TRY(ctx, hipGraphLaunch(r.first->exec, ctx->aux[0]));
-    if (tail >= 0) {
-      st = run_alone((uint32_t)tail, tail_cycles, 0);
+  // Every auxiliary stream this call uses forks here, before the RESIDENT
+  // launches are enqueued on the context stream, so that the captured
+  // cycles and the RESIDENT launches overlap.  The RESIDENT launches are
+  // enqueued first: submitting many cycle replays can block the host until
+  // the device has run most of them.
+  {
+    const size_t n_needed = (replays.empty() ? 0 : 1) + single.size();
+    for (uint32_t a = 0; a < std::min<size_t>(n_needed, 4); ++a) {
+      const rteaal_status st = fork_aux(a);
       if (st != RTEAAL_OK) return st;
     }
-    for (uint32_t k : multi) bs[k]->cycle += n_cycles[k];
-    n_aux = 1;
   }
-  for (uint32_t k : single) {
-    const uint32_t a = n_aux < 4 ? n_aux : 1u + (n_aux - 1u) % 3u;
-    rteaal_status st = fork_aux(a);
-    if (st != RTEAAL_OK) return st;
-    st = run_alone(k, n_cycles[k], a);
-    if (st != RTEAAL_OK) return st;
-    bs[k]->cycle += n_cycles[k];
-    ++n_aux;
-  }
-  if (!coop.empty()) {
-    const uint32_t a = n_aux < 4 ? n_aux : 3u;
-    rteaal_status st = fork_aux(a);
-    if (st != RTEAAL_OK) return st;
-    for (uint32_t k : coop) {
-      st = run_alone(k, n_cycles[k], a);
-      if (st != RTEAAL_OK) return st;
-      bs[k]->cycle += n_cycles[k];
-    }
-  }
-
   // RESIDENT batches: one persistent launch per kernel configuration, every
   // workgroup running one instance of one batch for that batch's cycles.
   struct Key {
@@ -2491,6 +2519,44 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
       for (auto& a : adv) HIP_TRY(ctx, launch_advance(a.first, a.second, ctx->stream));
     }
     for (uint32_t k : g.second) bs[k]->cycle += n_cycles[k];
+  }
+  uint32_t n_aux = 0;
+  if (!replays.empty()) {
+    rteaal_status st = fork_aux(0);
+    if (st != RTEAAL_OK) return st;
+    for (auto& r : replays)
+      for (uint64_t c = 0; c < r.second; ++c) HIP_TRY(ctx, hipGraphLaunch(r.first->exec, ctx->aux[0]));
+    if (tail >= 0) {
+      st = run_alone((uint32_t)tail, tail_cycles, 0);
+      if (st != RTEAAL_OK) return st;
+    }
+    for (uint32_t k : multi) bs[k]->cycle += n_cycles[k];
+    n_aux = 1;
+  }
+  for (uint32_t k : single) {
+    const uint32_t a = n_aux < 4 ? n_aux : 1u + (n_aux - 1u) % 3u;
+    rteaal_status st = fork_aux(a);
+    if (st != RTEAAL_OK) return st;
+    st = run_alone(k, n_cycles[k], a);
+    if (st != RTEAAL_OK) return st;
+    bs[k]->cycle += n_cycles[k];
+    ++n_aux;
+  }
+  // Cooperative batches last, on the context stream once everything above
+  // (the auxiliary streams included) has finished: their workgroups spin at
+  // grid barriers until all are resident, so they must not wait for
+  // long-running workgroups of other launches to leave the device.
+  if (!coop.empty()) {
+    for (uint32_t a = 0; a < n_forked; ++a) {
+      HIP_TRY(ctx, hipEventRecord(ctx->join[a], ctx->aux[a]));
+      HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, ctx->join[a], 0));
+    }
+    n_forked = 0;
+    for (uint32_t k : coop) {
+      const rteaal_status st = enqueue_cycles(ctx, *find_design(ctx, bs[k]->design), *bs[k], n_cycles[k]);
+      if (st != RTEAAL_OK) return st;
+      bs[k]->cycle += n_cycles[k];
+    }
   }
   return RTEAAL_OK;  // `finish` joins the auxiliary streams
 }
@@ -2972,7 +3038,7 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
   // Trial length: about 4e9 op-evaluations per policy, 2..32 cycles.
   const uint64_t cyc = trial_cycles ? trial_cycles
                                     : (uint64_t)std::max(2.0, std::min(32.0, 4e9 / std::max<double>((double)total, 1.0)));
-  std::string key = "joint|o11|" + device_tag(ctx->device);
+  std::string key = "joint|o11p11|" + device_tag(ctx->device);
   {
     uint64_t fp = 1469598103934665603ull;
     for (uint32_t k = 0; k < n; ++k) {
@@ -2991,11 +3057,15 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
     // run SWEEP (records shared by a wavefront's instances, tile groups up
     // to tg_cap tiles), smaller ones RESIDENT, or LAYERED when their design
     // is large (a layer over the whole device rather than one compute unit).
+    // SWEEP batches take ops_per_wave operations per wavefront: fewer give
+    // a captured cycle's small launches more, shorter wavefronts.
     struct Policy {
-      uint32_t sweep_min, tg_cap, layered_ops;
+      uint32_t sweep_min, tg_cap, layered_ops, opw;
     };
-    const Policy pol[] = {{16, 4, UINT32_MAX}, {16, 4, 100000}, {48, 4, 100000}, {16, 2, 100000},
-                          {8, 4, 100000}, {48, 2, UINT32_MAX}};
+    const Policy pol[] = {{16, 4, UINT32_MAX, 8}, {16, 4, 100000, 8}, {48, 4, 100000, 8},
+                          {16, 2, 100000, 8},     {8, 4, 100000, 8},   {48, 2, UINT32_MAX, 8},
+                          {48, 2, UINT32_MAX, 2}, {48, 2, UINT32_MAX, 4}, {16, 2, UINT32_MAX, 2},
+                          {96, 2, UINT32_MAX, 2}, {UINT32_MAX, 1, UINT32_MAX, 8}};
     auto opts_of = [&](const Policy& p, uint32_t k) {
       rteaal_batch_opts o{};
       const uint32_t ni = n_inst[k];
@@ -3004,7 +3074,7 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
         uint32_t tg = 1;
         while (tg * 2 <= std::min(tiles, p.tg_cap)) tg *= 2;
         o.mapping = RTEAAL_MAP_SWEEP;
-        o.ops_per_wave = 8;
+        o.ops_per_wave = p.opw;
         o.unroll = 1;
         o.tiles_per_wave = tg;
       } else if (hs[k]->ops.size() >= p.layered_ops && ni <= 65535) {
@@ -3064,7 +3134,8 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
       if (st != RTEAAL_OK) break;
       if (log)
         std::fprintf(stderr, "rteaal_autotune_many: sweep from %u instances, tile groups up to %u, "
-                     "LAYERED from %u ops -> %.4g\n", p.sweep_min, p.tg_cap, p.layered_ops, r);
+                     "%u ops per wavefront, LAYERED from %u ops -> %.4g\n", p.sweep_min, p.tg_cap,
+                     p.opw, p.layered_ops, r);
       if (r > best_rate) {
         best_rate = r;
         chosen = os;

@@ -185,7 +185,8 @@ struct ResJob {
 // opw operations (split: chunks in [b0, e0)) times n_groups tile groups;
 // SWEEP heavy operations and fused mux chains: those of layer `layer` in the
 // same way; LAYERED: layer `layer`, n_groups wavefronts of 64 positions per
-// instance.
+// instance.  variant (mixed launches only): kind x 8 + log2(tile group), the
+// kinds as in launch_multi.
 struct MultiSeg {
   const DevOp* ops;
   const DevLayer* layers;
@@ -195,7 +196,7 @@ struct MultiSeg {
   const DevCtl* ctl;
   StateLayout L;
   OpRanges r;
-  uint32_t layer, n_inst, words_per_inst, opw, split, n_groups, pad[2];
+  uint32_t layer, n_inst, words_per_inst, opw, split, n_groups, variant, pad;
 };
 static_assert(sizeof(MultiSeg) == 128, "MultiSeg layout");
 
@@ -297,7 +298,11 @@ uint32_t partitioned_capacity(uint32_t block, bool lds_state, size_t lds);
 // device memory, wave0 the prefix of the segments' wavefronts (n_waves =
 // wave0[n_seg]).  kind 0: SWEEP common operations (tile group tg: 1, 2, 4,
 // 8 or 16), 1: SWEEP heavy (tg 1 or 2), 2: fused mux chains (tg 1, 2 or 4),
-// 3: LAYERED (tg ignored).
+// 3: LAYERED (tg ignored), 4: mixed, each segment of its own kind and tile
+// group (its variant; common operations with tile groups up to 4), so that
+// the small pieces of one layer index need one launch instead of one per
+// kind and tile group.
+bool multi_mixable(uint32_t kind, uint32_t tg);
 hipError_t launch_multi(uint32_t kind, uint32_t tg, const MultiSeg* segs, const uint32_t* wave0,
                         uint32_t n_seg, uint64_t n_waves, hipStream_t s);
 // Register digest of several batches, then their folds and cycle advance

@@ -331,26 +331,31 @@ __global__ void __launch_bounds__(256) k_layer(ResJob J, uint32_t li) {
 // Barrier of all blocks of a cooperative launch (all of them resident).  The
 // block whose arrival completes round r opens it; the others wait with a
 // bounded spin.  A wait past spin_limit sets the error flag and goes on, so
-// every block still ends (the host then reports a device error).  The
-// release of the arrival and the acquire of the wait, at device scope, make
-// every store before the barrier visible to every block after it.
+// every block still ends (the host then reports a device error).  Each
+// arrival is a release at device scope and the opening one also acquires
+// before it releases the open count; a waiter spins on plain device-scope
+// loads and acquires once it sees the barrier open, so every store before
+// the barrier is visible to every block after it without a cache
+// invalidation per spin.
 __device__ __forceinline__ void grid_barrier(GridSync* gs, uint32_t& round, uint32_t spin_limit) {
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t want = round + 1u;
     const uint32_t arrived =
-        __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1u;
     if (arrived == want * gridDim.x) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __hip_atomic_store(&gs->opened, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       uint32_t spins = 0;
-      while (__hip_atomic_load(&gs->opened, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < want) {
+      while (__hip_atomic_load(&gs->opened, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
         if (++spins > spin_limit) {
           __hip_atomic_store(&gs->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
   }
   round += 1u;
@@ -1205,22 +1210,65 @@ k_sweep_muxc_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict
 // LAYERED segments: wavefront (block of 64 threads) w of segment g runs
 // positions [64 (w % n_groups), +64) of layer g.layer for instance
 // w / n_groups.
-__global__ void __launch_bounds__(64)
-k_layer_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wave0,
-              uint32_t n_seg) {
-  const uint32_t wave = blockIdx.x;
-  if (wave >= wave0[n_seg]) return;
-  const uint32_t k = find_seg(wave0, n_seg, wave);
-  const MultiSeg& g = segs[k];
-  const uint32_t local = wave - wave0[k];
-  const uint32_t inst = local / g.n_groups, q0 = (local % g.n_groups) * 64u + threadIdx.x;
+__device__ __forceinline__ void layer_wave(const MultiSeg& g, uint32_t local, uint32_t lane) {
+  const uint32_t inst = local / g.n_groups, q0 = (local % g.n_groups) * 64u + lane;
   const DevLayer ly = g.layers[g.layer];
   const uint32_t n = ly.end - ly.begin, n64 = (n + 63u) & ~63u;
   const uint64_t cycle = g.ctl->cycle;
   const uint64_t words_row =
       ((cycle - g.ctl->step_cycle0) * (uint64_t)g.n_inst + inst) * (uint64_t)g.words_per_inst;
   resident_ops<1>(g.const_limbs, g.state + (uint64_t)inst * g.L.pitch, g.ops, ly, q0, 64u, n, n64,
-                  g.seeds[inst], cycle, g.ctl->words, words_row, threadIdx.x);
+                  g.seeds[inst], cycle, g.ctl->words, words_row, lane);
+}
+
+__global__ void __launch_bounds__(64)
+k_layer_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wave0,
+              uint32_t n_seg) {
+  const uint32_t wave = blockIdx.x;
+  if (wave >= wave0[n_seg]) return;
+  const uint32_t k = find_seg(wave0, n_seg, wave);
+  layer_wave(segs[k], wave - wave0[k], threadIdx.x);
+}
+
+// Mixed launch: every segment names its own kind and tile group (variant);
+// the branch on it is uniform over the wavefront.
+__global__ void __launch_bounds__(256)
+k_mixed_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wave0,
+              uint32_t n_seg) {
+  const uint32_t wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  if (wave >= wave0[n_seg]) return;
+  const uint32_t k = find_seg(wave0, n_seg, wave);
+  const MultiSeg& g = segs[k];
+  const uint32_t local = wave - wave0[k], lane = threadIdx.x & 63u;
+  switch (__builtin_amdgcn_readfirstlane(g.variant)) {
+    case 0: sweep_wave<1, 1, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, local, lane); break;
+    case 1: sweep_wave<1, 2, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, local, lane); break;
+    case 2: sweep_wave<1, 4, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, local, lane); break;
+    case 8:
+      heavy_wave<1>(g.ops, g.layers[g.layer], g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
+                    g.ctl, g.n_inst, g.opw, 0u, g.n_groups, local, lane);
+      break;
+    case 9:
+      heavy_wave<2>(g.ops, g.layers[g.layer], g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
+                    g.ctl, g.n_inst, g.opw, 0u, g.n_groups, local, lane);
+      break;
+    case 16: muxc_wave<1>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
+    case 17: muxc_wave<2>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
+    case 18: muxc_wave<4>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
+    case 24: layer_wave(g, local, lane); break;
+    default: break;
+  }
+}
+
+bool multi_mixable(uint32_t kind, uint32_t tg) {
+  switch (kind) {
+    case 0: return tg == 1 || tg == 2 || tg == 4;
+    case 1: return tg == 1 || tg == 2;
+    case 2: return tg == 1 || tg == 2 || tg == 4;
+    case 3: return true;
+    default: return false;
+  }
 }
 
 // Digest of several batches: segment g's wavefronts run k_digest's body for
@@ -1871,6 +1919,11 @@ hipError_t launch_multi(uint32_t kind, uint32_t tg, const MultiSeg* segs, const 
                         uint32_t n_seg, uint64_t n_waves, hipStream_t s) {
   if (n_seg == 0 || n_waves == 0) return hipSuccess;
   if (n_waves >= (1ull << 32)) return hipErrorInvalidValue;
+  if (kind == 4) {
+    hipLaunchKernelGGL(k_mixed_multi, dim3((uint32_t)((n_waves + 3) / 4)), dim3(256), 0, s, segs,
+                       wave0, n_seg);
+    return hipGetLastError();
+  }
   if (kind == 3) {
     hipLaunchKernelGGL(k_layer_multi, dim3((uint32_t)n_waves), dim3(64), 0, s, segs, wave0, n_seg);
     return hipGetLastError();

@@ -24,6 +24,7 @@ __all__ = [
     "rteaal_validate_design", "rteaal_load_design", "rteaal_unload_design", "rteaal_design_format",
     "RTEAAL_LOAD_KEEP_ALL_SLOTS",
     "rteaal_batch_footprint", "rteaal_batch_resources", "rteaal_create_batch", "rteaal_free_batch",
+    "rteaal_partition_plan_stats",
     "rteaal_batch_info",
     "rteaal_batch_options",
     "rteaal_step", "rteaal_step_many", "rteaal_sync", "rteaal_read_state", "rteaal_write_state",
@@ -91,6 +92,11 @@ class rteaal_batch_opts(C.Structure):
                 ("partitions", C.c_uint32)]
 
 
+class rteaal_partition_stats(C.Structure):
+    _fields_ = [("design_ops", C.c_uint64), ("cone_ops", C.c_uint64), ("padded_ops", C.c_uint64),
+                ("max_part_ops", C.c_uint64), ("exchange", C.c_uint64)]
+
+
 class rteaal_stimulus(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("words_on_device", C.c_uint32), ("words", C.c_void_p)]
 
@@ -131,6 +137,7 @@ def library():
         "rteaal_batch_footprint": ([vp, u32, u32, C.POINTER(rteaal_batch_opts), C.POINTER(u64)], st),
         "rteaal_batch_resources": ([vp, u32, u32, C.POINTER(rteaal_batch_opts), C.POINTER(u64),
                                     C.POINTER(u64)], st),
+        "rteaal_partition_plan_stats": ([vp, u32, u32, C.POINTER(rteaal_partition_stats)], st),
         "rteaal_create_batch": ([vp, u32, u32, vp, C.POINTER(rteaal_batch_opts), C.POINTER(u32)], st),
         "rteaal_free_batch": ([vp, u32], st),
         "rteaal_batch_info": ([vp, u32, C.POINTER(u32), C.POINTER(u64)], st),
@@ -163,8 +170,8 @@ def exported_symbols():
     return ["rteaal_create", "rteaal_destroy", "rteaal_last_error", "rteaal_validate_design",
             "rteaal_load_design", "rteaal_load_design_ex", "rteaal_unload_design",
             "rteaal_design_format",
-            "rteaal_batch_footprint", "rteaal_batch_resources", "rteaal_create_batch",
-            "rteaal_free_batch",
+            "rteaal_batch_footprint", "rteaal_batch_resources", "rteaal_partition_plan_stats",
+            "rteaal_create_batch", "rteaal_free_batch",
             "rteaal_batch_info", "rteaal_batch_options", "rteaal_step", "rteaal_step_many", "rteaal_sync",
             "rteaal_read_state", "rteaal_read_state_noalloc", "rteaal_write_state",
             "rteaal_write_digest",
@@ -469,6 +476,15 @@ def rteaal_batch_resources(ctx, design_id, n_instances, mapping=RTEAAL_MAP_AUTO,
     _check(ctx.handle, library().rteaal_batch_resources(ctx.handle, int(design_id), int(n_instances),
                                                         C.byref(o), C.byref(hbm), C.byref(lds)))
     return hbm.value, lds.value
+
+
+def rteaal_partition_plan_stats(ctx, design_id, partitions):
+    """The partitioned form's size for `partitions` register partitions (host
+    only): dict of design_ops, cone_ops, padded_ops, max_part_ops, exchange."""
+    o = rteaal_partition_stats()
+    _check(ctx.handle, library().rteaal_partition_plan_stats(ctx.handle, int(design_id),
+                                                             int(partitions), C.byref(o)))
+    return {k: int(getattr(o, k)) for k, _ in o._fields_}
 
 
 def rteaal_create_batch(ctx, design_id, seeds, mapping=RTEAAL_MAP_AUTO, **opts):

@@ -344,11 +344,16 @@ void digest_shape(bool sweep, uint32_t n_regs, uint32_t n_inst, uint32_t* n_unit
   if (!sweep) q = (q + 63u) & ~uint64_t(63);
   *per = (uint32_t)q;
 }
-hipError_t launch_multi(uint32_t, uint32_t, const MultiSeg* segs, const uint32_t* wave0,
+bool multi_mixable(uint32_t kind, uint32_t tg) {
+  return kind == 3 || ((kind == 0 || kind == 2) && tg <= 4) || (kind == 1 && tg <= 2);
+}
+hipError_t launch_multi(uint32_t kind, uint32_t, const MultiSeg* segs, const uint32_t* wave0,
                         uint32_t n_seg, uint64_t n_waves, hipStream_t s) {
   launched(s, {segs, wave0, segs + n_seg - 1, wave0 + n_seg});
   if (wave0[n_seg] != n_waves) die("segment prefix does not match the wave count", wave0);
   for (uint32_t k = 0; k < n_seg; ++k) {
+    if (kind == 4 && !multi_mixable(segs[k].variant / 8, 1u << (segs[k].variant % 8)))
+      die("mixed segment of an unknown variant", &segs[k]);
     launched(s, {segs[k].ops, segs[k].layers, segs[k].const_limbs, segs[k].state, segs[k].seeds,
                  segs[k].ctl});
     if (wave0[k + 1] <= wave0[k]) die("empty or decreasing segment", &wave0[k]);

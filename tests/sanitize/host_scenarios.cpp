@@ -241,6 +241,19 @@ int main(int argc, char** argv) {
     }
     ok(rteaal_sync(g_ctx), "sync");
     for (rteaal_batch_id b : bs) ok(rteaal_free_batch(g_ctx, b), "free_batch");
+    for (size_t k = 0; k < D; ++k) {
+      const uint32_t nr = (uint32_t)ds[k].reg_slot.size();
+      for (uint32_t p : {1u, 2u, nr}) {
+        if (p == 0 || p > nr || p > 1024) continue;
+        rteaal_partition_stats st{};
+        ok(rteaal_partition_plan_stats(g_ctx, ids[k], p, &st), "partition_plan_stats");
+        if (st.cone_ops > st.padded_ops || st.max_part_ops > st.padded_ops ||
+            (p == 1 && (st.exchange != 0 || st.cone_ops > st.design_ops))) {
+          std::fprintf(stderr, "partition stats out of range\n");
+          return 3;
+        }
+      }
+    }
   }
   // 4. Autotuners.
   {

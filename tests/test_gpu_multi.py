@@ -2,13 +2,17 @@
 
 SWEEP and LAYERED batches stepped together run as one captured cycle per
 set of batches: every batch's layers spread over shared layer slots, one
-launch per slot and kind over a table of segments.  Each batch must still
-equal the oracle (registers and per-cycle digest): with uneven cycle counts
-(batches drop out of the set in order, the last one finishing alone), with
-watched or tile-pass batches beside them (stepped on their own), with a
-RESIDENT batch in the same call, after a batch of a cached set is freed,
-and when more sets are used than the cache holds.  Tolerance 0.
+launch per slot and kind over a table of segments, or, while a slot's
+pieces are small, one mixed launch whose segments name their own kind.
+Each batch must still equal the oracle (registers and per-cycle digest):
+with uneven cycle counts (batches drop out of the set in order, the last
+one finishing alone), with mixed launches off and everywhere, with watched
+or tile-pass batches beside them (stepped on their own), with a RESIDENT
+batch in the same call, after a batch of a cached set is freed, and when
+more sets are used than the cache holds.  Tolerance 0.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -65,6 +69,33 @@ SHAPES = [dict(mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=1),
 
 
 def test_uneven_cycles_every_shape(ctx, designs):
+    uneven_cycles_every_shape(ctx, designs)
+
+
+@pytest.mark.parametrize("max_waves", ["0", "1000000000"])
+def test_uneven_cycles_mixed_launches_off_and_everywhere(designs, max_waves):
+    """The same with the pieces of a layer index never merged into one mixed
+    launch, and merged wherever their kinds allow it."""
+    old = os.environ.get("RTEAAL_MIXED_MAX_WAVES")
+    os.environ["RTEAAL_MIXED_MAX_WAVES"] = max_waves
+    try:
+        c = gpu_ctx()
+    finally:
+        if old is None:
+            del os.environ["RTEAAL_MIXED_MAX_WAVES"]
+        else:
+            os.environ["RTEAAL_MIXED_MAX_WAVES"] = old
+    ds, refs, _ = designs
+    ids = [R.rteaal_load_design(c, d) for d in ds]
+    try:
+        uneven_cycles_every_shape(c, (ds, refs, ids))
+    finally:
+        for i in ids:
+            R.rteaal_unload_design(c, i)
+        R.rteaal_destroy(c)
+
+
+def uneven_cycles_every_shape(ctx, designs):
     ds, refs, ids = designs
     rng = np.random.default_rng(9)
     plan = []

@@ -222,7 +222,7 @@ def test_layered_plain_form_large_layers(ctx):
     did = R.rteaal_load_design(ctx, d)
     try:
         with pytest.raises(R.RteaalError) as e:
-            R.rteaal_create_batch(ctx, did, [1], mapping=4)
+            R.rteaal_create_batch(ctx, did, [1], mapping=5)
         assert e.value.status == 1
     finally:
         R.rteaal_unload_design(ctx, did)

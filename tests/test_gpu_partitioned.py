@@ -170,3 +170,27 @@ def test_partitioned_refusals(ctx):
             R.rteaal_free_batch(ctx, bid)
     finally:
         R.rteaal_unload_design(ctx, did)
+
+
+def test_partition_plan_stats(ctx):
+    """Host-side size of the partitioned form: every cone of one partition is
+    the union of all cones (the operations that reach a register), each
+    partition count replicates at least that much, and the exchange is empty
+    for one partition."""
+    d = rtlgen.generate(rtlgen.GenConfig(3000, 20, 100, 16, rtlgen.generator.WIDTHS_LARGE,
+                                         "part"), 51)
+    did = R.rteaal_load_design(ctx, d)
+    try:
+        one = R.rteaal_partition_plan_stats(ctx, did, 1)
+        assert one["exchange"] == 0 and one["cone_ops"] <= one["design_ops"]
+        assert one["max_part_ops"] == one["padded_ops"] >= one["cone_ops"]
+        for p in (2, 7, 100):
+            st = R.rteaal_partition_plan_stats(ctx, did, p)
+            assert st["design_ops"] == one["design_ops"]
+            assert one["cone_ops"] <= st["cone_ops"] <= p * one["cone_ops"]
+            assert st["cone_ops"] <= st["padded_ops"] and st["max_part_ops"] <= st["padded_ops"]
+            assert st["exchange"] > 0
+        with pytest.raises(R.RteaalError):
+            R.rteaal_partition_plan_stats(ctx, did, 101)
+    finally:
+        R.rteaal_unload_design(ctx, did)

@@ -1082,23 +1082,23 @@ def main():
 
     if args.workload == "multi-64":
         args.designs = args.designs or 64
-        print(json.dumps(bench_multi(args, R, torch)), flush=True)
-        return
-    if args.workload == "serving":
+        result = bench_multi(args, R, torch)
+    elif args.workload == "serving":
         args.designs = args.designs or 32
-        print(json.dumps(bench_serving(args, R, torch)), flush=True)
-        return
-    if args.workload == "levelize-5m":
-        print(json.dumps(bench_levelize(args, R, torch)), flush=True)
-        return
-    if args.workload == "waveform":
-        print(json.dumps(bench_waveform(args, R, torch)), flush=True)
-        return
-    if args.workload == "muxchain-2m":
-        print(json.dumps(bench_muxchain(args, R, torch)), flush=True)
-        return
-
-    print(json.dumps(bench_single(args, R, torch)), flush=True)
+        result = bench_serving(args, R, torch)
+    elif args.workload == "levelize-5m":
+        result = bench_levelize(args, R, torch)
+    elif args.workload == "waveform":
+        result = bench_waveform(args, R, torch)
+    elif args.workload == "muxchain-2m":
+        result = bench_muxchain(args, R, torch)
+    else:
+        result = bench_single(args, R, torch)
+    print(json.dumps(result), flush=True)
+    if result.get("parity_sample_ok") is False:
+        print("[bench] PARITY MISMATCH against the oracle (see the parity field)", file=sys.stderr,
+              flush=True)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -446,13 +446,13 @@ rteaal_status rteaal_step(rteaal_ctx* ctx, rteaal_batch_id batch, uint64_t n_cyc
  * [n_cycles[k]][n_instances][W] of that batch).  Enqueue only, except that
  * host words are copied before the call returns (it then waits for the
  * step).  How the work is laid out: all RESIDENT batches advance in one
- * persistent launch per kernel configuration; SWEEP and LAYERED batches
- * advance together through one captured cycle per set of batches (the
- * pieces of a layer index in one mixed launch while they are small,
- * environment RTEAAL_MIXED_MAX_WAVES, default 4096 wavefronts, 0 = never),
- * beside the RESIDENT launches; cooperative batches (persistent LAYERED,
- * PARTITIONED) run last, one at a time, with nothing else of the call
- * beside them.  Errors: RTEAAL_E_INVALID_ARG (unknown or repeated batch,
+ * persistent launch per kernel configuration, the configurations on up to
+ * four streams; SWEEP and LAYERED batches advance together, beside them,
+ * through one captured cycle per set of batches (the pieces of a layer
+ * index in one mixed launch while they total at most
+ * RTEAAL_MIXED_MAX_WAVES wavefronts, an environment variable, default
+ * 2^20, 0 = never); cooperative batches (persistent LAYERED, PARTITIONED)
+ * run last, one at a time, with nothing else of the call beside them.  Errors: RTEAAL_E_INVALID_ARG (unknown or repeated batch,
  * bad stimulus: then nothing has been enqueued), RTEAAL_E_NO_MEMORY,
  * RTEAAL_E_DEVICE (the context is then unusable). */
 rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_id* batches,

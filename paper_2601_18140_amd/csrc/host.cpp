@@ -79,7 +79,7 @@ struct rteaal_ctx {
   uint32_t spin_limit = 1u << 22;  // grid barrier waits of persistent launches
   // Captured multi-batch cycles: the pieces of one layer index run as one
   // mixed launch while they total at most this many wavefronts (0: never).
-  uint32_t mixed_max_waves = 4096;
+  uint32_t mixed_max_waves = 1u << 20;
   uint64_t* scratch = nullptr;  // this device's staging array (rteaal_read_state_noalloc)
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -2440,42 +2440,82 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
     ctx->stream = keep;
     return st;
   };
-  // Every auxiliary stream this call uses forks here, before the RESIDENT
-  // launches are enqueued on the context stream, so that the captured
-  // cycles and the RESIDENT launches overlap.  The RESIDENT launches are
-  // enqueued first: submitting many cycle replays can block the host until
-  // the device has run most of them.
+  // RESIDENT batches: one persistent launch per kernel configuration, every
+  // workgroup running one instance of one batch for that batch's cycles.
+  // Watched RESIDENT batches run one cycle per launch (captured after each)
+  // on the context stream instead.
+  // A launch gives every workgroup the largest LDS of its jobs, so jobs are
+  // also grouped by how many of their workgroups fit a compute unit's LDS
+  // (1, 2, 4 or 8): small designs then share compute units instead of each
+  // holding one as large designs do.
+  struct Key {
+    bool lds, ops;
+    uint32_t unroll, block, per_cu;
+    bool operator<(const Key& o) const {
+      return std::tie(lds, ops, unroll, block, per_cu) <
+             std::tie(o.lds, o.ops, o.unroll, o.block, o.per_cu);
+    }
+  };
+  std::map<Key, std::vector<uint32_t>> group_map;
+  std::vector<uint32_t> watched_res;
+  for (uint32_t k = 0; k < n; ++k) {
+    Batch& b = *bs[k];
+    if (b.mapping != RTEAAL_MAP_RESIDENT || !n_cycles[k]) continue;
+    if (b.n_watch) {
+      watched_res.push_back(k);
+      continue;
+    }
+    const DesignHost& h = *find_design(ctx, b.design);
+    const size_t lb = resident_lds_bytes(b.L, (uint32_t)h.ops.size(), (uint32_t)h.layers.size(),
+                                         b.lds, b.lds_ops);
+    uint32_t per_cu = lb ? (uint32_t)std::min<size_t>(8, (160u * 1024u) / (lb + 256)) : 8u;
+    per_cu = per_cu >= 8 ? 8 : per_cu >= 4 ? 4 : per_cu >= 2 ? 2 : 1;
+    group_map[Key{b.lds, b.lds_ops, b.unroll, b.block, per_cu}].push_back(k);
+  }
+  std::vector<std::pair<Key, std::vector<uint32_t>>> groups(group_map.begin(), group_map.end());
+  // Group g runs on the context stream (g = 0) or on auxiliary stream
+  // 1 + (g - 1) mod 3, so that configurations run side by side.
+  auto group_stream = [&](size_t g) { return g == 0 ? ctx->stream : ctx->aux[1 + (g - 1) % 3]; };
+
+  // Every auxiliary stream this call uses forks here, before anything else
+  // is enqueued, so that the captured cycles, the single batches and the
+  // RESIDENT launches overlap.  The RESIDENT launches are enqueued first:
+  // submitting many cycle replays can block the host until the device has
+  // run most of them.
   {
-    const size_t n_needed = (replays.empty() ? 0 : 1) + single.size();
+    size_t n_needed = (replays.empty() ? 0 : 1) + single.size();
+    if (groups.size() > 1) n_needed = std::max<size_t>(n_needed, std::min<size_t>(groups.size(), 4));
     for (uint32_t a = 0; a < std::min<size_t>(n_needed, 4); ++a) {
       const rteaal_status st = fork_aux(a);
       if (st != RTEAAL_OK) return st;
     }
   }
-  // RESIDENT batches: one persistent launch per kernel configuration, every
-  // workgroup running one instance of one batch for that batch's cycles.
-  struct Key {
-    bool lds, ops;
-    uint32_t unroll, block;
-    bool operator<(const Key& o) const {
-      return std::tie(lds, ops, unroll, block) < std::tie(o.lds, o.ops, o.unroll, o.block);
-    }
-  };
-  // Watched RESIDENT batches run one cycle per launch (captured after each)
-  // on the context stream instead.
-  std::map<Key, std::vector<uint32_t>> groups;
-  for (uint32_t k = 0; k < n; ++k) {
-    Batch& b = *bs[k];
-    if (b.mapping != RTEAAL_MAP_RESIDENT || !n_cycles[k]) continue;
-    if (b.n_watch) {
-      rteaal_status st = enqueue_cycles(ctx, *find_design(ctx, b.design), b, n_cycles[k]);
-      if (st != RTEAAL_OK) return st;
-      b.cycle += n_cycles[k];
-      continue;
-    }
-    groups[Key{b.lds, b.lds_ops, b.unroll, b.block}].push_back(k);
+  // Job tables: one region of the context's table buffer per group (its
+  // first chunk is its largest), so that groups on different streams never
+  // share one.  The buffer is reused only by later calls, which are ordered
+  // after this one's launches (the call ends by joining its streams).
+  std::vector<size_t> goff(groups.size() + 1, 0);
+  for (size_t g = 0; g < groups.size(); ++g) {
+    size_t need = groups[g].second.size() * sizeof(ResJob);
+    for (uint32_t k : groups[g].second) need += (size_t)bs[k]->n_inst * sizeof(uint2);
+    goff[g + 1] = goff[g] + ((need + 255) & ~size_t(255));
   }
-  for (auto& g : groups) {
+  if (ctx->multi.bytes < goff.back()) {
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    dev_free(ctx, ctx->multi);
+    if (!alloc_all(ctx, {{&ctx->multi, std::max<size_t>(goff.back(), 1u << 16) * 2}}))
+      return fail(ctx, RTEAAL_E_NO_MEMORY, "job table allocation failed");
+  }
+  for (uint32_t k : watched_res) {
+    Batch& b = *bs[k];
+    rteaal_status st = enqueue_cycles(ctx, *find_design(ctx, b.design), b, n_cycles[k]);
+    if (st != RTEAAL_OK) return st;
+    b.cycle += n_cycles[k];
+  }
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    auto& g = groups[gi];
+    hipStream_t gs = group_stream(gi);
+    char* table = (char*)ctx->multi.p + goff[gi];
     std::vector<uint64_t> left(g.second.size());
     for (size_t q = 0; q < g.second.size(); ++q) left[q] = n_cycles[g.second[q]];
     for (;;) {
@@ -2498,25 +2538,17 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
       }
       if (jobs.empty()) break;
       const size_t need = jobs.size() * sizeof(ResJob) + map.size() * sizeof(uint2);
-      if (ctx->multi.bytes < need) {
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-        dev_free(ctx, ctx->multi);
-        if (!alloc_all(ctx, {{&ctx->multi, std::max<size_t>(need, 1u << 16) * 2}})) {
-          ctx->poisoned = true;  // batches before this group have advanced, the rest have not
-          return fail(ctx, RTEAAL_E_NO_MEMORY, "job table allocation failed");
-        }
-      }
       std::vector<char> blob(need);
       memcpy(blob.data(), jobs.data(), jobs.size() * sizeof(ResJob));
       memcpy(blob.data() + jobs.size() * sizeof(ResJob), map.data(), map.size() * sizeof(uint2));
-      HIP_TRY(ctx, hipMemcpyAsync(ctx->multi.p, blob.data(), need, hipMemcpyHostToDevice, ctx->stream));
-      // The copy above was staged from pageable memory; the next reuse of the
-      // table is ordered after this launch on the same stream.
-      const ResJob* dj = (const ResJob*)ctx->multi.p;
-      const uint2* dm = (const uint2*)((char*)ctx->multi.p + jobs.size() * sizeof(ResJob));
+      // Staged from pageable memory; the group's next chunk reuses the
+      // region after this launch on the same stream.
+      HIP_TRY(ctx, hipMemcpyAsync(table, blob.data(), need, hipMemcpyHostToDevice, gs));
+      const ResJob* dj = (const ResJob*)table;
+      const uint2* dm = (const uint2*)(table + jobs.size() * sizeof(ResJob));
       HIP_TRY(ctx, launch_resident_multi(dj, dm, (uint32_t)map.size(), g.first.block, g.first.lds,
-                                         g.first.ops, g.first.unroll, lds, ctx->stream));
-      for (auto& a : adv) HIP_TRY(ctx, launch_advance(a.first, a.second, ctx->stream));
+                                         g.first.ops, g.first.unroll, lds, gs));
+      for (auto& a : adv) HIP_TRY(ctx, launch_advance(a.first, a.second, gs));
     }
     for (uint32_t k : g.second) bs[k]->cycle += n_cycles[k];
   }
@@ -3038,7 +3070,7 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
   // Trial length: about 4e9 op-evaluations per policy, 2..32 cycles.
   const uint64_t cyc = trial_cycles ? trial_cycles
                                     : (uint64_t)std::max(2.0, std::min(32.0, 4e9 / std::max<double>((double)total, 1.0)));
-  std::string key = "joint|o11p11|" + device_tag(ctx->device);
+  std::string key = "joint|o11q16|" + device_tag(ctx->device);
   {
     uint64_t fp = 1469598103934665603ull;
     for (uint32_t k = 0; k < n; ++k) {
@@ -3058,18 +3090,29 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
     // to tg_cap tiles), smaller ones RESIDENT, or LAYERED when their design
     // is large (a layer over the whole device rather than one compute unit).
     // SWEEP batches take ops_per_wave operations per wavefront: fewer give
-    // a captured cycle's small launches more, shorter wavefronts.
+    // a captured cycle's small launches more, shorter wavefronts.  RESIDENT
+    // batches take at most res_block threads per workgroup (0: the
+    // design's default): smaller workgroups put more instances on a compute
+    // unit, whose layer barriers then stall less of it.
+    // Designs of at least sweep_ops operations run SWEEP whatever their
+    // instance count: a RESIDENT instance of a large design keeps one
+    // compute unit busy for the whole step.
     struct Policy {
-      uint32_t sweep_min, tg_cap, layered_ops, opw;
+      uint32_t sweep_min, tg_cap, layered_ops, opw, res_block, sweep_ops;
     };
-    const Policy pol[] = {{16, 4, UINT32_MAX, 8}, {16, 4, 100000, 8}, {48, 4, 100000, 8},
-                          {16, 2, 100000, 8},     {8, 4, 100000, 8},   {48, 2, UINT32_MAX, 8},
-                          {48, 2, UINT32_MAX, 2}, {48, 2, UINT32_MAX, 4}, {16, 2, UINT32_MAX, 2},
-                          {96, 2, UINT32_MAX, 2}, {UINT32_MAX, 1, UINT32_MAX, 8}};
+    constexpr uint32_t kNever = UINT32_MAX;
+    const Policy pol[] = {{16, 4, kNever, 8, 0, kNever},      {16, 4, 100000, 8, 0, kNever},
+                          {48, 4, 100000, 8, 0, kNever},      {16, 2, 100000, 8, 0, kNever},
+                          {48, 2, kNever, 8, 0, kNever},      {48, 2, kNever, 2, 0, kNever},
+                          {48, 2, kNever, 4, 0, kNever},      {96, 2, kNever, 2, 0, kNever},
+                          {kNever, 1, kNever, 8, 0, kNever},  {48, 2, kNever, 4, 256, kNever},
+                          {48, 2, kNever, 2, 256, kNever},    {48, 2, kNever, 4, 256, 300000},
+                          {48, 2, kNever, 4, 256, 150000},    {48, 2, kNever, 4, 256, 75000},
+                          {48, 2, kNever, 2, 256, 150000},    {96, 2, kNever, 4, 256, 150000}};
     auto opts_of = [&](const Policy& p, uint32_t k) {
       rteaal_batch_opts o{};
       const uint32_t ni = n_inst[k];
-      if (ni >= p.sweep_min) {
+      if (ni >= p.sweep_min || hs[k]->ops.size() >= p.sweep_ops) {
         const uint32_t tiles = (ni + 63) / 64;
         uint32_t tg = 1;
         while (tg * 2 <= std::min(tiles, p.tg_cap)) tg *= 2;
@@ -3083,6 +3126,8 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
         o.unroll = 1;
       } else {
         o.mapping = RTEAAL_MAP_RESIDENT;
+        const uint32_t m = ((hs[k]->max_layer_ops + 63) / 64) * 64;
+        if (p.res_block && m > p.res_block) o.block_threads = p.res_block;
       }
       return o;
     };
@@ -3133,9 +3178,10 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
       for (rteaal_batch_id b : bs) rteaal_free_batch(ctx, b);
       if (st != RTEAAL_OK) break;
       if (log)
-        std::fprintf(stderr, "rteaal_autotune_many: sweep from %u instances, tile groups up to %u, "
-                     "%u ops per wavefront, LAYERED from %u ops -> %.4g\n", p.sweep_min, p.tg_cap,
-                     p.opw, p.layered_ops, r);
+        std::fprintf(stderr, "rteaal_autotune_many: sweep from %u instances or %u ops, tile groups "
+                     "up to %u, %u ops per wavefront, LAYERED from %u ops, RESIDENT blocks up to "
+                     "%u -> %.4g\n", p.sweep_min, p.sweep_ops, p.tg_cap, p.opw, p.layered_ops,
+                     p.res_block, r);
       if (r > best_rate) {
         best_rate = r;
         chosen = os;

@@ -1826,11 +1826,14 @@ hipError_t launch_capture(bool sweep, const StateLayout& L, const char* state, c
 
 void digest_shape(bool sweep, uint32_t n_regs, uint32_t n_inst, uint32_t* n_units, uint32_t* per) {
   // About 16,384 wavefronts (64 per compute unit) to keep many loads in
-  // flight, with few atomics.
+  // flight, with few atomics: in the SWEEP layout every lane of a wavefront
+  // adds its instance's sum with one atomic, so a wavefront takes at least
+  // 32 registers (small batches would otherwise spend one atomic per term).
   *n_units = sweep ? (n_inst + 63u) / 64u : n_inst;
   const uint64_t want = std::max<uint64_t>(1, (16384u + *n_units - 1) / *n_units);
   uint64_t p = ((uint64_t)std::max<uint32_t>(n_regs, 1u) + want - 1) / want;
-  if (!sweep) p = (p + 63u) & ~uint64_t(63);
+  if (sweep) p = std::max<uint64_t>(p, 32u);
+  else p = (p + 63u) & ~uint64_t(63);
   *per = (uint32_t)p;
 }
 

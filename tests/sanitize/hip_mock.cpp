@@ -341,7 +341,8 @@ void digest_shape(bool sweep, uint32_t n_regs, uint32_t n_inst, uint32_t* n_unit
   *n_units = sweep ? (n_inst + 63u) / 64u : n_inst;
   const uint64_t want = std::max<uint64_t>(1, (16384u + *n_units - 1) / *n_units);
   uint64_t q = ((uint64_t)std::max<uint32_t>(n_regs, 1u) + want - 1) / want;
-  if (!sweep) q = (q + 63u) & ~uint64_t(63);
+  if (sweep) q = std::max<uint64_t>(q, 32u);
+  else q = (q + 63u) & ~uint64_t(63);
   *per = (uint32_t)q;
 }
 bool multi_mixable(uint32_t kind, uint32_t tg) {

@@ -11,6 +11,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -874,10 +875,12 @@ struct PartPlan {
   std::vector<uint32_t> lists;            // per partition: own, then need
   std::vector<uint32_t> op_begin, own_begin, own_n, need_begin, need_n;
   uint64_t cone_ops = 0;                  // operations in all cones (without padding)
-  uint64_t max_part_ops = 0, exchange = 0;
+  uint64_t padded_ops = 0, max_part_ops = 0, exchange = 0;
 };
 
-void plan_partitions(const DesignHost& h, uint32_t P, PartPlan* out) {
+// materialize: false only counts (cone_ops, padded_ops, max_part_ops,
+// exchange), without building the sub-programs.
+void plan_partitions(const DesignHost& h, uint32_t P, PartPlan* out, bool materialize) {
   const uint32_t W = (P + 63) / 64;
   const size_t NW = h.n_enc_slots, NL = h.layers.size(), NO = h.ops.size();
   std::vector<uint64_t> need((size_t)NW * W, 0), mask(NO * W, 0);
@@ -905,12 +908,12 @@ void plan_partitions(const DesignHost& h, uint32_t P, PartPlan* out) {
     const uint32_t pw = p / 64;
     const uint64_t pb = 1ull << (p % 64);
     auto in = [&](uint32_t pos) { return (mask[(size_t)pos * W + pw] & pb) != 0; };
-    const uint32_t base = (uint32_t)pl.ops.size();
-    pl.op_begin.push_back(base);
+    const uint64_t before = pl.padded_ops;
+    if (materialize) pl.op_begin.push_back((uint32_t)pl.ops.size());
     for (size_t k = 0; k < NL; ++k) {
       const DevLayer& ly = h.layers[k];
       DevLayer sl{};
-      sl.begin = (uint32_t)pl.ops.size() - base;
+      sl.begin = (uint32_t)(pl.padded_ops - before);
       for (uint32_t g0 = 0; g0 < ly.n_bdst; g0 += 64) {
         const uint32_t g1 = std::min(ly.n_bdst, g0 + 64);
         bool any = false;
@@ -919,30 +922,40 @@ void plan_partitions(const DesignHost& h, uint32_t P, PartPlan* out) {
           any = any || x;
           pl.cone_ops += x;
         }
-        if (any)
+        if (!any) continue;
+        pl.padded_ops += g1 - g0;
+        if (materialize)
           pl.ops.insert(pl.ops.end(), h.ops.begin() + ly.begin + g0, h.ops.begin() + ly.begin + g1);
       }
       for (uint32_t pos = ly.begin + ly.n_bdst; pos < ly.end; ++pos)
         if (in(pos)) {
-          pl.ops.push_back(h.ops[pos]);
           ++pl.cone_ops;
+          ++pl.padded_ops;
+          if (materialize) pl.ops.push_back(h.ops[pos]);
         }
-      sl.end = (uint32_t)pl.ops.size() - base;
-      pl.layers.push_back(sl);
+      sl.end = (uint32_t)(pl.padded_ops - before);
+      if (materialize) pl.layers.push_back(sl);
     }
-    pl.own_begin.push_back((uint32_t)pl.lists.size());
+    pl.max_part_ops = std::max<uint64_t>(pl.max_part_ops, pl.padded_ops - before);
+    if (materialize) {
+      pl.own_begin.push_back((uint32_t)pl.lists.size());
+      for (uint32_t j = 0; j < h.n_regs; ++j)
+        if (owner(j) == p) pl.lists.push_back(j);
+      pl.own_n.push_back((uint32_t)pl.lists.size() - pl.own_begin.back());
+      pl.need_begin.push_back((uint32_t)pl.lists.size());
+    }
     for (uint32_t j = 0; j < h.n_regs; ++j)
-      if (owner(j) == p) pl.lists.push_back(j);
-    pl.own_n.push_back((uint32_t)pl.lists.size() - pl.own_begin.back());
-    pl.need_begin.push_back((uint32_t)pl.lists.size());
-    for (uint32_t j = 0; j < h.n_regs; ++j)
-      if (owner(j) != p && (need[(size_t)h.reg_slot[j] * W + pw] & pb)) pl.lists.push_back(j);
-    pl.need_n.push_back((uint32_t)pl.lists.size() - pl.need_begin.back());
-    pl.max_part_ops = std::max<uint64_t>(pl.max_part_ops, pl.ops.size() - base);
-    for (uint32_t i = pl.need_begin.back(); i < pl.lists.size(); ++i)
-      pl.exchange += (h.reg_refs[pl.lists[i]].width + 63) / 64;
+      if (owner(j) != p && (need[(size_t)h.reg_slot[j] * W + pw] & pb)) {
+        pl.exchange += (h.reg_refs[j].width + 63) / 64;
+        if (materialize) pl.lists.push_back(j);
+      }
+    if (materialize) pl.need_n.push_back((uint32_t)pl.lists.size() - pl.need_begin.back());
   }
 }
+
+// Largest partitioned program a batch may hold (operation records, 32 bytes
+// each): 2^27 operations, 4 GiB.
+constexpr uint64_t kMaxPartOps = 1ull << 27;
 
 // PARTITIONED set-up on the host: the partition count, the plan, the block
 // size, LDS use and the co-residency check, and the host image of the
@@ -958,7 +971,18 @@ rteaal_status plan_batch_partitions(rteaal_ctx* ctx, const DesignHost& h, uint32
   const uint64_t copy_pitch = (h.n_rows * 8 + 15) & ~uint64_t(15);
   if (copy_pitch * P * 8 >= (1ull << 32))
     return fail(ctx, RTEAAL_E_INVALID_ARG, "PARTITIONED: %u copies of the state exceed 512 MB", P);
-  plan_partitions(h, P, plan);
+  try {
+    PartPlan count;
+    plan_partitions(h, P, &count, false);
+    if (count.padded_ops > kMaxPartOps)
+      return fail(ctx, RTEAAL_E_INVALID_ARG,
+                  "PARTITIONED: %u partitions replicate the design into %llu operations (at most "
+                  "%llu); use fewer partitions",
+                  P, (unsigned long long)count.padded_ops, (unsigned long long)kMaxPartOps);
+    plan_partitions(h, P, plan, true);
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, RTEAAL_E_NO_MEMORY, "PARTITIONED: host memory for the partition plan");
+  }
   uint32_t m = 0;
   for (const DevLayer& l : plan->layers) m = std::max(m, l.end - l.begin);
   uint32_t blk = o && o->block_threads ? o->block_threads : 0;
@@ -2046,10 +2070,14 @@ rteaal_status rteaal_partition_plan_stats(rteaal_ctx* ctx, rteaal_design_id id, 
   if (partitions == 0 || partitions > 1024 || partitions > std::max<uint32_t>(h->n_regs, 1))
     return fail(ctx, RTEAAL_E_INVALID_ARG, "%u partitions for %u registers", partitions, h->n_regs);
   PartPlan pl;
-  plan_partitions(*h, partitions, &pl);
+  try {
+    plan_partitions(*h, partitions, &pl, false);
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, RTEAAL_E_NO_MEMORY, "host memory for the partition plan");
+  }
   out->design_ops = h->ops.size();
   out->cone_ops = pl.cone_ops;
-  out->padded_ops = pl.ops.size();
+  out->padded_ops = pl.padded_ops;
   out->max_part_ops = pl.max_part_ops;
   out->exchange = pl.exchange;
   return RTEAAL_OK;

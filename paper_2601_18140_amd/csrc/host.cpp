@@ -3098,7 +3098,7 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
   // Trial length: about 4e9 op-evaluations per policy, 2..32 cycles.
   const uint64_t cyc = trial_cycles ? trial_cycles
                                     : (uint64_t)std::max(2.0, std::min(32.0, 4e9 / std::max<double>((double)total, 1.0)));
-  std::string key = "joint|o11q16|" + device_tag(ctx->device);
+  std::string key = "joint|o11r16|" + device_tag(ctx->device);
   {
     uint64_t fp = 1469598103934665603ull;
     for (uint32_t k = 0; k < n; ++k) {
@@ -3124,23 +3124,35 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
     // unit, whose layer barriers then stall less of it.
     // Designs of at least sweep_ops operations run SWEEP whatever their
     // instance count: a RESIDENT instance of a large design keeps one
-    // compute unit busy for the whole step.
+    // compute unit busy for the whole step.  With lds_only, RESIDENT is
+    // kept only for designs whose state and program records both fit a
+    // workgroup's LDS (the records then are read from HBM once per launch,
+    // not once per instance and cycle); the others run SWEEP.
     struct Policy {
-      uint32_t sweep_min, tg_cap, layered_ops, opw, res_block, sweep_ops;
+      uint32_t sweep_min, tg_cap, layered_ops, opw, res_block, sweep_ops, lds_only;
     };
     constexpr uint32_t kNever = UINT32_MAX;
-    const Policy pol[] = {{16, 4, kNever, 8, 0, kNever},      {16, 4, 100000, 8, 0, kNever},
-                          {48, 4, 100000, 8, 0, kNever},      {16, 2, 100000, 8, 0, kNever},
-                          {48, 2, kNever, 8, 0, kNever},      {48, 2, kNever, 2, 0, kNever},
-                          {48, 2, kNever, 4, 0, kNever},      {96, 2, kNever, 2, 0, kNever},
-                          {kNever, 1, kNever, 8, 0, kNever},  {48, 2, kNever, 4, 256, kNever},
-                          {48, 2, kNever, 2, 256, kNever},    {48, 2, kNever, 4, 256, 300000},
-                          {48, 2, kNever, 4, 256, 150000},    {48, 2, kNever, 4, 256, 75000},
-                          {48, 2, kNever, 2, 256, 150000},    {96, 2, kNever, 4, 256, 150000}};
+    const Policy pol[] = {
+        {16, 4, kNever, 8, 0, kNever, 0},     {16, 4, 100000, 8, 0, kNever, 0},
+        {48, 4, 100000, 8, 0, kNever, 0},     {48, 2, kNever, 8, 0, kNever, 0},
+        {48, 2, kNever, 2, 0, kNever, 0},     {48, 2, kNever, 4, 0, kNever, 0},
+        {96, 2, kNever, 2, 0, kNever, 0},     {kNever, 1, kNever, 8, 0, kNever, 0},
+        {48, 2, kNever, 4, 256, kNever, 0},   {48, 2, kNever, 2, 256, kNever, 0},
+        {48, 2, kNever, 4, 256, 150000, 0},   {48, 2, 100000, 4, 256, kNever, 0},
+        {48, 2, kNever, 4, 256, kNever, 1},   {48, 2, kNever, 2, 0, kNever, 1},
+        {96, 2, kNever, 4, 256, kNever, 1},   {kNever, 2, kNever, 4, 256, kNever, 1}};
     auto opts_of = [&](const Policy& p, uint32_t k) {
       rteaal_batch_opts o{};
       const uint32_t ni = n_inst[k];
-      if (ni >= p.sweep_min || hs[k]->ops.size() >= p.sweep_ops) {
+      bool res_fits = true;
+      if (p.lds_only) {
+        StateLayout L;
+        uint64_t sb = 0;
+        make_layout(*hs[k], RTEAAL_MAP_RESIDENT, ni, 1, &L, &sb);
+        res_fits = resident_lds_bytes(L, (uint32_t)hs[k]->ops.size(), (uint32_t)hs[k]->layers.size(),
+                                      true, true) <= ctx->max_lds;
+      }
+      if (ni >= p.sweep_min || hs[k]->ops.size() >= p.sweep_ops || !res_fits) {
         const uint32_t tiles = (ni + 63) / 64;
         uint32_t tg = 1;
         while (tg * 2 <= std::min(tiles, p.tg_cap)) tg *= 2;
@@ -3206,9 +3218,10 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
       for (rteaal_batch_id b : bs) rteaal_free_batch(ctx, b);
       if (st != RTEAAL_OK) break;
       if (log)
-        std::fprintf(stderr, "rteaal_autotune_many: sweep from %u instances or %u ops, tile groups "
-                     "up to %u, %u ops per wavefront, LAYERED from %u ops, RESIDENT blocks up to "
-                     "%u -> %.4g\n", p.sweep_min, p.sweep_ops, p.tg_cap, p.opw, p.layered_ops,
+        std::fprintf(stderr, "rteaal_autotune_many: sweep from %u instances or %u ops%s, tile "
+                     "groups up to %u, %u ops per wavefront, LAYERED from %u ops, RESIDENT blocks "
+                     "up to %u -> %.4g\n", p.sweep_min, p.sweep_ops,
+                     p.lds_only ? " or records beyond LDS" : "", p.tg_cap, p.opw, p.layered_ops,
                      p.res_block, r);
       if (r > best_rate) {
         best_rate = r;

@@ -18,7 +18,8 @@
 //   5. a stable radix sort of (layer, index) gives the order, and the first
 //      position of every layer value gives the layer ranges.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include <algorithm>
 
@@ -178,11 +179,11 @@ uint32_t bits_for(uint32_t v) {
 
 hipError_t levelize_temp_bytes(uint32_t n, size_t* bytes) {
   size_t a = 0, b = 0;
-  hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, a, (const uint32_t*)nullptr,
-                                                  (uint32_t*)nullptr, (int)n + 1);
+  hipError_t e = rocprim::exclusive_scan(nullptr, a, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                         0u, (size_t)n + 1, rocprim::plus<uint32_t>());
   if (e != hipSuccess) return e;
-  e = hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                         (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)n, 0, 32);
+  e = rocprim::radix_sort_pairs(nullptr, b, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)n, 0u, 32u);
   *bytes = std::max(a, b);
   return e;
 }
@@ -237,7 +238,8 @@ hipError_t levelize_run(const LvBuffers& B, uint32_t n_slots, uint32_t n, uint32
   LV_TRY(hipGetLastError());
   // 3. consumer lists.
   size_t tb = B.temp_bytes;
-  LV_TRY(hipcub::DeviceScan::ExclusiveSum(B.temp, tb, B.outdeg, B.out_ptr, (int)n + 1, s));
+  LV_TRY(rocprim::exclusive_scan(B.temp, tb, B.outdeg, B.out_ptr, 0u, (size_t)n + 1,
+                                 rocprim::plus<uint32_t>(), s));
   hipLaunchKernelGGL(k_lv_consumers, dim3(blocks_for(n)), dim3(kBlock), 0, s, B.src_ptr, B.src,
                      B.producer, n, B.out_ptr, B.cursor, B.out_idx);
   LV_TRY(hipGetLastError());
@@ -277,8 +279,8 @@ hipError_t levelize_run(const LvBuffers& B, uint32_t n_slots, uint32_t n, uint32
   // 5. order and layer ranges.
   hipLaunchKernelGGL(k_lv_iota, dim3(blocks_for(n)), dim3(kBlock), 0, s, B.vals_in, n);
   tb = B.temp_bytes;
-  LV_TRY(hipcub::DeviceRadixSort::SortPairs(B.temp, tb, B.layer, B.keys_out, B.vals_in, B.order,
-                                            (int)n, 0, (int)bits_for(L - 1), s));
+  LV_TRY(rocprim::radix_sort_pairs(B.temp, tb, B.layer, B.keys_out, B.vals_in, B.order, (size_t)n,
+                                   0u, bits_for(L - 1), s));
   hipLaunchKernelGGL(k_lv_bounds, dim3(blocks_for(n)), dim3(kBlock), 0, s, B.keys_out, n,
                      B.layer_ptr);
   hipLaunchKernelGGL(k_lv_fill, dim3(1), dim3(kBlock), 0, s, B.layer_ptr + L, n, (uint64_t)1);

@@ -1243,7 +1243,10 @@ rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
         g.split = (n1 + opw - 1) / opw;
         g.n_groups = T / b->tg;
         ok = ok && add(t, 0, b->tg, g, (uint64_t)(g.split + (n2 + opw - 1) / opw) * g.n_groups);
-        const uint32_t th = std::min(b->tg, 2u);
+        // Heavy pieces take one tile per wavefront when the batch's tile
+        // group is at most 2, so that a layer index stays within the lean
+        // mixed variants.
+        const uint32_t th = b->tg <= 2 ? 1u : 2u;
         const uint32_t h1 = ly.hm0 - ly.hbeg, h2 = ly.hend - ly.hm1;
         g.n_groups = T / th;
         ok = ok && add(t, 1, th, g,
@@ -1282,13 +1285,14 @@ rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
   for (auto& v : slots) {
     if (v.size() < 2) continue;
     uint64_t waves = 0;
-    bool ok = true;
+    bool ok = true, lean = true;
     for (const Launch& l : v) {
       waves += l.wave0.back();
       ok = ok && multi_mixable(l.kind, l.tg);
+      lean = lean && multi_lean(l.kind, l.tg);
     }
     if (!ok || waves > ctx->mixed_max_waves) continue;
-    Launch m{4u, 0u, {}, {0u}, 0};
+    Launch m{lean ? 5u : 4u, 0u, {}, {0u}, 0};
     for (const Launch& l : v) {
       const uint32_t lg = l.tg >= 4 ? 2u : l.tg >= 2 ? 1u : 0u;
       for (size_t k = 0; k < l.segs.size(); ++k) {
@@ -1308,10 +1312,12 @@ rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
     bytes = (bytes + n + 255) & ~size_t(255);
     return o;
   };
+  // Per launch: the segments, then the prefix wave0 and the segment of
+  // every wavefront after it.
   for (auto& v : slots)
     for (auto& l : v) {
       l.off = place(l.segs.size() * sizeof(MultiSeg));
-      place(l.wave0.size() * 4);
+      place((l.wave0.size() + l.wave0.back()) * 4);
     }
   const size_t doff = place(dsegs.size() * sizeof(DigestSeg));
   const size_t dwoff = place(dwave0.size() * 4);
@@ -1321,6 +1327,9 @@ rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
       memcpy(host.data() + l.off, l.segs.data(), l.segs.size() * sizeof(MultiSeg));
       const size_t woff = (l.off + l.segs.size() * sizeof(MultiSeg) + 255) & ~size_t(255);
       memcpy(host.data() + woff, l.wave0.data(), l.wave0.size() * 4);
+      uint32_t* seg_of = (uint32_t*)(host.data() + woff) + l.wave0.size();
+      for (uint32_t k = 0; k + 1 < l.wave0.size(); ++k)
+        for (uint32_t w = l.wave0[k]; w < l.wave0[k + 1]; ++w) seg_of[w] = k;
     }
   memcpy(host.data() + doff, dsegs.data(), dsegs.size() * sizeof(DigestSeg));
   memcpy(host.data() + dwoff, dwave0.data(), dwave0.size() * 4);

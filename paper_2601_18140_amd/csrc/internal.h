@@ -296,13 +296,16 @@ uint32_t partitioned_capacity(uint32_t block, bool lds_state, size_t lds);
 
 // Launches over several batches: segs[0 .. n_seg) and wave0[0 .. n_seg] in
 // device memory, wave0 the prefix of the segments' wavefronts (n_waves =
-// wave0[n_seg]).  kind 0: SWEEP common operations (tile group tg: 1, 2, 4,
+// wave0[n_seg]), followed by the segment of every wavefront
+// (wave0[n_seg + 1 + w], w < n_waves).  kind 0: SWEEP common operations (tile group tg: 1, 2, 4,
 // 8 or 16), 1: SWEEP heavy (tg 1 or 2), 2: fused mux chains (tg 1, 2 or 4),
 // 3: LAYERED (tg ignored), 4: mixed, each segment of its own kind and tile
 // group (its variant; common operations with tile groups up to 4), so that
 // the small pieces of one layer index need one launch instead of one per
-// kind and tile group.
+// kind and tile group; 5: the same for the variants of small register
+// footprint only (multi_lean).
 bool multi_mixable(uint32_t kind, uint32_t tg);
+bool multi_lean(uint32_t kind, uint32_t tg);
 hipError_t launch_multi(uint32_t kind, uint32_t tg, const MultiSeg* segs, const uint32_t* wave0,
                         uint32_t n_seg, uint64_t n_waves, hipStream_t s);
 // Register digest of several batches, then their folds and cycle advance

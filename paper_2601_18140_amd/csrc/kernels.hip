@@ -1154,8 +1154,10 @@ k_sweep_heavy(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers
 // Several batches in one launch (rteaal_step_many): a table of segments, each
 // a piece of one batch's layer (its operation ranges, launch shape and
 // state), the launch's wavefronts split among them by the prefix wave0.
-// Every wavefront finds its segment by a binary search over wave0 (wave-
-// uniform scalar loads) and runs the same body as the per-batch kernels.
+// The segment launches also carry, after wave0's n_seg + 1 entries, the
+// segment of every wavefront, so a wavefront finds its segment with one
+// scalar load (the digest launch searches wave0 instead) and runs the same
+// body as the per-batch kernels.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t find_seg(const uint32_t* __restrict__ wave0, uint32_t n_seg,
                                              uint32_t wave) {
@@ -1175,7 +1177,7 @@ k_sweep_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wa
   const uint32_t wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   if (wave >= wave0[n_seg]) return;
-  const uint32_t k = find_seg(wave0, n_seg, wave);
+  const uint32_t k = wave0[n_seg + 1u + wave];
   const MultiSeg& g = segs[k];
   sweep_wave<1, TG, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, wave - wave0[k],
                        threadIdx.x & 63u);
@@ -1188,7 +1190,7 @@ k_sweep_heavy_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restric
   const uint32_t wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   if (wave >= wave0[n_seg]) return;
-  const uint32_t k = find_seg(wave0, n_seg, wave);
+  const uint32_t k = wave0[n_seg + 1u + wave];
   const MultiSeg& g = segs[k];
   heavy_wave<TG>(g.ops, g.layers[g.layer], g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
                  g.ctl, g.n_inst, g.opw, 0u, g.n_groups, wave - wave0[k], threadIdx.x & 63u);
@@ -1201,7 +1203,7 @@ k_sweep_muxc_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict
   const uint32_t wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   if (wave >= wave0[n_seg]) return;
-  const uint32_t k = find_seg(wave0, n_seg, wave);
+  const uint32_t k = wave0[n_seg + 1u + wave];
   const MultiSeg& g = segs[k];
   muxc_wave<TG>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups,
                 wave - wave0[k], threadIdx.x & 63u);
@@ -1226,39 +1228,52 @@ k_layer_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wa
               uint32_t n_seg) {
   const uint32_t wave = blockIdx.x;
   if (wave >= wave0[n_seg]) return;
-  const uint32_t k = find_seg(wave0, n_seg, wave);
+  const uint32_t k = wave0[n_seg + 1u + wave];
   layer_wave(segs[k], wave - wave0[k], threadIdx.x);
 }
 
 // Mixed launch: every segment names its own kind and tile group (variant);
-// the branch on it is uniform over the wavefront.
+// the branch on it is uniform over the wavefront.  LEAN holds only the
+// variants of small register footprint (common operations with 1 or 2
+// tiles, heavy operations with 1, LAYERED), so that its wavefronts still
+// find room beside long-running RESIDENT workgroups on a compute unit.
+template <bool LEAN>
 __global__ void __launch_bounds__(256)
 k_mixed_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wave0,
               uint32_t n_seg) {
   const uint32_t wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   if (wave >= wave0[n_seg]) return;
-  const uint32_t k = find_seg(wave0, n_seg, wave);
+  const uint32_t k = wave0[n_seg + 1u + wave];
   const MultiSeg& g = segs[k];
   const uint32_t local = wave - wave0[k], lane = threadIdx.x & 63u;
-  switch (__builtin_amdgcn_readfirstlane(g.variant)) {
-    case 0: sweep_wave<1, 1, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, local, lane); break;
-    case 1: sweep_wave<1, 2, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, local, lane); break;
-    case 2: sweep_wave<1, 4, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, local, lane); break;
-    case 8:
-      heavy_wave<1>(g.ops, g.layers[g.layer], g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
-                    g.ctl, g.n_inst, g.opw, 0u, g.n_groups, local, lane);
-      break;
-    case 9:
-      heavy_wave<2>(g.ops, g.layers[g.layer], g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
-                    g.ctl, g.n_inst, g.opw, 0u, g.n_groups, local, lane);
-      break;
-    case 16: muxc_wave<1>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
-    case 17: muxc_wave<2>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
-    case 18: muxc_wave<4>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
-    case 24: layer_wave(g, local, lane); break;
-    default: break;
+  const uint32_t v = __builtin_amdgcn_readfirstlane(g.variant);
+  if (v == 0) {
+    sweep_wave<1, 1, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, local, lane);
+  } else if (v == 1) {
+    sweep_wave<1, 2, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, local, lane);
+  } else if (v == 8) {
+    heavy_wave<1>(g.ops, g.layers[g.layer], g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
+                  g.ctl, g.n_inst, g.opw, 0u, g.n_groups, local, lane);
+  } else if (v == 24) {
+    layer_wave(g, local, lane);
+  } else if (!LEAN) {
+    switch (v) {
+      case 2: sweep_wave<1, 4, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, local, lane); break;
+      case 9:
+        heavy_wave<2>(g.ops, g.layers[g.layer], g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
+                      g.ctl, g.n_inst, g.opw, 0u, g.n_groups, local, lane);
+        break;
+      case 16: muxc_wave<1>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
+      case 17: muxc_wave<2>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
+      case 18: muxc_wave<4>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
+      default: break;
+    }
   }
+}
+
+bool multi_lean(uint32_t kind, uint32_t tg) {
+  return (kind == 0 && tg <= 2) || (kind == 1 && tg == 1) || kind == 3;
 }
 
 bool multi_mixable(uint32_t kind, uint32_t tg) {
@@ -1922,9 +1937,10 @@ hipError_t launch_multi(uint32_t kind, uint32_t tg, const MultiSeg* segs, const 
                         uint32_t n_seg, uint64_t n_waves, hipStream_t s) {
   if (n_seg == 0 || n_waves == 0) return hipSuccess;
   if (n_waves >= (1ull << 32)) return hipErrorInvalidValue;
-  if (kind == 4) {
-    hipLaunchKernelGGL(k_mixed_multi, dim3((uint32_t)((n_waves + 3) / 4)), dim3(256), 0, s, segs,
-                       wave0, n_seg);
+  if (kind == 4 || kind == 5) {
+    const dim3 grid((uint32_t)((n_waves + 3) / 4)), blk(256);
+    if (kind == 5) hipLaunchKernelGGL(k_mixed_multi<true>, grid, blk, 0, s, segs, wave0, n_seg);
+    else hipLaunchKernelGGL(k_mixed_multi<false>, grid, blk, 0, s, segs, wave0, n_seg);
     return hipGetLastError();
   }
   if (kind == 3) {

@@ -348,13 +348,23 @@ void digest_shape(bool sweep, uint32_t n_regs, uint32_t n_inst, uint32_t* n_unit
 bool multi_mixable(uint32_t kind, uint32_t tg) {
   return kind == 3 || ((kind == 0 || kind == 2) && tg <= 4) || (kind == 1 && tg <= 2);
 }
+bool multi_lean(uint32_t kind, uint32_t tg) {
+  return (kind == 0 && tg <= 2) || (kind == 1 && tg == 1) || kind == 3;
+}
 hipError_t launch_multi(uint32_t kind, uint32_t, const MultiSeg* segs, const uint32_t* wave0,
                         uint32_t n_seg, uint64_t n_waves, hipStream_t s) {
   launched(s, {segs, wave0, segs + n_seg - 1, wave0 + n_seg});
   if (wave0[n_seg] != n_waves) die("segment prefix does not match the wave count", wave0);
+  copy_check(wave0, (n_seg + 1 + n_waves) * 4);  // the per-wavefront segment table follows
+  for (uint64_t w = 0; w < n_waves; ++w) {
+    const uint32_t k = wave0[n_seg + 1 + w];
+    if (k >= n_seg || w < wave0[k] || w >= wave0[k + 1]) die("wavefront segment table", &wave0[n_seg + 1 + w]);
+  }
   for (uint32_t k = 0; k < n_seg; ++k) {
     if (kind == 4 && !multi_mixable(segs[k].variant / 8, 1u << (segs[k].variant % 8)))
       die("mixed segment of an unknown variant", &segs[k]);
+    if (kind == 5 && !multi_lean(segs[k].variant / 8, 1u << (segs[k].variant % 8)))
+      die("lean mixed segment of a variant outside the lean set", &segs[k]);
     launched(s, {segs[k].ops, segs[k].layers, segs[k].const_limbs, segs[k].state, segs[k].seeds,
                  segs[k].ctl});
     if (wave0[k + 1] <= wave0[k]) die("empty or decreasing segment", &wave0[k]);

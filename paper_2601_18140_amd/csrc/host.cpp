@@ -1228,6 +1228,7 @@ rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
     base.n_inst = b->n_inst;
     base.words_per_inst = h.words_per_inst;
     base.opw = b->opw ? b->opw : 16u;
+    base.unroll = b->unroll ? b->unroll : 1u;
     const bool sweep = b->mapping == RTEAAL_MAP_SWEEP;
     const uint32_t T = b->L.n_tiles_alloc;
     for (uint32_t li = 0; li < Lb; ++li) {
@@ -1248,6 +1249,7 @@ rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
         // mixed variants.
         const uint32_t th = b->tg <= 2 ? 1u : 2u;
         const uint32_t h1 = ly.hm0 - ly.hbeg, h2 = ly.hend - ly.hm1;
+        g.r = OpRanges{ly.hbeg, ly.hm0, ly.hm1, ly.hend};  // the heavy range (see MultiSeg)
         g.n_groups = T / th;
         ok = ok && add(t, 1, th, g,
                        (uint64_t)((h1 + opw - 1) / opw + (h2 + opw - 1) / opw) * g.n_groups);
@@ -1294,10 +1296,9 @@ rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
     if (!ok || waves > ctx->mixed_max_waves) continue;
     Launch m{lean ? 5u : 4u, 0u, {}, {0u}, 0};
     for (const Launch& l : v) {
-      const uint32_t lg = l.tg >= 4 ? 2u : l.tg >= 2 ? 1u : 0u;
       for (size_t k = 0; k < l.segs.size(); ++k) {
         MultiSeg x = l.segs[k];
-        x.variant = l.kind * 8u + lg;
+        x.variant = multi_variant(l.kind, l.tg, x.unroll, lean);
         m.segs.push_back(x);
         m.wave0.push_back(m.wave0.back() + (l.wave0[k + 1] - l.wave0[k]));
       }
@@ -3107,7 +3108,7 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
   // Trial length: about 4e9 op-evaluations per policy, 2..32 cycles.
   const uint64_t cyc = trial_cycles ? trial_cycles
                                     : (uint64_t)std::max(2.0, std::min(32.0, 4e9 / std::max<double>((double)total, 1.0)));
-  std::string key = "joint|o11r16|" + device_tag(ctx->device);
+  std::string key = "joint|o11s18|" + device_tag(ctx->device);
   {
     uint64_t fp = 1469598103934665603ull;
     for (uint32_t k = 0; k < n; ++k) {
@@ -3137,19 +3138,21 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
     // kept only for designs whose state and program records both fit a
     // workgroup's LDS (the records then are read from HBM once per launch,
     // not once per instance and cycle); the others run SWEEP.
+    // unroll: SWEEP batches' operations in flight per wavefront.
     struct Policy {
-      uint32_t sweep_min, tg_cap, layered_ops, opw, res_block, sweep_ops, lds_only;
+      uint32_t sweep_min, tg_cap, layered_ops, opw, res_block, sweep_ops, lds_only, unroll;
     };
     constexpr uint32_t kNever = UINT32_MAX;
     const Policy pol[] = {
-        {16, 4, kNever, 8, 0, kNever, 0},     {16, 4, 100000, 8, 0, kNever, 0},
-        {48, 4, 100000, 8, 0, kNever, 0},     {48, 2, kNever, 8, 0, kNever, 0},
-        {48, 2, kNever, 2, 0, kNever, 0},     {48, 2, kNever, 4, 0, kNever, 0},
-        {96, 2, kNever, 2, 0, kNever, 0},     {kNever, 1, kNever, 8, 0, kNever, 0},
-        {48, 2, kNever, 4, 256, kNever, 0},   {48, 2, kNever, 2, 256, kNever, 0},
-        {48, 2, kNever, 4, 256, 150000, 0},   {48, 2, 100000, 4, 256, kNever, 0},
-        {48, 2, kNever, 4, 256, kNever, 1},   {48, 2, kNever, 2, 0, kNever, 1},
-        {96, 2, kNever, 4, 256, kNever, 1},   {kNever, 2, kNever, 4, 256, kNever, 1}};
+        {16, 4, kNever, 8, 0, kNever, 0, 1},     {48, 4, 100000, 8, 0, kNever, 0, 1},
+        {48, 2, kNever, 8, 0, kNever, 0, 1},     {48, 2, kNever, 2, 0, kNever, 0, 1},
+        {48, 2, kNever, 4, 0, kNever, 0, 1},     {96, 2, kNever, 2, 0, kNever, 0, 1},
+        {kNever, 1, kNever, 8, 0, kNever, 0, 1}, {48, 2, kNever, 4, 256, kNever, 0, 1},
+        {48, 2, 100000, 4, 256, kNever, 0, 1},   {48, 2, kNever, 4, 256, kNever, 1, 1},
+        {48, 2, kNever, 4, 0, kNever, 0, 2},     {48, 2, kNever, 8, 0, kNever, 0, 2},
+        {48, 2, kNever, 8, 0, kNever, 0, 4},     {48, 2, kNever, 16, 0, kNever, 0, 4},
+        {32, 2, kNever, 8, 0, kNever, 0, 2},     {96, 2, kNever, 8, 0, kNever, 0, 2},
+        {48, 2, kNever, 8, 256, kNever, 0, 2},   {48, 2, kNever, 8, 0, kNever, 1, 2}};
     auto opts_of = [&](const Policy& p, uint32_t k) {
       rteaal_batch_opts o{};
       const uint32_t ni = n_inst[k];
@@ -3167,7 +3170,7 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
         while (tg * 2 <= std::min(tiles, p.tg_cap)) tg *= 2;
         o.mapping = RTEAAL_MAP_SWEEP;
         o.ops_per_wave = p.opw;
-        o.unroll = 1;
+        o.unroll = p.unroll;
         o.tiles_per_wave = tg;
       } else if (hs[k]->ops.size() >= p.layered_ops && ni <= 65535) {
         o.mapping = RTEAAL_MAP_LAYERED;
@@ -3228,10 +3231,10 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
       if (st != RTEAAL_OK) break;
       if (log)
         std::fprintf(stderr, "rteaal_autotune_many: sweep from %u instances or %u ops%s, tile "
-                     "groups up to %u, %u ops per wavefront, LAYERED from %u ops, RESIDENT blocks "
-                     "up to %u -> %.4g\n", p.sweep_min, p.sweep_ops,
-                     p.lds_only ? " or records beyond LDS" : "", p.tg_cap, p.opw, p.layered_ops,
-                     p.res_block, r);
+                     "groups up to %u, %u ops per wavefront, unroll %u, LAYERED from %u ops, "
+                     "RESIDENT blocks up to %u -> %.4g\n", p.sweep_min, p.sweep_ops,
+                     p.lds_only ? " or records beyond LDS" : "", p.tg_cap, p.opw, p.unroll,
+                     p.layered_ops, p.res_block, r);
       if (r > best_rate) {
         best_rate = r;
         chosen = os;

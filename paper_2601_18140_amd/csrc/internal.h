@@ -184,9 +184,11 @@ struct ResJob {
 // of one batch's layer.  SWEEP common operations: the ranges r in chunks of
 // opw operations (split: chunks in [b0, e0)) times n_groups tile groups;
 // SWEEP heavy operations and fused mux chains: those of layer `layer` in the
-// same way; LAYERED: layer `layer`, n_groups wavefronts of 64 positions per
-// instance.  variant (mixed launches only): kind x 8 + log2(tile group), the
-// kinds as in launch_multi.
+// same way, r then holding the layer's (hbeg, hm0, hm1, hend); LAYERED: layer `layer`, n_groups wavefronts of 64 positions per
+// instance.  variant (mixed launches only, multi_variant): kind x 8 +
+// log2(tile group) + 64 x log2(unroll depth of common operations), the kinds
+// as in launch_multi.  unroll: the batch's unroll depth (mixed launches run
+// common operations with it; the other multi-batch launches with 1).
 struct MultiSeg {
   const DevOp* ops;
   const DevLayer* layers;
@@ -196,7 +198,7 @@ struct MultiSeg {
   const DevCtl* ctl;
   StateLayout L;
   OpRanges r;
-  uint32_t layer, n_inst, words_per_inst, opw, split, n_groups, variant, pad;
+  uint32_t layer, n_inst, words_per_inst, opw, split, n_groups, variant, unroll;
 };
 static_assert(sizeof(MultiSeg) == 128, "MultiSeg layout");
 
@@ -306,6 +308,7 @@ uint32_t partitioned_capacity(uint32_t block, bool lds_state, size_t lds);
 // footprint only (multi_lean).
 bool multi_mixable(uint32_t kind, uint32_t tg);
 bool multi_lean(uint32_t kind, uint32_t tg);
+uint32_t multi_variant(uint32_t kind, uint32_t tg, uint32_t unroll, bool lean);
 hipError_t launch_multi(uint32_t kind, uint32_t tg, const MultiSeg* segs, const uint32_t* wave0,
                         uint32_t n_seg, uint64_t n_waves, hipStream_t s);
 // Register digest of several batches, then their folds and cycle advance

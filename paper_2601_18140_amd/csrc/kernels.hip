@@ -1183,6 +1183,17 @@ k_sweep_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wa
                        threadIdx.x & 63u);
 }
 
+// Heavy and mux-chain segments carry their layer's heavy range in r
+// (hbeg, hm0, hm1, hend), so a wavefront needs no load of the layer record.
+__device__ __forceinline__ DevLayer seg_heavy_range(const MultiSeg& g) {
+  DevLayer ly{};
+  ly.hbeg = g.r.b0;
+  ly.hm0 = g.r.e0;
+  ly.hm1 = g.r.b1;
+  ly.hend = g.r.e1;
+  return ly;
+}
+
 template <int TG>
 __global__ void __launch_bounds__(256)
 k_sweep_heavy_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wave0,
@@ -1192,7 +1203,7 @@ k_sweep_heavy_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restric
   if (wave >= wave0[n_seg]) return;
   const uint32_t k = wave0[n_seg + 1u + wave];
   const MultiSeg& g = segs[k];
-  heavy_wave<TG>(g.ops, g.layers[g.layer], g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
+  heavy_wave<TG>(g.ops, seg_heavy_range(g), g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
                  g.ctl, g.n_inst, g.opw, 0u, g.n_groups, wave - wave0[k], threadIdx.x & 63u);
 }
 
@@ -1205,7 +1216,7 @@ k_sweep_muxc_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict
   if (wave >= wave0[n_seg]) return;
   const uint32_t k = wave0[n_seg + 1u + wave];
   const MultiSeg& g = segs[k];
-  muxc_wave<TG>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups,
+  muxc_wave<TG>(g.ops, seg_heavy_range(g), g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups,
                 wave - wave0[k], threadIdx.x & 63u);
 }
 
@@ -1248,32 +1259,55 @@ k_mixed_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wa
   const MultiSeg& g = segs[k];
   const uint32_t local = wave - wave0[k], lane = threadIdx.x & 63u;
   const uint32_t v = __builtin_amdgcn_readfirstlane(g.variant);
+#define RTEAAL_MIX_SWEEP(U, TG) \
+  sweep_wave<U, TG, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, local, lane)
   if (v == 0) {
-    sweep_wave<1, 1, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, local, lane);
+    RTEAAL_MIX_SWEEP(1, 1);
   } else if (v == 1) {
-    sweep_wave<1, 2, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, local, lane);
+    RTEAAL_MIX_SWEEP(1, 2);
+  } else if (v == 64) {
+    RTEAAL_MIX_SWEEP(2, 1);
+  } else if (v == 65) {
+    RTEAAL_MIX_SWEEP(2, 2);
+  } else if (v == 128) {
+    RTEAAL_MIX_SWEEP(4, 1);
   } else if (v == 8) {
-    heavy_wave<1>(g.ops, g.layers[g.layer], g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
+    heavy_wave<1>(g.ops, seg_heavy_range(g), g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
                   g.ctl, g.n_inst, g.opw, 0u, g.n_groups, local, lane);
   } else if (v == 24) {
     layer_wave(g, local, lane);
   } else if (!LEAN) {
     switch (v) {
-      case 2: sweep_wave<1, 4, 3>(g.ops, g.L, g.state, g.r, g.opw, g.split, 0u, g.n_groups, local, lane); break;
+      case 2: RTEAAL_MIX_SWEEP(1, 4); break;
+      case 66: RTEAAL_MIX_SWEEP(2, 4); break;
+      case 129: RTEAAL_MIX_SWEEP(4, 2); break;
       case 9:
-        heavy_wave<2>(g.ops, g.layers[g.layer], g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
+        heavy_wave<2>(g.ops, seg_heavy_range(g), g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
                       g.ctl, g.n_inst, g.opw, 0u, g.n_groups, local, lane);
         break;
-      case 16: muxc_wave<1>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
-      case 17: muxc_wave<2>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
-      case 18: muxc_wave<4>(g.ops, g.layers[g.layer], g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
+      case 16: muxc_wave<1>(g.ops, seg_heavy_range(g), g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
+      case 17: muxc_wave<2>(g.ops, seg_heavy_range(g), g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
+      case 18: muxc_wave<4>(g.ops, seg_heavy_range(g), g.const_limbs, g.L, g.state, 1u, 0u, g.n_groups, local, lane); break;
       default: break;
     }
   }
+#undef RTEAAL_MIX_SWEEP
 }
 
 bool multi_lean(uint32_t kind, uint32_t tg) {
   return (kind == 0 && tg <= 2) || (kind == 1 && tg == 1) || kind == 3;
+}
+
+uint32_t multi_variant(uint32_t kind, uint32_t tg, uint32_t unroll, bool lean) {
+  const uint32_t lg = tg >= 4 ? 2u : tg >= 2 ? 1u : 0u;
+  uint32_t lu = 0;
+  if (kind == 0) {  // common operations may keep their batch's unroll depth
+    if (unroll == 2 && tg <= 4) lu = 1;
+    if (unroll == 4 && tg <= 2) lu = 2;
+    if (lean && lu == 1 && tg > 2) lu = 0;
+    if (lean && lu == 2 && tg > 1) lu = 1;  // the lean kernel runs 4 in flight on one tile only
+  }
+  return kind * 8u + lg + 64u * lu;
 }
 
 bool multi_mixable(uint32_t kind, uint32_t tg) {

@@ -351,6 +351,17 @@ bool multi_mixable(uint32_t kind, uint32_t tg) {
 bool multi_lean(uint32_t kind, uint32_t tg) {
   return (kind == 0 && tg <= 2) || (kind == 1 && tg == 1) || kind == 3;
 }
+uint32_t multi_variant(uint32_t kind, uint32_t tg, uint32_t unroll, bool lean) {
+  const uint32_t lg = tg >= 4 ? 2u : tg >= 2 ? 1u : 0u;
+  uint32_t lu = 0;
+  if (kind == 0) {
+    if (unroll == 2 && tg <= 4) lu = 1;
+    if (unroll == 4 && tg <= 2) lu = 2;
+    if (lean && lu == 1 && tg > 2) lu = 0;
+    if (lean && lu == 2 && tg > 1) lu = 1;  // the lean kernel runs 4 in flight on one tile only
+  }
+  return kind * 8u + lg + 64u * lu;
+}
 hipError_t launch_multi(uint32_t kind, uint32_t, const MultiSeg* segs, const uint32_t* wave0,
                         uint32_t n_seg, uint64_t n_waves, hipStream_t s) {
   launched(s, {segs, wave0, segs + n_seg - 1, wave0 + n_seg});
@@ -361,9 +372,12 @@ hipError_t launch_multi(uint32_t kind, uint32_t, const MultiSeg* segs, const uin
     if (k >= n_seg || w < wave0[k] || w >= wave0[k + 1]) die("wavefront segment table", &wave0[n_seg + 1 + w]);
   }
   for (uint32_t k = 0; k < n_seg; ++k) {
-    if (kind == 4 && !multi_mixable(segs[k].variant / 8, 1u << (segs[k].variant % 8)))
-      die("mixed segment of an unknown variant", &segs[k]);
-    if (kind == 5 && !multi_lean(segs[k].variant / 8, 1u << (segs[k].variant % 8)))
+    const uint32_t vk = (segs[k].variant % 64) / 8, vt = 1u << (segs[k].variant % 8);
+    const uint32_t vu = 1u << (segs[k].variant / 64);
+    if ((kind == 4 || kind == 5) && vu > 1 && (vk != 0 || vu > 4 || (vu == 4 && vt > 2) || vt > 4))
+      die("mixed segment with an unroll depth outside the kernel's variants", &segs[k]);
+    if (kind == 4 && !multi_mixable(vk, vt)) die("mixed segment of an unknown variant", &segs[k]);
+    if (kind == 5 && (!multi_lean(vk, vt) || (vu == 2 && vt > 2) || (vu == 4 && vt > 1)))
       die("lean mixed segment of a variant outside the lean set", &segs[k]);
     launched(s, {segs[k].ops, segs[k].layers, segs[k].const_limbs, segs[k].state, segs[k].seeds,
                  segs[k].ctl});

@@ -63,6 +63,9 @@ SHAPES = [dict(mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=1),
           dict(mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=4, unroll=1),
           dict(mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=8, unroll=1, ops_per_wave=5),
           dict(mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=16, unroll=1),
+          dict(mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=1, unroll=4, ops_per_wave=7),
+          dict(mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=4, unroll=2),
+          dict(mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=2, unroll=4, ops_per_wave=9),
           dict(mapping=R.RTEAAL_MAP_LAYERED),
           dict(mapping=R.RTEAAL_MAP_LAYERED, block_threads=128, unroll=2),
           dict(mapping=R.RTEAAL_MAP_RESIDENT)]

@@ -94,8 +94,16 @@ struct rteaal_ctx {
   size_t max_lds = 0;
   // rteaal_step_many: auxiliary streams (default priority) for SWEEP batches,
   // fork/join events, and a grow-only device scratch for job tables.
-  hipStream_t aux[4] = {nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t fork = nullptr, join[4] = {nullptr, nullptr, nullptr, nullptr};
+  // Auxiliary streams of rteaal_step_many: 0..3 for captured multi-batch
+  // cycles (one chain each) and batches stepped alone, 4..7 for RESIDENT
+  // configurations beyond the first.
+  static constexpr int kAux = 8;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t fork = nullptr, join[kAux] = {};
+  // Captured multi-batch cycles per call: SWEEP and LAYERED batches split by
+  // layer count into this many independent chains (environment
+  // RTEAAL_MULTI_CHAINS, 1..4).
+  uint32_t multi_chains = 1;
   // Streams and events that only serve graph capture: the launches of one
   // layer fork onto them, so the captured graph runs them concurrently.
   hipStream_t cap[3] = {nullptr, nullptr, nullptr};
@@ -1668,6 +1676,8 @@ rteaal_status rteaal_create(int device, void* stream, const rteaal_allocator* al
   }
   if (const char* sl = std::getenv("RTEAAL_GRID_SPIN_LIMIT"))
     ctx->spin_limit = (uint32_t)std::max(1L, std::min(std::atol(sl), (long)UINT32_MAX));
+  if (const char* mc = std::getenv("RTEAAL_MULTI_CHAINS"))
+    ctx->multi_chains = (uint32_t)std::max(1L, std::min(std::atol(mc), 4L));
   if (const char* mw = std::getenv("RTEAAL_MIXED_MAX_WAVES"))
     ctx->mixed_max_waves = (uint32_t)std::max(0L, std::min(std::atol(mw), (long)UINT32_MAX));
   ctx->scratch = scratch_on(device);
@@ -1709,7 +1719,7 @@ void rteaal_destroy(rteaal_ctx* ctx) {
   }
   dev_free(ctx, ctx->multi);
   while (!ctx->mgraphs.empty()) drop_multi_graph(ctx, ctx->mgraphs.size() - 1);
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < rteaal_ctx::kAux; ++k) {
     if (ctx->aux[k]) (void)hipStreamDestroy(ctx->aux[k]);
     if (ctx->join[k]) (void)hipEventDestroy(ctx->join[k]);
   }
@@ -2366,13 +2376,14 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
   // context stream on every exit path, so that nothing the step enqueued
   // outlives a later wait on the context stream.
   std::vector<Mem> tmps(n);
-  uint32_t n_forked = 0;
+  uint32_t forked = 0;  // bit a: auxiliary stream a has forked in this call
   struct Finish {
     rteaal_ctx* ctx;
     std::vector<Mem>& tmps;
-    uint32_t& n_forked;
+    uint32_t& forked;
     ~Finish() {
-      for (uint32_t a = 0; a < n_forked; ++a) {
+      for (int a = 0; a < rteaal_ctx::kAux; ++a) {
+        if (!(forked >> a & 1u)) continue;
         if (hipEventRecord(ctx->join[a], ctx->aux[a]) != hipSuccess ||
             hipStreamWaitEvent(ctx->stream, ctx->join[a], 0) != hipSuccess)
           (void)hipStreamSynchronize(ctx->aux[a]);
@@ -2384,7 +2395,7 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
         for (Mem& m : tmps) dev_free(ctx, m);
       }
     }
-  } finish{ctx, tmps, n_forked};
+  } finish{ctx, tmps, forked};
   for (uint32_t k = 0; k < n; ++k) {
     const uint64_t* words = nullptr;
     const rteaal_status st = stimulus_words(ctx, *find_design(ctx, bs[k]->design), *bs[k],
@@ -2409,65 +2420,125 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
     else if (!b.n_watch && !b.profile && b.tpp == 0) multi.push_back(k);
     else single.push_back(k);
   }
-  if (multi.size() == 1) {
-    single.push_back(multi[0]);
-    multi.clear();
-  }
-  std::vector<std::pair<MultiGraph*, uint64_t>> replays;  // graph, cycles
-  int tail = -1;  // a batch left alone for the last cycles, after the replays
-  uint64_t tail_cycles = 0;
+  // Chains: the batches sorted by layer count and cut into contiguous groups
+  // of about equal work (operations x instances), each stepped through its
+  // own captured cycles on its own stream, so a group of shallow designs
+  // does not wait at the layer indices of the deepest.
+  std::vector<std::vector<uint32_t>> chain_ks;
   {
-    std::vector<uint64_t> counts;
-    for (uint32_t k : multi) counts.push_back(n_cycles[k]);
-    std::sort(counts.begin(), counts.end());
-    counts.erase(std::unique(counts.begin(), counts.end()), counts.end());
+    const uint32_t C = std::min<uint32_t>(ctx->multi_chains, (uint32_t)(multi.size() / 2));
+    if (C <= 1) {
+      if (!multi.empty()) chain_ks.push_back(multi);
+    } else {
+      auto layers_of = [&](uint32_t k) { return find_design(ctx, bs[k]->design)->layers.size(); };
+      auto work_of = [&](uint32_t k) {
+        return (double)find_design(ctx, bs[k]->design)->ops.size() * bs[k]->n_inst;
+      };
+      std::vector<uint32_t> ord = multi;
+      std::stable_sort(ord.begin(), ord.end(),
+                       [&](uint32_t x, uint32_t y) { return layers_of(x) < layers_of(y); });
+      double total = 0;
+      for (uint32_t k : ord) total += work_of(k);
+      double acc = 0;
+      chain_ks.emplace_back();
+      for (uint32_t k : ord) {
+        if (acc >= total * chain_ks.size() / C && chain_ks.size() < C && chain_ks.back().size() >= 2)
+          chain_ks.emplace_back();
+        chain_ks.back().push_back(k);
+        acc += work_of(k);
+      }
+      if (chain_ks.size() > 1 && chain_ks.back().size() < 2) {  // a lone last batch joins the one before
+        const uint32_t k = chain_ks.back()[0];
+        chain_ks.pop_back();
+        chain_ks.back().push_back(k);
+      }
+    }
+  }
+  for (size_t c = 0; c < chain_ks.size();) {
+    if (chain_ks[c].size() == 1) {
+      single.push_back(chain_ks[c][0]);
+      chain_ks.erase(chain_ks.begin() + c);
+    } else {
+      ++c;
+    }
+  }
+  // Per chain: the replays (graph, cycles) of its phases and a batch left
+  // alone for the last cycles (tail), after the replays.
+  struct ChainPlan {
+    std::vector<std::pair<MultiGraph*, uint64_t>> replays;
+    int tail = -1;
+    uint64_t tail_cycles = 0;
+  };
+  std::vector<ChainPlan> chains(chain_ks.size());
+  {
     // The cache must hold every set of this call's phases; otherwise the
     // batches are stepped one by one (captured cycles are not evicted).
+    auto phases = [&](const std::vector<uint32_t>& ks) {
+      std::vector<uint64_t> counts;
+      for (uint32_t k : ks) counts.push_back(n_cycles[k]);
+      std::sort(counts.begin(), counts.end());
+      counts.erase(std::unique(counts.begin(), counts.end()), counts.end());
+      return counts;
+    };
     size_t need = 0;
-    for (uint64_t c : counts) {
-      std::vector<Batch*> set;
-      for (uint32_t k : multi)
-        if (n_cycles[k] >= c) set.push_back(bs[k]);
-      if (set.size() >= 2 && !cached_multi_graph(ctx, set)) ++need;
-    }
-    if (ctx->mgraphs.size() + need > kMaxMultiGraphs) {
-      single.insert(single.end(), multi.begin(), multi.end());
-      multi.clear();
-      counts.clear();
-    }
-    uint64_t prev = 0;
-    for (uint64_t c : counts) {
-      std::vector<Batch*> set;
-      int last = -1;
-      for (uint32_t k : multi)
-        if (n_cycles[k] >= c) {
-          set.push_back(bs[k]);
-          last = (int)k;
-        }
-      if (set.size() == 1) {
-        tail = last;
-        tail_cycles = n_cycles[last] - prev;
-        break;
+    for (const auto& ks : chain_ks)
+      for (uint64_t c : phases(ks)) {
+        std::vector<Batch*> set;
+        for (uint32_t k : ks)
+          if (n_cycles[k] >= c) set.push_back(bs[k]);
+        if (set.size() >= 2 && !cached_multi_graph(ctx, set)) ++need;
       }
-      MultiGraph* g = nullptr;
-      const rteaal_status st = multi_graph(ctx, set, &g);
-      if (st != RTEAAL_OK) return st;
-      replays.push_back({g, c - prev});
-      prev = c;
+    if (ctx->mgraphs.size() + need > kMaxMultiGraphs) {
+      for (const auto& ks : chain_ks) single.insert(single.end(), ks.begin(), ks.end());
+      chain_ks.clear();
+      chains.clear();
+    }
+    for (size_t ci = 0; ci < chain_ks.size(); ++ci) {
+      const auto& ks = chain_ks[ci];
+      ChainPlan& cp = chains[ci];
+      uint64_t prev = 0;
+      for (uint64_t c : phases(ks)) {
+        std::vector<Batch*> set;
+        int last = -1;
+        for (uint32_t k : ks)
+          if (n_cycles[k] >= c) {
+            set.push_back(bs[k]);
+            last = (int)k;
+          }
+        if (set.size() == 1) {
+          cp.tail = last;
+          cp.tail_cycles = n_cycles[last] - prev;
+          break;
+        }
+        MultiGraph* g = nullptr;
+        const rteaal_status st = multi_graph(ctx, set, &g);
+        if (st != RTEAAL_OK) return st;
+        cp.replays.push_back({g, c - prev});
+        prev = c;
+      }
     }
   }
+  // Forks auxiliary stream a from the context stream's current position.
   auto fork_aux = [&](uint32_t a) -> rteaal_status {
     if (!ctx->aux[a]) {
       HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->aux[a], hipStreamNonBlocking));
       HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->join[a], hipEventDisableTiming));
     }
     if (!ctx->fork) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
-    if (a >= n_forked) {
+    if (!(forked >> a & 1u)) {
       HIP_TRY(ctx, hipEventRecord(ctx->fork, ctx->stream));
       HIP_TRY(ctx, hipStreamWaitEvent(ctx->aux[a], ctx->fork, 0));
-      n_forked = a + 1;
+      forked |= 1u << a;
     }
     return RTEAAL_OK;
+  };
+  // Streams: chain c on auxiliary stream c; batches stepped alone on the
+  // streams after the chains (up to 3); RESIDENT configuration g >= 1 on
+  // stream 4 + (g - 1) mod 4.
+  const uint32_t n_chain_streams = (uint32_t)chains.size();
+  auto single_stream = [&](size_t j) {
+    const uint32_t first = std::min<uint32_t>(n_chain_streams, 3);
+    return first + (uint32_t)(j % (4 - first));
   };
   // Runs batch k alone for c cycles on auxiliary stream a.
   auto run_alone = [&](uint32_t k, uint64_t c, uint32_t a) -> rteaal_status {
@@ -2513,7 +2584,8 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
   std::vector<std::pair<Key, std::vector<uint32_t>>> groups(group_map.begin(), group_map.end());
   // Group g runs on the context stream (g = 0) or on auxiliary stream
   // 1 + (g - 1) mod 3, so that configurations run side by side.
-  auto group_stream = [&](size_t g) { return g == 0 ? ctx->stream : ctx->aux[1 + (g - 1) % 3]; };
+  auto group_aux = [&](size_t g) { return (uint32_t)(4 + (g - 1) % 4); };
+  auto group_stream = [&](size_t g) { return g == 0 ? ctx->stream : ctx->aux[group_aux(g)]; };
 
   // Every auxiliary stream this call uses forks here, before anything else
   // is enqueued, so that the captured cycles, the single batches and the
@@ -2521,12 +2593,15 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
   // submitting many cycle replays can block the host until the device has
   // run most of them.
   {
-    size_t n_needed = (replays.empty() ? 0 : 1) + single.size();
-    if (groups.size() > 1) n_needed = std::max<size_t>(n_needed, std::min<size_t>(groups.size(), 4));
-    for (uint32_t a = 0; a < std::min<size_t>(n_needed, 4); ++a) {
-      const rteaal_status st = fork_aux(a);
-      if (st != RTEAAL_OK) return st;
-    }
+    uint32_t want = 0;
+    for (uint32_t c = 0; c < n_chain_streams; ++c) want |= 1u << c;
+    for (size_t j = 0; j < single.size(); ++j) want |= 1u << single_stream(j);
+    for (size_t g = 1; g < groups.size(); ++g) want |= 1u << group_aux(g);
+    for (uint32_t a = 0; a < (uint32_t)rteaal_ctx::kAux; ++a)
+      if (want >> a & 1u) {
+        const rteaal_status st = fork_aux(a);
+        if (st != RTEAAL_OK) return st;
+      }
   }
   // Job tables: one region of the context's table buffer per group (its
   // first chunk is its largest), so that groups on different streams never
@@ -2590,38 +2665,49 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
     }
     for (uint32_t k : g.second) bs[k]->cycle += n_cycles[k];
   }
-  uint32_t n_aux = 0;
-  if (!replays.empty()) {
-    rteaal_status st = fork_aux(0);
-    if (st != RTEAAL_OK) return st;
-    for (auto& r : replays)
-      for (uint64_t c = 0; c < r.second; ++c) HIP_TRY(ctx, hipGraphLaunch(r.first->exec, ctx->aux[0]));
-    if (tail >= 0) {
-      st = run_alone((uint32_t)tail, tail_cycles, 0);
-      if (st != RTEAAL_OK) return st;
+  // The chains' replays, interleaved one cycle at a time across chains, so
+  // that a host blocked by a full queue still feeds every chain.
+  {
+    std::vector<size_t> ri(chains.size(), 0);
+    std::vector<uint64_t> done(chains.size(), 0);
+    for (bool more = true; more;) {
+      more = false;
+      for (size_t c = 0; c < chains.size(); ++c) {
+        ChainPlan& cp = chains[c];
+        if (ri[c] >= cp.replays.size()) continue;
+        HIP_TRY(ctx, hipGraphLaunch(cp.replays[ri[c]].first->exec, ctx->aux[c]));
+        if (++done[c] == cp.replays[ri[c]].second) {
+          ++ri[c];
+          done[c] = 0;
+        }
+        more = more || ri[c] < cp.replays.size();
+      }
     }
-    for (uint32_t k : multi) bs[k]->cycle += n_cycles[k];
-    n_aux = 1;
+    for (size_t c = 0; c < chains.size(); ++c) {
+      if (chains[c].tail >= 0) {
+        const rteaal_status st = run_alone((uint32_t)chains[c].tail, chains[c].tail_cycles, (uint32_t)c);
+        if (st != RTEAAL_OK) return st;
+      }
+      for (uint32_t k : chain_ks[c]) bs[k]->cycle += n_cycles[k];
+    }
   }
-  for (uint32_t k : single) {
-    const uint32_t a = n_aux < 4 ? n_aux : 1u + (n_aux - 1u) % 3u;
-    rteaal_status st = fork_aux(a);
-    if (st != RTEAAL_OK) return st;
-    st = run_alone(k, n_cycles[k], a);
+  for (size_t j = 0; j < single.size(); ++j) {
+    const uint32_t k = single[j];
+    const rteaal_status st = run_alone(k, n_cycles[k], single_stream(j));
     if (st != RTEAAL_OK) return st;
     bs[k]->cycle += n_cycles[k];
-    ++n_aux;
   }
   // Cooperative batches last, on the context stream once everything above
   // (the auxiliary streams included) has finished: their workgroups spin at
   // grid barriers until all are resident, so they must not wait for
   // long-running workgroups of other launches to leave the device.
   if (!coop.empty()) {
-    for (uint32_t a = 0; a < n_forked; ++a) {
+    for (int a = 0; a < rteaal_ctx::kAux; ++a) {
+      if (!(forked >> a & 1u)) continue;
       HIP_TRY(ctx, hipEventRecord(ctx->join[a], ctx->aux[a]));
       HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, ctx->join[a], 0));
     }
-    n_forked = 0;
+    forked = 0;
     for (uint32_t k : coop) {
       const rteaal_status st = enqueue_cycles(ctx, *find_design(ctx, bs[k]->design), *bs[k], n_cycles[k]);
       if (st != RTEAAL_OK) return st;

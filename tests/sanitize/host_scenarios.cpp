@@ -268,6 +268,35 @@ int main(int argc, char** argv) {
   }
   for (rteaal_design_id id : ids) ok(rteaal_unload_design(g_ctx, id), "unload");
   rteaal_destroy(g_ctx);
+  // 5. Captured cycles split into several chains (a context created with
+  //    RTEAAL_MULTI_CHAINS set), uneven cycle counts, RESIDENT beside them.
+  for (const char* chains : {"2", "3"}) {
+    setenv("RTEAAL_MULTI_CHAINS", chains, 1);
+    ok(rteaal_create(0, nullptr, nullptr, &g_ctx), "create");
+    unsetenv("RTEAAL_MULTI_CHAINS");
+    ids.clear();
+    for (auto& d : ds) {
+      rteaal_design_id id = 0;
+      ok(rteaal_load_design(g_ctx, &d.desc, &id), "load_design");
+      ids.push_back(id);
+    }
+    std::vector<rteaal_batch_id> bs;
+    for (uint32_t k = 0; k < 9; ++k) bs.push_back(batch(ids[k % D], 70 + 10 * k, sweep(1 + k % 2)));
+    rteaal_batch_opts res{};
+    res.mapping = RTEAAL_MAP_RESIDENT;
+    bs.push_back(batch(ids[0], 5, res));
+    many(bs, std::vector<uint64_t>(bs.size(), 3));
+    std::vector<uint64_t> cyc;
+    for (size_t k = 0; k < bs.size(); ++k) cyc.push_back(k % 4);
+    many(bs, cyc);
+    ok(rteaal_free_batch(g_ctx, bs[2]), "free_batch");
+    bs.erase(bs.begin() + 2);
+    many(bs, std::vector<uint64_t>(bs.size(), 2));
+    ok(rteaal_sync(g_ctx), "sync");
+    for (rteaal_batch_id b : bs) ok(rteaal_free_batch(g_ctx, b), "free_batch");
+    for (rteaal_design_id id : ids) ok(rteaal_unload_design(g_ctx, id), "unload");
+    rteaal_destroy(g_ctx);
+  }
   std::printf("scenarios ok\n");
   return 0;
 }

@@ -6,10 +6,11 @@ launch per slot and kind over a table of segments, or, while a slot's
 pieces are small, one mixed launch whose segments name their own kind.
 Each batch must still equal the oracle (registers and per-cycle digest):
 with uneven cycle counts (batches drop out of the set in order, the last
-one finishing alone), with mixed launches off and everywhere, with watched
-or tile-pass batches beside them (stepped on their own), with a RESIDENT
-batch in the same call, after a batch of a cached set is freed, and when
-more sets are used than the cache holds.  Tolerance 0.
+one finishing alone), with mixed launches off and everywhere, split into
+chains of their own, with watched or tile-pass batches beside them
+(stepped on their own), with a RESIDENT batch in the same call, after a
+batch of a cached set is freed, and when more sets are used than the cache
+holds.  Tolerance 0.
 """
 import os
 
@@ -75,19 +76,23 @@ def test_uneven_cycles_every_shape(ctx, designs):
     uneven_cycles_every_shape(ctx, designs)
 
 
-@pytest.mark.parametrize("max_waves", ["0", "1000000000"])
-def test_uneven_cycles_mixed_launches_off_and_everywhere(designs, max_waves):
+@pytest.mark.parametrize("var,value", [("RTEAAL_MIXED_MAX_WAVES", "0"),
+                                       ("RTEAAL_MIXED_MAX_WAVES", "1000000000"),
+                                       ("RTEAAL_MULTI_CHAINS", "2"),
+                                       ("RTEAAL_MULTI_CHAINS", "3")])
+def test_uneven_cycles_mixed_launches_and_chains(designs, var, value):
     """The same with the pieces of a layer index never merged into one mixed
-    launch, and merged wherever their kinds allow it."""
-    old = os.environ.get("RTEAAL_MIXED_MAX_WAVES")
-    os.environ["RTEAAL_MIXED_MAX_WAVES"] = max_waves
+    launch, merged wherever their kinds allow it, and with the batches split
+    into two or three chains of captured cycles on their own streams."""
+    old = os.environ.get(var)
+    os.environ[var] = value
     try:
         c = gpu_ctx()
     finally:
         if old is None:
-            del os.environ["RTEAAL_MIXED_MAX_WAVES"]
+            del os.environ[var]
         else:
-            os.environ["RTEAAL_MIXED_MAX_WAVES"] = old
+            os.environ[var] = old
     ds, refs, _ = designs
     ids = [R.rteaal_load_design(c, d) for d in ds]
     try:

@@ -28,6 +28,12 @@ import time
 
 import numpy as np
 
+# More hardware queues than HIP's default of 4, so that the streams
+# rteaal_step_many uses (a chain of captured cycles, RESIDENT configurations
+# beside it) each get their own queue rather than waiting behind another's
+# long launch.  Set before the HIP runtime starts; an explicit setting wins.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 

@@ -452,7 +452,10 @@ rteaal_status rteaal_step(rteaal_ctx* ctx, rteaal_batch_id batch, uint64_t n_cyc
  * index in one mixed launch while they total at most
  * RTEAAL_MIXED_MAX_WAVES wavefronts, an environment variable, default
  * 2^20, 0 = never); cooperative batches (persistent LAYERED, PARTITIONED)
- * run last, one at a time, with nothing else of the call beside them.  Errors: RTEAAL_E_INVALID_ARG (unknown or repeated batch,
+ * run last, one at a time, with nothing else of the call beside them.  The
+ * context creates its auxiliary streams in a fixed order; with at least 8
+ * hardware queues (HIP's GPU_MAX_HW_QUEUES, default 4) each gets its own,
+ * and a chain of captured cycles never waits behind a RESIDENT launch.  Errors: RTEAAL_E_INVALID_ARG (unknown or repeated batch,
  * bad stimulus: then nothing has been enqueued), RTEAAL_E_NO_MEMORY,
  * RTEAAL_E_DEVICE (the context is then unusable). */
 rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_id* batches,

@@ -1685,6 +1685,23 @@ rteaal_status rteaal_create(int device, void* stream, const rteaal_allocator* al
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     return fail(nullptr, RTEAAL_E_DEVICE, "hipGetSymbolAddress of the staging array failed");
   }
+  // The auxiliary streams of rteaal_step_many, created now and in this
+  // order (the first chain's, then the RESIDENT configurations', then the
+  // rest), so that the runtime hands them hardware queues in that order:
+  // with enough queues (GPU_MAX_HW_QUEUES) a chain of captured cycles does
+  // not share a queue with a long RESIDENT launch.
+  for (int a : {0, 4, 5, 6, 1, 2, 3, 7}) {
+    e = hipStreamCreateWithFlags(&ctx->aux[a], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join[a], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      for (int k = 0; k < rteaal_ctx::kAux; ++k) {
+        if (ctx->aux[k]) (void)hipStreamDestroy(ctx->aux[k]);
+        if (ctx->join[k]) (void)hipEventDestroy(ctx->join[k]);
+      }
+      if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+      return fail(nullptr, RTEAAL_E_DEVICE, "auxiliary stream: %s", hipGetErrorString(e));
+    }
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess)
     ctx->max_lds = std::min<size_t>(prop.maxSharedMemoryPerMultiProcessor, resident_max_lds());

@@ -151,7 +151,7 @@ def measured_traffic(role, workload, opts):
         return None
     key = (f"{role}|{workload}|sweep/opw{opts['ops_per_wave']}/u{opts['unroll']}"
            f"/tg{opts['tiles_per_wave']}/as{opts.get('arity_split', 0)}"
-           f"/tpp{opts.get('tiles_per_pass', 0)}")
+           f"/tpp{opts.get('tiles_per_pass', 0)}" + ("/pb1" if opts.get("pass_branches") else ""))
     with open(path) as fh:
         rec = json.load(fh).get(key)
     if rec is None or rec["source_sha256"] != kernel_sources_sha256():
@@ -277,7 +277,8 @@ def bench_single(args, R, torch):
     stream = ctx.stream
     did = R.rteaal_load_design(ctx, d)
     manual = (args.mapping != "auto" or args.block or args.ops_per_wave or args.unroll
-              or args.tiles_per_wave or args.arity_split or args.tiles_per_pass or args.partitions)
+              or args.tiles_per_wave or args.arity_split or args.tiles_per_pass or args.partitions
+              or args.pass_branches)
     if not manual and not args.no_autotune:
         t0 = time.perf_counter()
         tuned, trate = R.rteaal_autotune(ctx, did, n_inst)
@@ -286,7 +287,8 @@ def bench_single(args, R, torch):
     bid = R.rteaal_create_batch(ctx, did, seeds, mapping=mapping, block_threads=args.block,
                                 ops_per_wave=args.ops_per_wave, unroll=args.unroll,
                                 tiles_per_wave=args.tiles_per_wave, arity_split=args.arity_split,
-                                tiles_per_pass=args.tiles_per_pass, partitions=args.partitions)
+                                tiles_per_pass=args.tiles_per_pass, partitions=args.partitions,
+                                pass_branches=args.pass_branches)
     used_map, _ = R.rteaal_batch_info(ctx, bid)
     bopts = R.rteaal_batch_options(ctx, bid)
     for _ in range(args.warmup):
@@ -1050,6 +1052,8 @@ def main():
     ap.add_argument("--tiles-per-wave", type=int, default=0)
     ap.add_argument("--arity-split", type=int, default=0, help="SWEEP: 0 auto, 1 never, 2 always")
     ap.add_argument("--tiles-per-pass", type=int, default=0, help="SWEEP: 0 all tiles per pass")
+    ap.add_argument("--pass-branches", type=int, default=0,
+                    help="SWEEP: 1 = tile passes as parallel graph branches")
     ap.add_argument("--plain-cycles", type=int, default=None)
     ap.add_argument("--profile-cycles", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -346,6 +346,12 @@ typedef struct {
                               partitions.  block_threads (64..1024, multiple
                               of 64, default from the largest sub-program
                               layer) and lds_state apply as for RESIDENT      */
+  uint32_t pass_branches;  /* SWEEP with tiles_per_pass: 0 = the passes run
+                              one after another; 1 = each pass is a branch of
+                              its own in the captured cycle graph (its layers
+                              in order), the branches running side by side
+                              and joining before the register digest; at most
+                              4 passes                                        */
 } rteaal_batch_opts;
 
 /* Device bytes a batch of n_instances of `design` would allocate under
@@ -403,7 +409,7 @@ rteaal_status rteaal_batch_info(rteaal_ctx* ctx, rteaal_batch_id batch, uint32_t
  * passing *out back creates a batch of the same shape: mapping, and for
  * RESIDENT block_threads, lds_state/lds_ops (0 = in LDS, 1 = in HBM),
  * unroll; for SWEEP ops_per_wave, unroll, tiles_per_wave, arity_split,
- * tiles_per_pass (0 = all); for LAYERED block_threads, unroll, persistent;
+ * tiles_per_pass (0 = all), pass_branches; for LAYERED block_threads, unroll, persistent;
  * for PARTITIONED block_threads, lds_state, partitions (other fields 0). */
 rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id batch, rteaal_batch_opts* out);
 

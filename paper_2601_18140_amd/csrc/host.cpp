@@ -734,6 +734,7 @@ struct Batch {
   uint32_t id = 0, design = 0, n_inst = 0, mapping = 0, block = 0, opw = 0, unroll = 0, tg = 1;
   uint32_t arity_split = 0;
   uint32_t tpp = 0;  // SWEEP tiles per pass, 0 = all
+  bool pbranch = false;  // SWEEP: tile passes as parallel graph branches
   bool lds = false, lds_ops = false;
   bool persistent = false;  // LAYERED: one cooperative launch per chunk of cycles
   Mem gsync;                // its grid barrier state
@@ -1587,7 +1588,17 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
       uint32_t n_src;  // 0: the heavy launch
     };
     std::vector<Piece> pieces;
-    for (const TilePass& tp : passes)
+    // Parallel passes: every tile pass is a graph branch of its own (its
+    // layers in order on one stream), joined before the digest.
+    const bool branches = b.pbranch && passes.size() > 1;
+    if (branches) {
+      e = hipEventRecord(ctx->cap_fork, ctx->stream);
+      for (size_t k = 0; k + 1 < passes.size() && e == hipSuccess; ++k)
+        e = hipStreamWaitEvent(ctx->cap[k], ctx->cap_fork, 0);
+    }
+    for (size_t pi = 0; pi < passes.size(); ++pi) {
+      const TilePass& tp = passes[pi];
+      hipStream_t ps = branches && pi > 0 ? ctx->cap[pi - 1] : ctx->stream;
       for (uint32_t li = 0; li < h.layers.size() && e == hipSuccess; ++li) {
         const DevLayer& ly = h.layers[li];
         pieces.clear();
@@ -1605,20 +1616,28 @@ rteaal_status enqueue_cycles(rteaal_ctx* ctx, DesignHost& h, Batch& b, uint64_t 
         // Only large layers fork: for small ones the branches' scheduling costs
         // more than the overlap returns, and batches stepped together already
         // overlap on their own streams.
+        // (Parallel passes use the branch streams, so their layers do not fork.)
         const bool large = (uint64_t)(ly.end - ly.begin) * tp.count >= (1ull << 20);
-        const size_t n_fork = large ? std::min<size_t>(pieces.size(), 4) - (pieces.empty() ? 0 : 1) : 0;
+        const size_t n_fork =
+            large && !branches ? std::min<size_t>(pieces.size(), 4) - (pieces.empty() ? 0 : 1) : 0;
         if (e == hipSuccess && n_fork) {
-          e = hipEventRecord(ctx->cap_fork, ctx->stream);
+          e = hipEventRecord(ctx->cap_fork, ps);
           for (size_t k = 0; k < n_fork && e == hipSuccess; ++k)
             e = hipStreamWaitEvent(ctx->cap[k], ctx->cap_fork, 0);
         }
         for (size_t k = 0; k < pieces.size() && e == hipSuccess; ++k)
-          e = run(pieces[k], k == 0 || k > n_fork ? ctx->stream : ctx->cap[k - 1]);
+          e = run(pieces[k], k == 0 || k > n_fork ? ps : ctx->cap[k - 1]);
         // (pieces beyond the forked ones, if any, run on the capturing stream)
         for (size_t k = 0; k < n_fork && e == hipSuccess; ++k) {
           e = hipEventRecord(ctx->cap_join[k], ctx->cap[k]);
-          if (e == hipSuccess) e = hipStreamWaitEvent(ctx->stream, ctx->cap_join[k], 0);
+          if (e == hipSuccess) e = hipStreamWaitEvent(ps, ctx->cap_join[k], 0);
         }
+      }
+    }
+    if (branches)
+      for (size_t k = 0; k + 1 < passes.size() && e == hipSuccess; ++k) {
+        e = hipEventRecord(ctx->cap_join[k], ctx->cap[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ctx->stream, ctx->cap_join[k], 0);
       }
     if (e == hipSuccess) e = digest(h, b, ctx->stream);
     if (e == hipSuccess) e = launch_advance(ctl, 1, ctx->stream);
@@ -2199,6 +2218,13 @@ rteaal_status rteaal_create_batch(rteaal_ctx* ctx, rteaal_design_id id, uint32_t
     if (tpp % tg != 0)
       return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP tiles_per_pass must be a multiple of tiles_per_wave");
     b->tpp = tpp >= b->L.n_tiles_alloc ? 0u : tpp;
+    const uint32_t pb = opts ? opts->pass_branches : 0u;
+    if (pb > 1) return fail(ctx, RTEAAL_E_INVALID_ARG, "SWEEP pass_branches must be 0 or 1");
+    if (pb && b->tpp && (b->L.n_tiles_alloc + b->tpp - 1) / b->tpp > 4)
+      return fail(ctx, RTEAAL_E_INVALID_ARG,
+                  "SWEEP pass_branches: at most 4 tile passes (tiles_per_pass %u of %u tiles)", b->tpp,
+                  b->L.n_tiles_alloc);
+    b->pbranch = pb == 1 && b->tpp != 0;
   }
   const uint64_t n_seed = b->mapping == RTEAAL_MAP_SWEEP ? (uint64_t)b->L.n_tiles_alloc * 64 : n_inst;
   b->n_slot = n_seed;
@@ -2302,6 +2328,7 @@ rteaal_status rteaal_batch_options(rteaal_ctx* ctx, rteaal_batch_id id, rteaal_b
     o.tiles_per_wave = b->tg;
     o.arity_split = b->arity_split;
     o.tiles_per_pass = b->tpp;
+    o.pass_branches = b->pbranch ? 1u : 0u;
   }
   *out = o;
   return RTEAAL_OK;
@@ -2989,12 +3016,12 @@ std::string device_tag(int device) {
   return t;
 }
 
-constexpr int kOptFields = 11;  // (entries name their field count in the key: "o11")
+constexpr int kOptFields = 12;  // (entries name their field count in the key: "o12")
 
 void opts_to(const rteaal_batch_opts& o, uint32_t* v) {
   const uint32_t a[kOptFields] = {o.mapping, o.block_threads, o.ops_per_wave, o.lds_state, o.lds_ops,
                                   o.unroll, o.tiles_per_wave, o.arity_split, o.tiles_per_pass,
-                                  o.persistent, o.partitions};
+                                  o.persistent, o.partitions, o.pass_branches};
   std::copy(a, a + kOptFields, v);
 }
 
@@ -3011,6 +3038,7 @@ rteaal_batch_opts opts_from(const uint32_t* v) {
   o.tiles_per_pass = v[8];
   o.persistent = v[9];
   o.partitions = v[10];
+  o.pass_branches = v[11];
   return o;
 }
 
@@ -3072,7 +3100,7 @@ std::string single_key(rteaal_ctx* ctx, const DesignHost& h, uint32_t n_inst, ui
   char buf[128];
   std::snprintf(buf, sizeof buf, "|%016llx|%u|%llu", (unsigned long long)h.fingerprint, n_inst,
                 (unsigned long long)cycles);
-  return "single|o11|" + device_tag(ctx->device) + buf;
+  return "single|o12|" + device_tag(ctx->device) + buf;
 }
 
 }  // namespace
@@ -3137,6 +3165,18 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
         if (u * tg <= 8 || (tg == 16 && u == 1))
           cand.push_back(rteaal_batch_opts{RTEAAL_MAP_SWEEP, 0, opw, 0, 0, u, tg});
   }
+  // Tile passes as parallel graph branches (2 or 4 passes), for a few of
+  // the shapes that do well one pass at a time.
+  if (n_tiles >= 4)
+    for (uint32_t np : {2u, 4u})
+      for (uint32_t tg : {2u, 4u})
+        for (uint32_t u : {1u, 2u}) {
+          if (n_tiles % (np * tg) != 0) continue;
+          rteaal_batch_opts o{RTEAAL_MAP_SWEEP, 0, 2, 0, 0, u, tg};
+          o.tiles_per_pass = n_tiles / np;
+          o.pass_branches = 1;
+          cand.push_back(o);
+        }
   std::vector<uint64_t> seeds(n_inst);
   for (uint32_t i = 0; i < n_inst; ++i) seeds[i] = i;
   const char* log_env = std::getenv("RTEAAL_AUTOTUNE_LOG");
@@ -3174,8 +3214,9 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
     const double r = (double)n_inst * (double)cyc / (std::max(ms, 1e-3f) * 1e-3);
     if (log)
       std::fprintf(stderr, "rteaal_autotune: mapping %u block %u ops/wave %u unroll %u tiles %u "
-                   "persistent %u partitions %u -> %.4g\n", o.mapping, o.block_threads,
-                   o.ops_per_wave, o.unroll, o.tiles_per_wave, o.persistent, o.partitions, r);
+                   "persistent %u partitions %u passes of %u tiles%s -> %.4g\n", o.mapping,
+                   o.block_threads, o.ops_per_wave, o.unroll, o.tiles_per_wave, o.persistent,
+                   o.partitions, o.tiles_per_pass, o.pass_branches ? " in parallel" : "", r);
     if (r > best_rate) {
       best_rate = r;
       best_o = o;
@@ -3211,7 +3252,7 @@ rteaal_status rteaal_autotune_many(rteaal_ctx* ctx, uint32_t n, const rteaal_des
   // Trial length: about 4e9 op-evaluations per policy, 2..32 cycles.
   const uint64_t cyc = trial_cycles ? trial_cycles
                                     : (uint64_t)std::max(2.0, std::min(32.0, 4e9 / std::max<double>((double)total, 1.0)));
-  std::string key = "joint|o11s18|" + device_tag(ctx->device);
+  std::string key = "joint|o12s18|" + device_tag(ctx->device);
   {
     uint64_t fp = 1469598103934665603ull;
     for (uint32_t k = 0; k < n; ++k) {

@@ -89,7 +89,7 @@ class rteaal_batch_opts(C.Structure):
                 ("lds_ops", C.c_uint32), ("unroll", C.c_uint32),
                 ("tiles_per_wave", C.c_uint32), ("arity_split", C.c_uint32),
                 ("tiles_per_pass", C.c_uint32), ("persistent", C.c_uint32),
-                ("partitions", C.c_uint32)]
+                ("partitions", C.c_uint32), ("pass_branches", C.c_uint32)]
 
 
 class rteaal_partition_stats(C.Structure):
@@ -455,10 +455,12 @@ def rteaal_design_format(ctx, design_id, layer):
 
 
 def _opts(mapping, block_threads=0, ops_per_wave=0, lds_state=0, lds_ops=0, unroll=0,
-          tiles_per_wave=0, arity_split=0, tiles_per_pass=0, persistent=0, partitions=0):
+          tiles_per_wave=0, arity_split=0, tiles_per_pass=0, persistent=0, partitions=0,
+          pass_branches=0):
     return rteaal_batch_opts(int(mapping), int(block_threads), int(ops_per_wave), int(lds_state),
                              int(lds_ops), int(unroll), int(tiles_per_wave), int(arity_split),
-                             int(tiles_per_pass), int(persistent), int(partitions))
+                             int(tiles_per_pass), int(persistent), int(partitions),
+                             int(pass_branches))
 
 
 def rteaal_batch_footprint(ctx, design_id, n_instances, mapping=RTEAAL_MAP_AUTO, **opts):
@@ -489,7 +491,8 @@ def rteaal_partition_plan_stats(ctx, design_id, partitions):
 
 def rteaal_create_batch(ctx, design_id, seeds, mapping=RTEAAL_MAP_AUTO, **opts):
     """opts: block_threads, ops_per_wave, lds_state, lds_ops, unroll, tiles_per_wave,
-    arity_split, tiles_per_pass, persistent, partitions (see rteaal_batch_opts)."""
+    arity_split, tiles_per_pass, persistent, partitions, pass_branches (see
+    rteaal_batch_opts)."""
     seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
     o = _opts(mapping, **opts)
     out = C.c_uint32()
@@ -625,7 +628,7 @@ def opts_dict(o):
             "lds_state": o.lds_state, "lds_ops": o.lds_ops, "unroll": o.unroll,
             "tiles_per_wave": o.tiles_per_wave, "arity_split": o.arity_split,
             "tiles_per_pass": o.tiles_per_pass, "persistent": o.persistent,
-            "partitions": o.partitions}
+            "partitions": o.partitions, "pass_branches": o.pass_branches}
 
 
 def rteaal_autotune(ctx, design_id, n_instances, trial_cycles=0):

@@ -159,6 +159,38 @@ def test_sweep_tile_passes(ctx):
             assert_same(slots, ref_s, f"slots tg={tg} tpp={tpp}")
 
 
+def test_sweep_tile_passes_as_parallel_branches(ctx):
+    """Tile passes as parallel branches of the cycle graph (2 to 4 passes, the
+    last one shorter, per-operand-count launches inside a pass) equal the
+    oracle, every slot; more than 4 passes are refused."""
+    d = rtlgen.generate(SMALL[1], 24)
+    for n_inst in (300, 520):
+        seeds = np.arange(n_inst, dtype=np.uint64) * 3 + 1
+        ref_r, ref_s, _ = oracle.run(d, seeds, 7, want_slots=True)
+        for tg, tpp, u, split in [(1, 4, 2, 0), (1, 3, 1, 2), (2, 4, 2, 2), (2, 2, 1, 1)]:
+            if (n_inst + 63) // 64 > 4 * tpp:
+                continue
+            note(f"parallel passes n={n_inst} tiles_per_wave={tg} tiles_per_pass={tpp} u={u}")
+            regs, slots, _ = run_gpu(ctx, d, seeds, [3, 4], mapping=R.RTEAAL_MAP_SWEEP, slots=True,
+                                     tiles_per_wave=tg, unroll=u, ops_per_wave=5,
+                                     tiles_per_pass=tpp, arity_split=split, pass_branches=1)
+            assert_same(regs, ref_r, f"registers tg={tg} tpp={tpp}")
+            assert_same(slots, ref_s, f"slots tg={tg} tpp={tpp}")
+    did = R.rteaal_load_design(ctx, d)
+    try:
+        with pytest.raises(R.RteaalError):   # 9 tiles in passes of 2: 5 passes
+            R.rteaal_create_batch(ctx, did, np.arange(520, dtype=np.uint64),
+                                  mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=1, tiles_per_pass=2,
+                                  pass_branches=1)
+        b = R.rteaal_create_batch(ctx, did, np.arange(520, dtype=np.uint64),
+                                  mapping=R.RTEAAL_MAP_SWEEP, tiles_per_wave=1, tiles_per_pass=3,
+                                  pass_branches=1)
+        assert R.rteaal_batch_options(ctx, b)["pass_branches"] == 1
+        R.rteaal_free_batch(ctx, b)
+    finally:
+        R.rteaal_unload_design(ctx, did)
+
+
 def test_sweep_rejects_oversized_shape(ctx):
     d = rtlgen.generate(SMALL[2], 1)
     did = R.rteaal_load_design(ctx, d)
@@ -190,6 +222,8 @@ def test_batch_options_round_trip(ctx):
                              "ops_per_wave": 3, "arity_split": 2, "tiles_per_pass": 2}),
                       (1100, {"mapping": R.RTEAAL_MAP_SWEEP, "tiles_per_wave": 16, "unroll": 1,
                               "ops_per_wave": 4, "tiles_per_pass": 16}),
+                      (1100, {"mapping": R.RTEAAL_MAP_SWEEP, "tiles_per_wave": 2, "unroll": 2,
+                              "tiles_per_pass": 6, "pass_branches": 1}),
                       (5, {"mapping": R.RTEAAL_MAP_LAYERED, "unroll": 4, "block_threads": 192})]:
             seeds = np.arange(n, dtype=np.uint64)
             b1 = R.rteaal_create_batch(ctx, did, seeds, **kw)

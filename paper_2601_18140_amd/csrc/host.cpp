@@ -1296,14 +1296,17 @@ rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
   for (auto& v : slots) {
     if (v.size() < 2) continue;
     uint64_t waves = 0;
-    bool ok = true, lean = true;
+    bool ok = true, lean = true, small = true;
     for (const Launch& l : v) {
       waves += l.wave0.back();
       ok = ok && multi_mixable(l.kind, l.tg);
       lean = lean && multi_lean(l.kind, l.tg);
+      // the smallest set: no LAYERED pieces and at most 2 operations in flight
+      small = small && l.kind != 3;
+      for (const MultiSeg& x : l.segs) small = small && (l.kind != 0 || x.unroll <= 2);
     }
     if (!ok || waves > ctx->mixed_max_waves) continue;
-    Launch m{lean ? 5u : 4u, 0u, {}, {0u}, 0};
+    Launch m{lean ? (small ? 6u : 5u) : 4u, 0u, {}, {0u}, 0};
     for (const Launch& l : v) {
       for (size_t k = 0; k < l.segs.size(); ++k) {
         MultiSeg x = l.segs[k];

@@ -305,7 +305,8 @@ uint32_t partitioned_capacity(uint32_t block, bool lds_state, size_t lds);
 // group (its variant; common operations with tile groups up to 4), so that
 // the small pieces of one layer index need one launch instead of one per
 // kind and tile group; 5: the same for the variants of small register
-// footprint only (multi_lean).
+// footprint only (multi_lean); 6: the lean variants without LAYERED pieces
+// and with at most 2 common operations in flight, smaller still.
 bool multi_mixable(uint32_t kind, uint32_t tg);
 bool multi_lean(uint32_t kind, uint32_t tg);
 uint32_t multi_variant(uint32_t kind, uint32_t tg, uint32_t unroll, bool lean);

@@ -1244,14 +1244,15 @@ k_layer_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wa
 }
 
 // Mixed launch: every segment names its own kind and tile group (variant);
-// the branch on it is uniform over the wavefront.  LEAN holds only the
-// variants of small register footprint (common operations with 1 or 2
-// tiles, heavy operations with 1, LAYERED), so that its wavefronts still
-// find room beside long-running RESIDENT workgroups on a compute unit.
-template <bool LEAN>
-__global__ void __launch_bounds__(256)
-k_mixed_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wave0,
-              uint32_t n_seg) {
+// the branch on it is uniform over the wavefront.  SET 0 holds every
+// variant; 1 (lean) only those of small register footprint (common
+// operations with 1 or 2 tiles, 4 in flight on one, heavy operations with
+// 1, LAYERED), so that its wavefronts still find room beside long-running
+// RESIDENT workgroups on a compute unit; 2 the lean set without LAYERED and
+// 4 in flight, smaller still.
+template <int SET>
+__device__ __forceinline__ void mixed_body(const MultiSeg* __restrict__ segs,
+                                           const uint32_t* __restrict__ wave0, uint32_t n_seg) {
   const uint32_t wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   if (wave >= wave0[n_seg]) return;
@@ -1269,14 +1270,14 @@ k_mixed_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wa
     RTEAAL_MIX_SWEEP(2, 1);
   } else if (v == 65) {
     RTEAAL_MIX_SWEEP(2, 2);
-  } else if (v == 128) {
-    RTEAAL_MIX_SWEEP(4, 1);
   } else if (v == 8) {
     heavy_wave<1>(g.ops, seg_heavy_range(g), g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
                   g.ctl, g.n_inst, g.opw, 0u, g.n_groups, local, lane);
-  } else if (v == 24) {
+  } else if (SET <= 1 && v == 128) {
+    RTEAAL_MIX_SWEEP(4, 1);
+  } else if (SET <= 1 && v == 24) {
     layer_wave(g, local, lane);
-  } else if (!LEAN) {
+  } else if (SET == 0) {
     switch (v) {
       case 2: RTEAAL_MIX_SWEEP(1, 4); break;
       case 66: RTEAAL_MIX_SWEEP(2, 4); break;
@@ -1292,6 +1293,13 @@ k_mixed_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wa
     }
   }
 #undef RTEAAL_MIX_SWEEP
+}
+
+template <int SET>
+__global__ void __launch_bounds__(256)
+k_mixed_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wave0,
+              uint32_t n_seg) {
+  mixed_body<SET>(segs, wave0, n_seg);
 }
 
 bool multi_lean(uint32_t kind, uint32_t tg) {
@@ -1971,10 +1979,11 @@ hipError_t launch_multi(uint32_t kind, uint32_t tg, const MultiSeg* segs, const 
                         uint32_t n_seg, uint64_t n_waves, hipStream_t s) {
   if (n_seg == 0 || n_waves == 0) return hipSuccess;
   if (n_waves >= (1ull << 32)) return hipErrorInvalidValue;
-  if (kind == 4 || kind == 5) {
+  if (kind >= 4 && kind <= 6) {
     const dim3 grid((uint32_t)((n_waves + 3) / 4)), blk(256);
-    if (kind == 5) hipLaunchKernelGGL(k_mixed_multi<true>, grid, blk, 0, s, segs, wave0, n_seg);
-    else hipLaunchKernelGGL(k_mixed_multi<false>, grid, blk, 0, s, segs, wave0, n_seg);
+    if (kind == 6) hipLaunchKernelGGL(k_mixed_multi<2>, grid, blk, 0, s, segs, wave0, n_seg);
+    else if (kind == 5) hipLaunchKernelGGL(k_mixed_multi<1>, grid, blk, 0, s, segs, wave0, n_seg);
+    else hipLaunchKernelGGL(k_mixed_multi<0>, grid, blk, 0, s, segs, wave0, n_seg);
     return hipGetLastError();
   }
   if (kind == 3) {

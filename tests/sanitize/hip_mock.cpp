@@ -377,8 +377,10 @@ hipError_t launch_multi(uint32_t kind, uint32_t, const MultiSeg* segs, const uin
     if ((kind == 4 || kind == 5) && vu > 1 && (vk != 0 || vu > 4 || (vu == 4 && vt > 2) || vt > 4))
       die("mixed segment with an unroll depth outside the kernel's variants", &segs[k]);
     if (kind == 4 && !multi_mixable(vk, vt)) die("mixed segment of an unknown variant", &segs[k]);
-    if (kind == 5 && (!multi_lean(vk, vt) || (vu == 2 && vt > 2) || (vu == 4 && vt > 1)))
+    if ((kind == 5 || kind == 6) && (!multi_lean(vk, vt) || (vu == 2 && vt > 2) || (vu == 4 && vt > 1)))
       die("lean mixed segment of a variant outside the lean set", &segs[k]);
+    if (kind == 6 && (vk == 3 || vu > 2))
+      die("smallest mixed set with a LAYERED piece or 4 in flight", &segs[k]);
     launched(s, {segs[k].ops, segs[k].layers, segs[k].const_limbs, segs[k].state, segs[k].seeds,
                  segs[k].ctl});
     if (wave0[k + 1] <= wave0[k]) die("empty or decreasing segment", &wave0[k]);

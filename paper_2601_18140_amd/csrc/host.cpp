@@ -2454,11 +2454,11 @@ rteaal_status rteaal_step_many(rteaal_ctx* ctx, uint32_t n, const rteaal_batch_i
   // SWEEP and LAYERED batches.  Those that are not watched, timed or run in
   // tile passes advance together through captured multi-batch cycles (one
   // graph per set of batches that still have cycles to go, so batches with
-  // fewer cycles drop out in order); the rest each replay their own cycle
-  // graph.  Each kind runs on an auxiliary stream forked from the context
-  // stream, beside the RESIDENT launches on the context stream.
+  // fewer cycles drop out in order), in one or more chains; the rest each
+  // replay their own cycle graph.  All of them run on auxiliary streams
+  // forked from the context stream, beside the RESIDENT launches (below).
   // Cooperative batches (persistent LAYERED, PARTITIONED) run at the end,
-  // alone (below).
+  // alone.
   std::vector<uint32_t> multi, single, coop;
   for (uint32_t k = 0; k < n; ++k) {
     const Batch& b = *bs[k];

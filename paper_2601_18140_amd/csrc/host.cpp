@@ -3170,7 +3170,7 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
   }
   // Tile passes as parallel graph branches (2 or 4 passes), for a few of
   // the shapes that do well one pass at a time.
-  if (n_tiles >= 4)
+  if (n_tiles >= 4) {
     for (uint32_t np : {2u, 4u})
       for (uint32_t tg : {2u, 4u})
         for (uint32_t u : {1u, 2u}) {
@@ -3180,6 +3180,15 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
           o.pass_branches = 1;
           cand.push_back(o);
         }
+    for (uint32_t tg : {8u, 16u})      // two passes of wide tile groups
+      for (uint32_t opw : {2u, 8u}) {
+        if (n_tiles % (2 * tg) != 0) continue;
+        rteaal_batch_opts o{RTEAAL_MAP_SWEEP, 0, opw, 0, 0, 1, tg};
+        o.tiles_per_pass = n_tiles / 2;
+        o.pass_branches = 1;
+        cand.push_back(o);
+      }
+  }
   std::vector<uint64_t> seeds(n_inst);
   for (uint32_t i = 0; i < n_inst; ++i) seeds[i] = i;
   const char* log_env = std::getenv("RTEAAL_AUTOTUNE_LOG");

@@ -3180,7 +3180,7 @@ rteaal_status rteaal_autotune(rteaal_ctx* ctx, rteaal_design_id id, uint32_t n_i
           o.pass_branches = 1;
           cand.push_back(o);
         }
-    for (uint32_t tg : {8u, 16u})      // two passes of wide tile groups
+    for (uint32_t tg : {16u})          // two passes of the widest tile groups
       for (uint32_t opw : {2u, 8u}) {
         if (n_tiles % (2 * tg) != 0) continue;
         rteaal_batch_opts o{RTEAAL_MAP_SWEEP, 0, opw, 0, 0, 1, tg};

@@ -72,14 +72,16 @@ __device__ __forceinline__ uint64_t res_fetch(const char* s, uint32_t cls, uint3
   return v & cls_mask64(cls);
 }
 
-__device__ __forceinline__ V4 res_ldv(const char* s, uint32_t cls, uint32_t f) {
-  if (cls <= CW) return v4_from(res_fetch(s, cls, f));
+// A value of class cls (at most NL limbs) at slot field f.
+template <int NL = 4>
+__device__ __forceinline__ VN<NL> res_ldv(const char* s, uint32_t cls, uint32_t f) {
+  if (cls <= CW) return v4_from<NL>(res_fetch(s, cls, f));
   const char* q = s + (uint64_t)(f >> 6) * 8u;
   const uint32_t k = cls_limbs(cls);
-  V4 r = v4_from(*(const uint64_t*)q);
-  if (k > 1) r.l[1] = *(const uint64_t*)(q + 8);
-  if (k > 2) r.l[2] = *(const uint64_t*)(q + 16);
-  if (k > 3) r.l[3] = *(const uint64_t*)(q + 24);
+  VN<NL> r = v4_from<NL>(*(const uint64_t*)q);
+#pragma unroll
+  for (int l = 1; l < NL; ++l)
+    if ((uint32_t)l < k) r.l[l] = *(const uint64_t*)(q + 8 * l);
   return r;
 }
 
@@ -93,7 +95,8 @@ __device__ __forceinline__ void res_st64(char* s, uint32_t cls, uint32_t f, uint
   else *(uint64_t*)q = v;
 }
 
-__device__ __forceinline__ void res_stv(char* s, uint32_t cls, uint32_t f, const V4& v) {
+template <int NL>
+__device__ __forceinline__ void res_stv(char* s, uint32_t cls, uint32_t f, const VN<NL>& v) {
   if (cls <= CD) {
     res_st64(s, cls, f, v.l[0]);
     return;
@@ -101,9 +104,9 @@ __device__ __forceinline__ void res_stv(char* s, uint32_t cls, uint32_t f, const
   char* q = s + (uint64_t)(f >> 6) * 8u;
   const uint32_t k = cls_limbs(cls);
   *(uint64_t*)q = v.l[0];
-  if (k > 1) *(uint64_t*)(q + 8) = v.l[1];
-  if (k > 2) *(uint64_t*)(q + 16) = v.l[2];
-  if (k > 3) *(uint64_t*)(q + 24) = v.l[3];
+#pragma unroll
+  for (int l = 1; l < NL; ++l)
+    if ((uint32_t)l < k) *(uint64_t*)(q + 8 * l) = v.l[l];
 }
 
 // One RESIDENT instance for n_cycles.
@@ -1029,12 +1032,87 @@ k_sweep_muxc(const DevOp* __restrict__ ops, const DevLayer* __restrict__ layers,
                 threadIdx.x & 63u);
 }
 
+// Operands and value of heavy operation q (not a source) for the TG tiles, on
+// NL limbs: limb 0 of every operand from an 8-byte load holding the lane's
+// element, cut out as in the common kernel; the further limbs of wide
+// operands under a uniform branch.  All loads are in flight before the first
+// is used.
+template <int NL, int TG>
+__device__ __forceinline__ void heavy_eval(const SweepView& v, const DevOp& q, VN<NL> (&r)[TG]) {
+  const uint32_t code = q.code, opc = op_opc(code), ar = op_arity(code);
+  const uint32_t w = op_width(q.wimm), imm = op_imm(q.wimm);
+  uint64_t raw[3 * NL * TG];
+  uint32_t sh[3];
+  uint64_t m[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const uint32_t cls = op_scls(code, k), w3 = cls_w3(cls), kl = cls_limbs(cls);
+    const char* p = v.at(q.src[k], w3, 0u) + v.off64(w3);
+    const uint32_t step = 512u >> w3;
+    sh[k] = v.sh64(w3);
+    m[k] = cls_mask64(cls);
+#pragma unroll
+    for (int g = 0; g < TG; ++g) raw[(k * NL) * TG + g] = *(const uint64_t*)(p + g * step);
+    // Limbs 1.. exist only for values wider than 64 bits (then the lane
+    // offset is 8 lane and the step 512).
+#pragma unroll
+    for (int l = 1; l < NL; ++l) {
+      if ((uint32_t)l < kl) {
+#pragma unroll
+        for (int g = 0; g < TG; ++g)
+          raw[(k * NL + l) * TG + g] = *(const uint64_t*)(p + (uint64_t)l * v.row_bytes + g * 512u);
+      } else {
+#pragma unroll
+        for (int g = 0; g < TG; ++g) raw[(k * NL + l) * TG + g] = 0ull;
+      }
+    }
+  }
+  keep_loaded(raw);
+#pragma unroll
+  for (int g = 0; g < TG; ++g) {
+    VN<NL> x[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      x[k].l[0] = (raw[(k * NL) * TG + g] >> sh[k]) & m[k];
+#pragma unroll
+      for (int l = 1; l < NL; ++l) x[k].l[l] = raw[(k * NL + l) * TG + g];
+    }
+    r[g] = eval_wide(opc, ar, x[0], x[1], x[2], imm, w);
+  }
+}
+
+// Stores the TG tiles' results r of an operation with destination class dc
+// at slot field dst (dc has at most NL limbs).
+template <int NL, int TG>
+__device__ __forceinline__ void heavy_store(const SweepView& v, uint32_t dc, uint32_t dst,
+                                            const VN<NL> (&r)[TG]) {
+  if (dc == CB) {
+    uint64_t bits[TG];
+#pragma unroll
+    for (int g = 0; g < TG; ++g) bits[g] = __ballot((r[g].l[0] & 1ull) != 0ull);
+    v.st_bits<TG>(dst, bits);
+  } else if (dc <= CD) {
+    uint64_t x[TG];
+#pragma unroll
+    for (int g = 0; g < TG; ++g) x[g] = r[g].l[0];
+    v.st_dst<TG, true>(dc, dst, x);
+  } else {
+    const uint32_t kd = cls_limbs(dc);
+    char* d0 = v.at(dst, 0u, 0u) + v.lane * 8u;
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+      if ((uint32_t)l < kd) {
+#pragma unroll
+        for (int g = 0; g < TG; ++g)
+          *(uint64_t*)(d0 + (uint64_t)l * v.row_bytes + g * 512u) = r[g].l[l];
+      }
+  }
+}
+
 // The heavy operations of one layer (a value wider than 64 bits, a type run
-// in the wide form, or a source) other than the fused mux chains.  Limb 0 of
-// every operand is gathered without branches (an 8-byte load per tile holding
-// the lane's element, cut out as in the common kernel); the further limbs of
-// wide operands follow under a uniform branch.  All loads of an operation are
-// in flight before the first is used.
+// in the wide form, or a source) other than the fused mux chains.  An
+// operation whose destination and operands all fit 128 bits runs on two
+// limbs, a wider one on four.
 template <int TG>
 __device__ __forceinline__ void heavy_wave(const DevOp* __restrict__ ops, const DevLayer& ly,
                                            const uint64_t* __restrict__ const_limbs,
@@ -1057,11 +1135,11 @@ __device__ __forceinline__ void heavy_wave(const DevOp* __restrict__ ops, const 
 
   for (uint32_t o = o0; o < o1; ++o) {
     const DevOp q = ops[o];
-    const uint32_t code = q.code, opc = op_opc(code), ar = op_arity(code);
-    const uint32_t dc = op_dcls(code), w = op_width(q.wimm), imm = op_imm(q.wimm);
-    V4 r[TG];
+    const uint32_t code = q.code, opc = op_opc(code), dc = op_dcls(code);
     if (opc >= OP_STIM) {
+      const uint32_t w = op_width(q.wimm);
       const uint64_t cycle = ctl->cycle;
+      V4 r[TG];
 #pragma unroll
       for (int g = 0; g < TG; ++g) {
         const uint32_t inst = (tile0 + g) * 64u + lane;
@@ -1071,68 +1149,16 @@ __device__ __forceinline__ void heavy_wave(const DevOp* __restrict__ ops, const 
         if (inst < n_inst)
           r[g] = source_value(const_limbs, q, seeds[inst], cycle, ctl->words, words_row, w);
       }
+      heavy_store<4, TG>(v, dc, q.dst, r);
+    } else if (dc <= CL2 && op_scls(code, 0) <= CL2 && op_scls(code, 1) <= CL2 &&
+               op_scls(code, 2) <= CL2) {
+      VN<2> r[TG];
+      heavy_eval<2, TG>(v, q, r);
+      heavy_store<2, TG>(v, dc, q.dst, r);
     } else {
-      uint64_t raw[3 * 4 * TG];
-      uint32_t sh[3], kl[3];
-      uint64_t m[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const uint32_t cls = op_scls(code, k), w3 = cls_w3(cls);
-        const char* p = v.at(q.src[k], w3, 0u) + v.off64(w3);
-        const uint32_t step = 512u >> w3;
-        kl[k] = cls_limbs(cls);
-        sh[k] = v.sh64(w3);
-        m[k] = cls_mask64(cls);
-#pragma unroll
-        for (int g = 0; g < TG; ++g) raw[(k * 4) * TG + g] = *(const uint64_t*)(p + g * step);
-        // Limbs 1..3 exist only for values wider than 64 bits (then the
-        // lane offset is 8 lane and the step 512).
-#pragma unroll
-        for (int l = 1; l < 4; ++l) {
-          if ((uint32_t)l < kl[k]) {
-#pragma unroll
-            for (int g = 0; g < TG; ++g)
-              raw[(k * 4 + l) * TG + g] =
-                  *(const uint64_t*)(p + (uint64_t)l * v.row_bytes + g * 512u);
-          } else {
-#pragma unroll
-            for (int g = 0; g < TG; ++g) raw[(k * 4 + l) * TG + g] = 0ull;
-          }
-        }
-      }
-      keep_loaded(raw);
-#pragma unroll
-      for (int g = 0; g < TG; ++g) {
-        V4 x[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          x[k].l[0] = (raw[(k * 4) * TG + g] >> sh[k]) & m[k];
-#pragma unroll
-          for (int l = 1; l < 4; ++l) x[k].l[l] = raw[(k * 4 + l) * TG + g];
-        }
-        r[g] = eval_wide(opc, ar, x[0], x[1], x[2], imm, w);
-      }
-    }
-    if (dc == CB) {
-      uint64_t bits[TG];
-#pragma unroll
-      for (int g = 0; g < TG; ++g) bits[g] = __ballot((r[g].l[0] & 1ull) != 0ull);
-      v.st_bits<TG>(q.dst, bits);
-    } else if (dc <= CD) {
-      uint64_t x[TG];
-#pragma unroll
-      for (int g = 0; g < TG; ++g) x[g] = r[g].l[0];
-      v.st_dst<TG, true>(dc, q.dst, x);
-    } else {
-      const uint32_t kd = cls_limbs(dc);
-      char* d0 = v.at(q.dst, 0u, 0u) + lane * 8u;
-#pragma unroll
-      for (int l = 0; l < 4; ++l)
-        if ((uint32_t)l < kd) {
-#pragma unroll
-          for (int g = 0; g < TG; ++g)
-            *(uint64_t*)(d0 + (uint64_t)l * v.row_bytes + g * 512u) = r[g].l[l];
-        }
+      V4 r[TG];
+      heavy_eval<4, TG>(v, q, r);
+      heavy_store<4, TG>(v, dc, q.dst, r);
     }
   }
 }
@@ -1295,8 +1321,9 @@ __device__ __forceinline__ void mixed_body(const MultiSeg* __restrict__ segs,
 #undef RTEAAL_MIX_SWEEP
 }
 
+// The smallest set keeps six wavefronts per SIMD (at most 80 VGPRs).
 template <int SET>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SET == 2 ? 6 : 1)))
 k_mixed_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wave0,
               uint32_t n_seg) {
   mixed_body<SET>(segs, wave0, n_seg);

@@ -166,21 +166,47 @@ __device__ __forceinline__ uint64_t eval_bits(uint32_t opc, uint32_t arity, uint
   }
 }
 
-struct V4 {
-  uint64_t l[4];
+// A value of up to 64 NL bits in NL 64-bit limbs, least significant first.
+// Every operation below is exact modulo 2^(64 NL), so a value and its
+// operands that all fit 128 bits give the same result with NL = 2 as with
+// NL = 4 (the result is cut to its width w <= 64 NL either way).
+template <int NL>
+struct VN {
+  uint64_t l[NL];
 };
+using V4 = VN<4>;
 
-__device__ __forceinline__ V4 v4_from(uint64_t x) { return V4{{x, 0ull, 0ull, 0ull}}; }
-
-__device__ __forceinline__ bool v4_nonzero(const V4& a) {
-  return (a.l[0] | a.l[1] | a.l[2] | a.l[3]) != 0ull;
+template <int NL = 4>
+__device__ __forceinline__ VN<NL> v4_from(uint64_t x) {
+  VN<NL> r;
+  r.l[0] = x;
+#pragma unroll
+  for (int i = 1; i < NL; i++) r.l[i] = 0ull;
+  return r;
 }
 
-__device__ __forceinline__ V4 v4_add(const V4& a, const V4& b) {
-  V4 r;
+template <int NL>
+__device__ __forceinline__ VN<NL> v4_ones() {
+  VN<NL> r;
+#pragma unroll
+  for (int i = 0; i < NL; i++) r.l[i] = ~0ull;
+  return r;
+}
+
+template <int NL>
+__device__ __forceinline__ bool v4_nonzero(const VN<NL>& a) {
+  uint64_t x = 0;
+#pragma unroll
+  for (int i = 0; i < NL; i++) x |= a.l[i];
+  return x != 0ull;
+}
+
+template <int NL>
+__device__ __forceinline__ VN<NL> v4_add(const VN<NL>& a, const VN<NL>& b) {
+  VN<NL> r;
   uint64_t carry = 0;
 #pragma unroll
-  for (int i = 0; i < 4; i++) {
+  for (int i = 0; i < NL; i++) {
     uint64_t t = a.l[i] + b.l[i];
     uint64_t c1 = t < a.l[i];
     uint64_t s = t + carry;
@@ -191,11 +217,12 @@ __device__ __forceinline__ V4 v4_add(const V4& a, const V4& b) {
   return r;
 }
 
-__device__ __forceinline__ V4 v4_sub(const V4& a, const V4& b) {
-  V4 r;
+template <int NL>
+__device__ __forceinline__ VN<NL> v4_sub(const VN<NL>& a, const VN<NL>& b) {
+  VN<NL> r;
   uint64_t borrow = 0;
 #pragma unroll
-  for (int i = 0; i < 4; i++) {
+  for (int i = 0; i < NL; i++) {
     uint64_t t = a.l[i] - b.l[i];
     uint64_t b1 = a.l[i] < b.l[i];
     uint64_t s = t - borrow;
@@ -206,13 +233,14 @@ __device__ __forceinline__ V4 v4_sub(const V4& a, const V4& b) {
   return r;
 }
 
-__device__ __forceinline__ V4 v4_mul(const V4& a, const V4& b) {
-  V4 r = v4_from(0);
+template <int NL>
+__device__ __forceinline__ VN<NL> v4_mul(const VN<NL>& a, const VN<NL>& b) {
+  VN<NL> r = v4_from<NL>(0);
 #pragma unroll
-  for (int i = 0; i < 4; i++) {
+  for (int i = 0; i < NL; i++) {
     uint64_t carry = 0;
 #pragma unroll
-    for (int j = 0; i + j < 4; j++) {
+    for (int j = 0; i + j < NL; j++) {
       uint64_t lo = a.l[i] * b.l[j];
       uint64_t hi = __umul64hi(a.l[i], b.l[j]);
       uint64_t t = r.l[i + j] + lo;
@@ -226,48 +254,56 @@ __device__ __forceinline__ V4 v4_mul(const V4& a, const V4& b) {
   return r;
 }
 
-// Limb k of a (0 outside 0..3), as a select chain so that no local array is
-// indexed with a run-time value.
-__device__ __forceinline__ uint64_t v4_limb(const V4& a, int k) {
-  return k == 0 ? a.l[0] : k == 1 ? a.l[1] : k == 2 ? a.l[2] : k == 3 ? a.l[3] : 0ull;
+// Limb k of a (0 outside 0..NL-1), as a select chain so that no local array
+// is indexed with a run-time value.
+template <int NL>
+__device__ __forceinline__ uint64_t v4_limb(const VN<NL>& a, int k) {
+  uint64_t x = 0ull;
+#pragma unroll
+  for (int i = 0; i < NL; i++) x = k == i ? a.l[i] : x;
+  return x;
 }
 
-__device__ __forceinline__ V4 v4_shl(const V4& a, uint32_t k) {
-  V4 r = v4_from(0);
-  if (k >= 256) return r;
+template <int NL>
+__device__ __forceinline__ VN<NL> v4_shl(const VN<NL>& a, uint32_t k) {
+  VN<NL> r = v4_from<NL>(0);
+  if (k >= 64u * NL) return r;
   const int q = (int)(k >> 6);
   const uint32_t s = k & 63u;
 #pragma unroll
-  for (int i = 0; i < 4; i++) {
+  for (int i = 0; i < NL; i++) {
     const uint64_t hi = v4_limb(a, i - q), lo = v4_limb(a, i - q - 1);
     r.l[i] = s ? (hi << s) | (lo >> (64u - s)) : hi;
   }
   return r;
 }
 
-__device__ __forceinline__ V4 v4_shr(const V4& a, uint32_t k) {
-  V4 r = v4_from(0);
-  if (k >= 256) return r;
+template <int NL>
+__device__ __forceinline__ VN<NL> v4_shr(const VN<NL>& a, uint32_t k) {
+  VN<NL> r = v4_from<NL>(0);
+  if (k >= 64u * NL) return r;
   const int q = (int)(k >> 6);
   const uint32_t s = k & 63u;
 #pragma unroll
-  for (int i = 0; i < 4; i++) {
+  for (int i = 0; i < NL; i++) {
     const uint64_t lo = v4_limb(a, i + q), hi = v4_limb(a, i + q + 1);
     r.l[i] = s ? (lo >> s) | (hi << (64u - s)) : lo;
   }
   return r;
 }
 
-__device__ __forceinline__ bool v4_lt(const V4& a, const V4& b) {
-  if (a.l[3] != b.l[3]) return a.l[3] < b.l[3];
-  if (a.l[2] != b.l[2]) return a.l[2] < b.l[2];
-  if (a.l[1] != b.l[1]) return a.l[1] < b.l[1];
+template <int NL>
+__device__ __forceinline__ bool v4_lt(const VN<NL>& a, const VN<NL>& b) {
+#pragma unroll
+  for (int i = NL - 1; i > 0; i--)
+    if (a.l[i] != b.l[i]) return a.l[i] < b.l[i];
   return a.l[0] < b.l[0];
 }
 
-__device__ __forceinline__ V4 v4_mask(V4 a, uint32_t w) {
+template <int NL>
+__device__ __forceinline__ VN<NL> v4_mask(VN<NL> a, uint32_t w) {
 #pragma unroll
-  for (int i = 0; i < 4; i++) {
+  for (int i = 0; i < NL; i++) {
     const uint32_t lo = 64u * i;
     if (w <= lo) a.l[i] = 0;
     else if (w < lo + 64) a.l[i] &= (1ull << (w - lo)) - 1ull;
@@ -277,74 +313,85 @@ __device__ __forceinline__ V4 v4_mask(V4 a, uint32_t w) {
 
 // Quotient (want_q) or remainder of a / b, b != 0, by restoring long
 // division over a's significant bits.  The partial remainder stays below b,
-// but doubling it can need bit 256, which `top` keeps.
-__device__ __forceinline__ V4 v4_divmod(const V4& a, const V4& b, bool want_q) {
+// but doubling it can need bit 64 NL, which `top` keeps.
+template <int NL>
+__device__ __forceinline__ VN<NL> v4_divmod(const VN<NL>& a, const VN<NL>& b, bool want_q) {
   int n = 0;  // significant bits of a
 #pragma unroll
-  for (int k = 3; k >= 0; --k)
+  for (int k = NL - 1; k >= 0; --k)
     if (n == 0 && a.l[k]) n = 64 * k + 64 - __clzll((long long)a.l[k]);
-  V4 q = v4_from(0), r = v4_from(0);
+  VN<NL> q = v4_from<NL>(0), r = v4_from<NL>(0);
   for (int i = n - 1; i >= 0; --i) {
-    const uint64_t top = r.l[3] >> 63;
+    const uint64_t top = r.l[NL - 1] >> 63;
     r = v4_shl(r, 1u);
     r.l[0] |= (v4_limb(a, i >> 6) >> (i & 63)) & 1ull;
     if (top || !v4_lt(r, b)) {
       r = v4_sub(r, b);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) q.l[k] |= (k == (i >> 6)) ? 1ull << (i & 63) : 0ull;
+      for (int k = 0; k < NL; ++k) q.l[k] |= (k == (i >> 6)) ? 1ull << (i & 63) : 0ull;
     }
   }
   return want_q ? q : r;
 }
 
-// A shift amount held in a value, capped at 256 (everything shifted out).
-__device__ __forceinline__ uint32_t v4_amount(const V4& b) {
-  return (b.l[1] | b.l[2] | b.l[3]) || b.l[0] >= 256ull ? 256u : (uint32_t)b.l[0];
+// A shift amount held in a value, capped at 64 NL (everything shifted out).
+template <int NL>
+__device__ __forceinline__ uint32_t v4_amount(const VN<NL>& b) {
+  uint64_t hi = 0;
+#pragma unroll
+  for (int i = 1; i < NL; i++) hi |= b.l[i];
+  return hi || b.l[0] >= 64ull * NL ? 64u * NL : (uint32_t)b.l[0];
 }
 
-__device__ __forceinline__ V4 eval_wide(uint32_t opc, uint32_t arity, const V4& a, const V4& b,
-                                        const V4& c, uint32_t imm, uint32_t w) {
-  V4 r;
+template <int NL>
+__device__ __forceinline__ VN<NL> eval_wide(uint32_t opc, uint32_t arity, const VN<NL>& a,
+                                            const VN<NL>& b, const VN<NL>& c, uint32_t imm,
+                                            uint32_t w) {
+  VN<NL> r;
   switch (opc) {
     case OP_AND:
 #pragma unroll
-      for (int i = 0; i < 4; i++) r.l[i] = a.l[i] & b.l[i] & (arity == 3 ? c.l[i] : ~0ull);
+      for (int i = 0; i < NL; i++) r.l[i] = a.l[i] & b.l[i] & (arity == 3 ? c.l[i] : ~0ull);
       break;
     case OP_OR:
 #pragma unroll
-      for (int i = 0; i < 4; i++) r.l[i] = a.l[i] | b.l[i] | (arity == 3 ? c.l[i] : 0ull);
+      for (int i = 0; i < NL; i++) r.l[i] = a.l[i] | b.l[i] | (arity == 3 ? c.l[i] : 0ull);
       break;
     case OP_XOR:
 #pragma unroll
-      for (int i = 0; i < 4; i++) r.l[i] = a.l[i] ^ b.l[i] ^ (arity == 3 ? c.l[i] : 0ull);
+      for (int i = 0; i < NL; i++) r.l[i] = a.l[i] ^ b.l[i] ^ (arity == 3 ? c.l[i] : 0ull);
       break;
     case OP_NOT:
 #pragma unroll
-      for (int i = 0; i < 4; i++) r.l[i] = ~a.l[i];
+      for (int i = 0; i < NL; i++) r.l[i] = ~a.l[i];
       break;
     case OP_ADD: r = v4_add(a, b); break;
     case OP_SUB: r = v4_sub(a, b); break;
     case OP_MUL: r = v4_mul(a, b); break;
     case OP_MUX:
     case OP_MUXC: r = v4_nonzero(a) ? b : c; break;  // MUXC: c holds the folded further pairs
-    case OP_EQ:
-      r = v4_from((a.l[0] == b.l[0]) & (a.l[1] == b.l[1]) & (a.l[2] == b.l[2]) & (a.l[3] == b.l[3]));
+    case OP_EQ: {
+      bool eq = true;
+#pragma unroll
+      for (int i = 0; i < NL; i++) eq = eq & (a.l[i] == b.l[i]);
+      r = v4_from<NL>(eq);
       break;
-    case OP_LT: r = v4_from(v4_lt(a, b)); break;
+    }
+    case OP_LT: r = v4_from<NL>(v4_lt(a, b)); break;
     case OP_SHL: r = v4_shl(a, imm); break;
     case OP_SHR:
     case OP_EXTRACT: r = v4_shr(a, imm); break;
     case OP_CONCAT: {
       r = v4_shl(a, imm);
 #pragma unroll
-      for (int i = 0; i < 4; i++) r.l[i] |= b.l[i];
+      for (int i = 0; i < NL; i++) r.l[i] |= b.l[i];
       break;
     }
-    case OP_ORR: r = v4_from(v4_nonzero(a)); break;
+    case OP_ORR: r = v4_from<NL>(v4_nonzero(a)); break;
     // The FIRRTL primitives with no expansion in the types above; the
     // encoder runs them in this form whatever their widths.
     case OP_DIV:  // division by zero reads as quotient 0 ...
-      r = v4_nonzero(b) ? v4_divmod(a, b, true) : v4_from(0);
+      r = v4_nonzero(b) ? v4_divmod(a, b, true) : v4_from<NL>(0);
       break;
     case OP_REM:  // ... and remainder a
       r = v4_nonzero(b) ? v4_divmod(a, b, false) : a;
@@ -352,21 +399,27 @@ __device__ __forceinline__ V4 eval_wide(uint32_t opc, uint32_t arity, const V4& 
     case OP_DSHL: r = v4_shl(a, v4_amount(b)); break;
     case OP_DSHR: r = v4_shr(a, v4_amount(b)); break;
     case OP_ANDR: {  // imm = width of o0: are all its bits set?
-      const V4 ones = v4_mask(V4{{~0ull, ~0ull, ~0ull, ~0ull}}, imm);
-      r = v4_from((a.l[0] == ones.l[0]) & (a.l[1] == ones.l[1]) & (a.l[2] == ones.l[2]) &
-                  (a.l[3] == ones.l[3]));
+      const VN<NL> ones = v4_mask(v4_ones<NL>(), imm);
+      bool all = true;
+#pragma unroll
+      for (int i = 0; i < NL; i++) all = all & (a.l[i] == ones.l[i]);
+      r = v4_from<NL>(all);
       break;
     }
-    case OP_XORR:
-      r = v4_from((uint64_t)__popcll(a.l[0] ^ a.l[1] ^ a.l[2] ^ a.l[3]) & 1ull);
+    case OP_XORR: {
+      uint64_t x = 0;
+#pragma unroll
+      for (int i = 0; i < NL; i++) x ^= a.l[i];
+      r = v4_from<NL>((uint64_t)__popcll(x) & 1ull);
       break;
+    }
     case OP_SEXT: {  // imm = width of o0, read as two's complement
       r = a;
       const uint32_t sb = imm - 1u;
       if ((v4_limb(a, (int)(sb >> 6)) >> (sb & 63u)) & 1ull) {
-        const V4 high = v4_shl(V4{{~0ull, ~0ull, ~0ull, ~0ull}}, imm);
+        const VN<NL> high = v4_shl(v4_ones<NL>(), imm);
 #pragma unroll
-        for (int i = 0; i < 4; i++) r.l[i] |= high.l[i];
+        for (int i = 0; i < NL; i++) r.l[i] |= high.l[i];
       }
       break;
     }

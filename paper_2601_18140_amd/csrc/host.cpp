@@ -1197,6 +1197,7 @@ rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
                                 std::unique_ptr<MultiGraph>* out) {
   struct Launch {
     uint32_t kind, tg;
+    bool narrow;  // heavy pieces of designs with no value wider than 128 bits
     std::vector<MultiSeg> segs;
     std::vector<uint32_t> wave0;
     size_t off = 0;  // byte offset of the table in the device buffer
@@ -1204,14 +1205,15 @@ rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
   uint32_t S = 0;
   for (Batch* b : bs) S = std::max<uint32_t>(S, (uint32_t)find_design(ctx, b->design)->layers.size());
   std::vector<std::vector<Launch>> slots(S);
-  auto add = [&](uint32_t t, uint32_t kind, uint32_t tg, const MultiSeg& seg, uint64_t waves) {
+  auto add = [&](uint32_t t, uint32_t kind, uint32_t tg, bool narrow, const MultiSeg& seg,
+                 uint64_t waves) {
     if (!waves) return true;
     auto& v = slots[t];
     Launch* l = nullptr;
     for (auto& x : v)
-      if (x.kind == kind && x.tg == tg) l = &x;
+      if (x.kind == kind && x.tg == tg && x.narrow == narrow) l = &x;
     if (!l) {
-      v.push_back(Launch{kind, tg, {}, {0u}, 0});
+      v.push_back(Launch{kind, tg, narrow, {}, {0u}, 0});
       l = &v.back();
     }
     const uint64_t end = (uint64_t)l->wave0.back() + waves;
@@ -1252,23 +1254,27 @@ rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
         g.r = OpRanges{ly.begin, ly.hbeg, ly.hend, ly.end};
         g.split = (n1 + opw - 1) / opw;
         g.n_groups = T / b->tg;
-        ok = ok && add(t, 0, b->tg, g, (uint64_t)(g.split + (n2 + opw - 1) / opw) * g.n_groups);
+        ok = ok && add(t, 0, b->tg, false, g, (uint64_t)(g.split + (n2 + opw - 1) / opw) * g.n_groups);
         // Heavy pieces take one tile per wavefront when the batch's tile
         // group is at most 2, so that a layer index stays within the lean
-        // mixed variants.
+        // mixed variants.  A design with no value wider than 128 bits runs
+        // them in the two-limb form only (narrow: fewer instructions and
+        // registers).  Two tiles per wavefront in that form measured slower
+        // on multi-64 (1.40e6 against 1.60e6): it needs the larger lean set.
+        const bool narrow = h.n_idx[CL3] == 0 && h.n_idx[CL4] == 0;
         const uint32_t th = b->tg <= 2 ? 1u : 2u;
         const uint32_t h1 = ly.hm0 - ly.hbeg, h2 = ly.hend - ly.hm1;
         g.r = OpRanges{ly.hbeg, ly.hm0, ly.hm1, ly.hend};  // the heavy range (see MultiSeg)
         g.n_groups = T / th;
-        ok = ok && add(t, 1, th, g,
+        ok = ok && add(t, 1, th, narrow, g,
                        (uint64_t)((h1 + opw - 1) / opw + (h2 + opw - 1) / opw) * g.n_groups);
         const uint32_t tm = b->tg >= 4 ? 4u : b->tg;
         g.n_groups = T / tm;
-        ok = ok && add(t, 2, tm, g, (uint64_t)(ly.hm1 - ly.hm0) * g.n_groups);
+        ok = ok && add(t, 2, tm, false, g, (uint64_t)(ly.hm1 - ly.hm0) * g.n_groups);
       } else {
         const uint32_t n = ly.end - ly.begin;
         g.n_groups = (n + 63u) / 64u;
-        ok = ok && add(t, 3, 1, g, (uint64_t)g.n_groups * b->n_inst);
+        ok = ok && add(t, 3, 1, false, g, (uint64_t)g.n_groups * b->n_inst);
       }
       if (!ok) return fail(ctx, RTEAAL_E_UNSUPPORTED, "too many wavefronts for one multi-batch launch");
     }
@@ -1300,17 +1306,18 @@ rteaal_status build_multi_graph(rteaal_ctx* ctx, const std::vector<Batch*>& bs,
     for (const Launch& l : v) {
       waves += l.wave0.back();
       ok = ok && multi_mixable(l.kind, l.tg);
-      lean = lean && multi_lean(l.kind, l.tg);
-      // the smallest set: no LAYERED pieces and at most 2 operations in flight
-      small = small && l.kind != 3;
+      lean = lean && multi_lean(l.kind, l.tg, l.narrow);
+      // the smallest set: no LAYERED pieces, heavy pieces on one tile, at
+      // most 2 operations in flight
+      small = small && l.kind != 3 && (l.kind != 1 || l.tg == 1);
       for (const MultiSeg& x : l.segs) small = small && (l.kind != 0 || x.unroll <= 2);
     }
     if (!ok || waves > ctx->mixed_max_waves) continue;
-    Launch m{lean ? (small ? 6u : 5u) : 4u, 0u, {}, {0u}, 0};
+    Launch m{lean ? (small ? 6u : 5u) : 4u, 0u, false, {}, {0u}, 0};
     for (const Launch& l : v) {
       for (size_t k = 0; k < l.segs.size(); ++k) {
         MultiSeg x = l.segs[k];
-        x.variant = multi_variant(l.kind, l.tg, x.unroll, lean);
+        x.variant = multi_variant(l.kind, l.tg, x.unroll, lean, l.narrow);
         m.segs.push_back(x);
         m.wave0.push_back(m.wave0.back() + (l.wave0[k + 1] - l.wave0[k]));
       }

@@ -186,7 +186,8 @@ struct ResJob {
 // SWEEP heavy operations and fused mux chains: those of layer `layer` in the
 // same way, r then holding the layer's (hbeg, hm0, hm1, hend); LAYERED: layer `layer`, n_groups wavefronts of 64 positions per
 // instance.  variant (mixed launches only, multi_variant): kind x 8 +
-// log2(tile group) + 64 x log2(unroll depth of common operations), the kinds
+// log2(tile group) + 64 x log2(unroll depth of common operations) + 256 for
+// the heavy pieces of a design with no value wider than 128 bits, the kinds
 // as in launch_multi.  unroll: the batch's unroll depth (mixed launches run
 // common operations with it; the other multi-batch launches with 1).
 struct MultiSeg {
@@ -306,10 +307,12 @@ uint32_t partitioned_capacity(uint32_t block, bool lds_state, size_t lds);
 // the small pieces of one layer index need one launch instead of one per
 // kind and tile group; 5: the same for the variants of small register
 // footprint only (multi_lean); 6: the lean variants without LAYERED pieces
-// and with at most 2 common operations in flight, smaller still.
+// and with at most 2 common operations in flight, smaller still.  narrow:
+// heavy pieces of a design with no value wider than 128 bits, which run in
+// the two-limb form only (lean with tile groups up to 2; variant + 256).
 bool multi_mixable(uint32_t kind, uint32_t tg);
-bool multi_lean(uint32_t kind, uint32_t tg);
-uint32_t multi_variant(uint32_t kind, uint32_t tg, uint32_t unroll, bool lean);
+bool multi_lean(uint32_t kind, uint32_t tg, bool narrow = false);
+uint32_t multi_variant(uint32_t kind, uint32_t tg, uint32_t unroll, bool lean, bool narrow = false);
 hipError_t launch_multi(uint32_t kind, uint32_t tg, const MultiSeg* segs, const uint32_t* wave0,
                         uint32_t n_seg, uint64_t n_waves, hipStream_t s);
 // Register digest of several batches, then their folds and cycle advance

@@ -30,23 +30,24 @@
 
 namespace rteaal {
 
-// Value of a STIM or CONST operation for one instance.
-__device__ __forceinline__ V4 source_value(const uint64_t* const_limbs, const DevOp& op,
-                                           uint64_t seed, uint64_t cycle, const uint64_t* words,
-                                           uint64_t words_row, uint32_t w) {
-  V4 v = v4_from(0);
+// Value of a STIM or CONST operation for one instance (w <= 64 NL).
+template <int NL = 4>
+__device__ __forceinline__ VN<NL> source_value(const uint64_t* const_limbs, const DevOp& op,
+                                               uint64_t seed, uint64_t cycle, const uint64_t* words,
+                                               uint64_t words_row, uint32_t w) {
+  VN<NL> v = v4_from<NL>(0);
   const uint32_t nl = (w + 63u) >> 6;
   if (op_opc(op.code) == OP_CONST) {
 #pragma unroll
-    for (uint32_t l = 0; l < 4; ++l)
+    for (uint32_t l = 0; l < (uint32_t)NL; ++l)
       if (l < nl) v.l[l] = const_limbs[(uint64_t)op.aux0 * 4u + l];
   } else if (words) {
 #pragma unroll
-    for (uint32_t l = 0; l < 4; ++l)
+    for (uint32_t l = 0; l < (uint32_t)NL; ++l)
       if (l < nl) v.l[l] = words[words_row + op.aux1 + l];
   } else {
 #pragma unroll
-    for (uint32_t l = 0; l < 4; ++l)
+    for (uint32_t l = 0; l < (uint32_t)NL; ++l)
       if (l < nl) v.l[l] = stim_word(seed, cycle, op.aux0, l);
   }
   return v4_mask(v, w);
@@ -1112,8 +1113,9 @@ __device__ __forceinline__ void heavy_store(const SweepView& v, uint32_t dc, uin
 // The heavy operations of one layer (a value wider than 64 bits, a type run
 // in the wide form, or a source) other than the fused mux chains.  An
 // operation whose destination and operands all fit 128 bits runs on two
-// limbs, a wider one on four.
-template <int TG>
+// limbs, a wider one on four; NARROW: the design holds no value wider than
+// 128 bits, so only the two-limb form is compiled (fewer registers).
+template <int TG, bool NARROW = false>
 __device__ __forceinline__ void heavy_wave(const DevOp* __restrict__ ops, const DevLayer& ly,
                                            const uint64_t* __restrict__ const_limbs,
                                            uint32_t words_per_inst, const StateLayout& L,
@@ -1137,25 +1139,26 @@ __device__ __forceinline__ void heavy_wave(const DevOp* __restrict__ ops, const 
     const DevOp q = ops[o];
     const uint32_t code = q.code, opc = op_opc(code), dc = op_dcls(code);
     if (opc >= OP_STIM) {
+      constexpr int SL = NARROW ? 2 : 4;
       const uint32_t w = op_width(q.wimm);
       const uint64_t cycle = ctl->cycle;
-      V4 r[TG];
+      VN<SL> r[TG];
 #pragma unroll
       for (int g = 0; g < TG; ++g) {
         const uint32_t inst = (tile0 + g) * 64u + lane;
         const uint64_t words_row =
             ((cycle - ctl->step_cycle0) * (uint64_t)n_inst + inst) * (uint64_t)words_per_inst;
-        r[g] = v4_from(0);
+        r[g] = v4_from<SL>(0);
         if (inst < n_inst)
-          r[g] = source_value(const_limbs, q, seeds[inst], cycle, ctl->words, words_row, w);
+          r[g] = source_value<SL>(const_limbs, q, seeds[inst], cycle, ctl->words, words_row, w);
       }
-      heavy_store<4, TG>(v, dc, q.dst, r);
-    } else if (dc <= CL2 && op_scls(code, 0) <= CL2 && op_scls(code, 1) <= CL2 &&
-               op_scls(code, 2) <= CL2) {
+      heavy_store<SL, TG>(v, dc, q.dst, r);
+    } else if (NARROW || (dc <= CL2 && op_scls(code, 0) <= CL2 && op_scls(code, 1) <= CL2 &&
+                          op_scls(code, 2) <= CL2)) {
       VN<2> r[TG];
       heavy_eval<2, TG>(v, q, r);
       heavy_store<2, TG>(v, dc, q.dst, r);
-    } else {
+    } else if constexpr (!NARROW) {
       V4 r[TG];
       heavy_eval<4, TG>(v, q, r);
       heavy_store<4, TG>(v, dc, q.dst, r);
@@ -1273,7 +1276,8 @@ k_layer_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wa
 // the branch on it is uniform over the wavefront.  SET 0 holds every
 // variant; 1 (lean) only those of small register footprint (common
 // operations with 1 or 2 tiles, 4 in flight on one, heavy operations with
-// 1, LAYERED), so that its wavefronts still find room beside long-running
+// 1, or 2 in the two-limb form only, LAYERED), so that its wavefronts still
+// find room beside long-running
 // RESIDENT workgroups on a compute unit; 2 the lean set without LAYERED and
 // 4 in flight, smaller still.
 template <int SET>
@@ -1299,6 +1303,12 @@ __device__ __forceinline__ void mixed_body(const MultiSeg* __restrict__ segs,
   } else if (v == 8) {
     heavy_wave<1>(g.ops, seg_heavy_range(g), g.const_limbs, g.words_per_inst, g.L, g.state, g.seeds,
                   g.ctl, g.n_inst, g.opw, 0u, g.n_groups, local, lane);
+  } else if (v == 264) {
+    heavy_wave<1, true>(g.ops, seg_heavy_range(g), g.const_limbs, g.words_per_inst, g.L, g.state,
+                        g.seeds, g.ctl, g.n_inst, g.opw, 0u, g.n_groups, local, lane);
+  } else if (SET <= 1 && v == 265) {
+    heavy_wave<2, true>(g.ops, seg_heavy_range(g), g.const_limbs, g.words_per_inst, g.L, g.state,
+                        g.seeds, g.ctl, g.n_inst, g.opw, 0u, g.n_groups, local, lane);
   } else if (SET <= 1 && v == 128) {
     RTEAAL_MIX_SWEEP(4, 1);
   } else if (SET <= 1 && v == 24) {
@@ -1329,11 +1339,11 @@ k_mixed_multi(const MultiSeg* __restrict__ segs, const uint32_t* __restrict__ wa
   mixed_body<SET>(segs, wave0, n_seg);
 }
 
-bool multi_lean(uint32_t kind, uint32_t tg) {
-  return (kind == 0 && tg <= 2) || (kind == 1 && tg == 1) || kind == 3;
+bool multi_lean(uint32_t kind, uint32_t tg, bool narrow) {
+  return (kind == 0 && tg <= 2) || (kind == 1 && (tg == 1 || (narrow && tg == 2))) || kind == 3;
 }
 
-uint32_t multi_variant(uint32_t kind, uint32_t tg, uint32_t unroll, bool lean) {
+uint32_t multi_variant(uint32_t kind, uint32_t tg, uint32_t unroll, bool lean, bool narrow) {
   const uint32_t lg = tg >= 4 ? 2u : tg >= 2 ? 1u : 0u;
   uint32_t lu = 0;
   if (kind == 0) {  // common operations may keep their batch's unroll depth
@@ -1342,7 +1352,7 @@ uint32_t multi_variant(uint32_t kind, uint32_t tg, uint32_t unroll, bool lean) {
     if (lean && lu == 1 && tg > 2) lu = 0;
     if (lean && lu == 2 && tg > 1) lu = 1;  // the lean kernel runs 4 in flight on one tile only
   }
-  return kind * 8u + lg + 64u * lu;
+  return kind * 8u + lg + 64u * lu + (kind == 1 && narrow ? 256u : 0u);
 }
 
 bool multi_mixable(uint32_t kind, uint32_t tg) {

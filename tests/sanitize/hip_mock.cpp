@@ -348,10 +348,10 @@ void digest_shape(bool sweep, uint32_t n_regs, uint32_t n_inst, uint32_t* n_unit
 bool multi_mixable(uint32_t kind, uint32_t tg) {
   return kind == 3 || ((kind == 0 || kind == 2) && tg <= 4) || (kind == 1 && tg <= 2);
 }
-bool multi_lean(uint32_t kind, uint32_t tg) {
-  return (kind == 0 && tg <= 2) || (kind == 1 && tg == 1) || kind == 3;
+bool multi_lean(uint32_t kind, uint32_t tg, bool narrow) {
+  return (kind == 0 && tg <= 2) || (kind == 1 && (tg == 1 || (narrow && tg == 2))) || kind == 3;
 }
-uint32_t multi_variant(uint32_t kind, uint32_t tg, uint32_t unroll, bool lean) {
+uint32_t multi_variant(uint32_t kind, uint32_t tg, uint32_t unroll, bool lean, bool narrow) {
   const uint32_t lg = tg >= 4 ? 2u : tg >= 2 ? 1u : 0u;
   uint32_t lu = 0;
   if (kind == 0) {
@@ -360,7 +360,7 @@ uint32_t multi_variant(uint32_t kind, uint32_t tg, uint32_t unroll, bool lean) {
     if (lean && lu == 1 && tg > 2) lu = 0;
     if (lean && lu == 2 && tg > 1) lu = 1;  // the lean kernel runs 4 in flight on one tile only
   }
-  return kind * 8u + lg + 64u * lu;
+  return kind * 8u + lg + 64u * lu + (kind == 1 && narrow ? 256u : 0u);
 }
 hipError_t launch_multi(uint32_t kind, uint32_t, const MultiSeg* segs, const uint32_t* wave0,
                         uint32_t n_seg, uint64_t n_waves, hipStream_t s) {
@@ -373,13 +373,15 @@ hipError_t launch_multi(uint32_t kind, uint32_t, const MultiSeg* segs, const uin
   }
   for (uint32_t k = 0; k < n_seg; ++k) {
     const uint32_t vk = (segs[k].variant % 64) / 8, vt = 1u << (segs[k].variant % 8);
-    const uint32_t vu = 1u << (segs[k].variant / 64);
+    const uint32_t vu = 1u << ((segs[k].variant % 256) / 64);
+    const bool vn = segs[k].variant >= 256;
+    if (vn && vk != 1) die("two-limb variant on a piece that is not heavy", &segs[k]);
     if ((kind == 4 || kind == 5) && vu > 1 && (vk != 0 || vu > 4 || (vu == 4 && vt > 2) || vt > 4))
       die("mixed segment with an unroll depth outside the kernel's variants", &segs[k]);
     if (kind == 4 && !multi_mixable(vk, vt)) die("mixed segment of an unknown variant", &segs[k]);
-    if ((kind == 5 || kind == 6) && (!multi_lean(vk, vt) || (vu == 2 && vt > 2) || (vu == 4 && vt > 1)))
+    if ((kind == 5 || kind == 6) && (!multi_lean(vk, vt, vn) || (vu == 2 && vt > 2) || (vu == 4 && vt > 1)))
       die("lean mixed segment of a variant outside the lean set", &segs[k]);
-    if (kind == 6 && (vk == 3 || vu > 2))
+    if (kind == 6 && (vk == 3 || vu > 2 || (vk == 1 && vt > 1)))
       die("smallest mixed set with a LAYERED piece or 4 in flight", &segs[k]);
     launched(s, {segs[k].ops, segs[k].layers, segs[k].const_limbs, segs[k].state, segs[k].seeds,
                  segs[k].ctl});

@@ -15,7 +15,8 @@ Workloads: large-5m (default; 5M operations, 4,096 instances), single-200k,
 plain-2k, multi-64 (64 uneven designs in one rteaal_step_many), serving
 (continuous batching of a Poisson job stream), levelize-5m (the device
 levelizer on the shuffled large-5m graph), waveform (value-change capture),
-muxchain-2m (the same mux-heavy design as drawn and after mux-chain fusion).
+muxchain-2m (the same mux-heavy design as drawn and after mux-chain fusion),
+block-probe (the common kernel's gather rate by block size).
 """
 import argparse
 import hashlib
@@ -690,6 +691,60 @@ def bench_levelize(args, R, torch):
     }
 
 
+def bench_blocks(args, R, torch):
+    """Gather rate by block size, measured with the common kernel itself:
+    four designs of 200,000 two-operand XORs (20 layers) whose every value
+    has one width (8, 16, 32 or 64 bits), run batched with one 64-instance
+    tile per wavefront, so that every gather and store instruction touches
+    one block of 64 x (element bytes) = 64, 128, 256 or 512 bytes.  Per cycle
+    an operation moves 3 blocks per tile (two gathers, one store)."""
+    n_inst = args.instances or 4096
+    tiles = (n_inst + 63) // 64
+    cps = args.cycles_per_step or 20
+    steps = args.steps if args.steps is not None else 5
+    rows, ok = [], True
+    for w, e in ((8, 1), (16, 2), (32, 4), (64, 8)):
+        cfg = rtlgen.GenConfig(200_000, 20, 256, 16, ((w, w, 1.0),), f"blocks-{w}",
+                               op_mix=((rtlgen.XOR, 2, 1.0),))
+        d = rtlgen.generate(cfg, 5)
+        seeds = rtlgen.instance_seeds(n_inst)
+        ctx = R.rteaal_create(0)
+        did = R.rteaal_load_design(ctx, d)
+        bid = R.rteaal_create_batch(ctx, did, seeds, mapping=R.RTEAAL_MAP_SWEEP, ops_per_wave=8,
+                                    unroll=1, tiles_per_wave=1)
+        for _ in range(args.warmup):
+            R.rteaal_step(ctx, bid, cps)
+
+        def run():
+            for _ in range(steps):
+                R.rteaal_step(ctx, bid, cps)
+
+        runs = timed_runs(torch, ctx.stream, run, max(1, args.repeats))
+        t_cycle = float(np.median(runs)) / 1e3 / (steps * cps)
+        cycles = (args.warmup + max(1, args.repeats) * steps) * cps
+        got = R.unpack_limbs(R.rteaal_read_state(ctx, bid, 0, 1), d.slot_width[d.reg_slot])
+        R.rteaal_free_batch(ctx, bid)
+        R.rteaal_destroy(ctx)
+        import oracle
+        ref, _, _ = oracle.run(d, seeds[:1], cycles)
+        ok = ok and bool(np.array_equal(got, ref))
+        blocks = 3.0 * d.n_ops * tiles
+        rows.append({"bits": w, "block_bytes": 64 * e, "ms_per_cycle": round(t_cycle * 1e3, 4),
+                     "G_blocks_per_s": round(blocks / t_cycle / 1e9, 2),
+                     "useful_GBps": round(blocks * 64 * e / t_cycle / 1e9, 1)})
+        print(f"[bench] blocks {64 * e} B: {rows[-1]}", file=sys.stderr, flush=True)
+    return {
+        "metric": "gather blocks/s by block size", "value": rows[0]["G_blocks_per_s"],
+        "unit": "G blocks/s (64-byte blocks)", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": rows[0]["ms_per_cycle"] * cps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "block-probe", "instances": n_inst, "ops": 200_000, "layers": 20,
+                   "shape": "SWEEP, 8 operations per wavefront, U = 1, one tile per wavefront",
+                   "timed": "whole cycles (common kernel, sources, register commit, digest)"},
+        "parity_sample_ok": ok, "rows": rows, "roofline": None, "cpu_baseline": None,
+    }
+
+
 def bench_waveform(args, R, torch):
     """Value-change capture on single-200k (every slot kept, 1,024 instances):
     the rate with 8,192 watched signals (the 4,096 registers and 4,096 operation
@@ -1025,7 +1080,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large-5m",
                     choices=sorted(WORKLOADS) + ["multi-64", "serving", "levelize-5m", "waveform",
-                                                 "muxchain-2m"])
+                                                 "muxchain-2m", "block-probe"])
     ap.add_argument("--designs", type=int, default=None)
     ap.add_argument("--serving-jobs", type=int, default=2000)
     ap.add_argument("--serving-rate", type=float, default=4.0, help="job arrivals per second")
@@ -1102,6 +1157,8 @@ def main():
         result = bench_waveform(args, R, torch)
     elif args.workload == "muxchain-2m":
         result = bench_muxchain(args, R, torch)
+    elif args.workload == "block-probe":
+        result = bench_blocks(args, R, torch)
     else:
         result = bench_single(args, R, torch)
     print(json.dumps(result), flush=True)

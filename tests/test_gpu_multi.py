@@ -212,3 +212,24 @@ def test_cache_after_free_and_eviction(ctx, designs):
         for k, b in enumerate(bs):
             if k != 3:
                 R.rteaal_free_batch(ctx, b)
+
+
+def test_two_limb_heavy_pieces_on_two_tiles(ctx, designs):
+    """Heavy pieces of a design with no value wider than 128 bits run in the
+    two-limb-only variant; with tile groups of 4 or more they take two tiles
+    per wavefront.  Batches of the 65-128-bit design with 4 and 8 tiles per
+    wavefront, beside a design with 256-bit values, against the oracle."""
+    ds, refs, ids = designs
+    plan = [(1, 250, dict(tiles_per_wave=4, unroll=1)), (1, 300, dict(tiles_per_wave=8, unroll=1)),
+            (0, 130, dict(tiles_per_wave=2))]
+    seeds = [np.arange(n, dtype=np.uint64) * 7 + 1 for _, n, _ in plan]
+    bids = [R.rteaal_create_batch(ctx, ids[di], s, mapping=R.RTEAAL_MAP_SWEEP, **shape)
+            for (di, _, shape), s in zip(plan, seeds)]
+    try:
+        R.rteaal_step_many(ctx, bids, [6, 4, 5])
+        R.rteaal_step_many(ctx, bids, [3, 5, 4])
+        for (di, _, shape), s, b, c in zip(plan, seeds, bids, [9, 9, 9]):
+            check(ctx, b, ds[di], refs[di], s, c, f"design {di} shape {shape}")
+    finally:
+        for b in bids:
+            R.rteaal_free_batch(ctx, b)

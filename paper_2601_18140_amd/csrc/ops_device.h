@@ -3,8 +3,8 @@
 //   eval_u64  : every operand and the result fit 64 bits (one lane = one value);
 //   eval_bits : every operand and the result are 1 bit and each 64-bit word
 //               holds that signal for 64 instances (bit-sliced);
-//   eval_wide : up to 256 bits in four 64-bit limbs (also every operation of
-//               the types DIV .. SEXT, whatever its widths).
+//   eval_wide : up to 64 NL bits in NL 64-bit limbs, NL = 2 or 4 (also every
+//               operation of the types DIV .. SEXT, whatever its widths).
 // All results are reduced modulo 2^width of the destination.
 #pragma once
 #include "internal.h"
